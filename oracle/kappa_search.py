@@ -1,0 +1,141 @@
+"""Choose each workload's hopping parameter kappa with the oracle (writes synth/kappa.json).
+
+The workloads ask for lambda_min(M)/lambda_max(M) of M = A^dag A near a target ratio.
+Rule: scan kappa upward from 0.10 (step 0.01, 0.05 above 0.30) to the first kappa whose
+ratio is below the target, then bisect between the last two scan points until
+|log10(ratio / target)| <= 0.05.  The extreme eigenvalues come from a dense eigvalsh
+while 12*Vh <= 3072, otherwise from a plain Lanczos run (three-term recurrence, Ritz
+values of T), which converges to the extremes from inside the spectrum.
+
+Usage: python -m oracle.kappa_search c1 c2 ...
+This is a data-preparation script of the oracle: its output is an input of the workloads.
+"""
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+from scipy.linalg import eigvalsh_tridiagonal
+
+from oracle.wilson import WilsonEO, dense, flat, matvec_M
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+OUT = os.path.join(os.path.dirname(HERE), "synth", "kappa.json")
+
+
+def extremes_dense(op):
+    mv = matvec_M(op)
+    M = dense(mv, 12 * op.Vh)
+    lam = np.linalg.eigvalsh(0.5 * (M + M.conj().T))
+    return float(lam[0]), float(lam[-1]), "dense"
+
+
+def extremes_lanczos(op, seed=12345, rtol=2e-3, max_iter=6000, log=None):
+    """Plain Lanczos from a random start; stop when the lowest Ritz value moved < rtol over 100 steps."""
+    mv = matvec_M(op)
+    rng = np.random.default_rng(seed)
+    N = 12 * op.Vh
+    v = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    v /= np.linalg.norm(v)
+    v_prev = np.zeros_like(v)
+    b_prev = 0.0
+    a_list, b_list = [], []
+    lo_hist = []
+    lo = hi = None
+    for i in range(1, max_iter + 1):
+        f = mv(v) - b_prev * v_prev
+        a = float(np.vdot(v, f).real)
+        f -= a * v
+        b = float(np.linalg.norm(f))
+        a_list.append(a)
+        b_list.append(b)
+        if i % 50 == 0 or b < 1e-12:
+            th = eigvalsh_tridiagonal(np.array(a_list), np.array(b_list[:-1]))
+            lo, hi = float(th[0]), float(th[-1])
+            lo_hist.append((i, lo))
+            if log:
+                log(f"    lanczos it={i} theta_min={lo:.6e} theta_max={hi:.6e}")
+            old = [x for (j, x) in lo_hist if j <= i - 100]
+            if (old and abs(old[-1] - lo) <= rtol * lo) or b < 1e-12:
+                break
+        v_prev, v = v, f / b
+        b_prev = b
+    return lo, hi, f"lanczos({i})"
+
+
+def ratio_of(links, dims, kappa, t_bc=-1, log=None):
+    op = WilsonEO(links, dims, kappa, t_bc=t_bc)
+    if 12 * op.Vh <= 3072:
+        lo, hi, how = extremes_dense(op)
+    else:
+        lo, hi, how = extremes_lanczos(op, log=log)
+    return lo / hi, lo, hi, how
+
+
+def search(links, dims, target, t_bc=-1, log=print):
+    evals = []
+
+    def f(k):
+        r, lo, hi, how = ratio_of(links, dims, k, t_bc, log=None)
+        evals.append(dict(kappa=k, ratio=r, lambda_min=lo, lambda_max=hi, how=how))
+        log(f"  kappa={k:.6f} ratio={r:.4e} ({how})")
+        return math.log10(r / target), r, lo, hi
+
+    k_prev, k = None, 0.10
+    g, r, lo, hi = f(k)
+    while g > 0:
+        k_prev = k
+        k = round(k + (0.01 if k < 0.30 - 1e-12 else 0.05), 6)
+        if k > 2.0:
+            raise RuntimeError("no kappa below 2.0 reaches the target ratio")
+        g, r, lo, hi = f(k)
+    if k_prev is None:
+        raise RuntimeError("target already met at kappa = 0.10")
+    a, b = k_prev, k           # f(a) > 0 >= f(b)
+    best = (abs(g), k, r, lo, hi)
+    while abs(g) > 0.05:
+        mid = 0.5 * (a + b)
+        g, r, lo, hi = f(mid)
+        if abs(g) < best[0]:
+            best = (abs(g), mid, r, lo, hi)
+        if g > 0:
+            a = mid
+        else:
+            b = mid
+        if b - a < 1e-7:
+            break
+    _, k, r, lo, hi = best
+    return dict(kappa=k, ratio=r, lambda_min=lo, lambda_max=hi, target=target,
+                beyond_physical=bool(k > 0.25), evaluations=evals)
+
+
+def main(names):
+    from synth.configs import CONFIGS, make_links, batch_members
+    table = {}
+    if os.path.exists(OUT):
+        with open(OUT) as fh:
+            table = json.load(fh)
+    members = {c.name: c for c in batch_members()}
+    for name in names:
+        cfg = CONFIGS.get(name) or members[name]
+        t0 = time.time()
+        print(f"{name}: dims={cfg.dims} eps={cfg.eps} ape={cfg.ape_steps} target={cfg.ratio:g}", flush=True)
+        U = make_links(cfg)
+        res = search(U, cfg.dims, cfg.ratio, cfg.t_bc)
+        res["seconds"] = round(time.time() - t0, 1)
+        table[name] = res
+        # re-read and merge so that concurrent searches of other workloads are kept
+        if os.path.exists(OUT):
+            with open(OUT) as fh:
+                cur = json.load(fh)
+            cur.update({name: res})
+            table = cur
+        with open(OUT, "w") as fh:
+            json.dump(table, fh, indent=1, sort_keys=True)
+        print(f"{name}: kappa={res['kappa']:.6f} ratio={res['ratio']:.3e} ({res['seconds']} s)", flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

@@ -1,0 +1,136 @@
+"""Workload definitions: lattice, link generator, hopping parameter, sources, solver knobs.
+
+The hopping parameter kappa of each workload is a stored input: it was chosen so that
+lambda_min/lambda_max of M = A^dag A meets the workload's target, by a search script that
+uses only the FP64 oracle, and lives in kappa.json next to this file.
+"""
+import json
+import math
+import os
+from dataclasses import dataclass, field, replace
+
+import numpy as np
+
+from .links import random_su3_links, ape_smear
+from .sources import point_sources, gaussian_sources, z2_sources
+
+_KAPPA_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "kappa.json")
+
+BATCH_DIMS = ((8, 8, 8, 8), (8, 8, 8, 16), (12, 12, 12, 24), (12, 12, 12, 12))
+
+
+@dataclass(frozen=True)
+class SolverConfig:
+    name: str
+    dims: tuple
+    eps: float                 # link roughness: U = exp(i eps H)
+    ratio: float               # target lambda_min / lambda_max of M
+    seed: int
+    ape_steps: int = 0
+    ape_alpha: float = 0.5
+    sources: tuple = (("gaussian", 4),)   # (kind, count) in order
+    tol: float = 1e-10         # FP64 true relative residual
+    reorth_k: int = 10         # periodic reorthogonalisation frequency
+    past: float = 1.5          # m = ceil(past * i_conv)
+    prec: str = "fp64"         # fp64 | mixed | mixed_bf16
+    reliable_every: int = 50
+    t_bc: int = -1             # antiperiodic in t
+    kappa_override: float = None
+    notes: str = ""
+
+    @property
+    def nrhs(self):
+        return sum(c for _, c in self.sources)
+
+    @property
+    def volume(self):
+        return int(np.prod(self.dims))
+
+
+CONFIGS = {
+    # Small correctness workload: 4^4, eps = 0.3, lambda ratio 1e-3, 4 Gaussian sources, k = 10.
+    "c1": SolverConfig("c1", (4, 4, 4, 4), 0.3, 1e-3, 0x5EED00,
+                       sources=(("gaussian", 4),), reorth_k=10),
+    # 16^3 x 32, eps = 0.5 smeared by 2 APE steps (alpha 0.5), ratio 1e-5, 12 point sources, k = 20.
+    "c2": SolverConfig("c2", (16, 16, 16, 32), 0.5, 1e-5, 0x5EED01, ape_steps=2, ape_alpha=0.5,
+                       sources=(("point", 12),), reorth_k=20),
+    # 24^3 x 48, eps = 0.3, ratio 1e-5, 12 point + 12 Z2 sources, mixed precision with BF16 links.
+    "c3": SolverConfig("c3", (24, 24, 24, 48), 0.3, 1e-5, 0x5EED02,
+                       sources=(("point", 12), ("z2", 12)), reorth_k=10, prec="mixed_bf16"),
+    # 32^3 x 64, eps = 0.3, ratio 1e-6, 12 point sources (learned preconditioner workload).
+    "c5": SolverConfig("c5", (32, 32, 32, 64), 0.3, 1e-6, 0x5EED04,
+                       sources=(("point", 12),), reorth_k=10, prec="mixed"),
+    # Tiny lattices used by the tests.
+    "t2": SolverConfig("t2", (2, 2, 2, 2), 0.3, 1e-2, 0x5EED10, sources=(("gaussian", 3),),
+                       reorth_k=5, kappa_override=0.12),
+    "t4": SolverConfig("t4", (4, 4, 4, 4), 0.3, 1e-2, 0x5EED11, sources=(("gaussian", 4),),
+                       reorth_k=10, kappa_override=0.12),
+    "t8": SolverConfig("t8", (8, 8, 8, 8), 0.3, 1e-3, 0x5EED12, sources=(("point", 4),),
+                       reorth_k=10, kappa_override=0.13),
+    "t6x4": SolverConfig("t6x4", (6, 4, 4, 6), 0.5, 1e-2, 0x5EED13, sources=(("point", 3),),
+                         reorth_k=8, kappa_override=0.125, t_bc=1),
+}
+
+
+def batch_members(n=64, seed=0x5EED03):
+    """The batched workload: n configurations, dims uniform over BATCH_DIMS, ratio log-uniform in [1e-4, 1e-3]."""
+    rng = np.random.default_rng([seed, 7])
+    idx = rng.integers(0, len(BATCH_DIMS), size=n)
+    logr = rng.uniform(-4.0, -3.0, size=n)
+    out = []
+    for i in range(n):
+        out.append(SolverConfig(f"c4_{i:02d}", BATCH_DIMS[idx[i]], 0.3, float(10.0 ** logr[i]),
+                                seed + 1000 + i, sources=(("point", 12),), reorth_k=10,
+                                prec="mixed"))
+    return out
+
+
+def _kappa_table():
+    if not os.path.exists(_KAPPA_FILE):
+        return {}
+    with open(_KAPPA_FILE) as fh:
+        return json.load(fh)
+
+
+def kappa_for(cfg):
+    if cfg.kappa_override is not None:
+        return float(cfg.kappa_override)
+    tab = _kappa_table()
+    if cfg.name not in tab:
+        raise KeyError(f"no stored kappa for workload {cfg.name!r}; run the oracle's kappa search")
+    return float(tab[cfg.name]["kappa"])
+
+
+def make_links(cfg):
+    rng = np.random.default_rng([cfg.seed, 0])
+    U = random_su3_links(cfg.dims, cfg.eps, rng)
+    if cfg.ape_steps:
+        U = ape_smear(U, cfg.dims, cfg.ape_alpha, cfg.ape_steps)
+    return U
+
+
+def make_sources(cfg):
+    rng = np.random.default_rng([cfg.seed, 1])
+    parts = []
+    for kind, count in cfg.sources:
+        if kind == "point":
+            parts.append(point_sources(cfg.dims, count))
+        elif kind == "gaussian":
+            parts.append(gaussian_sources(cfg.dims, count, rng))
+        elif kind == "z2":
+            parts.append(z2_sources(cfg.dims, count, rng))
+        else:
+            raise ValueError(kind)
+    return np.concatenate(parts, axis=0)
+
+
+def make_inputs(cfg, with_kappa=True):
+    """Returns (links (4,V,3,3), phi (nrhs,Vh,4,3), kappa)."""
+    if isinstance(cfg, str):
+        cfg = CONFIGS[cfg]
+    kappa = kappa_for(cfg) if with_kappa else None
+    return make_links(cfg), make_sources(cfg), kappa
+
+
+def with_changes(cfg, **kw):
+    return replace(cfg, **kw)

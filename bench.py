@@ -1,0 +1,189 @@
+"""Benchmark: RHS/s of Seed-CG at an FP64 relative residual of 1e-10, and the D^dag D stencil rate.
+
+One step = the whole hot path on one batch of right-hand sides: Algorithm 1 on RHS 1 (Lanczos
+run past convergence, periodic reorthogonalisation, Galerkin seeding of the others through the
+LU of T), then plain CG from the seeded guesses on every right-hand side, until each one has an
+FP64 true relative residual <= tol.  Inputs are resident in HBM before the timed region.
+
+Default workload: 16^3 x 32 lattice, links exp(0.5 i H) smeared by 2 APE steps, kappa from the
+oracle's search, 12 point sources, plain FP64 Seed-CG with k = 20.
+
+Prints one JSON line (see the `result` dict at the end).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+METRIC = "RHS/s at FP64 rel. residual 1e-10 (learned+mixed vs plain Seed-CG); D†D GB/s"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--prec", default=None, help="override the workload precision (fp64|mixed|mixed_bf16)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=40, help="Lanczos steps in the oracle sample")
+    ap.add_argument("--sample-every", type=int, default=4, help="stencil launches per timed sample")
+    ap.add_argument("--mbench", type=int, default=200, help="back-to-back M applications for D^dag D GB/s")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from __graft_entry__ import _built, build
+    if not _built():
+        build()
+    from paper_0901_3512_amd import SeedCG
+    from synth.configs import CONFIGS, make_links, make_sources, kappa_for
+
+    cfg = CONFIGS[args.config]
+    prec = args.prec or cfg.prec
+    dev = torch.device("cuda:0")
+    t_gen = time.time()
+    U = make_links(cfg)
+    phi = make_sources(cfg)
+    kappa = kappa_for(cfg)
+    log(f"inputs {cfg.name} dims={cfg.dims} kappa={kappa} nrhs={cfg.nrhs} ({time.time() - t_gen:.1f} s)")
+    Ud = torch.from_numpy(U).to(dev)
+    phid = torch.from_numpy(phi).to(dev)
+    solver = SeedCG(Ud, cfg.dims, kappa, t_bc=cfg.t_bc, prec=prec, reorth_k=cfg.reorth_k, past=cfg.past,
+                    tol=cfg.tol, reliable_every=cfg.reliable_every)
+    B = solver.apply_A(phid, dagger=True)   # b = A^dag phi (input preparation, not timed)
+    nrhs = B.shape[0]
+    torch.cuda.synchronize()
+
+    def step():
+        X = torch.zeros_like(B)
+        X, rs = solver.solve_seed(B, X)
+        X, rr = solver.solve_rest(B, X)
+        return X, rs, rr
+
+    for w in range(args.warmup):
+        _, rs, rr = step()
+        log(f"warmup {w}: m={rs['m']} i_conv={rs['i_conv']} seed {rs['t_seed_s']:.3f}s rest {rr['t_rest_s']:.3f}s "
+            f"iters={rr['iters']}")
+
+    solver.set_timing(args.sample_every, 8192)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reports = []
+    solved = 0
+    for k in range(args.steps):
+        X, rs, rr = step()
+        reports.append((rs, rr))
+        solved += sum(1 for r in rr["true_relres"] if r <= cfg.tol)
+        log(f"step {k}: m={rs['m']} seed {rs['t_seed_s']:.3f}s rest {rr['t_rest_s']:.3f}s "
+            f"max relres {max(rr['true_relres']):.2e}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tm = solver.get_timing()
+    solver.set_timing(0, 0)
+    elapsed = t1 - t0
+    value = solved / elapsed
+
+    # D^dag D rate: back-to-back M applications on resident vectors (12 right-hand sides at once
+    # and one at a time), bytes per M from the algorithmic model 288 V s_link + 120 V s_spinor per vector
+    V = int(np.prod(cfg.dims))
+    s_l = 8.0 if prec == "fp64" else (4.0 if prec == "mixed" else 2.0)
+    s_s = 8.0 if prec == "fp64" else 4.0
+    x1 = B[:1].clone()
+    for _ in range(3):
+        solver.apply_M(x1)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    for _ in range(args.mbench):
+        solver.apply_M(x1)
+    torch.cuda.synchronize()
+    t_m_api = (time.perf_counter() - ta) / args.mbench
+
+    # roofline of the dominant kernel (the Wilson hop), measured live over the timed region
+    hop_ms = tm["ms"] / max(tm["launches"], 1)
+    hop_bytes = tm["bytes"] / max(tm["launches"], 1)
+    achieved = hop_bytes / (hop_ms * 1e-3) / 1e9 if tm["launches"] else None
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                "kernel": "hop_kernel (even-odd Wilson hop, fused epilogues)", "launches_sampled": tm["launches"],
+                "avg_launch_us": hop_ms * 1e3, "avg_launch_bytes": hop_bytes}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(cfg, U, phi, kappa, reports[-1], args.cpu_iters)
+
+    rs, rr = reports[-1]
+    result = {
+        "metric": METRIC, "value": value, "unit": "RHS/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if prec == "fp64" else f"f32+f64({prec})",
+        "data": "synthetic",
+        "config": {"workload": f"Seed-CG {prec}, Wilson even-odd normal system M = A^dag A on "
+                               f"{'x'.join(map(str, cfg.dims))}, {cfg.nrhs} RHS, tol {cfg.tol:g}, k={cfg.reorth_k}",
+                   "name": cfg.name, "lattice": list(cfg.dims), "kappa": kappa, "nrhs": nrhs,
+                   "reorth_k": cfg.reorth_k, "past_factor": cfg.past, "tol": cfg.tol, "precision": prec},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "detail": {"m": rs["m"], "i_conv": rs["i_conv"], "seed_status": rs["seed_status"],
+                   "t_seed_s": rs["t_seed_s"], "t_rest_s": rr["t_rest_s"], "cg_iters": rr["iters"],
+                   "max_true_relres": max(rr["true_relres"]),
+                   "dagger_d_gbs_api": (288 * V * s_l + 120 * V * s_s) / t_m_api / 1e9,
+                   "dagger_d_us_api": t_m_api * 1e6,
+                   "hop_launches_total": tm["seen"]},
+    }
+    print(json.dumps(result), flush=True)
+
+
+def cpu_baseline(cfg, U, phi, kappa, rep, n_iter):
+    """The FP64 oracle on the host cores, on a bounded sample: n_iter steps of Algorithm 1 on all
+    right-hand sides and n_iter CG steps on one, scaled by the GPU run's iteration counts to RHS/s."""
+    import numpy as np
+    from oracle import seedcg as osc
+    from oracle.wilson import WilsonEO, flat, matvec_M, num_threads
+    op = WilsonEO(U, cfg.dims, kappa, t_bc=cfg.t_bc)
+    mv = matvec_M(op)
+    B = flat(op.apply_Adag(phi))
+    # (1) Algorithm 1 without step 8: cost per Lanczos step with the seeding of every RHS
+    t0 = time.perf_counter()
+    osc.seed_cg(mv, B, k=0, tol=cfg.tol, m=n_iter)
+    t_step = (time.perf_counter() - t0) / n_iter
+    # (2) the same with step 8 at every step: the extra time per basis vector reorthogonalised against
+    t0 = time.perf_counter()
+    osc.seed_cg(mv, B, k=1, tol=cfg.tol, m=n_iter)
+    t_k1 = time.perf_counter() - t0
+    t_vec = max(0.0, t_k1 - t_step * n_iter) / (n_iter * (n_iter + 1) / 2.0)
+    # (3) plain CG steps
+    t0 = time.perf_counter()
+    osc.cg(mv, B[1], None, tol=1e-300, max_iter=n_iter)
+    t_cg = (time.perf_counter() - t0) / n_iter
+    rs, rr = rep
+    m, k = rs["m"], cfg.reorth_k
+    reorth_vecs = sum(range(k, m + 1, k)) if k else 0
+    t_total = m * t_step + reorth_vecs * t_vec + sum(rr["iters"]) * t_cg
+    return {"value": cfg.nrhs / t_total, "unit": "RHS/s", "cores": num_threads(), "kind": "oracle",
+            "sample": f"{n_iter} Algorithm-1 steps on {cfg.nrhs} RHS without and with reorthogonalisation "
+                      f"({t_step:.3f} s/step, {t_vec * 1e3:.2f} ms per basis vector reorthogonalised against) and "
+                      f"{n_iter} CG steps ({t_cg:.3f} s/step) on {'x'.join(map(str, cfg.dims))}, extrapolated to the "
+                      f"GPU run's m={m}, {reorth_vecs} vector reorthogonalisations and {sum(rr['iters'])} CG steps"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,158 @@
+/*
+ * seedcg.h -- C ABI of the MI355X (gfx950) Seed-CG library.
+ *
+ * Solves the multiple right-hand-side systems M x^j = b^j, j = 1..nrhs (section 2 of
+ * Abdel-Rehim, Morgan and Wilcox, "Seed methods for linear equations in lattice QCD
+ * problems with multiple right-hand sides", LATTICE 2008), where M = A^dag A is the
+ * normal operator of the even-odd preconditioned Wilson-Dirac matrix
+ * A = 1 - kappa^2 H_eo H_oe (section 3).  The first right-hand side is solved by the
+ * Lanczos form of CG run past convergence with periodic reorthogonalisation, every other
+ * right-hand side is seeded by the Galerkin projection of Eq. (1) through the LU
+ * factorisation of the Lanczos tridiagonal T of Eq. (2) (Algorithm 1, Seed-CG(m, k)),
+ * and all of them are then finished with plain CG from the seeded guesses.
+ *
+ * Conventions shared by every call:
+ *  - Array arguments are DEVICE pointers on the handle's device unless a comment says
+ *    HOST; the caller owns them and keeps them valid for the duration of the call.
+ *  - Complex numbers are interleaved (re, im) doubles.
+ *  - Site index s = x + Lx*(y + Ly*(z + Lz*t)), parity (x+y+z+t) mod 2.  An even-site
+ *    vector lists the Vh = V/2 even sites in increasing s and holds [spin 4][colour 3]
+ *    complex numbers per site (12*Vh complex per vector); a batch of n vectors is n
+ *    such vectors back to back.  Spin uses the Euclidean chiral basis
+ *    gamma_5 = diag(1, 1, -1, -1).
+ *  - Links: U[mu][s][a][b], mu = x, y, z, t, complex, U_mu(s) joins s to s + mu-hat.
+ *    The fermion boundary sign in t (params.t_bc) is applied by the library.
+ *  - Every call enqueues its GPU work on params.stream and returns when that work is
+ *    complete.  One host thread per handle.
+ *  - No C++ exception crosses this boundary; failures return a negative status and
+ *    seedcg_last_error() describes the last failure of that handle.
+ */
+#ifndef SEEDCG_H
+#define SEEDCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct seedcg_s* seedcg_t;
+
+typedef enum {
+    SEEDCG_OK = 0,
+    SEEDCG_ERR_ARG = -1,        /* invalid argument: null pointer, odd extent, bad size     */
+    SEEDCG_ERR_OOM = -2,        /* device allocation failed                                 */
+    SEEDCG_ERR_HIP = -3,        /* a HIP runtime call failed                                */
+    SEEDCG_ERR_BREAKDOWN = -4,  /* the method broke down and could not recover              */
+    SEEDCG_ERR_NOCONV = -5,     /* max_iter reached; X holds the last iterate               */
+    SEEDCG_ERR_STATE = -6       /* call out of order (e.g. seed data missing)              */
+} seedcg_status;
+
+typedef enum {
+    SEEDCG_FP64 = 0,                 /* all vectors, links and arithmetic in FP64            */
+    SEEDCG_MIXED_FP32 = 1,           /* FP32 stencil/basis/CG, FP64 reliable updates         */
+    SEEDCG_MIXED_FP32_BF16LINKS = 2  /* as MIXED_FP32 with the sloppy links stored as BF16   */
+} seedcg_prec;
+
+typedef struct {
+    int32_t dims[4];          /* Lx, Ly, Lz, Lt: each even and >= 2                              */
+    double kappa;             /* hopping parameter (Wilson r = 1)                                */
+    int32_t t_bc;             /* -1: antiperiodic in t, +1: periodic                             */
+    int32_t prec;             /* seedcg_prec                                                     */
+    int32_t m_max;            /* Krylov basis capacity (vectors); 0 = fit to free HBM            */
+    int32_t reorth_k;         /* periodic reorthogonalisation every k iterations; 0 = never      */
+    double past_factor;       /* m = ceil(past_factor * i_conv) (Algorithm 1 run past convergence);
+                                 <= 0 means m = m_max exactly (the paper's fixed m)             */
+    double tol;               /* relative residual ||b - M x|| / ||b|| judged in FP64            */
+    int32_t reliable_every;   /* mixed precision: FP64 r = b - M x every n CG iterations         */
+    int32_t seed_block;       /* seeding GEMM block b (1..32); 0 = 32                             */
+    int32_t max_iter;         /* CG iterations per right-hand side in solve_rest                 */
+    int32_t precond;          /* 0: none                                                         */
+    void* stream;             /* hipStream_t; NULL = the null stream                             */
+} seedcg_params;
+
+typedef struct {
+    /* HOST arrays of length nrhs supplied by the caller (each may be NULL) */
+    int32_t* iters;           /* CG iterations in solve_rest (Lanczos steps m for RHS 1 in solve_seed) */
+    int32_t* matvecs;         /* applications of M                                                     */
+    double* true_relres;      /* FP64 ||b - M x|| / ||b|| on return                                    */
+    /* filled by the library */
+    int32_t m_used;           /* Lanczos steps taken by solve_seed                                     */
+    int32_t i_conv;           /* first step whose residual estimate met tol (0 = never)                 */
+    int32_t seed_status;      /* 0 ok, 1 breakdown (invariant subspace), 2 indefinite, 3 capped         */
+    int32_t reorth_passes;    /* Gram-Schmidt passes (a DGKS repeat counts as a pass)                   */
+    double t_seed_s;          /* wall seconds of solve_seed                                            */
+    double t_rest_s;          /* wall seconds of solve_rest                                            */
+} seedcg_report;
+
+/* Fills *p with the defaults: t_bc = -1, FP64, m_max = 0, reorth_k = 10, past_factor = 1.5,
+   tol = 1e-10, reliable_every = 50, seed_block = 32, max_iter = 100000, precond = 0. */
+void seedcg_default_params(seedcg_params* p);
+
+/* Creates a solver for one gauge configuration.  links: device, 4*V*9 complex (layout above),
+   read once and repacked into the library's own copy.  On success *out owns the copy. */
+seedcg_status seedcg_create(const seedcg_params* p, const double* links, seedcg_t* out);
+
+/* y = M x for nvec even-site vectors (section 3: M = A^dag A).  x and y may not alias. */
+seedcg_status seedcg_apply_M(seedcg_t h, const double* x, double* y, int32_t nvec);
+
+/* y = A x (dagger = 0) or y = A^dag x (dagger = 1), A = 1 - kappa^2 H_eo H_oe (section 3);
+   the caller forms the normal-equation right-hand side b = A^dag phi with dagger = 1. */
+seedcg_status seedcg_apply_A(seedcg_t h, const double* x, double* y, int32_t nvec, int32_t dagger);
+
+/* Algorithm 1, Seed-CG(m, k): B (nrhs vectors) is read only; X holds x_0^j on entry and, on
+   return, the RHS-1 iterate after m Lanczos steps in X[0] and the Galerkin-seeded guesses of
+   Eq. (1) in X[1..nrhs-1].  The handle keeps the basis and T for seedcg_get_tridiag.
+   A breakdown of the seed (invariant subspace or lost definiteness) is reported in
+   r->seed_status and is not an error: solve_rest finishes every right-hand side. */
+seedcg_status seedcg_solve_seed(seedcg_t h, const double* B, double* X, int32_t nrhs, seedcg_report* r);
+
+/* Plain CG on every right-hand side whose FP64 true residual exceeds tol, starting from X
+   (section 2: the seeded guesses are finished by a standard CG solver).  Returns
+   SEEDCG_ERR_NOCONV if some right-hand side reached max_iter; X then holds its last iterate. */
+seedcg_status seedcg_solve_rest(seedcg_t h, const double* B, double* X, int32_t nrhs, seedcg_report* r);
+
+/* Copies the Lanczos coefficients of the last solve_seed to HOST arrays: alpha_1..alpha_m into
+   alpha[0..m-1] and beta_0..beta_m into beta[0..m]; cap is the length of alpha (beta needs cap+1).
+   *m receives m.  Eq. (2) defines T from these. */
+seedcg_status seedcg_get_tridiag(seedcg_t h, double* alpha, double* beta, int32_t cap, int32_t* m);
+
+/* Copies basis vector v_i (1 <= i <= m, as stored after any reorthogonalisation) to the
+   device vector v in the even-site layout. */
+seedcg_status seedcg_get_basis_vector(seedcg_t h, int32_t i, double* v);
+
+/* Building blocks of Algorithm 1 steps 4, 7 and 8 on flat complex vectors (device pointers,
+   any common element order): P = V^dag R, with V nv vectors and R nr vectors of n complex
+   each, P an nv x nr row-major complex matrix (device).  This is the dense contraction that
+   seeds the other right-hand sides and computes the reorthogonalisation coefficients. */
+seedcg_status seedcg_project(seedcg_t h, const double* Vv, int32_t nv, const double* R, int32_t nr,
+                             int64_t n, double* P);
+
+/* X += W E: W nw vectors, E an nw x nx row-major complex matrix (device), X nx vectors,
+   n complex each (the seeding update of Algorithm 1 step 7, x^j += eta^j w_i, blocked). */
+seedcg_status seedcg_update(seedcg_t h, const double* W, int32_t nw, const double* E, double* X,
+                            int32_t nx, int64_t n);
+
+/* Measurement support: from now on every sample_every-th launch of the stencil kernel (the
+   Wilson hop of section 3, the dominant kernel) is bracketed by a pair of hipEvents on the
+   handle's stream, up to max_samples pairs; 0 turns sampling off.  Resets the counters. */
+seedcg_status seedcg_set_timing(seedcg_t h, int32_t sample_every, int32_t max_samples);
+
+/* Reads the sampled stencil timings into out[5] (HOST): number of sampled launches, their total
+   milliseconds, their total algorithmic bytes (links once per launch, every spinor operand once),
+   their total flops (1320 per site and vector), and the number of stencil launches seen. */
+seedcg_status seedcg_get_timing(seedcg_t h, double* out);
+
+/* Frees the Krylov basis (the paper allocates it for the first right-hand side only). */
+seedcg_status seedcg_release_basis(seedcg_t h);
+
+void seedcg_destroy(seedcg_t h);
+
+/* Text of the last failure on h (or of the last failed create when h is NULL). */
+const char* seedcg_last_error(seedcg_t h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEEDCG_H */

@@ -3,9 +3,13 @@
 The workloads ask for lambda_min(M)/lambda_max(M) of M = A^dag A near a target ratio.
 Rule: scan kappa upward from 0.10 (step 0.01, 0.05 above 0.30) to the first kappa whose
 ratio is below the target, then bisect between the last two scan points until
-|log10(ratio / target)| <= 0.05.  The extreme eigenvalues come from a dense eigvalsh
-while 12*Vh <= 3072, otherwise from a plain Lanczos run (three-term recurrence, Ritz
-values of T), which converges to the extremes from inside the spectrum.
+|log10(ratio / target)| <= 0.05.  If the ratio turns upward before reaching the target (a
+local minimum of the ratio near the critical kappa), the minimum is refined by golden-section
+search; if the refined minimum lies below the target the left flank is bisected to the target,
+otherwise the minimum is kept and the target is recorded as unreachable on this configuration.
+The extreme eigenvalues come from a dense eigvalsh while 12*Vh <= 3072, otherwise from a plain
+Lanczos run (three-term recurrence, Ritz values of T) stopped when the residual bound of the
+lowest Ritz pair, beta_i |s_i|, is below 2% of that Ritz value.
 
 Usage: python -m oracle.kappa_search c1 c2 ...
 This is a data-preparation script of the oracle: its output is an input of the workloads.
@@ -17,7 +21,7 @@ import sys
 import time
 
 import numpy as np
-from scipy.linalg import eigvalsh_tridiagonal
+from scipy.linalg import eigh_tridiagonal, eigvalsh_tridiagonal
 
 from oracle.wilson import WilsonEO, dense, flat, matvec_M
 
@@ -32,8 +36,8 @@ def extremes_dense(op):
     return float(lam[0]), float(lam[-1]), "dense"
 
 
-def extremes_lanczos(op, seed=12345, rtol=2e-3, max_iter=6000, log=None):
-    """Plain Lanczos from a random start; stop when the lowest Ritz value moved < rtol over 100 steps."""
+def extremes_lanczos(op, seed=12345, rtol=2e-2, max_iter=8000, log=None):
+    """Plain Lanczos from a random start; stop when the lowest Ritz pair has residual <= rtol * theta."""
     mv = matvec_M(op)
     rng = np.random.default_rng(seed)
     N = 12 * op.Vh
@@ -52,13 +56,15 @@ def extremes_lanczos(op, seed=12345, rtol=2e-3, max_iter=6000, log=None):
         a_list.append(a)
         b_list.append(b)
         if i % 50 == 0 or b < 1e-12:
-            th = eigvalsh_tridiagonal(np.array(a_list), np.array(b_list[:-1]))
-            lo, hi = float(th[0]), float(th[-1])
+            th, S = eigh_tridiagonal(np.array(a_list), np.array(b_list[:-1]), select="i", select_range=(0, 0))
+            lo = float(th[0])
+            hi = float(eigvalsh_tridiagonal(np.array(a_list), np.array(b_list[:-1]), select="i",
+                                            select_range=(i - 1, i - 1))[0])
+            resid = abs(b * S[-1, 0])
             lo_hist.append((i, lo))
             if log:
-                log(f"    lanczos it={i} theta_min={lo:.6e} theta_max={hi:.6e}")
-            old = [x for (j, x) in lo_hist if j <= i - 100]
-            if (old and abs(old[-1] - lo) <= rtol * lo) or b < 1e-12:
+                log(f"    lanczos it={i} theta_min={lo:.6e} resid={resid:.2e} theta_max={hi:.6e}")
+            if resid <= rtol * lo or b < 1e-12:
                 break
         v_prev, v = v, f / b
         b_prev = b
@@ -83,14 +89,43 @@ def search(links, dims, target, t_bc=-1, log=print):
         log(f"  kappa={k:.6f} ratio={r:.4e} ({how})")
         return math.log10(r / target), r, lo, hi
 
+    hist = []
     k_prev, k = None, 0.10
     g, r, lo, hi = f(k)
+    hist.append((k, g, r, lo, hi))
+    unreachable = False
     while g > 0:
         k_prev = k
         k = round(k + (0.01 if k < 0.30 - 1e-12 else 0.05), 6)
         if k > 2.0:
             raise RuntimeError("no kappa below 2.0 reaches the target ratio")
         g, r, lo, hi = f(k)
+        hist.append((k, g, r, lo, hi))
+        if g > 0 and len(hist) >= 3 and hist[-2][1] < hist[-3][1] and hist[-2][1] < g:
+            # the ratio turned upward: refine the local minimum between the last three points
+            a, b = hist[-3][0], hist[-1][0]
+            phi = (math.sqrt(5.0) - 1.0) / 2.0
+            c, d = b - phi * (b - a), a + phi * (b - a)
+            fc, fd = f(c), f(d)
+            while b - a > 1e-3 and fc[0] > 0 and fd[0] > 0:
+                if fc[0] < fd[0]:
+                    b, d, fd = d, c, fc
+                    c = b - phi * (b - a)
+                    fc = f(c)
+                else:
+                    a, c, fc = c, d, fd
+                    d = a + phi * (b - a)
+                    fd = f(d)
+            kmin, fmin = (c, fc) if fc[0] < fd[0] else (d, fd)
+            if fmin[0] > 0.05:
+                g, r, lo, hi = fmin
+                unreachable = True
+                return dict(kappa=kmin, ratio=r, lambda_min=lo, lambda_max=hi, target=target,
+                            target_unreachable=True, beyond_physical=bool(kmin > 0.25), evaluations=evals)
+            # the dip reaches the target: bisect its left flank
+            k_prev, k, g = hist[-3][0], kmin, fmin[0]
+            r, lo, hi = fmin[1], fmin[2], fmin[3]
+            break
     if k_prev is None:
         raise RuntimeError("target already met at kappa = 0.10")
     a, b = k_prev, k           # f(a) > 0 >= f(b)
@@ -107,7 +142,7 @@ def search(links, dims, target, t_bc=-1, log=print):
         if b - a < 1e-7:
             break
     _, k, r, lo, hi = best
-    return dict(kappa=k, ratio=r, lambda_min=lo, lambda_max=hi, target=target,
+    return dict(kappa=k, ratio=r, lambda_min=lo, lambda_max=hi, target=target, target_unreachable=False,
                 beyond_physical=bool(k > 0.25), evaluations=evals)
 
 

@@ -1,0 +1,8 @@
+"""Seed-CG on AMD MI355X (gfx950): HIP kernels behind a C ABI, with a thin Python binding.
+
+Build with paper_0901_3512_amd.build.build(); the binding refuses to run without the
+compiled library.
+"""
+from .seedcg import SeedCG, SeedCGError, load_library, LIB_PATH, exported_symbols
+
+__all__ = ["SeedCG", "SeedCGError", "load_library", "LIB_PATH", "exported_symbols"]

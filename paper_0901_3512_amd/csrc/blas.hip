@@ -1,0 +1,685 @@
+// Vector kernels of Algorithm 1 and of plain CG, and the one-workgroup scalar kernels that
+// keep every recurrence on the device (no host round trip inside an iteration).
+//
+// Every reduction is deterministic: a fixed shuffle tree per block, then the block
+// partials are summed in index order by one workgroup.
+#include "kernels.h"
+
+namespace scg {
+
+// ---------------------------------------------------------------------------------------------
+// layout conversion at the C ABI boundary
+// ---------------------------------------------------------------------------------------------
+template <typename S>
+__device__ inline S conv_link(cx<double> u);
+template <>
+__device__ inline cx<double> conv_link<cx<double>>(cx<double> u) { return u; }
+template <>
+__device__ inline cx<float> conv_link<cx<float>>(cx<double> u) { return mk<float>((float)u.re, (float)u.im); }
+__device__ inline uint32_t bf16_bits(float f) {
+    // round to nearest even
+    uint32_t b = __float_as_uint(f);
+    uint32_t lsb = (b >> 16) & 1u;
+    b += 0x7fffu + lsb;
+    return b >> 16;
+}
+template <>
+__device__ inline uint32_t conv_link<uint32_t>(cx<double> u) {
+    return bf16_bits((float)u.re) | (bf16_bits((float)u.im) << 16);
+}
+
+template <typename S>
+__global__ void pack_links_kernel(Geom g, const cx<double>* __restrict__ U, S* __restrict__ out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= 4 * g.V) return;
+    const int mu = (int)(k / g.V);
+    const int64_t s = k % g.V;
+    const int x = (int)(s % g.L[0]);
+    int64_t r = s / g.L[0];
+    const int y = (int)(r % g.L[1]);
+    r /= g.L[1];
+    const int z = (int)(r % g.L[2]);
+    const int t = (int)(r / g.L[2]);
+    const int par = (x + y + z + t) & 1;
+    const int64_t h = s >> 1;
+    for (int c = 0; c < 9; c++) out[((int64_t)(mu * 2 + par) * 9 + c) * g.Vh + h] = conv_link<S>(U[k * 9 + c]);
+}
+
+void pack_links(Prec prec, const Geom& g, const double* U, void* out, hipStream_t s) {
+    const int64_t n = 4 * g.V;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (prec == P64)
+        hipLaunchKernelGGL(pack_links_kernel<cx<double>>, grid, dim3(256), 0, s, g, (const cx<double>*)U, (cx<double>*)out);
+    else if (prec == P32)
+        hipLaunchKernelGGL(pack_links_kernel<cx<float>>, grid, dim3(256), 0, s, g, (const cx<double>*)U, (cx<float>*)out);
+    else
+        hipLaunchKernelGGL(pack_links_kernel<uint32_t>, grid, dim3(256), 0, s, g, (const cx<double>*)U, (uint32_t*)out);
+}
+
+// canonical [n][Vh][12] (FP64)  <->  internal [n][12][Vh] (T)
+template <typename T>
+__global__ void pack_vec_kernel(const cx<double>* __restrict__ in, cx<T>* __restrict__ out, int64_t Vh, int64_t total) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (vec, c, h), h fastest
+    if (k >= total) return;
+    const int64_t h = k % Vh;
+    const int64_t c = (k / Vh) % 12;
+    const int64_t v = k / (12 * Vh);
+    const cx<double> a = in[(v * Vh + h) * 12 + c];
+    out[k] = mk<T>((T)a.re, (T)a.im);
+}
+template <typename T>
+__global__ void unpack_vec_kernel(const cx<T>* __restrict__ in, cx<double>* __restrict__ out, int64_t Vh, int64_t total) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= total) return;
+    const int64_t h = k % Vh;
+    const int64_t c = (k / Vh) % 12;
+    const int64_t v = k / (12 * Vh);
+    const cx<T> a = in[k];
+    out[(v * Vh + h) * 12 + c] = mk<double>((double)a.re, (double)a.im);
+}
+
+void pack_vec(bool fp32, const double* in, void* out, int64_t Vh, int nvec, hipStream_t s) {
+    const int64_t total = 12 * Vh * nvec;
+    const dim3 grid((unsigned)((total + 255) / 256));
+    if (fp32)
+        hipLaunchKernelGGL(pack_vec_kernel<float>, grid, dim3(256), 0, s, (const cx<double>*)in, (cx<float>*)out, Vh, total);
+    else
+        hipLaunchKernelGGL(pack_vec_kernel<double>, grid, dim3(256), 0, s, (const cx<double>*)in, (cx<double>*)out, Vh, total);
+}
+void unpack_vec(bool fp32, const void* in, double* out, int64_t Vh, int nvec, hipStream_t s) {
+    const int64_t total = 12 * Vh * nvec;
+    const dim3 grid((unsigned)((total + 255) / 256));
+    if (fp32)
+        hipLaunchKernelGGL(unpack_vec_kernel<float>, grid, dim3(256), 0, s, (const cx<float>*)in, (cx<double>*)out, Vh, total);
+    else
+        hipLaunchKernelGGL(unpack_vec_kernel<double>, grid, dim3(256), 0, s, (const cx<double>*)in, (cx<double>*)out, Vh, total);
+}
+
+// ---------------------------------------------------------------------------------------------
+// small vector helpers
+// ---------------------------------------------------------------------------------------------
+template <typename TA, typename TB>
+__global__ void convert_kernel(const cx<TA>* __restrict__ a, cx<TB>* __restrict__ b, int64_t n) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) b[k] = mk<TB>((TB)a[k].re, (TB)a[k].im);
+}
+void convert(bool from32, bool to32, const void* a, void* b, int64_t n, hipStream_t s) {
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (!from32 && to32)
+        hipLaunchKernelGGL((convert_kernel<double, float>), grid, dim3(256), 0, s, (const cx<double>*)a, (cx<float>*)b, n);
+    else if (from32 && !to32)
+        hipLaunchKernelGGL((convert_kernel<float, double>), grid, dim3(256), 0, s, (const cx<float>*)a, (cx<double>*)b, n);
+    else if (from32)
+        hipLaunchKernelGGL((convert_kernel<float, float>), grid, dim3(256), 0, s, (const cx<float>*)a, (cx<float>*)b, n);
+    else
+        hipLaunchKernelGGL((convert_kernel<double, double>), grid, dim3(256), 0, s, (const cx<double>*)a, (cx<double>*)b, n);
+}
+
+// partial sums of |a|^2 per block, for vector v of a batch (grid: blocks x nvec)
+template <typename T>
+__global__ void norm2_kernel(const cx<T>* __restrict__ a, int64_t n, double* part, int64_t nb) {
+    __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    const int64_t v = blockIdx.y;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    if (k < n) {
+        const cx<T> x = a[v * n + k];
+        s = (double)x.re * x.re + (double)x.im * x.im;
+    }
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) part[v * nb + blockIdx.x] = s;
+}
+void norm2_partials(bool fp32, const void* a, int64_t n, int nvec, double* part, hipStream_t st) {
+    const int64_t nb = (n + SCG_BLOCK - 1) / SCG_BLOCK;
+    if (fp32)
+        hipLaunchKernelGGL(norm2_kernel<float>, dim3((unsigned)nb, nvec), dim3(SCG_BLOCK), 0, st, (const cx<float>*)a, n, part, nb);
+    else
+        hipLaunchKernelGGL(norm2_kernel<double>, dim3((unsigned)nb, nvec), dim3(SCG_BLOCK), 0, st, (const cx<double>*)a, n, part, nb);
+}
+int64_t norm2_blocks(int64_t n) { return (n + SCG_BLOCK - 1) / SCG_BLOCK; }
+
+// out[v] = sum_k part[v * nb + k] (one workgroup per v)
+__global__ void sum_partials_kernel(const double* part, int64_t nb, double* out, int sqrt_out) {
+    __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    const double s = block_sum_array(part + (int64_t)blockIdx.x * nb, nb, lds);
+    if (threadIdx.x == 0) out[blockIdx.x] = sqrt_out ? sqrt(s) : s;
+}
+void sum_partials(const double* part, int64_t nb, int nvec, double* out, bool sqrt_out, hipStream_t s) {
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(nvec), dim3(SCG_BLOCK), 0, s, part, nb, out, (int)sqrt_out);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Algorithm 1: Lanczos vectors and the LU recurrences
+// ---------------------------------------------------------------------------------------------
+// Start: beta_0 = ||r_0^1|| (from partials), v_1 = r_0^1 / beta_0, bnorm1 from its partials.
+template <typename T>
+__global__ void lz_start_kernel(LzState* st, const double* r2part, int64_t nb, const double* b2part, double* beta) {
+    __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    const double r2 = block_sum_array(r2part, nb, lds);
+    __syncthreads();
+    const double b2 = block_sum_array(b2part, nb, lds);
+    if (threadIdx.x == 0) {
+        st->beta0 = sqrt(r2);
+        st->bnorm1 = sqrt(b2);
+        beta[0] = st->beta0;
+        if (!(st->beta0 > 0.0)) {  // zero residual: nothing to do
+            st->done = 1;
+            st->m = 0;
+        }
+    }
+}
+void lz_start(LzState* st, const double* r2part, int64_t nb, const double* b2part, double* beta, hipStream_t s) {
+    hipLaunchKernelGGL(lz_start_kernel<double>, dim3(1), dim3(SCG_BLOCK), 0, s, st, r2part, nb, b2part, beta);
+}
+
+template <typename T>
+__global__ void scale_from_kernel(const LzState* st, const cx<T>* __restrict__ r, cx<T>* __restrict__ v, int64_t n) {
+    if (st->done) return;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double inv = 1.0 / st->beta0;
+    const cx<T> a = r[k];
+    v[k] = mk<T>((T)(a.re * inv), (T)(a.im * inv));
+}
+void lz_first_vector(bool fp32, const LzState* st, const void* r, void* v, int64_t n, hipStream_t s) {
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (fp32)
+        hipLaunchKernelGGL(scale_from_kernel<float>, grid, dim3(256), 0, s, st, (const cx<float>*)r, (cx<float>*)v, n);
+    else
+        hipLaunchKernelGGL(scale_from_kernel<double>, grid, dim3(256), 0, s, st, (const cx<double>*)r, (cx<double>*)v, n);
+}
+
+// Step 6 scalars from alpha_i: gamma_{i-1} = beta_{i-1}/delta_{i-1}, delta_i, zeta_i.
+__global__ void lz_alpha_kernel(int i, LzState* st, const double* part, int64_t np, LzArrays a) {
+    __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    if (i > st->m) return;
+    const double al = block_sum_array(part, np, lds);
+    if (threadIdx.x != 0) return;
+    double g, d, z;
+    if (i == 1) {
+        g = 0.0;
+        d = al;
+        z = st->beta0;
+    } else {
+        g = a.beta[i - 1] / a.delta[i - 1];
+        d = al - g * a.beta[i - 1];
+        z = -g * a.zeta[i - 1];
+    }
+    if (!(d > 0.0) || !isfinite(d)) {  // definiteness lost in rounding: end before step i changes anything
+        st->status = 2;
+        st->m = i - 1;
+        st->done = 1;
+        return;
+    }
+    a.alpha[i] = al;
+    a.delta[i] = d;
+    a.gam[i] = g;
+    a.zeta[i] = z;
+    st->max_abs_alpha = fmax(st->max_abs_alpha, fabs(al));
+}
+void lz_alpha(int i, LzState* st, const double* part, int64_t np, const LzArrays& a, hipStream_t s) {
+    hipLaunchKernelGGL(lz_alpha_kernel, dim3(1), dim3(SCG_BLOCK), 0, s, i, st, part, np, a);
+}
+
+// Steps 5-6 vectors: f -= alpha_i v_i (and ||f||^2 partials); w_i = (v_i - beta_{i-1} w_{i-1}) / delta_i;
+// x^1 += zeta_i w_i.
+template <typename T>
+__global__ void lz_update_kernel(int i, const LzState* st, LzArrays a, cx<T>* __restrict__ f, const cx<T>* __restrict__ v,
+                                 const cx<T>* __restrict__ wprev, cx<T>* __restrict__ wout, cx<double>* __restrict__ x1,
+                                 double* f2part, int64_t n) {
+    __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    if (i > st->m) return;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double al = a.alpha[i], d = a.delta[i], z = a.zeta[i];
+    const double bp = i > 1 ? a.beta[i - 1] : 0.0;
+    double s = 0.0;
+    if (k < n) {
+        const cx<T> vv = v[k];
+        cx<T> ff = f[k];
+        ff = mk<T>(ff.re - (T)al * vv.re, ff.im - (T)al * vv.im);
+        f[k] = ff;
+        s = (double)ff.re * ff.re + (double)ff.im * ff.im;
+        double wr = vv.re, wi = vv.im;
+        if (i > 1) {
+            const cx<T> wp = wprev[k];
+            wr -= bp * wp.re;
+            wi -= bp * wp.im;
+        }
+        wr /= d;
+        wi /= d;
+        wout[k] = mk<T>((T)wr, (T)wi);
+        cx<double> xx = x1[k];
+        x1[k] = mk<double>(xx.re + z * wr, xx.im + z * wi);
+    }
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) f2part[blockIdx.x] = s;
+}
+void lz_update(bool fp32, int i, const LzState* st, const LzArrays& a, void* f, const void* v, const void* wprev, void* wout,
+               double* x1, double* f2part, int64_t n, hipStream_t s) {
+    const dim3 grid((unsigned)((n + SCG_BLOCK - 1) / SCG_BLOCK));
+    if (fp32)
+        hipLaunchKernelGGL(lz_update_kernel<float>, grid, dim3(SCG_BLOCK), 0, s, i, st, a, (cx<float>*)f, (const cx<float>*)v,
+                           (const cx<float>*)wprev, (cx<float>*)wout, (cx<double>*)x1, f2part, n);
+    else
+        hipLaunchKernelGGL(lz_update_kernel<double>, grid, dim3(SCG_BLOCK), 0, s, i, st, a, (cx<double>*)f,
+                           (const cx<double>*)v, (const cx<double>*)wprev, (cx<double>*)wout, (cx<double>*)x1, f2part, n);
+}
+
+// Step 9 scalars: beta_i = ||f||, the D-Lanczos residual estimate beta_i |zeta_i/delta_i|, i_conv,
+// m = min(ceil(past * i_conv), m_cap), breakdown.
+__global__ void lz_beta_kernel(int i, LzState* st, const double* part, int64_t np, LzArrays a) {
+    __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    if (i > st->m) return;
+    const double b = sqrt(block_sum_array(part, np, lds));
+    if (threadIdx.x != 0) return;
+    a.beta[i] = b;
+    const double e = b * fabs(a.zeta[i] / a.delta[i]);
+    a.est[i] = e / st->bnorm1;
+    if (st->i_conv == 0 && e <= st->tol * st->bnorm1) {
+        st->i_conv = i;
+        if (st->past > 0.0) {
+            const int mm = (int)ceil(st->past * (double)i);
+            st->m = mm < st->m_cap ? mm : st->m_cap;
+        }
+    }
+    if (b <= 1e-14 * st->max_abs_alpha) {
+        st->status = 1;
+        st->m = i;
+    }
+    if (i >= st->m) {
+        st->m = i;
+        st->done = 1;
+        if (st->status == 0 && st->i_conv == 0 && st->past > 0.0) st->status = 3;
+    }
+}
+void lz_beta(int i, LzState* st, const double* part, int64_t np, const LzArrays& a, hipStream_t s) {
+    hipLaunchKernelGGL(lz_beta_kernel, dim3(1), dim3(SCG_BLOCK), 0, s, i, st, part, np, a);
+}
+
+// Step 9 vector: v_{i+1} = f / beta_i (only when another step follows).
+template <typename T>
+__global__ void lz_next_kernel(int i, const LzState* st, const double* beta, const cx<T>* __restrict__ f,
+                               cx<T>* __restrict__ vn, int64_t n) {
+    if (i >= st->m) return;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double inv = 1.0 / beta[i];
+    const cx<T> a = f[k];
+    vn[k] = mk<T>((T)(a.re * inv), (T)(a.im * inv));
+}
+void lz_next(bool fp32, int i, const LzState* st, const double* beta, const void* f, void* vn, int64_t n, hipStream_t s) {
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (fp32)
+        hipLaunchKernelGGL(lz_next_kernel<float>, grid, dim3(256), 0, s, i, st, beta, (const cx<float>*)f, (cx<float>*)vn, n);
+    else
+        hipLaunchKernelGGL(lz_next_kernel<double>, grid, dim3(256), 0, s, i, st, beta, (const cx<double>*)f, (cx<double>*)vn, n);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Step 7, blocked: eta^j_i = (V^dag r_0^j)_i - gamma_{i-1} eta^j_{i-1} over the rows of a block,
+// then X^j += sum_i eta^j_i w_i.  Rows beyond m (the run ended inside the block) get eta = 0.
+// ---------------------------------------------------------------------------------------------
+__global__ void seed_eta_kernel(int i0, int nb, int nr, const LzState* st, const double* gam, const cx<double>* P,
+                                cx<double>* E, cx<double>* eta_prev, int32_t* nvalid) {
+    const int j = threadIdx.x;
+    const int valid = max(0, min(nb, st->m - i0 + 1));
+    if (j == 0) *nvalid = valid;
+    if (j >= nr) return;
+    cx<double> eta = eta_prev[j];
+    for (int r = 0; r < nb; r++) {
+        if (r < valid) {
+            const double g = gam[i0 + r];
+            const cx<double> p = P[r * nr + j];
+            eta = mk<double>(p.re - g * eta.re, p.im - g * eta.im);
+            E[r * nr + j] = eta;
+        } else {
+            E[r * nr + j] = mk<double>(0.0, 0.0);
+        }
+    }
+    eta_prev[j] = eta;
+}
+void seed_eta(int i0, int nb, int nr, const LzState* st, const double* gam, const double* P, double* E, double* eta_prev,
+              int32_t* nvalid, hipStream_t s) {
+    hipLaunchKernelGGL(seed_eta_kernel, dim3(1), dim3(64), 0, s, i0, nb, nr, st, gam, (const cx<double>*)P, (cx<double>*)E,
+                       (cx<double>*)eta_prev, nvalid);
+}
+
+// X[j] += sum_{r < nrow} W[r] E[r][j]  (flat vectors of n complex; nrow from the device or a constant)
+template <typename T, typename TX>
+__global__ __launch_bounds__(SCG_BLOCK) void seed_update_kernel(const cx<T>* __restrict__ W, int nw, const cx<double>* __restrict__ E,
+                                                                 cx<TX>* __restrict__ X, int nx, int64_t n, const int32_t* nrow_dev) {
+    __shared__ cx<double> e_lds[32 * 48];
+    const int nrow = nrow_dev ? min(*nrow_dev, nw) : nw;
+    if (nrow <= 0) return;
+    for (int k = threadIdx.x; k < nrow * nx; k += blockDim.x) e_lds[k] = E[k];
+    __syncthreads();
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    cx<T> w[32];
+#pragma unroll
+    for (int r = 0; r < 32; r++)
+        if (r < nrow) w[r] = W[(int64_t)r * n + k];
+    for (int j = 0; j < nx; j++) {
+        double ar = 0.0, ai = 0.0;
+#pragma unroll
+        for (int r = 0; r < 32; r++)
+            if (r < nrow) {
+                const cx<double> e = e_lds[r * nx + j];
+                ar += (double)w[r].re * e.re - (double)w[r].im * e.im;
+                ai += (double)w[r].re * e.im + (double)w[r].im * e.re;
+            }
+        cx<TX> x = X[(int64_t)j * n + k];
+        X[(int64_t)j * n + k] = mk<TX>((TX)(x.re + ar), (TX)(x.im + ai));
+    }
+}
+void seed_update(bool w32, bool x32, const void* W, int nw, const double* E, void* X, int nx, int64_t n, const int32_t* nrow_dev,
+                 hipStream_t s) {
+    const dim3 grid((unsigned)((n + SCG_BLOCK - 1) / SCG_BLOCK));
+    if (w32 && x32)
+        hipLaunchKernelGGL((seed_update_kernel<float, float>), grid, dim3(SCG_BLOCK), 0, s, (const cx<float>*)W, nw,
+                           (const cx<double>*)E, (cx<float>*)X, nx, n, nrow_dev);
+    else if (w32)
+        hipLaunchKernelGGL((seed_update_kernel<float, double>), grid, dim3(SCG_BLOCK), 0, s, (const cx<float>*)W, nw,
+                           (const cx<double>*)E, (cx<double>*)X, nx, n, nrow_dev);
+    else
+        hipLaunchKernelGGL((seed_update_kernel<double, double>), grid, dim3(SCG_BLOCK), 0, s, (const cx<double>*)W, nw,
+                           (const cx<double>*)E, (cx<double>*)X, nx, n, nrow_dev);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Step 8: periodic reorthogonalisation of the pair [v_i, f] by classical Gram-Schmidt.
+// G = V_{1..i}^dag [v_i, f] comes from the projection kernel.  Pass 1 always runs; pass 2
+// (the DGKS repeat) runs only for a vector whose norm fell below 1/sqrt(2) of its norm
+// before pass 1.
+// ---------------------------------------------------------------------------------------------
+__device__ inline bool reorth_gate(int i, int pass, const LzState* st, bool& use_v, bool& use_f) {
+    if (i > st->m) return false;
+    use_v = pass == 1 || st->rep_v;
+    use_f = pass == 1 || st->rep_f;
+    return use_v || use_f;
+}
+
+// v' = v - V_{1..i-1} c, f' = f - V_{1..i-1} d with c = G[:,0], d = G[:,1]; partials |v'|^2, v'^dag f'.
+template <typename T>
+__global__ __launch_bounds__(SCG_BLOCK) void reorth_update_kernel(int i, int pass, const LzState* st, const cx<T>* __restrict__ V,
+                                                                   int64_t n, const cx<double>* __restrict__ G,
+                                                                   cx<T>* __restrict__ v, cx<T>* __restrict__ f,
+                                                                   double* part) {
+    __shared__ cx<double> cd[2 * 1024];
+    __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    bool use_v, use_f;
+    if (!reorth_gate(i, pass, st, use_v, use_f)) return;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool act = k < n;
+    double vr = 0, vi = 0, fr = 0, fi = 0;
+    if (act) {
+        const cx<T> a = v[k], b = f[k];
+        vr = a.re; vi = a.im; fr = b.re; fi = b.im;
+    }
+    const int nrows = i - 1;
+    for (int r0 = 0; r0 < nrows; r0 += 1024) {
+        const int nr = min(1024, nrows - r0);
+        __syncthreads();
+        for (int q = threadIdx.x; q < nr; q += blockDim.x) {
+            cd[2 * q] = use_v ? G[2 * (r0 + q)] : mk<double>(0.0, 0.0);
+            cd[2 * q + 1] = use_f ? G[2 * (r0 + q) + 1] : mk<double>(0.0, 0.0);
+        }
+        __syncthreads();
+        if (act) {
+            const cx<T>* Vp = V + (int64_t)r0 * n + k;
+#pragma unroll 8
+            for (int q = 0; q < nr; q++) {
+                const cx<T> b = Vp[(int64_t)q * n];
+                const cx<double> c = cd[2 * q], d = cd[2 * q + 1];
+                const double br = b.re, bi = b.im;
+                vr -= br * c.re - bi * c.im;
+                vi -= br * c.im + bi * c.re;
+                fr -= br * d.re - bi * d.im;
+                fi -= br * d.im + bi * d.re;
+            }
+        }
+    }
+    double p0 = 0, p1 = 0, p2 = 0;
+    if (act) {
+        const cx<T> a = mk<T>((T)vr, (T)vi), b = mk<T>((T)fr, (T)fi);
+        if (use_v) v[k] = a;
+        if (use_f) f[k] = b;
+        // partials of |v'|^2 and v'^dag f' in the stored precision
+        p0 = (double)a.re * a.re + (double)a.im * a.im;
+        p1 = (double)a.re * b.re + (double)a.im * b.im;
+        p2 = (double)a.re * b.im - (double)a.im * b.re;
+    }
+    p0 = block_sum(p0, lds);
+    __syncthreads();
+    p1 = block_sum(p1, lds);
+    __syncthreads();
+    p2 = block_sum(p2, lds);
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x] = p0;
+        part[3 * blockIdx.x + 1] = p1;
+        part[3 * blockIdx.x + 2] = p2;
+    }
+}
+void reorth_update(bool fp32, int i, int pass, const LzState* st, const void* V, int64_t n, const double* G, void* v, void* f,
+                   double* part, hipStream_t s) {
+    const dim3 grid((unsigned)((n + SCG_BLOCK - 1) / SCG_BLOCK));
+    if (fp32)
+        hipLaunchKernelGGL(reorth_update_kernel<float>, grid, dim3(SCG_BLOCK), 0, s, i, pass, st, (const cx<float>*)V, n,
+                           (const cx<double>*)G, (cx<float>*)v, (cx<float>*)f, part);
+    else
+        hipLaunchKernelGGL(reorth_update_kernel<double>, grid, dim3(SCG_BLOCK), 0, s, i, pass, st, (const cx<double>*)V, n,
+                           (const cx<double>*)G, (cx<double>*)v, (cx<double>*)f, part);
+}
+
+// nv = ||v'||, e = v'^dag f' / ||v'||^2; the DGKS test for v (pass 1).
+__global__ void reorth_scalar_kernel(int i, int pass, LzState* st, const double* part, int64_t nb, const cx<double>* G) {
+    __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    bool use_v, use_f;
+    if (!reorth_gate(i, pass, st, use_v, use_f)) return;
+    double s[3];
+    for (int q = 0; q < 3; q++) {
+        double v = 0.0;
+        for (int64_t k = threadIdx.x; k < nb; k += blockDim.x) v += part[3 * k + q];
+        s[q] = block_sum(v, lds);
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    st->nv = sqrt(s[0]);
+    st->e = s[1] / s[0];
+    st->e_im = s[2] / s[0];
+    if (pass == 1) {
+        st->v2_before = G[2 * (i - 1)].re;  // v_i^dag v_i before the pass
+        st->passes += 2;
+    } else {
+        st->passes += (st->rep_v ? 1 : 0) + (st->rep_f ? 1 : 0);
+    }
+}
+void reorth_scalar(int i, int pass, LzState* st, const double* part, int64_t nb, const double* G, hipStream_t s) {
+    hipLaunchKernelGGL(reorth_scalar_kernel, dim3(1), dim3(SCG_BLOCK), 0, s, i, pass, st, part, nb, (const cx<double>*)G);
+}
+
+// v_i = v' / nv; f = f' - e v'; partials of |f|^2 (for beta_i).
+template <typename T>
+__global__ void reorth_finish_kernel(int i, int pass, const LzState* st, cx<T>* __restrict__ v, cx<T>* __restrict__ f,
+                                     double* f2part, int64_t n) {
+    __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    bool use_v, use_f;
+    if (!reorth_gate(i, pass, st, use_v, use_f)) return;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    if (k < n) {
+        const cx<T> a = v[k];
+        cx<T> b = f[k];
+        if (use_f) {
+            const double br = (double)b.re - (st->e * a.re - st->e_im * a.im);
+            const double bi = (double)b.im - (st->e * a.im + st->e_im * a.re);
+            b = mk<T>((T)br, (T)bi);
+            f[k] = b;
+        }
+        if (use_v) {
+            const double inv = 1.0 / st->nv;
+            v[k] = mk<T>((T)(a.re * inv), (T)(a.im * inv));
+        }
+        s = (double)b.re * b.re + (double)b.im * b.im;
+    }
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) f2part[blockIdx.x] = s;
+}
+void reorth_finish(bool fp32, int i, int pass, const LzState* st, void* v, void* f, double* f2part, int64_t n, hipStream_t s) {
+    const dim3 grid((unsigned)((n + SCG_BLOCK - 1) / SCG_BLOCK));
+    if (fp32)
+        hipLaunchKernelGGL(reorth_finish_kernel<float>, grid, dim3(SCG_BLOCK), 0, s, i, pass, st, (cx<float>*)v, (cx<float>*)f,
+                           f2part, n);
+    else
+        hipLaunchKernelGGL(reorth_finish_kernel<double>, grid, dim3(SCG_BLOCK), 0, s, i, pass, st, (cx<double>*)v,
+                           (cx<double>*)f, f2part, n);
+}
+
+// After a pass: decide the DGKS repeats (pass 1) or clear them (pass 2).
+__global__ void reorth_decide_kernel(int i, int pass, LzState* st, const double* f2_before_part, const double* f2_after_part,
+                                     int64_t nb) {
+    __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    if (i > st->m) return;
+    const double fb = block_sum_array(f2_before_part, nb, lds);
+    __syncthreads();
+    const double fa = block_sum_array(f2_after_part, nb, lds);
+    if (threadIdx.x != 0) return;
+    if (pass == 1) {
+        st->f2_before = fb;
+        st->rep_v = (st->nv * st->nv < 0.5 * st->v2_before) ? 1 : 0;
+        st->rep_f = (fa < 0.5 * fb) ? 1 : 0;
+    } else {
+        st->rep_v = 0;
+        st->rep_f = 0;
+    }
+    st->rep_any = st->rep_v | st->rep_f;
+}
+void reorth_decide(int i, int pass, LzState* st, const double* f2b, const double* f2a, int64_t nb, hipStream_t s) {
+    hipLaunchKernelGGL(reorth_decide_kernel, dim3(1), dim3(SCG_BLOCK), 0, s, i, pass, st, f2b, f2a, nb);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Plain CG on a batch of right-hand sides (one CgVec per right-hand side)
+// ---------------------------------------------------------------------------------------------
+__device__ inline bool cg_skip(const CgVec& c) { return c.done || c.frozen; }
+
+// a_j = rr_j / Re(p_j^dag q_j)
+__global__ void cg_alpha_kernel(CgVec* cg, const double* part, int64_t nb, const int32_t* vec_map) {
+    __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    const int vec = vec_map[blockIdx.x];
+    if (cg_skip(cg[vec])) return;
+    const double pq = block_sum_array(part + (int64_t)vec * nb, nb, lds);
+    if (threadIdx.x == 0) {
+        cg[vec].pq = pq;
+        cg[vec].a = cg[vec].rr / pq;
+    }
+}
+void cg_alpha(CgVec* cg, const double* part, int64_t nb, const int32_t* vec_map, int nact, hipStream_t s) {
+    hipLaunchKernelGGL(cg_alpha_kernel, dim3(nact), dim3(SCG_BLOCK), 0, s, cg, part, nb, vec_map);
+}
+
+// x += a p; r -= a q; partials |r|^2
+template <typename T, typename TX>
+__global__ void cg_update_kernel(const CgVec* cg, const int32_t* vec_map, int nact, cx<TX>* __restrict__ X, const cx<T>* __restrict__ P,
+                                 cx<T>* __restrict__ R, const cx<T>* __restrict__ Q, double* part, int64_t n, int64_t nb) {
+    __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    const int slot = blockIdx.y;
+    const int vec = vec_map[slot];
+    if (cg_skip(cg[vec])) return;
+    const double a = cg[vec].a;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    if (k < n) {
+        const int64_t o = (int64_t)vec * n + k;
+        const cx<T> p = P[o], q = Q[o];
+        const cx<TX> x = X[o];
+        X[o] = mk<TX>((TX)(x.re + a * p.re), (TX)(x.im + a * p.im));
+        const cx<T> r = R[o];
+        const cx<T> rn = mk<T>((T)(r.re - a * q.re), (T)(r.im - a * q.im));
+        R[o] = rn;
+        s = (double)rn.re * rn.re + (double)rn.im * rn.im;
+    }
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) part[(int64_t)vec * nb + blockIdx.x] = s;
+}
+void cg_update(bool fp32, bool x32, const CgVec* cg, const int32_t* vec_map, int nact, void* X, const void* P, void* R,
+               const void* Q, double* part, int64_t n, hipStream_t s) {
+    const int64_t nb = (n + SCG_BLOCK - 1) / SCG_BLOCK;
+    const dim3 grid((unsigned)nb, nact);
+    if (fp32 && x32)
+        hipLaunchKernelGGL((cg_update_kernel<float, float>), grid, dim3(SCG_BLOCK), 0, s, cg, vec_map, nact, (cx<float>*)X,
+                           (const cx<float>*)P, (cx<float>*)R, (const cx<float>*)Q, part, n, nb);
+    else if (fp32)
+        hipLaunchKernelGGL((cg_update_kernel<float, double>), grid, dim3(SCG_BLOCK), 0, s, cg, vec_map, nact, (cx<double>*)X,
+                           (const cx<float>*)P, (cx<float>*)R, (const cx<float>*)Q, part, n, nb);
+    else
+        hipLaunchKernelGGL((cg_update_kernel<double, double>), grid, dim3(SCG_BLOCK), 0, s, cg, vec_map, nact, (cx<double>*)X,
+                           (const cx<double>*)P, (cx<double>*)R, (const cx<double>*)Q, part, n, nb);
+}
+
+// rr_new = |r|^2; stop test on the recursive residual (freeze for a true-residual check);
+// b = rr_new / rr
+__global__ void cg_beta_kernel(CgVec* cg, const double* part, int64_t nb, const int32_t* vec_map, int max_iter) {
+    __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    const int vec = vec_map[blockIdx.x];
+    if (cg_skip(cg[vec])) return;
+    const double rr = block_sum_array(part + (int64_t)vec * nb, nb, lds);
+    if (threadIdx.x != 0) return;
+    CgVec& c = cg[vec];
+    c.iters += 1;
+    if (sqrt(rr) <= c.tol * c.bnorm || c.iters >= max_iter || !isfinite(rr)) {
+        c.frozen = 1;  // the host checks the true residual before going on
+        c.pq = rr;
+        return;
+    }
+    c.b = rr / c.rr;
+    c.rr_old = c.rr;
+    c.rr = rr;
+}
+void cg_beta(CgVec* cg, const double* part, int64_t nb, const int32_t* vec_map, int nact, int max_iter, hipStream_t s) {
+    hipLaunchKernelGGL(cg_beta_kernel, dim3(nact), dim3(SCG_BLOCK), 0, s, cg, part, nb, vec_map, max_iter);
+}
+
+// p = r + b p
+template <typename T>
+__global__ void cg_p_kernel(const CgVec* cg, const int32_t* vec_map, cx<T>* __restrict__ P, const cx<T>* __restrict__ R, int64_t n,
+                            int ignore_frozen) {
+    const int vec = vec_map[blockIdx.y];
+    if (cg[vec].done || (cg[vec].frozen && !ignore_frozen)) return;
+    const double b = cg[vec].b;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int64_t o = (int64_t)vec * n + k;
+    const cx<T> p = P[o], r = R[o];
+    P[o] = mk<T>((T)(r.re + b * p.re), (T)(r.im + b * p.im));
+}
+void cg_p(bool fp32, const CgVec* cg, const int32_t* vec_map, int nact, void* P, const void* R, int64_t n, bool ignore_frozen,
+          hipStream_t s) {
+    const dim3 grid((unsigned)((n + 255) / 256), nact);
+    if (fp32)
+        hipLaunchKernelGGL(cg_p_kernel<float>, grid, dim3(256), 0, s, cg, vec_map, (cx<float>*)P, (const cx<float>*)R, n,
+                           (int)ignore_frozen);
+    else
+        hipLaunchKernelGGL(cg_p_kernel<double>, grid, dim3(256), 0, s, cg, vec_map, (cx<double>*)P, (const cx<double>*)R, n,
+                           (int)ignore_frozen);
+}
+
+// gamma5 = diag(1, 1, -1, -1): components 6..11 (spins 2, 3) change sign
+template <typename T>
+__global__ void gamma5_copy_kernel(const cx<T>* a, cx<T>* b, int64_t Vh, int64_t total) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= total) return;
+    const int64_t c = (k / Vh) % 12;
+    const cx<T> v = a[k];
+    b[k] = c >= 6 ? mk<T>(-v.re, -v.im) : v;
+}
+void gamma5_copy(bool fp32, const void* a, void* b, int64_t Vh, int nvec, hipStream_t s) {
+    const int64_t total = 12 * Vh * nvec;
+    const dim3 grid((unsigned)((total + 255) / 256));
+    if (fp32)
+        hipLaunchKernelGGL(gamma5_copy_kernel<float>, grid, dim3(256), 0, s, (const cx<float>*)a, (cx<float>*)b, Vh, total);
+    else
+        hipLaunchKernelGGL(gamma5_copy_kernel<double>, grid, dim3(256), 0, s, (const cx<double>*)a, (cx<double>*)b, Vh, total);
+}
+
+}  // namespace scg

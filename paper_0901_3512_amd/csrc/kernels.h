@@ -1,0 +1,72 @@
+// Launchers of the library's HIP kernels (one declaration per kernel family).
+#pragma once
+#include "internal.h"
+
+namespace scg {
+
+// Device arrays of the Lanczos recurrences, indexed by the step i (1-based).
+struct LzArrays {
+    double* alpha;  // alpha_i
+    double* beta;   // beta_i (beta[0] = beta_0)
+    double* delta;  // delta_i
+    double* gam;    // gamma_{i-1}, the coefficient used at step i (gam[1] = 0)
+    double* zeta;   // zeta_i
+    double* est;    // relative residual estimate after step i
+};
+
+// P = V^dag R contraction (split-K partials then a fixed-order reduction)
+struct ProjArgs {
+    const void* V;          // rows of V, stride ldv complex
+    int64_t ldv;
+    int nv;                 // rows of V
+    const void* R[24];      // the nr vectors of R
+    int nr;
+    int64_t n;              // complex per vector
+    int64_t kchunk;         // complex per workgroup
+    double* part;           // [chunk][nv][nr] complex partials
+    int64_t part_stride;    // doubles per chunk (>= 2 * nv * nr)
+    const LzState* st;      // optional gate: skip when gate_i > st->m
+    int gate_i;
+    int rows_from_m;        // rows beyond st->m - i0 + 1 are treated as absent
+    int i0;
+    const int32_t* flag;    // optional gate: skip when *flag == 0
+};
+void project(bool fp32, const ProjArgs& a, int64_t nrowblocks, double* P, hipStream_t s);
+int64_t proj_chunks(int64_t n, int64_t kchunk);
+
+void pack_links(Prec prec, const Geom& g, const double* U, void* out, hipStream_t s);
+void pack_vec(bool fp32, const double* in, void* out, int64_t Vh, int nvec, hipStream_t s);
+void unpack_vec(bool fp32, const void* in, double* out, int64_t Vh, int nvec, hipStream_t s);
+void gamma5_copy(bool fp32, const void* a, void* b, int64_t Vh, int nvec, hipStream_t s);
+void convert(bool from32, bool to32, const void* a, void* b, int64_t n, hipStream_t s);
+void norm2_partials(bool fp32, const void* a, int64_t n, int nvec, double* part, hipStream_t s);
+int64_t norm2_blocks(int64_t n);
+void sum_partials(const double* part, int64_t nb, int nvec, double* out, bool sqrt_out, hipStream_t s);
+
+void lz_start(LzState* st, const double* r2part, int64_t nb, const double* b2part, double* beta, hipStream_t s);
+void lz_first_vector(bool fp32, const LzState* st, const void* r, void* v, int64_t n, hipStream_t s);
+void lz_alpha(int i, LzState* st, const double* part, int64_t np, const LzArrays& a, hipStream_t s);
+void lz_update(bool fp32, int i, const LzState* st, const LzArrays& a, void* f, const void* v, const void* wprev, void* wout,
+               double* x1, double* f2part, int64_t n, hipStream_t s);
+void lz_beta(int i, LzState* st, const double* part, int64_t np, const LzArrays& a, hipStream_t s);
+void lz_next(bool fp32, int i, const LzState* st, const double* beta, const void* f, void* vn, int64_t n, hipStream_t s);
+
+void seed_eta(int i0, int nb, int nr, const LzState* st, const double* gam, const double* P, double* E, double* eta_prev,
+              int32_t* nvalid, hipStream_t s);
+void seed_update(bool w32, bool x32, const void* W, int nw, const double* E, void* X, int nx, int64_t n, const int32_t* nrow_dev,
+                 hipStream_t s);
+
+void reorth_update(bool fp32, int i, int pass, const LzState* st, const void* V, int64_t n, const double* G, void* v, void* f,
+                   double* part, hipStream_t s);
+void reorth_scalar(int i, int pass, LzState* st, const double* part, int64_t nb, const double* G, hipStream_t s);
+void reorth_finish(bool fp32, int i, int pass, const LzState* st, void* v, void* f, double* f2part, int64_t n, hipStream_t s);
+void reorth_decide(int i, int pass, LzState* st, const double* f2b, const double* f2a, int64_t nb, hipStream_t s);
+
+void cg_alpha(CgVec* cg, const double* part, int64_t nb, const int32_t* vec_map, int nact, hipStream_t s);
+void cg_update(bool fp32, bool x32, const CgVec* cg, const int32_t* vec_map, int nact, void* X, const void* P, void* R,
+               const void* Q, double* part, int64_t n, hipStream_t s);
+void cg_beta(CgVec* cg, const double* part, int64_t nb, const int32_t* vec_map, int nact, int max_iter, hipStream_t s);
+void cg_p(bool fp32, const CgVec* cg, const int32_t* vec_map, int nact, void* P, const void* R, int64_t n, bool ignore_frozen,
+          hipStream_t s);
+
+}  // namespace scg

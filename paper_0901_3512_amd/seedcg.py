@@ -1,0 +1,248 @@
+"""Python binding of the C ABI in include/seedcg.h (ctypes; argument marshalling only).
+
+Every array is a torch tensor on the GPU in the canonical layouts of the C ABI:
+  links (4, V, 3, 3) complex128, vectors (n, Vh, 4, 3) complex128, contiguous.
+All arithmetic runs in the HIP library; if libseedcg.so is missing this module raises.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libseedcg.so")
+
+FP64, MIXED_FP32, MIXED_FP32_BF16LINKS = 0, 1, 2
+_PREC = {"fp64": FP64, "mixed": MIXED_FP32, "mixed_fp32": MIXED_FP32, "mixed_bf16": MIXED_FP32_BF16LINKS}
+STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_OOM", -3: "ERR_HIP", -4: "ERR_BREAKDOWN", -5: "ERR_NOCONV",
+          -6: "ERR_STATE"}
+SEED_STATUS = {0: "ok", 1: "breakdown", 2: "indefinite", 3: "capped"}
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32 * 4), ("kappa", ctypes.c_double), ("t_bc", ctypes.c_int32),
+                ("prec", ctypes.c_int32), ("m_max", ctypes.c_int32), ("reorth_k", ctypes.c_int32),
+                ("past_factor", ctypes.c_double), ("tol", ctypes.c_double), ("reliable_every", ctypes.c_int32),
+                ("seed_block", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("precond", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("iters", ctypes.POINTER(ctypes.c_int32)), ("matvecs", ctypes.POINTER(ctypes.c_int32)),
+                ("true_relres", ctypes.POINTER(ctypes.c_double)), ("m_used", ctypes.c_int32),
+                ("i_conv", ctypes.c_int32), ("seed_status", ctypes.c_int32), ("reorth_passes", ctypes.c_int32),
+                ("t_seed_s", ctypes.c_double), ("t_rest_s", ctypes.c_double)]
+
+
+class SeedCGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library():
+    """Load libseedcg.so (built by paper_0901_3512_amd.build); raises if it is not there."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_0901_3512_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    H = ctypes.c_void_p
+    P = ctypes.c_void_p
+    i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "seedcg_default_params": (None, [ctypes.POINTER(Params)]),
+        "seedcg_create": (i32, [ctypes.POINTER(Params), P, ctypes.POINTER(H)]),
+        "seedcg_apply_M": (i32, [H, P, P, i32]),
+        "seedcg_apply_A": (i32, [H, P, P, i32, i32]),
+        "seedcg_solve_seed": (i32, [H, P, P, i32, ctypes.POINTER(Report)]),
+        "seedcg_solve_rest": (i32, [H, P, P, i32, ctypes.POINTER(Report)]),
+        "seedcg_get_tridiag": (i32, [H, ctypes.POINTER(dbl), ctypes.POINTER(dbl), i32, ctypes.POINTER(i32)]),
+        "seedcg_get_basis_vector": (i32, [H, i32, P]),
+        "seedcg_project": (i32, [H, P, i32, P, i32, i64, P]),
+        "seedcg_update": (i32, [H, P, i32, P, P, i32, i64]),
+        "seedcg_set_timing": (i32, [H, i32, i32]),
+        "seedcg_get_timing": (i32, [H, ctypes.POINTER(dbl)]),
+        "seedcg_release_basis": (i32, [H]),
+        "seedcg_destroy": (None, [H]),
+        "seedcg_last_error": (ctypes.c_char_p, [H]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    """Names of the C ABI entry points this binding expects."""
+    return ["seedcg_default_params", "seedcg_create", "seedcg_apply_M", "seedcg_apply_A", "seedcg_solve_seed",
+            "seedcg_solve_rest", "seedcg_get_tridiag", "seedcg_get_basis_vector", "seedcg_project",
+            "seedcg_update", "seedcg_set_timing", "seedcg_get_timing", "seedcg_release_basis", "seedcg_destroy",
+            "seedcg_last_error"]
+
+
+def _check_vec(t, Vh, name):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or not t.is_cuda:
+        raise TypeError(f"{name}: expected a complex128 CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if t.dim() == 3:
+        t = t.unsqueeze(0)
+    if tuple(t.shape[1:]) != (Vh, 4, 3):
+        raise ValueError(f"{name}: expected shape (n, {Vh}, 4, 3), got {tuple(t.shape)}")
+    return t
+
+
+class SeedCG:
+    """One gauge configuration: M = A^dag A with A = 1 - kappa^2 H_eo H_oe (see include/seedcg.h)."""
+
+    def __init__(self, links, dims, kappa, *, t_bc=-1, prec="fp64", m_max=0, reorth_k=10, past=1.5,
+                 tol=1e-10, reliable_every=50, seed_block=32, max_iter=100000, stream=None):
+        lib = load_library()
+        self.dims = tuple(int(d) for d in dims)
+        self.V = self.dims[0] * self.dims[1] * self.dims[2] * self.dims[3]
+        self.Vh = self.V // 2
+        if not (isinstance(links, torch.Tensor) and links.is_cuda and links.dtype == torch.complex128):
+            raise TypeError("links: expected a complex128 CUDA tensor")
+        if tuple(links.shape) != (4, self.V, 3, 3) or not links.is_contiguous():
+            raise ValueError(f"links: expected a contiguous (4, {self.V}, 3, 3) tensor")
+        self.device = links.device
+        p = Params()
+        lib.seedcg_default_params(ctypes.byref(p))
+        for d in range(4):
+            p.dims[d] = self.dims[d]
+        p.kappa = float(kappa)
+        p.t_bc = int(t_bc)
+        p.prec = _PREC[prec] if isinstance(prec, str) else int(prec)
+        p.m_max = int(m_max)
+        p.reorth_k = int(reorth_k)
+        p.past_factor = float(past)
+        p.tol = float(tol)
+        p.reliable_every = int(reliable_every)
+        p.seed_block = int(seed_block)
+        p.max_iter = int(max_iter)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        p.stream = ctypes.c_void_p(stream.cuda_stream)
+        self.params = p
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = lib.seedcg_create(ctypes.byref(p), ctypes.c_void_p(links.data_ptr()), ctypes.byref(h))
+        if rc != 0:
+            raise SeedCGError(rc, lib.seedcg_last_error(None).decode())
+        self._h = h
+        self._lib = lib
+
+    # -- helpers -----------------------------------------------------------------------------
+    def _rc(self, rc):
+        if rc != 0:
+            raise SeedCGError(rc, self._lib.seedcg_last_error(self._h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.seedcg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- C ABI calls ---------------------------------------------------------------------------
+    def apply_M(self, x):
+        x = _check_vec(x, self.Vh, "x")
+        y = torch.empty_like(x)
+        self._rc(self._lib.seedcg_apply_M(self._h, x.data_ptr(), y.data_ptr(), x.shape[0]))
+        return y
+
+    def apply_A(self, x, dagger=False):
+        x = _check_vec(x, self.Vh, "x")
+        y = torch.empty_like(x)
+        self._rc(self._lib.seedcg_apply_A(self._h, x.data_ptr(), y.data_ptr(), x.shape[0], int(bool(dagger))))
+        return y
+
+    def _report(self, n):
+        it = (ctypes.c_int32 * n)()
+        mv = (ctypes.c_int32 * n)()
+        rr = (ctypes.c_double * n)()
+        r = Report()
+        r.iters = ctypes.cast(it, ctypes.POINTER(ctypes.c_int32))
+        r.matvecs = ctypes.cast(mv, ctypes.POINTER(ctypes.c_int32))
+        r.true_relres = ctypes.cast(rr, ctypes.POINTER(ctypes.c_double))
+        return r, it, mv, rr
+
+    def solve_seed(self, B, X=None):
+        """Algorithm 1; returns (X, report).  X[0]: RHS-1 iterate, X[1:]: seeded guesses."""
+        B = _check_vec(B, self.Vh, "B")
+        X = torch.zeros_like(B) if X is None else _check_vec(X, self.Vh, "X")
+        n = B.shape[0]
+        r, it, mv, rr = self._report(n)
+        self._rc(self._lib.seedcg_solve_seed(self._h, B.data_ptr(), X.data_ptr(), n, ctypes.byref(r)))
+        rep = dict(m=r.m_used, i_conv=r.i_conv, seed_status=SEED_STATUS.get(r.seed_status, r.seed_status),
+                   reorth_passes=r.reorth_passes, t_seed_s=r.t_seed_s, matvecs=list(mv))
+        return X, rep
+
+    def solve_rest(self, B, X, raise_on_noconv=True):
+        """Plain CG from X on every right-hand side above tol; returns (X, report)."""
+        B = _check_vec(B, self.Vh, "B")
+        X = _check_vec(X, self.Vh, "X")
+        n = B.shape[0]
+        r, it, mv, rr = self._report(n)
+        rc = self._lib.seedcg_solve_rest(self._h, B.data_ptr(), X.data_ptr(), n, ctypes.byref(r))
+        rep = dict(iters=list(it), matvecs=list(mv), true_relres=list(rr), t_rest_s=r.t_rest_s,
+                   status=STATUS.get(rc, rc))
+        if rc != 0 and (rc != -5 or raise_on_noconv):
+            self._rc(rc)
+        return X, rep
+
+    def get_tridiag(self):
+        m = ctypes.c_int32()
+        self._rc(self._lib.seedcg_get_tridiag(self._h, None, None, 0, ctypes.byref(m)))
+        n = m.value
+        a = (ctypes.c_double * max(n, 1))()
+        b = (ctypes.c_double * (n + 1))()
+        self._rc(self._lib.seedcg_get_tridiag(self._h, a, b, n, ctypes.byref(m)))
+        return list(a)[:n], list(b)[:n + 1]
+
+    def get_basis_vector(self, i):
+        v = torch.empty((1, self.Vh, 4, 3), dtype=torch.complex128, device=self.device)
+        self._rc(self._lib.seedcg_get_basis_vector(self._h, int(i), v.data_ptr()))
+        return v[0]
+
+    def project(self, Vv, R):
+        """P = V^dag R for flat complex128 (nv, n) and (nr, n) CUDA tensors."""
+        Vv = Vv.reshape(Vv.shape[0], -1)
+        R = R.reshape(R.shape[0], -1)
+        assert Vv.is_contiguous() and R.is_contiguous() and Vv.shape[1] == R.shape[1]
+        P = torch.empty((Vv.shape[0], R.shape[0]), dtype=torch.complex128, device=self.device)
+        self._rc(self._lib.seedcg_project(self._h, Vv.data_ptr(), Vv.shape[0], R.data_ptr(), R.shape[0],
+                                          Vv.shape[1], P.data_ptr()))
+        return P
+
+    def update(self, W, E, X):
+        """X += W E for flat complex128 W (nw, n), E (nw, nx), X (nx, n) CUDA tensors (in place)."""
+        assert W.is_contiguous() and E.is_contiguous() and X.is_contiguous()
+        self._rc(self._lib.seedcg_update(self._h, W.data_ptr(), W.shape[0], E.data_ptr(), X.data_ptr(),
+                                         X.shape[0], W.shape[1]))
+        return X
+
+    def set_timing(self, sample_every, max_samples=4096):
+        self._rc(self._lib.seedcg_set_timing(self._h, int(sample_every), int(max_samples)))
+
+    def get_timing(self):
+        """Sampled stencil launches: dict(launches, ms, bytes, flops, seen)."""
+        out = (ctypes.c_double * 5)()
+        self._rc(self._lib.seedcg_get_timing(self._h, out))
+        return dict(launches=int(out[0]), ms=out[1], bytes=out[2], flops=out[3], seen=int(out[4]))
+
+    def release_basis(self):
+        self._rc(self._lib.seedcg_release_basis(self._h))

@@ -1,0 +1,213 @@
+"""Algorithm 1 (solve_seed) and plain CG (solve_rest) on the GPU against the oracle.
+
+Bars (FP64):
+  * T: the first 20 Lanczos coefficients agree to 1e-10 relative (later ones drift apart
+    with rounding, as Lanczos does); m and i_conv agree to within one step.
+  * Seeded guesses: equal to the Galerkin solution of Eq. (1) on the GPU's own basis to 1e-7,
+    and to the oracle's seeded guesses to 1e-6 (two runs, two roundings of one method).
+  * Final solutions: FP64 true relative residual <= 1e-10 by the oracle's M, and within 1e-8
+    of the oracle's solution (dense solve on 4^4).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_helpers import cuda, host, print_case
+from oracle import seedcg as osc
+from oracle.wilson import WilsonEO, dense, flat, matvec_M
+from synth.configs import make_inputs
+from synth.links import random_su3_links
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(name, nrhs=None):
+    U, phi, kappa = make_inputs(name)
+    dims = {"t4": (4, 4, 4, 4), "c1": (4, 4, 4, 4)}[name]
+    op = WilsonEO(U, dims, kappa)
+    B = op.apply_Adag(phi if nrhs is None else phi[:nrhs])
+    return U, dims, kappa, op, B
+
+
+@pytest.fixture(scope="module")
+def c1():
+    U, dims, kappa, op, B = _setup("c1")
+    mv = matvec_M(op)
+    ref = osc.seed_cg(mv, flat(B), k=10, tol=1e-10, past=1.5)
+    Md = dense(mv, 12 * op.Vh)
+    xs = np.linalg.solve(Md, flat(B).T).T
+    return dict(U=U, dims=dims, kappa=kappa, op=op, B=B, mv=mv, ref=ref, xs=xs)
+
+
+def _solver(U, dims, kappa, **kw):
+    from paper_0901_3512_amd import SeedCG
+    return SeedCG(cuda(U), dims, kappa, **kw)
+
+
+def test_seed_t4_matches_oracle():
+    print_case("seed t4")
+    U, dims, kappa, op, B = _setup("t4")
+    mv = matvec_M(op)
+    ref = osc.seed_cg(mv, flat(B), k=10, tol=1e-10, past=1.5)
+    s = _solver(U, dims, kappa, reorth_k=10)
+    X, rep = s.solve_seed(cuda(B))
+    a, b = s.get_tridiag()
+    assert abs(rep["m"] - ref["m"]) <= 1 and abs(rep["i_conv"] - ref["i_conv"]) <= 1
+    n = min(20, len(a))
+    assert np.max(np.abs(np.array(a[:n]) - ref["alpha"][:n]) / np.abs(ref["alpha"][:n])) <= 1e-10
+    assert np.max(np.abs(np.array(b[:n]) - ref["beta"][:n]) / ref["beta"][:n]) <= 1e-10
+    x = flat(host(X))
+    rel = np.linalg.norm(x - ref["X"], axis=1) / np.linalg.norm(ref["X"], axis=1)
+    assert np.max(rel) <= 1e-6, rel
+
+
+def test_seed_c1_galerkin_on_gpu_basis(c1):
+    print_case("seed c1 galerkin")
+    s = _solver(c1["U"], c1["dims"], c1["kappa"], reorth_k=10)
+    X, rep = s.solve_seed(cuda(c1["B"]))
+    ref = c1["ref"]
+    assert rep["seed_status"] == "ok"
+    assert abs(rep["i_conv"] - ref["i_conv"]) <= 1
+    assert rep["m"] == math.ceil(1.5 * rep["i_conv"])
+    m = rep["m"]
+    Vg = np.stack([flat(host(s.get_basis_vector(i))) for i in range(1, m + 1)])
+    assert osc.orth_loss(Vg) <= 1e-8
+    R0 = flat(c1["B"])
+    Xg = osc.galerkin(c1["mv"], Vg, R0)
+    x = flat(host(X))
+    rel = np.linalg.norm(x - Xg, axis=1) / np.linalg.norm(Xg, axis=1)
+    assert np.max(rel) <= 1e-7, rel
+    rel_o = np.linalg.norm(x - ref["X"], axis=1) / np.linalg.norm(ref["X"], axis=1)
+    assert np.max(rel_o) <= 1e-6, rel_o
+    # RHS 1 solved past convergence
+    assert osc.true_relres(c1["mv"], R0[:1], x[:1])[0] <= 1e-10
+
+
+def test_rest_c1_reaches_tol_and_matches_dense_solve(c1):
+    print_case("rest c1")
+    s = _solver(c1["U"], c1["dims"], c1["kappa"], reorth_k=10)
+    Bd = cuda(c1["B"])
+    X, rep = s.solve_seed(Bd)
+    X, rep2 = s.solve_rest(Bd, X)
+    x = flat(host(X))
+    res = osc.true_relres(c1["mv"], flat(c1["B"]), x)
+    assert np.all(res <= 1e-10), res
+    assert np.all(np.array(rep2["true_relres"]) <= 1e-10)
+    assert np.allclose(rep2["true_relres"], res, rtol=1e-3, atol=1e-13)
+    err = np.linalg.norm(x - c1["xs"], axis=1) / np.linalg.norm(c1["xs"], axis=1)
+    assert np.all(err <= 1e-8), err
+    # seeding helps: every seeded RHS needs fewer CG iterations than a cold start
+    Xc, repc = s.solve_rest(Bd, cuda(np.zeros_like(c1["B"])))
+    assert all(a < b for a, b in zip(rep2["iters"][1:], repc["iters"][1:]))
+
+
+def test_plain_cg_iterations_match_oracle(c1):
+    print_case("cg iterations")
+    s = _solver(c1["U"], c1["dims"], c1["kappa"])
+    B = c1["B"]
+    X, rep = s.solve_rest(cuda(B), cuda(np.zeros_like(B)))
+    for j in range(B.shape[0]):
+        _, it, r, _ = osc.cg(c1["mv"], flat(B)[j], None, tol=1e-10)
+        assert abs(rep["iters"][j] - it) <= max(2, int(0.02 * it)), (rep["iters"][j], it)
+
+
+def test_nonzero_initial_guess_and_single_rhs():
+    print_case("x0 nonzero")
+    U, dims, kappa, op, B = _setup("t4")
+    mv = matvec_M(op)
+    rng = np.random.default_rng(5)
+    X0 = 0.1 * (rng.standard_normal(B.shape) + 1j * rng.standard_normal(B.shape))
+    ref = osc.seed_cg(mv, flat(B), flat(X0), k=10, tol=1e-10, past=1.5)
+    s = _solver(U, dims, kappa, reorth_k=10)
+    X, rep = s.solve_seed(cuda(B), cuda(X0.copy()))
+    assert abs(rep["m"] - ref["m"]) <= 1
+    rel = np.linalg.norm(flat(host(X)) - ref["X"], axis=1) / np.linalg.norm(ref["X"], axis=1)
+    assert np.max(rel) <= 1e-6
+    s1 = _solver(U, dims, kappa, reorth_k=10)
+    X1, rep1 = s1.solve_seed(cuda(B[:1]))
+    X1, r1 = s1.solve_rest(cuda(B[:1]), X1)
+    assert osc.true_relres(mv, flat(B[:1]), flat(host(X1)))[0] <= 1e-10
+
+
+@pytest.mark.parametrize("k", [0, 1, 3, 7])
+def test_reorth_frequencies(k):
+    print_case("reorth k", k)
+    U, dims, kappa, op, B = _setup("t4")
+    mv = matvec_M(op)
+    ref = osc.seed_cg(mv, flat(B), k=k, tol=1e-10, past=1.5)
+    s = _solver(U, dims, kappa, reorth_k=k, seed_block=5)
+    X, rep = s.solve_seed(cuda(B))
+    assert abs(rep["m"] - ref["m"]) <= 1
+    rel = np.linalg.norm(flat(host(X)) - ref["X"], axis=1) / np.linalg.norm(ref["X"], axis=1)
+    assert np.max(rel) <= 1e-6, rel
+    if k:
+        assert rep["reorth_passes"] >= 2 * (rep["m"] // k)
+
+
+@pytest.mark.parametrize("b", [1, 2, 13, 32])
+def test_seed_block_sizes_agree(b):
+    print_case("seed block", b)
+    U, dims, kappa, op, B = _setup("t4")
+    s = _solver(U, dims, kappa, reorth_k=10, seed_block=b)
+    X, rep = s.solve_seed(cuda(B))
+    s2 = _solver(U, dims, kappa, reorth_k=10, seed_block=1)
+    X2, rep2 = s2.solve_seed(cuda(B))
+    assert rep["m"] == rep2["m"]
+    x, x2 = flat(host(X)), flat(host(X2))
+    assert np.max(np.linalg.norm(x - x2, axis=1) / np.linalg.norm(x2, axis=1)) <= 1e-12
+
+
+def test_breakdown_invariant_subspace():
+    """Unit links on 2^4: few distinct eigenvalues, Lanczos stops in an invariant subspace."""
+    print_case("breakdown")
+    dims = (2, 2, 2, 2)
+    U = np.tile(np.eye(3, dtype=np.complex128), (4, 16, 1, 1))
+    op = WilsonEO(U, dims, 0.1)
+    mv = matvec_M(op)
+    rng = np.random.default_rng(1)
+    B = (rng.standard_normal((2, 8, 4, 3)) + 1j * rng.standard_normal((2, 8, 4, 3)))
+    ref = osc.seed_cg(mv, flat(B), k=0, tol=1e-30, past=1.5, m_max=200)
+    s = _solver(U, dims, 0.1, reorth_k=0, tol=1e-30, m_max=200)
+    X, rep = s.solve_seed(cuda(B))
+    assert rep["seed_status"] == "breakdown" and ref["status"] == "breakdown"
+    assert rep["m"] == ref["m"]
+    assert osc.true_relres(mv, flat(B[:1]), flat(host(X))[:1])[0] <= 1e-12
+
+
+def test_capped_basis_and_fixed_m():
+    print_case("capped")
+    U, dims, kappa, op, B = _setup("t4")
+    mv = matvec_M(op)
+    s = _solver(U, dims, kappa, reorth_k=10, m_max=12)
+    X, rep = s.solve_seed(cuda(B))
+    assert rep["m"] == 12 and rep["seed_status"] == "capped"
+    X, rep2 = s.solve_rest(cuda(B), X)
+    assert np.all(osc.true_relres(mv, flat(B), flat(host(X))) <= 1e-10)
+    # past_factor <= 0: the paper's fixed m
+    ref = osc.seed_cg(mv, flat(B), k=10, tol=1e-10, m=25)
+    s2 = _solver(U, dims, kappa, reorth_k=10, m_max=25, past=0.0)
+    X2, rep3 = s2.solve_seed(cuda(B))
+    assert rep3["m"] == 25
+    rel = np.linalg.norm(flat(host(X2)) - ref["X"], axis=1) / np.linalg.norm(ref["X"], axis=1)
+    assert np.max(rel) <= 1e-8
+
+
+def test_state_and_argument_errors():
+    from paper_0901_3512_amd import SeedCGError
+    print_case("errors")
+    U, dims, kappa, op, B = _setup("t4")
+    s = _solver(U, dims, kappa)
+    with pytest.raises(SeedCGError) as e:
+        s.get_tridiag()
+    assert e.value.code == -6
+    with pytest.raises(SeedCGError):
+        s.get_basis_vector(1)
+    with pytest.raises(ValueError):
+        s.apply_M(cuda(np.zeros((1, 7, 4, 3), dtype=np.complex128)))
+    X, rep = s.solve_seed(cuda(B))
+    with pytest.raises(SeedCGError):
+        s.get_basis_vector(rep["m"] + 1)
+    s.release_basis()
+    with pytest.raises(SeedCGError):
+        s.get_basis_vector(1)

@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=40, help="Lanczos steps in the oracle sample")
     ap.add_argument("--sample-every", type=int, default=4, help="stencil launches per timed sample")
     ap.add_argument("--mbench", type=int, default=200, help="back-to-back M applications for D^dag D GB/s")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run a plain 1 GiB device copy first (reference for the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -57,6 +59,13 @@ def main():
     from paper_0901_3512_amd import SeedCG
     from synth.configs import CONFIGS, make_links, make_sources, kappa_for
 
+    if args.copy_probe:
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cfg = CONFIGS[args.config]
     prec = args.prec or cfg.prec
     dev = torch.device("cuda:0")

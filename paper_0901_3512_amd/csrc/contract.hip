@@ -146,16 +146,19 @@ __global__ __launch_bounds__(256) void proj_kernel(ProjArgs pa) {
     }
 }
 
-// P[r][j] = sum over chunks of part[chunk][r][j]
+// P[r][j] = sum over chunks of part[chunk][r][j]; one wavefront per output value, lane c adds
+// chunks c, c+64, ... and the lanes are combined by a fixed shuffle tree (deterministic).
 __global__ void proj_reduce_kernel(const double* part, int64_t nchunks, int64_t stride, int64_t len, double* P,
                                    const LzState* st, int gate_i, const int32_t* flag) {
     if (st && gate_i > st->m) return;
     if (flag && *flag == 0) return;
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= len) return;
+    const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / SCG_WAVE;
+    const int lane = threadIdx.x % SCG_WAVE;
+    if (k >= len) return;  // uniform per wavefront
     double s = 0.0;
-    for (int64_t c = 0; c < nchunks; c++) s += part[c * stride + k];
-    P[k] = s;
+    for (int64_t c = lane; c < nchunks; c += SCG_WAVE) s += part[c * stride + k];
+    for (int off = SCG_WAVE / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) P[k] = s;
 }
 
 int64_t proj_chunks(int64_t n, int64_t kchunk) { return (n + kchunk - 1) / kchunk; }
@@ -168,7 +171,7 @@ void project(bool fp32, const ProjArgs& a, int64_t nrowblocks, double* P, hipStr
     else
         hipLaunchKernelGGL(proj_kernel<double>, grid, dim3(256), 0, s, a);
     const int64_t len = 2 * (int64_t)a.nv * a.nr;
-    hipLaunchKernelGGL(proj_reduce_kernel, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, a.part, nch, a.part_stride, len, P,
+    hipLaunchKernelGGL(proj_reduce_kernel, dim3((unsigned)((len * SCG_WAVE + 255) / 256)), dim3(256), 0, s, a.part, nch, a.part_stride, len, P,
                        a.st, a.gate_i, a.flag);
 }
 

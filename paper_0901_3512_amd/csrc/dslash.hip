@@ -17,6 +17,7 @@
 // coefficients c, d are units (+-1, +-i); the backward hop negates them.
 #include "internal.h"
 #include <hip/hip_bf16.h>
+#include <cstdlib>
 
 namespace scg {
 
@@ -62,6 +63,11 @@ struct LinkLoad<double> {
         cx<double> v = *p;
         return mk<T>((T)v.re, (T)v.im);
     }
+    template <typename T>
+    __device__ static inline cx<T> get32(const Store* base, uint32_t idx) {
+        const cx<double> v = *(const Store*)((const char*)base + idx * (uint32_t)sizeof(Store));
+        return mk<T>((T)v.re, (T)v.im);
+    }
 };
 template <>
 struct LinkLoad<float> {
@@ -69,6 +75,11 @@ struct LinkLoad<float> {
     template <typename T>
     __device__ static inline cx<T> get(const Store* p) {
         cx<float> v = *p;
+        return mk<T>((T)v.re, (T)v.im);
+    }
+    template <typename T>
+    __device__ static inline cx<T> get32(const Store* base, uint32_t idx) {
+        const cx<float> v = *(const Store*)((const char*)base + idx * (uint32_t)sizeof(Store));
         return mk<T>((T)v.re, (T)v.im);
     }
 };
@@ -83,6 +94,11 @@ struct LinkLoad<bf16link> {
         float re = __uint_as_float(w << 16);
         float im = __uint_as_float(w & 0xffff0000u);
         return mk<T>((T)re, (T)im);
+    }
+    template <typename T>
+    __device__ static inline cx<T> get32(const Store* base, uint32_t idx) {
+        const uint32_t w = *(const Store*)((const char*)base + idx * (uint32_t)sizeof(Store));
+        return mk<T>((T)__uint_as_float(w << 16), (T)__uint_as_float(w & 0xffff0000u));
     }
 };
 
@@ -102,172 +118,482 @@ struct EpiDev {
     const CgVec* cg;
 };
 
-template <typename T, typename LT, int TPS>
+// neighbour (checkerboard index) of site (x,y,z,t) with index h in direction mu, step +-1, and the
+// boundary sign of that hop
+struct Nb {
+    int64_t h;
+    int sign;
+};
+__device__ inline Nb neighbour(const Geom& g, int mu, int step, int x, int y, int z, int t, int xh, int64_t row) {
+    const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
+    Nb n;
+    n.sign = 1;
+    if (mu == 0) {
+        const int xn = (x + step + Lx) % Lx;
+        n.h = row + (xn >> 1);
+    } else if (mu == 1) {
+        const int yn = (y + step + Ly) % Ly;
+        n.h = xh + (int64_t)g.Lxh * (yn + (int64_t)Ly * (z + (int64_t)Lz * t));
+    } else if (mu == 2) {
+        const int zn = (z + step + Lz) % Lz;
+        n.h = xh + (int64_t)g.Lxh * (y + (int64_t)Ly * (zn + (int64_t)Lz * t));
+    } else {
+        const int tn = (t + step + Lt) % Lt;
+        n.h = xh + (int64_t)g.Lxh * (y + (int64_t)Ly * (z + (int64_t)Lz * tn));
+        if ((step == 1 && t == Lt - 1) || (step == -1 && t == 0)) n.sign = g.t_bc;
+    }
+    return n;
+}
+
+template <typename T, typename LT>
+__device__ inline void load_link(const typename LinkLoad<LT>::Store* links, int mu, int par, int64_t h, int64_t Vh, cx<T> u[9]) {
+    const typename LinkLoad<LT>::Store* lk = links + ((int64_t)(mu * 2 + par) * 9) * Vh + h;
+#pragma unroll
+    for (int c = 0; c < 9; c++) u[c] = LinkLoad<LT>::template get<T>(lk + (int64_t)c * Vh);
+}
+
+// acc += (1 -/+ gamma_mu) U psi(neighbour) for one hop (dir 0: forward with U_mu(n), 1: backward
+// with U_mu(n - mu)^dag)
+template <typename T>
+__device__ inline void hop_accumulate(const cx<T>* __restrict__ src, int64_t hn, int64_t Vh, const Proj& pr, int dir, T sign,
+                                      const cx<T> u[9], cx<T> acc[12]) {
+    // h_0 = psi_0 + c_0 psi_{a0}, h_1 = psi_1 + c_1 psi_{a1}: load the spins pairwise
+    const cx<T>* ps = src + hn;
+    const int s = dir == 0 ? 1 : -1;
+    const Unit c0 = {s * pr.c0.re, s * pr.c0.im};
+    const Unit c1 = {s * pr.c1.re, s * pr.c1.im};
+    const int64_t oa0 = (int64_t)(3 * pr.a0) * Vh, oa1 = (int64_t)(3 * (5 - pr.a0)) * Vh;
+    cx<T> hp[2][3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) hp[0][a] = ps[(int64_t)a * Vh] + umul(c0, ps[oa0 + (int64_t)a * Vh]);
+#pragma unroll
+    for (int a = 0; a < 3; a++) hp[1][a] = ps[(int64_t)(3 + a) * Vh] + umul(c1, ps[oa1 + (int64_t)a * Vh]);
+    cx<T> chi[2][3];
+#pragma unroll
+    for (int sp = 0; sp < 2; sp++)
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            cx<T> v = mk<T>(0, 0);
+#pragma unroll
+            for (int b = 0; b < 3; b++) v = v + (dir == 0 ? cmul(u[a * 3 + b], hp[sp][b]) : cjmul(u[b * 3 + a], hp[sp][b]));
+            chi[sp][a] = sign * v;
+        }
+    const Unit d0 = {s * pr.d0.re, s * pr.d0.im};
+    const Unit d1 = {s * pr.d1.re, s * pr.d1.im};
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        acc[a] = acc[a] + chi[0][a];
+        acc[3 + a] = acc[3 + a] + chi[1][a];
+        acc[6 + a] = acc[6 + a] + umul(d0, pr.b0 == 1 ? chi[1][a] : chi[0][a]);
+        acc[9 + a] = acc[9 + a] + umul(d1, pr.b0 == 1 ? chi[0][a] : chi[1][a]);
+    }
+}
+
+constexpr int HOP_MAX_VB = 32;
+
+// One workgroup = 256/TPS output sites x a group of vb vectors.  The links of the site's
+// directions are loaded once and, when they fit in registers (HOIST), reused for every vector
+// of the group; the vectors of the group are processed one after another so that the
+// neighbour spinors of consecutive sites stay in L2 as for a single vector.
+template <typename T, typename LT, int TPS, bool HOIST>
 __global__ __launch_bounds__(SCG_BLOCK) void hop_kernel(Geom g, const typename LinkLoad<LT>::Store* __restrict__ links,
                                                         const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
-                                                        int p, int nvec, int64_t nsb, EpiDev<T> e) {
-    __shared__ double red_lds[SCG_BLOCK / SCG_WAVE];
+                                                        int p, int nvec, int vb, int64_t nsb, EpiDev<T> e) {
+    constexpr int NMU = 4 / TPS;
+    __shared__ double red_lds[HOP_MAX_VB * (SCG_BLOCK / SCG_WAVE)];
     if (e.gate_m && e.gate_i > *e.gate_m) return;
-    const int64_t nblk = nsb * nvec;
+    const int nvg = (nvec + vb - 1) / vb;
+    const int64_t nblk = nsb * nvg;
     const int64_t logical = xcd_logical_block(nblk);
     if (logical >= nblk) return;
-    const int slot = (int)(logical % nvec);
-    const int64_t sb = logical / nvec;
-    const int vec = e.vec_map ? e.vec_map[slot] : slot;
-    if (e.cg && (e.cg[vec].done || e.cg[vec].frozen)) return;
+    const int vg = (int)(logical % nvg);
+    const int64_t sb = logical / nvg;
 
     const int64_t Vh = g.Vh;
     const int64_t tid = sb * SCG_BLOCK + threadIdx.x;
     const int64_t h = tid / TPS;
     const int sub = (int)(tid % TPS);
     const bool active = h < Vh;
-    const cx<T>* src = in + (int64_t)vec * 12 * Vh;
 
-    cx<T> acc[12];
-#pragma unroll
-    for (int c = 0; c < 12; c++) acc[c] = mk<T>(0, 0);
-
+    // site coordinates, neighbours and (hoisted) links of this lane's directions
+    Nb nb[NMU][2];
+    cx<T> uh[HOIST ? NMU : 1][2][9];
+    int mus[NMU];
     if (active) {
-        // coordinates of the output site (parity p, checkerboard index h)
-        const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
         const int xh = (int)(h % g.Lxh);
         int64_t r = h / g.Lxh;
-        const int y = (int)(r % Ly);
-        r /= Ly;
-        const int z = (int)(r % Lz);
-        const int t = (int)(r / Lz);
+        const int y = (int)(r % g.L[1]);
+        r /= g.L[1];
+        const int z = (int)(r % g.L[2]);
+        const int t = (int)(r / g.L[2]);
         const int x = 2 * xh + ((y + z + t + p) & 1);
-        const int64_t row = h - xh;  // h of the x = 0,1 pair in this (y,z,t) row
-
-        constexpr int NMU = 4 / TPS;
-#pragma unroll 1
+        const int64_t row = h - xh;
+#pragma unroll
         for (int k = 0; k < NMU; k++) {
             const int mu = (TPS == 1) ? k : sub * NMU + k;
-            const Proj pr = proj_of(mu);
-#pragma unroll
-            for (int dir = 0; dir < 2; dir++) {
-                // neighbour checkerboard index and boundary sign
-                int64_t hn;
-                T sign = 1;
-                const int step = dir == 0 ? 1 : -1;
-                if (mu == 0) {
-                    const int xn = (x + step + Lx) % Lx;
-                    hn = row + (xn >> 1);
-                } else if (mu == 1) {
-                    const int yn = (y + step + Ly) % Ly;
-                    hn = xh + (int64_t)g.Lxh * (yn + (int64_t)Ly * (z + (int64_t)Lz * t));
-                } else if (mu == 2) {
-                    const int zn = (z + step + Lz) % Lz;
-                    hn = xh + (int64_t)g.Lxh * (y + (int64_t)Ly * (zn + (int64_t)Lz * t));
-                } else {
-                    const int tn = (t + step + Lt) % Lt;
-                    hn = xh + (int64_t)g.Lxh * (y + (int64_t)Ly * (z + (int64_t)Lz * tn));
-                    if ((dir == 0 && t == Lt - 1) || (dir == 1 && t == 0)) sign = (T)g.t_bc;
-                }
-                // neighbour spinor, projected to two spin components
-                const cx<T>* ps = src + hn;
-                cx<T> psi[12];
-#pragma unroll
-                for (int c = 0; c < 12; c++) psi[c] = ps[(int64_t)c * Vh];
-                const T s = dir == 0 ? (T)1 : (T)-1;
-                const Unit c0 = {(int)s * pr.c0.re, (int)s * pr.c0.im};
-                const Unit c1 = {(int)s * pr.c1.re, (int)s * pr.c1.im};
-                cx<T> hp[2][3];
-#pragma unroll
-                for (int a = 0; a < 3; a++) {
-                    const cx<T> s2 = psi[6 + a], s3 = psi[9 + a];
-                    hp[0][a] = psi[a] + umul(c0, pr.a0 == 3 ? s3 : s2);
-                    hp[1][a] = psi[3 + a] + umul(c1, pr.a0 == 3 ? s2 : s3);
-                }
-                // link: U_mu(n) forward (this parity), U_mu(n - mu)^dag backward (other parity)
-                const int lp = dir == 0 ? p : 1 - p;
-                const int64_t lh = dir == 0 ? h : hn;
-                const typename LinkLoad<LT>::Store* lk = links + ((int64_t)(mu * 2 + lp) * 9) * Vh + lh;
-                cx<T> u[9];
-#pragma unroll
-                for (int c = 0; c < 9; c++) u[c] = LinkLoad<LT>::template get<T>(lk + (int64_t)c * Vh);
-                cx<T> chi[2][3];
-#pragma unroll
-                for (int sp = 0; sp < 2; sp++)
-#pragma unroll
-                    for (int a = 0; a < 3; a++) {
-                        cx<T> v = mk<T>(0, 0);
-#pragma unroll
-                        for (int b = 0; b < 3; b++)
-                            v = v + (dir == 0 ? cmul(u[a * 3 + b], hp[sp][b]) : cjmul(u[b * 3 + a], hp[sp][b]));
-                        chi[sp][a] = sign * v;
-                    }
-                const Unit d0 = {(int)s * pr.d0.re, (int)s * pr.d0.im};
-                const Unit d1 = {(int)s * pr.d1.re, (int)s * pr.d1.im};
-#pragma unroll
-                for (int a = 0; a < 3; a++) {
-                    acc[a] = acc[a] + chi[0][a];
-                    acc[3 + a] = acc[3 + a] + chi[1][a];
-                    acc[6 + a] = acc[6 + a] + umul(d0, pr.b0 == 1 ? chi[1][a] : chi[0][a]);
-                    acc[9 + a] = acc[9 + a] + umul(d1, pr.b0 == 1 ? chi[0][a] : chi[1][a]);
-                }
+            mus[k] = mu;
+            nb[k][0] = neighbour(g, mu, 1, x, y, z, t, xh, row);
+            nb[k][1] = neighbour(g, mu, -1, x, y, z, t, xh, row);
+            if constexpr (HOIST) {
+                load_link<T, LT>(links, mu, p, h, Vh, uh[k][0]);
+                load_link<T, LT>(links, mu, 1 - p, nb[k][1].h, Vh, uh[k][1]);
             }
         }
     }
 
-    // sum the partial results of the TPS lanes of this site
-    if (TPS > 1) {
-#pragma unroll
-        for (int off = 1; off < TPS; off <<= 1)
-#pragma unroll
-            for (int c = 0; c < 12; c++) {
-                acc[c].re += __shfl_xor(acc[c].re, off);
-                acc[c].im += __shfl_xor(acc[c].im, off);
-            }
-    }
-
-    // epilogue on this lane's 12/TPS components
     constexpr int NC = 12 / TPS;
-    double part = 0.0;
-    if (active) {
-        const int64_t vo = (int64_t)vec * 12 * Vh;
-        double czd = e.cz_host;
-        if (e.cz_dev) czd = e.cz_negate ? -e.cz_dev[vec] : e.cz_dev[vec];
-        const T cz = (T)czd;
+    for (int vi = 0; vi < vb; vi++) {
+        const int slot = vg * vb + vi;
+        if (slot >= nvec) break;
+        const int vec = e.vec_map ? e.vec_map[slot] : slot;
+        if (e.cg && (e.cg[vec].done || e.cg[vec].frozen)) continue;
+        const cx<T>* src = in + (int64_t)vec * 12 * Vh;
+
+        cx<T> acc[12];
 #pragma unroll
-        for (int c = 0; c < NC; c++) {
-            const int cc = sub * NC + c;
-            cx<T> v = acc[0];
+        for (int c = 0; c < 12; c++) acc[c] = mk<T>(0, 0);
+        if (active) {
 #pragma unroll
-            for (int q = 0; q < 12; q++)
-                if (q == cc) v = acc[q];
-            const int64_t idx = vo + (int64_t)cc * Vh + h;
-            cx<T> y = v;
-            if (e.combine) {
-                const cx<T> xv = e.x[idx];
-                y = mk<T>(xv.re - e.kappa2 * v.re, xv.im - e.kappa2 * v.im);
-                if (e.apply_g5 && cc >= 6) y = mk<T>(-y.re, -y.im);
+            for (int k = 0; k < NMU; k++) {
+                const Proj pr = proj_of(mus[k]);
+#pragma unroll
+                for (int dir = 0; dir < 2; dir++) {
+                    if constexpr (HOIST) {
+                        hop_accumulate<T>(src, nb[k][dir].h, Vh, pr, dir, (T)nb[k][dir].sign, uh[k][dir], acc);
+                    } else {
+                        cx<T> u[9];
+                        load_link<T, LT>(links, mus[k], dir == 0 ? p : 1 - p, dir == 0 ? h : nb[k][1].h, Vh, u);
+                        hop_accumulate<T>(src, nb[k][dir].h, Vh, pr, dir, (T)nb[k][dir].sign, u, acc);
+                    }
+                }
             }
-            cx<T> o = mk<T>(e.sy * y.re, e.sy * y.im);
-            if (e.z) {
-                const cx<T> zv = e.z[idx];
-                o = mk<T>(o.re + cz * zv.re, o.im + cz * zv.im);
+        }
+        // sum the partial results of the TPS lanes of this site
+        if (TPS > 1) {
+#pragma unroll
+            for (int off = 1; off < TPS; off <<= 1)
+#pragma unroll
+                for (int c = 0; c < 12; c++) {
+                    acc[c].re += __shfl_xor(acc[c].re, off);
+                    acc[c].im += __shfl_xor(acc[c].im, off);
+                }
+        }
+        // epilogue on this lane's 12/TPS components
+        double part = 0.0;
+        if (active) {
+            const int64_t vo = (int64_t)vec * 12 * Vh;
+            double czd = e.cz_host;
+            if (e.cz_dev) czd = e.cz_negate ? -e.cz_dev[vec] : e.cz_dev[vec];
+            const T cz = (T)czd;
+#pragma unroll
+            for (int c = 0; c < NC; c++) {
+                const int cc = sub * NC + c;
+                cx<T> v = acc[0];
+#pragma unroll
+                for (int q = 0; q < 12; q++)
+                    if (q == cc) v = acc[q];
+                const int64_t idx = vo + (int64_t)cc * Vh + h;
+                cx<T> y = v;
+                if (e.combine) {
+                    const cx<T> xv = e.x[idx];
+                    y = mk<T>(xv.re - e.kappa2 * v.re, xv.im - e.kappa2 * v.im);
+                    if (e.apply_g5 && cc >= 6) y = mk<T>(-y.re, -y.im);
+                }
+                cx<T> o = mk<T>(e.sy * y.re, e.sy * y.im);
+                if (e.z) {
+                    const cx<T> zv = e.z[idx];
+                    o = mk<T>(o.re + cz * zv.re, o.im + cz * zv.im);
+                }
+                out[idx] = o;
+                if (e.red == 1) {
+                    const cx<T> dv = e.d[idx];
+                    part += (double)dv.re * (double)o.re + (double)dv.im * (double)o.im;
+                } else if (e.red == 2) {
+                    part += (double)o.re * (double)o.re + (double)o.im * (double)o.im;
+                }
             }
-            out[idx] = o;
-            if (e.red == 1) {
-                const cx<T> dv = e.d[idx];
-                part += (double)dv.re * (double)o.re + (double)dv.im * (double)o.im;
-            } else if (e.red == 2) {
-                part += (double)o.re * (double)o.re + (double)o.im * (double)o.im;
-            }
+        }
+        if (e.red) {
+            // wave sum now, the waves of the workgroup after the vector loop (no barrier per vector)
+            for (int off = SCG_WAVE / 2; off > 0; off >>= 1) part += __shfl_xor(part, off);
+            if ((threadIdx.x % SCG_WAVE) == 0) red_lds[vi * (SCG_BLOCK / SCG_WAVE) + threadIdx.x / SCG_WAVE] = part;
         }
     }
     if (e.red) {
-        const double s = block_sum(part, red_lds);
-        if (threadIdx.x == 0) e.partials[(int64_t)vec * nsb + sb] = s;
+        __syncthreads();
+        const int vi = threadIdx.x;
+        if (vi < vb) {
+            const int slot = vg * vb + vi;
+            if (slot < nvec) {
+                const int vec = e.vec_map ? e.vec_map[slot] : slot;
+                if (!(e.cg && (e.cg[vec].done || e.cg[vec].frozen))) {
+                    double s = 0.0;
+                    for (int w = 0; w < SCG_BLOCK / SCG_WAVE; w++) s += red_lds[vi * (SCG_BLOCK / SCG_WAVE) + w];
+                    e.partials[(int64_t)vec * nsb + sb] = s;
+                }
+            }
+        }
     }
 }
 
-int hop_site_blocks(const Geom& g, int tps) { return (int)((g.Vh * tps + SCG_BLOCK - 1) / SCG_BLOCK); }
+// Lean variant: two lanes per site, lane 0 takes the four forward hops and lane 1 the four
+// backward hops.  The mu loop is unrolled, so every spin-projection coefficient is a
+// compile-time unit and folds into the adds; the lane's direction enters only as a sign sd
+// (and as U versus U^dag, by the order in which the link entries are read).
+template <int MU>
+__device__ constexpr Proj proj_c() {
+    return MU == 0 ? Proj{3, {0, 1}, {0, 1}, 1, {0, -1}, {0, -1}}
+         : MU == 1 ? Proj{3, {1, 0}, {-1, 0}, 1, {-1, 0}, {1, 0}}
+         : MU == 2 ? Proj{2, {0, 1}, {0, -1}, 0, {0, -1}, {0, 1}}
+                   : Proj{2, {-1, 0}, {-1, 0}, 0, {-1, 0}, {-1, 0}};
+}
+
+// load base[idx] with a 32-bit byte offset, so that a uniform base stays in SGPRs and only the
+// offset occupies a VGPR (the global_load saddr form)
+template <typename T>
+__device__ inline T ld32(const T* base, uint32_t idx) {
+    return *(const T*)((const char*)base + idx * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ inline void st32(T* base, uint32_t idx, T v) {
+    *(T*)((char*)base + idx * (uint32_t)sizeof(T)) = v;
+}
+
+// a + sd * u * b for a compile-time unit u
+template <typename T, int UR, int UI>
+__device__ inline cx<T> fma_unit(T sd, cx<T> b, cx<T> a) {
+    // u*b = (UR br - UI bi) + i (UR bi + UI br)
+    const T ur = UR ? (T)UR * b.re : (T)-UI * b.im;
+    const T ui = UR ? (T)UR * b.im : (T)UI * b.re;
+    return mk<T>(fma(sd, ur, a.re), fma(sd, ui, a.im));
+}
+
+template <typename T, typename LT, int MU>
+__device__ inline void hop_dir_lean(const cx<T>* __restrict__ src, const typename LinkLoad<LT>::Store* __restrict__ links,
+                                    uint32_t hn, uint32_t hl, uint32_t lpar, uint32_t Vh, int bwd, T sd, T sign,
+                                    cx<T> acc[12]) {
+    constexpr Proj pr = proj_c<MU>();
+    constexpr int a0 = pr.a0, a1 = 5 - pr.a0;
+    // uniform base of each spin-colour component plus a 32-bit per-lane site offset
+    cx<T> hp[2][3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        hp[0][a] = fma_unit<T, pr.c0.re, pr.c0.im>(sd, ld32(src + (size_t)(3 * a0 + a) * Vh, hn), ld32(src + (size_t)a * Vh, hn));
+        hp[1][a] = fma_unit<T, pr.c1.re, pr.c1.im>(sd, ld32(src + (size_t)(3 * a1 + a) * Vh, hn), ld32(src + (size_t)(3 + a) * Vh, hn));
+    }
+    if (MU == 3) {  // boundary sign of the t hop
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            hp[0][a] = sign * hp[0][a];
+            hp[1][a] = sign * hp[1][a];
+        }
+    }
+    // M[a][b] = U[a][b] (forward) or conj(U[b][a]) (backward); the link of parity lpar
+    const typename LinkLoad<LT>::Store* __restrict__ lk = links + (size_t)(MU * 2) * 9 * Vh;
+    const uint32_t lane_off = lpar * 9u * Vh + hl;
+    cx<T> chi[2][3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        cx<T> c0 = mk<T>(0, 0), c1 = mk<T>(0, 0);
+#pragma unroll
+        for (int b = 0; b < 3; b++) {
+            const uint32_t idx = bwd ? (uint32_t)(b * 3 + a) : (uint32_t)(a * 3 + b);
+            cx<T> m = LinkLoad<LT>::template get32<T>(lk, lane_off + idx * Vh);
+            if (bwd) m.im = -m.im;
+            c0 = c0 + cmul(m, hp[0][b]);
+            c1 = c1 + cmul(m, hp[1][b]);
+        }
+        chi[0][a] = c0;
+        chi[1][a] = c1;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        acc[a] = acc[a] + chi[0][a];
+        acc[3 + a] = acc[3 + a] + chi[1][a];
+        acc[6 + a] = fma_unit<T, pr.d0.re, pr.d0.im>(sd, pr.b0 == 1 ? chi[1][a] : chi[0][a], acc[6 + a]);
+        acc[9 + a] = fma_unit<T, pr.d1.re, pr.d1.im>(sd, pr.b0 == 1 ? chi[0][a] : chi[1][a], acc[9 + a]);
+    }
+}
+
+// the same hop with a wave-uniform runtime direction mu (coefficients from proj_of(mu))
+template <typename T>
+__device__ inline cx<T> fma_u(T sd, Unit u, cx<T> b, cx<T> a) {
+    const cx<T> ub = umul(u, b);
+    return mk<T>(fma(sd, ub.re, a.re), fma(sd, ub.im, a.im));
+}
+template <typename T, typename LT>
+__device__ inline void hop_dir_rt(const cx<T>* __restrict__ src, const typename LinkLoad<LT>::Store* __restrict__ links, int mu,
+                                  uint32_t hn, uint32_t hl, uint32_t lpar, uint32_t Vh, int bwd, T sd, T sign, cx<T> acc[12]) {
+    const Proj pr = proj_of(mu);
+    const uint32_t a0 = (uint32_t)pr.a0, a1 = 5u - a0;
+    cx<T> hp[2][3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        hp[0][a] = fma_u(sd, pr.c0, ld32(src + (size_t)(3 * a0 + a) * Vh, hn), ld32(src + (size_t)a * Vh, hn));
+        hp[1][a] = fma_u(sd, pr.c1, ld32(src + (size_t)(3 * a1 + a) * Vh, hn), ld32(src + (size_t)(3 + a) * Vh, hn));
+        hp[0][a] = sign * hp[0][a];
+        hp[1][a] = sign * hp[1][a];
+    }
+    const typename LinkLoad<LT>::Store* __restrict__ lk = links + (size_t)(mu * 2) * 9 * Vh;
+    const uint32_t lane_off = lpar * 9u * Vh + hl;
+    cx<T> chi[2][3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        cx<T> c0 = mk<T>(0, 0), c1 = mk<T>(0, 0);
+#pragma unroll
+        for (int b = 0; b < 3; b++) {
+            const uint32_t idx = bwd ? (uint32_t)(b * 3 + a) : (uint32_t)(a * 3 + b);
+            cx<T> m = LinkLoad<LT>::template get32<T>(lk, lane_off + idx * Vh);
+            if (bwd) m.im = -m.im;
+            c0 = c0 + cmul(m, hp[0][b]);
+            c1 = c1 + cmul(m, hp[1][b]);
+        }
+        chi[0][a] = c0;
+        chi[1][a] = c1;
+    }
+    const bool b1 = pr.b0 == 1;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        acc[a] = acc[a] + chi[0][a];
+        acc[3 + a] = acc[3 + a] + chi[1][a];
+        acc[6 + a] = fma_u(sd, pr.d0, b1 ? chi[1][a] : chi[0][a], acc[6 + a]);
+        acc[9 + a] = fma_u(sd, pr.d1, b1 ? chi[0][a] : chi[1][a], acc[9 + a]);
+    }
+}
+
+template <typename T, typename LT, bool ONE>
+__global__ __launch_bounds__(SCG_BLOCK) void hop_lean_kernel(Geom g, const typename LinkLoad<LT>::Store* __restrict__ links,
+                                                             const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+                                                             int p, int nvec, int vb, int64_t nsb, EpiDev<T> e) {
+    __shared__ double red_lds[HOP_MAX_VB * (SCG_BLOCK / SCG_WAVE)];
+    if (e.gate_m && e.gate_i > *e.gate_m) return;
+    const int nvg = (nvec + vb - 1) / vb;
+    const int64_t nblk = nsb * nvg;
+    const int64_t logical = xcd_logical_block(nblk);
+    if (logical >= nblk) return;
+    const int vg = (int)(logical % nvg);
+    const int64_t sb = logical / nvg;
+    const int64_t Vh = g.Vh;
+    const int64_t tid = sb * SCG_BLOCK + threadIdx.x;
+    const int64_t h = tid >> 1;
+    const int bwd = (int)(tid & 1);
+    const bool active = h < Vh;
+    const int step = bwd ? -1 : 1;
+    const T sd = bwd ? (T)-1 : (T)1;
+
+    int x = 0, y = 0, z = 0, t = 0, xh = 0;
+    int64_t row = 0;
+    if (active) {
+        xh = (int)(h % g.Lxh);
+        int64_t r = h / g.Lxh;
+        y = (int)(r % g.L[1]);
+        r /= g.L[1];
+        z = (int)(r % g.L[2]);
+        t = (int)(r / g.L[2]);
+        x = 2 * xh + ((y + z + t + p) & 1);
+        row = h - xh;
+    }
+    const uint32_t lpar = bwd ? 1u - (uint32_t)p : (uint32_t)p;
+    const uint32_t Vh32 = (uint32_t)Vh, h32 = (uint32_t)h;
+
+    // ONE: one vector per workgroup (vb == 1); the vectors of a site block are adjacent
+    // workgroups on one XCD and share the links through its L2
+    const int nloop = ONE ? 1 : vb;
+    for (int vi = 0; vi < nloop; vi++) {
+        const int slot = vg * vb + vi;
+        if (slot >= nvec) break;
+        const int vec = e.vec_map ? e.vec_map[slot] : slot;
+        if (e.cg && (e.cg[vec].done || e.cg[vec].frozen)) continue;
+        const cx<T>* src = in + (size_t)vec * 12 * Vh;
+        cx<T> acc[12];
+#pragma unroll
+        for (int c = 0; c < 12; c++) acc[c] = mk<T>(0, 0);
+        if (active) {
+            // one direction at a time (mu is the same for every lane): bounded register use
+#pragma unroll 1
+            for (int mu = 0; mu < 4; mu++) {
+                const Nb n = neighbour(g, mu, step, x, y, z, t, xh, row);
+                const uint32_t hn = (uint32_t)n.h;
+                hop_dir_rt<T, LT>(src, links, mu, hn, bwd ? hn : h32, lpar, Vh32, bwd, sd, (T)n.sign, acc);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 12; c++) {
+            acc[c].re += __shfl_xor(acc[c].re, 1);
+            acc[c].im += __shfl_xor(acc[c].im, 1);
+        }
+        double part = 0.0;
+        if (active) {
+            const size_t vo = (size_t)vec * 12 * Vh;
+            double czd = e.cz_host;
+            if (e.cz_dev) czd = e.cz_negate ? -e.cz_dev[vec] : e.cz_dev[vec];
+            const T cz = (T)czd;
+            const uint32_t lo = (uint32_t)bwd * 6u * Vh32 + h32;
+#pragma unroll
+            for (int c = 0; c < 6; c++) {
+                const cx<T> v = bwd ? acc[6 + c] : acc[c];
+                const size_t cb = vo + (size_t)c * Vh;   // uniform
+                cx<T> y = v;
+                if (e.combine) {
+                    const cx<T> xv = ld32(e.x + cb, lo);
+                    y = mk<T>(xv.re - e.kappa2 * v.re, xv.im - e.kappa2 * v.im);
+                    if (e.apply_g5 && bwd) y = mk<T>(-y.re, -y.im);
+                }
+                cx<T> o = mk<T>(e.sy * y.re, e.sy * y.im);
+                if (e.z) {
+                    const cx<T> zv = ld32(e.z + cb, lo);
+                    o = mk<T>(o.re + cz * zv.re, o.im + cz * zv.im);
+                }
+                st32(out + cb, lo, o);
+                if (e.red == 1) {
+                    const cx<T> dv = ld32(e.d + cb, lo);
+                    part += (double)dv.re * (double)o.re + (double)dv.im * (double)o.im;
+                } else if (e.red == 2) {
+                    part += (double)o.re * (double)o.re + (double)o.im * (double)o.im;
+                }
+            }
+        }
+        if (e.red) {
+            for (int off = SCG_WAVE / 2; off > 0; off >>= 1) part += __shfl_xor(part, off);
+            if ((threadIdx.x % SCG_WAVE) == 0) red_lds[vi * (SCG_BLOCK / SCG_WAVE) + threadIdx.x / SCG_WAVE] = part;
+        }
+    }
+    if (e.red) {
+        __syncthreads();
+        const int vi = threadIdx.x;
+        if (vi < vb) {
+            const int slot = vg * vb + vi;
+            if (slot < nvec) {
+                const int vec = e.vec_map ? e.vec_map[slot] : slot;
+                if (!(e.cg && (e.cg[vec].done || e.cg[vec].frozen))) {
+                    double s = 0.0;
+                    for (int w = 0; w < SCG_BLOCK / SCG_WAVE; w++) s += red_lds[vi * (SCG_BLOCK / SCG_WAVE) + w];
+                    e.partials[(int64_t)vec * nsb + sb] = s;
+                }
+            }
+        }
+    }
+}
+
+static int g_hoist = -1;
+bool hop_hoist_links() {
+    if (g_hoist < 0) {
+        const char* v = getenv("SEEDCG_HOIST");
+        g_hoist = v ? atoi(v) : 1;
+    }
+    return g_hoist != 0;
+}
+void set_hop_hoist_links(bool on) { g_hoist = on ? 1 : 0; }
+
+// tps: 1, 2, 4 lanes per site (direction split), or 3 = the lean forward/backward variant (2 lanes)
+int hop_threads_per_site(int tps) { return tps == 3 ? 2 : tps; }
+int hop_site_blocks(const Geom& g, int tps) {
+    return (int)((g.Vh * hop_threads_per_site(tps) + SCG_BLOCK - 1) / SCG_BLOCK);
+}
 
 template <typename T, typename LT>
 static void launch_t(const Geom& g, const void* links, const void* in, void* out, int p, int nvec, const HopEpi& epi,
-                     int tps, hipStream_t s) {
+                     int tps, int vb, hipStream_t s) {
     EpiDev<T> e;
     e.apply_g5 = epi.apply_g5;
     e.combine = epi.combine;
@@ -286,27 +612,40 @@ static void launch_t(const Geom& g, const void* links, const void* in, void* out
     e.vec_map = epi.vec_map;
     e.cg = epi.cg;
     const int64_t nsb = hop_site_blocks(g, tps);
-    const int64_t grid = xcd_grid(nsb * nvec);
+    vb = vb < 1 ? 1 : (vb > nvec ? nvec : vb);
+    vb = vb > HOP_MAX_VB ? HOP_MAX_VB : vb;
+    const int64_t grid = xcd_grid(nsb * ((nvec + vb - 1) / vb));
     using S = typename LinkLoad<LT>::Store;
-    if (tps == 1)
-        hipLaunchKernelGGL((hop_kernel<T, LT, 1>), dim3(grid), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
-                           (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e);
+    // links kept in registers across the vectors of a workgroup when one lane holds one direction
+    const bool hoist = tps == 4 && hop_hoist_links();
+    if (tps == 3 && vb == 1)
+        hipLaunchKernelGGL((hop_lean_kernel<T, LT, true>), dim3(grid), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
+                           (const cx<T>*)in, (cx<T>*)out, p, nvec, vb, nsb, e);
+    else if (tps == 3)
+        hipLaunchKernelGGL((hop_lean_kernel<T, LT, false>), dim3(grid), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
+                           (const cx<T>*)in, (cx<T>*)out, p, nvec, vb, nsb, e);
+    else if (tps == 1)
+        hipLaunchKernelGGL((hop_kernel<T, LT, 1, false>), dim3(grid), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
+                           (const cx<T>*)in, (cx<T>*)out, p, nvec, vb, nsb, e);
     else if (tps == 2)
-        hipLaunchKernelGGL((hop_kernel<T, LT, 2>), dim3(grid), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
-                           (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e);
+        hipLaunchKernelGGL((hop_kernel<T, LT, 2, false>), dim3(grid), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
+                           (const cx<T>*)in, (cx<T>*)out, p, nvec, vb, nsb, e);
+    else if (hoist)
+        hipLaunchKernelGGL((hop_kernel<T, LT, 4, true>), dim3(grid), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
+                           (const cx<T>*)in, (cx<T>*)out, p, nvec, vb, nsb, e);
     else
-        hipLaunchKernelGGL((hop_kernel<T, LT, 4>), dim3(grid), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
-                           (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e);
+        hipLaunchKernelGGL((hop_kernel<T, LT, 4, false>), dim3(grid), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
+                           (const cx<T>*)in, (cx<T>*)out, p, nvec, vb, nsb, e);
 }
 
 void launch_hop(Prec prec, const Geom& g, const void* links, const void* in, void* out, int out_parity, int nvec,
-                const HopEpi& epi, int tps, hipStream_t s) {
+                const HopEpi& epi, int tps, int vb, hipStream_t s) {
     if (prec == P64)
-        launch_t<double, double>(g, links, in, out, out_parity, nvec, epi, tps, s);
+        launch_t<double, double>(g, links, in, out, out_parity, nvec, epi, tps, vb, s);
     else if (prec == P32)
-        launch_t<float, float>(g, links, in, out, out_parity, nvec, epi, tps, s);
+        launch_t<float, float>(g, links, in, out, out_parity, nvec, epi, tps, vb, s);
     else
-        launch_t<float, bf16link>(g, links, in, out, out_parity, nvec, epi, tps, s);
+        launch_t<float, bf16link>(g, links, in, out, out_parity, nvec, epi, tps, vb, s);
 }
 
 }  // namespace scg

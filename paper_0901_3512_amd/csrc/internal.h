@@ -144,8 +144,11 @@ struct HopEpi {
 };
 
 // out(parity p) = H_{p,1-p} in, with the epilogue above, for nvec vectors.
+// vb: vectors per workgroup (the links of a site are loaded once per workgroup)
 void launch_hop(Prec prec, const Geom& g, const void* links, const void* in, void* out, int out_parity,
-                int nvec, const HopEpi& epi, int tps, hipStream_t s);
+                int nvec, const HopEpi& epi, int tps, int vb, hipStream_t s);
 int hop_site_blocks(const Geom& g, int tps);
+bool hop_hoist_links();
+void set_hop_hoist_links(bool on);
 
 }  // namespace scg

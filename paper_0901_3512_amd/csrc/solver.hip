@@ -96,7 +96,8 @@ struct seedcg_s {
     bool lo = false;        // FP32 inner vectors (mixed precision)
     Prec lo_prec = P64;     // precision of the inner stencil
     int64_t N = 0;          // complex per vector
-    int tps64 = 4, tps_lo = 4;
+    int tps64 = 3, tps_lo = 3;
+    int vb64 = 1, vb_lo = 1;      // vectors per stencil workgroup
     int sync_every = 16;
 
     DBuf links64, links_lo;
@@ -159,7 +160,7 @@ void ensure_work(seedcg_s* h, int nvec) {
 void hop(seedcg_s* h, Prec pr, const void* L, const void* in, void* out, int par, int nvec, const HopEpi& e, int tps) {
     const bool sample = h->timing_every > 0 && (h->hop_count++ % h->timing_every) == 0 && h->ev_used < h->ev0.size();
     if (sample) HIPCHK(hipEventRecord(h->ev0[h->ev_used], h->s));
-    launch_hop(pr, h->g, L, in, out, par, nvec, e, tps, h->s);
+    launch_hop(pr, h->g, L, in, out, par, nvec, e, tps, pr == P64 ? h->vb64 : h->vb_lo, h->s);
     if (sample) {
         HIPCHK(hipEventRecord(h->ev1[h->ev_used], h->s));
         const double sl = pr == P64 ? 8.0 : (pr == P32 ? 4.0 : 2.0);
@@ -239,13 +240,13 @@ void apply_A_int(seedcg_s* h, const void* x, void* out, int nvec, bool dagger) {
     }
     HopEpi e{};
     e.sy = 1.0;
-    launch_hop(P64, h->g, h->links64.p, in, h->t1_64.p, 1, nvec, e, h->tps64, h->s);
+    launch_hop(P64, h->g, h->links64.p, in, h->t1_64.p, 1, nvec, e, h->tps64, h->vb64, h->s);
     HopEpi e2 = e;
     e2.combine = 1;
     e2.apply_g5 = dagger ? 1 : 0;
     e2.kappa2 = k2;
     e2.x = in;
-    launch_hop(P64, h->g, h->links64.p, h->t1_64.p, out, 0, nvec, e2, h->tps64, h->s);
+    launch_hop(P64, h->g, h->links64.p, h->t1_64.p, out, 0, nvec, e2, h->tps64, h->vb64, h->s);
 }
 
 void check_launch() { HIPCHK(hipGetLastError()); }
@@ -268,6 +269,13 @@ int64_t kchunk_for(int64_t n, int64_t target_chunks) {
     int64_t kc = (n + target_chunks - 1) / target_chunks;
     kc = (kc + 31) / 32 * 32;
     return std::max<int64_t>(std::min<int64_t>(kc, 65536), 512);
+}
+
+// K-chunk of the reorthogonalisation coefficients V_{1..i}^dag [v_i, f]: about 2048 workgroups
+// over the (chunk, 32-row block) grid, at least 96 chunks.
+int64_t reorth_kchunk(int64_t n, int i) {
+    const int64_t rowblocks = (i + 31) / 32;
+    return kchunk_for(n, std::max<int64_t>(96, 2048 / rowblocks));
 }
 
 void alloc_seed(seedcg_s* h, int nrhs) {
@@ -307,11 +315,11 @@ void alloc_seed(seedcg_s* h, int nrhs) {
     h->m_cap = (int32_t)cap;
     h->basis.ensure((size_t)cap * h->vec_bytes(lo));
     h->arrays.ensure(6 * ((int64_t)cap + 2) * sizeof(double));
-    const int64_t kcr = kchunk_for(N, 96);
-    const int64_t nchr = proj_chunks(N, kcr);
     h->G.ensure(2 * 2 * ((int64_t)cap + 1) * sizeof(double));
-    h->projpart.ensure(std::max<int64_t>(nchr * 4 * ((int64_t)cap + 1), proj_chunks(N, kchunk_for(N, 1024)) * 2 * 32 * 24) *
-                       sizeof(double));
+    int64_t part_doubles = proj_chunks(N, kchunk_for(N, 1024)) * 2 * 32 * 24;
+    for (int64_t i = 1; i <= cap; i++)
+        part_doubles = std::max<int64_t>(part_doubles, proj_chunks(N, reorth_kchunk(N, (int)i)) * 4 * i);
+    h->projpart.ensure(part_doubles * sizeof(double));
 }
 
 void flush_seed_block(seedcg_s* h, int i0, int i1, int nrhs) {
@@ -355,7 +363,7 @@ void reorthogonalise(seedcg_s* h, int i) {
         a.R[1] = h->f.p;
         a.nr = 2;
         a.n = N;
-        a.kchunk = kchunk_for(N, 96);
+        a.kchunk = reorth_kchunk(N, i);
         a.part = h->projpart.as<double>();
         a.part_stride = 4 * (int64_t)i;
         a.st = st;
@@ -727,11 +735,15 @@ seedcg_status seedcg_create(const seedcg_params* p, const double* links, seedcg_
         h->N = 12 * g.Vh;
         h->lo = p->prec != SEEDCG_FP64;
         h->lo_prec = p->prec == SEEDCG_MIXED_FP32 ? P32 : (p->prec == SEEDCG_MIXED_FP32_BF16LINKS ? P32BF : P64);
-        h->tps64 = env_int("SEEDCG_TPS", 4);
-        h->tps_lo = env_int("SEEDCG_TPS_LO", 4);
-        if (h->tps64 != 1 && h->tps64 != 2 && h->tps64 != 4) h->tps64 = 4;
-        if (h->tps_lo != 1 && h->tps_lo != 2 && h->tps_lo != 4) h->tps_lo = 4;
+        // stencil launch shape: 3 = two lanes per site (forward / backward hops), one vector per
+        // workgroup; the vectors of a site block run as adjacent workgroups on one XCD
+        h->tps64 = env_int("SEEDCG_TPS", 3);
+        h->tps_lo = env_int("SEEDCG_TPS_LO", 3);
+        if (h->tps64 < 1 || h->tps64 > 4) h->tps64 = 4;
+        if (h->tps_lo < 1 || h->tps_lo > 4) h->tps_lo = 4;
         h->sync_every = std::max(1, env_int("SEEDCG_SYNC_EVERY", 16));
+        h->vb64 = std::max(1, env_int("SEEDCG_VB", 1));
+        h->vb_lo = std::max(1, env_int("SEEDCG_VB_LO", 1));
         h->links64.ensure(4 * g.V * 9 * 16);
         pack_links(P64, g, links, h->links64.p, h->s);
         if (h->lo) {

@@ -20,12 +20,15 @@ def _vecs(rng, n, Vh):
     return rng.standard_normal((n, Vh, 4, 3)) + 1j * rng.standard_normal((n, Vh, 4, 3))
 
 
-@pytest.mark.parametrize("tps", [1, 2, 4])
+@pytest.mark.parametrize("tps", [1, 2, 3, 4])
 @pytest.mark.parametrize("dims,t_bc,eps", CASES)
-def test_apply_M_matches_oracle(dims, t_bc, eps, tps, monkeypatch):
+@pytest.mark.parametrize("vb", [1, 2])
+def test_apply_M_matches_oracle(dims, t_bc, eps, tps, vb, monkeypatch):
+    """tps: lanes per site (1, 2, 4) or 3 = the forward/backward lean variant; vb: vectors per workgroup."""
     from paper_0901_3512_amd import SeedCG
-    print_case("apply_M", dims, t_bc, tps)
+    print_case("apply_M", dims, t_bc, tps, vb)
     monkeypatch.setenv("SEEDCG_TPS", str(tps))
+    monkeypatch.setenv("SEEDCG_VB", str(vb))
     rng = np.random.default_rng(abs(hash((dims, t_bc))) % 2**32)
     U = random_su3_links(dims, eps, rng)
     kappa = 0.137

@@ -40,7 +40,8 @@ struct MfmaAcc<float> {
     __device__ static inline int row(int lane, int q) { return 4 * (lane >> 4) + q; }
 };
 
-template <typename T>
+// TS: storage type of V and R; T: compute type (FP32 storage may be contracted in FP64)
+template <typename TS, typename T>
 __global__ __launch_bounds__(256) void proj_kernel(ProjArgs pa) {
     using Acc = MfmaAcc<T>;
     using V4 = typename Acc::V4;
@@ -55,7 +56,7 @@ __global__ __launch_bounds__(256) void proj_kernel(ProjArgs pa) {
     const int nrow = min(PJ_ROWS, nvalid - row0);
     if (nrow <= 0) return;
 
-    const T* V = (const T*)pa.V;
+    const TS* V = (const TS*)pa.V;
     const int nr = pa.nr;
     const int ncol = 2 * nr;
     const int ncolt = (ncol + 15) / 16;
@@ -80,9 +81,9 @@ __global__ __launch_bounds__(256) void proj_kernel(ProjArgs pa) {
             const int r = idx / PJ_KC, c = idx % PJ_KC;
             T re = 0, im = 0;
             if (r < nrow && c < kc) {
-                const T* p = V + 2 * ((int64_t)(row0 + r) * pa.ldv + kb + c);
-                re = p[0];
-                im = p[1];
+                const TS* p = V + 2 * ((int64_t)(row0 + r) * pa.ldv + kb + c);
+                re = (T)p[0];
+                im = (T)p[1];
             }
             As[r * PJ_LD + 2 * c] = re;
             As[r * PJ_LD + 2 * c + 1] = im;
@@ -91,9 +92,9 @@ __global__ __launch_bounds__(256) void proj_kernel(ProjArgs pa) {
             const int j = idx / PJ_KC, c = idx % PJ_KC;
             T re = 0, im = 0;
             if (c < kc) {
-                const T* p = (const T*)pa.R[j] + 2 * (kb + c);
-                re = p[0];
-                im = p[1];
+                const TS* p = (const TS*)pa.R[j] + 2 * (kb + c);
+                re = (T)p[0];
+                im = (T)p[1];
             }
             Bs[j * PJ_LD + 2 * c] = re;
             Bs[j * PJ_LD + 2 * c + 1] = im;
@@ -163,13 +164,15 @@ __global__ void proj_reduce_kernel(const double* part, int64_t nchunks, int64_t 
 
 int64_t proj_chunks(int64_t n, int64_t kchunk) { return (n + kchunk - 1) / kchunk; }
 
-void project(bool fp32, const ProjArgs& a, int64_t nrowblocks, double* P, hipStream_t s) {
+void project(bool fp32, const ProjArgs& a, int64_t nrowblocks, double* P, hipStream_t s, bool fp64_math) {
     const int64_t nch = proj_chunks(a.n, a.kchunk);
     const dim3 grid((unsigned)nch, (unsigned)nrowblocks);
-    if (fp32)
-        hipLaunchKernelGGL(proj_kernel<float>, grid, dim3(256), 0, s, a);
+    if (fp32 && fp64_math)
+        hipLaunchKernelGGL((proj_kernel<float, double>), grid, dim3(256), 0, s, a);
+    else if (fp32)
+        hipLaunchKernelGGL((proj_kernel<float, float>), grid, dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL(proj_kernel<double>, grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((proj_kernel<double, double>), grid, dim3(256), 0, s, a);
     const int64_t len = 2 * (int64_t)a.nv * a.nr;
     hipLaunchKernelGGL(proj_reduce_kernel, dim3((unsigned)((len * SCG_WAVE + 255) / 256)), dim3(256), 0, s, a.part, nch, a.part_stride, len, P,
                        a.st, a.gate_i, a.flag);

@@ -113,7 +113,8 @@ struct LzState {
 // Device-side scalars of the multi-RHS CG.
 struct CgVec {
     double rr, rr_old, pq, a, b, bnorm, tol;
-    int32_t iters, done, frozen, pad;
+    double rr_reliable;  // true |r|^2 at the previous reliable update (mixed precision)
+    int32_t iters, done, frozen, restarts;
 };
 
 }  // namespace scg

@@ -31,7 +31,8 @@ struct ProjArgs {
     int i0;
     const int32_t* flag;    // optional gate: skip when *flag == 0
 };
-void project(bool fp32, const ProjArgs& a, int64_t nrowblocks, double* P, hipStream_t s);
+// fp32: V and R stored in FP32; fp64_math: contract them on the FP64 matrix cores anyway
+void project(bool fp32, const ProjArgs& a, int64_t nrowblocks, double* P, hipStream_t s, bool fp64_math = false);
 int64_t proj_chunks(int64_t n, int64_t kchunk);
 
 void pack_links(Prec prec, const Geom& g, const double* U, void* out, hipStream_t s);

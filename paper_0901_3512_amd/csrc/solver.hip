@@ -99,6 +99,7 @@ struct seedcg_s {
     int tps64 = 3, tps_lo = 3;
     int vb64 = 1, vb_lo = 1;      // vectors per stencil workgroup
     int sync_every = 16;
+    int debug = 0;
 
     DBuf links64, links_lo;
     // operator work vectors (FP64), sized for a batch
@@ -369,7 +370,8 @@ void reorthogonalise(seedcg_s* h, int i) {
         a.st = st;
         a.gate_i = i;
         a.flag = pass == 2 ? &st->rep_any : nullptr;
-        project(lo, a, (i + 31) / 32, h->G.as<double>(), h->s);
+        // the reorthogonalisation coefficients are always accumulated in FP64
+        project(lo, a, (i + 31) / 32, h->G.as<double>(), h->s, true);
         reorth_update(lo, i, pass, st, h->basis.p, N, h->G.as<double>(), vi, h->f.p, h->rpart.as<double>(), h->s);
         reorth_scalar(i, pass, st, h->rpart.as<double>(), nb, h->G.as<double>(), h->s);
         reorth_finish(lo, i, pass, st, vi, h->f.p, h->f2b.as<double>(), N, h->s);
@@ -563,10 +565,17 @@ seedcg_status solve_rest_impl(seedcg_s* h, const double* B, double* X, int nrhs,
     HIPCHK(hipMemcpyAsync(h->cgv.p, cg.data(), nrhs * sizeof(CgVec), hipMemcpyHostToDevice, h->s));
 
     const int max_iter = h->p.max_iter > 0 ? h->p.max_iter : 100000;
+    // Mixed precision: reliable updates (Sleijpen and van der Vorst) replace the FP32 recursive
+    // residual by the FP64 true residual b - M x whenever the recursive residual norm has fallen
+    // a decade below the one at the previous replacement, and at least every reliable_every
+    // iterations; the host looks every 4 iterations so that FP32 never tracks more than a few
+    // decades on its own.
     const int rel_every = lo ? std::max(1, h->p.reliable_every) : 0;
+    const int G = lo ? std::min(h->sync_every, 4) : h->sync_every;
+    std::vector<int> it_rel(nrhs, 0);
+    for (int j = 0; j < nrhs; j++) cg[j].rr_reliable = cg[j].rr;
     std::vector<int> active;
     bool noconv = false;
-    int since_reliable = 0;
     for (;;) {
         active.clear();
         for (int j = 0; j < nrhs; j++)
@@ -575,8 +584,6 @@ seedcg_status solve_rest_impl(seedcg_s* h, const double* B, double* X, int nrhs,
         std::vector<int32_t> vm(active.begin(), active.end());
         HIPCHK(hipMemcpyAsync(h->vmap.p, vm.data(), vm.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->s));
         const int nact = (int)vm.size();
-        int G = h->sync_every;
-        if (rel_every) G = std::min(G, std::max(1, rel_every - since_reliable));
         for (int it = 0; it < G; it++) {
             MOpts o;
             o.red = 1;
@@ -591,18 +598,24 @@ seedcg_status solve_rest_impl(seedcg_s* h, const double* B, double* X, int nrhs,
             cg_beta(h->cgv.as<CgVec>(), h->rrpart.as<double>(), nb, h->vmap.as<int32_t>(), nact, max_iter, h->s);
             cg_p(lo, h->cgv.as<CgVec>(), h->vmap.as<int32_t>(), nact, h->Pv.p, Rw, N, false, h->s);
         }
-        since_reliable += G;
         check_launch();
         HIPCHK(hipMemcpyAsync(cg.data(), h->cgv.p, nrhs * sizeof(CgVec), hipMemcpyDeviceToHost, h->s));
         HIPCHK(hipStreamSynchronize(h->s));
         for (int j : active) matvecs[j] = 1 + cg[j].iters;
+        if (h->debug)
+            for (int j : active)
+                fprintf(stderr, "cg j=%d it=%d rr=%.3e a=%.3e b=%.3e pq=%.3e frozen=%d done=%d restarts=%d\n", j, cg[j].iters,
+                        cg[j].rr, cg[j].a, cg[j].b, cg[j].pq, cg[j].frozen, cg[j].done, cg[j].restarts);
 
-        // true residual for frozen vectors (and, in mixed precision, the reliable update of all)
+        // true residual for frozen vectors and, in mixed precision, the reliable updates
         std::vector<int> check;
-        const bool reliable = rel_every && since_reliable >= rel_every;
-        for (int j : active)
-            if (cg[j].frozen || (reliable && !cg[j].done)) check.push_back(j);
-        if (reliable) since_reliable = 0;
+        std::vector<char> is_rel(nrhs, 0);
+        for (int j : active) {
+            const bool rel = rel_every && !cg[j].frozen &&
+                             (cg[j].rr <= 1e-2 * cg[j].rr_reliable || cg[j].iters - it_rel[j] >= rel_every);
+            if (cg[j].frozen || rel) check.push_back(j);
+            is_rel[j] = rel;
+        }
         if (check.empty()) continue;
         true_residual(h, check, h->R64.p, h->cgpart.as<double>());
         sum_partials(h->cgpart.as<double>(), nsb64, nrhs, h->norms.as<double>() + nrhs, false, h->s);
@@ -629,7 +642,15 @@ seedcg_status solve_rest_impl(seedcg_s* h, const double* B, double* X, int nrhs,
                 c.b = rr / c.rr;
                 c.frozen = 0;
                 restart.push_back(j);
+            } else if (is_rel[j] && rr >= c.rr_reliable) {
+                // no decrease of the true residual since the previous replacement: the inner
+                // operator is too far from M for the old directions; restart with p = r
+                c.b = 0.0;
+                c.restarts += 1;
+                restart.push_back(j);
             }
+            c.rr_reliable = rr;
+            it_rel[j] = c.iters;
             c.rr = rr;
         }
         // r = b - M x in the working precision, then p = r + b p for the restarted ones
@@ -742,6 +763,7 @@ seedcg_status seedcg_create(const seedcg_params* p, const double* links, seedcg_
         if (h->tps64 < 1 || h->tps64 > 4) h->tps64 = 4;
         if (h->tps_lo < 1 || h->tps_lo > 4) h->tps_lo = 4;
         h->sync_every = std::max(1, env_int("SEEDCG_SYNC_EVERY", 16));
+        h->debug = env_int("SEEDCG_DEBUG", 0);
         h->vb64 = std::max(1, env_int("SEEDCG_VB", 1));
         h->vb_lo = std::max(1, env_int("SEEDCG_VB_LO", 1));
         h->links64.ensure(4 * g.V * 9 * 16);
@@ -774,6 +796,23 @@ seedcg_status seedcg_apply_M(seedcg_t h, const double* x, double* y, int32_t nve
         pack_vec(false, x, xi.p, h->g.Vh, nvec, h->s);
         apply_M_int(h, false, xi.p, yi.p, nvec, MOpts{});
         unpack_vec(false, yi.p, y, h->g.Vh, nvec, h->s);
+        check_launch();
+        HIPCHK(hipStreamSynchronize(h->s));
+        return SEEDCG_OK;
+    });
+}
+
+seedcg_status seedcg_apply_M_inner(seedcg_t h, const double* x, double* y, int32_t nvec) {
+    if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "apply_M_inner: null handle");
+    return guarded(h, [&]() -> seedcg_status {
+        if (!x || !y || nvec < 1) throw ArgError{"apply_M_inner: null pointer or nvec < 1"};
+        if (x == y) throw ArgError{"apply_M_inner: x and y alias"};
+        DBuf xi, yi;
+        xi.ensure(nvec * h->vec_bytes(h->lo));
+        yi.ensure(nvec * h->vec_bytes(h->lo));
+        pack_vec(h->lo, x, xi.p, h->g.Vh, nvec, h->s);
+        apply_M_int(h, h->lo, xi.p, yi.p, nvec, MOpts{});
+        unpack_vec(h->lo, yi.p, y, h->g.Vh, nvec, h->s);
         check_launch();
         HIPCHK(hipStreamSynchronize(h->s));
         return SEEDCG_OK;

@@ -58,6 +58,7 @@ def load_library():
         "seedcg_default_params": (None, [ctypes.POINTER(Params)]),
         "seedcg_create": (i32, [ctypes.POINTER(Params), P, ctypes.POINTER(H)]),
         "seedcg_apply_M": (i32, [H, P, P, i32]),
+        "seedcg_apply_M_inner": (i32, [H, P, P, i32]),
         "seedcg_apply_A": (i32, [H, P, P, i32, i32]),
         "seedcg_solve_seed": (i32, [H, P, P, i32, ctypes.POINTER(Report)]),
         "seedcg_solve_rest": (i32, [H, P, P, i32, ctypes.POINTER(Report)]),
@@ -81,7 +82,7 @@ def load_library():
 
 def exported_symbols():
     """Names of the C ABI entry points this binding expects."""
-    return ["seedcg_default_params", "seedcg_create", "seedcg_apply_M", "seedcg_apply_A", "seedcg_solve_seed",
+    return ["seedcg_default_params", "seedcg_create", "seedcg_apply_M", "seedcg_apply_M_inner", "seedcg_apply_A", "seedcg_solve_seed",
             "seedcg_solve_rest", "seedcg_get_tridiag", "seedcg_get_basis_vector", "seedcg_project",
             "seedcg_update", "seedcg_set_timing", "seedcg_get_timing", "seedcg_release_basis", "seedcg_destroy",
             "seedcg_last_error"]
@@ -162,6 +163,13 @@ class SeedCG:
         x = _check_vec(x, self.Vh, "x")
         y = torch.empty_like(x)
         self._rc(self._lib.seedcg_apply_M(self._h, x.data_ptr(), y.data_ptr(), x.shape[0]))
+        return y
+
+    def apply_M_inner(self, x):
+        """M x with the solver's inner precision (FP32/BF16 links for the mixed modes)."""
+        x = _check_vec(x, self.Vh, "x")
+        y = torch.empty_like(x)
+        self._rc(self._lib.seedcg_apply_M_inner(self._h, x.data_ptr(), y.data_ptr(), x.shape[0]))
         return y
 
     def apply_A(self, x, dagger=False):

@@ -1,0 +1,125 @@
+"""Mixed precision (FP32 stencil, basis and CG; optional BF16 links; FP64 reliable updates).
+
+  * The inner operator against the oracle applied to the same rounded inputs (links rounded
+    to FP32 or to BF16 by round-to-nearest-even, x rounded to FP32): this isolates the FP32
+    arithmetic, bar 5e-6 relative to max |M x|.
+  * Full solves: every right-hand side reaches an FP64 true relative residual <= 1e-10 by the
+    oracle's FP64 M, and agrees with the dense FP64 solution to 1e-8.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import cuda, host, print_case, relmax
+from oracle import seedcg as osc
+from oracle.wilson import WilsonEO, dense, flat, matvec_M
+from synth.configs import make_inputs
+from synth.links import random_su3_links
+
+pytestmark = pytest.mark.gpu
+
+
+def round_fp32(a):
+    return a.real.astype(np.float32).astype(np.float64) + 1j * a.imag.astype(np.float32).astype(np.float64)
+
+
+def _bf16(x):
+    f = np.ascontiguousarray(x, dtype=np.float64).astype(np.float32)
+    b = f.view(np.uint32).astype(np.uint64)
+    b = ((b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    return b.view(np.float32).astype(np.float64)
+
+
+def round_bf16(a):
+    return _bf16(a.real) + 1j * _bf16(a.imag)
+
+
+@pytest.mark.parametrize("prec,rounder", [("mixed", round_fp32), ("mixed_bf16", round_bf16)])
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 2, 6), (8, 8, 8, 16)])
+def test_inner_operator_matches_oracle_on_rounded_inputs(prec, rounder, dims):
+    from paper_0901_3512_amd import SeedCG
+    print_case("inner", prec, dims)
+    rng = np.random.default_rng(4)
+    U = random_su3_links(dims, 0.4, rng)
+    kappa = 0.13
+    op = WilsonEO(rounder(U), dims, kappa)
+    Vh = op.Vh
+    x = round_fp32(rng.standard_normal((2, Vh, 4, 3)) + 1j * rng.standard_normal((2, Vh, 4, 3)))
+    s = SeedCG(cuda(U), dims, kappa, prec=prec)
+    y = host(s.apply_M_inner(cuda(x)))
+    assert relmax(y, op.apply_M(x)) <= 5e-6
+
+
+@pytest.fixture(scope="module")
+def t8():
+    """8^4, kappa 0.13 (physical branch): the FP32 operator keeps Lanczos well defined."""
+    U, phi, kappa = make_inputs("t8")
+    dims = (8, 8, 8, 8)
+    op = WilsonEO(U, dims, kappa)
+    B = op.apply_Adag(phi)
+    mv = matvec_M(op)
+    ref = osc.seed_cg(mv, flat(B), k=10, tol=1e-10, past=1.5)
+    xs = np.stack([osc.cg(mv, flat(B)[j], ref["X"][j], tol=1e-13)[0] for j in range(B.shape[0])])
+    return dict(U=U, dims=dims, kappa=kappa, B=B, mv=mv, xs=xs, ref=ref)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    U, phi, kappa = make_inputs("c1")
+    dims = (4, 4, 4, 4)
+    op = WilsonEO(U, dims, kappa)
+    B = op.apply_Adag(phi)
+    mv = matvec_M(op)
+    xs = np.linalg.solve(dense(mv, 12 * op.Vh), flat(B).T).T
+    return dict(U=U, dims=dims, kappa=kappa, B=B, mv=mv, xs=xs)
+
+
+@pytest.mark.parametrize("prec", ["mixed", "mixed_bf16"])
+def test_mixed_solve_reaches_fp64_tolerance(t8, prec):
+    from paper_0901_3512_amd import SeedCG
+    print_case("mixed solve", prec)
+    s = SeedCG(cuda(t8["U"]), t8["dims"], t8["kappa"], prec=prec, reorth_k=10, reliable_every=50, max_iter=5000)
+    Bd = cuda(t8["B"])
+    X, rs = s.solve_seed(Bd)
+    assert rs["seed_status"] == "ok"
+    res_seed = osc.true_relres(t8["mv"], flat(t8["B"]), flat(host(X)))
+    assert np.all(res_seed < 1.0)
+    X, rr = s.solve_rest(Bd, X)
+    x = flat(host(X))
+    res = osc.true_relres(t8["mv"], flat(t8["B"]), x)
+    assert np.all(res <= 1e-10), res
+    err = np.linalg.norm(x - t8["xs"], axis=1) / np.linalg.norm(t8["xs"], axis=1)
+    assert np.all(err <= 1e-8), err
+
+
+def test_mixed_seed_basis_orthogonality_and_tridiag(t8):
+    """FP32 basis with FP64 reorthogonalisation coefficients stays orthogonal to FP32 accuracy, and
+    its T matches the FP64 oracle's in the first steps to FP32 accuracy."""
+    from paper_0901_3512_amd import SeedCG
+    print_case("mixed basis")
+    s = SeedCG(cuda(t8["U"]), t8["dims"], t8["kappa"], prec="mixed", reorth_k=10)
+    X, rs = s.solve_seed(cuda(t8["B"]))
+    m = rs["m"]
+    assert abs(m - t8["ref"]["m"]) <= max(2, m // 20)
+    Vg = np.stack([flat(host(s.get_basis_vector(i))) for i in range(1, m + 1)])
+    assert osc.orth_loss(Vg) <= 1e-5
+    a, b = s.get_tridiag()
+    n = 10
+    ref = t8["ref"]
+    assert np.max(np.abs(np.array(a[:n]) - ref["alpha"][:n]) / np.abs(ref["alpha"][:n])) <= 1e-5
+
+
+def test_mixed_at_large_kappa_still_converges(c1):
+    """At kappa = 0.8 the hopping term is ~40x the identity and FP32 rounding breaks the Lanczos
+    invariants (the same happens to the oracle's Algorithm 1 run on an FP32-rounded M); the seed
+    reports it and plain CG with FP64 reliable updates still reaches the FP64 tolerance."""
+    from paper_0901_3512_amd import SeedCG
+    print_case("mixed large kappa")
+    s = SeedCG(cuda(c1["U"]), c1["dims"], c1["kappa"], prec="mixed", reorth_k=10, max_iter=20000)
+    Bd = cuda(c1["B"])
+    X, rs = s.solve_seed(Bd)
+    X, rr = s.solve_rest(Bd, X)
+    x = flat(host(X))
+    res = osc.true_relres(c1["mv"], flat(c1["B"]), x)
+    assert np.all(res <= 1e-10), res
+    err = np.linalg.norm(x - c1["xs"], axis=1) / np.linalg.norm(c1["xs"], axis=1)
+    assert np.all(err <= 1e-8), err

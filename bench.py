@@ -131,7 +131,8 @@ def main():
     hop_bytes = tm["bytes"] / max(tm["launches"], 1)
     achieved = hop_bytes / (hop_ms * 1e-3) / 1e9 if tm["launches"] else None
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                "traffic": measured_traffic(cfg, prec),
                 "kernel": "hop_kernel (even-odd Wilson hop, fused epilogues)", "launches_sampled": tm["launches"],
                 "avg_launch_us": hop_ms * 1e3, "avg_launch_bytes": hop_bytes}
 
@@ -159,6 +160,21 @@ def main():
                    "hop_launches_total": tm["seen"]},
     }
     print(json.dumps(result), flush=True)
+
+
+def measured_traffic(cfg, prec):
+    """HBM bytes per stencil launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary of this
+    workload, or None when there is none or the stencil source changed since it was taken."""
+    from paper_0901_3512_amd.profsummary import source_digest
+    name = f"hop_kernel_{'x'.join(map(str, cfg.dims))}_{prec}_traffic.txt"
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    kv = dict(l.strip().split("=", 1) for l in open(path) if "=" in l and not l.startswith("#"))
+    src = os.path.join(ROOT, "paper_0901_3512_amd", "csrc", "dslash.hip")
+    if kv.get("source_sha256_16") != source_digest(src):
+        return None
+    return float(kv["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(cfg, U, phi, kappa, rep, n_iter):

@@ -148,6 +148,36 @@ seedcg_status seedcg_set_timing(seedcg_t h, int32_t sample_every, int32_t max_sa
    their total flops (1320 per site and vector), and the number of stencil launches seen. */
 seedcg_status seedcg_get_timing(seedcg_t h, double* out);
 
+/* ---- learned preconditioner P = K K^dag (an addition to the paper's method) -------------------
+   K = R_e L_3 L_2 L_1 E_e on full-lattice 12-spinors: E_e embeds an even-site vector (zero on odd
+   sites), R_e restricts to the even sites, and each layer is
+       (L psi)(x) = sum_{d=0..8} (w_d (x) 1_colour)(T_d psi)(x),
+   T_0 = 1, T_{+mu} psi(x) = U_mu(x) psi(x+mu), T_{-mu} psi(x) = U_mu(x-mu)^dag psi(x-mu) (with the
+   t boundary sign), d = 1..4 for +x..+t and 5..8 for -x..-t.  K^dag uses L^dag = sum_d (w_d^dag
+   (x) 1) T_{-d}.  Weights are 3 x 9 complex 4x4 spin matrices, [layer][d][a][b], 432 complex
+   (interleaved re, im), HOST arrays.  P is applied in FP32. */
+
+/* Trains K by `steps` Adam steps (learning rate lr, betas 0.9 / 0.999, eps 1e-8) from K = 1 on
+   the loss mean_s |K K^dag y_s - u_s|^2 / |u_s|^2 over u_s = the n_ritz lowest Ritz vectors of T
+   (V s, T s = theta s, from the last solve_seed) and n_lanczos stored basis vectors, y_s = M u_s.
+   out (HOST, may be NULL): initial loss, final loss, seconds, Ritz vectors used, training vectors.
+   Needs the basis of the last solve_seed (SEEDCG_ERR_STATE otherwise). */
+seedcg_status seedcg_train_precond(seedcg_t h, int32_t steps, int32_t n_ritz, int32_t n_lanczos, double lr, double* out);
+
+/* on != 0: solve_rest runs preconditioned CG with P = K K^dag (needs weights). */
+seedcg_status seedcg_use_precond(seedcg_t h, int32_t on);
+
+/* Sets / reads the weights of K (HOST arrays of 3*9*16 complex). */
+seedcg_status seedcg_set_precond_weights(seedcg_t h, const double* w);
+seedcg_status seedcg_get_precond_weights(seedcg_t h, double* w);
+
+/* y = K K^dag x for nvec even-site vectors (device, canonical layout). */
+seedcg_status seedcg_apply_P(seedcg_t h, const double* x, double* y, int32_t nvec);
+
+/* The training loss for pairs (U, Y) of S even-site vectors (device, canonical layout, 1 <= S <= 32)
+   at the current weights, and its Wirtinger gradient dL/d(conj w) (HOST, 432 complex, may be NULL). */
+seedcg_status seedcg_precond_loss_grad(seedcg_t h, const double* U, const double* Y, int32_t S, double* loss, double* grad);
+
 /* Frees the Krylov basis (the paper allocates it for the first right-hand side only). */
 seedcg_status seedcg_release_basis(seedcg_t h);
 

@@ -563,19 +563,73 @@ void reorth_decide(int i, int pass, LzState* st, const double* f2b, const double
 // ---------------------------------------------------------------------------------------------
 __device__ inline bool cg_skip(const CgVec& c) { return c.done || c.frozen; }
 
-// a_j = rr_j / Re(p_j^dag q_j)
-__global__ void cg_alpha_kernel(CgVec* cg, const double* part, int64_t nb, const int32_t* vec_map) {
+// a_j = rr_j / Re(p_j^dag q_j)   (preconditioned: rz_j = Re r_j^dag z_j in the numerator)
+__global__ void cg_alpha_kernel(CgVec* cg, const double* part, int64_t nb, const int32_t* vec_map, int pc) {
     __shared__ double lds[SCG_BLOCK / SCG_WAVE];
     const int vec = vec_map[blockIdx.x];
     if (cg_skip(cg[vec])) return;
     const double pq = block_sum_array(part + (int64_t)vec * nb, nb, lds);
     if (threadIdx.x == 0) {
         cg[vec].pq = pq;
-        cg[vec].a = cg[vec].rr / pq;
+        cg[vec].a = (pc ? cg[vec].rz : cg[vec].rr) / pq;
     }
 }
-void cg_alpha(CgVec* cg, const double* part, int64_t nb, const int32_t* vec_map, int nact, hipStream_t s) {
-    hipLaunchKernelGGL(cg_alpha_kernel, dim3(nact), dim3(SCG_BLOCK), 0, s, cg, part, nb, vec_map);
+void cg_alpha(CgVec* cg, const double* part, int64_t nb, const int32_t* vec_map, int nact, hipStream_t s, bool pc) {
+    hipLaunchKernelGGL(cg_alpha_kernel, dim3(nact), dim3(SCG_BLOCK), 0, s, cg, part, nb, vec_map, (int)pc);
+}
+
+// partials of Re a_v^dag b_v for the vectors of vec_map (grid: blocks x nact)
+template <typename T>
+__global__ void dot_map_kernel(const cx<T>* __restrict__ a, const cx<T>* __restrict__ b, int64_t n, const int32_t* vec_map,
+                               const CgVec* cg, double* part, int64_t nb) {
+    __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    const int vec = vec_map[blockIdx.y];
+    if (cg && cg_skip(cg[vec])) return;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    if (k < n) {
+        const cx<T> x = a[(int64_t)vec * n + k], y = b[(int64_t)vec * n + k];
+        s = (double)x.re * y.re + (double)x.im * y.im;
+    }
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) part[(int64_t)vec * nb + blockIdx.x] = s;
+}
+void dot_map(bool fp32, const void* a, const void* b, int64_t n, const int32_t* vec_map, int nact, const CgVec* cg, double* part,
+             hipStream_t s) {
+    const int64_t nb = (n + SCG_BLOCK - 1) / SCG_BLOCK;
+    const dim3 grid((unsigned)nb, nact);
+    if (fp32)
+        hipLaunchKernelGGL(dot_map_kernel<float>, grid, dim3(SCG_BLOCK), 0, s, (const cx<float>*)a, (const cx<float>*)b, n, vec_map, cg,
+                           part, nb);
+    else
+        hipLaunchKernelGGL(dot_map_kernel<double>, grid, dim3(SCG_BLOCK), 0, s, (const cx<double>*)a, (const cx<double>*)b, n, vec_map,
+                           cg, part, nb);
+}
+
+// preconditioned CG: rr_new = |r|^2 for the stop test, rz_new = Re r^dag z, b = rz_new / rz
+__global__ void cg_beta_pc_kernel(CgVec* cg, const double* rrpart, const double* rzpart, int64_t nb, const int32_t* vec_map, int max_iter) {
+    __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    const int vec = vec_map[blockIdx.x];
+    if (cg_skip(cg[vec])) return;
+    const double rr = block_sum_array(rrpart + (int64_t)vec * nb, nb, lds);
+    __syncthreads();
+    const double rz = block_sum_array(rzpart + (int64_t)vec * nb, nb, lds);
+    if (threadIdx.x != 0) return;
+    CgVec& c = cg[vec];
+    c.iters += 1;
+    if (sqrt(rr) <= c.tol * c.bnorm || c.iters >= max_iter || !isfinite(rr) || !(rz > 0.0)) {
+        c.frozen = 1;
+        c.pq = rr;
+        return;
+    }
+    c.b = rz / c.rz;
+    c.rz = rz;
+    c.rr_old = c.rr;
+    c.rr = rr;
+}
+void cg_beta_pc(CgVec* cg, const double* rrpart, const double* rzpart, int64_t nb, const int32_t* vec_map, int nact, int max_iter,
+                hipStream_t s) {
+    hipLaunchKernelGGL(cg_beta_pc_kernel, dim3(nact), dim3(SCG_BLOCK), 0, s, cg, rrpart, rzpart, nb, vec_map, max_iter);
 }
 
 // x += a p; r -= a q; partials |r|^2

@@ -114,6 +114,7 @@ struct LzState {
 struct CgVec {
     double rr, rr_old, pq, a, b, bnorm, tol;
     double rr_reliable;  // true |r|^2 at the previous reliable update (mixed precision)
+    double rz;           // Re r^dag z with z = P r (preconditioned CG)
     int32_t iters, done, frozen, restarts;
 };
 

@@ -63,11 +63,29 @@ void reorth_scalar(int i, int pass, LzState* st, const double* part, int64_t nb,
 void reorth_finish(bool fp32, int i, int pass, const LzState* st, void* v, void* f, double* f2part, int64_t n, hipStream_t s);
 void reorth_decide(int i, int pass, LzState* st, const double* f2b, const double* f2a, int64_t nb, hipStream_t s);
 
-void cg_alpha(CgVec* cg, const double* part, int64_t nb, const int32_t* vec_map, int nact, hipStream_t s);
+void cg_alpha(CgVec* cg, const double* part, int64_t nb, const int32_t* vec_map, int nact, hipStream_t s, bool pc = false);
+void dot_map(bool fp32, const void* a, const void* b, int64_t n, const int32_t* vec_map, int nact, const CgVec* cg, double* part,
+             hipStream_t s);
+void cg_beta_pc(CgVec* cg, const double* rrpart, const double* rzpart, int64_t nb, const int32_t* vec_map, int nact, int max_iter,
+                hipStream_t s);
 void cg_update(bool fp32, bool x32, const CgVec* cg, const int32_t* vec_map, int nact, void* X, const void* P, void* R,
                const void* Q, double* part, int64_t n, hipStream_t s);
 void cg_beta(CgVec* cg, const double* part, int64_t nb, const int32_t* vec_map, int nact, int max_iter, hipStream_t s);
 void cg_p(bool fp32, const CgVec* cg, const int32_t* vec_map, int nact, void* P, const void* R, int64_t n, bool ignore_frozen,
           hipStream_t s);
+
+// learned preconditioner K (learned.hip); fields are [vec][parity][12][Vh] complex FP32
+void k_layer(const Geom& g, const void* links32, const void* in, void* out, const void* W, bool dagger, const int32_t* vmap,
+             int nvec, bool zero_odd_input, hipStream_t s);
+void k_grad(const Geom& g, const void* links32, const void* gv, const void* in, bool dagger, int nvec, double* part, double* Gtot,
+            hipStream_t s);
+int64_t k_grad_blocks(const Geom& g);
+void k_embed(bool x32, const void* x, void* full, int64_t n, const int32_t* vmap, int nvec, hipStream_t s);
+void k_restrict(bool x32, const void* full, void* x, int64_t n, const int32_t* vmap, int nvec, hipStream_t s);
+void k_zero_odd(void* full, int64_t n, int nvec, hipStream_t s);
+void k_residual(const void* zfull, const void* u, const double* unorm2, void* gfull, int64_t n, int S, double* part, hipStream_t s);
+int64_t k_residual_blocks(int64_t n);
+void k_adam(double* Wm, void* W32, double* G, double* m, double* v, int t, double lr, int n, hipStream_t s);
+void k_combine(bool v32, const void* V, int m, const double* S, int nout, void* X, int64_t n, hipStream_t s);
 
 }  // namespace scg

@@ -113,6 +113,11 @@ struct seedcg_s {
     int seed_nrhs = 0;
     // CG
     DBuf cgv, vmap, Pv, Rv, Qv, R64, cgpart, rrpart, respart, norms;
+    // learned preconditioner P = K K^dag (FP32 weights, FP64 Adam master copy)
+    bool k_ready = false;
+    DBuf kW32, kWm, kG, kAm, kAv, kpart, klinks32, kU, kY, kun2, klpart, kS, kfield, pfa, pfb, Zv, rzpart;
+    int k_steps = 0, k_train_vecs = 0, k_ritz = 0;
+    double k_loss0 = 0.0, k_loss1 = 0.0, k_t_train = 0.0;
     // sampled timing of the stencil launches (hipEvent pairs on the handle's stream)
     int timing_every = 0;
     int64_t hop_count = 0;
@@ -497,6 +502,254 @@ void solve_seed_impl(seedcg_s* h, const double* B, double* X, int nrhs, seedcg_r
 }
 
 // ---------------------------------------------------------------------------------------------
+// learned preconditioner P = K K^dag
+// ---------------------------------------------------------------------------------------------
+constexpr int K_LAYERS = 3, K_NW = 9 * 16;   // complex weights per layer
+constexpr int K_NREAL = K_LAYERS * K_NW * 2;  // reals updated by Adam
+
+// FP32 links for the transports of K (the inner links when they are FP32, else a copy)
+const void* k_links(seedcg_s* h) {
+    if (h->lo && h->lo_prec == P32) return h->links_lo.p;
+    if (!h->klinks32.p) {
+        // repack from the FP64 internal copy: same layout, entry by entry
+        h->klinks32.ensure(4 * h->g.V * 9 * 8);
+        convert(false, true, h->links64.p, h->klinks32.p, 4 * h->g.V * 9, h->s);
+    }
+    return h->klinks32.p;
+}
+
+const void* k_weights(seedcg_s* h, int layer) { return (const char*)h->kW32.p + (int64_t)layer * K_NW * 8; }
+
+// z = K K^dag r for the vectors of vmap (r and z in the working precision)
+void apply_P(seedcg_s* h, bool low, const void* r, void* z, const int32_t* vmap, int nact, int nalloc) {
+    const int64_t N = h->N;
+    h->pfa.ensure((int64_t)nalloc * 2 * N * 8);
+    h->pfb.ensure((int64_t)nalloc * 2 * N * 8);
+    const void* L = k_links(h);
+    k_embed(low, r, h->pfa.p, N, vmap, nact, h->s);
+    // K^dag = R_e L_1^dag L_2^dag L_3^dag E_e
+    k_layer(h->g, L, h->pfa.p, h->pfb.p, k_weights(h, 2), true, vmap, nact, true, h->s);
+    k_layer(h->g, L, h->pfb.p, h->pfa.p, k_weights(h, 1), true, vmap, nact, false, h->s);
+    k_layer(h->g, L, h->pfa.p, h->pfb.p, k_weights(h, 0), true, vmap, nact, false, h->s);
+    // K = R_e L_3 L_2 L_1 E_e (the odd half of pfb is ignored by the zero-odd layer)
+    k_layer(h->g, L, h->pfb.p, h->pfa.p, k_weights(h, 0), false, vmap, nact, true, h->s);
+    k_layer(h->g, L, h->pfa.p, h->pfb.p, k_weights(h, 1), false, vmap, nact, false, h->s);
+    k_layer(h->g, L, h->pfb.p, h->pfa.p, k_weights(h, 2), false, vmap, nact, false, h->s);
+    k_restrict(low, h->pfa.p, z, N, vmap, nact, h->s);
+}
+
+// Lowest eigenpairs of the symmetric tridiagonal T (diagonal a[0..m), off-diagonal b[0..m-2]) by
+// Sturm-sequence bisection and inverse iteration (Wilkinson's classical method).
+int sturm_count(const std::vector<double>& a, const std::vector<double>& b, double x) {
+    int cnt = 0;
+    double d = 1.0;
+    for (size_t i = 0; i < a.size(); i++) {
+        d = a[i] - x - (i ? b[i - 1] * b[i - 1] / d : 0.0);
+        if (d == 0.0) d = -1e-300;
+        if (d < 0.0) cnt++;
+    }
+    return cnt;
+}
+
+void ritz_lowest(const std::vector<double>& a, const std::vector<double>& b, int want, std::vector<double>& lam,
+                 std::vector<double>& vecs /* m x nout, row-major */) {
+    const int m = (int)a.size();
+    double lo = a[0], hi = a[0];
+    for (int i = 0; i < m; i++) {
+        const double r = (i ? std::fabs(b[i - 1]) : 0.0) + (i < m - 1 ? std::fabs(b[i]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+    }
+    const double scale = std::max(std::fabs(lo), std::fabs(hi));
+    lam.clear();
+    std::vector<std::vector<double>> ys;
+    for (int k = 0; k < m && (int)lam.size() < want; k++) {
+        double l = lo, u = hi;  // the (k+1)-th smallest eigenvalue lies in [l, u]
+        for (int it = 0; it < 200 && u - l > 4e-16 * scale; it++) {
+            const double mid = 0.5 * (l + u);
+            if (sturm_count(a, b, mid) > k) u = mid; else l = mid;
+        }
+        const double ev = 0.5 * (l + u);
+        if (!lam.empty() && std::fabs(ev - lam.back()) <= 1e-8 * std::max(std::fabs(ev), 1e-300)) continue;  // ghost copy
+        // inverse iteration with (T - (ev + tiny) I), Thomas algorithm
+        std::vector<double> y(m, 1.0 / std::sqrt((double)m)), c(m), d(m), rhs(m);
+        const double shift = ev + 1e-12 * scale;
+        for (int it = 0; it < 3; it++) {
+            for (int i = 0; i < m; i++) d[i] = a[i] - shift;
+            rhs = y;
+            for (int i = 1; i < m; i++) {
+                const double piv = (d[i - 1] == 0.0) ? 1e-300 : d[i - 1];
+                const double f = b[i - 1] / piv;
+                d[i] -= f * b[i - 1];
+                rhs[i] -= f * rhs[i - 1];
+            }
+            y[m - 1] = rhs[m - 1] / (d[m - 1] == 0.0 ? 1e-300 : d[m - 1]);
+            for (int i = m - 2; i >= 0; i--) y[i] = (rhs[i] - b[i] * y[i + 1]) / (d[i] == 0.0 ? 1e-300 : d[i]);
+            double nrm = 0.0;
+            for (double v : y) nrm += v * v;
+            nrm = std::sqrt(nrm);
+            for (double& v : y) v /= nrm;
+        }
+        lam.push_back(ev);
+        ys.push_back(y);
+    }
+    const int nout = (int)lam.size();
+    vecs.assign((size_t)m * nout, 0.0);
+    for (int j = 0; j < nout; j++)
+        for (int i = 0; i < m; i++) vecs[(size_t)i * nout + j] = ys[j][i];
+}
+
+// One pass over the training set (kU, kY, kun2 of S vectors): the loss and, if `backward`,
+// its gradient accumulated into kG.  Returns the loss when `want_loss` (else 0).
+double k_pass(seedcg_s* h, int S, bool backward, bool want_loss) {
+    const int64_t N = h->N;
+    const int64_t fb = (int64_t)S * 2 * N * 8;
+    h->kfield.ensure(10 * fb);
+    auto F = [&](int i) { return (void*)((char*)h->kfield.p + i * fb); };
+    void *a0 = F(0), *a1 = F(1), *a2 = F(2), *a3 = F(3), *b0 = F(4), *b1 = F(5), *b2 = F(6), *b3 = F(7), *g = F(8), *gt = F(9);
+    h->kpart.ensure(9 * k_grad_blocks(h->g) * 32 * sizeof(double));
+    const int64_t nbr = k_residual_blocks(N);
+    h->klpart.ensure(std::max<int64_t>(norm2_blocks(N), nbr) * S * sizeof(double));
+    const void* L = k_links(h);
+    double* Gl[3] = {h->kG.as<double>(), h->kG.as<double>() + K_NW * 2, h->kG.as<double>() + 2 * K_NW * 2};
+    // forward: a = K^dag chain on E_e y, b = K chain on E_e R_e a3
+    k_embed(true, h->kY.p, a0, N, nullptr, S, h->s);
+    k_layer(h->g, L, a0, a1, k_weights(h, 2), true, nullptr, S, true, h->s);
+    k_layer(h->g, L, a1, a2, k_weights(h, 1), true, nullptr, S, false, h->s);
+    k_layer(h->g, L, a2, a3, k_weights(h, 0), true, nullptr, S, false, h->s);
+    HIPCHK(hipMemcpyAsync(b0, a3, fb, hipMemcpyDeviceToDevice, h->s));
+    k_zero_odd(b0, N, S, h->s);
+    k_layer(h->g, L, b0, b1, k_weights(h, 0), false, nullptr, S, true, h->s);
+    k_layer(h->g, L, b1, b2, k_weights(h, 1), false, nullptr, S, false, h->s);
+    k_layer(h->g, L, b2, b3, k_weights(h, 2), false, nullptr, S, false, h->s);
+    k_residual(b3, h->kU.p, h->kun2.as<double>(), g, N, S, h->klpart.as<double>(), h->s);
+    double loss = 0.0;
+    if (want_loss) {
+        DBuf lossv;
+        lossv.ensure(S * sizeof(double));
+        sum_partials(h->klpart.as<double>(), nbr, S, lossv.as<double>(), false, h->s);
+        std::vector<double> lv(S);
+        HIPCHK(hipMemcpyAsync(lv.data(), lossv.p, S * sizeof(double), hipMemcpyDeviceToHost, h->s));
+        HIPCHK(hipStreamSynchronize(h->s));
+        for (double v : lv) loss += v;
+        loss /= S;
+    }
+    if (!backward) return loss;
+    // backward through K (layers 3, 2, 1) ...
+    k_grad(h->g, L, g, b2, false, S, h->kpart.as<double>(), Gl[2], h->s);
+    k_layer(h->g, L, g, gt, k_weights(h, 2), true, nullptr, S, false, h->s);
+    k_grad(h->g, L, gt, b1, false, S, h->kpart.as<double>(), Gl[1], h->s);
+    k_layer(h->g, L, gt, g, k_weights(h, 1), true, nullptr, S, false, h->s);
+    k_grad(h->g, L, g, b0, false, S, h->kpart.as<double>(), Gl[0], h->s);
+    k_layer(h->g, L, g, gt, k_weights(h, 0), true, nullptr, S, false, h->s);
+    k_zero_odd(gt, N, S, h->s);  // through E_e R_e
+    // ... and through K^dag (layers 1^dag, 2^dag, 3^dag)
+    k_grad(h->g, L, gt, a2, true, S, h->kpart.as<double>(), Gl[0], h->s);
+    k_layer(h->g, L, gt, g, k_weights(h, 0), false, nullptr, S, false, h->s);
+    k_grad(h->g, L, g, a1, true, S, h->kpart.as<double>(), Gl[1], h->s);
+    k_layer(h->g, L, g, gt, k_weights(h, 1), false, nullptr, S, false, h->s);
+    k_grad(h->g, L, gt, a0, true, S, h->kpart.as<double>(), Gl[2], h->s);
+    return loss;
+}
+
+void k_alloc_weights(seedcg_s* h) {
+    h->kWm.ensure(K_NREAL * sizeof(double));
+    h->kW32.ensure(K_NREAL * sizeof(float));
+    h->kG.ensure(K_NREAL * sizeof(double));
+    h->kAm.ensure(K_NREAL * sizeof(double));
+    h->kAv.ensure(K_NREAL * sizeof(double));
+}
+
+// host weights (FP64 complex, [layer][d][4][4]) -> device FP64 master and FP32 copy
+void k_set_weights(seedcg_s* h, const double* w) {
+    k_alloc_weights(h);
+    std::vector<float> w32(w, w + K_NREAL);
+    HIPCHK(hipMemcpyAsync(h->kWm.p, w, K_NREAL * sizeof(double), hipMemcpyHostToDevice, h->s));
+    HIPCHK(hipMemcpyAsync(h->kW32.p, w32.data(), K_NREAL * sizeof(float), hipMemcpyHostToDevice, h->s));
+    HIPCHK(hipStreamSynchronize(h->s));
+}
+
+// Trains K on the Ritz vectors of T (lowest n_ritz) and n_lanczos stored basis vectors, with
+// targets y = M u (inner precision), by `steps` Adam steps of the loss
+// mean_s |K K^dag y_s - u_s|^2 / |u_s|^2 from K = 1.
+void train_precond_impl(seedcg_s* h, int steps, int n_ritz, int n_lanczos, double lr) {
+    if (!h->have_seed || !h->basis.p) throw StateError{"train_precond: needs the basis of a seed solve"};
+    if (steps < 0 || n_ritz < 0 || n_lanczos < 0 || n_ritz > 16 || n_ritz + n_lanczos > 32 || n_ritz + n_lanczos < 1)
+        throw ArgError{"train_precond: 0 <= n_ritz <= 16, 1 <= n_ritz + n_lanczos <= 32, steps >= 0"};
+    const double t0 = now_s();
+    const int64_t N = h->N;
+    const int m = h->m_used;
+    if (m < 2) throw StateError{"train_precond: the seed solve took fewer than 2 steps"};
+    const LzArrays A = h->arr();
+    std::vector<double> alpha(m), beta(m + 1);
+    HIPCHK(hipMemcpyAsync(alpha.data(), A.alpha + 1, m * sizeof(double), hipMemcpyDeviceToHost, h->s));
+    HIPCHK(hipMemcpyAsync(beta.data(), A.beta, (m + 1) * sizeof(double), hipMemcpyDeviceToHost, h->s));
+    HIPCHK(hipStreamSynchronize(h->s));
+    std::vector<double> off(beta.begin() + 1, beta.begin() + m), lam, Sv;
+    ritz_lowest(alpha, off, std::min(n_ritz, m), lam, Sv);
+    const int nr = (int)lam.size();
+    const int nl = std::min(n_lanczos, m);
+    const int S = nr + nl;
+    h->k_ritz = nr;
+    h->k_train_vecs = S;
+    h->kU.ensure((int64_t)S * N * 8);
+    h->kY.ensure((int64_t)S * N * 8);
+    if (nr > 0) {
+        h->kS.ensure(Sv.size() * sizeof(double));
+        HIPCHK(hipMemcpyAsync(h->kS.p, Sv.data(), Sv.size() * sizeof(double), hipMemcpyHostToDevice, h->s));
+        k_combine(h->lo, h->basis.p, m, h->kS.as<double>(), nr, h->kU.p, N, h->s);
+    }
+    for (int j = 0; j < nl; j++) {  // basis vectors (normalised CG residuals), evenly spread over 1..m
+        const int i = nl == 1 ? 1 : 1 + (int)((int64_t)j * (m - 1) / (nl - 1));
+        convert(h->lo, true, (const char*)h->basis.p + (int64_t)(i - 1) * h->vec_bytes(h->lo), (char*)h->kU.p + (int64_t)(nr + j) * N * 8,
+                N, h->s);
+    }
+    // y = M u with the inner operator
+    if (h->lo) {
+        apply_M_int(h, true, h->kU.p, h->kY.p, S, MOpts{});
+    } else {
+        DBuf u64, y64;
+        u64.ensure((int64_t)S * h->vec_bytes(false));
+        y64.ensure((int64_t)S * h->vec_bytes(false));
+        convert(true, false, h->kU.p, u64.p, S * N, h->s);
+        apply_M_int(h, false, u64.p, y64.p, S, MOpts{});
+        convert(false, true, y64.p, h->kY.p, S * N, h->s);
+        HIPCHK(hipStreamSynchronize(h->s));
+    }
+    const int64_t nbn = norm2_blocks(N);
+    h->kun2.ensure(S * sizeof(double));
+    h->klpart.ensure(std::max<int64_t>(nbn, k_residual_blocks(N)) * S * sizeof(double));
+    norm2_partials(true, h->kU.p, N, S, h->klpart.as<double>(), h->s);
+    sum_partials(h->klpart.as<double>(), nbn, S, h->kun2.as<double>(), false, h->s);
+    // weights: K = 1; Adam state cleared
+    std::vector<double> w0(K_NREAL, 0.0);
+    for (int l = 0; l < K_LAYERS; l++)
+        for (int a = 0; a < 4; a++) w0[(size_t)l * K_NW * 2 + 2 * (a * 4 + a)] = 1.0;
+    k_set_weights(h, w0.data());
+    HIPCHK(hipMemsetAsync(h->kG.p, 0, K_NREAL * sizeof(double), h->s));
+    HIPCHK(hipMemsetAsync(h->kAm.p, 0, K_NREAL * sizeof(double), h->s));
+    HIPCHK(hipMemsetAsync(h->kAv.p, 0, K_NREAL * sizeof(double), h->s));
+    for (int step = 0; step <= steps; step++) {
+        const bool last = step == steps;
+        const double loss = k_pass(h, S, !last, step == 0 || last);
+        if (step == 0) h->k_loss0 = loss;
+        if (last) {
+            h->k_loss1 = loss;
+            break;
+        }
+        k_adam(h->kWm.as<double>(), h->kW32.p, h->kG.as<double>(), h->kAm.as<double>(), h->kAv.as<double>(), step + 1, lr, K_NREAL,
+               h->s);
+        if ((step & 63) == 63) check_launch();
+    }
+    check_launch();
+    HIPCHK(hipStreamSynchronize(h->s));
+    h->kfield.release();
+    h->k_steps = steps;
+    h->k_ready = true;
+    h->k_t_train = now_s() - t0;
+}
+
+// ---------------------------------------------------------------------------------------------
 // plain CG on a batch (FP64, or FP32 inner iterations with FP64 reliable updates)
 // ---------------------------------------------------------------------------------------------
 void true_residual(seedcg_s* h, const std::vector<int>& vecs, void* R64, double* part) {
@@ -561,7 +814,39 @@ seedcg_status solve_rest_impl(seedcg_s* h, const double* B, double* X, int nrhs,
         c.done = (std::sqrt(c.rr) <= tol * c.bnorm) ? 1 : 0;
     }
     if (lo) convert(false, true, h->R64.p, h->Rv.p, nrhs * N, h->s);
-    convert(lo, lo, Rw, h->Pv.p, nrhs * N, h->s);  // p = r
+    // preconditioned CG with the learned P = K K^dag when it has been trained and is asked for
+    const bool pc = h->p.precond == 1 && h->k_ready;
+    if (pc) {
+        h->Zv.ensure(nrhs * h->vec_bytes(lo));
+        h->rzpart.ensure(nrhs * nb * sizeof(double));
+    }
+    // z = P r and rz = Re r^dag z for the vectors in `vecs`; returns rz per vector
+    auto precondition = [&](const std::vector<int>& vecs) {
+        std::vector<int32_t> vm(vecs.begin(), vecs.end());
+        DBuf dm;
+        dm.ensure(vm.size() * sizeof(int32_t));
+        HIPCHK(hipMemcpyAsync(dm.p, vm.data(), vm.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->s));
+        apply_P(h, lo, Rw, h->Zv.p, dm.as<int32_t>(), (int)vm.size(), nrhs);
+        dot_map(lo, Rw, h->Zv.p, N, dm.as<int32_t>(), (int)vm.size(), nullptr, h->rzpart.as<double>(), h->s);
+        h->respart.ensure(nrhs * sizeof(double));
+        sum_partials(h->rzpart.as<double>(), nb, nrhs, h->respart.as<double>(), false, h->s);
+        std::vector<double> rz(nrhs);
+        HIPCHK(hipMemcpyAsync(rz.data(), h->respart.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, h->s));
+        HIPCHK(hipStreamSynchronize(h->s));
+        return rz;
+    };
+    if (pc) {
+        std::vector<int> live;
+        for (int j = 0; j < nrhs; j++)
+            if (!cg[j].done) live.push_back(j);
+        if (!live.empty()) {
+            const std::vector<double> rz = precondition(live);
+            for (int j : live) cg[j].rz = rz[j];
+        }
+        convert(lo, lo, h->Zv.p, h->Pv.p, nrhs * N, h->s);  // p = z
+    } else {
+        convert(lo, lo, Rw, h->Pv.p, nrhs * N, h->s);  // p = r
+    }
     HIPCHK(hipMemcpyAsync(h->cgv.p, cg.data(), nrhs * sizeof(CgVec), hipMemcpyHostToDevice, h->s));
 
     const int max_iter = h->p.max_iter > 0 ? h->p.max_iter : 100000;
@@ -592,11 +877,19 @@ seedcg_status solve_rest_impl(seedcg_s* h, const double* B, double* X, int nrhs,
             o.vec_map = h->vmap.as<int32_t>();
             o.cg = h->cgv.as<CgVec>();
             apply_M_int(h, lo, h->Pv.p, h->Qv.p, nact, o);
-            cg_alpha(h->cgv.as<CgVec>(), h->cgpart.as<double>(), nsbl, h->vmap.as<int32_t>(), nact, h->s);
+            cg_alpha(h->cgv.as<CgVec>(), h->cgpart.as<double>(), nsbl, h->vmap.as<int32_t>(), nact, h->s, pc);
             cg_update(lo, false, h->cgv.as<CgVec>(), h->vmap.as<int32_t>(), nact, h->Xint.p, h->Pv.p, Rw, h->Qv.p,
                       h->rrpart.as<double>(), N, h->s);
-            cg_beta(h->cgv.as<CgVec>(), h->rrpart.as<double>(), nb, h->vmap.as<int32_t>(), nact, max_iter, h->s);
-            cg_p(lo, h->cgv.as<CgVec>(), h->vmap.as<int32_t>(), nact, h->Pv.p, Rw, N, false, h->s);
+            if (pc) {
+                apply_P(h, lo, Rw, h->Zv.p, h->vmap.as<int32_t>(), nact, nrhs);
+                dot_map(lo, Rw, h->Zv.p, N, h->vmap.as<int32_t>(), nact, h->cgv.as<CgVec>(), h->rzpart.as<double>(), h->s);
+                cg_beta_pc(h->cgv.as<CgVec>(), h->rrpart.as<double>(), h->rzpart.as<double>(), nb, h->vmap.as<int32_t>(), nact,
+                           max_iter, h->s);
+                cg_p(lo, h->cgv.as<CgVec>(), h->vmap.as<int32_t>(), nact, h->Pv.p, h->Zv.p, N, false, h->s);
+            } else {
+                cg_beta(h->cgv.as<CgVec>(), h->rrpart.as<double>(), nb, h->vmap.as<int32_t>(), nact, max_iter, h->s);
+                cg_p(lo, h->cgv.as<CgVec>(), h->vmap.as<int32_t>(), nact, h->Pv.p, Rw, N, false, h->s);
+            }
         }
         check_launch();
         HIPCHK(hipMemcpyAsync(cg.data(), h->cgv.p, nrhs * sizeof(CgVec), hipMemcpyDeviceToHost, h->s));
@@ -649,6 +942,7 @@ seedcg_status solve_rest_impl(seedcg_s* h, const double* B, double* X, int nrhs,
                 c.restarts += 1;
                 restart.push_back(j);
             }
+            if (pc && !c.frozen && !(is_rel[j] && rr >= c.rr_reliable)) restart.push_back(j);  // z = P r changed too
             c.rr_reliable = rr;
             it_rel[j] = c.iters;
             c.rr = rr;
@@ -659,13 +953,24 @@ seedcg_status solve_rest_impl(seedcg_s* h, const double* B, double* X, int nrhs,
                 if (!cg[j].done)
                     convert(false, true, (char*)h->R64.p + j * h->vec_bytes(false), (char*)h->Rv.p + j * h->vec_bytes(true), N, h->s);
         }
+        std::sort(restart.begin(), restart.end());
+        restart.erase(std::unique(restart.begin(), restart.end()), restart.end());
+        if (pc && !restart.empty()) {
+            // preconditioned restart from the new residual: z = P r, p = z, rz = r^dag z
+            HIPCHK(hipStreamSynchronize(h->s));
+            const std::vector<double> rz = precondition(restart);
+            for (int j : restart) {
+                cg[j].rz = rz[j];
+                cg[j].b = 0.0;
+            }
+        }
         HIPCHK(hipMemcpyAsync(h->cgv.p, cg.data(), nrhs * sizeof(CgVec), hipMemcpyHostToDevice, h->s));
         if (!restart.empty()) {
             std::vector<int32_t> rm(restart.begin(), restart.end());
             DBuf dm;
             dm.ensure(rm.size() * sizeof(int32_t));
             HIPCHK(hipMemcpyAsync(dm.p, rm.data(), rm.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->s));
-            cg_p(lo, h->cgv.as<CgVec>(), dm.as<int32_t>(), (int)rm.size(), h->Pv.p, Rw, N, false, h->s);
+            cg_p(lo, h->cgv.as<CgVec>(), dm.as<int32_t>(), (int)rm.size(), h->Pv.p, pc ? h->Zv.p : Rw, N, false, h->s);
             HIPCHK(hipStreamSynchronize(h->s));
         }
     }
@@ -963,6 +1268,95 @@ seedcg_status seedcg_get_timing(seedcg_t h, double* out) {
         out[2] = h->t_bytes;
         out[3] = h->t_flops;
         out[4] = (double)h->hop_count;
+        return SEEDCG_OK;
+    });
+}
+
+seedcg_status seedcg_train_precond(seedcg_t h, int32_t steps, int32_t n_ritz, int32_t n_lanczos, double lr, double* out) {
+    if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "train_precond: null handle");
+    return guarded(h, [&]() -> seedcg_status {
+        train_precond_impl(h, steps, n_ritz, n_lanczos, lr);
+        if (out) {
+            out[0] = h->k_loss0;
+            out[1] = h->k_loss1;
+            out[2] = h->k_t_train;
+            out[3] = h->k_ritz;
+            out[4] = h->k_train_vecs;
+        }
+        return SEEDCG_OK;
+    });
+}
+
+seedcg_status seedcg_use_precond(seedcg_t h, int32_t on) {
+    if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "use_precond: null handle");
+    return guarded(h, [&]() -> seedcg_status {
+        if (on && !h->k_ready) throw StateError{"use_precond: the preconditioner has no weights"};
+        h->p.precond = on ? 1 : 0;
+        return SEEDCG_OK;
+    });
+}
+
+seedcg_status seedcg_set_precond_weights(seedcg_t h, const double* w) {
+    if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "set_precond_weights: null handle");
+    return guarded(h, [&]() -> seedcg_status {
+        if (!w) throw ArgError{"set_precond_weights: null pointer"};
+        k_set_weights(h, w);
+        h->k_ready = true;
+        return SEEDCG_OK;
+    });
+}
+
+seedcg_status seedcg_get_precond_weights(seedcg_t h, double* w) {
+    if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "get_precond_weights: null handle");
+    return guarded(h, [&]() -> seedcg_status {
+        if (!w) throw ArgError{"get_precond_weights: null pointer"};
+        if (!h->k_ready) throw StateError{"get_precond_weights: no weights"};
+        HIPCHK(hipMemcpyAsync(w, h->kWm.p, K_NREAL * sizeof(double), hipMemcpyDeviceToHost, h->s));
+        HIPCHK(hipStreamSynchronize(h->s));
+        return SEEDCG_OK;
+    });
+}
+
+seedcg_status seedcg_apply_P(seedcg_t h, const double* x, double* y, int32_t nvec) {
+    if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "apply_P: null handle");
+    return guarded(h, [&]() -> seedcg_status {
+        if (!x || !y || nvec < 1) throw ArgError{"apply_P: null pointer or nvec < 1"};
+        if (!h->k_ready) throw StateError{"apply_P: the preconditioner has no weights"};
+        DBuf xi, yi;
+        xi.ensure(nvec * h->vec_bytes(false));
+        yi.ensure(nvec * h->vec_bytes(false));
+        pack_vec(false, x, xi.p, h->g.Vh, nvec, h->s);
+        apply_P(h, false, xi.p, yi.p, nullptr, nvec, nvec);
+        unpack_vec(false, yi.p, y, h->g.Vh, nvec, h->s);
+        check_launch();
+        HIPCHK(hipStreamSynchronize(h->s));
+        return SEEDCG_OK;
+    });
+}
+
+seedcg_status seedcg_precond_loss_grad(seedcg_t h, const double* U, const double* Y, int32_t S, double* loss, double* grad) {
+    if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "precond_loss_grad: null handle");
+    return guarded(h, [&]() -> seedcg_status {
+        if (!U || !Y || S < 1 || S > 32) throw ArgError{"precond_loss_grad: null pointer or S not in 1..32"};
+        if (!h->k_ready) throw StateError{"precond_loss_grad: the preconditioner has no weights"};
+        const int64_t N = h->N;
+        h->kU.ensure((int64_t)S * N * 8);
+        h->kY.ensure((int64_t)S * N * 8);
+        pack_vec(true, U, h->kU.p, h->g.Vh, S, h->s);
+        pack_vec(true, Y, h->kY.p, h->g.Vh, S, h->s);
+        const int64_t nbn = norm2_blocks(N);
+        h->kun2.ensure(S * sizeof(double));
+        h->klpart.ensure(std::max<int64_t>(nbn, k_residual_blocks(N)) * S * sizeof(double));
+        norm2_partials(true, h->kU.p, N, S, h->klpart.as<double>(), h->s);
+        sum_partials(h->klpart.as<double>(), nbn, S, h->kun2.as<double>(), false, h->s);
+        HIPCHK(hipMemsetAsync(h->kG.p, 0, K_NREAL * sizeof(double), h->s));
+        const double l = k_pass(h, S, grad != nullptr, true);
+        if (loss) *loss = l;
+        if (grad) {
+            HIPCHK(hipMemcpyAsync(grad, h->kG.p, K_NREAL * sizeof(double), hipMemcpyDeviceToHost, h->s));
+            HIPCHK(hipMemsetAsync(h->kG.p, 0, K_NREAL * sizeof(double), h->s));
+        }
+        HIPCHK(hipStreamSynchronize(h->s));
         return SEEDCG_OK;
     });
 }

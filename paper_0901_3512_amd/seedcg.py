@@ -66,6 +66,12 @@ def load_library():
         "seedcg_get_basis_vector": (i32, [H, i32, P]),
         "seedcg_project": (i32, [H, P, i32, P, i32, i64, P]),
         "seedcg_update": (i32, [H, P, i32, P, P, i32, i64]),
+        "seedcg_train_precond": (i32, [H, i32, i32, i32, dbl, ctypes.POINTER(dbl)]),
+        "seedcg_use_precond": (i32, [H, i32]),
+        "seedcg_set_precond_weights": (i32, [H, ctypes.POINTER(dbl)]),
+        "seedcg_get_precond_weights": (i32, [H, ctypes.POINTER(dbl)]),
+        "seedcg_apply_P": (i32, [H, P, P, i32]),
+        "seedcg_precond_loss_grad": (i32, [H, P, P, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]),
         "seedcg_set_timing": (i32, [H, i32, i32]),
         "seedcg_get_timing": (i32, [H, ctypes.POINTER(dbl)]),
         "seedcg_release_basis": (i32, [H]),
@@ -84,8 +90,9 @@ def exported_symbols():
     """Names of the C ABI entry points this binding expects."""
     return ["seedcg_default_params", "seedcg_create", "seedcg_apply_M", "seedcg_apply_M_inner", "seedcg_apply_A", "seedcg_solve_seed",
             "seedcg_solve_rest", "seedcg_get_tridiag", "seedcg_get_basis_vector", "seedcg_project",
-            "seedcg_update", "seedcg_set_timing", "seedcg_get_timing", "seedcg_release_basis", "seedcg_destroy",
-            "seedcg_last_error"]
+            "seedcg_update", "seedcg_train_precond", "seedcg_use_precond", "seedcg_set_precond_weights",
+            "seedcg_get_precond_weights", "seedcg_apply_P", "seedcg_precond_loss_grad", "seedcg_set_timing",
+            "seedcg_get_timing", "seedcg_release_basis", "seedcg_destroy", "seedcg_last_error"]
 
 
 def _check_vec(t, Vh, name):
@@ -242,6 +249,42 @@ class SeedCG:
         self._rc(self._lib.seedcg_update(self._h, W.data_ptr(), W.shape[0], E.data_ptr(), X.data_ptr(),
                                          X.shape[0], W.shape[1]))
         return X
+
+    # -- learned preconditioner P = K K^dag -------------------------------------------------------
+    def train_precond(self, steps=2000, n_ritz=8, n_lanczos=8, lr=1e-3):
+        out = (ctypes.c_double * 5)()
+        self._rc(self._lib.seedcg_train_precond(self._h, int(steps), int(n_ritz), int(n_lanczos), float(lr), out))
+        return dict(loss0=out[0], loss1=out[1], t_train_s=out[2], n_ritz=int(out[3]), n_train=int(out[4]))
+
+    def use_precond(self, on=True):
+        self._rc(self._lib.seedcg_use_precond(self._h, int(bool(on))))
+
+    def set_precond_weights(self, W):
+        import numpy as np
+        w = np.ascontiguousarray(np.asarray(W, dtype=np.complex128).reshape(3, 9, 4, 4))
+        self._rc(self._lib.seedcg_set_precond_weights(self._h, w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+
+    def get_precond_weights(self):
+        import numpy as np
+        w = np.empty((3, 9, 4, 4), dtype=np.complex128)
+        self._rc(self._lib.seedcg_get_precond_weights(self._h, w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return w
+
+    def apply_P(self, x):
+        x = _check_vec(x, self.Vh, "x")
+        y = torch.empty_like(x)
+        self._rc(self._lib.seedcg_apply_P(self._h, x.data_ptr(), y.data_ptr(), x.shape[0]))
+        return y
+
+    def precond_loss_grad(self, U, Y):
+        import numpy as np
+        U = _check_vec(U, self.Vh, "U")
+        Y = _check_vec(Y, self.Vh, "Y")
+        loss = ctypes.c_double()
+        g = np.empty((3, 9, 4, 4), dtype=np.complex128)
+        self._rc(self._lib.seedcg_precond_loss_grad(self._h, U.data_ptr(), Y.data_ptr(), U.shape[0], ctypes.byref(loss),
+                                                    g.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return loss.value, g
 
     def set_timing(self, sample_every, max_samples=4096):
         self._rc(self._lib.seedcg_set_timing(self._h, int(sample_every), int(max_samples)))

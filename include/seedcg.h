@@ -160,7 +160,9 @@ seedcg_status seedcg_get_timing(seedcg_t h, double* out);
 /* Trains K by `steps` Adam steps (learning rate lr, betas 0.9 / 0.999, eps 1e-8) from K = 1 on
    the loss mean_s |K K^dag y_s - u_s|^2 / |u_s|^2 over u_s = the n_ritz lowest Ritz vectors of T
    (V s, T s = theta s, from the last solve_seed) and n_lanczos stored basis vectors, y_s = M u_s.
-   out (HOST, may be NULL): initial loss, final loss, seconds, Ritz vectors used, training vectors.
+   out (HOST, 6 doubles, may be NULL): initial loss, final loss, seconds, Ritz vectors used,
+   training vectors, accepted (1 if the final loss is at most half the initial one; a K that is not
+   accepted is not used by solve_rest, which then runs plain CG: the fallback).
    Needs the basis of the last solve_seed (SEEDCG_ERR_STATE otherwise). */
 seedcg_status seedcg_train_precond(seedcg_t h, int32_t steps, int32_t n_ritz, int32_t n_lanczos, double lr, double* out);
 

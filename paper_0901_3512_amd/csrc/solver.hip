@@ -115,6 +115,7 @@ struct seedcg_s {
     DBuf cgv, vmap, Pv, Rv, Qv, R64, cgpart, rrpart, respart, norms;
     // learned preconditioner P = K K^dag (FP32 weights, FP64 Adam master copy)
     bool k_ready = false;
+    bool k_accepted = false;   // the trained K passed the acceptance test (loss at most halved)
     DBuf kW32, kWm, kG, kAm, kAv, kpart, klinks32, kU, kY, kun2, klpart, kS, kfield, pfa, pfb, Zv, rzpart;
     int k_steps = 0, k_train_vecs = 0, k_ritz = 0;
     double k_loss0 = 0.0, k_loss1 = 0.0, k_t_train = 0.0;
@@ -746,6 +747,9 @@ void train_precond_impl(seedcg_s* h, int steps, int n_ritz, int n_lanczos, doubl
     h->kfield.release();
     h->k_steps = steps;
     h->k_ready = true;
+    // acceptance: keep K only if training at least halved the loss; otherwise solve_rest falls back
+    // to plain CG even when asked to precondition
+    h->k_accepted = h->k_loss1 <= 0.5 * h->k_loss0;
     h->k_t_train = now_s() - t0;
 }
 
@@ -815,7 +819,7 @@ seedcg_status solve_rest_impl(seedcg_s* h, const double* B, double* X, int nrhs,
     }
     if (lo) convert(false, true, h->R64.p, h->Rv.p, nrhs * N, h->s);
     // preconditioned CG with the learned P = K K^dag when it has been trained and is asked for
-    const bool pc = h->p.precond == 1 && h->k_ready;
+    const bool pc = h->p.precond == 1 && h->k_ready && h->k_accepted;
     if (pc) {
         h->Zv.ensure(nrhs * h->vec_bytes(lo));
         h->rzpart.ensure(nrhs * nb * sizeof(double));
@@ -1273,6 +1277,7 @@ seedcg_status seedcg_get_timing(seedcg_t h, double* out) {
 }
 
 seedcg_status seedcg_train_precond(seedcg_t h, int32_t steps, int32_t n_ritz, int32_t n_lanczos, double lr, double* out) {
+    // out[0..5]: initial loss, final loss, seconds, Ritz vectors, training vectors, accepted
     if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "train_precond: null handle");
     return guarded(h, [&]() -> seedcg_status {
         train_precond_impl(h, steps, n_ritz, n_lanczos, lr);
@@ -1282,6 +1287,7 @@ seedcg_status seedcg_train_precond(seedcg_t h, int32_t steps, int32_t n_ritz, in
             out[2] = h->k_t_train;
             out[3] = h->k_ritz;
             out[4] = h->k_train_vecs;
+            out[5] = h->k_accepted ? 1.0 : 0.0;
         }
         return SEEDCG_OK;
     });
@@ -1302,6 +1308,7 @@ seedcg_status seedcg_set_precond_weights(seedcg_t h, const double* w) {
         if (!w) throw ArgError{"set_precond_weights: null pointer"};
         k_set_weights(h, w);
         h->k_ready = true;
+        h->k_accepted = true;
         return SEEDCG_OK;
     });
 }

@@ -252,9 +252,10 @@ class SeedCG:
 
     # -- learned preconditioner P = K K^dag -------------------------------------------------------
     def train_precond(self, steps=2000, n_ritz=8, n_lanczos=8, lr=1e-3):
-        out = (ctypes.c_double * 5)()
+        out = (ctypes.c_double * 6)()
         self._rc(self._lib.seedcg_train_precond(self._h, int(steps), int(n_ritz), int(n_lanczos), float(lr), out))
-        return dict(loss0=out[0], loss1=out[1], t_train_s=out[2], n_ritz=int(out[3]), n_train=int(out[4]))
+        return dict(loss0=out[0], loss1=out[1], t_train_s=out[2], n_ritz=int(out[3]), n_train=int(out[4]),
+                    accepted=bool(out[5]))
 
     def use_precond(self, on=True):
         self._rc(self._lib.seedcg_use_precond(self._h, int(bool(on))))

@@ -37,6 +37,7 @@ extern "C" {
 #endif
 
 typedef struct seedcg_s* seedcg_t;
+typedef struct seedcg_batch_s* seedcg_batch_t;
 
 typedef enum {
     SEEDCG_OK = 0,
@@ -68,6 +69,9 @@ typedef struct {
     int32_t seed_block;       /* seeding GEMM block b (1..32); 0 = 32                             */
     int32_t max_iter;         /* CG iterations per right-hand side in solve_rest                 */
     int32_t precond;          /* 0: none                                                         */
+    int32_t autotune;         /* 1: choose the stencil launch shapes (lanes per site, vectors per
+                                 workgroup) by timing the candidates once per lattice shape;
+                                 0: the fixed default (two lanes per site, one vector each)     */
     void* stream;             /* hipStream_t; NULL = the null stream                             */
 } seedcg_params;
 
@@ -86,7 +90,7 @@ typedef struct {
 } seedcg_report;
 
 /* Fills *p with the defaults: t_bc = -1, FP64, m_max = 0, reorth_k = 10, past_factor = 1.5,
-   tol = 1e-10, reliable_every = 50, seed_block = 32, max_iter = 100000, precond = 0. */
+   tol = 1e-10, reliable_every = 50, seed_block = 32, max_iter = 100000, precond = 0, autotune = 1. */
 void seedcg_default_params(seedcg_params* p);
 
 /* Creates a solver for one gauge configuration.  links: device, 4*V*9 complex (layout above),
@@ -179,6 +183,38 @@ seedcg_status seedcg_apply_P(seedcg_t h, const double* x, double* y, int32_t nve
 /* The training loss for pairs (U, Y) of S even-site vectors (device, canonical layout, 1 <= S <= 32)
    at the current weights, and its Wirtinger gradient dL/d(conj w) (HOST, 432 complex, may be NULL). */
 seedcg_status seedcg_precond_loss_grad(seedcg_t h, const double* U, const double* Y, int32_t S, double* loss, double* grad);
+
+/* ---- batches of configurations (an addition to the paper's method) -------------------------
+   Many independent gauge configurations, possibly of different lattice shapes, each with nrhs
+   right-hand sides, solved together: per configuration, Algorithm 1 on its first right-hand side
+   with Galerkin seeding of the others, then plain CG on all of them, exactly as solve_seed
+   followed by solve_rest on a handle of its own.  Configurations of one shape share every launch
+   (one kernel covers all of them); shapes run concurrently on streams of their own. */
+
+/* dims: HOST [ncfg][4]; kappa: HOST [ncfg]; links: HOST array of ncfg device pointers (each
+   4*V*9 complex, layout above).  p supplies everything else (its dims, kappa and precond are
+   ignored; precond must be 0).  Memory for every Krylov basis is reserved here: m_max vectors per
+   configuration, or (m_max = 0) the largest common capacity that fits in 90% of the free HBM
+   less 4 GiB.  nrhs: right-hand sides per configuration of every solve (1..25). */
+seedcg_status seedcg_create_batch(int32_t ncfg, const int32_t* dims, const double* kappa, const double* const* links,
+                                  int32_t nrhs, const seedcg_params* p, seedcg_batch_t* out);
+
+/* B, X: HOST arrays of ncfg device pointers, each nrhs even-site vectors of that configuration
+   (X holds the starting guesses and receives the solutions).  rep: HOST array of ncfg reports
+   (may be NULL); its iters count Lanczos steps plus CG iterations, its matvecs every application
+   of M of both phases.  Returns when every configuration is done; SEEDCG_ERR_NOCONV if some
+   right-hand side reached max_iter. */
+seedcg_status seedcg_solve_batch(seedcg_batch_t b, const double* const* B, double* const* X, seedcg_report* rep);
+
+/* HOST outputs, each may be NULL: the number of shape classes, class_of[ncfg], m_cap[nclass] and
+   tune[4*nclass] = the inner stencil's lanes per site and vectors per workgroup for one vector and
+   for several vectors. */
+seedcg_status seedcg_batch_info(seedcg_batch_t b, int32_t* nclass, int32_t* class_of, int32_t* m_cap, double* tune);
+
+void seedcg_destroy_batch(seedcg_batch_t b);
+
+/* Text of the last failure of the batch (or of the last failed create_batch when b is NULL). */
+const char* seedcg_batch_last_error(seedcg_batch_t b);
 
 /* Frees the Krylov basis (the paper allocates it for the first right-hand side only). */
 seedcg_status seedcg_release_basis(seedcg_t h);

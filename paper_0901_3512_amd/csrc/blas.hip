@@ -3,6 +3,8 @@
 //
 // Every reduction is deterministic: a fixed shuffle tree per block, then the block
 // partials are summed in index order by one workgroup.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace scg {
@@ -58,7 +60,10 @@ void pack_links(Prec prec, const Geom& g, const double* U, void* out, hipStream_
 
 // canonical [n][Vh][12] (FP64)  <->  internal [n][12][Vh] (T)
 template <typename T>
-__global__ void pack_vec_kernel(const cx<double>* __restrict__ in, cx<T>* __restrict__ out, int64_t Vh, int64_t total) {
+__global__ void pack_vec_kernel(const cx<double>* __restrict__ in, cx<T>* __restrict__ out, int64_t Vh, int64_t total,
+                                const double* const* tab, int64_t cs) {
+    if (tab) in = (const cx<double>*)tab[blockIdx.z];
+    out = zoff(out, cs);
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (vec, c, h), h fastest
     if (k >= total) return;
     const int64_t h = k % Vh;
@@ -68,7 +73,10 @@ __global__ void pack_vec_kernel(const cx<double>* __restrict__ in, cx<T>* __rest
     out[k] = mk<T>((T)a.re, (T)a.im);
 }
 template <typename T>
-__global__ void unpack_vec_kernel(const cx<T>* __restrict__ in, cx<double>* __restrict__ out, int64_t Vh, int64_t total) {
+__global__ void unpack_vec_kernel(const cx<T>* __restrict__ in, cx<double>* __restrict__ out, int64_t Vh, int64_t total,
+                                  double* const* tab, int64_t cs) {
+    if (tab) out = (cx<double>*)tab[blockIdx.z];
+    in = zoff(in, cs);
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= total) return;
     const int64_t h = k % Vh;
@@ -78,47 +86,107 @@ __global__ void unpack_vec_kernel(const cx<T>* __restrict__ in, cx<double>* __re
     out[(v * Vh + h) * 12 + c] = mk<double>((double)a.re, (double)a.im);
 }
 
-void pack_vec(bool fp32, const double* in, void* out, int64_t Vh, int nvec, hipStream_t s) {
+void pack_vec(bool fp32, const double* in, void* out, int64_t Vh, int nvec, const Launch& L, const double* const* tab) {
     const int64_t total = 12 * Vh * nvec;
-    const dim3 grid((unsigned)((total + 255) / 256));
+    const dim3 grid((unsigned)((total + 255) / 256), 1, L.nz);
     if (fp32)
-        hipLaunchKernelGGL(pack_vec_kernel<float>, grid, dim3(256), 0, s, (const cx<double>*)in, (cx<float>*)out, Vh, total);
+        hipLaunchKernelGGL(pack_vec_kernel<float>, grid, dim3(256), 0, L.s, (const cx<double>*)in, (cx<float>*)out, Vh, total, tab, L.cs);
     else
-        hipLaunchKernelGGL(pack_vec_kernel<double>, grid, dim3(256), 0, s, (const cx<double>*)in, (cx<double>*)out, Vh, total);
+        hipLaunchKernelGGL(pack_vec_kernel<double>, grid, dim3(256), 0, L.s, (const cx<double>*)in, (cx<double>*)out, Vh, total, tab, L.cs);
 }
-void unpack_vec(bool fp32, const void* in, double* out, int64_t Vh, int nvec, hipStream_t s) {
+void unpack_vec(bool fp32, const void* in, double* out, int64_t Vh, int nvec, const Launch& L, double* const* tab) {
     const int64_t total = 12 * Vh * nvec;
-    const dim3 grid((unsigned)((total + 255) / 256));
+    const dim3 grid((unsigned)((total + 255) / 256), 1, L.nz);
     if (fp32)
-        hipLaunchKernelGGL(unpack_vec_kernel<float>, grid, dim3(256), 0, s, (const cx<float>*)in, (cx<double>*)out, Vh, total);
+        hipLaunchKernelGGL(unpack_vec_kernel<float>, grid, dim3(256), 0, L.s, (const cx<float>*)in, (cx<double>*)out, Vh, total, tab, L.cs);
     else
-        hipLaunchKernelGGL(unpack_vec_kernel<double>, grid, dim3(256), 0, s, (const cx<double>*)in, (cx<double>*)out, Vh, total);
+        hipLaunchKernelGGL(unpack_vec_kernel<double>, grid, dim3(256), 0, L.s, (const cx<double>*)in, (cx<double>*)out, Vh, total, tab, L.cs);
 }
 
 // ---------------------------------------------------------------------------------------------
 // small vector helpers
 // ---------------------------------------------------------------------------------------------
 template <typename TA, typename TB>
-__global__ void convert_kernel(const cx<TA>* __restrict__ a, cx<TB>* __restrict__ b, int64_t n) {
+__global__ void convert_kernel(const cx<TA>* __restrict__ a, cx<TB>* __restrict__ b, int64_t n, int64_t cs) {
+    a = zoff(a, cs);
+    b = zoff(b, cs);
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < n) b[k] = mk<TB>((TB)a[k].re, (TB)a[k].im);
 }
-void convert(bool from32, bool to32, const void* a, void* b, int64_t n, hipStream_t s) {
-    const dim3 grid((unsigned)((n + 255) / 256));
+void convert(bool from32, bool to32, const void* a, void* b, int64_t n, const Launch& L) {
+    const hipStream_t s = L.s;
+    const dim3 grid((unsigned)((n + 255) / 256), 1, L.nz);
     if (!from32 && to32)
-        hipLaunchKernelGGL((convert_kernel<double, float>), grid, dim3(256), 0, s, (const cx<double>*)a, (cx<float>*)b, n);
+        hipLaunchKernelGGL((convert_kernel<double, float>), grid, dim3(256), 0, s, (const cx<double>*)a, (cx<float>*)b, n, L.cs);
     else if (from32 && !to32)
-        hipLaunchKernelGGL((convert_kernel<float, double>), grid, dim3(256), 0, s, (const cx<float>*)a, (cx<double>*)b, n);
+        hipLaunchKernelGGL((convert_kernel<float, double>), grid, dim3(256), 0, s, (const cx<float>*)a, (cx<double>*)b, n, L.cs);
     else if (from32)
-        hipLaunchKernelGGL((convert_kernel<float, float>), grid, dim3(256), 0, s, (const cx<float>*)a, (cx<float>*)b, n);
+        hipLaunchKernelGGL((convert_kernel<float, float>), grid, dim3(256), 0, s, (const cx<float>*)a, (cx<float>*)b, n, L.cs);
     else
-        hipLaunchKernelGGL((convert_kernel<double, double>), grid, dim3(256), 0, s, (const cx<double>*)a, (cx<double>*)b, n);
+        hipLaunchKernelGGL((convert_kernel<double, double>), grid, dim3(256), 0, s, (const cx<double>*)a, (cx<double>*)b, n, L.cs);
+}
+
+// b_v = a_v (with precision change) for the vectors v of vec_map (-1: empty slot)
+template <typename TA, typename TB>
+__global__ void convert_map_kernel(const cx<TA>* __restrict__ a, cx<TB>* __restrict__ b, int64_t n, const int32_t* vec_map,
+                                   int64_t cs) {
+    a = zoff(a, cs);
+    b = zoff(b, cs);
+    vec_map = zoff(vec_map, cs);
+    const int vec = vec_map[blockIdx.y];
+    if (vec < 0) return;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const cx<TA> v = a[(int64_t)vec * n + k];
+    b[(int64_t)vec * n + k] = mk<TB>((TB)v.re, (TB)v.im);
+}
+void convert_map(bool from32, bool to32, const void* a, void* b, int64_t n, const int32_t* vec_map, int nact, const Launch& L) {
+    const dim3 grid((unsigned)((n + 255) / 256), nact, L.nz);
+    if (!from32 && to32)
+        hipLaunchKernelGGL((convert_map_kernel<double, float>), grid, dim3(256), 0, L.s, (const cx<double>*)a, (cx<float>*)b, n,
+                           vec_map, L.cs);
+    else if (!from32 && !to32)
+        hipLaunchKernelGGL((convert_map_kernel<double, double>), grid, dim3(256), 0, L.s, (const cx<double>*)a, (cx<double>*)b, n,
+                           vec_map, L.cs);
+    else if (from32 && to32)
+        hipLaunchKernelGGL((convert_map_kernel<float, float>), grid, dim3(256), 0, L.s, (const cx<float>*)a, (cx<float>*)b, n,
+                           vec_map, L.cs);
+    else
+        hipLaunchKernelGGL((convert_map_kernel<float, double>), grid, dim3(256), 0, L.s, (const cx<float>*)a, (cx<double>*)b, n,
+                           vec_map, L.cs);
+}
+
+// Byte copies between per-configuration buffers and compact staging arrays (4-byte words):
+// configuration z copies src + z*src_cs to dst + z*dst_cs.  Kernels rather than memcpy/memset
+// calls, so that the same code is safe inside captured graphs.
+__global__ void cfg_copy_kernel(const uint32_t* src, int64_t src_cs, uint32_t* dst, int64_t dst_cs, int64_t nwords) {
+    src = (const uint32_t*)((const char*)src + (int64_t)blockIdx.z * src_cs);
+    dst = (uint32_t*)((char*)dst + (int64_t)blockIdx.z * dst_cs);
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nwords; k += (int64_t)gridDim.x * blockDim.x)
+        dst[k] = src[k];
+}
+void cfg_copy(const void* src, int64_t src_cs, void* dst, int64_t dst_cs, int64_t bytes, const Launch& L) {
+    const int64_t nw = bytes / 4;
+    const unsigned nb = (unsigned)std::min<int64_t>((nw + 255) / 256, 4096);
+    hipLaunchKernelGGL(cfg_copy_kernel, dim3(std::max(nb, 1u), 1, L.nz), dim3(256), 0, L.s, (const uint32_t*)src, src_cs,
+                       (uint32_t*)dst, dst_cs, nw);
+}
+__global__ void cfg_zero_kernel(uint32_t* dst, int64_t cs, int64_t nwords) {
+    dst = (uint32_t*)((char*)dst + (int64_t)blockIdx.z * cs);
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nwords; k += (int64_t)gridDim.x * blockDim.x) dst[k] = 0u;
+}
+void cfg_zero(void* dst, int64_t bytes, const Launch& L) {
+    const int64_t nw = bytes / 4;
+    const unsigned nb = (unsigned)std::min<int64_t>((nw + 255) / 256, 4096);
+    hipLaunchKernelGGL(cfg_zero_kernel, dim3(std::max(nb, 1u), 1, L.nz), dim3(256), 0, L.s, (uint32_t*)dst, L.cs, nw);
 }
 
 // partial sums of |a|^2 per block, for vector v of a batch (grid: blocks x nvec)
 template <typename T>
-__global__ void norm2_kernel(const cx<T>* __restrict__ a, int64_t n, double* part, int64_t nb) {
+__global__ void norm2_kernel(const cx<T>* __restrict__ a, int64_t n, double* part, int64_t nb, int64_t cs) {
     __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    a = zoff(a, cs);
+    part = zoff(part, cs);
     const int64_t v = blockIdx.y;
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double s = 0.0;
@@ -129,23 +197,26 @@ __global__ void norm2_kernel(const cx<T>* __restrict__ a, int64_t n, double* par
     s = block_sum(s, lds);
     if (threadIdx.x == 0) part[v * nb + blockIdx.x] = s;
 }
-void norm2_partials(bool fp32, const void* a, int64_t n, int nvec, double* part, hipStream_t st) {
+void norm2_partials(bool fp32, const void* a, int64_t n, int nvec, double* part, const Launch& L) {
     const int64_t nb = (n + SCG_BLOCK - 1) / SCG_BLOCK;
+    const dim3 grid((unsigned)nb, nvec, L.nz);
     if (fp32)
-        hipLaunchKernelGGL(norm2_kernel<float>, dim3((unsigned)nb, nvec), dim3(SCG_BLOCK), 0, st, (const cx<float>*)a, n, part, nb);
+        hipLaunchKernelGGL(norm2_kernel<float>, grid, dim3(SCG_BLOCK), 0, L.s, (const cx<float>*)a, n, part, nb, L.cs);
     else
-        hipLaunchKernelGGL(norm2_kernel<double>, dim3((unsigned)nb, nvec), dim3(SCG_BLOCK), 0, st, (const cx<double>*)a, n, part, nb);
+        hipLaunchKernelGGL(norm2_kernel<double>, grid, dim3(SCG_BLOCK), 0, L.s, (const cx<double>*)a, n, part, nb, L.cs);
 }
 int64_t norm2_blocks(int64_t n) { return (n + SCG_BLOCK - 1) / SCG_BLOCK; }
 
 // out[v] = sum_k part[v * nb + k] (one workgroup per v)
-__global__ void sum_partials_kernel(const double* part, int64_t nb, double* out, int sqrt_out) {
+__global__ void sum_partials_kernel(const double* part, int64_t nb, double* out, int sqrt_out, int64_t cs) {
     __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    part = zoff(part, cs);
+    out = zoff(out, cs);
     const double s = block_sum_array(part + (int64_t)blockIdx.x * nb, nb, lds);
     if (threadIdx.x == 0) out[blockIdx.x] = sqrt_out ? sqrt(s) : s;
 }
-void sum_partials(const double* part, int64_t nb, int nvec, double* out, bool sqrt_out, hipStream_t s) {
-    hipLaunchKernelGGL(sum_partials_kernel, dim3(nvec), dim3(SCG_BLOCK), 0, s, part, nb, out, (int)sqrt_out);
+void sum_partials(const double* part, int64_t nb, int nvec, double* out, bool sqrt_out, const Launch& L) {
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(nvec, 1, L.nz), dim3(SCG_BLOCK), 0, L.s, part, nb, out, (int)sqrt_out, L.cs);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -153,8 +224,12 @@ void sum_partials(const double* part, int64_t nb, int nvec, double* out, bool sq
 // ---------------------------------------------------------------------------------------------
 // Start: beta_0 = ||r_0^1|| (from partials), v_1 = r_0^1 / beta_0, bnorm1 from its partials.
 template <typename T>
-__global__ void lz_start_kernel(LzState* st, const double* r2part, int64_t nb, const double* b2part, double* beta) {
+__global__ void lz_start_kernel(LzState* st, const double* r2part, int64_t nb, const double* b2part, double* beta, int64_t cs) {
     __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    st = zoff(st, cs);
+    r2part = zoff(r2part, cs);
+    b2part = zoff(b2part, cs);
+    beta = zoff(beta, cs);
     const double r2 = block_sum_array(r2part, nb, lds);
     __syncthreads();
     const double b2 = block_sum_array(b2part, nb, lds);
@@ -168,12 +243,15 @@ __global__ void lz_start_kernel(LzState* st, const double* r2part, int64_t nb, c
         }
     }
 }
-void lz_start(LzState* st, const double* r2part, int64_t nb, const double* b2part, double* beta, hipStream_t s) {
-    hipLaunchKernelGGL(lz_start_kernel<double>, dim3(1), dim3(SCG_BLOCK), 0, s, st, r2part, nb, b2part, beta);
+void lz_start(LzState* st, const double* r2part, int64_t nb, const double* b2part, double* beta, const Launch& L) {
+    hipLaunchKernelGGL(lz_start_kernel<double>, dim3(1, 1, L.nz), dim3(SCG_BLOCK), 0, L.s, st, r2part, nb, b2part, beta, L.cs);
 }
 
 template <typename T>
-__global__ void scale_from_kernel(const LzState* st, const cx<T>* __restrict__ r, cx<T>* __restrict__ v, int64_t n) {
+__global__ void scale_from_kernel(const LzState* st, const cx<T>* __restrict__ r, cx<T>* __restrict__ v, int64_t n, int64_t cs) {
+    st = zoff(st, cs);
+    r = zoff(r, cs);
+    v = zoff(v, cs);
     if (st->done) return;
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
@@ -181,17 +259,20 @@ __global__ void scale_from_kernel(const LzState* st, const cx<T>* __restrict__ r
     const cx<T> a = r[k];
     v[k] = mk<T>((T)(a.re * inv), (T)(a.im * inv));
 }
-void lz_first_vector(bool fp32, const LzState* st, const void* r, void* v, int64_t n, hipStream_t s) {
-    const dim3 grid((unsigned)((n + 255) / 256));
+void lz_first_vector(bool fp32, const LzState* st, const void* r, void* v, int64_t n, const Launch& L) {
+    const dim3 grid((unsigned)((n + 255) / 256), 1, L.nz);
     if (fp32)
-        hipLaunchKernelGGL(scale_from_kernel<float>, grid, dim3(256), 0, s, st, (const cx<float>*)r, (cx<float>*)v, n);
+        hipLaunchKernelGGL(scale_from_kernel<float>, grid, dim3(256), 0, L.s, st, (const cx<float>*)r, (cx<float>*)v, n, L.cs);
     else
-        hipLaunchKernelGGL(scale_from_kernel<double>, grid, dim3(256), 0, s, st, (const cx<double>*)r, (cx<double>*)v, n);
+        hipLaunchKernelGGL(scale_from_kernel<double>, grid, dim3(256), 0, L.s, st, (const cx<double>*)r, (cx<double>*)v, n, L.cs);
 }
 
 // Step 6 scalars from alpha_i: gamma_{i-1} = beta_{i-1}/delta_{i-1}, delta_i, zeta_i.
-__global__ void lz_alpha_kernel(int i, LzState* st, const double* part, int64_t np, LzArrays a) {
+__global__ void lz_alpha_kernel(int i, LzState* st, const double* part, int64_t np, LzArrays a, int64_t cs) {
     __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    st = zoff(st, cs);
+    part = zoff(part, cs);
+    a = zoff(a, cs);
     if (i > st->m) return;
     const double al = block_sum_array(part, np, lds);
     if (threadIdx.x != 0) return;
@@ -217,8 +298,8 @@ __global__ void lz_alpha_kernel(int i, LzState* st, const double* part, int64_t 
     a.zeta[i] = z;
     st->max_abs_alpha = fmax(st->max_abs_alpha, fabs(al));
 }
-void lz_alpha(int i, LzState* st, const double* part, int64_t np, const LzArrays& a, hipStream_t s) {
-    hipLaunchKernelGGL(lz_alpha_kernel, dim3(1), dim3(SCG_BLOCK), 0, s, i, st, part, np, a);
+void lz_alpha(int i, LzState* st, const double* part, int64_t np, const LzArrays& a, const Launch& L) {
+    hipLaunchKernelGGL(lz_alpha_kernel, dim3(1, 1, L.nz), dim3(SCG_BLOCK), 0, L.s, i, st, part, np, a, L.cs);
 }
 
 // Steps 5-6 vectors: f -= alpha_i v_i (and ||f||^2 partials); w_i = (v_i - beta_{i-1} w_{i-1}) / delta_i;
@@ -226,8 +307,16 @@ void lz_alpha(int i, LzState* st, const double* part, int64_t np, const LzArrays
 template <typename T>
 __global__ void lz_update_kernel(int i, const LzState* st, LzArrays a, cx<T>* __restrict__ f, const cx<T>* __restrict__ v,
                                  const cx<T>* __restrict__ wprev, cx<T>* __restrict__ wout, cx<double>* __restrict__ x1,
-                                 double* f2part, int64_t n) {
+                                 double* f2part, int64_t n, int64_t cs) {
     __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    st = zoff(st, cs);
+    a = zoff(a, cs);
+    f = zoff(f, cs);
+    v = zoff(v, cs);
+    wprev = zoff(wprev, cs);
+    wout = zoff(wout, cs);
+    x1 = zoff(x1, cs);
+    f2part = zoff(f2part, cs);
     if (i > st->m) return;
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const double al = a.alpha[i], d = a.delta[i], z = a.zeta[i];
@@ -255,20 +344,23 @@ __global__ void lz_update_kernel(int i, const LzState* st, LzArrays a, cx<T>* __
     if (threadIdx.x == 0) f2part[blockIdx.x] = s;
 }
 void lz_update(bool fp32, int i, const LzState* st, const LzArrays& a, void* f, const void* v, const void* wprev, void* wout,
-               double* x1, double* f2part, int64_t n, hipStream_t s) {
-    const dim3 grid((unsigned)((n + SCG_BLOCK - 1) / SCG_BLOCK));
+               double* x1, double* f2part, int64_t n, const Launch& L) {
+    const dim3 grid((unsigned)((n + SCG_BLOCK - 1) / SCG_BLOCK), 1, L.nz);
     if (fp32)
-        hipLaunchKernelGGL(lz_update_kernel<float>, grid, dim3(SCG_BLOCK), 0, s, i, st, a, (cx<float>*)f, (const cx<float>*)v,
-                           (const cx<float>*)wprev, (cx<float>*)wout, (cx<double>*)x1, f2part, n);
+        hipLaunchKernelGGL(lz_update_kernel<float>, grid, dim3(SCG_BLOCK), 0, L.s, i, st, a, (cx<float>*)f, (const cx<float>*)v,
+                           (const cx<float>*)wprev, (cx<float>*)wout, (cx<double>*)x1, f2part, n, L.cs);
     else
-        hipLaunchKernelGGL(lz_update_kernel<double>, grid, dim3(SCG_BLOCK), 0, s, i, st, a, (cx<double>*)f,
-                           (const cx<double>*)v, (const cx<double>*)wprev, (cx<double>*)wout, (cx<double>*)x1, f2part, n);
+        hipLaunchKernelGGL(lz_update_kernel<double>, grid, dim3(SCG_BLOCK), 0, L.s, i, st, a, (cx<double>*)f,
+                           (const cx<double>*)v, (const cx<double>*)wprev, (cx<double>*)wout, (cx<double>*)x1, f2part, n, L.cs);
 }
 
 // Step 9 scalars: beta_i = ||f||, the D-Lanczos residual estimate beta_i |zeta_i/delta_i|, i_conv,
 // m = min(ceil(past * i_conv), m_cap), breakdown.
-__global__ void lz_beta_kernel(int i, LzState* st, const double* part, int64_t np, LzArrays a) {
+__global__ void lz_beta_kernel(int i, LzState* st, const double* part, int64_t np, LzArrays a, int64_t cs) {
     __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    st = zoff(st, cs);
+    part = zoff(part, cs);
+    a = zoff(a, cs);
     if (i > st->m) return;
     const double b = sqrt(block_sum_array(part, np, lds));
     if (threadIdx.x != 0) return;
@@ -292,14 +384,18 @@ __global__ void lz_beta_kernel(int i, LzState* st, const double* part, int64_t n
         if (st->status == 0 && st->i_conv == 0 && st->past > 0.0) st->status = 3;
     }
 }
-void lz_beta(int i, LzState* st, const double* part, int64_t np, const LzArrays& a, hipStream_t s) {
-    hipLaunchKernelGGL(lz_beta_kernel, dim3(1), dim3(SCG_BLOCK), 0, s, i, st, part, np, a);
+void lz_beta(int i, LzState* st, const double* part, int64_t np, const LzArrays& a, const Launch& L) {
+    hipLaunchKernelGGL(lz_beta_kernel, dim3(1, 1, L.nz), dim3(SCG_BLOCK), 0, L.s, i, st, part, np, a, L.cs);
 }
 
 // Step 9 vector: v_{i+1} = f / beta_i (only when another step follows).
 template <typename T>
 __global__ void lz_next_kernel(int i, const LzState* st, const double* beta, const cx<T>* __restrict__ f,
-                               cx<T>* __restrict__ vn, int64_t n) {
+                               cx<T>* __restrict__ vn, int64_t n, int64_t cs) {
+    st = zoff(st, cs);
+    beta = zoff(beta, cs);
+    f = zoff(f, cs);
+    vn = zoff(vn, cs);
     if (i >= st->m) return;
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
@@ -307,12 +403,12 @@ __global__ void lz_next_kernel(int i, const LzState* st, const double* beta, con
     const cx<T> a = f[k];
     vn[k] = mk<T>((T)(a.re * inv), (T)(a.im * inv));
 }
-void lz_next(bool fp32, int i, const LzState* st, const double* beta, const void* f, void* vn, int64_t n, hipStream_t s) {
-    const dim3 grid((unsigned)((n + 255) / 256));
+void lz_next(bool fp32, int i, const LzState* st, const double* beta, const void* f, void* vn, int64_t n, const Launch& L) {
+    const dim3 grid((unsigned)((n + 255) / 256), 1, L.nz);
     if (fp32)
-        hipLaunchKernelGGL(lz_next_kernel<float>, grid, dim3(256), 0, s, i, st, beta, (const cx<float>*)f, (cx<float>*)vn, n);
+        hipLaunchKernelGGL(lz_next_kernel<float>, grid, dim3(256), 0, L.s, i, st, beta, (const cx<float>*)f, (cx<float>*)vn, n, L.cs);
     else
-        hipLaunchKernelGGL(lz_next_kernel<double>, grid, dim3(256), 0, s, i, st, beta, (const cx<double>*)f, (cx<double>*)vn, n);
+        hipLaunchKernelGGL(lz_next_kernel<double>, grid, dim3(256), 0, L.s, i, st, beta, (const cx<double>*)f, (cx<double>*)vn, n, L.cs);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -320,7 +416,13 @@ void lz_next(bool fp32, int i, const LzState* st, const double* beta, const void
 // then X^j += sum_i eta^j_i w_i.  Rows beyond m (the run ended inside the block) get eta = 0.
 // ---------------------------------------------------------------------------------------------
 __global__ void seed_eta_kernel(int i0, int nb, int nr, const LzState* st, const double* gam, const cx<double>* P,
-                                cx<double>* E, cx<double>* eta_prev, int32_t* nvalid) {
+                                cx<double>* E, cx<double>* eta_prev, int32_t* nvalid, int64_t cs) {
+    st = zoff(st, cs);
+    gam = zoff(gam, cs);
+    P = zoff(P, cs);
+    E = zoff(E, cs);
+    eta_prev = zoff(eta_prev, cs);
+    nvalid = zoff(nvalid, cs);
     const int j = threadIdx.x;
     const int valid = max(0, min(nb, st->m - i0 + 1));
     if (j == 0) *nvalid = valid;
@@ -339,16 +441,21 @@ __global__ void seed_eta_kernel(int i0, int nb, int nr, const LzState* st, const
     eta_prev[j] = eta;
 }
 void seed_eta(int i0, int nb, int nr, const LzState* st, const double* gam, const double* P, double* E, double* eta_prev,
-              int32_t* nvalid, hipStream_t s) {
-    hipLaunchKernelGGL(seed_eta_kernel, dim3(1), dim3(64), 0, s, i0, nb, nr, st, gam, (const cx<double>*)P, (cx<double>*)E,
-                       (cx<double>*)eta_prev, nvalid);
+              int32_t* nvalid, const Launch& L) {
+    hipLaunchKernelGGL(seed_eta_kernel, dim3(1, 1, L.nz), dim3(64), 0, L.s, i0, nb, nr, st, gam, (const cx<double>*)P, (cx<double>*)E,
+                       (cx<double>*)eta_prev, nvalid, L.cs);
 }
 
 // X[j] += sum_{r < nrow} W[r] E[r][j]  (flat vectors of n complex; nrow from the device or a constant)
 template <typename T, typename TX>
 __global__ __launch_bounds__(SCG_BLOCK) void seed_update_kernel(const cx<T>* __restrict__ W, int nw, const cx<double>* __restrict__ E,
-                                                                 cx<TX>* __restrict__ X, int nx, int64_t n, const int32_t* nrow_dev) {
+                                                                 cx<TX>* __restrict__ X, int nx, int64_t n, const int32_t* nrow_dev,
+                                                                 int64_t cs) {
     __shared__ cx<double> e_lds[32 * 48];
+    W = zoff(W, cs);
+    E = zoff(E, cs);
+    X = zoff(X, cs);
+    nrow_dev = zoff(nrow_dev, cs);
     const int nrow = nrow_dev ? min(*nrow_dev, nw) : nw;
     if (nrow <= 0) return;
     for (int k = threadIdx.x; k < nrow * nx; k += blockDim.x) e_lds[k] = E[k];
@@ -373,17 +480,18 @@ __global__ __launch_bounds__(SCG_BLOCK) void seed_update_kernel(const cx<T>* __r
     }
 }
 void seed_update(bool w32, bool x32, const void* W, int nw, const double* E, void* X, int nx, int64_t n, const int32_t* nrow_dev,
-                 hipStream_t s) {
-    const dim3 grid((unsigned)((n + SCG_BLOCK - 1) / SCG_BLOCK));
+                 const Launch& L) {
+    const hipStream_t s = L.s;
+    const dim3 grid((unsigned)((n + SCG_BLOCK - 1) / SCG_BLOCK), 1, L.nz);
     if (w32 && x32)
         hipLaunchKernelGGL((seed_update_kernel<float, float>), grid, dim3(SCG_BLOCK), 0, s, (const cx<float>*)W, nw,
-                           (const cx<double>*)E, (cx<float>*)X, nx, n, nrow_dev);
+                           (const cx<double>*)E, (cx<float>*)X, nx, n, nrow_dev, L.cs);
     else if (w32)
         hipLaunchKernelGGL((seed_update_kernel<float, double>), grid, dim3(SCG_BLOCK), 0, s, (const cx<float>*)W, nw,
-                           (const cx<double>*)E, (cx<double>*)X, nx, n, nrow_dev);
+                           (const cx<double>*)E, (cx<double>*)X, nx, n, nrow_dev, L.cs);
     else
         hipLaunchKernelGGL((seed_update_kernel<double, double>), grid, dim3(SCG_BLOCK), 0, s, (const cx<double>*)W, nw,
-                           (const cx<double>*)E, (cx<double>*)X, nx, n, nrow_dev);
+                           (const cx<double>*)E, (cx<double>*)X, nx, n, nrow_dev, L.cs);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -404,9 +512,15 @@ template <typename T>
 __global__ __launch_bounds__(SCG_BLOCK) void reorth_update_kernel(int i, int pass, const LzState* st, const cx<T>* __restrict__ V,
                                                                    int64_t n, const cx<double>* __restrict__ G,
                                                                    cx<T>* __restrict__ v, cx<T>* __restrict__ f,
-                                                                   double* part) {
+                                                                   double* part, int64_t cs) {
     __shared__ cx<double> cd[2 * 1024];
     __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    st = zoff(st, cs);
+    V = zoff(V, cs);
+    G = zoff(G, cs);
+    v = zoff(v, cs);
+    f = zoff(f, cs);
+    part = zoff(part, cs);
     bool use_v, use_f;
     if (!reorth_gate(i, pass, st, use_v, use_f)) return;
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -461,19 +575,23 @@ __global__ __launch_bounds__(SCG_BLOCK) void reorth_update_kernel(int i, int pas
     }
 }
 void reorth_update(bool fp32, int i, int pass, const LzState* st, const void* V, int64_t n, const double* G, void* v, void* f,
-                   double* part, hipStream_t s) {
-    const dim3 grid((unsigned)((n + SCG_BLOCK - 1) / SCG_BLOCK));
+                   double* part, const Launch& L) {
+    const dim3 grid((unsigned)((n + SCG_BLOCK - 1) / SCG_BLOCK), 1, L.nz);
     if (fp32)
-        hipLaunchKernelGGL(reorth_update_kernel<float>, grid, dim3(SCG_BLOCK), 0, s, i, pass, st, (const cx<float>*)V, n,
-                           (const cx<double>*)G, (cx<float>*)v, (cx<float>*)f, part);
+        hipLaunchKernelGGL(reorth_update_kernel<float>, grid, dim3(SCG_BLOCK), 0, L.s, i, pass, st, (const cx<float>*)V, n,
+                           (const cx<double>*)G, (cx<float>*)v, (cx<float>*)f, part, L.cs);
     else
-        hipLaunchKernelGGL(reorth_update_kernel<double>, grid, dim3(SCG_BLOCK), 0, s, i, pass, st, (const cx<double>*)V, n,
-                           (const cx<double>*)G, (cx<double>*)v, (cx<double>*)f, part);
+        hipLaunchKernelGGL(reorth_update_kernel<double>, grid, dim3(SCG_BLOCK), 0, L.s, i, pass, st, (const cx<double>*)V, n,
+                           (const cx<double>*)G, (cx<double>*)v, (cx<double>*)f, part, L.cs);
 }
 
 // nv = ||v'||, e = v'^dag f' / ||v'||^2; the DGKS test for v (pass 1).
-__global__ void reorth_scalar_kernel(int i, int pass, LzState* st, const double* part, int64_t nb, const cx<double>* G) {
+__global__ void reorth_scalar_kernel(int i, int pass, LzState* st, const double* part, int64_t nb, const cx<double>* G,
+                                     int64_t cs) {
     __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    st = zoff(st, cs);
+    part = zoff(part, cs);
+    G = zoff(G, cs);
     bool use_v, use_f;
     if (!reorth_gate(i, pass, st, use_v, use_f)) return;
     double s[3];
@@ -494,15 +612,19 @@ __global__ void reorth_scalar_kernel(int i, int pass, LzState* st, const double*
         st->passes += (st->rep_v ? 1 : 0) + (st->rep_f ? 1 : 0);
     }
 }
-void reorth_scalar(int i, int pass, LzState* st, const double* part, int64_t nb, const double* G, hipStream_t s) {
-    hipLaunchKernelGGL(reorth_scalar_kernel, dim3(1), dim3(SCG_BLOCK), 0, s, i, pass, st, part, nb, (const cx<double>*)G);
+void reorth_scalar(int i, int pass, LzState* st, const double* part, int64_t nb, const double* G, const Launch& L) {
+    hipLaunchKernelGGL(reorth_scalar_kernel, dim3(1, 1, L.nz), dim3(SCG_BLOCK), 0, L.s, i, pass, st, part, nb, (const cx<double>*)G, L.cs);
 }
 
 // v_i = v' / nv; f = f' - e v'; partials of |f|^2 (for beta_i).
 template <typename T>
 __global__ void reorth_finish_kernel(int i, int pass, const LzState* st, cx<T>* __restrict__ v, cx<T>* __restrict__ f,
-                                     double* f2part, int64_t n) {
+                                     double* f2part, int64_t n, int64_t cs) {
     __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    st = zoff(st, cs);
+    v = zoff(v, cs);
+    f = zoff(f, cs);
+    f2part = zoff(f2part, cs);
     bool use_v, use_f;
     if (!reorth_gate(i, pass, st, use_v, use_f)) return;
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -525,20 +647,23 @@ __global__ void reorth_finish_kernel(int i, int pass, const LzState* st, cx<T>* 
     s = block_sum(s, lds);
     if (threadIdx.x == 0) f2part[blockIdx.x] = s;
 }
-void reorth_finish(bool fp32, int i, int pass, const LzState* st, void* v, void* f, double* f2part, int64_t n, hipStream_t s) {
-    const dim3 grid((unsigned)((n + SCG_BLOCK - 1) / SCG_BLOCK));
+void reorth_finish(bool fp32, int i, int pass, const LzState* st, void* v, void* f, double* f2part, int64_t n, const Launch& L) {
+    const dim3 grid((unsigned)((n + SCG_BLOCK - 1) / SCG_BLOCK), 1, L.nz);
     if (fp32)
-        hipLaunchKernelGGL(reorth_finish_kernel<float>, grid, dim3(SCG_BLOCK), 0, s, i, pass, st, (cx<float>*)v, (cx<float>*)f,
-                           f2part, n);
+        hipLaunchKernelGGL(reorth_finish_kernel<float>, grid, dim3(SCG_BLOCK), 0, L.s, i, pass, st, (cx<float>*)v, (cx<float>*)f,
+                           f2part, n, L.cs);
     else
-        hipLaunchKernelGGL(reorth_finish_kernel<double>, grid, dim3(SCG_BLOCK), 0, s, i, pass, st, (cx<double>*)v,
-                           (cx<double>*)f, f2part, n);
+        hipLaunchKernelGGL(reorth_finish_kernel<double>, grid, dim3(SCG_BLOCK), 0, L.s, i, pass, st, (cx<double>*)v,
+                           (cx<double>*)f, f2part, n, L.cs);
 }
 
 // After a pass: decide the DGKS repeats (pass 1) or clear them (pass 2).
 __global__ void reorth_decide_kernel(int i, int pass, LzState* st, const double* f2_before_part, const double* f2_after_part,
-                                     int64_t nb) {
+                                     int64_t nb, int64_t cs) {
     __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    st = zoff(st, cs);
+    f2_before_part = zoff(f2_before_part, cs);
+    f2_after_part = zoff(f2_after_part, cs);
     if (i > st->m) return;
     const double fb = block_sum_array(f2_before_part, nb, lds);
     __syncthreads();
@@ -554,8 +679,8 @@ __global__ void reorth_decide_kernel(int i, int pass, LzState* st, const double*
     }
     st->rep_any = st->rep_v | st->rep_f;
 }
-void reorth_decide(int i, int pass, LzState* st, const double* f2b, const double* f2a, int64_t nb, hipStream_t s) {
-    hipLaunchKernelGGL(reorth_decide_kernel, dim3(1), dim3(SCG_BLOCK), 0, s, i, pass, st, f2b, f2a, nb);
+void reorth_decide(int i, int pass, LzState* st, const double* f2b, const double* f2a, int64_t nb, const Launch& L) {
+    hipLaunchKernelGGL(reorth_decide_kernel, dim3(1, 1, L.nz), dim3(SCG_BLOCK), 0, L.s, i, pass, st, f2b, f2a, nb, L.cs);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -564,27 +689,35 @@ void reorth_decide(int i, int pass, LzState* st, const double* f2b, const double
 __device__ inline bool cg_skip(const CgVec& c) { return c.done || c.frozen; }
 
 // a_j = rr_j / Re(p_j^dag q_j)   (preconditioned: rz_j = Re r_j^dag z_j in the numerator)
-__global__ void cg_alpha_kernel(CgVec* cg, const double* part, int64_t nb, const int32_t* vec_map, int pc) {
+__global__ void cg_alpha_kernel(CgVec* cg, const double* part, int64_t nb, const int32_t* vec_map, int pc, int64_t cs) {
     __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    cg = zoff(cg, cs);
+    part = zoff(part, cs);
+    vec_map = zoff(vec_map, cs);
     const int vec = vec_map[blockIdx.x];
-    if (cg_skip(cg[vec])) return;
+    if (vec < 0 || cg_skip(cg[vec])) return;
     const double pq = block_sum_array(part + (int64_t)vec * nb, nb, lds);
     if (threadIdx.x == 0) {
         cg[vec].pq = pq;
         cg[vec].a = (pc ? cg[vec].rz : cg[vec].rr) / pq;
     }
 }
-void cg_alpha(CgVec* cg, const double* part, int64_t nb, const int32_t* vec_map, int nact, hipStream_t s, bool pc) {
-    hipLaunchKernelGGL(cg_alpha_kernel, dim3(nact), dim3(SCG_BLOCK), 0, s, cg, part, nb, vec_map, (int)pc);
+void cg_alpha(CgVec* cg, const double* part, int64_t nb, const int32_t* vec_map, int nact, const Launch& L, bool pc) {
+    hipLaunchKernelGGL(cg_alpha_kernel, dim3(nact, 1, L.nz), dim3(SCG_BLOCK), 0, L.s, cg, part, nb, vec_map, (int)pc, L.cs);
 }
 
 // partials of Re a_v^dag b_v for the vectors of vec_map (grid: blocks x nact)
 template <typename T>
 __global__ void dot_map_kernel(const cx<T>* __restrict__ a, const cx<T>* __restrict__ b, int64_t n, const int32_t* vec_map,
-                               const CgVec* cg, double* part, int64_t nb) {
+                               const CgVec* cg, double* part, int64_t nb, int64_t cs) {
     __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    a = zoff(a, cs);
+    b = zoff(b, cs);
+    vec_map = zoff(vec_map, cs);
+    cg = zoff(cg, cs);
+    part = zoff(part, cs);
     const int vec = vec_map[blockIdx.y];
-    if (cg && cg_skip(cg[vec])) return;
+    if (vec < 0 || (cg && cg_skip(cg[vec]))) return;
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double s = 0.0;
     if (k < n) {
@@ -595,22 +728,27 @@ __global__ void dot_map_kernel(const cx<T>* __restrict__ a, const cx<T>* __restr
     if (threadIdx.x == 0) part[(int64_t)vec * nb + blockIdx.x] = s;
 }
 void dot_map(bool fp32, const void* a, const void* b, int64_t n, const int32_t* vec_map, int nact, const CgVec* cg, double* part,
-             hipStream_t s) {
+             const Launch& L) {
     const int64_t nb = (n + SCG_BLOCK - 1) / SCG_BLOCK;
-    const dim3 grid((unsigned)nb, nact);
+    const dim3 grid((unsigned)nb, nact, L.nz);
     if (fp32)
-        hipLaunchKernelGGL(dot_map_kernel<float>, grid, dim3(SCG_BLOCK), 0, s, (const cx<float>*)a, (const cx<float>*)b, n, vec_map, cg,
-                           part, nb);
+        hipLaunchKernelGGL(dot_map_kernel<float>, grid, dim3(SCG_BLOCK), 0, L.s, (const cx<float>*)a, (const cx<float>*)b, n, vec_map, cg,
+                           part, nb, L.cs);
     else
-        hipLaunchKernelGGL(dot_map_kernel<double>, grid, dim3(SCG_BLOCK), 0, s, (const cx<double>*)a, (const cx<double>*)b, n, vec_map,
-                           cg, part, nb);
+        hipLaunchKernelGGL(dot_map_kernel<double>, grid, dim3(SCG_BLOCK), 0, L.s, (const cx<double>*)a, (const cx<double>*)b, n, vec_map,
+                           cg, part, nb, L.cs);
 }
 
 // preconditioned CG: rr_new = |r|^2 for the stop test, rz_new = Re r^dag z, b = rz_new / rz
-__global__ void cg_beta_pc_kernel(CgVec* cg, const double* rrpart, const double* rzpart, int64_t nb, const int32_t* vec_map, int max_iter) {
+__global__ void cg_beta_pc_kernel(CgVec* cg, const double* rrpart, const double* rzpart, int64_t nb, const int32_t* vec_map, int max_iter,
+                                  int64_t cs) {
     __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    cg = zoff(cg, cs);
+    rrpart = zoff(rrpart, cs);
+    rzpart = zoff(rzpart, cs);
+    vec_map = zoff(vec_map, cs);
     const int vec = vec_map[blockIdx.x];
-    if (cg_skip(cg[vec])) return;
+    if (vec < 0 || cg_skip(cg[vec])) return;
     const double rr = block_sum_array(rrpart + (int64_t)vec * nb, nb, lds);
     __syncthreads();
     const double rz = block_sum_array(rzpart + (int64_t)vec * nb, nb, lds);
@@ -628,18 +766,26 @@ __global__ void cg_beta_pc_kernel(CgVec* cg, const double* rrpart, const double*
     c.rr = rr;
 }
 void cg_beta_pc(CgVec* cg, const double* rrpart, const double* rzpart, int64_t nb, const int32_t* vec_map, int nact, int max_iter,
-                hipStream_t s) {
-    hipLaunchKernelGGL(cg_beta_pc_kernel, dim3(nact), dim3(SCG_BLOCK), 0, s, cg, rrpart, rzpart, nb, vec_map, max_iter);
+                const Launch& L) {
+    hipLaunchKernelGGL(cg_beta_pc_kernel, dim3(nact, 1, L.nz), dim3(SCG_BLOCK), 0, L.s, cg, rrpart, rzpart, nb, vec_map, max_iter, L.cs);
 }
 
 // x += a p; r -= a q; partials |r|^2
 template <typename T, typename TX>
 __global__ void cg_update_kernel(const CgVec* cg, const int32_t* vec_map, int nact, cx<TX>* __restrict__ X, const cx<T>* __restrict__ P,
-                                 cx<T>* __restrict__ R, const cx<T>* __restrict__ Q, double* part, int64_t n, int64_t nb) {
+                                 cx<T>* __restrict__ R, const cx<T>* __restrict__ Q, double* part, int64_t n, int64_t nb,
+                                 int64_t cs) {
     __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    cg = zoff(cg, cs);
+    vec_map = zoff(vec_map, cs);
+    X = zoff(X, cs);
+    P = zoff(P, cs);
+    R = zoff(R, cs);
+    Q = zoff(Q, cs);
+    part = zoff(part, cs);
     const int slot = blockIdx.y;
     const int vec = vec_map[slot];
-    if (cg_skip(cg[vec])) return;
+    if (vec < 0 || cg_skip(cg[vec])) return;
     const double a = cg[vec].a;
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double s = 0.0;
@@ -657,26 +803,30 @@ __global__ void cg_update_kernel(const CgVec* cg, const int32_t* vec_map, int na
     if (threadIdx.x == 0) part[(int64_t)vec * nb + blockIdx.x] = s;
 }
 void cg_update(bool fp32, bool x32, const CgVec* cg, const int32_t* vec_map, int nact, void* X, const void* P, void* R,
-               const void* Q, double* part, int64_t n, hipStream_t s) {
+               const void* Q, double* part, int64_t n, const Launch& L) {
+    const hipStream_t s = L.s;
     const int64_t nb = (n + SCG_BLOCK - 1) / SCG_BLOCK;
-    const dim3 grid((unsigned)nb, nact);
+    const dim3 grid((unsigned)nb, nact, L.nz);
     if (fp32 && x32)
         hipLaunchKernelGGL((cg_update_kernel<float, float>), grid, dim3(SCG_BLOCK), 0, s, cg, vec_map, nact, (cx<float>*)X,
-                           (const cx<float>*)P, (cx<float>*)R, (const cx<float>*)Q, part, n, nb);
+                           (const cx<float>*)P, (cx<float>*)R, (const cx<float>*)Q, part, n, nb, L.cs);
     else if (fp32)
         hipLaunchKernelGGL((cg_update_kernel<float, double>), grid, dim3(SCG_BLOCK), 0, s, cg, vec_map, nact, (cx<double>*)X,
-                           (const cx<float>*)P, (cx<float>*)R, (const cx<float>*)Q, part, n, nb);
+                           (const cx<float>*)P, (cx<float>*)R, (const cx<float>*)Q, part, n, nb, L.cs);
     else
         hipLaunchKernelGGL((cg_update_kernel<double, double>), grid, dim3(SCG_BLOCK), 0, s, cg, vec_map, nact, (cx<double>*)X,
-                           (const cx<double>*)P, (cx<double>*)R, (const cx<double>*)Q, part, n, nb);
+                           (const cx<double>*)P, (cx<double>*)R, (const cx<double>*)Q, part, n, nb, L.cs);
 }
 
 // rr_new = |r|^2; stop test on the recursive residual (freeze for a true-residual check);
 // b = rr_new / rr
-__global__ void cg_beta_kernel(CgVec* cg, const double* part, int64_t nb, const int32_t* vec_map, int max_iter) {
+__global__ void cg_beta_kernel(CgVec* cg, const double* part, int64_t nb, const int32_t* vec_map, int max_iter, int64_t cs) {
     __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    cg = zoff(cg, cs);
+    part = zoff(part, cs);
+    vec_map = zoff(vec_map, cs);
     const int vec = vec_map[blockIdx.x];
-    if (cg_skip(cg[vec])) return;
+    if (vec < 0 || cg_skip(cg[vec])) return;
     const double rr = block_sum_array(part + (int64_t)vec * nb, nb, lds);
     if (threadIdx.x != 0) return;
     CgVec& c = cg[vec];
@@ -690,16 +840,20 @@ __global__ void cg_beta_kernel(CgVec* cg, const double* part, int64_t nb, const 
     c.rr_old = c.rr;
     c.rr = rr;
 }
-void cg_beta(CgVec* cg, const double* part, int64_t nb, const int32_t* vec_map, int nact, int max_iter, hipStream_t s) {
-    hipLaunchKernelGGL(cg_beta_kernel, dim3(nact), dim3(SCG_BLOCK), 0, s, cg, part, nb, vec_map, max_iter);
+void cg_beta(CgVec* cg, const double* part, int64_t nb, const int32_t* vec_map, int nact, int max_iter, const Launch& L) {
+    hipLaunchKernelGGL(cg_beta_kernel, dim3(nact, 1, L.nz), dim3(SCG_BLOCK), 0, L.s, cg, part, nb, vec_map, max_iter, L.cs);
 }
 
 // p = r + b p
 template <typename T>
 __global__ void cg_p_kernel(const CgVec* cg, const int32_t* vec_map, cx<T>* __restrict__ P, const cx<T>* __restrict__ R, int64_t n,
-                            int ignore_frozen) {
+                            int ignore_frozen, int64_t cs) {
+    cg = zoff(cg, cs);
+    vec_map = zoff(vec_map, cs);
+    P = zoff(P, cs);
+    R = zoff(R, cs);
     const int vec = vec_map[blockIdx.y];
-    if (cg[vec].done || (cg[vec].frozen && !ignore_frozen)) return;
+    if (vec < 0 || cg[vec].done || (cg[vec].frozen && !ignore_frozen)) return;
     const double b = cg[vec].b;
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
@@ -708,32 +862,34 @@ __global__ void cg_p_kernel(const CgVec* cg, const int32_t* vec_map, cx<T>* __re
     P[o] = mk<T>((T)(r.re + b * p.re), (T)(r.im + b * p.im));
 }
 void cg_p(bool fp32, const CgVec* cg, const int32_t* vec_map, int nact, void* P, const void* R, int64_t n, bool ignore_frozen,
-          hipStream_t s) {
-    const dim3 grid((unsigned)((n + 255) / 256), nact);
+          const Launch& L) {
+    const dim3 grid((unsigned)((n + 255) / 256), nact, L.nz);
     if (fp32)
-        hipLaunchKernelGGL(cg_p_kernel<float>, grid, dim3(256), 0, s, cg, vec_map, (cx<float>*)P, (const cx<float>*)R, n,
-                           (int)ignore_frozen);
+        hipLaunchKernelGGL(cg_p_kernel<float>, grid, dim3(256), 0, L.s, cg, vec_map, (cx<float>*)P, (const cx<float>*)R, n,
+                           (int)ignore_frozen, L.cs);
     else
-        hipLaunchKernelGGL(cg_p_kernel<double>, grid, dim3(256), 0, s, cg, vec_map, (cx<double>*)P, (const cx<double>*)R, n,
-                           (int)ignore_frozen);
+        hipLaunchKernelGGL(cg_p_kernel<double>, grid, dim3(256), 0, L.s, cg, vec_map, (cx<double>*)P, (const cx<double>*)R, n,
+                           (int)ignore_frozen, L.cs);
 }
 
 // gamma5 = diag(1, 1, -1, -1): components 6..11 (spins 2, 3) change sign
 template <typename T>
-__global__ void gamma5_copy_kernel(const cx<T>* a, cx<T>* b, int64_t Vh, int64_t total) {
+__global__ void gamma5_copy_kernel(const cx<T>* a, cx<T>* b, int64_t Vh, int64_t total, int64_t cs) {
+    a = zoff(a, cs);
+    b = zoff(b, cs);
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= total) return;
     const int64_t c = (k / Vh) % 12;
     const cx<T> v = a[k];
     b[k] = c >= 6 ? mk<T>(-v.re, -v.im) : v;
 }
-void gamma5_copy(bool fp32, const void* a, void* b, int64_t Vh, int nvec, hipStream_t s) {
+void gamma5_copy(bool fp32, const void* a, void* b, int64_t Vh, int nvec, const Launch& L) {
     const int64_t total = 12 * Vh * nvec;
-    const dim3 grid((unsigned)((total + 255) / 256));
+    const dim3 grid((unsigned)((total + 255) / 256), 1, L.nz);
     if (fp32)
-        hipLaunchKernelGGL(gamma5_copy_kernel<float>, grid, dim3(256), 0, s, (const cx<float>*)a, (cx<float>*)b, Vh, total);
+        hipLaunchKernelGGL(gamma5_copy_kernel<float>, grid, dim3(256), 0, L.s, (const cx<float>*)a, (cx<float>*)b, Vh, total, L.cs);
     else
-        hipLaunchKernelGGL(gamma5_copy_kernel<double>, grid, dim3(256), 0, s, (const cx<double>*)a, (cx<double>*)b, Vh, total);
+        hipLaunchKernelGGL(gamma5_copy_kernel<double>, grid, dim3(256), 0, L.s, (const cx<double>*)a, (cx<double>*)b, Vh, total, L.cs);
 }
 
 }  // namespace scg

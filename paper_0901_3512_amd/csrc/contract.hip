@@ -42,12 +42,19 @@ struct MfmaAcc<float> {
 
 // TS: storage type of V and R; T: compute type (FP32 storage may be contracted in FP64)
 template <typename TS, typename T>
-__global__ __launch_bounds__(256) void proj_kernel(ProjArgs pa) {
+__global__ __launch_bounds__(256) void proj_kernel(ProjArgs pa, int64_t cs) {
     using Acc = MfmaAcc<T>;
     using V4 = typename Acc::V4;
     __shared__ T As[PJ_ROWS * PJ_LD];
     __shared__ T Bs[PJ_MAXR * PJ_LD];
 
+    if (cs) {
+        pa.V = zoff(pa.V, cs);
+        for (int j = 0; j < pa.nr; j++) pa.R[j] = zoff(pa.R[j], cs);
+        pa.part = zoff(pa.part, cs);
+        pa.st = zoff(pa.st, cs);
+        pa.flag = zoff(pa.flag, cs);
+    }
     if (pa.st && pa.gate_i > pa.st->m) return;
     if (pa.flag && *pa.flag == 0) return;
     int nvalid = pa.nv;
@@ -150,7 +157,11 @@ __global__ __launch_bounds__(256) void proj_kernel(ProjArgs pa) {
 // P[r][j] = sum over chunks of part[chunk][r][j]; one wavefront per output value, lane c adds
 // chunks c, c+64, ... and the lanes are combined by a fixed shuffle tree (deterministic).
 __global__ void proj_reduce_kernel(const double* part, int64_t nchunks, int64_t stride, int64_t len, double* P,
-                                   const LzState* st, int gate_i, const int32_t* flag) {
+                                   const LzState* st, int gate_i, const int32_t* flag, int64_t cs) {
+    part = zoff(part, cs);
+    P = zoff(P, cs);
+    st = zoff(st, cs);
+    flag = zoff(flag, cs);
     if (st && gate_i > st->m) return;
     if (flag && *flag == 0) return;
     const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / SCG_WAVE;
@@ -164,18 +175,19 @@ __global__ void proj_reduce_kernel(const double* part, int64_t nchunks, int64_t 
 
 int64_t proj_chunks(int64_t n, int64_t kchunk) { return (n + kchunk - 1) / kchunk; }
 
-void project(bool fp32, const ProjArgs& a, int64_t nrowblocks, double* P, hipStream_t s, bool fp64_math) {
+void project(bool fp32, const ProjArgs& a, int64_t nrowblocks, double* P, const Launch& L, bool fp64_math) {
+    const hipStream_t s = L.s;
     const int64_t nch = proj_chunks(a.n, a.kchunk);
-    const dim3 grid((unsigned)nch, (unsigned)nrowblocks);
+    const dim3 grid((unsigned)nch, (unsigned)nrowblocks, L.nz);
     if (fp32 && fp64_math)
-        hipLaunchKernelGGL((proj_kernel<float, double>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((proj_kernel<float, double>), grid, dim3(256), 0, s, a, L.cs);
     else if (fp32)
-        hipLaunchKernelGGL((proj_kernel<float, float>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((proj_kernel<float, float>), grid, dim3(256), 0, s, a, L.cs);
     else
-        hipLaunchKernelGGL((proj_kernel<double, double>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((proj_kernel<double, double>), grid, dim3(256), 0, s, a, L.cs);
     const int64_t len = 2 * (int64_t)a.nv * a.nr;
-    hipLaunchKernelGGL(proj_reduce_kernel, dim3((unsigned)((len * SCG_WAVE + 255) / 256)), dim3(256), 0, s, a.part, nch, a.part_stride, len, P,
-                       a.st, a.gate_i, a.flag);
+    hipLaunchKernelGGL(proj_reduce_kernel, dim3((unsigned)((len * SCG_WAVE + 255) / 256), 1, L.nz), dim3(256), 0, s, a.part, nch,
+                       a.part_stride, len, P, a.st, a.gate_i, a.flag, L.cs);
 }
 
 }  // namespace scg

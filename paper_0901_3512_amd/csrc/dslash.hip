@@ -116,7 +116,26 @@ struct EpiDev {
     int32_t gate_i;
     const int32_t* vec_map;
     const CgVec* cg;
+    const double* kappa2_dev;
 };
+
+// move every per-configuration pointer of a launch to configuration blockIdx.z
+template <typename T, typename PL, typename PI, typename PO>
+__device__ inline void zoff_hop(int64_t cs, PL& links, PI& in, PO& out, EpiDev<T>& e) {
+    if (cs == 0) return;
+    links = zoff(links, cs);
+    in = zoff(in, cs);
+    out = zoff(out, cs);
+    e.x = zoff(e.x, cs);
+    e.z = zoff(e.z, cs);
+    e.cz_dev = zoff(e.cz_dev, cs);
+    e.d = zoff(e.d, cs);
+    e.partials = zoff(e.partials, cs);
+    e.gate_m = zoff(e.gate_m, cs);
+    e.vec_map = zoff(e.vec_map, cs);
+    e.cg = zoff(e.cg, cs);
+    e.kappa2_dev = zoff(e.kappa2_dev, cs);
+}
 
 // neighbour (checkerboard index) of site (x,y,z,t) with index h in direction mu, step +-1, and the
 // boundary sign of that hop
@@ -198,10 +217,12 @@ constexpr int HOP_MAX_VB = 32;
 template <typename T, typename LT, int TPS, bool HOIST>
 __global__ __launch_bounds__(SCG_BLOCK) void hop_kernel(Geom g, const typename LinkLoad<LT>::Store* __restrict__ links,
                                                         const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
-                                                        int p, int nvec, int vb, int64_t nsb, EpiDev<T> e) {
+                                                        int p, int nvec, int vb, int64_t nsb, EpiDev<T> e, int64_t cs) {
     constexpr int NMU = 4 / TPS;
     __shared__ double red_lds[HOP_MAX_VB * (SCG_BLOCK / SCG_WAVE)];
+    zoff_hop(cs, links, in, out, e);
     if (e.gate_m && e.gate_i > *e.gate_m) return;
+    if (e.kappa2_dev) e.kappa2 = (T)*e.kappa2_dev;
     const int nvg = (nvec + vb - 1) / vb;
     const int64_t nblk = nsb * nvg;
     const int64_t logical = xcd_logical_block(nblk);
@@ -246,7 +267,7 @@ __global__ __launch_bounds__(SCG_BLOCK) void hop_kernel(Geom g, const typename L
         const int slot = vg * vb + vi;
         if (slot >= nvec) break;
         const int vec = e.vec_map ? e.vec_map[slot] : slot;
-        if (e.cg && (e.cg[vec].done || e.cg[vec].frozen)) continue;
+        if (vec < 0 || (e.cg && (e.cg[vec].done || e.cg[vec].frozen))) continue;
         const cx<T>* src = in + (int64_t)vec * 12 * Vh;
 
         cx<T> acc[12];
@@ -326,7 +347,7 @@ __global__ __launch_bounds__(SCG_BLOCK) void hop_kernel(Geom g, const typename L
             const int slot = vg * vb + vi;
             if (slot < nvec) {
                 const int vec = e.vec_map ? e.vec_map[slot] : slot;
-                if (!(e.cg && (e.cg[vec].done || e.cg[vec].frozen))) {
+                if (vec >= 0 && !(e.cg && (e.cg[vec].done || e.cg[vec].frozen))) {
                     double s = 0.0;
                     for (int w = 0; w < SCG_BLOCK / SCG_WAVE; w++) s += red_lds[vi * (SCG_BLOCK / SCG_WAVE) + w];
                     e.partials[(int64_t)vec * nsb + sb] = s;
@@ -464,9 +485,11 @@ __device__ inline void hop_dir_rt(const cx<T>* __restrict__ src, const typename 
 template <typename T, typename LT, bool ONE>
 __global__ __launch_bounds__(SCG_BLOCK) void hop_lean_kernel(Geom g, const typename LinkLoad<LT>::Store* __restrict__ links,
                                                              const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
-                                                             int p, int nvec, int vb, int64_t nsb, EpiDev<T> e) {
+                                                             int p, int nvec, int vb, int64_t nsb, EpiDev<T> e, int64_t cs) {
     __shared__ double red_lds[HOP_MAX_VB * (SCG_BLOCK / SCG_WAVE)];
+    zoff_hop(cs, links, in, out, e);
     if (e.gate_m && e.gate_i > *e.gate_m) return;
+    if (e.kappa2_dev) e.kappa2 = (T)*e.kappa2_dev;
     const int nvg = (nvec + vb - 1) / vb;
     const int64_t nblk = nsb * nvg;
     const int64_t logical = xcd_logical_block(nblk);
@@ -503,7 +526,7 @@ __global__ __launch_bounds__(SCG_BLOCK) void hop_lean_kernel(Geom g, const typen
         const int slot = vg * vb + vi;
         if (slot >= nvec) break;
         const int vec = e.vec_map ? e.vec_map[slot] : slot;
-        if (e.cg && (e.cg[vec].done || e.cg[vec].frozen)) continue;
+        if (vec < 0 || (e.cg && (e.cg[vec].done || e.cg[vec].frozen))) continue;
         const cx<T>* src = in + (size_t)vec * 12 * Vh;
         cx<T> acc[12];
 #pragma unroll
@@ -565,7 +588,7 @@ __global__ __launch_bounds__(SCG_BLOCK) void hop_lean_kernel(Geom g, const typen
             const int slot = vg * vb + vi;
             if (slot < nvec) {
                 const int vec = e.vec_map ? e.vec_map[slot] : slot;
-                if (!(e.cg && (e.cg[vec].done || e.cg[vec].frozen))) {
+                if (vec >= 0 && !(e.cg && (e.cg[vec].done || e.cg[vec].frozen))) {
                     double s = 0.0;
                     for (int w = 0; w < SCG_BLOCK / SCG_WAVE; w++) s += red_lds[vi * (SCG_BLOCK / SCG_WAVE) + w];
                     e.partials[(int64_t)vec * nsb + sb] = s;
@@ -593,7 +616,8 @@ int hop_site_blocks(const Geom& g, int tps) {
 
 template <typename T, typename LT>
 static void launch_t(const Geom& g, const void* links, const void* in, void* out, int p, int nvec, const HopEpi& epi,
-                     int tps, int vb, hipStream_t s) {
+                     int tps, int vb, const Launch& L) {
+    const hipStream_t s = L.s;
     EpiDev<T> e;
     e.apply_g5 = epi.apply_g5;
     e.combine = epi.combine;
@@ -611,6 +635,7 @@ static void launch_t(const Geom& g, const void* links, const void* in, void* out
     e.gate_i = epi.gate_i;
     e.vec_map = epi.vec_map;
     e.cg = epi.cg;
+    e.kappa2_dev = epi.kappa2_dev;
     const int64_t nsb = hop_site_blocks(g, tps);
     vb = vb < 1 ? 1 : (vb > nvec ? nvec : vb);
     vb = vb > HOP_MAX_VB ? HOP_MAX_VB : vb;
@@ -619,33 +644,33 @@ static void launch_t(const Geom& g, const void* links, const void* in, void* out
     // links kept in registers across the vectors of a workgroup when one lane holds one direction
     const bool hoist = tps == 4 && hop_hoist_links();
     if (tps == 3 && vb == 1)
-        hipLaunchKernelGGL((hop_lean_kernel<T, LT, true>), dim3(grid), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
-                           (const cx<T>*)in, (cx<T>*)out, p, nvec, vb, nsb, e);
+        hipLaunchKernelGGL((hop_lean_kernel<T, LT, true>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
+                           (const cx<T>*)in, (cx<T>*)out, p, nvec, vb, nsb, e, L.cs);
     else if (tps == 3)
-        hipLaunchKernelGGL((hop_lean_kernel<T, LT, false>), dim3(grid), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
-                           (const cx<T>*)in, (cx<T>*)out, p, nvec, vb, nsb, e);
+        hipLaunchKernelGGL((hop_lean_kernel<T, LT, false>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
+                           (const cx<T>*)in, (cx<T>*)out, p, nvec, vb, nsb, e, L.cs);
     else if (tps == 1)
-        hipLaunchKernelGGL((hop_kernel<T, LT, 1, false>), dim3(grid), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
-                           (const cx<T>*)in, (cx<T>*)out, p, nvec, vb, nsb, e);
+        hipLaunchKernelGGL((hop_kernel<T, LT, 1, false>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
+                           (const cx<T>*)in, (cx<T>*)out, p, nvec, vb, nsb, e, L.cs);
     else if (tps == 2)
-        hipLaunchKernelGGL((hop_kernel<T, LT, 2, false>), dim3(grid), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
-                           (const cx<T>*)in, (cx<T>*)out, p, nvec, vb, nsb, e);
+        hipLaunchKernelGGL((hop_kernel<T, LT, 2, false>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
+                           (const cx<T>*)in, (cx<T>*)out, p, nvec, vb, nsb, e, L.cs);
     else if (hoist)
-        hipLaunchKernelGGL((hop_kernel<T, LT, 4, true>), dim3(grid), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
-                           (const cx<T>*)in, (cx<T>*)out, p, nvec, vb, nsb, e);
+        hipLaunchKernelGGL((hop_kernel<T, LT, 4, true>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
+                           (const cx<T>*)in, (cx<T>*)out, p, nvec, vb, nsb, e, L.cs);
     else
-        hipLaunchKernelGGL((hop_kernel<T, LT, 4, false>), dim3(grid), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
-                           (const cx<T>*)in, (cx<T>*)out, p, nvec, vb, nsb, e);
+        hipLaunchKernelGGL((hop_kernel<T, LT, 4, false>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
+                           (const cx<T>*)in, (cx<T>*)out, p, nvec, vb, nsb, e, L.cs);
 }
 
 void launch_hop(Prec prec, const Geom& g, const void* links, const void* in, void* out, int out_parity, int nvec,
-                const HopEpi& epi, int tps, int vb, hipStream_t s) {
+                const HopEpi& epi, int tps, int vb, const Launch& L) {
     if (prec == P64)
-        launch_t<double, double>(g, links, in, out, out_parity, nvec, epi, tps, vb, s);
+        launch_t<double, double>(g, links, in, out, out_parity, nvec, epi, tps, vb, L);
     else if (prec == P32)
-        launch_t<float, float>(g, links, in, out, out_parity, nvec, epi, tps, vb, s);
+        launch_t<float, float>(g, links, in, out, out_parity, nvec, epi, tps, vb, L);
     else
-        launch_t<float, bf16link>(g, links, in, out, out_parity, nvec, epi, tps, vb, s);
+        launch_t<float, bf16link>(g, links, in, out, out_parity, nvec, epi, tps, vb, L);
 }
 
 }  // namespace scg

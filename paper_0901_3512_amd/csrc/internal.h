@@ -72,6 +72,21 @@ __device__ inline int64_t xcd_logical_block(int64_t nblocks) {
 }
 inline int64_t xcd_grid(int64_t nblocks) { return (nblocks + SCG_NXCD - 1) / SCG_NXCD * SCG_NXCD; }
 
+// A batch of same-shape configurations shares one allocation per buffer family laid out so
+// that every per-configuration buffer of configuration c sits exactly c * cs bytes after
+// configuration 0's.  A launch then covers all configurations with grid.z = nz, and each
+// kernel moves its pointer arguments by blockIdx.z * cs (cs = 0, nz = 1 for a single one).
+struct Launch {
+    hipStream_t s;
+    int nz;
+    int64_t cs;
+    Launch(hipStream_t s_ = nullptr, int nz_ = 1, int64_t cs_ = 0) : s(s_), nz(nz_), cs(cs_) {}
+};
+template <typename P>
+__device__ inline P* zoff(P* p, int64_t cs) {
+    return p ? (P*)((char*)p + (int64_t)blockIdx.z * cs) : p;
+}
+
 // Deterministic block reduction of one double (fixed shuffle tree, then waves in order).
 __device__ inline double block_sum(double v, double* lds /* >= SCG_BLOCK/SCG_WAVE */) {
     for (int off = SCG_WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -141,14 +156,15 @@ struct HopEpi {
     double* partials;  // [vec][nblocks_site]
     const int32_t* gate_m;  // if non-null: skip when gate_i > *gate_m
     int32_t gate_i;
-    const int32_t* vec_map; // optional: vector slot -> stored vector index
+    const int32_t* vec_map; // optional: vector slot -> stored vector index (-1: empty slot)
     const CgVec* cg;   // optional: skip vectors whose CG is done or frozen
+    const double* kappa2_dev;  // optional: kappa^2 from device memory (per configuration)
 };
 
 // out(parity p) = H_{p,1-p} in, with the epilogue above, for nvec vectors.
 // vb: vectors per workgroup (the links of a site are loaded once per workgroup)
 void launch_hop(Prec prec, const Geom& g, const void* links, const void* in, void* out, int out_parity,
-                int nvec, const HopEpi& epi, int tps, int vb, hipStream_t s);
+                int nvec, const HopEpi& epi, int tps, int vb, const Launch& L);
 int hop_site_blocks(const Geom& g, int tps);
 bool hop_hoist_links();
 void set_hop_hoist_links(bool on);

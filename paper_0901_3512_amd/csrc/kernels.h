@@ -13,6 +13,10 @@ struct LzArrays {
     double* zeta;   // zeta_i
     double* est;    // relative residual estimate after step i
 };
+__device__ inline LzArrays zoff(LzArrays a, int64_t cs) {
+    if (cs == 0) return a;
+    return LzArrays{zoff(a.alpha, cs), zoff(a.beta, cs), zoff(a.delta, cs), zoff(a.gam, cs), zoff(a.zeta, cs), zoff(a.est, cs)};
+}
 
 // P = V^dag R contraction (split-K partials then a fixed-order reduction)
 struct ProjArgs {
@@ -32,47 +36,53 @@ struct ProjArgs {
     const int32_t* flag;    // optional gate: skip when *flag == 0
 };
 // fp32: V and R stored in FP32; fp64_math: contract them on the FP64 matrix cores anyway
-void project(bool fp32, const ProjArgs& a, int64_t nrowblocks, double* P, hipStream_t s, bool fp64_math = false);
+void project(bool fp32, const ProjArgs& a, int64_t nrowblocks, double* P, const Launch& L, bool fp64_math = false);
 int64_t proj_chunks(int64_t n, int64_t kchunk);
 
 void pack_links(Prec prec, const Geom& g, const double* U, void* out, hipStream_t s);
-void pack_vec(bool fp32, const double* in, void* out, int64_t Vh, int nvec, hipStream_t s);
-void unpack_vec(bool fp32, const void* in, double* out, int64_t Vh, int nvec, hipStream_t s);
-void gamma5_copy(bool fp32, const void* a, void* b, int64_t Vh, int nvec, hipStream_t s);
-void convert(bool from32, bool to32, const void* a, void* b, int64_t n, hipStream_t s);
-void norm2_partials(bool fp32, const void* a, int64_t n, int nvec, double* part, hipStream_t s);
+// tab (optional, device memory): one canonical pointer per configuration of the launch
+void pack_vec(bool fp32, const double* in, void* out, int64_t Vh, int nvec, const Launch& L, const double* const* tab = nullptr);
+void unpack_vec(bool fp32, const void* in, double* out, int64_t Vh, int nvec, const Launch& L, double* const* tab = nullptr);
+void gamma5_copy(bool fp32, const void* a, void* b, int64_t Vh, int nvec, const Launch& L);
+void convert(bool from32, bool to32, const void* a, void* b, int64_t n, const Launch& L);
+void convert_map(bool from32, bool to32, const void* a, void* b, int64_t n, const int32_t* vec_map, int nact, const Launch& L);
+// per-configuration byte copies (bytes a multiple of 4): configuration z moves src + z*src_cs to
+// dst + z*dst_cs; cfg_zero clears bytes at dst + z*L.cs
+void cfg_copy(const void* src, int64_t src_cs, void* dst, int64_t dst_cs, int64_t bytes, const Launch& L);
+void cfg_zero(void* dst, int64_t bytes, const Launch& L);
+void norm2_partials(bool fp32, const void* a, int64_t n, int nvec, double* part, const Launch& L);
 int64_t norm2_blocks(int64_t n);
-void sum_partials(const double* part, int64_t nb, int nvec, double* out, bool sqrt_out, hipStream_t s);
+void sum_partials(const double* part, int64_t nb, int nvec, double* out, bool sqrt_out, const Launch& L);
 
-void lz_start(LzState* st, const double* r2part, int64_t nb, const double* b2part, double* beta, hipStream_t s);
-void lz_first_vector(bool fp32, const LzState* st, const void* r, void* v, int64_t n, hipStream_t s);
-void lz_alpha(int i, LzState* st, const double* part, int64_t np, const LzArrays& a, hipStream_t s);
+void lz_start(LzState* st, const double* r2part, int64_t nb, const double* b2part, double* beta, const Launch& L);
+void lz_first_vector(bool fp32, const LzState* st, const void* r, void* v, int64_t n, const Launch& L);
+void lz_alpha(int i, LzState* st, const double* part, int64_t np, const LzArrays& a, const Launch& L);
 void lz_update(bool fp32, int i, const LzState* st, const LzArrays& a, void* f, const void* v, const void* wprev, void* wout,
-               double* x1, double* f2part, int64_t n, hipStream_t s);
-void lz_beta(int i, LzState* st, const double* part, int64_t np, const LzArrays& a, hipStream_t s);
-void lz_next(bool fp32, int i, const LzState* st, const double* beta, const void* f, void* vn, int64_t n, hipStream_t s);
+               double* x1, double* f2part, int64_t n, const Launch& L);
+void lz_beta(int i, LzState* st, const double* part, int64_t np, const LzArrays& a, const Launch& L);
+void lz_next(bool fp32, int i, const LzState* st, const double* beta, const void* f, void* vn, int64_t n, const Launch& L);
 
 void seed_eta(int i0, int nb, int nr, const LzState* st, const double* gam, const double* P, double* E, double* eta_prev,
-              int32_t* nvalid, hipStream_t s);
+              int32_t* nvalid, const Launch& L);
 void seed_update(bool w32, bool x32, const void* W, int nw, const double* E, void* X, int nx, int64_t n, const int32_t* nrow_dev,
-                 hipStream_t s);
+                 const Launch& L);
 
 void reorth_update(bool fp32, int i, int pass, const LzState* st, const void* V, int64_t n, const double* G, void* v, void* f,
-                   double* part, hipStream_t s);
-void reorth_scalar(int i, int pass, LzState* st, const double* part, int64_t nb, const double* G, hipStream_t s);
-void reorth_finish(bool fp32, int i, int pass, const LzState* st, void* v, void* f, double* f2part, int64_t n, hipStream_t s);
-void reorth_decide(int i, int pass, LzState* st, const double* f2b, const double* f2a, int64_t nb, hipStream_t s);
+                   double* part, const Launch& L);
+void reorth_scalar(int i, int pass, LzState* st, const double* part, int64_t nb, const double* G, const Launch& L);
+void reorth_finish(bool fp32, int i, int pass, const LzState* st, void* v, void* f, double* f2part, int64_t n, const Launch& L);
+void reorth_decide(int i, int pass, LzState* st, const double* f2b, const double* f2a, int64_t nb, const Launch& L);
 
-void cg_alpha(CgVec* cg, const double* part, int64_t nb, const int32_t* vec_map, int nact, hipStream_t s, bool pc = false);
+void cg_alpha(CgVec* cg, const double* part, int64_t nb, const int32_t* vec_map, int nact, const Launch& L, bool pc = false);
 void dot_map(bool fp32, const void* a, const void* b, int64_t n, const int32_t* vec_map, int nact, const CgVec* cg, double* part,
-             hipStream_t s);
+             const Launch& L);
 void cg_beta_pc(CgVec* cg, const double* rrpart, const double* rzpart, int64_t nb, const int32_t* vec_map, int nact, int max_iter,
-                hipStream_t s);
+                const Launch& L);
 void cg_update(bool fp32, bool x32, const CgVec* cg, const int32_t* vec_map, int nact, void* X, const void* P, void* R,
-               const void* Q, double* part, int64_t n, hipStream_t s);
-void cg_beta(CgVec* cg, const double* part, int64_t nb, const int32_t* vec_map, int nact, int max_iter, hipStream_t s);
+               const void* Q, double* part, int64_t n, const Launch& L);
+void cg_beta(CgVec* cg, const double* part, int64_t nb, const int32_t* vec_map, int nact, int max_iter, const Launch& L);
 void cg_p(bool fp32, const CgVec* cg, const int32_t* vec_map, int nact, void* P, const void* R, int64_t n, bool ignore_frozen,
-          hipStream_t s);
+          const Launch& L);
 
 // learned preconditioner K (learned.hip); fields are [vec][parity][12][Vh] complex FP32
 void k_layer(const Geom& g, const void* links32, const void* in, void* out, const void* W, bool dagger, const int32_t* vmap,

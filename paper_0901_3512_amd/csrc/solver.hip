@@ -12,6 +12,9 @@
 // The result is the paper's step 7 exactly, summed in another order.
 #include <algorithm>
 #include <chrono>
+#include <map>
+#include <mutex>
+#include <thread>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -47,19 +50,46 @@ struct OomError {
             throw HipError{std::string(#call) + ": " + hipGetErrorString(e_)};                      \
     } while (0)
 
+struct DBuf;
+// Sizing pass of a batch: while a plan is open on this thread, ensure() records the largest
+// request of every buffer instead of allocating.
+struct Plan {
+    std::vector<std::pair<DBuf*, size_t>> req;
+    void note(DBuf* b, size_t n) {
+        for (auto& r : req)
+            if (r.first == b) {
+                r.second = std::max(r.second, n);
+                return;
+            }
+        req.push_back({b, n});
+    }
+};
+thread_local Plan* g_plan = nullptr;
+
 struct DBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    bool view = false;  // a slice of a batch arena (configuration 0's copy), not owned
     DBuf() = default;
     DBuf(const DBuf&) = delete;
     DBuf& operator=(const DBuf&) = delete;
     ~DBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p && !view) (void)hipFree(p);
         p = nullptr;
         bytes = 0;
+        view = false;
     }
     void ensure(size_t nbytes) {
+        if (g_plan) {
+            g_plan->note(this, nbytes == 0 ? 256 : nbytes);
+            return;
+        }
+        if (view) {
+            if (nbytes > bytes) throw StateError{"batch buffer smaller than a request (" + std::to_string(nbytes) + " > " +
+                                                 std::to_string(bytes) + " bytes)"};
+            return;
+        }
         if (nbytes <= bytes && p) return;
         release();
         if (nbytes == 0) nbytes = 256;
@@ -92,6 +122,8 @@ struct seedcg_s {
     seedcg_params p;
     Geom g;
     hipStream_t s = nullptr;
+    bool own_stream = false;  // batch classes run on a stream of their own
+    int device = 0;
     std::string err;
     bool lo = false;        // FP32 inner vectors (mixed precision)
     Prec lo_prec = P64;     // precision of the inner stencil
@@ -100,6 +132,26 @@ struct seedcg_s {
     int vb64 = 1, vb_lo = 1;      // vectors per stencil workgroup
     int sync_every = 16;
     int debug = 0;
+    // stencil launch shapes for several vectors per launch (the CG phase); the single-vector
+    // ones above serve the Lanczos steps
+    int tps64_multi = 3, tps_lo_multi = 3;
+    int vb64_multi = 1, vb_lo_multi = 1;
+    bool tuned = false;
+    // batch of same-shape configurations: buffers of configuration c at c * cs bytes from
+    // configuration 0's, launches over grid.z = ncfg
+    int ncfg = 1;
+    int64_t cs = 0;
+    DBuf arena;
+    std::vector<double> kappas;      // per configuration
+    DBuf kap2;                       // kappa^2 per configuration (device)
+    DBuf stage;                      // compact staging array, ncfg x (largest per-config record)
+    DBuf tabs;                       // per-configuration canonical B / X pointers (device)
+    DBuf r64, tmap, rmap;            // FP64 start residuals; vector maps of checks and restarts
+    // one CG iteration as a hipGraph per active-set width (not used while timing launches)
+    bool use_graphs = true;
+    hipStream_t cap_stream = nullptr;
+    std::map<int, hipGraphExec_t> cg_graphs;
+    Launch L() const { return Launch(s, ncfg, cs); }
 
     DBuf links64, links_lo;
     // operator work vectors (FP64), sized for a batch
@@ -130,6 +182,13 @@ struct seedcg_s {
     ~seedcg_s() {
         for (auto e : ev0) (void)hipEventDestroy(e);
         for (auto e : ev1) (void)hipEventDestroy(e);
+        drop_graphs();
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        if (own_stream && s) (void)hipStreamDestroy(s);
+    }
+    void drop_graphs() {
+        for (auto& kv : cg_graphs) (void)hipGraphExecDestroy(kv.second);
+        cg_graphs.clear();
     }
 
     int64_t vec_bytes(bool low) const { return N * (low ? 8 : 16); }
@@ -141,6 +200,18 @@ struct seedcg_s {
 };
 
 static std::string g_create_error;
+
+// A batch: one strided handle per lattice shape ("class"), each with its own stream.
+struct seedcg_batch_s {
+    std::vector<seedcg_s*> cls;
+    std::vector<std::vector<int>> members;   // class -> configurations
+    int ncfg = 0, nrhs = 0;
+    hipStream_t user_stream = nullptr;
+    std::string err;
+    ~seedcg_batch_s() {
+        for (auto h : cls) delete h;
+    }
+};
 
 // ---------------------------------------------------------------------------------------------
 // the operator
@@ -164,15 +235,15 @@ void ensure_work(seedcg_s* h, int nvec) {
 // its algorithmic bytes are recorded: links 144 reals per output site (read once for the whole
 // batch), and per vector the input and output spinors (24 reals each per site) plus every
 // epilogue operand (24 reals per site each).
-void hop(seedcg_s* h, Prec pr, const void* L, const void* in, void* out, int par, int nvec, const HopEpi& e, int tps) {
+void hop(seedcg_s* h, Prec pr, const void* L, const void* in, void* out, int par, int nvec, const HopEpi& e, int tps, int vb) {
     const bool sample = h->timing_every > 0 && (h->hop_count++ % h->timing_every) == 0 && h->ev_used < h->ev0.size();
     if (sample) HIPCHK(hipEventRecord(h->ev0[h->ev_used], h->s));
-    launch_hop(pr, h->g, L, in, out, par, nvec, e, tps, pr == P64 ? h->vb64 : h->vb_lo, h->s);
+    launch_hop(pr, h->g, L, in, out, par, nvec, e, tps, vb, h->L());
     if (sample) {
         HIPCHK(hipEventRecord(h->ev1[h->ev_used], h->s));
         const double sl = pr == P64 ? 8.0 : (pr == P32 ? 4.0 : 2.0);
         const double ss = pr == P64 ? 8.0 : 4.0;
-        const double Vh = (double)h->g.Vh;
+        const double Vh = (double)h->g.Vh * h->ncfg;
         int ops = 2 + (e.combine ? 1 : 0) + (e.z ? 1 : 0) + (e.red == 1 ? 1 : 0);
         h->ev_bytes.push_back(Vh * 144.0 * sl + (double)nvec * Vh * 24.0 * ss * ops);
         h->ev_flops.push_back((double)nvec * Vh * 1320.0);
@@ -203,25 +274,28 @@ void apply_M_int(seedcg_s* h, bool low, const void* x, void* out, int nvec, cons
     const void* L = low ? h->links_lo.p : h->links64.p;
     void* t1 = low ? h->t1_lo.p : h->t1_64.p;
     void* u = low ? h->u_lo.p : h->u_64.p;
-    const int tps = low ? h->tps_lo : h->tps64;
+    const bool multi = nvec > 1;
+    const int tps = low ? (multi ? h->tps_lo_multi : h->tps_lo) : (multi ? h->tps64_multi : h->tps64);
+    const int vb = low ? (multi ? h->vb_lo_multi : h->vb_lo) : (multi ? h->vb64_multi : h->vb64);
     const double k2 = h->p.kappa * h->p.kappa;
     HopEpi e{};
+    e.kappa2_dev = h->kap2.p ? h->kap2.as<double>() : nullptr;  // batch classes: kappa per configuration
     e.gate_m = o.gate_m;
     e.gate_i = o.gate_i;
     e.vec_map = o.vec_map;
     e.cg = o.cg;
     e.sy = 1.0;
     // t1 = H_oe x
-    hop(h, pr, L, x, t1, 1, nvec, e, tps);
+    hop(h, pr, L, x, t1, 1, nvec, e, tps, vb);
     // u = gamma5 (x - kappa^2 H_eo t1)
     HopEpi e2 = e;
     e2.combine = 1;
     e2.apply_g5 = 1;
     e2.kappa2 = k2;
     e2.x = x;
-    hop(h, pr, L, t1, u, 0, nvec, e2, tps);
+    hop(h, pr, L, t1, u, 0, nvec, e2, tps, vb);
     // t1 = H_oe u
-    hop(h, pr, L, u, t1, 1, nvec, e, tps);
+    hop(h, pr, L, u, t1, 1, nvec, e, tps, vb);
     // out = sy * gamma5 (u - kappa^2 H_eo t1) + cz z
     HopEpi e4 = e2;
     e4.x = u;
@@ -233,7 +307,7 @@ void apply_M_int(seedcg_s* h, bool low, const void* x, void* out, int nvec, cons
     e4.red = o.red;
     e4.d = o.d;
     e4.partials = o.partials;
-    hop(h, pr, L, t1, out, 0, nvec, e4, tps);
+    hop(h, pr, L, t1, out, 0, nvec, e4, tps, vb);
 }
 
 // y = A x or A^dag x = gamma5 A gamma5 x (FP64)
@@ -242,23 +316,65 @@ void apply_A_int(seedcg_s* h, const void* x, void* out, int nvec, bool dagger) {
     const double k2 = h->p.kappa * h->p.kappa;
     const void* in = x;
     if (dagger) {  // A^dag = gamma5 A gamma5: the last gamma5 is the hop epilogue's
-        gamma5_copy(false, x, h->g5buf.p, h->g.Vh, nvec, h->s);
+        gamma5_copy(false, x, h->g5buf.p, h->g.Vh, nvec, h->L());
         in = h->g5buf.p;
     }
     HopEpi e{};
     e.sy = 1.0;
-    launch_hop(P64, h->g, h->links64.p, in, h->t1_64.p, 1, nvec, e, h->tps64, h->vb64, h->s);
+    e.kappa2_dev = h->kap2.p ? h->kap2.as<double>() : nullptr;
+    launch_hop(P64, h->g, h->links64.p, in, h->t1_64.p, 1, nvec, e, h->tps64, h->vb64, h->L());
     HopEpi e2 = e;
     e2.combine = 1;
     e2.apply_g5 = dagger ? 1 : 0;
     e2.kappa2 = k2;
     e2.x = in;
-    launch_hop(P64, h->g, h->links64.p, h->t1_64.p, out, 0, nvec, e2, h->tps64, h->vb64, h->s);
+    launch_hop(P64, h->g, h->links64.p, h->t1_64.p, out, 0, nvec, e2, h->tps64, h->vb64, h->L());
 }
 
 void check_launch() { HIPCHK(hipGetLastError()); }
 
-int64_t nsb_of(seedcg_s* h, bool low) { return hop_site_blocks(h->g, low ? h->tps_lo : h->tps64); }
+// site blocks of the stencil launch that apply_M_int makes for nvec vectors (its reduction
+// partials come one per site block), and the largest over every launch shape (allocation)
+int64_t nsb_for(seedcg_s* h, bool low, int nvec) {
+    const bool multi = nvec > 1;
+    return hop_site_blocks(h->g, low ? (multi ? h->tps_lo_multi : h->tps_lo) : (multi ? h->tps64_multi : h->tps64));
+}
+int64_t nsb_of(seedcg_s* h, bool) { return hop_site_blocks(h->g, 4); }
+
+// host[c * bytes .. ] -> dev (configuration c's copy), for every configuration
+void to_cfg(seedcg_s* h, void* dev, const void* host, size_t bytes) {
+    if (h->ncfg == 1) {
+        HIPCHK(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, h->s));
+        return;
+    }
+    HIPCHK(hipMemcpyAsync(h->stage.p, host, bytes * h->ncfg, hipMemcpyHostToDevice, h->s));
+    cfg_copy(h->stage.p, (int64_t)bytes, dev, h->cs, (int64_t)bytes, h->L());
+}
+// dev (every configuration's copy) -> host[c * bytes ..]; the caller synchronises
+void from_cfg(seedcg_s* h, void* host, const void* dev, size_t bytes) {
+    if (h->ncfg == 1) {
+        HIPCHK(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, h->s));
+        return;
+    }
+    cfg_copy(dev, h->cs, h->stage.p, (int64_t)bytes, (int64_t)bytes, h->L());
+    HIPCHK(hipMemcpyAsync(host, h->stage.p, bytes * h->ncfg, hipMemcpyDeviceToHost, h->s));
+}
+void copy_cfg(seedcg_s* h, void* dst, const void* src, size_t bytes) { cfg_copy(src, h->cs, dst, h->cs, (int64_t)bytes, h->L()); }
+void zero_cfg(seedcg_s* h, void* dst, size_t bytes) { cfg_zero(dst, (int64_t)bytes, h->L()); }
+
+// per-configuration lists of vector indices -> a padded [ncfg][width] map on the device (-1 = none);
+// returns the width (0 when every list is empty)
+int upload_map(seedcg_s* h, DBuf& map, const std::vector<std::vector<int>>& lists) {
+    int w = 0;
+    for (const auto& l : lists) w = std::max<int>(w, (int)l.size());
+    if (w == 0) return 0;
+    std::vector<int32_t> m((size_t)h->ncfg * w, -1);
+    for (int c = 0; c < h->ncfg; c++)
+        for (size_t k = 0; k < lists[c].size(); k++) m[(size_t)c * w + k] = lists[c][k];
+    map.ensure(w * sizeof(int32_t));
+    to_cfg(h, map.p, m.data(), w * sizeof(int32_t));
+    return w;
+}
 
 }  // namespace
 
@@ -306,6 +422,7 @@ void alloc_seed(seedcg_s* h, int nrhs) {
     h->E.ensure(2 * 32 * 24 * sizeof(double));
     h->etaprev.ensure(2 * 24 * sizeof(double));
     h->nvalid.ensure(sizeof(int32_t));
+    h->r64.ensure(nrhs * h->vec_bytes(false));
     ensure_work(h, nrhs);
 
     // basis capacity: params.m_max, or what fits in free HBM (at most 8192 vectors)
@@ -348,11 +465,11 @@ void flush_seed_block(seedcg_s* h, int i0, int i1, int nrhs) {
     a.gate_i = i0;
     a.rows_from_m = 1;
     a.i0 = i0;
-    project(lo, a, 1, h->P.as<double>(), h->s);
+    project(lo, a, 1, h->P.as<double>(), h->L());
     seed_eta(i0, nb, nr, h->st.as<LzState>(), h->arr().gam, h->P.as<double>(), h->E.as<double>(), h->etaprev.as<double>(),
-             h->nvalid.as<int32_t>(), h->s);
+             h->nvalid.as<int32_t>(), h->L());
     seed_update(lo, false, h->wring.p, nb, h->E.as<double>(), (char*)h->Xint.p + h->vec_bytes(false), nr, N,
-                h->nvalid.as<int32_t>(), h->s);
+                h->nvalid.as<int32_t>(), h->L());
 }
 
 void reorthogonalise(seedcg_s* h, int i) {
@@ -377,68 +494,95 @@ void reorthogonalise(seedcg_s* h, int i) {
         a.gate_i = i;
         a.flag = pass == 2 ? &st->rep_any : nullptr;
         // the reorthogonalisation coefficients are always accumulated in FP64
-        project(lo, a, (i + 31) / 32, h->G.as<double>(), h->s, true);
-        reorth_update(lo, i, pass, st, h->basis.p, N, h->G.as<double>(), vi, h->f.p, h->rpart.as<double>(), h->s);
-        reorth_scalar(i, pass, st, h->rpart.as<double>(), nb, h->G.as<double>(), h->s);
-        reorth_finish(lo, i, pass, st, vi, h->f.p, h->f2b.as<double>(), N, h->s);
-        reorth_decide(i, pass, st, h->f2a.as<double>(), h->f2b.as<double>(), nb, h->s);
+        project(lo, a, (i + 31) / 32, h->G.as<double>(), h->L(), true);
+        reorth_update(lo, i, pass, st, h->basis.p, N, h->G.as<double>(), vi, h->f.p, h->rpart.as<double>(), h->L());
+        reorth_scalar(i, pass, st, h->rpart.as<double>(), nb, h->G.as<double>(), h->L());
+        reorth_finish(lo, i, pass, st, vi, h->f.p, h->f2b.as<double>(), N, h->L());
+        reorth_decide(i, pass, st, h->f2a.as<double>(), h->f2b.as<double>(), nb, h->L());
     }
 }
 
-void solve_seed_impl(seedcg_s* h, const double* B, double* X, int nrhs, seedcg_report* rep) {
-    if (!B || !X || nrhs < 1) throw ArgError{"solve_seed: null pointer or nrhs < 1"};
+// Caller vectors in the canonical layout: one array for a single configuration, or a device table
+// of one pointer per configuration for a batch.
+struct Io {
+    const double* B = nullptr;
+    double* X = nullptr;
+    const double* const* Btab = nullptr;
+    double* const* Xtab = nullptr;
+};
+void pack_in(seedcg_s* h, const Io& io, bool x, void* dst, int nrhs) {
+    if (h->ncfg > 1)
+        pack_vec(false, nullptr, dst, h->g.Vh, nrhs, h->L(), x ? (const double* const*)io.Xtab : io.Btab);
+    else
+        pack_vec(false, x ? io.X : io.B, dst, h->g.Vh, nrhs, h->L());
+}
+void unpack_out(seedcg_s* h, const Io& io, const void* src, int nrhs) {
+    if (h->ncfg > 1)
+        unpack_vec(false, src, nullptr, h->g.Vh, nrhs, h->L(), io.Xtab);
+    else
+        unpack_vec(false, src, io.X, h->g.Vh, nrhs, h->L());
+}
+
+// rep: one report per configuration
+void solve_seed_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report* rep) {
+    if (nrhs < 1) throw ArgError{"solve_seed: nrhs < 1"};
     if (nrhs > 25) throw ArgError{"solve_seed: at most 25 right-hand sides (24 seeded)"};
     const double t0 = now_s();
     const bool lo = h->lo;
-    const int64_t N = h->N, Vh = h->g.Vh;
+    const int64_t N = h->N;
+    const int C = h->ncfg;
+    const Launch L = h->L();
     alloc_seed(h, nrhs);
     LzState* st = h->st.as<LzState>();
     const LzArrays A = h->arr();
     const int nr = nrhs - 1;
 
-    pack_vec(false, B, h->Bint.p, Vh, nrhs, h->s);
-    pack_vec(false, X, h->Xint.p, Vh, nrhs, h->s);
+    pack_in(h, io, false, h->Bint.p, nrhs);
+    pack_in(h, io, true, h->Xint.p, nrhs);
     // Step 1: r_0^j = b^j - M x_0^j (FP64), kept in the inner precision for the projections;
     // RHS 1's goes straight to v_1 after scaling.
-    DBuf r64;
-    r64.ensure(nrhs * h->vec_bytes(false));
+    h->r64.ensure(nrhs * h->vec_bytes(false));
     {
         MOpts o;
         o.sy = -1.0;
         o.z = h->Bint.p;
         o.cz_host = 1.0;
-        apply_M_int(h, false, h->Xint.p, r64.p, nrhs, o);
+        apply_M_int(h, false, h->Xint.p, h->r64.p, nrhs, o);
     }
-    if (nr > 0) convert(false, lo, (char*)r64.p + h->vec_bytes(false), h->R0.p, nr * N, h->s);
-    HIPCHK(hipMemcpyAsync(h->x1.p, h->Xint.p, h->vec_bytes(false), hipMemcpyDeviceToDevice, h->s));
-    HIPCHK(hipMemsetAsync(h->etaprev.p, 0, 2 * 24 * sizeof(double), h->s));
-    HIPCHK(hipMemsetAsync(h->arrays.p, 0, h->arrays.bytes, h->s));
+    if (nr > 0) convert(false, lo, (char*)h->r64.p + h->vec_bytes(false), h->R0.p, nr * N, L);
+    copy_cfg(h, h->x1.p, h->Xint.p, h->vec_bytes(false));
+    zero_cfg(h, h->etaprev.p, 2 * 24 * sizeof(double));
+    zero_cfg(h, h->arrays.p, 6 * ((int64_t)h->m_cap + 2) * sizeof(double));
 
-    LzState hs{};
-    hs.m = h->m_cap;
-    hs.m_cap = h->m_cap;
-    hs.tol = h->p.tol;
-    hs.past = h->p.past_factor;
-    HIPCHK(hipMemcpyAsync(st, &hs, sizeof(hs), hipMemcpyHostToDevice, h->s));
+    std::vector<LzState> hs(C);
+    for (auto& x : hs) {
+        x = LzState{};
+        x.m = h->m_cap;
+        x.m_cap = h->m_cap;
+        x.tol = h->p.tol;
+        x.past = h->p.past_factor;
+    }
+    to_cfg(h, st, hs.data(), sizeof(LzState));
     // Step 2: beta_0 = ||r_0^1||, v_1 = r_0^1 / beta_0
     const int64_t nb = norm2_blocks(N);
-    norm2_partials(false, r64.p, N, 1, h->f2a.as<double>(), h->s);
-    norm2_partials(false, h->Bint.p, N, 1, h->f2a.as<double>() + nb, h->s);
-    lz_start(st, h->f2a.as<double>(), nb, h->f2a.as<double>() + nb, A.beta, h->s);
+    norm2_partials(false, h->r64.p, N, 1, h->f2a.as<double>(), L);
+    norm2_partials(false, h->Bint.p, N, 1, h->f2a.as<double>() + nb, L);
+    lz_start(st, h->f2a.as<double>(), nb, h->f2a.as<double>() + nb, A.beta, L);
     if (lo) {
-        convert(false, true, r64.p, h->f.p, N, h->s);
-        lz_first_vector(true, st, h->f.p, h->basis.p, N, h->s);
+        convert(false, true, h->r64.p, h->f.p, N, L);
+        lz_first_vector(true, st, h->f.p, h->basis.p, N, L);
     } else {
-        lz_first_vector(false, st, r64.p, h->basis.p, N, h->s);
+        lz_first_vector(false, st, h->r64.p, h->basis.p, N, L);
     }
     check_launch();
 
     const int b = seed_block_of(h);
     const int k = h->p.reorth_k;
-    const int64_t nsb = nsb_of(h, lo);
+    const int64_t nsb = nsb_for(h, lo, 1);
     int i0 = 1;          // first step of the pending seeding block
     int last_slot = 0;   // ring slot of w_{i-1}
     int i = 1;
+    int m_max = 0;       // largest m over the configurations
     bool finished = false;
     while (!finished) {
         const int i_end = std::min<int>(h->m_cap, i + h->sync_every - 1);
@@ -457,11 +601,11 @@ void solve_seed_impl(seedcg_s* h, const double* B, double* X, int nrhs, seedcg_r
             o.gate_i = i;
             apply_M_int(h, lo, vi, h->f.p, 1, o);
             // Step 6: LU scalars; f -= alpha_i v_i; w_i; x^1 += zeta_i w_i
-            lz_alpha(i, st, h->apart.as<double>(), nsb, A, h->s);
+            lz_alpha(i, st, h->apart.as<double>(), nsb, A, L);
             const int slot = i - i0;
             void* wout = (char*)h->wring.p + (int64_t)slot * h->vec_bytes(lo);
             const void* wprev = (const char*)h->wring.p + (int64_t)(slot > 0 ? slot - 1 : last_slot) * h->vec_bytes(lo);
-            lz_update(lo, i, st, A, h->f.p, vi, wprev, wout, h->x1.as<double>(), h->f2a.as<double>(), N, h->s);
+            lz_update(lo, i, st, A, h->f.p, vi, wprev, wout, h->x1.as<double>(), h->f2a.as<double>(), N, L);
             // Step 7, blocked (before step 8 can touch v_i)
             const bool reorth_now = k > 0 && i % k == 0;
             if (slot + 1 == b || reorth_now) {
@@ -472,33 +616,40 @@ void solve_seed_impl(seedcg_s* h, const double* B, double* X, int nrhs, seedcg_r
             // Step 8
             if (reorth_now) reorthogonalise(h, i);
             // Step 9
-            lz_beta(i, st, reorth_now ? h->f2b.as<double>() : h->f2a.as<double>(), nb, A, h->s);
-            lz_next(lo, i, st, A.beta, h->f.p, (char*)h->basis.p + (int64_t)i * h->vec_bytes(lo), N, h->s);
+            lz_beta(i, st, reorth_now ? h->f2b.as<double>() : h->f2a.as<double>(), nb, A, L);
+            lz_next(lo, i, st, A.beta, h->f.p, (char*)h->basis.p + (int64_t)i * h->vec_bytes(lo), N, L);
         }
         check_launch();
-        HIPCHK(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, h->s));
+        from_cfg(h, hs.data(), st, sizeof(LzState));
         HIPCHK(hipStreamSynchronize(h->s));
-        if (hs.done || i > h->m_cap) finished = true;
+        bool all_done = true;
+        for (const auto& x : hs) all_done = all_done && x.done;
+        if (all_done || i > h->m_cap) finished = true;
     }
-    // the last (partial) seeding block
-    if (i0 <= hs.m) flush_seed_block(h, i0, std::min(hs.m, i - 1), nrhs);
-    HIPCHK(hipMemcpyAsync(h->Xint.p, h->x1.p, h->vec_bytes(false), hipMemcpyDeviceToDevice, h->s));
-    unpack_vec(false, h->Xint.p, X, Vh, nrhs, h->s);
+    for (const auto& x : hs) m_max = std::max(m_max, (int)x.m);
+    // the last (partial) seeding block; configurations that stopped earlier get no rows from it
+    if (i0 <= m_max) flush_seed_block(h, i0, std::min(m_max, i - 1), nrhs);
+    copy_cfg(h, h->Xint.p, h->x1.p, h->vec_bytes(false));
+    unpack_out(h, io, h->Xint.p, nrhs);
     check_launch();
-    HIPCHK(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, h->s));
+    from_cfg(h, hs.data(), st, sizeof(LzState));
     HIPCHK(hipStreamSynchronize(h->s));
-    h->m_used = hs.m;
+    h->m_used = m_max;
     h->have_seed = true;
     h->seed_nrhs = nrhs;
     if (rep) {
-        rep->m_used = hs.m;
-        rep->i_conv = hs.i_conv;
-        rep->seed_status = hs.status;
-        rep->reorth_passes = hs.passes;
-        rep->t_seed_s = now_s() - t0;
-        if (rep->iters) rep->iters[0] = hs.m;
-        if (rep->matvecs)
-            for (int j = 0; j < nrhs; j++) rep->matvecs[j] = (j == 0 ? hs.m : 0) + 1;
+        const double t = now_s() - t0;
+        for (int c = 0; c < C; c++) {
+            seedcg_report& r = rep[c];
+            r.m_used = hs[c].m;
+            r.i_conv = hs[c].i_conv;
+            r.seed_status = hs[c].status;
+            r.reorth_passes = hs[c].passes;
+            r.t_seed_s = t;
+            if (r.iters) r.iters[0] = hs[c].m;
+            if (r.matvecs)
+                for (int j = 0; j < nrhs; j++) r.matvecs[j] = (j == 0 ? hs[c].m : 0) + 1;
+        }
     }
 }
 
@@ -756,28 +907,24 @@ void train_precond_impl(seedcg_s* h, int steps, int n_ritz, int n_lanczos, doubl
 // ---------------------------------------------------------------------------------------------
 // plain CG on a batch (FP64, or FP32 inner iterations with FP64 reliable updates)
 // ---------------------------------------------------------------------------------------------
-void true_residual(seedcg_s* h, const std::vector<int>& vecs, void* R64, double* part) {
-    if (vecs.empty()) return;
-    std::vector<int32_t> vm(vecs.begin(), vecs.end());
-    DBuf dmap;
-    dmap.ensure(vm.size() * sizeof(int32_t));
-    HIPCHK(hipMemcpyAsync(dmap.p, vm.data(), vm.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->s));
+// r = b - M x (FP64) and its |r|^2 partials for the listed vectors of every configuration
+// Returns the number of |r|^2 partials per vector (0 when nothing was listed).
+int64_t true_residual(seedcg_s* h, const std::vector<std::vector<int>>& vecs, void* R64, double* part) {
+    const int w = upload_map(h, h->tmap, vecs);
+    if (w == 0) return 0;
     MOpts o;
     o.sy = -1.0;
     o.z = h->Bint.p;
     o.cz_host = 1.0;
     o.red = 2;
     o.partials = part;
-    o.vec_map = dmap.as<int32_t>();
-    apply_M_int(h, false, h->Xint.p, R64, (int)vm.size(), o);
-    HIPCHK(hipStreamSynchronize(h->s));  // dmap must outlive the kernels
+    o.vec_map = h->tmap.as<int32_t>();
+    apply_M_int(h, false, h->Xint.p, R64, w, o);
+    return nsb_for(h, false, w);
 }
 
-seedcg_status solve_rest_impl(seedcg_s* h, const double* B, double* X, int nrhs, seedcg_report* rep) {
-    if (!B || !X || nrhs < 1) throw ArgError{"solve_rest: null pointer or nrhs < 1"};
-    const double t0 = now_s();
+void alloc_rest(seedcg_s* h, int nrhs) {
     const bool lo = h->lo;
-    const int64_t N = h->N, Vh = h->g.Vh;
     h->Bint.ensure(nrhs * h->vec_bytes(false));
     h->Xint.ensure(nrhs * h->vec_bytes(false));
     h->R64.ensure(nrhs * h->vec_bytes(false));
@@ -786,54 +933,131 @@ seedcg_status solve_rest_impl(seedcg_s* h, const double* B, double* X, int nrhs,
     if (lo) h->Rv.ensure(nrhs * h->vec_bytes(true));
     h->cgv.ensure(nrhs * sizeof(CgVec));
     h->vmap.ensure(nrhs * sizeof(int32_t));
-    const int64_t nsb64 = nsb_of(h, false), nsbl = nsb_of(h, lo), nb = norm2_blocks(N);
+    h->tmap.ensure(nrhs * sizeof(int32_t));
+    h->rmap.ensure(nrhs * sizeof(int32_t));
+    const int64_t nsb64 = nsb_of(h, false), nsbl = nsb_of(h, lo), nb = norm2_blocks(h->N);
     h->cgpart.ensure(nrhs * std::max(nsb64, nsbl) * sizeof(double));
     h->rrpart.ensure(nrhs * std::max(nb, nsb64) * sizeof(double));
     h->norms.ensure(2 * nrhs * sizeof(double));
     ensure_work(h, nrhs);
-    void* Rw = lo ? h->Rv.p : h->R64.p;  // the recursive residual
+}
 
-    pack_vec(false, B, h->Bint.p, Vh, nrhs, h->s);
-    pack_vec(false, X, h->Xint.p, Vh, nrhs, h->s);
-    // ||b_j|| and the true residuals of the starting guesses
-    norm2_partials(false, h->Bint.p, N, nrhs, h->rrpart.as<double>(), h->s);
-    sum_partials(h->rrpart.as<double>(), nb, nrhs, h->norms.as<double>(), true, h->s);
-    std::vector<int> all(nrhs);
-    for (int j = 0; j < nrhs; j++) all[j] = j;
-    true_residual(h, all, h->R64.p, h->cgpart.as<double>());
-    sum_partials(h->cgpart.as<double>(), nsb64, nrhs, h->norms.as<double>() + nrhs, false, h->s);
-    std::vector<double> hn(2 * nrhs);
-    HIPCHK(hipMemcpyAsync(hn.data(), h->norms.p, 2 * nrhs * sizeof(double), hipMemcpyDeviceToHost, h->s));
-    HIPCHK(hipStreamSynchronize(h->s));
-
-    std::vector<CgVec> cg(nrhs);
-    std::vector<int> matvecs(nrhs, 1);
-    const double tol = h->p.tol;
-    for (int j = 0; j < nrhs; j++) {
-        CgVec& c = cg[j];
-        c = CgVec{};
-        c.bnorm = hn[j];
-        c.tol = tol;
-        c.rr = hn[nrhs + j];
-        c.done = (std::sqrt(c.rr) <= tol * c.bnorm) ? 1 : 0;
+// One iteration of (preconditioned) CG on the nact vectors of the device map vmap.
+void cg_iteration(seedcg_s* h, bool lo, bool pc, int nact, int nalloc, int64_t nb, int max_iter, void* Rw) {
+    const Launch L = h->L();
+    const int64_t nsbl = nsb_for(h, lo, nact);
+    MOpts o;
+    o.red = 1;
+    o.d = h->Pv.p;
+    o.partials = h->cgpart.as<double>();
+    o.vec_map = h->vmap.as<int32_t>();
+    o.cg = h->cgv.as<CgVec>();
+    apply_M_int(h, lo, h->Pv.p, h->Qv.p, nact, o);
+    cg_alpha(h->cgv.as<CgVec>(), h->cgpart.as<double>(), nsbl, h->vmap.as<int32_t>(), nact, L, pc);
+    cg_update(lo, false, h->cgv.as<CgVec>(), h->vmap.as<int32_t>(), nact, h->Xint.p, h->Pv.p, Rw, h->Qv.p, h->rrpart.as<double>(),
+              h->N, L);
+    if (pc) {
+        apply_P(h, lo, Rw, h->Zv.p, h->vmap.as<int32_t>(), nact, nalloc);
+        dot_map(lo, Rw, h->Zv.p, h->N, h->vmap.as<int32_t>(), nact, h->cgv.as<CgVec>(), h->rzpart.as<double>(), L);
+        cg_beta_pc(h->cgv.as<CgVec>(), h->rrpart.as<double>(), h->rzpart.as<double>(), nb, h->vmap.as<int32_t>(), nact, max_iter, L);
+        cg_p(lo, h->cgv.as<CgVec>(), h->vmap.as<int32_t>(), nact, h->Pv.p, h->Zv.p, h->N, false, L);
+    } else {
+        cg_beta(h->cgv.as<CgVec>(), h->rrpart.as<double>(), nb, h->vmap.as<int32_t>(), nact, max_iter, L);
+        cg_p(lo, h->cgv.as<CgVec>(), h->vmap.as<int32_t>(), nact, h->Pv.p, Rw, h->N, false, L);
     }
-    if (lo) convert(false, true, h->R64.p, h->Rv.p, nrhs * N, h->s);
+}
+
+// The iteration above captured once per active-set width (on a private stream) and replayed on
+// the handle's stream: every argument is a fixed device address, the changing active set is
+// read from vmap and the scalars from the CgVec records.  It holds kernel nodes only.
+hipGraphExec_t cg_graph(seedcg_s* h, bool lo, int nact, int nalloc, int64_t nb, int max_iter, void* Rw) {
+    auto it = h->cg_graphs.find(nact);
+    if (it != h->cg_graphs.end()) return it->second;
+    if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    const hipStream_t saved = h->s;
+    h->s = h->cap_stream;
+    hipError_t eb = hipStreamBeginCapture(h->s, hipStreamCaptureModeThreadLocal);
+    if (eb != hipSuccess) {
+        h->s = saved;
+        HIPCHK(eb);
+    }
+    try {
+        cg_iteration(h, lo, false, nact, nalloc, nb, max_iter, Rw);
+    } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(h->s, &g);
+        if (g) (void)hipGraphDestroy(g);
+        h->s = saved;
+        throw;
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = hipStreamEndCapture(h->s, &graph);
+    h->s = saved;
+    HIPCHK(ee);
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIPCHK(ei);
+    h->cg_graphs[nact] = exec;
+    return exec;
+}
+
+// rep: one report per configuration
+seedcg_status solve_rest_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report* rep) {
+    if (nrhs < 1) throw ArgError{"solve_rest: nrhs < 1"};
+    const double t0 = now_s();
+    const bool lo = h->lo;
+    const int64_t N = h->N;
+    const int C = h->ncfg;
+    const Launch L = h->L();
+    alloc_rest(h, nrhs);
+    const int64_t nb = norm2_blocks(N);
+    void* Rw = lo ? h->Rv.p : h->R64.p;  // the recursive residual
+    // buffers may have moved since the graphs were captured
+    h->drop_graphs();
+
+    pack_in(h, io, false, h->Bint.p, nrhs);
+    pack_in(h, io, true, h->Xint.p, nrhs);
+    // ||b_j|| and the true residuals of the starting guesses
+    norm2_partials(false, h->Bint.p, N, nrhs, h->rrpart.as<double>(), L);
+    sum_partials(h->rrpart.as<double>(), nb, nrhs, h->norms.as<double>(), true, L);
+    std::vector<std::vector<int>> all(C);
+    for (int c = 0; c < C; c++)
+        for (int j = 0; j < nrhs; j++) all[c].push_back(j);
+    int64_t np = true_residual(h, all, h->R64.p, h->cgpart.as<double>());
+    sum_partials(h->cgpart.as<double>(), np, nrhs, h->norms.as<double>() + nrhs, false, L);
+    std::vector<double> hn((size_t)C * 2 * nrhs);   // [c][ ||b_j|| (nrhs), |r_j|^2 (nrhs) ]
+    from_cfg(h, hn.data(), h->norms.p, 2 * nrhs * sizeof(double));
+    HIPCHK(hipStreamSynchronize(h->s));
+    auto bn = [&](int c, int j) { return hn[(size_t)c * 2 * nrhs + j]; };
+    auto rr_of = [&](int c, int j) { return hn[(size_t)c * 2 * nrhs + nrhs + j]; };
+
+    std::vector<CgVec> cg((size_t)C * nrhs);
+    std::vector<int> matvecs((size_t)C * nrhs, 1);
+    const double tol = h->p.tol;
+    for (int c = 0; c < C; c++)
+        for (int j = 0; j < nrhs; j++) {
+            CgVec& x = cg[(size_t)c * nrhs + j];
+            x = CgVec{};
+            x.bnorm = bn(c, j);
+            x.tol = tol;
+            x.rr = rr_of(c, j);
+            x.done = (std::sqrt(x.rr) <= tol * x.bnorm) ? 1 : 0;
+        }
+    if (lo) convert(false, true, h->R64.p, h->Rv.p, nrhs * N, L);
     // preconditioned CG with the learned P = K K^dag when it has been trained and is asked for
-    const bool pc = h->p.precond == 1 && h->k_ready && h->k_accepted;
+    const bool pc = C == 1 && h->p.precond == 1 && h->k_ready && h->k_accepted;
     if (pc) {
         h->Zv.ensure(nrhs * h->vec_bytes(lo));
         h->rzpart.ensure(nrhs * nb * sizeof(double));
-    }
-    // z = P r and rz = Re r^dag z for the vectors in `vecs`; returns rz per vector
-    auto precondition = [&](const std::vector<int>& vecs) {
-        std::vector<int32_t> vm(vecs.begin(), vecs.end());
-        DBuf dm;
-        dm.ensure(vm.size() * sizeof(int32_t));
-        HIPCHK(hipMemcpyAsync(dm.p, vm.data(), vm.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->s));
-        apply_P(h, lo, Rw, h->Zv.p, dm.as<int32_t>(), (int)vm.size(), nrhs);
-        dot_map(lo, Rw, h->Zv.p, N, dm.as<int32_t>(), (int)vm.size(), nullptr, h->rzpart.as<double>(), h->s);
         h->respart.ensure(nrhs * sizeof(double));
-        sum_partials(h->rzpart.as<double>(), nb, nrhs, h->respart.as<double>(), false, h->s);
+    }
+    // z = P r and rz = Re r^dag z for the vectors in `vecs` (one configuration); returns rz per vector
+    auto precondition = [&](const std::vector<int>& vecs) {
+        const int w = upload_map(h, h->rmap, {vecs});
+        apply_P(h, lo, Rw, h->Zv.p, h->rmap.as<int32_t>(), w, nrhs);
+        dot_map(lo, Rw, h->Zv.p, N, h->rmap.as<int32_t>(), w, nullptr, h->rzpart.as<double>(), L);
+        sum_partials(h->rzpart.as<double>(), nb, nrhs, h->respart.as<double>(), false, L);
         std::vector<double> rz(nrhs);
         HIPCHK(hipMemcpyAsync(rz.data(), h->respart.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, h->s));
         HIPCHK(hipStreamSynchronize(h->s));
@@ -847,11 +1071,11 @@ seedcg_status solve_rest_impl(seedcg_s* h, const double* B, double* X, int nrhs,
             const std::vector<double> rz = precondition(live);
             for (int j : live) cg[j].rz = rz[j];
         }
-        convert(lo, lo, h->Zv.p, h->Pv.p, nrhs * N, h->s);  // p = z
+        convert(lo, lo, h->Zv.p, h->Pv.p, nrhs * N, L);  // p = z
     } else {
-        convert(lo, lo, Rw, h->Pv.p, nrhs * N, h->s);  // p = r
+        convert(lo, lo, Rw, h->Pv.p, nrhs * N, L);  // p = r
     }
-    HIPCHK(hipMemcpyAsync(h->cgv.p, cg.data(), nrhs * sizeof(CgVec), hipMemcpyHostToDevice, h->s));
+    to_cfg(h, h->cgv.p, cg.data(), nrhs * sizeof(CgVec));
 
     const int max_iter = h->p.max_iter > 0 ? h->p.max_iter : 100000;
     // Mixed precision: reliable updates (Sleijpen and van der Vorst) replace the FP32 recursive
@@ -861,138 +1085,299 @@ seedcg_status solve_rest_impl(seedcg_s* h, const double* B, double* X, int nrhs,
     // decades on its own.
     const int rel_every = lo ? std::max(1, h->p.reliable_every) : 0;
     const int G = lo ? std::min(h->sync_every, 4) : h->sync_every;
-    std::vector<int> it_rel(nrhs, 0);
-    for (int j = 0; j < nrhs; j++) cg[j].rr_reliable = cg[j].rr;
-    std::vector<int> active;
+    std::vector<int> it_rel((size_t)C * nrhs, 0);
+    for (auto& x : cg) x.rr_reliable = x.rr;
     bool noconv = false;
+    const bool graphs = h->use_graphs && h->timing_every == 0 && !pc;
     for (;;) {
-        active.clear();
-        for (int j = 0; j < nrhs; j++)
-            if (!cg[j].done) active.push_back(j);
-        if (active.empty()) break;
-        std::vector<int32_t> vm(active.begin(), active.end());
-        HIPCHK(hipMemcpyAsync(h->vmap.p, vm.data(), vm.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->s));
-        const int nact = (int)vm.size();
-        for (int it = 0; it < G; it++) {
-            MOpts o;
-            o.red = 1;
-            o.d = h->Pv.p;
-            o.partials = h->cgpart.as<double>();
-            o.vec_map = h->vmap.as<int32_t>();
-            o.cg = h->cgv.as<CgVec>();
-            apply_M_int(h, lo, h->Pv.p, h->Qv.p, nact, o);
-            cg_alpha(h->cgv.as<CgVec>(), h->cgpart.as<double>(), nsbl, h->vmap.as<int32_t>(), nact, h->s, pc);
-            cg_update(lo, false, h->cgv.as<CgVec>(), h->vmap.as<int32_t>(), nact, h->Xint.p, h->Pv.p, Rw, h->Qv.p,
-                      h->rrpart.as<double>(), N, h->s);
-            if (pc) {
-                apply_P(h, lo, Rw, h->Zv.p, h->vmap.as<int32_t>(), nact, nrhs);
-                dot_map(lo, Rw, h->Zv.p, N, h->vmap.as<int32_t>(), nact, h->cgv.as<CgVec>(), h->rzpart.as<double>(), h->s);
-                cg_beta_pc(h->cgv.as<CgVec>(), h->rrpart.as<double>(), h->rzpart.as<double>(), nb, h->vmap.as<int32_t>(), nact,
-                           max_iter, h->s);
-                cg_p(lo, h->cgv.as<CgVec>(), h->vmap.as<int32_t>(), nact, h->Pv.p, h->Zv.p, N, false, h->s);
-            } else {
-                cg_beta(h->cgv.as<CgVec>(), h->rrpart.as<double>(), nb, h->vmap.as<int32_t>(), nact, max_iter, h->s);
-                cg_p(lo, h->cgv.as<CgVec>(), h->vmap.as<int32_t>(), nact, h->Pv.p, Rw, N, false, h->s);
-            }
+        std::vector<std::vector<int>> active(C);
+        bool any = false;
+        for (int c = 0; c < C; c++)
+            for (int j = 0; j < nrhs; j++)
+                if (!cg[(size_t)c * nrhs + j].done) {
+                    active[c].push_back(j);
+                    any = true;
+                }
+        if (!any) break;
+        const int nact = upload_map(h, h->vmap, active);
+        if (graphs) {
+            const hipGraphExec_t ge = cg_graph(h, lo, nact, nrhs, nb, max_iter, Rw);
+            for (int it = 0; it < G; it++) HIPCHK(hipGraphLaunch(ge, h->s));
+        } else {
+            for (int it = 0; it < G; it++) cg_iteration(h, lo, pc, nact, nrhs, nb, max_iter, Rw);
         }
         check_launch();
-        HIPCHK(hipMemcpyAsync(cg.data(), h->cgv.p, nrhs * sizeof(CgVec), hipMemcpyDeviceToHost, h->s));
+        from_cfg(h, cg.data(), h->cgv.p, nrhs * sizeof(CgVec));
         HIPCHK(hipStreamSynchronize(h->s));
-        for (int j : active) matvecs[j] = 1 + cg[j].iters;
+        for (int c = 0; c < C; c++)
+            for (int j : active[c]) matvecs[(size_t)c * nrhs + j] = 1 + cg[(size_t)c * nrhs + j].iters;
         if (h->debug)
-            for (int j : active)
-                fprintf(stderr, "cg j=%d it=%d rr=%.3e a=%.3e b=%.3e pq=%.3e frozen=%d done=%d restarts=%d\n", j, cg[j].iters,
-                        cg[j].rr, cg[j].a, cg[j].b, cg[j].pq, cg[j].frozen, cg[j].done, cg[j].restarts);
+            for (int c = 0; c < C; c++)
+                for (int j : active[c]) {
+                    const CgVec& x = cg[(size_t)c * nrhs + j];
+                    fprintf(stderr, "cg c=%d j=%d it=%d rr=%.3e a=%.3e b=%.3e pq=%.3e frozen=%d done=%d restarts=%d\n", c, j, x.iters,
+                            x.rr, x.a, x.b, x.pq, x.frozen, x.done, x.restarts);
+                }
 
         // true residual for frozen vectors and, in mixed precision, the reliable updates
-        std::vector<int> check;
-        std::vector<char> is_rel(nrhs, 0);
-        for (int j : active) {
-            const bool rel = rel_every && !cg[j].frozen &&
-                             (cg[j].rr <= 1e-2 * cg[j].rr_reliable || cg[j].iters - it_rel[j] >= rel_every);
-            if (cg[j].frozen || rel) check.push_back(j);
-            is_rel[j] = rel;
-        }
-        if (check.empty()) continue;
-        true_residual(h, check, h->R64.p, h->cgpart.as<double>());
-        sum_partials(h->cgpart.as<double>(), nsb64, nrhs, h->norms.as<double>() + nrhs, false, h->s);
-        HIPCHK(hipMemcpyAsync(hn.data(), h->norms.p, 2 * nrhs * sizeof(double), hipMemcpyDeviceToHost, h->s));
+        std::vector<std::vector<int>> check(C);
+        std::vector<char> is_rel((size_t)C * nrhs, 0);
+        bool any_check = false;
+        for (int c = 0; c < C; c++)
+            for (int j : active[c]) {
+                const size_t q = (size_t)c * nrhs + j;
+                const CgVec& x = cg[q];
+                const bool rel = rel_every && !x.frozen && (x.rr <= 1e-2 * x.rr_reliable || x.iters - it_rel[q] >= rel_every);
+                if (x.frozen || rel) {
+                    check[c].push_back(j);
+                    any_check = true;
+                }
+                is_rel[q] = rel;
+            }
+        if (!any_check) continue;
+        np = true_residual(h, check, h->R64.p, h->cgpart.as<double>());
+        sum_partials(h->cgpart.as<double>(), np, nrhs, h->norms.as<double>() + nrhs, false, L);
+        from_cfg(h, hn.data(), h->norms.p, 2 * nrhs * sizeof(double));
         HIPCHK(hipStreamSynchronize(h->s));
-        std::vector<int> restart;
-        for (int j : check) {
-            CgVec& c = cg[j];
-            const double rr = hn[nrhs + j];
-            matvecs[j] += 1;
-            if (std::sqrt(rr) <= tol * c.bnorm) {
-                c.done = 1;
-                c.frozen = 0;
-                continue;
+        std::vector<std::vector<int>> restart(C), reload(C);
+        for (int c = 0; c < C; c++)
+            for (int j : check[c]) {
+                const size_t q = (size_t)c * nrhs + j;
+                CgVec& x = cg[q];
+                const double rr = rr_of(c, j);
+                matvecs[q] += 1;
+                if (std::sqrt(rr) <= tol * x.bnorm) {
+                    x.done = 1;
+                    x.frozen = 0;
+                    continue;
+                }
+                if (x.iters >= max_iter || !std::isfinite(rr)) {
+                    x.done = 1;
+                    x.frozen = 0;
+                    noconv = true;
+                    continue;
+                }
+                reload[c].push_back(j);
+                const bool stalled = is_rel[q] && rr >= x.rr_reliable;
+                if (x.frozen) {
+                    // the recursive residual met tol but the true one did not: go on from r = b - M x
+                    x.b = rr / x.rr;
+                    x.frozen = 0;
+                    restart[c].push_back(j);
+                } else if (stalled) {
+                    // no decrease of the true residual since the previous replacement: the inner
+                    // operator is too far from M for the old directions; restart with p = r
+                    x.b = 0.0;
+                    x.restarts += 1;
+                    restart[c].push_back(j);
+                } else if (pc) {
+                    restart[c].push_back(j);  // z = P r changed too
+                }
+                x.rr_reliable = rr;
+                it_rel[q] = x.iters;
+                x.rr = rr;
             }
-            if (c.iters >= max_iter || !std::isfinite(rr)) {
-                c.done = 1;
-                c.frozen = 0;
-                noconv = true;
-                continue;
-            }
-            if (c.frozen) {
-                // the recursive residual met tol but the true one did not: go on from r = b - M x
-                c.b = rr / c.rr;
-                c.frozen = 0;
-                restart.push_back(j);
-            } else if (is_rel[j] && rr >= c.rr_reliable) {
-                // no decrease of the true residual since the previous replacement: the inner
-                // operator is too far from M for the old directions; restart with p = r
-                c.b = 0.0;
-                c.restarts += 1;
-                restart.push_back(j);
-            }
-            if (pc && !c.frozen && !(is_rel[j] && rr >= c.rr_reliable)) restart.push_back(j);  // z = P r changed too
-            c.rr_reliable = rr;
-            it_rel[j] = c.iters;
-            c.rr = rr;
-        }
         // r = b - M x in the working precision, then p = r + b p for the restarted ones
         if (lo) {
-            for (int j : check)
-                if (!cg[j].done)
-                    convert(false, true, (char*)h->R64.p + j * h->vec_bytes(false), (char*)h->Rv.p + j * h->vec_bytes(true), N, h->s);
+            const int w = upload_map(h, h->tmap, reload);
+            if (w) convert_map(false, true, h->R64.p, h->Rv.p, N, h->tmap.as<int32_t>(), w, L);
         }
-        std::sort(restart.begin(), restart.end());
-        restart.erase(std::unique(restart.begin(), restart.end()), restart.end());
-        if (pc && !restart.empty()) {
+        if (pc && !restart[0].empty()) {
             // preconditioned restart from the new residual: z = P r, p = z, rz = r^dag z
-            HIPCHK(hipStreamSynchronize(h->s));
-            const std::vector<double> rz = precondition(restart);
-            for (int j : restart) {
+            const std::vector<double> rz = precondition(restart[0]);
+            for (int j : restart[0]) {
                 cg[j].rz = rz[j];
                 cg[j].b = 0.0;
             }
         }
-        HIPCHK(hipMemcpyAsync(h->cgv.p, cg.data(), nrhs * sizeof(CgVec), hipMemcpyHostToDevice, h->s));
-        if (!restart.empty()) {
-            std::vector<int32_t> rm(restart.begin(), restart.end());
-            DBuf dm;
-            dm.ensure(rm.size() * sizeof(int32_t));
-            HIPCHK(hipMemcpyAsync(dm.p, rm.data(), rm.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->s));
-            cg_p(lo, h->cgv.as<CgVec>(), dm.as<int32_t>(), (int)rm.size(), h->Pv.p, pc ? h->Zv.p : Rw, N, false, h->s);
-            HIPCHK(hipStreamSynchronize(h->s));
-        }
+        to_cfg(h, h->cgv.p, cg.data(), nrhs * sizeof(CgVec));
+        const int wr = upload_map(h, h->rmap, restart);
+        if (wr) cg_p(lo, h->cgv.as<CgVec>(), h->rmap.as<int32_t>(), wr, h->Pv.p, pc ? h->Zv.p : Rw, N, false, L);
     }
-    unpack_vec(false, h->Xint.p, X, Vh, nrhs, h->s);
+    unpack_out(h, io, h->Xint.p, nrhs);
     // final FP64 true residuals for the report
-    true_residual(h, all, h->R64.p, h->cgpart.as<double>());
-    sum_partials(h->cgpart.as<double>(), nsb64, nrhs, h->norms.as<double>() + nrhs, false, h->s);
-    HIPCHK(hipMemcpyAsync(hn.data(), h->norms.p, 2 * nrhs * sizeof(double), hipMemcpyDeviceToHost, h->s));
+    np = true_residual(h, all, h->R64.p, h->cgpart.as<double>());
+    sum_partials(h->cgpart.as<double>(), np, nrhs, h->norms.as<double>() + nrhs, false, L);
+    from_cfg(h, hn.data(), h->norms.p, 2 * nrhs * sizeof(double));
     HIPCHK(hipStreamSynchronize(h->s));
     if (rep) {
-        for (int j = 0; j < nrhs; j++) {
-            if (rep->iters) rep->iters[j] = cg[j].iters;
-            if (rep->matvecs) rep->matvecs[j] = matvecs[j];
-            if (rep->true_relres) rep->true_relres[j] = std::sqrt(hn[nrhs + j]) / hn[j];
+        const double t = now_s() - t0;
+        for (int c = 0; c < C; c++) {
+            seedcg_report& r = rep[c];
+            for (int j = 0; j < nrhs; j++) {
+                const size_t q = (size_t)c * nrhs + j;
+                if (r.iters) r.iters[j] = cg[q].iters;
+                if (r.matvecs) r.matvecs[j] = matvecs[q];
+                if (r.true_relres) r.true_relres[j] = std::sqrt(rr_of(c, j)) / bn(c, j);
+            }
+            r.t_rest_s = t;
         }
-        rep->t_rest_s = now_s() - t0;
     }
     return noconv ? SEEDCG_ERR_NOCONV : SEEDCG_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// handle set-up, stencil autotuning and the batch arena
+// ---------------------------------------------------------------------------------------------
+void init_geometry(seedcg_s* h, const seedcg_params* p, const int32_t* dims) {
+    h->p = *p;
+    for (int d = 0; d < 4; d++) h->p.dims[d] = dims[d];
+    Geom& g = h->g;
+    for (int d = 0; d < 4; d++) g.L[d] = dims[d];
+    g.Lxh = g.L[0] / 2;
+    g.V = (int64_t)g.L[0] * g.L[1] * g.L[2] * g.L[3];
+    g.Vh = g.V / 2;
+    g.t_bc = p->t_bc;
+    h->N = 12 * g.Vh;
+    h->lo = p->prec != SEEDCG_FP64;
+    h->lo_prec = p->prec == SEEDCG_MIXED_FP32 ? P32 : (p->prec == SEEDCG_MIXED_FP32_BF16LINKS ? P32BF : P64);
+    // default stencil launch shape: 3 = two lanes per site (forward / backward hops), one vector
+    // per workgroup; the vectors of a site block run as adjacent workgroups on one XCD
+    h->tps64 = env_int("SEEDCG_TPS", 3);
+    h->tps_lo = env_int("SEEDCG_TPS_LO", 3);
+    if (h->tps64 < 1 || h->tps64 > 4) h->tps64 = 4;
+    if (h->tps_lo < 1 || h->tps_lo > 4) h->tps_lo = 4;
+    h->vb64 = std::max(1, env_int("SEEDCG_VB", 1));
+    h->vb_lo = std::max(1, env_int("SEEDCG_VB_LO", 1));
+    h->tps64_multi = h->tps64;
+    h->tps_lo_multi = h->tps_lo;
+    h->vb64_multi = h->vb64;
+    h->vb_lo_multi = h->vb_lo;
+    h->sync_every = std::max(1, env_int("SEEDCG_SYNC_EVERY", 16));
+    h->debug = env_int("SEEDCG_DEBUG", 0);
+    h->use_graphs = env_int("SEEDCG_GRAPHS", 1) != 0;
+    HIPCHK(hipGetDevice(&h->device));
+}
+
+bool env_shape_fixed() {
+    return getenv("SEEDCG_TPS") || getenv("SEEDCG_TPS_LO") || getenv("SEEDCG_VB") || getenv("SEEDCG_VB_LO");
+}
+
+// Process-wide cache of tuned launch shapes: (Lx, Ly, Lz, Lt, precision, configurations, nvec).
+std::mutex g_tune_mu;
+std::map<std::vector<int>, std::pair<int, int>> g_tune;
+
+// Times M on nvec vectors for every candidate launch shape of the stencil (lanes per site and
+// vectors per workgroup) and keeps the fastest for this width class (one vector: the Lanczos
+// steps; several: the CG iterations).  x, y: nvec vectors of the precision `low` (all configurations).
+void tune_shape(seedcg_s* h, bool low, int nvec, const void* x, void* y) {
+    const bool multi = nvec > 1;
+    int& tps = low ? (multi ? h->tps_lo_multi : h->tps_lo) : (multi ? h->tps64_multi : h->tps64);
+    int& vb = low ? (multi ? h->vb_lo_multi : h->vb_lo) : (multi ? h->vb64_multi : h->vb64);
+    const std::vector<int> key{h->g.L[0], h->g.L[1], h->g.L[2], h->g.L[3], low ? (int)h->lo_prec : (int)P64, h->ncfg, nvec};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            tps = it->second.first;
+            vb = it->second.second;
+            return;
+        }
+    }
+    std::vector<std::pair<int, int>> cand{{3, 1}, {4, 1}, {2, 1}, {1, 1}};
+    if (multi) {
+        cand.push_back({4, 2});
+        cand.push_back({4, 4});
+        cand.push_back({3, 2});
+    }
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best = 1e30f;
+    std::pair<int, int> pick{tps, vb};
+    const int timing_saved = h->timing_every;
+    h->timing_every = 0;
+    try {
+        for (const auto& c : cand) {
+            tps = c.first;
+            vb = c.second;
+            apply_M_int(h, low, x, y, nvec, MOpts{});  // warm-up
+            HIPCHK(hipEventRecord(e0, h->s));
+            for (int r = 0; r < 3; r++) apply_M_int(h, low, x, y, nvec, MOpts{});
+            HIPCHK(hipEventRecord(e1, h->s));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                pick = c;
+            }
+        }
+    } catch (...) {
+        h->timing_every = timing_saved;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    h->timing_every = timing_saved;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    tps = pick.first;
+    vb = pick.second;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = pick;
+}
+
+// Tunes the inner-precision shapes of a single-configuration handle on scratch vectors.
+void autotune_single(seedcg_s* h, int nvec_multi) {
+    if (!h->p.autotune || env_shape_fixed()) return;
+    const bool low = h->lo;
+    DBuf x, y;
+    x.ensure(nvec_multi * h->vec_bytes(low));
+    y.ensure(nvec_multi * h->vec_bytes(low));
+    ensure_work(h, nvec_multi);
+    cfg_zero(x.p, nvec_multi * h->vec_bytes(low), h->L());
+    tune_shape(h, low, 1, x.p, y.p);
+    tune_shape(h, low, nvec_multi, x.p, y.p);
+    HIPCHK(hipStreamSynchronize(h->s));
+    h->tuned = true;
+}
+
+// Bytes one configuration of a batch class needs with basis capacity m_cap, and (optionally) the
+// buffers with their sizes, from a sizing pass through the allocation code.
+size_t plan_layout(seedcg_s* h, int nrhs, int m_cap, std::vector<std::pair<DBuf*, size_t>>* out) {
+    Plan pl;
+    g_plan = &pl;
+    h->p.m_max = m_cap;
+    h->work_vecs = 0;
+    try {
+        h->links64.ensure(4 * h->g.V * 9 * 16);
+        if (h->lo) h->links_lo.ensure(4 * h->g.V * 9 * (h->lo_prec == P32 ? 8 : 4));
+        h->kap2.ensure(sizeof(double));
+        alloc_seed(h, nrhs);
+        alloc_rest(h, nrhs);
+    } catch (...) {
+        g_plan = nullptr;
+        throw;
+    }
+    g_plan = nullptr;
+    h->work_vecs = 0;
+    size_t off = 0;
+    for (const auto& r : pl.req) off = (off + 255) / 256 * 256 + r.second;
+    if (out) *out = pl.req;
+    return (off + 4095) / 4096 * 4096;
+}
+
+void apply_layout(seedcg_s* h, int nrhs, int m_cap) {
+    std::vector<std::pair<DBuf*, size_t>> req;
+    const size_t per = plan_layout(h, nrhs, m_cap, &req);
+    h->arena.ensure(per * (size_t)h->ncfg);
+    size_t off = 0;
+    for (const auto& r : req) {
+        off = (off + 255) / 256 * 256;
+        r.first->release();
+        r.first->p = (char*)h->arena.p + off;
+        r.first->bytes = r.second;
+        r.first->view = true;
+        off += r.second;
+    }
+    h->cs = (int64_t)per;
+    h->p.m_max = m_cap;
+    h->m_cap = m_cap;
+    const size_t rec = std::max({sizeof(LzState), (size_t)nrhs * sizeof(CgVec), (size_t)nrhs * 2 * sizeof(double),
+                                 (size_t)nrhs * sizeof(int32_t)});
+    h->stage.ensure(rec * h->ncfg);
+    h->tabs.ensure(2 * sizeof(void*) * h->ncfg);
 }
 
 seedcg_status fail(seedcg_s* h, seedcg_status code, const std::string& msg) {
@@ -1040,6 +1425,7 @@ void seedcg_default_params(seedcg_params* p) {
     p->reliable_every = 50;
     p->seed_block = 32;
     p->max_iter = 100000;
+    p->autotune = 1;
 }
 
 seedcg_status seedcg_create(const seedcg_params* p, const double* links, seedcg_t* out) {
@@ -1054,33 +1440,17 @@ seedcg_status seedcg_create(const seedcg_params* p, const double* links, seedcg_
     seedcg_s* h = new (std::nothrow) seedcg_s;
     if (!h) return fail(nullptr, SEEDCG_ERR_OOM, "create: host allocation failed");
     seedcg_status st = guarded(h, [&]() -> seedcg_status {
-        h->p = *p;
         h->s = (hipStream_t)p->stream;
-        Geom& g = h->g;
-        for (int d = 0; d < 4; d++) g.L[d] = p->dims[d];
-        g.Lxh = g.L[0] / 2;
-        g.V = (int64_t)g.L[0] * g.L[1] * g.L[2] * g.L[3];
-        g.Vh = g.V / 2;
-        g.t_bc = p->t_bc;
-        h->N = 12 * g.Vh;
-        h->lo = p->prec != SEEDCG_FP64;
-        h->lo_prec = p->prec == SEEDCG_MIXED_FP32 ? P32 : (p->prec == SEEDCG_MIXED_FP32_BF16LINKS ? P32BF : P64);
-        // stencil launch shape: 3 = two lanes per site (forward / backward hops), one vector per
-        // workgroup; the vectors of a site block run as adjacent workgroups on one XCD
-        h->tps64 = env_int("SEEDCG_TPS", 3);
-        h->tps_lo = env_int("SEEDCG_TPS_LO", 3);
-        if (h->tps64 < 1 || h->tps64 > 4) h->tps64 = 4;
-        if (h->tps_lo < 1 || h->tps_lo > 4) h->tps_lo = 4;
-        h->sync_every = std::max(1, env_int("SEEDCG_SYNC_EVERY", 16));
-        h->debug = env_int("SEEDCG_DEBUG", 0);
-        h->vb64 = std::max(1, env_int("SEEDCG_VB", 1));
-        h->vb_lo = std::max(1, env_int("SEEDCG_VB_LO", 1));
+        init_geometry(h, p, p->dims);
+        const Geom& g = h->g;
         h->links64.ensure(4 * g.V * 9 * 16);
         pack_links(P64, g, links, h->links64.p, h->s);
         if (h->lo) {
             h->links_lo.ensure(4 * g.V * 9 * (h->lo_prec == P32 ? 8 : 4));
             pack_links(h->lo_prec, g, links, h->links_lo.p, h->s);
         }
+        check_launch();
+        autotune_single(h, 12);
         check_launch();
         HIPCHK(hipStreamSynchronize(h->s));
         return SEEDCG_OK;
@@ -1093,6 +1463,220 @@ seedcg_status seedcg_create(const seedcg_params* p, const double* links, seedcg_
     *out = h;
     return SEEDCG_OK;
 }
+
+seedcg_status seedcg_create_batch(int32_t ncfg, const int32_t* dims, const double* kappa, const double* const* links, int32_t nrhs,
+                                  const seedcg_params* p, seedcg_batch_t* out) {
+    if (!p || !dims || !kappa || !links || !out) return fail(nullptr, SEEDCG_ERR_ARG, "create_batch: null pointer");
+    *out = nullptr;
+    if (ncfg < 1) return fail(nullptr, SEEDCG_ERR_ARG, "create_batch: ncfg < 1");
+    if (nrhs < 1 || nrhs > 25) return fail(nullptr, SEEDCG_ERR_ARG, "create_batch: nrhs must be 1..25");
+    for (int c = 0; c < ncfg; c++) {
+        for (int d = 0; d < 4; d++)
+            if (dims[4 * c + d] < 2 || dims[4 * c + d] % 2)
+                return fail(nullptr, SEEDCG_ERR_ARG, "create_batch: every extent must be even and >= 2");
+        if (!links[c]) return fail(nullptr, SEEDCG_ERR_ARG, "create_batch: null links pointer");
+        if (!(kappa[c] > 0.0)) return fail(nullptr, SEEDCG_ERR_ARG, "create_batch: kappa must be > 0");
+    }
+    if (p->t_bc != 1 && p->t_bc != -1) return fail(nullptr, SEEDCG_ERR_ARG, "create_batch: t_bc must be +1 or -1");
+    if (p->prec < 0 || p->prec > 2) return fail(nullptr, SEEDCG_ERR_ARG, "create_batch: unknown precision");
+    if (!(p->tol > 0.0)) return fail(nullptr, SEEDCG_ERR_ARG, "create_batch: tol must be > 0");
+    if (p->reorth_k < 0) return fail(nullptr, SEEDCG_ERR_ARG, "create_batch: reorth_k must be >= 0");
+    if (p->precond != 0) return fail(nullptr, SEEDCG_ERR_ARG, "create_batch: the learned preconditioner is per configuration");
+    seedcg_batch_s* b = new (std::nothrow) seedcg_batch_s;
+    if (!b) return fail(nullptr, SEEDCG_ERR_OOM, "create_batch: host allocation failed");
+    b->ncfg = ncfg;
+    b->nrhs = nrhs;
+    b->user_stream = (hipStream_t)p->stream;
+    seedcg_s tmp;  // collects the error text of the set-up
+    const seedcg_status st = guarded(&tmp, [&]() -> seedcg_status {
+        // classes in order of first appearance
+        for (int c = 0; c < ncfg; c++) {
+            int k = 0;
+            for (; k < (int)b->members.size(); k++)
+                if (std::equal(dims + 4 * c, dims + 4 * c + 4, dims + 4 * b->members[k][0])) break;
+            if (k == (int)b->members.size()) b->members.push_back({});
+            b->members[k].push_back(c);
+        }
+        for (const auto& mem : b->members) {
+            seedcg_s* h = new seedcg_s;
+            b->cls.push_back(h);
+            init_geometry(h, p, dims + 4 * mem[0]);
+            h->ncfg = (int)mem.size();
+            h->p.kappa = kappa[mem[0]];
+            for (int c : mem) h->kappas.push_back(kappa[c]);
+            HIPCHK(hipStreamCreateWithFlags(&h->s, hipStreamNonBlocking));
+            h->own_stream = true;
+        }
+        // one basis capacity for every class: params.m_max, or the largest that fits in 90% of
+        // the free HBM less 4 GiB
+        size_t freeb = 0, total = 0;
+        HIPCHK(hipMemGetInfo(&freeb, &total));
+        const double budget = 0.9 * (double)freeb - 4.0 * (1 << 30);
+        auto need = [&](int m) {
+            double t = 0.0;
+            for (auto h : b->cls) t += (double)plan_layout(h, nrhs, m, nullptr) * h->ncfg;
+            return t;
+        };
+        int m_cap = p->m_max;
+        if (m_cap > 0) {
+            if (need(m_cap) > budget) throw OomError{"create_batch: the Krylov bases of m_max vectors do not fit in HBM"};
+        } else {
+            int lo = 2, hi = 8192;
+            if (need(lo) > budget) throw OomError{"create_batch: no room for the Krylov bases"};
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) / 2;
+                if (need(mid) <= budget)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            m_cap = lo;
+        }
+        for (size_t k = 0; k < b->cls.size(); k++) {
+            seedcg_s* h = b->cls[k];
+            apply_layout(h, nrhs, m_cap);
+            const Geom& g = h->g;
+            std::vector<double> k2;
+            for (int i = 0; i < h->ncfg; i++) {
+                const int c = b->members[k][i];
+                pack_links(P64, g, links[c], (char*)h->links64.p + (int64_t)i * h->cs, h->s);
+                if (h->lo) pack_links(h->lo_prec, g, links[c], (char*)h->links_lo.p + (int64_t)i * h->cs, h->s);
+                k2.push_back(kappa[c] * kappa[c]);
+            }
+            to_cfg(h, h->kap2.p, k2.data(), sizeof(double));
+            check_launch();
+            // launch shapes timed on the batch itself (zeroed vectors of the CG and Lanczos buffers)
+            if (h->p.autotune && !env_shape_fixed()) {
+                zero_cfg(h, h->Pv.p, nrhs * h->vec_bytes(h->lo));
+                zero_cfg(h, h->basis.p, h->vec_bytes(h->lo));
+                tune_shape(h, h->lo, 1, h->basis.p, h->f.p);
+                if (nrhs > 1) tune_shape(h, h->lo, nrhs, h->Pv.p, h->Qv.p);
+                h->tuned = true;
+            }
+            HIPCHK(hipStreamSynchronize(h->s));
+        }
+        return SEEDCG_OK;
+    });
+    if (st != SEEDCG_OK) {
+        g_create_error = tmp.err;
+        delete b;
+        return st;
+    }
+    *out = b;
+    return SEEDCG_OK;
+}
+
+seedcg_status seedcg_solve_batch(seedcg_batch_t b, const double* const* B, double* const* X, seedcg_report* rep) {
+    if (!b) return fail(nullptr, SEEDCG_ERR_ARG, "solve_batch: null batch");
+    if (!B || !X) {
+        b->err = "solve_batch: null pointer";
+        return SEEDCG_ERR_ARG;
+    }
+    for (int c = 0; c < b->ncfg; c++)
+        if (!B[c] || !X[c]) {
+            b->err = "solve_batch: null vector pointer";
+            return SEEDCG_ERR_ARG;
+        }
+    const hipError_t e0 = hipStreamSynchronize(b->user_stream);  // B and X are ready
+    if (e0 != hipSuccess) {
+        b->err = std::string("solve_batch: ") + hipGetErrorString(e0);
+        return SEEDCG_ERR_HIP;
+    }
+    const int K = (int)b->cls.size(), nrhs = b->nrhs;
+    std::vector<seedcg_status> sts(K, SEEDCG_OK);
+    std::vector<std::thread> th;
+    for (int k = 0; k < K; k++) {
+        th.emplace_back([&, k]() {
+            seedcg_s* h = b->cls[k];
+            const std::vector<int>& mem = b->members[k];
+            const int n = (int)mem.size();
+            sts[k] = guarded(h, [&]() -> seedcg_status {
+                HIPCHK(hipSetDevice(h->device));
+                Io io;
+                if (n == 1) {
+                    io.B = B[mem[0]];
+                    io.X = X[mem[0]];
+                } else {
+                    std::vector<const void*> t(2 * n);
+                    for (int i = 0; i < n; i++) {
+                        t[i] = B[mem[i]];
+                        t[n + i] = X[mem[i]];
+                    }
+                    HIPCHK(hipMemcpyAsync(h->tabs.p, t.data(), t.size() * sizeof(void*), hipMemcpyHostToDevice, h->s));
+                    HIPCHK(hipStreamSynchronize(h->s));
+                    io.Btab = (const double* const*)h->tabs.p;
+                    io.Xtab = (double* const*)h->tabs.p + n;
+                }
+                std::vector<int32_t> it_s((size_t)n * nrhs), mv_s((size_t)n * nrhs), it_r((size_t)n * nrhs), mv_r((size_t)n * nrhs);
+                std::vector<double> res((size_t)n * nrhs);
+                std::vector<seedcg_report> rs(n), rr(n);
+                for (int i = 0; i < n; i++) {
+                    rs[i] = seedcg_report{};
+                    rs[i].iters = &it_s[(size_t)i * nrhs];
+                    rs[i].matvecs = &mv_s[(size_t)i * nrhs];
+                    rr[i] = seedcg_report{};
+                    rr[i].iters = &it_r[(size_t)i * nrhs];
+                    rr[i].matvecs = &mv_r[(size_t)i * nrhs];
+                    rr[i].true_relres = &res[(size_t)i * nrhs];
+                }
+                solve_seed_impl(h, io, nrhs, rs.data());
+                const seedcg_status s2 = solve_rest_impl(h, io, nrhs, rr.data());
+                if (rep)
+                    for (int i = 0; i < n; i++) {
+                        seedcg_report& u = rep[mem[i]];
+                        for (int j = 0; j < nrhs; j++) {
+                            const size_t q = (size_t)i * nrhs + j;
+                            if (u.iters) u.iters[j] = (j == 0 ? it_s[q] : 0) + it_r[q];
+                            if (u.matvecs) u.matvecs[j] = mv_s[q] + mv_r[q];
+                            if (u.true_relres) u.true_relres[j] = res[q];
+                        }
+                        u.m_used = rs[i].m_used;
+                        u.i_conv = rs[i].i_conv;
+                        u.seed_status = rs[i].seed_status;
+                        u.reorth_passes = rs[i].reorth_passes;
+                        u.t_seed_s = rs[i].t_seed_s;
+                        u.t_rest_s = rr[i].t_rest_s;
+                    }
+                if (s2 == SEEDCG_ERR_NOCONV) h->err = "solve_batch: max_iter reached before tol";
+                return s2;
+            });
+        });
+    }
+    for (auto& t : th) t.join();
+    for (int k = 0; k < K; k++)
+        if (sts[k] != SEEDCG_OK) {
+            b->err = b->cls[k]->err;
+            return sts[k];
+        }
+    return SEEDCG_OK;
+}
+
+seedcg_status seedcg_batch_info(seedcg_batch_t b, int32_t* nclass, int32_t* class_of, int32_t* m_cap, double* tune) {
+    if (!b) return fail(nullptr, SEEDCG_ERR_ARG, "batch_info: null batch");
+    if (nclass) *nclass = (int32_t)b->cls.size();
+    for (size_t k = 0; k < b->cls.size(); k++) {
+        if (class_of)
+            for (int c : b->members[k]) class_of[c] = (int32_t)k;
+        if (m_cap) m_cap[k] = b->cls[k]->m_cap;
+        if (tune) {
+            const seedcg_s* h = b->cls[k];
+            const bool lo = h->lo;
+            tune[4 * k + 0] = lo ? h->tps_lo : h->tps64;
+            tune[4 * k + 1] = lo ? h->vb_lo : h->vb64;
+            tune[4 * k + 2] = lo ? h->tps_lo_multi : h->tps64_multi;
+            tune[4 * k + 3] = lo ? h->vb_lo_multi : h->vb64_multi;
+        }
+    }
+    return SEEDCG_OK;
+}
+
+void seedcg_destroy_batch(seedcg_batch_t b) {
+    if (!b) return;
+    for (auto h : b->cls) (void)hipStreamSynchronize(h->s);
+    delete b;
+}
+
+const char* seedcg_batch_last_error(seedcg_batch_t b) { return b ? b->err.c_str() : g_create_error.c_str(); }
 
 seedcg_status seedcg_apply_M(seedcg_t h, const double* x, double* y, int32_t nvec) {
     if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "apply_M: null handle");
@@ -1148,7 +1732,11 @@ seedcg_status seedcg_apply_A(seedcg_t h, const double* x, double* y, int32_t nve
 seedcg_status seedcg_solve_seed(seedcg_t h, const double* B, double* X, int32_t nrhs, seedcg_report* r) {
     if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "solve_seed: null handle");
     return guarded(h, [&]() -> seedcg_status {
-        solve_seed_impl(h, B, X, nrhs, r);
+        if (!B || !X) throw ArgError{"solve_seed: null pointer"};
+        Io io;
+        io.B = B;
+        io.X = X;
+        solve_seed_impl(h, io, nrhs, r);
         return SEEDCG_OK;
     });
 }
@@ -1156,7 +1744,11 @@ seedcg_status seedcg_solve_seed(seedcg_t h, const double* B, double* X, int32_t 
 seedcg_status seedcg_solve_rest(seedcg_t h, const double* B, double* X, int32_t nrhs, seedcg_report* r) {
     if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "solve_rest: null handle");
     return guarded(h, [&]() -> seedcg_status {
-        seedcg_status s = solve_rest_impl(h, B, X, nrhs, r);
+        if (!B || !X) throw ArgError{"solve_rest: null pointer"};
+        Io io;
+        io.B = B;
+        io.X = X;
+        seedcg_status s = solve_rest_impl(h, io, nrhs, r);
         if (s == SEEDCG_ERR_NOCONV) h->err = "solve_rest: max_iter reached before tol";
         return s;
     });

@@ -24,7 +24,7 @@ class Params(ctypes.Structure):
                 ("prec", ctypes.c_int32), ("m_max", ctypes.c_int32), ("reorth_k", ctypes.c_int32),
                 ("past_factor", ctypes.c_double), ("tol", ctypes.c_double), ("reliable_every", ctypes.c_int32),
                 ("seed_block", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("precond", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("autotune", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class Report(ctypes.Structure):
@@ -77,6 +77,12 @@ def load_library():
         "seedcg_release_basis": (i32, [H]),
         "seedcg_destroy": (None, [H]),
         "seedcg_last_error": (ctypes.c_char_p, [H]),
+        "seedcg_create_batch": (i32, [i32, ctypes.POINTER(i32), ctypes.POINTER(dbl), ctypes.POINTER(P), i32,
+                                      ctypes.POINTER(Params), ctypes.POINTER(H)]),
+        "seedcg_solve_batch": (i32, [H, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(Report)]),
+        "seedcg_batch_info": (i32, [H, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(dbl)]),
+        "seedcg_destroy_batch": (None, [H]),
+        "seedcg_batch_last_error": (ctypes.c_char_p, [H]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -92,7 +98,8 @@ def exported_symbols():
             "seedcg_solve_rest", "seedcg_get_tridiag", "seedcg_get_basis_vector", "seedcg_project",
             "seedcg_update", "seedcg_train_precond", "seedcg_use_precond", "seedcg_set_precond_weights",
             "seedcg_get_precond_weights", "seedcg_apply_P", "seedcg_precond_loss_grad", "seedcg_set_timing",
-            "seedcg_get_timing", "seedcg_release_basis", "seedcg_destroy", "seedcg_last_error"]
+            "seedcg_get_timing", "seedcg_release_basis", "seedcg_destroy", "seedcg_last_error", "seedcg_create_batch",
+            "seedcg_solve_batch", "seedcg_batch_info", "seedcg_destroy_batch", "seedcg_batch_last_error"]
 
 
 def _check_vec(t, Vh, name):
@@ -111,7 +118,7 @@ class SeedCG:
     """One gauge configuration: M = A^dag A with A = 1 - kappa^2 H_eo H_oe (see include/seedcg.h)."""
 
     def __init__(self, links, dims, kappa, *, t_bc=-1, prec="fp64", m_max=0, reorth_k=10, past=1.5,
-                 tol=1e-10, reliable_every=50, seed_block=32, max_iter=100000, stream=None):
+                 tol=1e-10, reliable_every=50, seed_block=32, max_iter=100000, autotune=True, stream=None):
         lib = load_library()
         self.dims = tuple(int(d) for d in dims)
         self.V = self.dims[0] * self.dims[1] * self.dims[2] * self.dims[3]
@@ -135,6 +142,7 @@ class SeedCG:
         p.reliable_every = int(reliable_every)
         p.seed_block = int(seed_block)
         p.max_iter = int(max_iter)
+        p.autotune = int(bool(autotune))
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
@@ -298,3 +306,106 @@ class SeedCG:
 
     def release_basis(self):
         self._rc(self._lib.seedcg_release_basis(self._h))
+
+
+class SeedCGBatch:
+    """Many configurations (any mix of lattice shapes), nrhs right-hand sides each, solved together:
+    per configuration Algorithm 1 on its first right-hand side and plain CG on all of them."""
+
+    def __init__(self, links, dims, kappas, nrhs, *, t_bc=-1, prec="mixed", m_max=0, reorth_k=10, past=1.5,
+                 tol=1e-10, reliable_every=50, seed_block=32, max_iter=100000, autotune=True, stream=None):
+        lib = load_library()
+        n = len(links)
+        if not (len(dims) == n and len(kappas) == n) or n < 1:
+            raise ValueError("links, dims and kappas must have one entry per configuration")
+        self.dims = [tuple(int(d) for d in dd) for dd in dims]
+        self.Vh = [dd[0] * dd[1] * dd[2] * dd[3] // 2 for dd in self.dims]
+        for c, (U, dd) in enumerate(zip(links, self.dims)):
+            V = 2 * self.Vh[c]
+            if not (isinstance(U, torch.Tensor) and U.is_cuda and U.dtype == torch.complex128):
+                raise TypeError(f"links[{c}]: expected a complex128 CUDA tensor")
+            if tuple(U.shape) != (4, V, 3, 3) or not U.is_contiguous():
+                raise ValueError(f"links[{c}]: expected a contiguous (4, {V}, 3, 3) tensor")
+        self.n, self.nrhs = n, int(nrhs)
+        self.device = links[0].device
+        p = Params()
+        lib.seedcg_default_params(ctypes.byref(p))
+        p.t_bc = int(t_bc)
+        p.prec = _PREC[prec] if isinstance(prec, str) else int(prec)
+        p.m_max = int(m_max)
+        p.reorth_k = int(reorth_k)
+        p.past_factor = float(past)
+        p.tol = float(tol)
+        p.reliable_every = int(reliable_every)
+        p.seed_block = int(seed_block)
+        p.max_iter = int(max_iter)
+        p.autotune = int(bool(autotune))
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        p.stream = ctypes.c_void_p(stream.cuda_stream)
+        dims_a = (ctypes.c_int32 * (4 * n))(*[d for dd in self.dims for d in dd])
+        kap_a = (ctypes.c_double * n)(*[float(k) for k in kappas])
+        lk_a = (ctypes.c_void_p * n)(*[U.data_ptr() for U in links])
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = lib.seedcg_create_batch(n, dims_a, kap_a, lk_a, self.nrhs, ctypes.byref(p), ctypes.byref(h))
+        if rc != 0:
+            raise SeedCGError(rc, lib.seedcg_batch_last_error(None).decode())
+        self._h = h
+        self._lib = lib
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.seedcg_destroy_batch(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        ncls = ctypes.c_int32()
+        self._lib.seedcg_batch_info(self._h, ctypes.byref(ncls), None, None, None)
+        k = ncls.value
+        cls = (ctypes.c_int32 * self.n)()
+        mc = (ctypes.c_int32 * k)()
+        tune = (ctypes.c_double * (4 * k))()
+        self._lib.seedcg_batch_info(self._h, None, cls, mc, tune)
+        return dict(nclass=k, class_of=list(cls), m_cap=list(mc),
+                    tune=[tuple(int(x) for x in tune[4 * i:4 * i + 4]) for i in range(k)])
+
+    def solve(self, B, X=None, raise_on_noconv=True):
+        """B: list of (nrhs, Vh_c, 4, 3) complex128 CUDA tensors; returns (X list, per-config reports)."""
+        if len(B) != self.n:
+            raise ValueError("B: one tensor per configuration")
+        B = [_check_vec(b, self.Vh[c], f"B[{c}]") for c, b in enumerate(B)]
+        for c, b in enumerate(B):
+            if b.shape[0] != self.nrhs:
+                raise ValueError(f"B[{c}]: expected {self.nrhs} vectors")
+        X = [torch.zeros_like(b) for b in B] if X is None else [_check_vec(x, self.Vh[c], f"X[{c}]") for c, x in enumerate(X)]
+        bp = (ctypes.c_void_p * self.n)(*[b.data_ptr() for b in B])
+        xp = (ctypes.c_void_p * self.n)(*[x.data_ptr() for x in X])
+        reps = (Report * self.n)()
+        keep = []
+        for c in range(self.n):
+            it = (ctypes.c_int32 * self.nrhs)()
+            mv = (ctypes.c_int32 * self.nrhs)()
+            rr = (ctypes.c_double * self.nrhs)()
+            reps[c].iters = ctypes.cast(it, ctypes.POINTER(ctypes.c_int32))
+            reps[c].matvecs = ctypes.cast(mv, ctypes.POINTER(ctypes.c_int32))
+            reps[c].true_relres = ctypes.cast(rr, ctypes.POINTER(ctypes.c_double))
+            keep.append((it, mv, rr))
+        rc = self._lib.seedcg_solve_batch(self._h, bp, xp, reps)
+        out = []
+        for c in range(self.n):
+            it, mv, rr = keep[c]
+            r = reps[c]
+            out.append(dict(iters=list(it), matvecs=list(mv), true_relres=list(rr), m=r.m_used, i_conv=r.i_conv,
+                            seed_status=SEED_STATUS.get(r.seed_status, r.seed_status), reorth_passes=r.reorth_passes,
+                            t_seed_s=r.t_seed_s, t_rest_s=r.t_rest_s))
+        if rc != 0 and (rc != -5 or raise_on_noconv):
+            raise SeedCGError(rc, self._lib.seedcg_batch_last_error(self._h).decode())
+        return X, out

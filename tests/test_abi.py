@@ -57,3 +57,25 @@ def test_create_rejects_bad_arguments_on_host(lib):
     assert lib.seedcg_create(None, dummy, ctypes.byref(h)) == -1
     assert lib.seedcg_apply_M(None, None, None, 1) == -1
     assert lib.seedcg_solve_seed(None, None, None, 1, None) == -1
+
+
+def test_create_batch_rejects_bad_arguments_on_host(lib):
+    from paper_0901_3512_amd.seedcg import Params
+    p = Params()
+    lib.seedcg_default_params(ctypes.byref(p))
+    assert p.autotune == 1
+    h = ctypes.c_void_p()
+    dims = (ctypes.c_int32 * 8)(4, 4, 4, 4, 4, 4, 4, 4)
+    kap = (ctypes.c_double * 2)(0.12, 0.13)
+    links = (ctypes.c_void_p * 2)(16, 32)   # never dereferenced: validation fails first
+    assert lib.seedcg_create_batch(0, dims, kap, links, 4, ctypes.byref(p), ctypes.byref(h)) == -1
+    assert lib.seedcg_create_batch(2, dims, kap, links, 26, ctypes.byref(p), ctypes.byref(h)) == -1
+    assert b"nrhs" in lib.seedcg_batch_last_error(None)
+    bad = (ctypes.c_int32 * 8)(4, 4, 4, 4, 4, 3, 4, 4)
+    assert lib.seedcg_create_batch(2, bad, kap, links, 4, ctypes.byref(p), ctypes.byref(h)) == -1
+    nolink = (ctypes.c_void_p * 2)(16, None)
+    assert lib.seedcg_create_batch(2, dims, kap, nolink, 4, ctypes.byref(p), ctypes.byref(h)) == -1
+    p.precond = 1
+    assert lib.seedcg_create_batch(2, dims, kap, links, 4, ctypes.byref(p), ctypes.byref(h)) == -1
+    assert lib.seedcg_solve_batch(None, None, None, None) == -1
+    lib.seedcg_destroy_batch(None)

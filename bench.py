@@ -8,6 +8,10 @@ FP64 true relative residual <= tol.  Inputs are resident in HBM before the timed
 Default workload: 16^3 x 32 lattice, links exp(0.5 i H) smeared by 2 APE steps, kappa from the
 oracle's search, 12 point sources, plain FP64 Seed-CG with k = 20.
 
+--config c4: the batched workload instead, 64 configurations of lattice sizes drawn from
+{8^4, 8^3 x 16, 12^3 x 24, 12^4}, 12 point sources each, mixed precision, every configuration
+solved by one batch call per step (value = right-hand sides solved per second over the batch).
+
 Prints one JSON line (see the `result` dict at the end).
 """
 import argparse
@@ -39,6 +43,7 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=40, help="Lanczos steps in the oracle sample")
     ap.add_argument("--sample-every", type=int, default=4, help="stencil launches per timed sample")
     ap.add_argument("--mbench", type=int, default=200, help="back-to-back M applications for D^dag D GB/s")
+    ap.add_argument("--batch-n", type=int, default=64, help="c4: number of batch members (the workload has 64)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 1 GiB device copy first (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -59,13 +64,10 @@ def main():
     from paper_0901_3512_amd import SeedCG
     from synth.configs import CONFIGS, make_links, make_sources, kappa_for
 
+    if args.config == "c4":
+        return bench_batch(args)   # generates its inputs in worker processes before any GPU call
     if args.copy_probe:
-        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        copy_probe()
     cfg = CONFIGS[args.config]
     prec = args.prec or cfg.prec
     dev = torch.device("cuda:0")
@@ -158,6 +160,104 @@ def main():
                    "dagger_d_gbs_api": (288 * V * s_l + 120 * V * s_s) / t_m_api / 1e9,
                    "dagger_d_us_api": t_m_api * 1e6,
                    "hop_launches_total": tm["seen"]},
+    }
+    print(json.dumps(result), flush=True)
+
+
+def copy_probe():
+    """A plain 1 GiB device copy: the reference for scaling the HBM byte counters."""
+    import torch
+    src = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+def _member_inputs(name):
+    from synth.configs import batch_members, make_links, make_sources
+    m = {c.name: c for c in batch_members()}[name]
+    return make_links(m), make_sources(m)
+
+
+def bench_batch(args):
+    """The batched workload: every member solved by Algorithm 1 + CG inside one seedcg_solve_batch call."""
+    import numpy as np
+    import torch
+    from concurrent.futures import ProcessPoolExecutor
+    from paper_0901_3512_amd import SeedCG, SeedCGBatch
+    from synth.configs import batch_members, kappa_for
+
+    members = batch_members()[:args.batch_n]
+    kappas = [kappa_for(m) for m in members]
+    prec = args.prec or members[0].prec
+    dev = torch.device("cuda:0")
+    t_gen = time.time()
+    with ProcessPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        inputs = list(ex.map(_member_inputs, [m.name for m in members]))
+    log(f"inputs: {len(members)} configurations ({time.time() - t_gen:.1f} s)")
+    if args.copy_probe:
+        copy_probe()
+    links = [torch.from_numpy(U).to(dev) for U, _ in inputs]
+    B = []
+    for m, k, (U, phi), Ud in zip(members, kappas, inputs, links):
+        s = SeedCG(Ud, m.dims, k, t_bc=m.t_bc, autotune=False, m_max=2)
+        B.append(s.apply_A(torch.from_numpy(phi).to(dev), dagger=True))   # b = A^dag phi (not timed)
+        s.close()
+    del inputs
+    nrhs = B[0].shape[0]
+    torch.cuda.synchronize()
+    t_c = time.time()
+    m0 = members[0]
+    batch = SeedCGBatch(links, [m.dims for m in members], kappas, nrhs, t_bc=m0.t_bc, prec=prec, reorth_k=m0.reorth_k,
+                        past=m0.past, tol=m0.tol, reliable_every=m0.reliable_every)
+    info = batch.info()
+    log(f"batch: {info['nclass']} shape classes, m_cap {info['m_cap']}, launch shapes {info['tune']} "
+        f"(set-up {time.time() - t_c:.1f} s)")
+
+    def step():
+        X, reps = batch.solve(B)
+        return X, reps
+
+    for w in range(args.warmup):
+        _, reps = step()
+        log(f"warmup {w}: m {min(r['m'] for r in reps)}..{max(r['m'] for r in reps)}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solved, last = 0, None
+    for k in range(args.steps):
+        X, reps = step()
+        last = reps
+        solved += sum(1 for r in reps for x in r["true_relres"] if x <= m0.tol)
+        log(f"step {k}: max relres {max(max(r['true_relres']) for r in reps):.2e}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    # the stencil rate, sampled on one more solve (event sampling replaces graph replay by eager launches)
+    batch.set_timing(args.sample_every, 16384)
+    batch.solve(B)
+    torch.cuda.synchronize()
+    tm = batch.get_timing()
+    batch.set_timing(0, 0)
+    hop_ms = tm["ms"] / max(tm["launches"], 1)
+    hop_bytes = tm["bytes"] / max(tm["launches"], 1)
+    achieved = hop_bytes / (hop_ms * 1e-3) / 1e9 if tm["launches"] else None
+    V = sum(int(np.prod(m.dims)) for m in members)
+    result = {
+        "metric": METRIC, "value": solved / elapsed, "unit": "RHS/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if prec == "fp64" else f"f32+f64({prec})", "data": "synthetic",
+        "config": {"workload": f"batched Seed-CG {prec}: {len(members)} configurations of "
+                               f"{{8^4, 8^3x16, 12^3x24, 12^4}} ({V} sites), {nrhs} point sources each, tol {m0.tol:g}, "
+                               f"k={m0.reorth_k}", "name": "c4", "configurations": len(members), "sites": V,
+                   "nrhs": nrhs, "precision": prec},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "kernel": "hop kernels of the batch (one launch per shape class, concurrent classes)",
+                     "launches_sampled": tm["launches"], "avg_launch_us": hop_ms * 1e3, "avg_launch_bytes": hop_bytes},
+        "cpu_baseline": None,
+        "detail": {"classes": info, "m": [r["m"] for r in last], "i_conv": [r["i_conv"] for r in last],
+                   "iters": [r["iters"] for r in last], "max_true_relres": max(max(r["true_relres"]) for r in last)},
     }
     print(json.dumps(result), flush=True)
 

@@ -211,6 +211,11 @@ seedcg_status seedcg_solve_batch(seedcg_batch_t b, const double* const* B, doubl
    for several vectors. */
 seedcg_status seedcg_batch_info(seedcg_batch_t b, int32_t* nclass, int32_t* class_of, int32_t* m_cap, double* tune);
 
+/* seedcg_set_timing / seedcg_get_timing for every shape class of the batch; the counts and sums
+   of get_timing are totals over the classes (whose launches may overlap in time on their streams). */
+seedcg_status seedcg_batch_set_timing(seedcg_batch_t b, int32_t sample_every, int32_t max_samples);
+seedcg_status seedcg_batch_get_timing(seedcg_batch_t b, double* out);
+
 void seedcg_destroy_batch(seedcg_batch_t b);
 
 /* Text of the last failure of the batch (or of the last failed create_batch when b is NULL). */

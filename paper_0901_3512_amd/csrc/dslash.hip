@@ -436,6 +436,48 @@ __device__ inline void hop_dir_lean(const cx<T>* __restrict__ src, const typenam
     }
 }
 
+// Epilogue of the two-lanes-per-site kernels for one vector: out = sy*[gamma5](x - kappa^2 v) +
+// cz z, with the reduction partial of Re d^dag out or |out|^2.  Every operand load is issued before
+// the first use (three independent batches of six), so the epilogue costs one memory round trip
+// instead of one per component and operand.
+template <typename T>
+__device__ inline double epilogue2(const EpiDev<T>& e, const cx<T>* v, int bwd, size_t vo, int64_t Vh, uint32_t lo, cx<T>* __restrict__ out,
+                                   T cz) {
+    cx<T> xv[6], zv[6], dv[6];
+#pragma unroll
+    for (int c = 0; c < 6; c++) xv[c] = zv[c] = dv[c] = mk<T>(0, 0);
+    if (e.combine) {
+#pragma unroll
+        for (int c = 0; c < 6; c++) xv[c] = ld32(e.x + vo + (size_t)c * Vh, lo);
+    }
+    if (e.z) {
+#pragma unroll
+        for (int c = 0; c < 6; c++) zv[c] = ld32(e.z + vo + (size_t)c * Vh, lo);
+    }
+    if (e.red == 1) {
+#pragma unroll
+        for (int c = 0; c < 6; c++) dv[c] = ld32(e.d + vo + (size_t)c * Vh, lo);
+    }
+    double part = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; c++) {
+        const cx<T> w = v[c];
+        cx<T> y = w;
+        if (e.combine) {
+            y = mk<T>(xv[c].re - e.kappa2 * w.re, xv[c].im - e.kappa2 * w.im);
+            if (e.apply_g5 && bwd) y = mk<T>(-y.re, -y.im);
+        }
+        cx<T> o = mk<T>(e.sy * y.re, e.sy * y.im);
+        if (e.z) o = mk<T>(o.re + cz * zv[c].re, o.im + cz * zv[c].im);
+        st32(out + vo + (size_t)c * Vh, lo, o);
+        if (e.red == 1)
+            part += (double)dv[c].re * (double)o.re + (double)dv[c].im * (double)o.im;
+        else if (e.red == 2)
+            part += (double)o.re * (double)o.re + (double)o.im * (double)o.im;
+    }
+    return part;
+}
+
 // the same hop with a wave-uniform runtime direction mu (coefficients from proj_of(mu))
 template <typename T>
 __device__ inline cx<T> fma_u(T sd, Unit u, cx<T> b, cx<T> a) {
@@ -482,7 +524,11 @@ __device__ inline void hop_dir_rt(const cx<T>* __restrict__ src, const typename 
     }
 }
 
-template <typename T, typename LT, bool ONE>
+// UNR: directions per pass of the mu loop.  1 keeps one direction's loads in flight (fewest
+// registers, for grids with many waves per SIMD); 2 and 4 issue the loads of several directions
+// together, which shortens the chain of dependent memory round trips when the half lattice gives
+// only a couple of waves per SIMD.
+template <typename T, typename LT, bool ONE, int UNR>
 __global__ __launch_bounds__(SCG_BLOCK) void hop_lean_kernel(Geom g, const typename LinkLoad<LT>::Store* __restrict__ links,
                                                              const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
                                                              int p, int nvec, int vb, int64_t nsb, EpiDev<T> e, int64_t cs) {
@@ -532,12 +578,16 @@ __global__ __launch_bounds__(SCG_BLOCK) void hop_lean_kernel(Geom g, const typen
 #pragma unroll
         for (int c = 0; c < 12; c++) acc[c] = mk<T>(0, 0);
         if (active) {
-            // one direction at a time (mu is the same for every lane): bounded register use
+            // UNR directions per pass (mu is the same for every lane)
 #pragma unroll 1
-            for (int mu = 0; mu < 4; mu++) {
-                const Nb n = neighbour(g, mu, step, x, y, z, t, xh, row);
-                const uint32_t hn = (uint32_t)n.h;
-                hop_dir_rt<T, LT>(src, links, mu, hn, bwd ? hn : h32, lpar, Vh32, bwd, sd, (T)n.sign, acc);
+            for (int mu0 = 0; mu0 < 4; mu0 += UNR) {
+#pragma unroll
+                for (int u = 0; u < UNR; u++) {
+                    const int mu = mu0 + u;
+                    const Nb n = neighbour(g, mu, step, x, y, z, t, xh, row);
+                    const uint32_t hn = (uint32_t)n.h;
+                    hop_dir_rt<T, LT>(src, links, mu, hn, bwd ? hn : h32, lpar, Vh32, bwd, sd, (T)n.sign, acc);
+                }
             }
         }
 #pragma unroll
@@ -550,31 +600,11 @@ __global__ __launch_bounds__(SCG_BLOCK) void hop_lean_kernel(Geom g, const typen
             const size_t vo = (size_t)vec * 12 * Vh;
             double czd = e.cz_host;
             if (e.cz_dev) czd = e.cz_negate ? -e.cz_dev[vec] : e.cz_dev[vec];
-            const T cz = (T)czd;
             const uint32_t lo = (uint32_t)bwd * 6u * Vh32 + h32;
+            cx<T> v[6];
 #pragma unroll
-            for (int c = 0; c < 6; c++) {
-                const cx<T> v = bwd ? acc[6 + c] : acc[c];
-                const size_t cb = vo + (size_t)c * Vh;   // uniform
-                cx<T> y = v;
-                if (e.combine) {
-                    const cx<T> xv = ld32(e.x + cb, lo);
-                    y = mk<T>(xv.re - e.kappa2 * v.re, xv.im - e.kappa2 * v.im);
-                    if (e.apply_g5 && bwd) y = mk<T>(-y.re, -y.im);
-                }
-                cx<T> o = mk<T>(e.sy * y.re, e.sy * y.im);
-                if (e.z) {
-                    const cx<T> zv = ld32(e.z + cb, lo);
-                    o = mk<T>(o.re + cz * zv.re, o.im + cz * zv.im);
-                }
-                st32(out + cb, lo, o);
-                if (e.red == 1) {
-                    const cx<T> dv = ld32(e.d + cb, lo);
-                    part += (double)dv.re * (double)o.re + (double)dv.im * (double)o.im;
-                } else if (e.red == 2) {
-                    part += (double)o.re * (double)o.re + (double)o.im * (double)o.im;
-                }
-            }
+            for (int c = 0; c < 6; c++) v[c] = bwd ? acc[6 + c] : acc[c];
+            part = epilogue2<T>(e, v, bwd, vo, Vh, lo, out, (T)czd);
         }
         if (e.red) {
             for (int off = SCG_WAVE / 2; off > 0; off >>= 1) part += __shfl_xor(part, off);
@@ -598,6 +628,156 @@ __global__ __launch_bounds__(SCG_BLOCK) void hop_lean_kernel(Geom g, const typen
     }
 }
 
+// Several vectors per lane: the link of a direction is loaded once and applied to the NV vectors
+// of the workgroup's group, so a multi-vector launch reads the links once per site block instead
+// of once per vector.  Two lanes per site as in the lean kernel.
+template <typename T, typename LT, int NV>
+__global__ __launch_bounds__(SCG_BLOCK) void hop_multi_kernel(Geom g, const typename LinkLoad<LT>::Store* __restrict__ links,
+                                                              const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+                                                              int p, int nvec, int64_t nsb, EpiDev<T> e, int64_t cs) {
+    __shared__ double red_lds[NV * (SCG_BLOCK / SCG_WAVE)];
+    zoff_hop(cs, links, in, out, e);
+    if (e.gate_m && e.gate_i > *e.gate_m) return;
+    if (e.kappa2_dev) e.kappa2 = (T)*e.kappa2_dev;
+    const int nvg = (nvec + NV - 1) / NV;
+    const int64_t nblk = nsb * nvg;
+    const int64_t logical = xcd_logical_block(nblk);
+    if (logical >= nblk) return;
+    const int vg = (int)(logical % nvg);
+    const int64_t sb = logical / nvg;
+    const int64_t Vh = g.Vh;
+    const int64_t tid = sb * SCG_BLOCK + threadIdx.x;
+    const int64_t h = tid >> 1;
+    const int bwd = (int)(tid & 1);
+    const bool active = h < Vh;
+    const int step = bwd ? -1 : 1;
+    const T sd = bwd ? (T)-1 : (T)1;
+
+    int x = 0, y = 0, z = 0, t = 0, xh = 0;
+    int64_t row = 0;
+    if (active) {
+        xh = (int)(h % g.Lxh);
+        int64_t r = h / g.Lxh;
+        y = (int)(r % g.L[1]);
+        r /= g.L[1];
+        z = (int)(r % g.L[2]);
+        t = (int)(r / g.L[2]);
+        x = 2 * xh + ((y + z + t + p) & 1);
+        row = h - xh;
+    }
+    const uint32_t lpar = bwd ? 1u - (uint32_t)p : (uint32_t)p;
+    const uint32_t Vh32 = (uint32_t)Vh, h32 = (uint32_t)h;
+
+    // the group's vectors (-1: empty slot, or a vector whose CG is done or frozen)
+    int vec[NV];
+    bool any = false;
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+        const int slot = vg * NV + v;
+        int q = -1;
+        if (slot < nvec) {
+            q = e.vec_map ? e.vec_map[slot] : slot;
+            if (q >= 0 && e.cg && (e.cg[q].done || e.cg[q].frozen)) q = -1;
+        }
+        vec[v] = q;
+        any = any || q >= 0;
+    }
+    if (!any) return;  // uniform over the workgroup
+
+    cx<T> acc[NV][12];
+#pragma unroll
+    for (int v = 0; v < NV; v++)
+#pragma unroll
+        for (int c = 0; c < 12; c++) acc[v][c] = mk<T>(0, 0);
+    if (active) {
+#pragma unroll 1
+        for (int mu = 0; mu < 4; mu++) {
+            const Nb n = neighbour(g, mu, step, x, y, z, t, xh, row);
+            const uint32_t hn = (uint32_t)n.h;
+            const uint32_t hl = bwd ? hn : h32;
+            const Proj pr = proj_of(mu);
+            const uint32_t a0 = (uint32_t)pr.a0, a1 = 5u - a0;
+            // M[a][b] = U[a][b] (forward) or conj(U[b][a]) (backward), loaded once
+            const typename LinkLoad<LT>::Store* __restrict__ lk = links + (size_t)(mu * 2) * 9 * Vh;
+            const uint32_t lane_off = lpar * 9u * Vh32 + hl;
+            cx<T> m[9];
+#pragma unroll
+            for (int a = 0; a < 3; a++)
+#pragma unroll
+                for (int b = 0; b < 3; b++) {
+                    const uint32_t idx = bwd ? (uint32_t)(b * 3 + a) : (uint32_t)(a * 3 + b);
+                    cx<T> u = LinkLoad<LT>::template get32<T>(lk, lane_off + idx * Vh32);
+                    if (bwd) u.im = -u.im;
+                    m[a * 3 + b] = u;
+                }
+            const T sign = (T)n.sign;
+            const bool b1 = pr.b0 == 1;
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                if (vec[v] < 0) continue;
+                const cx<T>* src = in + (size_t)vec[v] * 12 * Vh;
+                cx<T> hp[2][3];
+#pragma unroll
+                for (int a = 0; a < 3; a++) {
+                    hp[0][a] = sign * fma_u(sd, pr.c0, ld32(src + (size_t)(3 * a0 + a) * Vh, hn), ld32(src + (size_t)a * Vh, hn));
+                    hp[1][a] = sign * fma_u(sd, pr.c1, ld32(src + (size_t)(3 * a1 + a) * Vh, hn), ld32(src + (size_t)(3 + a) * Vh, hn));
+                }
+#pragma unroll
+                for (int a = 0; a < 3; a++) {
+                    cx<T> c0 = mk<T>(0, 0), c1 = mk<T>(0, 0);
+#pragma unroll
+                    for (int b = 0; b < 3; b++) {
+                        c0 = c0 + cmul(m[a * 3 + b], hp[0][b]);
+                        c1 = c1 + cmul(m[a * 3 + b], hp[1][b]);
+                    }
+                    acc[v][a] = acc[v][a] + c0;
+                    acc[v][3 + a] = acc[v][3 + a] + c1;
+                    acc[v][6 + a] = fma_u(sd, pr.d0, b1 ? c1 : c0, acc[v][6 + a]);
+                    acc[v][9 + a] = fma_u(sd, pr.d1, b1 ? c0 : c1, acc[v][9 + a]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+#pragma unroll
+        for (int c = 0; c < 12; c++) {
+            acc[v][c].re += __shfl_xor(acc[v][c].re, 1);
+            acc[v][c].im += __shfl_xor(acc[v][c].im, 1);
+        }
+        double part = 0.0;
+        if (active && vec[v] >= 0) {
+            const size_t vo = (size_t)vec[v] * 12 * Vh;
+            double czd = e.cz_host;
+            if (e.cz_dev) czd = e.cz_negate ? -e.cz_dev[vec[v]] : e.cz_dev[vec[v]];
+            const uint32_t lo = (uint32_t)bwd * 6u * Vh32 + h32;
+            cx<T> w[6];
+#pragma unroll
+            for (int c = 0; c < 6; c++) w[c] = bwd ? acc[v][6 + c] : acc[v][c];
+            part = epilogue2<T>(e, w, bwd, vo, Vh, lo, out, (T)czd);
+        }
+        if (e.red) {
+            for (int off = SCG_WAVE / 2; off > 0; off >>= 1) part += __shfl_xor(part, off);
+            if ((threadIdx.x % SCG_WAVE) == 0) red_lds[v * (SCG_BLOCK / SCG_WAVE) + threadIdx.x / SCG_WAVE] = part;
+        }
+    }
+    if (e.red) {
+        __syncthreads();
+        const int v = threadIdx.x;
+        if (v < NV) {
+            int q = -1;
+#pragma unroll
+            for (int k = 0; k < NV; k++)
+                if (k == v) q = vec[k];
+            if (q >= 0) {
+                double s = 0.0;
+                for (int w = 0; w < SCG_BLOCK / SCG_WAVE; w++) s += red_lds[v * (SCG_BLOCK / SCG_WAVE) + w];
+                e.partials[(int64_t)q * nsb + sb] = s;
+            }
+        }
+    }
+}
+
 static int g_hoist = -1;
 bool hop_hoist_links() {
     if (g_hoist < 0) {
@@ -608,8 +788,10 @@ bool hop_hoist_links() {
 }
 void set_hop_hoist_links(bool on) { g_hoist = on ? 1 : 0; }
 
-// tps: 1, 2, 4 lanes per site (direction split), or 3 = the lean forward/backward variant (2 lanes)
-int hop_threads_per_site(int tps) { return tps == 3 ? 2 : tps; }
+// tps: 1, 2, 4 lanes per site (direction split), or the lean forward/backward variant (2 lanes)
+// with 1 (tps 3), 2 (tps 5) or 4 (tps 6) directions per pass
+// tps 7: the multi-vector variant (two lanes per site, links loaded once for vb vectors, vb 2 or 4)
+int hop_threads_per_site(int tps) { return (tps == 3 || tps == 5 || tps == 6 || tps == 7) ? 2 : tps; }
 int hop_site_blocks(const Geom& g, int tps) {
     return (int)((g.Vh * hop_threads_per_site(tps) + SCG_BLOCK - 1) / SCG_BLOCK);
 }
@@ -639,16 +821,30 @@ static void launch_t(const Geom& g, const void* links, const void* in, void* out
     const int64_t nsb = hop_site_blocks(g, tps);
     vb = vb < 1 ? 1 : (vb > nvec ? nvec : vb);
     vb = vb > HOP_MAX_VB ? HOP_MAX_VB : vb;
+    if (tps == 5 || tps == 6) vb = 1;
+    if (tps == 7) vb = vb <= 2 ? 2 : 4;
     const int64_t grid = xcd_grid(nsb * ((nvec + vb - 1) / vb));
     using S = typename LinkLoad<LT>::Store;
     // links kept in registers across the vectors of a workgroup when one lane holds one direction
     const bool hoist = tps == 4 && hop_hoist_links();
     if (tps == 3 && vb == 1)
-        hipLaunchKernelGGL((hop_lean_kernel<T, LT, true>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
+        hipLaunchKernelGGL((hop_lean_kernel<T, LT, true, 1>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
                            (const cx<T>*)in, (cx<T>*)out, p, nvec, vb, nsb, e, L.cs);
     else if (tps == 3)
-        hipLaunchKernelGGL((hop_lean_kernel<T, LT, false>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
+        hipLaunchKernelGGL((hop_lean_kernel<T, LT, false, 1>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
                            (const cx<T>*)in, (cx<T>*)out, p, nvec, vb, nsb, e, L.cs);
+    else if (tps == 7 && vb == 2)
+        hipLaunchKernelGGL((hop_multi_kernel<T, LT, 2>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
+                           (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e, L.cs);
+    else if (tps == 7)
+        hipLaunchKernelGGL((hop_multi_kernel<T, LT, 4>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
+                           (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e, L.cs);
+    else if (tps == 5)
+        hipLaunchKernelGGL((hop_lean_kernel<T, LT, true, 2>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
+                           (const cx<T>*)in, (cx<T>*)out, p, nvec, 1, nsb, e, L.cs);
+    else if (tps == 6)
+        hipLaunchKernelGGL((hop_lean_kernel<T, LT, true, 4>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
+                           (const cx<T>*)in, (cx<T>*)out, p, nvec, 1, nsb, e, L.cs);
     else if (tps == 1)
         hipLaunchKernelGGL((hop_kernel<T, LT, 1, false>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
                            (const cx<T>*)in, (cx<T>*)out, p, nvec, vb, nsb, e, L.cs);

@@ -1235,8 +1235,8 @@ void init_geometry(seedcg_s* h, const seedcg_params* p, const int32_t* dims) {
     // per workgroup; the vectors of a site block run as adjacent workgroups on one XCD
     h->tps64 = env_int("SEEDCG_TPS", 3);
     h->tps_lo = env_int("SEEDCG_TPS_LO", 3);
-    if (h->tps64 < 1 || h->tps64 > 4) h->tps64 = 4;
-    if (h->tps_lo < 1 || h->tps_lo > 4) h->tps_lo = 4;
+    if (h->tps64 < 1 || h->tps64 > 7) h->tps64 = 3;
+    if (h->tps_lo < 1 || h->tps_lo > 7) h->tps_lo = 3;
     h->vb64 = std::max(1, env_int("SEEDCG_VB", 1));
     h->vb_lo = std::max(1, env_int("SEEDCG_VB_LO", 1));
     h->tps64_multi = h->tps64;
@@ -1274,11 +1274,12 @@ void tune_shape(seedcg_s* h, bool low, int nvec, const void* x, void* y) {
             return;
         }
     }
-    std::vector<std::pair<int, int>> cand{{3, 1}, {4, 1}, {2, 1}, {1, 1}};
+    std::vector<std::pair<int, int>> cand{{3, 1}, {5, 1}, {6, 1}, {4, 1}, {2, 1}, {1, 1}};
     if (multi) {
         cand.push_back({4, 2});
         cand.push_back({4, 4});
-        cand.push_back({3, 2});
+        cand.push_back({7, 2});                 // links once per pair of vectors
+        if (low) cand.push_back({7, 4});        // (four FP64 vectors do not fit in registers)
     }
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
@@ -1667,6 +1668,38 @@ seedcg_status seedcg_batch_info(seedcg_batch_t b, int32_t* nclass, int32_t* clas
             tune[4 * k + 3] = lo ? h->vb_lo_multi : h->vb64_multi;
         }
     }
+    return SEEDCG_OK;
+}
+
+seedcg_status seedcg_batch_set_timing(seedcg_batch_t b, int32_t sample_every, int32_t max_samples) {
+    if (!b) return fail(nullptr, SEEDCG_ERR_ARG, "batch_set_timing: null batch");
+    for (auto h : b->cls) {
+        const seedcg_status st = seedcg_set_timing(h, sample_every, max_samples);
+        if (st != SEEDCG_OK) {
+            b->err = h->err;
+            return st;
+        }
+    }
+    return SEEDCG_OK;
+}
+
+seedcg_status seedcg_batch_get_timing(seedcg_batch_t b, double* out) {
+    if (!b) return fail(nullptr, SEEDCG_ERR_ARG, "batch_get_timing: null batch");
+    if (!out) {
+        b->err = "batch_get_timing: null pointer";
+        return SEEDCG_ERR_ARG;
+    }
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (auto h : b->cls) {
+        double o[5];
+        const seedcg_status st = seedcg_get_timing(h, o);
+        if (st != SEEDCG_OK) {
+            b->err = h->err;
+            return st;
+        }
+        for (int k = 0; k < 5; k++) acc[k] += o[k];
+    }
+    for (int k = 0; k < 5; k++) out[k] = acc[k];
     return SEEDCG_OK;
 }
 

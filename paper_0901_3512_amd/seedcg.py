@@ -81,6 +81,8 @@ def load_library():
                                       ctypes.POINTER(Params), ctypes.POINTER(H)]),
         "seedcg_solve_batch": (i32, [H, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(Report)]),
         "seedcg_batch_info": (i32, [H, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(dbl)]),
+        "seedcg_batch_set_timing": (i32, [H, i32, i32]),
+        "seedcg_batch_get_timing": (i32, [H, ctypes.POINTER(dbl)]),
         "seedcg_destroy_batch": (None, [H]),
         "seedcg_batch_last_error": (ctypes.c_char_p, [H]),
     }
@@ -99,7 +101,8 @@ def exported_symbols():
             "seedcg_update", "seedcg_train_precond", "seedcg_use_precond", "seedcg_set_precond_weights",
             "seedcg_get_precond_weights", "seedcg_apply_P", "seedcg_precond_loss_grad", "seedcg_set_timing",
             "seedcg_get_timing", "seedcg_release_basis", "seedcg_destroy", "seedcg_last_error", "seedcg_create_batch",
-            "seedcg_solve_batch", "seedcg_batch_info", "seedcg_destroy_batch", "seedcg_batch_last_error"]
+            "seedcg_solve_batch", "seedcg_batch_info", "seedcg_batch_set_timing", "seedcg_batch_get_timing",
+            "seedcg_destroy_batch", "seedcg_batch_last_error"]
 
 
 def _check_vec(t, Vh, name):
@@ -376,6 +379,19 @@ class SeedCGBatch:
         self._lib.seedcg_batch_info(self._h, None, cls, mc, tune)
         return dict(nclass=k, class_of=list(cls), m_cap=list(mc),
                     tune=[tuple(int(x) for x in tune[4 * i:4 * i + 4]) for i in range(k)])
+
+    def set_timing(self, sample_every, max_samples=4096):
+        rc = self._lib.seedcg_batch_set_timing(self._h, int(sample_every), int(max_samples))
+        if rc != 0:
+            raise SeedCGError(rc, self._lib.seedcg_batch_last_error(self._h).decode())
+
+    def get_timing(self):
+        """Sampled stencil launches over every shape class: dict(launches, ms, bytes, flops, seen)."""
+        out = (ctypes.c_double * 5)()
+        rc = self._lib.seedcg_batch_get_timing(self._h, out)
+        if rc != 0:
+            raise SeedCGError(rc, self._lib.seedcg_batch_last_error(self._h).decode())
+        return dict(launches=int(out[0]), ms=out[1], bytes=out[2], flops=out[3], seen=int(out[4]))
 
     def solve(self, B, X=None, raise_on_noconv=True):
         """B: list of (nrhs, Vh_c, 4, 3) complex128 CUDA tensors; returns (X list, per-config reports)."""

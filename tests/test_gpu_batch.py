@@ -144,3 +144,53 @@ def test_batch_argument_errors(cfgs):
     b = _batch(cfgs[:2], "fp64", m_max=100)
     with pytest.raises(ValueError):
         b.solve([cuda(cfgs[0]["B"])])
+
+
+def _member_inputs(name):
+    from synth.configs import batch_members, make_links, make_sources
+    m = {c.name: c for c in batch_members()}[name]
+    return make_links(m), make_sources(m)
+
+
+def _c4_kappas_ready():
+    import json
+    from synth import configs
+    path = configs._KAPPA_FILE
+    if not os.path.exists(path):
+        return False
+    tab = json.load(open(path))
+    return all(m.name in tab for m in configs.batch_members())
+
+
+@pytest.mark.skipif(not _c4_kappas_ready(), reason="the oracle's kappa search has not covered every batch member")
+def test_c4_full_batch_sampled_against_oracle():
+    """The batched workload at its full size (64 configurations, 12 point sources each, mixed precision),
+    in the launch configuration the benchmark times: every right-hand side reports an FP64 true residual
+    <= 1e-10, and for one member of every shape the oracle's M confirms it on all 12 solutions."""
+    from paper_0901_3512_amd import SeedCG, SeedCGBatch
+    from synth.configs import batch_members, kappa_for
+    import torch
+    members = batch_members()
+    print_case("c4 full batch", len(members))
+    inputs = [_member_inputs(m.name) for m in members]   # host only (this process already uses the GPU)
+    kappas = [kappa_for(m) for m in members]
+    links = [cuda(U) for U, _ in inputs]
+    B = []
+    for m, k, (U, phi), Ud in zip(members, kappas, inputs, links):
+        s = SeedCG(Ud, m.dims, k, autotune=False)
+        B.append(s.apply_A(cuda(phi), dagger=True))
+        s.close()
+    b = SeedCGBatch(links, [m.dims for m in members], kappas, 12, prec="mixed", reorth_k=10)
+    X, reps = b.solve(B)
+    torch.cuda.synchronize()
+    worst = max(max(r["true_relres"]) for r in reps)
+    assert worst <= 1e-10, worst
+    seen = set()
+    for c, m in enumerate(members):
+        if m.dims in seen:
+            continue
+        seen.add(m.dims)
+        op = WilsonEO(inputs[c][0], m.dims, kappas[c])
+        res = osc.true_relres(matvec_M(op), flat(host(B[c])), flat(host(X[c])))
+        assert np.all(res <= 1e-10), (m.name, res)
+        print("c4", m.name, m.dims, "m", reps[c]["m"], "iters", reps[c]["iters"], "oracle relres", float(res.max()))

@@ -35,15 +35,18 @@ def round_bf16(a):
 
 @pytest.mark.parametrize("prec,rounder", [("mixed", round_fp32), ("mixed_bf16", round_bf16)])
 @pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 2, 6), (8, 8, 8, 16)])
-def test_inner_operator_matches_oracle_on_rounded_inputs(prec, rounder, dims):
+@pytest.mark.parametrize("shape", [("3", "1"), ("6", "1"), ("7", "2"), ("7", "4")])
+def test_inner_operator_matches_oracle_on_rounded_inputs(prec, rounder, dims, shape, monkeypatch):
     from paper_0901_3512_amd import SeedCG
-    print_case("inner", prec, dims)
+    print_case("inner", prec, dims, shape)
+    monkeypatch.setenv("SEEDCG_TPS_LO", shape[0])
+    monkeypatch.setenv("SEEDCG_VB_LO", shape[1])
     rng = np.random.default_rng(4)
     U = random_su3_links(dims, 0.4, rng)
     kappa = 0.13
     op = WilsonEO(rounder(U), dims, kappa)
     Vh = op.Vh
-    x = round_fp32(rng.standard_normal((2, Vh, 4, 3)) + 1j * rng.standard_normal((2, Vh, 4, 3)))
+    x = round_fp32(rng.standard_normal((5, Vh, 4, 3)) + 1j * rng.standard_normal((5, Vh, 4, 3)))
     s = SeedCG(cuda(U), dims, kappa, prec=prec)
     y = host(s.apply_M_inner(cuda(x)))
     assert relmax(y, op.apply_M(x)) <= 5e-6

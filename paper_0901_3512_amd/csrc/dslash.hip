@@ -137,6 +137,21 @@ __device__ inline void zoff_hop(int64_t cs, PL& links, PI& in, PO& out, EpiDev<T
     e.kappa2_dev = zoff(e.kappa2_dev, cs);
 }
 
+// Site-block visiting order of the two-lanes-per-site kernels.  A site block (128 sites) lies in
+// one t-slice when bps = sites per slice / 128 is whole; blocks are then visited in tiles of
+// SB_TILE_T consecutive slices with t fastest, so that the t-neighbours of a block were read by
+// the block just before it (instead of a whole slice of blocks earlier) and the z-neighbours a
+// few blocks away: both stay in L2.  With bps = 0 the order is the plain one.
+constexpr int SB_TILE_T = 4;
+__device__ inline int64_t sb_order(int64_t p, int64_t bps, int Lt) {
+    if (bps <= 0) return p;
+    const int64_t tile = bps * SB_TILE_T;
+    const int64_t t0 = (p / tile) * SB_TILE_T;
+    const int64_t r = p % tile;
+    const int64_t T = (t0 + SB_TILE_T <= Lt) ? SB_TILE_T : (Lt - t0);
+    return (t0 + r % T) * bps + r / T;
+}
+
 // neighbour (checkerboard index) of site (x,y,z,t) with index h in direction mu, step +-1, and the
 // boundary sign of that hop
 struct Nb {
@@ -531,7 +546,8 @@ __device__ inline void hop_dir_rt(const cx<T>* __restrict__ src, const typename 
 template <typename T, typename LT, bool ONE, int UNR>
 __global__ __launch_bounds__(SCG_BLOCK) void hop_lean_kernel(Geom g, const typename LinkLoad<LT>::Store* __restrict__ links,
                                                              const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
-                                                             int p, int nvec, int vb, int64_t nsb, EpiDev<T> e, int64_t cs) {
+                                                             int p, int nvec, int vb, int64_t nsb, EpiDev<T> e, int64_t cs,
+                                                             int64_t bps) {
     __shared__ double red_lds[HOP_MAX_VB * (SCG_BLOCK / SCG_WAVE)];
     zoff_hop(cs, links, in, out, e);
     if (e.gate_m && e.gate_i > *e.gate_m) return;
@@ -541,9 +557,9 @@ __global__ __launch_bounds__(SCG_BLOCK) void hop_lean_kernel(Geom g, const typen
     const int64_t logical = xcd_logical_block(nblk);
     if (logical >= nblk) return;
     const int vg = (int)(logical % nvg);
-    const int64_t sb = logical / nvg;
+    const int64_t sb = logical / nvg;   // position in the visiting order (partials are indexed by it)
     const int64_t Vh = g.Vh;
-    const int64_t tid = sb * SCG_BLOCK + threadIdx.x;
+    const int64_t tid = sb_order(sb, bps, g.L[3]) * SCG_BLOCK + threadIdx.x;
     const int64_t h = tid >> 1;
     const int bwd = (int)(tid & 1);
     const bool active = h < Vh;
@@ -634,7 +650,7 @@ __global__ __launch_bounds__(SCG_BLOCK) void hop_lean_kernel(Geom g, const typen
 template <typename T, typename LT, int NV>
 __global__ __launch_bounds__(SCG_BLOCK) void hop_multi_kernel(Geom g, const typename LinkLoad<LT>::Store* __restrict__ links,
                                                               const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
-                                                              int p, int nvec, int64_t nsb, EpiDev<T> e, int64_t cs) {
+                                                              int p, int nvec, int64_t nsb, EpiDev<T> e, int64_t cs, int64_t bps) {
     __shared__ double red_lds[NV * (SCG_BLOCK / SCG_WAVE)];
     zoff_hop(cs, links, in, out, e);
     if (e.gate_m && e.gate_i > *e.gate_m) return;
@@ -644,9 +660,9 @@ __global__ __launch_bounds__(SCG_BLOCK) void hop_multi_kernel(Geom g, const type
     const int64_t logical = xcd_logical_block(nblk);
     if (logical >= nblk) return;
     const int vg = (int)(logical % nvg);
-    const int64_t sb = logical / nvg;
+    const int64_t sb = logical / nvg;   // position in the visiting order (partials are indexed by it)
     const int64_t Vh = g.Vh;
-    const int64_t tid = sb * SCG_BLOCK + threadIdx.x;
+    const int64_t tid = sb_order(sb, bps, g.L[3]) * SCG_BLOCK + threadIdx.x;
     const int64_t h = tid >> 1;
     const int bwd = (int)(tid & 1);
     const bool active = h < Vh;
@@ -778,6 +794,15 @@ __global__ __launch_bounds__(SCG_BLOCK) void hop_multi_kernel(Geom g, const type
     }
 }
 
+static int g_order = -1;
+static bool getenv_order() {
+    if (g_order < 0) {
+        const char* v = getenv("SEEDCG_SB_ORDER");
+        g_order = v ? atoi(v) : 1;
+    }
+    return g_order != 0;
+}
+
 static int g_hoist = -1;
 bool hop_hoist_links() {
     if (g_hoist < 0) {
@@ -824,27 +849,30 @@ static void launch_t(const Geom& g, const void* links, const void* in, void* out
     if (tps == 5 || tps == 6) vb = 1;
     if (tps == 7) vb = vb <= 2 ? 2 : 4;
     const int64_t grid = xcd_grid(nsb * ((nvec + vb - 1) / vb));
+    // site blocks per t-slice for the tiled visiting order (two lanes per site, 128 sites a block)
+    const int64_t slice = g.Vh / g.L[3];
+    const int64_t bps = (slice % (SCG_BLOCK / 2) == 0 && getenv_order()) ? slice / (SCG_BLOCK / 2) : 0;
     using S = typename LinkLoad<LT>::Store;
     // links kept in registers across the vectors of a workgroup when one lane holds one direction
     const bool hoist = tps == 4 && hop_hoist_links();
     if (tps == 3 && vb == 1)
         hipLaunchKernelGGL((hop_lean_kernel<T, LT, true, 1>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
-                           (const cx<T>*)in, (cx<T>*)out, p, nvec, vb, nsb, e, L.cs);
+                           (const cx<T>*)in, (cx<T>*)out, p, nvec, vb, nsb, e, L.cs, bps);
     else if (tps == 3)
         hipLaunchKernelGGL((hop_lean_kernel<T, LT, false, 1>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
-                           (const cx<T>*)in, (cx<T>*)out, p, nvec, vb, nsb, e, L.cs);
+                           (const cx<T>*)in, (cx<T>*)out, p, nvec, vb, nsb, e, L.cs, bps);
     else if (tps == 7 && vb == 2)
         hipLaunchKernelGGL((hop_multi_kernel<T, LT, 2>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
-                           (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e, L.cs);
+                           (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e, L.cs, bps);
     else if (tps == 7)
         hipLaunchKernelGGL((hop_multi_kernel<T, LT, 4>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
-                           (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e, L.cs);
+                           (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e, L.cs, bps);
     else if (tps == 5)
         hipLaunchKernelGGL((hop_lean_kernel<T, LT, true, 2>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
-                           (const cx<T>*)in, (cx<T>*)out, p, nvec, 1, nsb, e, L.cs);
+                           (const cx<T>*)in, (cx<T>*)out, p, nvec, 1, nsb, e, L.cs, bps);
     else if (tps == 6)
         hipLaunchKernelGGL((hop_lean_kernel<T, LT, true, 4>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
-                           (const cx<T>*)in, (cx<T>*)out, p, nvec, 1, nsb, e, L.cs);
+                           (const cx<T>*)in, (cx<T>*)out, p, nvec, 1, nsb, e, L.cs, bps);
     else if (tps == 1)
         hipLaunchKernelGGL((hop_kernel<T, LT, 1, false>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
                            (const cx<T>*)in, (cx<T>*)out, p, nvec, vb, nsb, e, L.cs);

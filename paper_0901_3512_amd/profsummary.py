@@ -4,9 +4,9 @@
   python -m paper_0901_3512_amd.profsummary bytes  <fetch-dir> <write-dir> --kernel hop_kernel
 
 `bytes` averages FETCH_SIZE and WRITE_SIZE (KiB per dispatch) over the dispatches of the named
-kernel and scales each by what the same counter reads for a plain device copy of exactly 1 GiB
-(the benchmark's --copy-probe: a 1 GiB copy reads and writes 1,048,576 KiB), giving HBM bytes
-per launch.
+kernel that follow the copy probe and scales each by what the same counter reads for a plain
+device copy of exactly 1 GiB (the benchmark's --copy-probe, made just before its timed region: a
+1 GiB copy reads and writes 1,048,576 KiB), giving HBM bytes per launch of the timed region.
 """
 import argparse
 import csv
@@ -44,21 +44,23 @@ def _counter(d, name):
 
 
 def _copy_reference(rows):
-    """Counter value of the 1 GiB copy probe: the largest copy dispatches (the probe is by far the
-    largest copy of a benchmark run; smaller copies can share its grid size)."""
-    vals = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
-    top = max(vals)
-    big = [v for v in vals if v >= 0.9 * top]
-    return sum(big) / len(big)
+    """Counter value of the 1 GiB copy probe and the last dispatch id of the probe: the largest copy
+    dispatches (the probe is by far the largest copy of a benchmark run)."""
+    cp = [(float(r["Counter_Value"]), int(r["Dispatch_Id"])) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+    top = max(v for v, _ in cp)
+    big = [(v, d) for v, d in cp if v >= 0.9 * top]
+    return sum(v for v, _ in big) / len(big), max(d for _, d in big)
 
 
 def bytes_per_launch(fetch_dir, write_dir, kernel):
     f = _counter(fetch_dir, "FETCH_SIZE")
     w = _counter(write_dir, "WRITE_SIZE")
-    f_scale = GIB_KIB / _copy_reference(f)
-    w_scale = GIB_KIB / _copy_reference(w)
-    fk = [float(r["Counter_Value"]) for r in f if kernel in r["Kernel_Name"]]
-    wk = [float(r["Counter_Value"]) for r in w if kernel in r["Kernel_Name"]]
+    fref, fd = _copy_reference(f)
+    wref, wd = _copy_reference(w)
+    f_scale = GIB_KIB / fref
+    w_scale = GIB_KIB / wref
+    fk = [float(r["Counter_Value"]) for r in f if kernel in r["Kernel_Name"] and int(r["Dispatch_Id"]) > fd]
+    wk = [float(r["Counter_Value"]) for r in w if kernel in r["Kernel_Name"] and int(r["Dispatch_Id"]) > wd]
     fetch = sum(fk) / len(fk) * f_scale * 1024.0
     write = sum(wk) / len(wk) * w_scale * 1024.0
     return dict(fetch_scale=f_scale, write_scale=w_scale, dispatches=len(fk), fetch_bytes=fetch,

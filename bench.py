@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--sample-every", type=int, default=4, help="stencil launches per timed sample")
     ap.add_argument("--mbench", type=int, default=200, help="back-to-back M applications for D^dag D GB/s")
     ap.add_argument("--batch-n", type=int, default=64, help="c4: number of batch members (the workload has 64)")
+    ap.add_argument("--deflate", type=int, default=0, help="deflated CG with this many Ritz vectors (0: plain CG)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 1 GiB device copy first (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -77,7 +78,7 @@ def main():
     Ud = torch.from_numpy(U).to(dev)
     phid = torch.from_numpy(phi).to(dev)
     solver = SeedCG(Ud, cfg.dims, kappa, t_bc=cfg.t_bc, prec=prec, reorth_k=cfg.reorth_k, past=cfg.past,
-                    tol=cfg.tol, reliable_every=cfg.reliable_every)
+                    tol=cfg.tol, reliable_every=cfg.reliable_every, deflate=args.deflate)
     B = solver.apply_A(phid, dagger=True)   # b = A^dag phi (input preparation, not timed)
     nrhs = B.shape[0]
     torch.cuda.synchronize()
@@ -153,7 +154,8 @@ def main():
         "config": {"workload": f"Seed-CG {prec}, Wilson even-odd normal system M = A^dag A on "
                                f"{'x'.join(map(str, cfg.dims))}, {cfg.nrhs} RHS, tol {cfg.tol:g}, k={cfg.reorth_k}",
                    "name": cfg.name, "lattice": list(cfg.dims), "kappa": kappa, "nrhs": nrhs,
-                   "reorth_k": cfg.reorth_k, "past_factor": cfg.past, "tol": cfg.tol, "precision": prec},
+                   "reorth_k": cfg.reorth_k, "past_factor": cfg.past, "tol": cfg.tol, "precision": prec,
+                   "deflate": args.deflate},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "detail": {"m": rs["m"], "i_conv": rs["i_conv"], "seed_status": rs["seed_status"],

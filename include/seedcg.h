@@ -72,6 +72,9 @@ typedef struct {
     int32_t autotune;         /* 1: choose the stencil launch shapes (lanes per site, vectors per
                                  workgroup) by timing the candidates once per lattice shape;
                                  0: the fixed default (two lanes per site, one vector each)     */
+    int32_t deflate;          /* 0: plain CG in solve_rest; n > 0: deflated CG with the n (<= 24)
+                                 lowest Ritz vectors of the last solve_seed's T, lifted by its
+                                 stored basis (one configuration, no learned preconditioner)      */
     void* stream;             /* hipStream_t; NULL = the null stream                             */
 } seedcg_params;
 
@@ -90,7 +93,8 @@ typedef struct {
 } seedcg_report;
 
 /* Fills *p with the defaults: t_bc = -1, FP64, m_max = 0, reorth_k = 10, past_factor = 1.5,
-   tol = 1e-10, reliable_every = 50, seed_block = 32, max_iter = 100000, precond = 0, autotune = 1. */
+   tol = 1e-10, reliable_every = 50, seed_block = 32, max_iter = 100000, precond = 0, autotune = 1,
+   deflate = 0. */
 void seedcg_default_params(seedcg_params* p);
 
 /* Creates a solver for one gauge configuration.  links: device, 4*V*9 complex (layout above),
@@ -125,6 +129,14 @@ seedcg_status seedcg_solve_rest(seedcg_t h, const double* B, double* X, int32_t 
    alpha[0..m-1] and beta_0..beta_m into beta[0..m]; cap is the length of alpha (beta needs cap+1).
    *m receives m.  Eq. (2) defines T from these. */
 seedcg_status seedcg_get_tridiag(seedcg_t h, double* alpha, double* beta, int32_t cap, int32_t* m);
+
+/* Deflated CG (params.deflate = n > 0; the paper's motivation: seeding deflates the small
+   eigenvalues, section 1): solve_rest takes W = the n lowest Ritz vectors V s_k of the last
+   solve_seed's T (T s_k = theta_k s_k, Eq. 2), starts from x += W (W^dag M W)^{-1} W^dag r and keeps
+   every CG direction M-orthogonal to W (p = r + b p - W (W^dag M W)^{-1} (M W)^dag r; Saad, Yeung,
+   Erhel and Guyomarc'h, 2000).  Copies the Ritz values theta_k of the W in use (ascending) to the
+   HOST array theta (cap entries); *n receives how many there are (0 before a deflated solve_rest). */
+seedcg_status seedcg_get_ritz(seedcg_t h, double* theta, int32_t cap, int32_t* n);
 
 /* Copies basis vector v_i (1 <= i <= m, as stored after any reorthogonalisation) to the
    device vector v in the even-site layout. */

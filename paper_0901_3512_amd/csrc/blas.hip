@@ -872,6 +872,40 @@ void cg_p(bool fp32, const CgVec* cg, const int32_t* vec_map, int nact, void* P,
                            (int)ignore_frozen, L.cs);
 }
 
+// Deflated CG (coefficients of the deflation space in a direction or an iterate): one workgroup.
+__global__ void defl_mu_kernel(const cx<double>* Ginv, const cx<double>* P, int nev, int ncol, const int32_t* map, int w,
+                               const CgVec* cg, double sign, cx<double>* E, int64_t cs) {
+    __shared__ int sel[32];
+    P = zoff(P, cs);
+    E = zoff(E, cs);
+    Ginv = zoff(Ginv, cs);
+    map = zoff(map, cs);
+    cg = zoff(cg, cs);
+    if (threadIdx.x < 32) sel[threadIdx.x] = 0;
+    __syncthreads();
+    if ((int)threadIdx.x < w) {
+        const int j = map ? map[threadIdx.x] : (int)threadIdx.x;
+        if (j >= 0 && j < ncol && !(cg && (cg[j].done || cg[j].frozen))) sel[j] = 1;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < nev * ncol; q += blockDim.x) {
+        const int k = q / ncol, j = q % ncol;
+        double sr = 0.0, si = 0.0;
+        if (sel[j])
+            for (int l = 0; l < nev; l++) {
+                const cx<double> g = Ginv[k * nev + l], pv = P[l * ncol + j];
+                sr += g.re * pv.re - g.im * pv.im;
+                si += g.re * pv.im + g.im * pv.re;
+            }
+        E[q] = mk<double>(sign * sr, sign * si);
+    }
+}
+void defl_mu(const double* Ginv, const double* P, int nev, int ncol, const int32_t* map, int w, const CgVec* cg, double sign,
+             double* E, const Launch& L) {
+    hipLaunchKernelGGL(defl_mu_kernel, dim3(1, 1, L.nz), dim3(256), 0, L.s, (const cx<double>*)Ginv, (const cx<double>*)P, nev, ncol,
+                       map, w, cg, sign, (cx<double>*)E, L.cs);
+}
+
 // gamma5 = diag(1, 1, -1, -1): components 6..11 (spins 2, 3) change sign
 template <typename T>
 __global__ void gamma5_copy_kernel(const cx<T>* a, cx<T>* b, int64_t Vh, int64_t total, int64_t cs) {

@@ -96,6 +96,12 @@ void k_zero_odd(void* full, int64_t n, int nvec, hipStream_t s);
 void k_residual(const void* zfull, const void* u, const double* unorm2, void* gfull, int64_t n, int S, double* part, hipStream_t s);
 int64_t k_residual_blocks(int64_t n);
 void k_adam(double* Wm, void* W32, double* G, double* m, double* v, int t, double lr, int n, hipStream_t s);
-void k_combine(bool v32, const void* V, int m, const double* S, int nout, void* X, int64_t n, hipStream_t s);
+// X = V S for nout <= 16 outputs (S: m x nout row-major); X in FP32, or FP64 with x64
+void k_combine(bool v32, const void* V, int m, const double* S, int nout, void* X, int64_t n, hipStream_t s, bool x64 = false);
+// deflated CG: E[k][j] = sign * sum_l Ginv[k][l] P[l][j] for the columns j listed in map (w entries,
+// -1 = none) whose CG record (if cg is given) is neither done nor frozen; 0 in every other column.
+// Ginv: nev x nev, P and E: nev x ncol, complex FP64 row-major; ncol <= 32.
+void defl_mu(const double* Ginv, const double* P, int nev, int ncol, const int32_t* map, int w, const CgVec* cg, double sign,
+             double* E, const Launch& L);
 
 }  // namespace scg

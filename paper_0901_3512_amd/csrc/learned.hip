@@ -308,9 +308,9 @@ void k_adam(double* Wm, void* W32, double* G, double* m, double* v, int t, doubl
 }
 
 // X[j] = sum_{r < m} V[r] S[r][j], j < nout (<= 16): Ritz vectors u = V s from the stored basis
-template <typename TV>
+template <typename TV, typename TO>
 __global__ __launch_bounds__(256) void k_combine_kernel(const cx<TV>* __restrict__ V, int m, const double* __restrict__ S, int nout,
-                                                        cx<float>* __restrict__ X, int64_t n) {
+                                                        cx<TO>* __restrict__ X, int64_t n) {
     __shared__ double sl[256 * 16];
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double ar[16], ai[16];
@@ -335,14 +335,18 @@ __global__ __launch_bounds__(256) void k_combine_kernel(const cx<TV>* __restrict
     if (k < n)
 #pragma unroll
         for (int j = 0; j < 16; j++)
-            if (j < nout) X[(int64_t)j * n + k] = mk<float>((float)ar[j], (float)ai[j]);
+            if (j < nout) X[(int64_t)j * n + k] = mk<TO>((TO)ar[j], (TO)ai[j]);
 }
-void k_combine(bool v32, const void* V, int m, const double* S, int nout, void* X, int64_t n, hipStream_t s) {
+void k_combine(bool v32, const void* V, int m, const double* S, int nout, void* X, int64_t n, hipStream_t s, bool x64) {
     const dim3 grid((unsigned)((n + 255) / 256));
-    if (v32)
-        hipLaunchKernelGGL(k_combine_kernel<float>, grid, dim3(256), 0, s, (const cx<float>*)V, m, S, nout, (cx<float>*)X, n);
+    if (v32 && !x64)
+        hipLaunchKernelGGL((k_combine_kernel<float, float>), grid, dim3(256), 0, s, (const cx<float>*)V, m, S, nout, (cx<float>*)X, n);
+    else if (v32)
+        hipLaunchKernelGGL((k_combine_kernel<float, double>), grid, dim3(256), 0, s, (const cx<float>*)V, m, S, nout, (cx<double>*)X, n);
+    else if (!x64)
+        hipLaunchKernelGGL((k_combine_kernel<double, float>), grid, dim3(256), 0, s, (const cx<double>*)V, m, S, nout, (cx<float>*)X, n);
     else
-        hipLaunchKernelGGL(k_combine_kernel<double>, grid, dim3(256), 0, s, (const cx<double>*)V, m, S, nout, (cx<float>*)X, n);
+        hipLaunchKernelGGL((k_combine_kernel<double, double>), grid, dim3(256), 0, s, (const cx<double>*)V, m, S, nout, (cx<double>*)X, n);
 }
 
 }  // namespace scg

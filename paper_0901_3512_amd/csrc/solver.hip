@@ -12,6 +12,7 @@
 // The result is the paper's step 7 exactly, summed in another order.
 #include <algorithm>
 #include <chrono>
+#include <complex>
 #include <map>
 #include <mutex>
 #include <thread>
@@ -169,6 +170,12 @@ struct seedcg_s {
     bool k_ready = false;
     bool k_accepted = false;   // the trained K passed the acceptance test (loss at most halved)
     DBuf kW32, kWm, kG, kAm, kAv, kpart, klinks32, kU, kY, kun2, klpart, kS, kfield, pfa, pfb, Zv, rzpart;
+    // deflated CG: W (the lowest Ritz vectors of T lifted by V), Z = M W, (W^dag M W)^{-1},
+    // coefficient blocks, Ritz coefficients
+    DBuf dW, dZ, dGinv, dP, dE, dS;
+    int nev = 0;
+    bool defl_stale = true;   // a seed solve ran since W was built
+    std::vector<double> ritz_theta;
     int k_steps = 0, k_train_vecs = 0, k_ritz = 0;
     double k_loss0 = 0.0, k_loss1 = 0.0, k_t_train = 0.0;
     // sampled timing of the stencil launches (hipEvent pairs on the handle's stream)
@@ -636,6 +643,7 @@ void solve_seed_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report* rep) {
     HIPCHK(hipStreamSynchronize(h->s));
     h->m_used = m_max;
     h->have_seed = true;
+    h->defl_stale = true;
     h->seed_nrhs = nrhs;
     if (rep) {
         const double t = now_s() - t0;
@@ -942,6 +950,130 @@ void alloc_rest(seedcg_s* h, int nrhs) {
     ensure_work(h, nrhs);
 }
 
+// ---------------------------------------------------------------------------------------------
+// deflated CG from the Ritz vectors of the last seed solve (Saad, Yeung, Erhel and Guyomarc'h):
+// W = the nev lowest Ritz vectors V s_k of T, Z = M W, G = W^dag Z;  every direction is made
+// M-orthogonal to W by p -= W G^{-1} Z^dag r, and the start is x += W G^{-1} W^dag r.
+// ---------------------------------------------------------------------------------------------
+std::vector<std::complex<double>> invert_hpd(std::vector<std::complex<double>> A, int n) {
+    // Gauss-Jordan with partial pivoting (n <= 24)
+    std::vector<std::complex<double>> I((size_t)n * n, 0.0);
+    for (int i = 0; i < n; i++) I[(size_t)i * n + i] = 1.0;
+    for (int c = 0; c < n; c++) {
+        int piv = c;
+        for (int r = c + 1; r < n; r++)
+            if (std::abs(A[(size_t)r * n + c]) > std::abs(A[(size_t)piv * n + c])) piv = r;
+        if (!(std::abs(A[(size_t)piv * n + c]) > 0.0)) throw StateError{"deflation: W^dag M W is singular"};
+        for (int k = 0; k < n; k++) {
+            std::swap(A[(size_t)c * n + k], A[(size_t)piv * n + k]);
+            std::swap(I[(size_t)c * n + k], I[(size_t)piv * n + k]);
+        }
+        const std::complex<double> d = 1.0 / A[(size_t)c * n + c];
+        for (int k = 0; k < n; k++) {
+            A[(size_t)c * n + k] *= d;
+            I[(size_t)c * n + k] *= d;
+        }
+        for (int r = 0; r < n; r++)
+            if (r != c) {
+                const std::complex<double> f = A[(size_t)r * n + c];
+                if (f == 0.0) continue;
+                for (int k = 0; k < n; k++) {
+                    A[(size_t)r * n + k] -= f * A[(size_t)c * n + k];
+                    I[(size_t)r * n + k] -= f * I[(size_t)c * n + k];
+                }
+            }
+    }
+    return I;
+}
+
+ProjArgs defl_proj_args(seedcg_s* h, const void* rows, int nrows, const void* R, int nr) {
+    ProjArgs a{};
+    a.V = rows;
+    a.ldv = h->N;
+    a.nv = nrows;
+    for (int j = 0; j < nr; j++) a.R[j] = (const char*)R + (int64_t)j * h->vec_bytes(h->lo);
+    a.nr = nr;
+    a.n = h->N;
+    a.kchunk = kchunk_for(h->N, 1024);
+    a.part = h->projpart.as<double>();
+    a.part_stride = 2 * 32 * 24;
+    return a;
+}
+
+// W, Z = M W and G^{-1} from the tridiagonal and basis of the last seed solve (one configuration)
+void build_deflation(seedcg_s* h, int want) {
+    h->nev = 0;
+    h->ritz_theta.clear();
+    const int m = h->m_used;
+    want = std::min({want, m, 24});
+    if (want <= 0 || !h->basis.p) return;
+    const bool lo = h->lo;
+    const int64_t N = h->N;
+    const LzArrays A = h->arr();
+    std::vector<double> alpha(m), beta(m + 1);
+    HIPCHK(hipMemcpyAsync(alpha.data(), A.alpha + 1, m * sizeof(double), hipMemcpyDeviceToHost, h->s));
+    HIPCHK(hipMemcpyAsync(beta.data(), A.beta, (m + 1) * sizeof(double), hipMemcpyDeviceToHost, h->s));
+    HIPCHK(hipStreamSynchronize(h->s));
+    std::vector<double> off(beta.begin() + 1, beta.begin() + m), lam, Sv;
+    ritz_lowest(alpha, off, want, lam, Sv);
+    const int nev = (int)lam.size();
+    if (nev == 0) return;
+    h->dW.ensure((int64_t)nev * h->vec_bytes(lo));
+    h->dZ.ensure((int64_t)nev * h->vec_bytes(lo));
+    // u_k = V s_k, at most 16 per pass
+    for (int k0 = 0; k0 < nev; k0 += 16) {
+        const int nk = std::min(16, nev - k0);
+        std::vector<double> S((size_t)m * nk);
+        for (int i = 0; i < m; i++)
+            for (int k = 0; k < nk; k++) S[(size_t)i * nk + k] = Sv[(size_t)i * nev + k0 + k];
+        h->dS.ensure(S.size() * sizeof(double));
+        HIPCHK(hipMemcpyAsync(h->dS.p, S.data(), S.size() * sizeof(double), hipMemcpyHostToDevice, h->s));
+        k_combine(lo, h->basis.p, m, h->dS.as<double>(), nk, (char*)h->dW.p + (int64_t)k0 * h->vec_bytes(lo), N, h->s, !lo);
+        HIPCHK(hipStreamSynchronize(h->s));  // dS is reused by the next pass
+    }
+    apply_M_int(h, lo, h->dW.p, h->dZ.p, nev, MOpts{});
+    h->dP.ensure((size_t)2 * 32 * 24 * sizeof(double));
+    h->dE.ensure((size_t)2 * 32 * 24 * sizeof(double));
+    h->dGinv.ensure((size_t)2 * nev * nev * sizeof(double));
+    project(lo, defl_proj_args(h, h->dW.p, nev, h->dZ.p, nev), 1, h->dP.as<double>(), h->L(), true);
+    std::vector<std::complex<double>> G((size_t)nev * nev);
+    HIPCHK(hipMemcpyAsync(G.data(), h->dP.p, G.size() * sizeof(std::complex<double>), hipMemcpyDeviceToHost, h->s));
+    HIPCHK(hipStreamSynchronize(h->s));
+    for (int i = 0; i < nev; i++)   // G is Hermitian: keep its Hermitian part
+        for (int j = i; j < nev; j++) {
+            const std::complex<double> g = 0.5 * (G[(size_t)i * nev + j] + std::conj(G[(size_t)j * nev + i]));
+            G[(size_t)i * nev + j] = g;
+            G[(size_t)j * nev + i] = std::conj(g);
+        }
+    const std::vector<std::complex<double>> Gi = invert_hpd(G, nev);
+    HIPCHK(hipMemcpyAsync(h->dGinv.p, Gi.data(), Gi.size() * sizeof(std::complex<double>), hipMemcpyHostToDevice, h->s));
+    HIPCHK(hipStreamSynchronize(h->s));
+    h->nev = nev;
+    h->ritz_theta = lam;
+}
+
+// init: X += W G^{-1} W^dag R (all nrhs vectors);  otherwise: X -= W G^{-1} Z^dag R for the vectors
+// of map (w entries) whose CG record is running.  R in the working precision.
+void deflate_step(seedcg_s* h, bool init, const void* R, int nrhs, const int32_t* map, int w, void* X, bool x32,
+                  bool use_cg = true) {
+    const bool lo = h->lo;
+    project(lo, defl_proj_args(h, init ? h->dW.p : h->dZ.p, h->nev, R, nrhs), 1, h->dP.as<double>(), h->L(), true);
+    defl_mu(h->dGinv.as<double>(), h->dP.as<double>(), h->nev, nrhs, map, w, (init || !use_cg) ? nullptr : h->cgv.as<CgVec>(),
+            init ? 1.0 : -1.0, h->dE.as<double>(), h->L());
+    seed_update(lo, x32, h->dW.p, h->nev, h->dE.as<double>(), X, nrhs, h->N, nullptr, h->L());
+}
+
+// After a residual replacement: r is b - M x again and no longer exactly orthogonal to W; move the
+// listed vectors back, x += W G^{-1} W^dag r and r -= Z G^{-1} W^dag r (Z = M W, so r stays b - M x).
+void redeflate(seedcg_s* h, void* Rw, int nrhs, const int32_t* map, int w) {
+    const bool lo = h->lo;
+    project(lo, defl_proj_args(h, h->dW.p, h->nev, Rw, nrhs), 1, h->dP.as<double>(), h->L(), true);
+    defl_mu(h->dGinv.as<double>(), h->dP.as<double>(), h->nev, nrhs, map, w, nullptr, 1.0, h->dE.as<double>(), h->L());
+    seed_update(lo, false, h->dW.p, h->nev, h->dE.as<double>(), h->Xint.p, nrhs, h->N, nullptr, h->L());
+    defl_mu(h->dGinv.as<double>(), h->dP.as<double>(), h->nev, nrhs, map, w, nullptr, -1.0, h->dE.as<double>(), h->L());
+    seed_update(lo, lo, h->dZ.p, h->nev, h->dE.as<double>(), Rw, nrhs, h->N, nullptr, h->L());
+}
+
 // One iteration of (preconditioned) CG on the nact vectors of the device map vmap.
 void cg_iteration(seedcg_s* h, bool lo, bool pc, int nact, int nalloc, int64_t nb, int max_iter, void* Rw) {
     const Launch L = h->L();
@@ -964,6 +1096,7 @@ void cg_iteration(seedcg_s* h, bool lo, bool pc, int nact, int nalloc, int64_t n
     } else {
         cg_beta(h->cgv.as<CgVec>(), h->rrpart.as<double>(), nb, h->vmap.as<int32_t>(), nact, max_iter, L);
         cg_p(lo, h->cgv.as<CgVec>(), h->vmap.as<int32_t>(), nact, h->Pv.p, Rw, h->N, false, L);
+        if (h->nev) deflate_step(h, false, Rw, nalloc, h->vmap.as<int32_t>(), nact, h->Pv.p, lo);
     }
 }
 
@@ -1013,6 +1146,14 @@ seedcg_status solve_rest_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report
     alloc_rest(h, nrhs);
     const int64_t nb = norm2_blocks(N);
     void* Rw = lo ? h->Rv.p : h->R64.p;  // the recursive residual
+    // deflated CG from the Ritz vectors of the last seed solve (one configuration, no learned P)
+    const bool want_defl = h->p.deflate > 0 && C == 1 && h->have_seed && !(h->p.precond == 1 && h->k_ready && h->k_accepted);
+    if (!want_defl)
+        h->nev = 0;
+    else if (h->defl_stale || h->nev == 0) {
+        build_deflation(h, h->p.deflate);
+        h->defl_stale = false;
+    }
     // buffers may have moved since the graphs were captured
     h->drop_graphs();
 
@@ -1031,6 +1172,15 @@ seedcg_status solve_rest_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report
     HIPCHK(hipStreamSynchronize(h->s));
     auto bn = [&](int c, int j) { return hn[(size_t)c * 2 * nrhs + j]; };
     auto rr_of = [&](int c, int j) { return hn[(size_t)c * 2 * nrhs + nrhs + j]; };
+    if (h->nev) {
+        // the deflated start x += W G^{-1} W^dag r, then the true residuals again
+        if (lo) convert(false, true, h->R64.p, h->Rv.p, nrhs * N, L);
+        deflate_step(h, true, Rw, nrhs, nullptr, nrhs, h->Xint.p, false);
+        np = true_residual(h, all, h->R64.p, h->cgpart.as<double>());
+        sum_partials(h->cgpart.as<double>(), np, nrhs, h->norms.as<double>() + nrhs, false, L);
+        from_cfg(h, hn.data(), h->norms.p, 2 * nrhs * sizeof(double));
+        HIPCHK(hipStreamSynchronize(h->s));
+    }
 
     std::vector<CgVec> cg((size_t)C * nrhs);
     std::vector<int> matvecs((size_t)C * nrhs, 1);
@@ -1074,6 +1224,7 @@ seedcg_status solve_rest_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report
         convert(lo, lo, h->Zv.p, h->Pv.p, nrhs * N, L);  // p = z
     } else {
         convert(lo, lo, Rw, h->Pv.p, nrhs * N, L);  // p = r
+        if (h->nev) deflate_step(h, false, Rw, nrhs, nullptr, nrhs, h->Pv.p, lo, false);  // p = r - W mu
     }
     to_cfg(h, h->cgv.p, cg.data(), nrhs * sizeof(CgVec));
 
@@ -1182,6 +1333,10 @@ seedcg_status solve_rest_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report
             const int w = upload_map(h, h->tmap, reload);
             if (w) convert_map(false, true, h->R64.p, h->Rv.p, N, h->tmap.as<int32_t>(), w, L);
         }
+        if (h->nev) {
+            const int w = upload_map(h, h->tmap, reload);
+            if (w) redeflate(h, Rw, nrhs, h->tmap.as<int32_t>(), w);
+        }
         if (pc && !restart[0].empty()) {
             // preconditioned restart from the new residual: z = P r, p = z, rz = r^dag z
             const std::vector<double> rz = precondition(restart[0]);
@@ -1193,6 +1348,7 @@ seedcg_status solve_rest_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report
         to_cfg(h, h->cgv.p, cg.data(), nrhs * sizeof(CgVec));
         const int wr = upload_map(h, h->rmap, restart);
         if (wr) cg_p(lo, h->cgv.as<CgVec>(), h->rmap.as<int32_t>(), wr, h->Pv.p, pc ? h->Zv.p : Rw, N, false, L);
+        if (wr && h->nev) deflate_step(h, false, Rw, nrhs, h->rmap.as<int32_t>(), wr, h->Pv.p, lo);
     }
     unpack_out(h, io, h->Xint.p, nrhs);
     // final FP64 true residuals for the report
@@ -1427,6 +1583,7 @@ void seedcg_default_params(seedcg_params* p) {
     p->seed_block = 32;
     p->max_iter = 100000;
     p->autotune = 1;
+    p->deflate = 0;
 }
 
 seedcg_status seedcg_create(const seedcg_params* p, const double* links, seedcg_t* out) {
@@ -1799,6 +1956,18 @@ seedcg_status seedcg_get_tridiag(seedcg_t h, double* alpha, double* beta, int32_
         HIPCHK(hipMemcpyAsync(alpha, A.alpha + 1, h->m_used * sizeof(double), hipMemcpyDeviceToHost, h->s));
         HIPCHK(hipMemcpyAsync(beta, A.beta, (h->m_used + 1) * sizeof(double), hipMemcpyDeviceToHost, h->s));
         HIPCHK(hipStreamSynchronize(h->s));
+        return SEEDCG_OK;
+    });
+}
+
+seedcg_status seedcg_get_ritz(seedcg_t h, double* theta, int32_t cap, int32_t* n) {
+    if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "get_ritz: null handle");
+    return guarded(h, [&]() -> seedcg_status {
+        if (!n) throw ArgError{"get_ritz: null n"};
+        *n = h->nev;
+        if (!theta) return SEEDCG_OK;
+        if (cap < h->nev) throw ArgError{"get_ritz: cap < n"};
+        for (int k = 0; k < h->nev; k++) theta[k] = h->ritz_theta[k];
         return SEEDCG_OK;
     });
 }

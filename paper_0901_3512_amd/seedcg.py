@@ -24,7 +24,7 @@ class Params(ctypes.Structure):
                 ("prec", ctypes.c_int32), ("m_max", ctypes.c_int32), ("reorth_k", ctypes.c_int32),
                 ("past_factor", ctypes.c_double), ("tol", ctypes.c_double), ("reliable_every", ctypes.c_int32),
                 ("seed_block", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("precond", ctypes.c_int32),
-                ("autotune", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("autotune", ctypes.c_int32), ("deflate", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class Report(ctypes.Structure):
@@ -64,6 +64,7 @@ def load_library():
         "seedcg_solve_rest": (i32, [H, P, P, i32, ctypes.POINTER(Report)]),
         "seedcg_get_tridiag": (i32, [H, ctypes.POINTER(dbl), ctypes.POINTER(dbl), i32, ctypes.POINTER(i32)]),
         "seedcg_get_basis_vector": (i32, [H, i32, P]),
+        "seedcg_get_ritz": (i32, [H, ctypes.POINTER(dbl), i32, ctypes.POINTER(i32)]),
         "seedcg_project": (i32, [H, P, i32, P, i32, i64, P]),
         "seedcg_update": (i32, [H, P, i32, P, P, i32, i64]),
         "seedcg_train_precond": (i32, [H, i32, i32, i32, dbl, ctypes.POINTER(dbl)]),
@@ -97,7 +98,7 @@ def load_library():
 def exported_symbols():
     """Names of the C ABI entry points this binding expects."""
     return ["seedcg_default_params", "seedcg_create", "seedcg_apply_M", "seedcg_apply_M_inner", "seedcg_apply_A", "seedcg_solve_seed",
-            "seedcg_solve_rest", "seedcg_get_tridiag", "seedcg_get_basis_vector", "seedcg_project",
+            "seedcg_solve_rest", "seedcg_get_tridiag", "seedcg_get_basis_vector", "seedcg_get_ritz", "seedcg_project",
             "seedcg_update", "seedcg_train_precond", "seedcg_use_precond", "seedcg_set_precond_weights",
             "seedcg_get_precond_weights", "seedcg_apply_P", "seedcg_precond_loss_grad", "seedcg_set_timing",
             "seedcg_get_timing", "seedcg_release_basis", "seedcg_destroy", "seedcg_last_error", "seedcg_create_batch",
@@ -121,7 +122,7 @@ class SeedCG:
     """One gauge configuration: M = A^dag A with A = 1 - kappa^2 H_eo H_oe (see include/seedcg.h)."""
 
     def __init__(self, links, dims, kappa, *, t_bc=-1, prec="fp64", m_max=0, reorth_k=10, past=1.5,
-                 tol=1e-10, reliable_every=50, seed_block=32, max_iter=100000, autotune=True, stream=None):
+                 tol=1e-10, reliable_every=50, seed_block=32, max_iter=100000, autotune=True, deflate=0, stream=None):
         lib = load_library()
         self.dims = tuple(int(d) for d in dims)
         self.V = self.dims[0] * self.dims[1] * self.dims[2] * self.dims[3]
@@ -146,6 +147,7 @@ class SeedCG:
         p.seed_block = int(seed_block)
         p.max_iter = int(max_iter)
         p.autotune = int(bool(autotune))
+        p.deflate = int(deflate)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
@@ -238,6 +240,14 @@ class SeedCG:
         b = (ctypes.c_double * (n + 1))()
         self._rc(self._lib.seedcg_get_tridiag(self._h, a, b, n, ctypes.byref(m)))
         return list(a)[:n], list(b)[:n + 1]
+
+    def get_ritz(self):
+        """Ritz values of the deflation space used by the last deflated solve_rest (ascending)."""
+        n = ctypes.c_int32()
+        self._rc(self._lib.seedcg_get_ritz(self._h, None, 0, ctypes.byref(n)))
+        th = (ctypes.c_double * max(n.value, 1))()
+        self._rc(self._lib.seedcg_get_ritz(self._h, th, n.value, ctypes.byref(n)))
+        return list(th)[:n.value]
 
     def get_basis_vector(self, i):
         v = torch.empty((1, self.Vh, 4, 3), dtype=torch.complex128, device=self.device)

@@ -31,7 +31,7 @@ __device__ inline uint32_t conv_link<uint32_t>(cx<double> u) {
 }
 
 template <typename S>
-__global__ void pack_links_kernel(Geom g, const cx<double>* __restrict__ U, S* __restrict__ out) {
+__global__ void pack_links_kernel(Geom g, const cx<double>* __restrict__ U, S* __restrict__ out, int ne) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= 4 * g.V) return;
     const int mu = (int)(k / g.V);
@@ -44,18 +44,57 @@ __global__ void pack_links_kernel(Geom g, const cx<double>* __restrict__ U, S* _
     const int t = (int)(r / g.L[2]);
     const int par = (x + y + z + t) & 1;
     const int64_t h = s >> 1;
-    for (int c = 0; c < 9; c++) out[((int64_t)(mu * 2 + par) * 9 + c) * g.Vh + h] = conv_link<S>(U[k * 9 + c]);
+    for (int c = 0; c < ne; c++) out[((int64_t)(mu * 2 + par) * ne + c) * g.Vh + h] = conv_link<S>(U[k * 9 + c]);
 }
 
 void pack_links(Prec prec, const Geom& g, const double* U, void* out, hipStream_t s) {
     const int64_t n = 4 * g.V;
     const dim3 grid((unsigned)((n + 255) / 256));
-    if (prec == P64)
-        hipLaunchKernelGGL(pack_links_kernel<cx<double>>, grid, dim3(256), 0, s, g, (const cx<double>*)U, (cx<double>*)out);
-    else if (prec == P32)
-        hipLaunchKernelGGL(pack_links_kernel<cx<float>>, grid, dim3(256), 0, s, g, (const cx<double>*)U, (cx<float>*)out);
+    // the two-row formats keep entries 0..5 (rows 0 and 1) of every link
+    const int ne = (prec == P64R || prec == P32R) ? 6 : 9;
+    if (prec == P64 || prec == P64R)
+        hipLaunchKernelGGL(pack_links_kernel<cx<double>>, grid, dim3(256), 0, s, g, (const cx<double>*)U, (cx<double>*)out, ne);
+    else if (prec == P32 || prec == P32R)
+        hipLaunchKernelGGL(pack_links_kernel<cx<float>>, grid, dim3(256), 0, s, g, (const cx<double>*)U, (cx<float>*)out, ne);
     else
-        hipLaunchKernelGGL(pack_links_kernel<uint32_t>, grid, dim3(256), 0, s, g, (const cx<double>*)U, (uint32_t*)out);
+        hipLaunchKernelGGL(pack_links_kernel<uint32_t>, grid, dim3(256), 0, s, g, (const cx<double>*)U, (uint32_t*)out, ne);
+}
+
+// max over links of |row 2 - conj(row 0 x row 1)| and |det U - 1| (canonical FP64 links), per
+// block; the two-row link formats are used only when this is at rounding level
+__global__ void su3_defect_kernel(const cx<double>* __restrict__ U, int64_t nlinks, double* part) {
+    __shared__ double lds[SCG_BLOCK];
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double d = 0.0;
+    if (k < nlinks) {
+        const cx<double>* u = U + k * 9;
+        cx<double> r[3];
+        r[0] = mk<double>(0, 0);
+        // conj(u0 x u1)
+        const cx<double> c0 = cmul(u[1], u[5]) - cmul(u[2], u[4]);
+        const cx<double> c1 = cmul(u[2], u[3]) - cmul(u[0], u[5]);
+        const cx<double> c2 = cmul(u[0], u[4]) - cmul(u[1], u[3]);
+        r[0] = u[6] - mk<double>(c0.re, -c0.im);
+        r[1] = u[7] - mk<double>(c1.re, -c1.im);
+        r[2] = u[8] - mk<double>(c2.re, -c2.im);
+        for (int a = 0; a < 3; a++) d = fmax(d, sqrt(r[a].re * r[a].re + r[a].im * r[a].im));
+        // det U = row 2 . (row 0 x row 1)
+        const cx<double> det = cmul(u[6], c0) + cmul(u[7], c1) + cmul(u[8], c2);
+        d = fmax(d, sqrt((det.re - 1.0) * (det.re - 1.0) + det.im * det.im));
+        if (!(d == d)) d = 1e300;   // NaN
+    }
+    lds[threadIdx.x] = d;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) lds[threadIdx.x] = fmax(lds[threadIdx.x], lds[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = lds[0];
+}
+int64_t su3_defect_blocks(int64_t nlinks) { return (nlinks + SCG_BLOCK - 1) / SCG_BLOCK; }
+void su3_defect(const double* U, int64_t nlinks, double* part, hipStream_t s) {
+    hipLaunchKernelGGL(su3_defect_kernel, dim3((unsigned)su3_defect_blocks(nlinks)), dim3(SCG_BLOCK), 0, s, (const cx<double>*)U,
+                       nlinks, part);
 }
 
 // canonical [n][Vh][12] (FP64)  <->  internal [n][12][Vh] (T)

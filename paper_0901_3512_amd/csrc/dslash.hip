@@ -58,6 +58,7 @@ struct LinkLoad;
 template <>
 struct LinkLoad<double> {
     using Store = cx<double>;
+    static constexpr int NE = 9;  // stored complex entries per link
     template <typename T>
     __device__ static inline cx<T> get(const Store* p) {
         cx<double> v = *p;
@@ -72,6 +73,7 @@ struct LinkLoad<double> {
 template <>
 struct LinkLoad<float> {
     using Store = cx<float>;
+    static constexpr int NE = 9;
     template <typename T>
     __device__ static inline cx<T> get(const Store* p) {
         cx<float> v = *p;
@@ -88,6 +90,7 @@ struct bf16link {};
 template <>
 struct LinkLoad<bf16link> {
     using Store = uint32_t;
+    static constexpr int NE = 9;
     template <typename T>
     __device__ static inline cx<T> get(const Store* p) {
         uint32_t w = *p;
@@ -101,6 +104,42 @@ struct LinkLoad<bf16link> {
         return mk<T>((T)__uint_as_float(w << 16), (T)__uint_as_float(w & 0xffff0000u));
     }
 };
+
+// Special-unitary links stored as their first two rows (6 complex entries); the third row is
+// rebuilt in registers as conj(row 0 x row 1), which holds for every U in SU(3).
+template <typename S>
+struct su3rows {};
+template <typename S>
+struct LinkLoad<su3rows<S>> {
+    using Store = cx<S>;
+    static constexpr int NE = 6;
+    template <typename T>
+    __device__ static inline cx<T> get(const Store* p) {
+        const cx<S> v = *p;
+        return mk<T>((T)v.re, (T)v.im);
+    }
+    template <typename T>
+    __device__ static inline cx<T> get32(const Store* base, uint32_t idx) {
+        const cx<S> v = *(const Store*)((const char*)base + idx * (uint32_t)sizeof(Store));
+        return mk<T>((T)v.re, (T)v.im);
+    }
+};
+template <typename T>
+__device__ inline cx<T> conjc(cx<T> a) { return mk<T>(a.re, -a.im); }
+template <typename T>
+__device__ inline void su3_third_row(cx<T> u[9]) {
+    u[6] = conjc(cmul(u[1], u[5]) - cmul(u[2], u[4]));
+    u[7] = conjc(cmul(u[2], u[3]) - cmul(u[0], u[5]));
+    u[8] = conjc(cmul(u[0], u[4]) - cmul(u[1], u[3]));
+}
+// U of one link: entries c * Vh apart from lk + lane_off (32-bit offsets)
+template <typename T, typename LT>
+__device__ inline void load_u32(const typename LinkLoad<LT>::Store* __restrict__ lk, uint32_t lane_off, uint32_t Vh, cx<T> u[9]) {
+    constexpr int NE = LinkLoad<LT>::NE;
+#pragma unroll
+    for (int c = 0; c < NE; c++) u[c] = LinkLoad<LT>::template get32<T>(lk, lane_off + (uint32_t)c * Vh);
+    if constexpr (NE == 6) su3_third_row(u);
+}
 
 template <typename T>
 struct EpiDev {
@@ -181,9 +220,11 @@ __device__ inline Nb neighbour(const Geom& g, int mu, int step, int x, int y, in
 
 template <typename T, typename LT>
 __device__ inline void load_link(const typename LinkLoad<LT>::Store* links, int mu, int par, int64_t h, int64_t Vh, cx<T> u[9]) {
-    const typename LinkLoad<LT>::Store* lk = links + ((int64_t)(mu * 2 + par) * 9) * Vh + h;
+    constexpr int NE = LinkLoad<LT>::NE;
+    const typename LinkLoad<LT>::Store* lk = links + ((int64_t)(mu * 2 + par) * NE) * Vh + h;
 #pragma unroll
-    for (int c = 0; c < 9; c++) u[c] = LinkLoad<LT>::template get<T>(lk + (int64_t)c * Vh);
+    for (int c = 0; c < NE; c++) u[c] = LinkLoad<LT>::template get<T>(lk + (int64_t)c * Vh);
+    if constexpr (NE == 6) su3_third_row(u);
 }
 
 // acc += (1 -/+ gamma_mu) U psi(neighbour) for one hop (dir 0: forward with U_mu(n), 1: backward
@@ -372,18 +413,6 @@ __global__ __launch_bounds__(SCG_BLOCK) void hop_kernel(Geom g, const typename L
     }
 }
 
-// Lean variant: two lanes per site, lane 0 takes the four forward hops and lane 1 the four
-// backward hops.  The mu loop is unrolled, so every spin-projection coefficient is a
-// compile-time unit and folds into the adds; the lane's direction enters only as a sign sd
-// (and as U versus U^dag, by the order in which the link entries are read).
-template <int MU>
-__device__ constexpr Proj proj_c() {
-    return MU == 0 ? Proj{3, {0, 1}, {0, 1}, 1, {0, -1}, {0, -1}}
-         : MU == 1 ? Proj{3, {1, 0}, {-1, 0}, 1, {-1, 0}, {1, 0}}
-         : MU == 2 ? Proj{2, {0, 1}, {0, -1}, 0, {0, -1}, {0, 1}}
-                   : Proj{2, {-1, 0}, {-1, 0}, 0, {-1, 0}, {-1, 0}};
-}
-
 // load base[idx] with a 32-bit byte offset, so that a uniform base stays in SGPRs and only the
 // offset occupies a VGPR (the global_load saddr form)
 template <typename T>
@@ -393,62 +422,6 @@ __device__ inline T ld32(const T* base, uint32_t idx) {
 template <typename T>
 __device__ inline void st32(T* base, uint32_t idx, T v) {
     *(T*)((char*)base + idx * (uint32_t)sizeof(T)) = v;
-}
-
-// a + sd * u * b for a compile-time unit u
-template <typename T, int UR, int UI>
-__device__ inline cx<T> fma_unit(T sd, cx<T> b, cx<T> a) {
-    // u*b = (UR br - UI bi) + i (UR bi + UI br)
-    const T ur = UR ? (T)UR * b.re : (T)-UI * b.im;
-    const T ui = UR ? (T)UR * b.im : (T)UI * b.re;
-    return mk<T>(fma(sd, ur, a.re), fma(sd, ui, a.im));
-}
-
-template <typename T, typename LT, int MU>
-__device__ inline void hop_dir_lean(const cx<T>* __restrict__ src, const typename LinkLoad<LT>::Store* __restrict__ links,
-                                    uint32_t hn, uint32_t hl, uint32_t lpar, uint32_t Vh, int bwd, T sd, T sign,
-                                    cx<T> acc[12]) {
-    constexpr Proj pr = proj_c<MU>();
-    constexpr int a0 = pr.a0, a1 = 5 - pr.a0;
-    // uniform base of each spin-colour component plus a 32-bit per-lane site offset
-    cx<T> hp[2][3];
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        hp[0][a] = fma_unit<T, pr.c0.re, pr.c0.im>(sd, ld32(src + (size_t)(3 * a0 + a) * Vh, hn), ld32(src + (size_t)a * Vh, hn));
-        hp[1][a] = fma_unit<T, pr.c1.re, pr.c1.im>(sd, ld32(src + (size_t)(3 * a1 + a) * Vh, hn), ld32(src + (size_t)(3 + a) * Vh, hn));
-    }
-    if (MU == 3) {  // boundary sign of the t hop
-#pragma unroll
-        for (int a = 0; a < 3; a++) {
-            hp[0][a] = sign * hp[0][a];
-            hp[1][a] = sign * hp[1][a];
-        }
-    }
-    // M[a][b] = U[a][b] (forward) or conj(U[b][a]) (backward); the link of parity lpar
-    const typename LinkLoad<LT>::Store* __restrict__ lk = links + (size_t)(MU * 2) * 9 * Vh;
-    const uint32_t lane_off = lpar * 9u * Vh + hl;
-    cx<T> chi[2][3];
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        cx<T> c0 = mk<T>(0, 0), c1 = mk<T>(0, 0);
-#pragma unroll
-        for (int b = 0; b < 3; b++) {
-            const uint32_t idx = bwd ? (uint32_t)(b * 3 + a) : (uint32_t)(a * 3 + b);
-            cx<T> m = LinkLoad<LT>::template get32<T>(lk, lane_off + idx * Vh);
-            if (bwd) m.im = -m.im;
-            c0 = c0 + cmul(m, hp[0][b]);
-            c1 = c1 + cmul(m, hp[1][b]);
-        }
-        chi[0][a] = c0;
-        chi[1][a] = c1;
-    }
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        acc[a] = acc[a] + chi[0][a];
-        acc[3 + a] = acc[3 + a] + chi[1][a];
-        acc[6 + a] = fma_unit<T, pr.d0.re, pr.d0.im>(sd, pr.b0 == 1 ? chi[1][a] : chi[0][a], acc[6 + a]);
-        acc[9 + a] = fma_unit<T, pr.d1.re, pr.d1.im>(sd, pr.b0 == 1 ? chi[0][a] : chi[1][a], acc[9 + a]);
-    }
 }
 
 // Epilogue of the two-lanes-per-site kernels for one vector: out = sy*[gamma5](x - kappa^2 v) +
@@ -512,16 +485,18 @@ __device__ inline void hop_dir_rt(const cx<T>* __restrict__ src, const typename 
         hp[0][a] = sign * hp[0][a];
         hp[1][a] = sign * hp[1][a];
     }
-    const typename LinkLoad<LT>::Store* __restrict__ lk = links + (size_t)(mu * 2) * 9 * Vh;
-    const uint32_t lane_off = lpar * 9u * Vh + hl;
+    constexpr int NE = LinkLoad<LT>::NE;
+    const typename LinkLoad<LT>::Store* __restrict__ lk = links + (size_t)(mu * 2) * NE * Vh;
+    cx<T> u[9];
+    load_u32<T, LT>(lk, lpar * (uint32_t)NE * Vh + hl, Vh, u);
     cx<T> chi[2][3];
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         cx<T> c0 = mk<T>(0, 0), c1 = mk<T>(0, 0);
 #pragma unroll
         for (int b = 0; b < 3; b++) {
-            const uint32_t idx = bwd ? (uint32_t)(b * 3 + a) : (uint32_t)(a * 3 + b);
-            cx<T> m = LinkLoad<LT>::template get32<T>(lk, lane_off + idx * Vh);
+            // M[a][b] = U[a][b] (forward) or conj(U[b][a]) (backward)
+            cx<T> m = bwd ? u[b * 3 + a] : u[a * 3 + b];
             if (bwd) m.im = -m.im;
             c0 = c0 + cmul(m, hp[0][b]);
             c1 = c1 + cmul(m, hp[1][b]);
@@ -539,6 +514,9 @@ __device__ inline void hop_dir_rt(const cx<T>* __restrict__ src, const typename 
     }
 }
 
+// Lean variant: two lanes per site, the even lane takes the four forward hops and the odd lane the
+// four backward hops (the direction enters as a sign and as U versus U^dag); the mu loop is
+// wave-uniform.
 // UNR: directions per pass of the mu loop.  1 keeps one direction's loads in flight (fewest
 // registers, for grids with many waves per SIMD); 2 and 4 issue the loads of several directions
 // together, which shortens the chain of dependent memory round trips when the half lattice gives
@@ -714,17 +692,17 @@ __global__ __launch_bounds__(SCG_BLOCK) void hop_multi_kernel(Geom g, const type
             const Proj pr = proj_of(mu);
             const uint32_t a0 = (uint32_t)pr.a0, a1 = 5u - a0;
             // M[a][b] = U[a][b] (forward) or conj(U[b][a]) (backward), loaded once
-            const typename LinkLoad<LT>::Store* __restrict__ lk = links + (size_t)(mu * 2) * 9 * Vh;
-            const uint32_t lane_off = lpar * 9u * Vh32 + hl;
-            cx<T> m[9];
+            constexpr int NE = LinkLoad<LT>::NE;
+            const typename LinkLoad<LT>::Store* __restrict__ lk = links + (size_t)(mu * 2) * NE * Vh;
+            cx<T> u[9], m[9];
+            load_u32<T, LT>(lk, lpar * (uint32_t)NE * Vh32 + hl, Vh32, u);
 #pragma unroll
             for (int a = 0; a < 3; a++)
 #pragma unroll
                 for (int b = 0; b < 3; b++) {
-                    const uint32_t idx = bwd ? (uint32_t)(b * 3 + a) : (uint32_t)(a * 3 + b);
-                    cx<T> u = LinkLoad<LT>::template get32<T>(lk, lane_off + idx * Vh32);
-                    if (bwd) u.im = -u.im;
-                    m[a * 3 + b] = u;
+                    cx<T> v = bwd ? u[b * 3 + a] : u[a * 3 + b];
+                    if (bwd) v.im = -v.im;
+                    m[a * 3 + b] = v;
                 }
             const T sign = (T)n.sign;
             const bool b1 = pr.b0 == 1;
@@ -891,8 +869,12 @@ void launch_hop(Prec prec, const Geom& g, const void* links, const void* in, voi
                 const HopEpi& epi, int tps, int vb, const Launch& L) {
     if (prec == P64)
         launch_t<double, double>(g, links, in, out, out_parity, nvec, epi, tps, vb, L);
+    else if (prec == P64R)
+        launch_t<double, su3rows<double>>(g, links, in, out, out_parity, nvec, epi, tps, vb, L);
     else if (prec == P32)
         launch_t<float, float>(g, links, in, out, out_parity, nvec, epi, tps, vb, L);
+    else if (prec == P32R)
+        launch_t<float, su3rows<float>>(g, links, in, out, out_parity, nvec, epi, tps, vb, L);
     else
         launch_t<float, bf16link>(g, links, in, out, out_parity, nvec, epi, tps, vb, L);
 }

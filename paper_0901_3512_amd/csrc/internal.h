@@ -138,7 +138,8 @@ struct CgVec {
 // ---- launchers implemented in the .hip files -------------------------------------------------
 namespace scg {
 
-enum Prec { P64 = 0, P32 = 1, P32BF = 2 };
+// P64R / P32R: links stored as their first two rows (special unitary fields only)
+enum Prec { P64 = 0, P32 = 1, P32BF = 2, P64R = 3, P32R = 4 };
 
 struct HopEpi {
     // y = [gamma5] (x - kappa^2 * hop);  out = sy*y + [cz * z]; optional reduction

@@ -40,6 +40,9 @@ void project(bool fp32, const ProjArgs& a, int64_t nrowblocks, double* P, const 
 int64_t proj_chunks(int64_t n, int64_t kchunk);
 
 void pack_links(Prec prec, const Geom& g, const double* U, void* out, hipStream_t s);
+// per-block maxima of the distance of every link from SU(3) as its two-row format sees it
+void su3_defect(const double* U, int64_t nlinks, double* part, hipStream_t s);
+int64_t su3_defect_blocks(int64_t nlinks);
 // tab (optional, device memory): one canonical pointer per configuration of the launch
 void pack_vec(bool fp32, const double* in, void* out, int64_t Vh, int nvec, const Launch& L, const double* const* tab = nullptr);
 void unpack_vec(bool fp32, const void* in, double* out, int64_t Vh, int nvec, const Launch& L, double* const* tab = nullptr);

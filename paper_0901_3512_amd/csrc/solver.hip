@@ -154,7 +154,9 @@ struct seedcg_s {
     std::map<int, hipGraphExec_t> cg_graphs;
     Launch L() const { return Launch(s, ncfg, cs); }
 
-    DBuf links64, links_lo;
+    DBuf links64, links_lo;      // full 3x3 links (FP64; FP32 or BF16 inner)
+    DBuf links64r, links_lor;    // two-row copies for the stencil when the field is special unitary
+    Prec hop64 = P64, hop_lo = P64;  // link formats the stencil reads
     // operator work vectors (FP64), sized for a batch
     DBuf t1_64, u_64, t1_lo, u_lo, g5buf;
     int64_t work_vecs = 0;
@@ -238,9 +240,14 @@ void ensure_work(seedcg_s* h, int nvec) {
     h->work_vecs = n;
 }
 
+const void* hop_links(const seedcg_s* h, bool low) {
+    if (low) return h->hop_lo == P32R ? h->links_lor.p : h->links_lo.p;
+    return h->hop64 == P64R ? h->links64r.p : h->links64.p;
+}
+
 // One stencil launch; when timing is on, every timing_every-th launch is bracketed by events and
-// its algorithmic bytes are recorded: links 144 reals per output site (read once for the whole
-// batch), and per vector the input and output spinors (24 reals each per site) plus every
+// its algorithmic bytes are recorded: links 144 reals per output site (96 in the two-row format;
+// read once for the whole batch), and per vector the input and output spinors (24 reals each per site) plus every
 // epilogue operand (24 reals per site each).
 void hop(seedcg_s* h, Prec pr, const void* L, const void* in, void* out, int par, int nvec, const HopEpi& e, int tps, int vb) {
     const bool sample = h->timing_every > 0 && (h->hop_count++ % h->timing_every) == 0 && h->ev_used < h->ev0.size();
@@ -248,11 +255,12 @@ void hop(seedcg_s* h, Prec pr, const void* L, const void* in, void* out, int par
     launch_hop(pr, h->g, L, in, out, par, nvec, e, tps, vb, h->L());
     if (sample) {
         HIPCHK(hipEventRecord(h->ev1[h->ev_used], h->s));
-        const double sl = pr == P64 ? 8.0 : (pr == P32 ? 4.0 : 2.0);
-        const double ss = pr == P64 ? 8.0 : 4.0;
+        const double sl = (pr == P64 || pr == P64R) ? 8.0 : (pr == P32BF ? 2.0 : 4.0);
+        const double ss = (pr == P64 || pr == P64R) ? 8.0 : 4.0;
+        const double lr = (pr == P64R || pr == P32R) ? 96.0 : 144.0;   // link reals per site (two rows or all)
         const double Vh = (double)h->g.Vh * h->ncfg;
         int ops = 2 + (e.combine ? 1 : 0) + (e.z ? 1 : 0) + (e.red == 1 ? 1 : 0);
-        h->ev_bytes.push_back(Vh * 144.0 * sl + (double)nvec * Vh * 24.0 * ss * ops);
+        h->ev_bytes.push_back(Vh * lr * sl + (double)nvec * Vh * 24.0 * ss * ops);
         h->ev_flops.push_back((double)nvec * Vh * 1320.0);
         h->ev_used++;
     }
@@ -277,8 +285,8 @@ struct MOpts {
 // the last hop.  low = FP32 vectors with the inner links.
 void apply_M_int(seedcg_s* h, bool low, const void* x, void* out, int nvec, const MOpts& o) {
     ensure_work(h, nvec);
-    const Prec pr = low ? h->lo_prec : P64;
-    const void* L = low ? h->links_lo.p : h->links64.p;
+    const Prec pr = low ? h->hop_lo : h->hop64;
+    const void* L = hop_links(h, low);
     void* t1 = low ? h->t1_lo.p : h->t1_64.p;
     void* u = low ? h->u_lo.p : h->u_64.p;
     const bool multi = nvec > 1;
@@ -329,13 +337,13 @@ void apply_A_int(seedcg_s* h, const void* x, void* out, int nvec, bool dagger) {
     HopEpi e{};
     e.sy = 1.0;
     e.kappa2_dev = h->kap2.p ? h->kap2.as<double>() : nullptr;
-    launch_hop(P64, h->g, h->links64.p, in, h->t1_64.p, 1, nvec, e, h->tps64, h->vb64, h->L());
+    launch_hop(h->hop64, h->g, hop_links(h, false), in, h->t1_64.p, 1, nvec, e, h->tps64, h->vb64, h->L());
     HopEpi e2 = e;
     e2.combine = 1;
     e2.apply_g5 = dagger ? 1 : 0;
     e2.kappa2 = k2;
     e2.x = in;
-    launch_hop(P64, h->g, h->links64.p, h->t1_64.p, out, 0, nvec, e2, h->tps64, h->vb64, h->L());
+    launch_hop(h->hop64, h->g, hop_links(h, false), h->t1_64.p, out, 0, nvec, e2, h->tps64, h->vb64, h->L());
 }
 
 void check_launch() { HIPCHK(hipGetLastError()); }
@@ -1405,6 +1413,30 @@ void init_geometry(seedcg_s* h, const seedcg_params* p, const int32_t* dims) {
     HIPCHK(hipGetDevice(&h->device));
 }
 
+// Largest distance of a link from SU(3) as the two-row format sees it (canonical FP64 links on the
+// device); the stencil reads two-row links only when this is at rounding level.
+double su3_defect_max(seedcg_s* h, const double* links) {
+    const int64_t nl = 4 * h->g.V;
+    const int64_t nb = su3_defect_blocks(nl);
+    DBuf part;
+    part.ensure(nb * sizeof(double));
+    su3_defect(links, nl, part.as<double>(), h->s);
+    std::vector<double> v(nb);
+    HIPCHK(hipMemcpyAsync(v.data(), part.p, nb * sizeof(double), hipMemcpyDeviceToHost, h->s));
+    HIPCHK(hipStreamSynchronize(h->s));
+    double m = 0.0;
+    for (double x : v) m = std::max(m, x);
+    return m;
+}
+constexpr double SU3_DEFECT_TOL = 1e-12;
+
+// link formats of the stencil: two rows when allowed and the field is special unitary
+void choose_link_formats(seedcg_s* h, bool special_unitary) {
+    const bool rows2 = special_unitary && env_int("SEEDCG_LINK_ROWS", 2) != 9;
+    h->hop64 = rows2 ? P64R : P64;
+    h->hop_lo = h->lo_prec == P32 ? (rows2 ? P32R : P32) : h->lo_prec;
+}
+
 bool env_shape_fixed() {
     return getenv("SEEDCG_TPS") || getenv("SEEDCG_TPS_LO") || getenv("SEEDCG_VB") || getenv("SEEDCG_VB_LO");
 }
@@ -1420,7 +1452,7 @@ void tune_shape(seedcg_s* h, bool low, int nvec, const void* x, void* y) {
     const bool multi = nvec > 1;
     int& tps = low ? (multi ? h->tps_lo_multi : h->tps_lo) : (multi ? h->tps64_multi : h->tps64);
     int& vb = low ? (multi ? h->vb_lo_multi : h->vb_lo) : (multi ? h->vb64_multi : h->vb64);
-    const std::vector<int> key{h->g.L[0], h->g.L[1], h->g.L[2], h->g.L[3], low ? (int)h->lo_prec : (int)P64, h->ncfg, nvec};
+    const std::vector<int> key{h->g.L[0], h->g.L[1], h->g.L[2], h->g.L[3], low ? (int)h->hop_lo : (int)h->hop64, h->ncfg, nvec};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(key);
@@ -1500,6 +1532,8 @@ size_t plan_layout(seedcg_s* h, int nrhs, int m_cap, std::vector<std::pair<DBuf*
     try {
         h->links64.ensure(4 * h->g.V * 9 * 16);
         if (h->lo) h->links_lo.ensure(4 * h->g.V * 9 * (h->lo_prec == P32 ? 8 : 4));
+        if (h->hop64 == P64R) h->links64r.ensure(4 * h->g.V * 6 * 16);
+        if (h->hop_lo == P32R) h->links_lor.ensure(4 * h->g.V * 6 * 8);
         h->kap2.ensure(sizeof(double));
         alloc_seed(h, nrhs);
         alloc_rest(h, nrhs);
@@ -1607,6 +1641,15 @@ seedcg_status seedcg_create(const seedcg_params* p, const double* links, seedcg_
             h->links_lo.ensure(4 * g.V * 9 * (h->lo_prec == P32 ? 8 : 4));
             pack_links(h->lo_prec, g, links, h->links_lo.p, h->s);
         }
+        choose_link_formats(h, su3_defect_max(h, links) <= SU3_DEFECT_TOL);
+        if (h->hop64 == P64R) {
+            h->links64r.ensure(4 * g.V * 6 * 16);
+            pack_links(P64R, g, links, h->links64r.p, h->s);
+        }
+        if (h->hop_lo == P32R) {
+            h->links_lor.ensure(4 * g.V * 6 * 8);
+            pack_links(P32R, g, links, h->links_lor.p, h->s);
+        }
         check_launch();
         autotune_single(h, 12);
         check_launch();
@@ -1665,6 +1708,12 @@ seedcg_status seedcg_create_batch(int32_t ncfg, const int32_t* dims, const doubl
             HIPCHK(hipStreamCreateWithFlags(&h->s, hipStreamNonBlocking));
             h->own_stream = true;
         }
+        // two-row links for a class only when every member's field is special unitary
+        for (size_t k = 0; k < b->cls.size(); k++) {
+            bool su = true;
+            for (int c : b->members[k]) su = su && su3_defect_max(b->cls[k], links[c]) <= SU3_DEFECT_TOL;
+            choose_link_formats(b->cls[k], su);
+        }
         // one basis capacity for every class: params.m_max, or the largest that fits in 90% of
         // the free HBM less 4 GiB
         size_t freeb = 0, total = 0;
@@ -1699,6 +1748,8 @@ seedcg_status seedcg_create_batch(int32_t ncfg, const int32_t* dims, const doubl
                 const int c = b->members[k][i];
                 pack_links(P64, g, links[c], (char*)h->links64.p + (int64_t)i * h->cs, h->s);
                 if (h->lo) pack_links(h->lo_prec, g, links[c], (char*)h->links_lo.p + (int64_t)i * h->cs, h->s);
+                if (h->hop64 == P64R) pack_links(P64R, g, links[c], (char*)h->links64r.p + (int64_t)i * h->cs, h->s);
+                if (h->hop_lo == P32R) pack_links(P32R, g, links[c], (char*)h->links_lor.p + (int64_t)i * h->cs, h->s);
                 k2.push_back(kappa[c] * kappa[c]);
             }
             to_cfg(h, h->kap2.p, k2.data(), sizeof(double));

@@ -95,3 +95,37 @@ def test_free_field_plane_wave_eigenvector():
     lam = abs(1.0 - 4.0 * kappa ** 2 * (C - 1j * S) ** 2) ** 2
     y = host(s.apply_M(cuda(psi)))[0]
     assert relmax(y, lam * psi) <= 1e-13
+
+
+def test_two_row_links_match_full_links(monkeypatch):
+    """On a special-unitary field the stencil reads two-row links and rebuilds the third row; the
+    result equals the full-link stencil to rounding (and both equal the oracle)."""
+    from paper_0901_3512_amd import SeedCG
+    print_case("two-row links")
+    dims = (8, 4, 6, 8)
+    rng = np.random.default_rng(11)
+    U = random_su3_links(dims, 0.9, rng)
+    op = WilsonEO(U, dims, 0.14)
+    x = _vecs(rng, 2, op.Vh)
+    y2 = host(SeedCG(cuda(U), dims, 0.14).apply_M(cuda(x)))
+    monkeypatch.setenv("SEEDCG_LINK_ROWS", "9")
+    y9 = host(SeedCG(cuda(U), dims, 0.14).apply_M(cuda(x)))
+    assert relmax(y2, y9) <= 1e-13
+    assert relmax(y2, op.apply_M(x)) <= 1e-13
+
+
+def test_non_unitary_links_keep_full_links():
+    """A field that is not special unitary (here random complex matrices) is read in full: the stencil
+    still matches the oracle, which takes the links as given."""
+    from paper_0901_3512_amd import SeedCG
+    print_case("non-unitary links")
+    dims = (4, 4, 4, 4)
+    rng = np.random.default_rng(12)
+    V = int(np.prod(dims))
+    U = 0.6 * (rng.standard_normal((4, V, 3, 3)) + 1j * rng.standard_normal((4, V, 3, 3)))
+    op = WilsonEO(U, dims, 0.1)
+    x = _vecs(rng, 2, op.Vh)
+    for prec in ("fp64", "mixed"):
+        s = SeedCG(cuda(U), dims, 0.1, prec=prec)
+        y = host(s.apply_M(cuda(x)))
+        assert relmax(y, op.apply_M(x)) <= 1e-13, prec

@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--mbench", type=int, default=200, help="back-to-back M applications for D^dag D GB/s")
     ap.add_argument("--batch-n", type=int, default=64, help="c4: number of batch members (the workload has 64)")
     ap.add_argument("--deflate", type=int, default=0, help="deflated CG with this many Ritz vectors (0: plain CG)")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the same-lattice comparison runs (mixed precision, and learned K with --learned)")
+    ap.add_argument("--learned", action="store_true", help="compare also the learned preconditioner (2000 Adam steps)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 1 GiB device copy first (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -141,6 +144,10 @@ def main():
                 "kernel": "hop_kernel (even-odd Wilson hop, fused epilogues)", "launches_sampled": tm["launches"],
                 "avg_launch_us": hop_ms * 1e3, "avg_launch_bytes": hop_bytes}
 
+    compare = None
+    if not args.no_compare:
+        compare = compare_forms(args, cfg, Ud, kappa, B, value, prec)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cfg, U, phi, kappa, reports[-1], args.cpu_iters)
@@ -163,9 +170,50 @@ def main():
                    "max_true_relres": max(rr["true_relres"]),
                    "dagger_d_gbs_api": (288 * V * s_l + 120 * V * s_s) / t_m_api / 1e9 if t_m_api else None,
                    "dagger_d_us_api": t_m_api * 1e6 if t_m_api else None,
-                   "hop_launches_total": tm["seen"]},
+                   "hop_launches_total": tm["seen"], "compare": compare},
     }
     print(json.dumps(result), flush=True)
+
+
+def compare_forms(args, cfg, Ud, kappa, B, value_ref, prec_ref):
+    """The same lattice and right-hand sides solved by the other forms of the method, timed the same
+    way (1 warmup, then args.steps solves): mixed precision, and with --learned the learned K + mixed
+    (training on the seed solve's Ritz and basis vectors is part of every step)."""
+    import torch
+    from paper_0901_3512_amd import SeedCG
+    out = {"reference": {"form": prec_ref, "rhs_per_s": value_ref}}
+    forms = [("mixed", False)] + ([("mixed", True)] if args.learned else [])
+    for prec, learned in forms:
+        s = SeedCG(Ud, cfg.dims, kappa, t_bc=cfg.t_bc, prec=prec, reorth_k=cfg.reorth_k, past=cfg.past, tol=cfg.tol,
+                   reliable_every=cfg.reliable_every)
+        tr = None
+
+        def step():
+            nonlocal tr
+            X = torch.zeros_like(B)
+            X, _ = s.solve_seed(B, X)
+            if learned:
+                tr = s.train_precond(steps=2000, n_ritz=8, n_lanczos=8, lr=1e-3)
+                s.use_precond(True)
+            X, rr = s.solve_rest(B, X)
+            return rr
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        solved = 0
+        for _ in range(args.steps):
+            rr = step()
+            solved += sum(1 for r in rr["true_relres"] if r <= cfg.tol)
+        torch.cuda.synchronize()
+        v = solved / (time.perf_counter() - t0)
+        key = "learned+" + prec if learned else prec
+        out[key] = {"rhs_per_s": v, "vs_reference": v / value_ref, "cg_iters": rr["iters"],
+                    "max_true_relres": max(rr["true_relres"])}
+        if learned and tr:
+            out[key]["training"] = tr
+        log(f"compare {key}: {v:.2f} RHS/s ({v / value_ref:.2f}x)")
+        s.close()
+    return out
 
 
 def copy_probe():

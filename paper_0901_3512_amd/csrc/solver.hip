@@ -440,14 +440,15 @@ void alloc_seed(seedcg_s* h, int nrhs) {
     h->r64.ensure(nrhs * h->vec_bytes(false));
     ensure_work(h, nrhs);
 
-    // basis capacity: params.m_max, or what fits in free HBM (at most 8192 vectors)
+    // basis capacity: params.m_max, or 3/4 of the free HBM less 4 GiB (at most 8192 vectors); the
+    // rest stays free for the CG vectors, the deflation space and the training of the learned K
     int64_t cap = h->p.m_max;
     if (cap <= 0) {
         size_t freeb = 0, total = 0;
         HIPCHK(hipMemGetInfo(&freeb, &total));
-        const int64_t reserve = 2LL << 30;
+        const int64_t reserve = 4LL << 30;
         const int64_t avail = (int64_t)freeb - reserve + (int64_t)h->basis.bytes;
-        cap = std::max<int64_t>(0, (int64_t)(0.9 * (double)avail) / h->vec_bytes(lo));
+        cap = std::max<int64_t>(0, (int64_t)(0.75 * (double)avail) / h->vec_bytes(lo));
         cap = std::min<int64_t>(cap, 8192);
         if (cap < 2) throw OomError{"no room for a Krylov basis"};
     }

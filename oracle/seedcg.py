@@ -237,3 +237,28 @@ def orth_loss(V):
     """max |V^dag V - I|."""
     G = V.conj() @ V.T
     return float(np.max(np.abs(G - np.eye(G.shape[0]))))
+
+
+def repeated_seed(matvec, B, X0=None, *, k, tol, m_max=2000):
+    """Traditional repeated seeding (section 2 of the paper; the comparison variant): system j runs
+    Algorithm 1 from its current guess until its residual estimate meets tol (m = i_conv) and
+    seeds systems j+1..n from its own Krylov space; then plain CG finishes any system whose FP64
+    true residual is above tol.  Returns dict(X, lanczos=[m_j], cg=[iterations_j], seeded=[...])
+    where seeded[j] holds, after run j, the residual of system j+1 (for the Galerkin pin)."""
+    B = np.atleast_2d(np.asarray(B, dtype=np.complex128))
+    n = B.shape[0]
+    X = np.zeros_like(B) if X0 is None else np.array(np.atleast_2d(X0), dtype=np.complex128, copy=True)
+    lanczos, seeded, bases = [], [], []
+    for j in range(n):
+        out = seed_cg(matvec, B[j:], X[j:], k=k, tol=tol, past=1.0, m_max=m_max)
+        X[j:] = out["X"]
+        lanczos.append(out["m"])
+        bases.append(out["V"])
+        if j + 1 < n:
+            seeded.append(B[j + 1] - matvec(X[j + 1]))
+    cg_iters = []
+    for j in range(n):
+        x, it, _, _ = cg(matvec, B[j], X[j], tol=tol)
+        X[j] = x
+        cg_iters.append(it)
+    return dict(X=X, lanczos=lanczos, cg=cg_iters, seeded=seeded, bases=bases)

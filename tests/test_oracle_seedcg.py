@@ -172,3 +172,19 @@ def test_breakdown_on_few_distinct_eigenvalues():
     assert out["status"] == "breakdown"
     assert out["m"] <= n_distinct
     assert sc.true_relres(mv, B[:1], out["X"][:1])[0] < 1e-12
+
+
+def test_repeated_seeding_pins(c1):
+    """Repeated seeding: one system is Algorithm 1 run to convergence then CG; after run j the
+    residual of system j+1 is orthogonal to run j's basis (the Galerkin condition of Eq. (1)); every
+    final solution meets the FP64 tolerance."""
+    op, mv, B = c1
+    one = sc.repeated_seed(mv, B[:1], k=10, tol=1e-10)
+    ref = sc.seed_cg(mv, B[:1], k=10, tol=1e-10, past=1.0)
+    assert one["lanczos"] == [ref["m"]]
+    out = sc.repeated_seed(mv, B, k=10, tol=1e-10)
+    for j, r in enumerate(out["seeded"]):
+        V = out["bases"][j]
+        assert np.max(np.abs(V.conj() @ r)) <= 1e-8 * np.linalg.norm(B[j + 1])
+    res = sc.true_relres(mv, B, out["X"])
+    assert np.all(res <= 1e-10)

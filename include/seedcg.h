@@ -126,6 +126,14 @@ seedcg_status seedcg_solve_seed(seedcg_t h, const double* B, double* X, int32_t 
    SEEDCG_ERR_NOCONV if some right-hand side reached max_iter; X then holds its last iterate. */
 seedcg_status seedcg_solve_rest(seedcg_t h, const double* B, double* X, int32_t nrhs, seedcg_report* r);
 
+/* Traditional repeated seeding (section 2: the variant the improved method is compared with):
+   system j = 1..nrhs runs Algorithm 1 from its current guess until its own residual estimate meets
+   tol (m = i_conv) and seeds systems j+1..nrhs from its Krylov space; then plain CG (solve_rest)
+   finishes every system whose FP64 true residual is above tol.  r->iters[j] = Lanczos steps of
+   system j + its CG iterations; r->m_used = the Lanczos steps of system 1.  Same arguments and
+   layouts as seedcg_solve_seed; nrhs <= 25. */
+seedcg_status seedcg_solve_repeated(seedcg_t h, const double* B, double* X, int32_t nrhs, seedcg_report* r);
+
 /* Copies the Lanczos coefficients of the last solve_seed to HOST arrays: alpha_1..alpha_m into
    alpha[0..m-1] and beta_0..beta_m into beta[0..m]; cap is the length of alpha (beta needs cap+1).
    *m receives m.  Eq. (2) defines T from these. */

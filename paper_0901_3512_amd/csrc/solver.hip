@@ -1996,6 +1996,61 @@ seedcg_status seedcg_solve_rest(seedcg_t h, const double* B, double* X, int32_t 
     });
 }
 
+seedcg_status seedcg_solve_repeated(seedcg_t h, const double* B, double* X, int32_t nrhs, seedcg_report* r) {
+    if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "solve_repeated: null handle");
+    return guarded(h, [&]() -> seedcg_status {
+        if (!B || !X || nrhs < 1) throw ArgError{"solve_repeated: null pointer or nrhs < 1"};
+        if (nrhs > 25) throw ArgError{"solve_repeated: at most 25 right-hand sides"};
+        if (h->ncfg != 1) throw StateError{"solve_repeated: one configuration per handle"};
+        const int64_t stride = h->g.Vh * 12 * 2;   // doubles per canonical vector
+        std::vector<int32_t> lz(nrhs, 0), lmv(nrhs, 0);
+        const double past = h->p.past_factor;
+        h->p.past_factor = 1.0;   // every system runs Algorithm 1 just to its own convergence
+        try {
+            for (int j = 0; j < nrhs; j++) {
+                Io io;
+                io.B = B + (int64_t)j * stride;
+                io.X = X + (int64_t)j * stride;
+                seedcg_report rj{};
+                solve_seed_impl(h, io, nrhs - j, &rj);
+                lz[j] = rj.m_used;
+                lmv[j] = rj.m_used + 1;
+                if (r && j == 0) {
+                    r->i_conv = rj.i_conv;
+                    r->seed_status = rj.seed_status;
+                }
+                if (r) r->reorth_passes += rj.reorth_passes;
+            }
+        } catch (...) {
+            h->p.past_factor = past;
+            throw;
+        }
+        h->p.past_factor = past;
+        const double t1 = now_s();
+        std::vector<int32_t> it(nrhs), mv(nrhs);
+        std::vector<double> res(nrhs);
+        seedcg_report rr{};
+        rr.iters = it.data();
+        rr.matvecs = mv.data();
+        rr.true_relres = res.data();
+        Io io;
+        io.B = B;
+        io.X = X;
+        const seedcg_status st = solve_rest_impl(h, io, nrhs, &rr);
+        if (r) {
+            for (int j = 0; j < nrhs; j++) {
+                if (r->iters) r->iters[j] = lz[j] + it[j];
+                if (r->matvecs) r->matvecs[j] = lmv[j] + mv[j];
+                if (r->true_relres) r->true_relres[j] = res[j];
+            }
+            r->m_used = lz[0];
+            r->t_rest_s = now_s() - t1;
+        }
+        if (st == SEEDCG_ERR_NOCONV) h->err = "solve_repeated: max_iter reached before tol";
+        return st;
+    });
+}
+
 seedcg_status seedcg_get_tridiag(seedcg_t h, double* alpha, double* beta, int32_t cap, int32_t* m) {
     if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "get_tridiag: null handle");
     return guarded(h, [&]() -> seedcg_status {

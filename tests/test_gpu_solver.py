@@ -211,3 +211,19 @@ def test_state_and_argument_errors():
     s.release_basis()
     with pytest.raises(SeedCGError):
         s.get_basis_vector(1)
+
+
+def test_repeated_seeding_matches_oracle(c1):
+    """Traditional repeated seeding: the Lanczos steps of every system agree with the oracle's
+    repeated seeding to within one step (system 1) or two (later systems, which start from seeded
+    guesses rounded differently), and every solution meets the FP64 tolerance."""
+    print_case("repeated seeding c1")
+    s = _solver(c1["U"], c1["dims"], c1["kappa"], reorth_k=10)
+    X, rep = s.solve_repeated(cuda(c1["B"]))
+    ref = osc.repeated_seed(c1["mv"], flat(c1["B"]), k=10, tol=1e-10)
+    assert abs(rep["m"] - ref["lanczos"][0]) <= 1
+    assert np.all(osc.true_relres(c1["mv"], flat(c1["B"]), flat(host(X))) <= 1e-10)
+    total_ref = [a + b for a, b in zip(ref["lanczos"], ref["cg"])]
+    for a, b in zip(rep["iters"], total_ref):
+        assert abs(a - b) <= max(3, 0.05 * b), (rep["iters"], total_ref)
+    print("repeated: gpu", rep["iters"], "oracle lanczos", ref["lanczos"], "cg", ref["cg"])

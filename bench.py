@@ -147,6 +147,7 @@ def main():
     compare = None
     if not args.no_compare:
         compare = compare_forms(args, cfg, Ud, kappa, B, value, prec)
+    copy_gbs = copy_rate()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -170,7 +171,8 @@ def main():
                    "max_true_relres": max(rr["true_relres"]),
                    "dagger_d_gbs_api": (288 * V * s_l + 120 * V * s_s) / t_m_api / 1e9 if t_m_api else None,
                    "dagger_d_us_api": t_m_api * 1e6 if t_m_api else None,
-                   "hop_launches_total": tm["seen"], "compare": compare},
+                   "hop_launches_total": tm["seen"], "compare": compare,
+                   "device_copy_gbs": copy_gbs},
     }
     print(json.dumps(result), flush=True)
 
@@ -229,6 +231,24 @@ def compare_forms(args, cfg, Ud, kappa, B, value_ref, prec_ref):
         log(f"compare {key}: {v:.2f} RHS/s ({v / value_ref:.2f}x)")
         s.close()
     return out
+
+
+def copy_rate():
+    """GB/s of a plain 1 GiB device-to-device copy (read + write bytes), timed with events: what HBM
+    delivers in practice, beside the 8 TB/s peak."""
+    import torch
+    src = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    del src, dst
+    return 2.0 * (1 << 30) / (ms * 1e-3) / 1e9
 
 
 def copy_probe():

@@ -180,7 +180,8 @@ def test_c4_full_batch_sampled_against_oracle():
         s = SeedCG(Ud, m.dims, k, autotune=False)
         B.append(s.apply_A(cuda(phi), dagger=True))
         s.close()
-    b = SeedCGBatch(links, [m.dims for m in members], kappas, 12, prec="mixed", reorth_k=10)
+    b = SeedCGBatch(links, [m.dims for m in members], kappas, 12, prec=members[0].prec, reorth_k=members[0].reorth_k,
+                    tol=members[0].tol)
     X, reps = b.solve(B)
     torch.cuda.synchronize()
     worst = max(max(r["true_relres"]) for r in reps)

@@ -192,6 +192,7 @@ def test_c4_full_batch_sampled_against_oracle():
             continue
         seen.add(m.dims)
         op = WilsonEO(inputs[c][0], m.dims, kappas[c])
-        res = osc.true_relres(matvec_M(op), flat(host(B[c])), flat(host(X[c])))
+        B_ref = op.apply_Adag(inputs[c][1])      # the oracle's own right-hand sides
+        res = osc.true_relres(matvec_M(op), flat(B_ref), flat(host(X[c])))
         assert np.all(res <= 1e-10), (m.name, res)
         print("c4", m.name, m.dims, "m", reps[c]["m"], "iters", reps[c]["iters"], "oracle relres", float(res.max()))

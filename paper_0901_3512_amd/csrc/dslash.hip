@@ -69,6 +69,8 @@ struct LinkLoad<double> {
         const cx<double> v = *(const Store*)((const char*)base + idx * (uint32_t)sizeof(Store));
         return mk<T>((T)v.re, (T)v.im);
     }
+    template <typename T>
+    __device__ static inline cx<T> cvt(Store v) { return mk<T>((T)v.re, (T)v.im); }
 };
 template <>
 struct LinkLoad<float> {
@@ -84,6 +86,8 @@ struct LinkLoad<float> {
         const cx<float> v = *(const Store*)((const char*)base + idx * (uint32_t)sizeof(Store));
         return mk<T>((T)v.re, (T)v.im);
     }
+    template <typename T>
+    __device__ static inline cx<T> cvt(Store v) { return mk<T>((T)v.re, (T)v.im); }
 };
 // BF16 links: one 32-bit word per complex entry, re in the low half, im in the high half.
 struct bf16link {};
@@ -103,6 +107,8 @@ struct LinkLoad<bf16link> {
         const uint32_t w = *(const Store*)((const char*)base + idx * (uint32_t)sizeof(Store));
         return mk<T>((T)__uint_as_float(w << 16), (T)__uint_as_float(w & 0xffff0000u));
     }
+    template <typename T>
+    __device__ static inline cx<T> cvt(Store w) { return mk<T>((T)__uint_as_float(w << 16), (T)__uint_as_float(w & 0xffff0000u)); }
 };
 
 // Special-unitary links stored as their first two rows (6 complex entries); the third row is
@@ -123,6 +129,8 @@ struct LinkLoad<su3rows<S>> {
         const cx<S> v = *(const Store*)((const char*)base + idx * (uint32_t)sizeof(Store));
         return mk<T>((T)v.re, (T)v.im);
     }
+    template <typename T>
+    __device__ static inline cx<T> cvt(Store v) { return mk<T>((T)v.re, (T)v.im); }
 };
 template <typename T>
 __device__ inline cx<T> conjc(cx<T> a) { return mk<T>(a.re, -a.im); }
@@ -772,6 +780,305 @@ __global__ __launch_bounds__(SCG_BLOCK) void hop_multi_kernel(Geom g, const type
     }
 }
 
+// ---- wave-split variant -------------------------------------------------------------------
+// The two lanes-per-site kernels above give each site's forward hops to an even lane and its
+// backward hops to the odd lane, so every lane selects between U and U^dag, between the signs of
+// the two hop directions and between the projection coefficients at run time: on a 16-lane SIMD
+// those selects cost as much issue time as the arithmetic itself.  Here whole wavefronts take one
+// hop direction: waves 0 and 1 of a workgroup the forward hops of its 128 sites, waves 2 and 3 the
+// backward hops of the same sites, and the direction mu is a compile-time constant in each of the
+// four unrolled bodies.  Projection and reconstruction coefficients then fold into adds and
+// fused multiply-adds, U^dag into operand order and signs.  The two halves of each site's sum meet
+// in LDS: every wave hands the six output components that the other wave writes, adds the six it
+// receives and runs the epilogue on its own six.
+
+// Raw buffer loads: a descriptor (base and size in bytes) in scalar registers and one 32-bit lane
+// offset shared by all component loads of a field, the component's offset going into the scalar
+// soffset operand; a 64-bit address per load would cost two VGPRs and a 64-bit add each.  An
+// offset beyond the size reads zero instead of faulting.
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <typename S>
+__device__ inline S bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    static_assert(sizeof(S) == 16 || sizeof(S) == 8 || sizeof(S) == 4, "load width");
+    if constexpr (sizeof(S) == 16)
+        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    else if constexpr (sizeof(S) == 8)
+        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    else
+        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+// projection coefficients of proj_of(mu) as compile-time constants (forward hop)
+template <int MU>
+struct PJ;
+template <>
+struct PJ<0> {
+    static constexpr int a0 = 3, c0r = 0, c0i = 1, c1r = 0, c1i = 1, b0 = 1, d0r = 0, d0i = -1, d1r = 0, d1i = -1;
+};
+template <>
+struct PJ<1> {
+    static constexpr int a0 = 3, c0r = 1, c0i = 0, c1r = -1, c1i = 0, b0 = 1, d0r = -1, d0i = 0, d1r = 1, d1i = 0;
+};
+template <>
+struct PJ<2> {
+    static constexpr int a0 = 2, c0r = 0, c0i = 1, c1r = 0, c1i = -1, b0 = 0, d0r = 0, d0i = -1, d1r = 0, d1i = 1;
+};
+template <>
+struct PJ<3> {
+    static constexpr int a0 = 2, c0r = -1, c0i = 0, c1r = -1, c1i = 0, b0 = 0, d0r = -1, d0i = 0, d1r = -1, d1i = 0;
+};
+
+// u * a for a compile-time unit u = R + i I (one of R, I is zero): a sign change or a swap, never
+// a multiplication (0 * x does not fold away in IEEE arithmetic)
+template <int R, int I, typename T>
+__device__ inline cx<T> umulc(cx<T> a) {
+    static_assert((R == 0) != (I == 0), "unit coefficient");
+    if constexpr (I == 0)
+        return R > 0 ? a : mk<T>(-a.re, -a.im);
+    else
+        return I > 0 ? mk<T>(-a.im, a.re) : mk<T>(a.im, -a.re);
+}
+
+// w += a * b and w += conj(a) * b as four fused multiply-adds each
+template <typename T>
+__device__ inline void cmac(cx<T>& w, cx<T> a, cx<T> b) {
+    w.re = fma(a.re, b.re, w.re);
+    w.re = fma(-a.im, b.im, w.re);
+    w.im = fma(a.re, b.im, w.im);
+    w.im = fma(a.im, b.re, w.im);
+}
+template <typename T>
+__device__ inline void cjmac(cx<T>& w, cx<T> a, cx<T> b) {
+    w.re = fma(a.re, b.re, w.re);
+    w.re = fma(a.im, b.im, w.re);
+    w.im = fma(a.re, b.im, w.im);
+    w.im = fma(-a.im, b.re, w.im);
+}
+
+// neighbour index of site h = (x, y, z, t) in direction MU (forward, or backward when BWD) without
+// divisions: a step along y, z or t moves h by a fixed stride, wrapping at the boundary
+template <int MU, bool BWD>
+__device__ inline uint32_t nb_split(const Geom& g, int x, int y, int z, int t, int xh, uint32_t h32, int& sign) {
+    sign = 1;
+    if constexpr (MU == 0) {
+        const int xn = BWD ? (x == 0 ? g.L[0] - 1 : x - 1) : (x == g.L[0] - 1 ? 0 : x + 1);
+        return h32 - (uint32_t)xh + (uint32_t)(xn >> 1);
+    } else {
+        const int c = MU == 1 ? y : (MU == 2 ? z : t);
+        const int L = g.L[MU];
+        const uint32_t stride = (uint32_t)g.Lxh * (MU >= 2 ? (uint32_t)g.L[1] : 1u) * (MU == 3 ? (uint32_t)g.L[2] : 1u);
+        const bool wrap = BWD ? c == 0 : c == L - 1;
+        if (MU == 3 && wrap) sign = g.t_bc;
+        const uint32_t span = (uint32_t)(L - 1) * stride;
+        if constexpr (BWD)
+            return wrap ? h32 + span : h32 - stride;
+        else
+            return wrap ? h32 - span : h32 + stride;
+    }
+}
+
+// acc += s * w for a runtime sign s = +-1, as fused multiply-adds
+template <typename T>
+__device__ inline void acc_fma(cx<T>& acc, T s, cx<T> w) {
+    acc.re = fma(s, w.re, acc.re);
+    acc.im = fma(s, w.im, acc.im);
+}
+
+// One hop direction of the wave-split kernel for NV vectors: the neighbour's spinor projected
+// with (1 -/+ gamma_mu), multiplied by U (forward) or U^dag (backward) and reconstructed into acc.
+template <typename T, typename LT, int NV, int MU, bool BWD>
+__device__ __attribute__((always_inline)) inline void split_dir(const Geom& g, const typename LinkLoad<LT>::Store* __restrict__ links, const cx<T>* __restrict__ in,
+                                 const int (&vec)[NV], int p, int x, int y, int z, int t, int xh, int64_t row, uint32_t h32,
+                                 cx<T> (&acc)[NV][12]) {
+    using C = PJ<MU>;
+    constexpr int s = BWD ? -1 : 1;   // the backward hop negates every coefficient
+    constexpr int a0 = C::a0, a1 = 5 - C::a0;
+    int nsign;
+    const uint32_t hn = nb_split<MU, BWD>(g, x, y, z, t, xh, h32, nsign);
+    const T sign = (T)nsign;
+    const uint32_t Vh32 = (uint32_t)g.Vh;
+    const uint32_t lpar = BWD ? 1u - (uint32_t)p : (uint32_t)p;
+    using S = typename LinkLoad<LT>::Store;
+    constexpr int NE = LinkLoad<LT>::NE;
+    const auto lr = buf_rsrc(links + (size_t)(MU * 2 + lpar) * NE * Vh32, (uint32_t)NE * Vh32 * (uint32_t)sizeof(S));
+    const uint32_t loff = (BWD ? hn : h32) * (uint32_t)sizeof(S);
+    cx<T> u[9];
+#pragma unroll
+    for (int c = 0; c < NE; c++) u[c] = LinkLoad<LT>::template cvt<T>(bload<S>(lr, loff, (uint32_t)c * Vh32 * (uint32_t)sizeof(S)));
+    if constexpr (NE == 6) su3_third_row(u);
+    const uint32_t soff = hn * (uint32_t)sizeof(cx<T>);
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+        if (vec[v] < 0) continue;   // uniform
+        const auto sr = buf_rsrc(in + (size_t)vec[v] * 12 * Vh32, 12u * Vh32 * (uint32_t)sizeof(cx<T>));
+        cx<T> ps[12];
+#pragma unroll
+        for (int c = 0; c < 12; c++) ps[c] = bload<cx<T>>(sr, soff, (uint32_t)c * Vh32 * (uint32_t)sizeof(cx<T>));
+        cx<T> hp[2][3];
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            hp[0][a] = ps[a] + umulc<s * C::c0r, s * C::c0i>(ps[3 * a0 + a]);
+            hp[1][a] = ps[3 + a] + umulc<s * C::c1r, s * C::c1i>(ps[3 * a1 + a]);
+        }
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            cx<T> ch[2];
+#pragma unroll
+            for (int sp = 0; sp < 2; sp++) {
+                cx<T> w = BWD ? cjmul(u[a], hp[sp][0]) : cmul(u[a * 3], hp[sp][0]);
+#pragma unroll
+                for (int b = 1; b < 3; b++) {
+                    if (BWD)
+                        cjmac(w, u[b * 3 + a], hp[sp][b]);
+                    else
+                        cmac(w, u[a * 3 + b], hp[sp][b]);
+                }
+                ch[sp] = w;
+            }
+            acc_fma(acc[v][a], sign, ch[0]);
+            acc_fma(acc[v][3 + a], sign, ch[1]);
+            acc_fma(acc[v][6 + a], sign, umulc<s * C::d0r, s * C::d0i>(C::b0 == 1 ? ch[1] : ch[0]));
+            acc_fma(acc[v][9 + a], sign, umulc<s * C::d1r, s * C::d1i>(C::b0 == 1 ? ch[0] : ch[1]));
+        }
+    }
+}
+
+// the four directions of one hop side, then the hand-over of the other side's six components
+template <typename T, typename LT, int NV, bool BWD>
+__device__ __attribute__((always_inline)) inline void split_hops(const Geom& g, const typename LinkLoad<LT>::Store* __restrict__ links, const cx<T>* __restrict__ in,
+                                  const int (&vec)[NV], int p, bool active, int x, int y, int z, int t, int xh, int64_t row,
+                                  uint32_t h32, int sl, cx<T> (&acc)[NV][12], cx<T>* xch) {
+    if (active) {
+        // straight-line directions; the scheduling fences keep each direction's loads with it, so
+        // that the registers in flight are those of one direction
+        split_dir<T, LT, NV, 0, BWD>(g, links, in, vec, p, x, y, z, t, xh, row, h32, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        split_dir<T, LT, NV, 1, BWD>(g, links, in, vec, p, x, y, z, t, xh, row, h32, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        split_dir<T, LT, NV, 2, BWD>(g, links, in, vec, p, x, y, z, t, xh, row, h32, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        split_dir<T, LT, NV, 3, BWD>(g, links, in, vec, p, x, y, z, t, xh, row, h32, acc);
+    }
+    // hand over the components the other side writes: [vector][side receiving][component][site]
+    constexpr int other = BWD ? 0 : 6;
+#pragma unroll
+    for (int v = 0; v < NV; v++)
+#pragma unroll
+        for (int c = 0; c < 6; c++) xch[((v * 2 + (BWD ? 0 : 1)) * 6 + c) * (SCG_BLOCK / 2) + sl] = acc[v][other + c];
+}
+
+// the other side's six components added to this side's, then the epilogue on them
+template <typename T, int NV, bool BWD>
+__device__ __attribute__((always_inline)) inline void split_tail(const EpiDev<T>& e, const int (&vec)[NV], bool active, uint32_t Vh32,
+                                                                 uint32_t h32, int sl, int wave, const cx<T> (&acc)[NV][12],
+                                                                 const cx<T>* xch, cx<T>* __restrict__ out, double* red_lds) {
+    constexpr int own = BWD ? 6 : 0;
+    const uint32_t lo = (uint32_t)own * Vh32 + h32;
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+        double part = 0.0;
+        if (active && vec[v] >= 0) {
+            cx<T> w[6];
+#pragma unroll
+            for (int c = 0; c < 6; c++) w[c] = acc[v][own + c] + xch[((v * 2 + (BWD ? 1 : 0)) * 6 + c) * (SCG_BLOCK / 2) + sl];
+            const size_t vo = (size_t)vec[v] * 12 * Vh32;
+            double czd = e.cz_host;
+            if (e.cz_dev) czd = e.cz_negate ? -e.cz_dev[vec[v]] : e.cz_dev[vec[v]];
+            part = epilogue2<T>(e, w, BWD ? 1 : 0, vo, (int64_t)Vh32, lo, out, (T)czd);
+        }
+        if (e.red) {
+            for (int off = SCG_WAVE / 2; off > 0; off >>= 1) part += __shfl_xor(part, off);
+            if ((threadIdx.x % SCG_WAVE) == 0) red_lds[v * (SCG_BLOCK / SCG_WAVE) + wave] = part;
+        }
+    }
+}
+
+template <typename T, typename LT, int NV>
+__global__ __launch_bounds__(SCG_BLOCK) void hop_split_kernel(Geom g, const typename LinkLoad<LT>::Store* __restrict__ links,
+                                                              const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+                                                              int p, int nvec, int64_t nsb, EpiDev<T> e, int64_t cs, int64_t bps) {
+    __shared__ cx<T> xch[NV * 2 * 6 * (SCG_BLOCK / 2)];
+    __shared__ double red_lds[NV * (SCG_BLOCK / SCG_WAVE)];
+    zoff_hop(cs, links, in, out, e);
+    if (e.gate_m && e.gate_i > *e.gate_m) return;
+    if (e.kappa2_dev) e.kappa2 = (T)*e.kappa2_dev;
+    const int nvg = (nvec + NV - 1) / NV;
+    const int64_t nblk = nsb * nvg;
+    const int64_t logical = xcd_logical_block(nblk);
+    if (logical >= nblk) return;
+    const int vg = (int)(logical % nvg);
+    const int64_t sb = logical / nvg;   // position in the visiting order (partials are indexed by it)
+    const int64_t Vh = g.Vh;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / SCG_WAVE));
+    const bool bwd = wave >= 2;                                   // uniform over the wavefront
+    const int sl = (wave & 1) * SCG_WAVE + (int)(threadIdx.x % SCG_WAVE);   // site within the block
+    const int64_t h = sb_order(sb, bps, g.L[3]) * (SCG_BLOCK / 2) + sl;
+    const bool active = h < Vh;
+
+    int x = 0, y = 0, z = 0, t = 0, xh = 0;
+    const int64_t row = 0;   // unused: neighbours come from nb_split
+    if (active) {            // 32-bit arithmetic: a half lattice has fewer than 2^31 sites
+        const uint32_t hu = (uint32_t)h;
+        xh = (int)(hu % (uint32_t)g.Lxh);
+        uint32_t r = hu / (uint32_t)g.Lxh;
+        y = (int)(r % (uint32_t)g.L[1]);
+        r /= (uint32_t)g.L[1];
+        z = (int)(r % (uint32_t)g.L[2]);
+        t = (int)(r / (uint32_t)g.L[2]);
+        x = 2 * xh + ((y + z + t + p) & 1);
+    }
+    const uint32_t Vh32 = (uint32_t)Vh, h32 = (uint32_t)h;
+
+    // the group's vectors (-1: empty slot, or a vector whose CG is done or frozen); uniform
+    int vec[NV];
+    bool any = false;
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+        const int slot = vg * NV + v;
+        int q = -1;
+        if (slot < nvec) {
+            q = e.vec_map ? e.vec_map[slot] : slot;
+            if (q >= 0 && e.cg && (e.cg[q].done || e.cg[q].frozen)) q = -1;
+        }
+        vec[v] = __builtin_amdgcn_readfirstlane(q);
+        any = any || vec[v] >= 0;
+    }
+    if (!any) return;  // uniform over the workgroup
+
+    cx<T> acc[NV][12];
+#pragma unroll
+    for (int v = 0; v < NV; v++)
+#pragma unroll
+        for (int c = 0; c < 12; c++) acc[v][c] = mk<T>(0, 0);
+    if (bwd)
+        split_hops<T, LT, NV, true>(g, links, in, vec, p, active, x, y, z, t, xh, row, h32, sl, acc, xch);
+    else
+        split_hops<T, LT, NV, false>(g, links, in, vec, p, active, x, y, z, t, xh, row, h32, sl, acc, xch);
+    __syncthreads();
+
+    if (bwd)
+        split_tail<T, NV, true>(e, vec, active, Vh32, h32, sl, wave, acc, xch, out, red_lds);
+    else
+        split_tail<T, NV, false>(e, vec, active, Vh32, h32, sl, wave, acc, xch, out, red_lds);
+    if (e.red) {
+        __syncthreads();
+        const int v = threadIdx.x;
+        if (v < NV) {
+            int q = -1;
+#pragma unroll
+            for (int k = 0; k < NV; k++)
+                if (k == v) q = vec[k];
+            if (q >= 0) {
+                double s = 0.0;
+                for (int w = 0; w < SCG_BLOCK / SCG_WAVE; w++) s += red_lds[v * (SCG_BLOCK / SCG_WAVE) + w];
+                e.partials[(int64_t)q * nsb + sb] = s;
+            }
+        }
+    }
+}
+
 static int g_order = -1;
 static bool getenv_order() {
     if (g_order < 0) {
@@ -794,7 +1101,9 @@ void set_hop_hoist_links(bool on) { g_hoist = on ? 1 : 0; }
 // tps: 1, 2, 4 lanes per site (direction split), or the lean forward/backward variant (2 lanes)
 // with 1 (tps 3), 2 (tps 5) or 4 (tps 6) directions per pass
 // tps 7: the multi-vector variant (two lanes per site, links loaded once for vb vectors, vb 2 or 4)
-int hop_threads_per_site(int tps) { return (tps == 3 || tps == 5 || tps == 6 || tps == 7) ? 2 : tps; }
+// tps 8: the wave-split variant (forward and backward hops on separate wavefronts, vb 1, 2 or 4
+// vectors per workgroup)
+int hop_threads_per_site(int tps) { return (tps == 3 || tps == 5 || tps == 6 || tps == 7 || tps == 8) ? 2 : tps; }
 int hop_site_blocks(const Geom& g, int tps) {
     return (int)((g.Vh * hop_threads_per_site(tps) + SCG_BLOCK - 1) / SCG_BLOCK);
 }
@@ -826,6 +1135,9 @@ static void launch_t(const Geom& g, const void* links, const void* in, void* out
     vb = vb > HOP_MAX_VB ? HOP_MAX_VB : vb;
     if (tps == 5 || tps == 6) vb = 1;
     if (tps == 7) vb = vb <= 2 ? 2 : 4;
+    if (tps == 8) vb = vb <= 1 ? 1 : (vb <= 2 ? 2 : 4);
+    // the wave-split kernel addresses a vector and a link field with 32-bit byte offsets
+    if (tps == 8 && (double)g.Vh * 12.0 * (double)sizeof(cx<T>) >= 4294967296.0) tps = 3, vb = 1;
     const int64_t grid = xcd_grid(nsb * ((nvec + vb - 1) / vb));
     // site blocks per t-slice for the tiled visiting order (two lanes per site, 128 sites a block)
     const int64_t slice = g.Vh / g.L[3];
@@ -844,6 +1156,15 @@ static void launch_t(const Geom& g, const void* links, const void* in, void* out
                            (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e, L.cs, bps);
     else if (tps == 7)
         hipLaunchKernelGGL((hop_multi_kernel<T, LT, 4>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
+                           (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e, L.cs, bps);
+    else if (tps == 8 && vb == 1)
+        hipLaunchKernelGGL((hop_split_kernel<T, LT, 1>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
+                           (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e, L.cs, bps);
+    else if (tps == 8 && vb == 2)
+        hipLaunchKernelGGL((hop_split_kernel<T, LT, 2>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
+                           (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e, L.cs, bps);
+    else if (tps == 8)
+        hipLaunchKernelGGL((hop_split_kernel<T, LT, 4>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
                            (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e, L.cs, bps);
     else if (tps == 5)
         hipLaunchKernelGGL((hop_lean_kernel<T, LT, true, 2>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,

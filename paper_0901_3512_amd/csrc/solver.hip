@@ -1400,8 +1400,8 @@ void init_geometry(seedcg_s* h, const seedcg_params* p, const int32_t* dims) {
     // per workgroup; the vectors of a site block run as adjacent workgroups on one XCD
     h->tps64 = env_int("SEEDCG_TPS", 3);
     h->tps_lo = env_int("SEEDCG_TPS_LO", 3);
-    if (h->tps64 < 1 || h->tps64 > 7) h->tps64 = 3;
-    if (h->tps_lo < 1 || h->tps_lo > 7) h->tps_lo = 3;
+    if (h->tps64 < 1 || h->tps64 > 8) h->tps64 = 3;
+    if (h->tps_lo < 1 || h->tps_lo > 8) h->tps_lo = 3;
     h->vb64 = std::max(1, env_int("SEEDCG_VB", 1));
     h->vb_lo = std::max(1, env_int("SEEDCG_VB_LO", 1));
     h->tps64_multi = h->tps64;
@@ -1463,8 +1463,10 @@ void tune_shape(seedcg_s* h, bool low, int nvec, const void* x, void* y) {
             return;
         }
     }
-    std::vector<std::pair<int, int>> cand{{3, 1}, {5, 1}, {6, 1}, {4, 1}, {2, 1}, {1, 1}};
+    std::vector<std::pair<int, int>> cand{{8, 1}, {3, 1}, {5, 1}, {6, 1}, {4, 1}, {2, 1}, {1, 1}};
     if (multi) {
+        cand.push_back({8, 2});                 // wave-split, links once per pair / quad of vectors
+        cand.push_back({8, 4});
         cand.push_back({4, 2});
         cand.push_back({4, 4});
         cand.push_back({7, 2});                 // links once per pair of vectors

@@ -20,13 +20,14 @@ def _vecs(rng, n, Vh):
     return rng.standard_normal((n, Vh, 4, 3)) + 1j * rng.standard_normal((n, Vh, 4, 3))
 
 
-@pytest.mark.parametrize("tps", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("tps", [1, 2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("dims,t_bc,eps", CASES)
 @pytest.mark.parametrize("vb", [1, 2, 4])
 def test_apply_M_matches_oracle(dims, t_bc, eps, tps, vb, monkeypatch):
     """tps: lanes per site (1, 2, 4), or two lanes per site: 3 / 5 / 6 = one / two / four directions per
-    pass, 7 = links loaded once for a group of vb vectors (2 or 4); vb: vectors per workgroup."""
-    if vb == 4 and tps != 7:
+    pass, 7 = links loaded once for a group of vb vectors (2 or 4), 8 = forward and backward hops on
+    separate wavefronts for a group of vb vectors (1, 2 or 4); vb: vectors per workgroup."""
+    if vb == 4 and tps not in (7, 8):
         pytest.skip("vb = 4 only changes the multi-vector variant")
     from paper_0901_3512_amd import SeedCG
     print_case("apply_M", dims, t_bc, tps, vb)

@@ -18,6 +18,7 @@
 #include "internal.h"
 #include <hip/hip_bf16.h>
 #include <cstdlib>
+#include <stdexcept>
 
 namespace scg {
 
@@ -886,18 +887,42 @@ __device__ inline void acc_fma(cx<T>& acc, T s, cx<T> w) {
     acc.im = fma(s, w.im, acc.im);
 }
 
+// The input spinors of a tile of xy-rows staged in LDS ([vector][component][staged site]): the x
+// and y neighbours of the tile's sites are read from there.  rown is the lane's row in the stage;
+// with whole set the stage is the whole xy-plane and y wraps inside it, otherwise it holds one
+// halo row on either side of the tile.
+template <typename T>
+struct Stage {
+    const cx<T>* st;
+    uint32_t S;   // staged sites
+    int rown, whole;
+};
+
 // One hop direction of the wave-split kernel for NV vectors: the neighbour's spinor projected
 // with (1 -/+ gamma_mu), multiplied by U (forward) or U^dag (backward) and reconstructed into acc.
-template <typename T, typename LT, int NV, int MU, bool BWD>
+// PLANE: x and y neighbours come from the LDS stage.
+template <typename T, typename LT, int NV, int MU, bool BWD, bool PLANE>
 __device__ __attribute__((always_inline)) inline void split_dir(const Geom& g, const typename LinkLoad<LT>::Store* __restrict__ links, const cx<T>* __restrict__ in,
-                                 const int (&vec)[NV], int p, int x, int y, int z, int t, int xh, int64_t row, uint32_t h32,
-                                 cx<T> (&acc)[NV][12]) {
+                                 const int (&vec)[NV], int p, int x, int y, int z, int t, int xh, uint32_t h32,
+                                 const Stage<T>& sg, cx<T> (&acc)[NV][12]) {
     using C = PJ<MU>;
     constexpr int s = BWD ? -1 : 1;   // the backward hop negates every coefficient
     constexpr int a0 = C::a0, a1 = 5 - C::a0;
     int nsign;
     const uint32_t hn = nb_split<MU, BWD>(g, x, y, z, t, xh, h32, nsign);
     const T sign = (T)nsign;
+    constexpr bool LDS = PLANE && MU <= 1;
+    uint32_t ln = 0;   // the neighbour's staged site
+    if constexpr (LDS) {
+        if constexpr (MU == 0) {
+            const int xn = BWD ? (x == 0 ? g.L[0] - 1 : x - 1) : (x == g.L[0] - 1 ? 0 : x + 1);
+            ln = (uint32_t)(sg.rown * g.Lxh + (xn >> 1));
+        } else {
+            int rn = BWD ? sg.rown - 1 : sg.rown + 1;
+            if (sg.whole) rn = BWD ? (y == 0 ? g.L[1] - 1 : rn) : (y == g.L[1] - 1 ? 0 : rn);
+            ln = (uint32_t)(rn * g.Lxh + xh);
+        }
+    }
     const uint32_t Vh32 = (uint32_t)g.Vh;
     const uint32_t lpar = BWD ? 1u - (uint32_t)p : (uint32_t)p;
     using S = typename LinkLoad<LT>::Store;
@@ -912,10 +937,15 @@ __device__ __attribute__((always_inline)) inline void split_dir(const Geom& g, c
 #pragma unroll
     for (int v = 0; v < NV; v++) {
         if (vec[v] < 0) continue;   // uniform
-        const auto sr = buf_rsrc(in + (size_t)vec[v] * 12 * Vh32, 12u * Vh32 * (uint32_t)sizeof(cx<T>));
         cx<T> ps[12];
+        if constexpr (LDS) {
 #pragma unroll
-        for (int c = 0; c < 12; c++) ps[c] = bload<cx<T>>(sr, soff, (uint32_t)c * Vh32 * (uint32_t)sizeof(cx<T>));
+            for (int c = 0; c < 12; c++) ps[c] = sg.st[(uint32_t)(v * 12 + c) * sg.S + ln];
+        } else {
+            const auto sr = buf_rsrc(in + (size_t)vec[v] * 12 * Vh32, 12u * Vh32 * (uint32_t)sizeof(cx<T>));
+#pragma unroll
+            for (int c = 0; c < 12; c++) ps[c] = bload<cx<T>>(sr, soff, (uint32_t)c * Vh32 * (uint32_t)sizeof(cx<T>));
+        }
         cx<T> hp[2][3];
 #pragma unroll
         for (int a = 0; a < 3; a++) {
@@ -945,35 +975,39 @@ __device__ __attribute__((always_inline)) inline void split_dir(const Geom& g, c
     }
 }
 
-// the four directions of one hop side, then the hand-over of the other side's six components
-template <typename T, typename LT, int NV, bool BWD>
+// the four directions of one hop side
+template <typename T, typename LT, int NV, bool BWD, bool PLANE>
 __device__ __attribute__((always_inline)) inline void split_hops(const Geom& g, const typename LinkLoad<LT>::Store* __restrict__ links, const cx<T>* __restrict__ in,
-                                  const int (&vec)[NV], int p, bool active, int x, int y, int z, int t, int xh, int64_t row,
-                                  uint32_t h32, int sl, cx<T> (&acc)[NV][12], cx<T>* xch) {
+                                  const int (&vec)[NV], int p, bool active, int x, int y, int z, int t, int xh,
+                                  uint32_t h32, const Stage<T>& sg, cx<T> (&acc)[NV][12]) {
     if (active) {
         // straight-line directions; the scheduling fences keep each direction's loads with it, so
         // that the registers in flight are those of one direction
-        split_dir<T, LT, NV, 0, BWD>(g, links, in, vec, p, x, y, z, t, xh, row, h32, acc);
+        split_dir<T, LT, NV, 0, BWD, PLANE>(g, links, in, vec, p, x, y, z, t, xh, h32, sg, acc);
         __builtin_amdgcn_sched_barrier(0);
-        split_dir<T, LT, NV, 1, BWD>(g, links, in, vec, p, x, y, z, t, xh, row, h32, acc);
+        split_dir<T, LT, NV, 1, BWD, PLANE>(g, links, in, vec, p, x, y, z, t, xh, h32, sg, acc);
         __builtin_amdgcn_sched_barrier(0);
-        split_dir<T, LT, NV, 2, BWD>(g, links, in, vec, p, x, y, z, t, xh, row, h32, acc);
+        split_dir<T, LT, NV, 2, BWD, PLANE>(g, links, in, vec, p, x, y, z, t, xh, h32, sg, acc);
         __builtin_amdgcn_sched_barrier(0);
-        split_dir<T, LT, NV, 3, BWD>(g, links, in, vec, p, x, y, z, t, xh, row, h32, acc);
+        split_dir<T, LT, NV, 3, BWD, PLANE>(g, links, in, vec, p, x, y, z, t, xh, h32, sg, acc);
     }
-    // hand over the components the other side writes: [vector][side receiving][component][site]
+}
+
+// hand over the six components the other side writes: xch[vector][side receiving][component][site]
+template <typename T, int NV, bool BWD>
+__device__ __attribute__((always_inline)) inline void split_handover(const cx<T> (&acc)[NV][12], cx<T>* xch, uint32_t xs, int sl) {
     constexpr int other = BWD ? 0 : 6;
 #pragma unroll
     for (int v = 0; v < NV; v++)
 #pragma unroll
-        for (int c = 0; c < 6; c++) xch[((v * 2 + (BWD ? 0 : 1)) * 6 + c) * (SCG_BLOCK / 2) + sl] = acc[v][other + c];
+        for (int c = 0; c < 6; c++) xch[(uint32_t)((v * 2 + (BWD ? 0 : 1)) * 6 + c) * xs + sl] = acc[v][other + c];
 }
 
 // the other side's six components added to this side's, then the epilogue on them
 template <typename T, int NV, bool BWD>
 __device__ __attribute__((always_inline)) inline void split_tail(const EpiDev<T>& e, const int (&vec)[NV], bool active, uint32_t Vh32,
-                                                                 uint32_t h32, int sl, int wave, const cx<T> (&acc)[NV][12],
-                                                                 const cx<T>* xch, cx<T>* __restrict__ out, double* red_lds) {
+                                                                 uint32_t h32, int sl, int wave, int nwave, const cx<T> (&acc)[NV][12],
+                                                                 const cx<T>* xch, uint32_t xs, cx<T>* __restrict__ out, double* red_lds) {
     constexpr int own = BWD ? 6 : 0;
     const uint32_t lo = (uint32_t)own * Vh32 + h32;
 #pragma unroll
@@ -982,7 +1016,7 @@ __device__ __attribute__((always_inline)) inline void split_tail(const EpiDev<T>
         if (active && vec[v] >= 0) {
             cx<T> w[6];
 #pragma unroll
-            for (int c = 0; c < 6; c++) w[c] = acc[v][own + c] + xch[((v * 2 + (BWD ? 1 : 0)) * 6 + c) * (SCG_BLOCK / 2) + sl];
+            for (int c = 0; c < 6; c++) w[c] = acc[v][own + c] + xch[(uint32_t)((v * 2 + (BWD ? 1 : 0)) * 6 + c) * xs + sl];
             const size_t vo = (size_t)vec[v] * 12 * Vh32;
             double czd = e.cz_host;
             if (e.cz_dev) czd = e.cz_negate ? -e.cz_dev[vec[v]] : e.cz_dev[vec[v]];
@@ -990,7 +1024,7 @@ __device__ __attribute__((always_inline)) inline void split_tail(const EpiDev<T>
         }
         if (e.red) {
             for (int off = SCG_WAVE / 2; off > 0; off >>= 1) part += __shfl_xor(part, off);
-            if ((threadIdx.x % SCG_WAVE) == 0) red_lds[v * (SCG_BLOCK / SCG_WAVE) + wave] = part;
+            if ((threadIdx.x % SCG_WAVE) == 0) red_lds[v * nwave + wave] = part;
         }
     }
 }
@@ -1018,8 +1052,7 @@ __global__ __launch_bounds__(SCG_BLOCK) void hop_split_kernel(Geom g, const type
     const bool active = h < Vh;
 
     int x = 0, y = 0, z = 0, t = 0, xh = 0;
-    const int64_t row = 0;   // unused: neighbours come from nb_split
-    if (active) {            // 32-bit arithmetic: a half lattice has fewer than 2^31 sites
+    if (active) {   // 32-bit arithmetic: a half lattice has fewer than 2^31 sites
         const uint32_t hu = (uint32_t)h;
         xh = (int)(hu % (uint32_t)g.Lxh);
         uint32_t r = hu / (uint32_t)g.Lxh;
@@ -1052,16 +1085,22 @@ __global__ __launch_bounds__(SCG_BLOCK) void hop_split_kernel(Geom g, const type
     for (int v = 0; v < NV; v++)
 #pragma unroll
         for (int c = 0; c < 12; c++) acc[v][c] = mk<T>(0, 0);
-    if (bwd)
-        split_hops<T, LT, NV, true>(g, links, in, vec, p, active, x, y, z, t, xh, row, h32, sl, acc, xch);
-    else
-        split_hops<T, LT, NV, false>(g, links, in, vec, p, active, x, y, z, t, xh, row, h32, sl, acc, xch);
+    const Stage<T> sg{nullptr, 0, 0, 0};
+    constexpr uint32_t xs = SCG_BLOCK / 2;
+    if (bwd) {
+        split_hops<T, LT, NV, true, false>(g, links, in, vec, p, active, x, y, z, t, xh, h32, sg, acc);
+        split_handover<T, NV, true>(acc, xch, xs, sl);
+    } else {
+        split_hops<T, LT, NV, false, false>(g, links, in, vec, p, active, x, y, z, t, xh, h32, sg, acc);
+        split_handover<T, NV, false>(acc, xch, xs, sl);
+    }
     __syncthreads();
 
+    constexpr int nwave = SCG_BLOCK / SCG_WAVE;
     if (bwd)
-        split_tail<T, NV, true>(e, vec, active, Vh32, h32, sl, wave, acc, xch, out, red_lds);
+        split_tail<T, NV, true>(e, vec, active, Vh32, h32, sl, wave, nwave, acc, xch, xs, out, red_lds);
     else
-        split_tail<T, NV, false>(e, vec, active, Vh32, h32, sl, wave, acc, xch, out, red_lds);
+        split_tail<T, NV, false>(e, vec, active, Vh32, h32, sl, wave, nwave, acc, xch, xs, out, red_lds);
     if (e.red) {
         __syncthreads();
         const int v = threadIdx.x;
@@ -1077,6 +1116,167 @@ __global__ __launch_bounds__(SCG_BLOCK) void hop_split_kernel(Geom g, const type
             }
         }
     }
+}
+
+// ---- LDS-staged variant --------------------------------------------------------------------
+// The wave-split kernel with the x and y neighbours read from LDS.  A workgroup takes a tile of R
+// whole xy-rows of one (z, t) plane (the whole plane when it has at most 256 sites, else tiles of
+// balanced size) and first
+// stages the input spinors of those rows, plus one halo row on either side, in LDS: every input
+// site is then fetched once for the four x and y hops instead of four times, and only the z and t
+// neighbours come from L2.  After the hops the same LDS holds the hand-over of the two sides.
+__host__ __device__ inline int plane_rows(const Geom& g) {
+    const int rmax = g.Lxh >= 256 ? 1 : 256 / g.Lxh;     // rows of at most 256 sites
+    const int ntile = (g.L[1] + rmax - 1) / rmax;
+    return (g.L[1] + ntile - 1) / ntile;                // balanced tiles
+}
+__host__ __device__ inline int plane_tiles(const Geom& g) { return (g.L[1] + plane_rows(g) - 1) / plane_rows(g); }
+// staged sites of the largest tile
+__host__ __device__ inline int plane_stage_sites(const Geom& g) {
+    const int R = plane_rows(g);
+    return (R >= g.L[1] ? g.L[1] : R + 2) * g.Lxh;
+}
+
+template <typename T, typename LT, int NV>
+__global__ __launch_bounds__(512) void hop_plane_kernel(Geom g, const typename LinkLoad<LT>::Store* __restrict__ links,
+                                                        const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int p, int nvec,
+                                                        int64_t nsb, EpiDev<T> e, int64_t cs, int Pw) {
+    extern __shared__ __align__(16) unsigned char plane_smem[];
+    cx<T>* st = reinterpret_cast<cx<T>*>(plane_smem);
+    __shared__ double red_lds[NV * 8];
+    zoff_hop(cs, links, in, out, e);
+    if (e.gate_m && e.gate_i > *e.gate_m) return;
+    if (e.kappa2_dev) e.kappa2 = (T)*e.kappa2_dev;
+    const int nvg = (nvec + NV - 1) / NV;
+    const int64_t nblk = nsb * nvg;
+    const int64_t logical = xcd_logical_block(nblk);
+    if (logical >= nblk) return;
+    const int vg = (int)(logical % nvg);
+    const int blk = (int)(logical / nvg);   // tile index (partials are indexed by it)
+    const int ntile = plane_tiles(g), R = plane_rows(g);
+    const int q = blk / ntile, j = blk - q * ntile;   // plane z + Lz t, tile within it
+    const int Lxh = g.Lxh, Ly = g.L[1];
+    const bool whole = R >= Ly;
+    const int y0 = j * R, Rt = min(R, Ly - y0), St = Rt * Lxh;
+    const int nws = Pw / SCG_WAVE;   // wavefronts per side
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / SCG_WAVE));
+    const bool bwd = wave >= nws;
+    const int sl = (wave - (bwd ? nws : 0)) * SCG_WAVE + (int)(threadIdx.x % SCG_WAVE);   // site within the tile
+    const bool active = sl < St;
+    const uint32_t Vh32 = (uint32_t)g.Vh;
+    const uint32_t base = (uint32_t)q * (uint32_t)(Lxh * Ly);   // first site of the plane
+    int x = 0, y = 0, z = 0, t = 0, xh = 0, yl = 0;
+    if (active) {
+        yl = sl / Lxh;
+        xh = sl - yl * Lxh;
+        y = y0 + yl;
+        z = q % g.L[2];
+        t = q / g.L[2];
+        x = 2 * xh + ((y + z + t + p) & 1);
+    }
+    const uint32_t h32 = base + (uint32_t)(y0 * Lxh + sl);
+
+    int vec[NV];
+    bool any = false;
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+        const int slot = vg * NV + v;
+        int qv = -1;
+        if (slot < nvec) {
+            qv = e.vec_map ? e.vec_map[slot] : slot;
+            if (qv >= 0 && e.cg && (e.cg[qv].done || e.cg[qv].frozen)) qv = -1;
+        }
+        vec[v] = __builtin_amdgcn_readfirstlane(qv);
+        any = any || vec[v] >= 0;
+    }
+    if (!any) return;  // uniform over the workgroup
+
+    // stage the tile's rows and halo rows of every vector of the group
+    const int nrs = whole ? Ly : Rt + 2;
+    const uint32_t S = (uint32_t)(nrs * Lxh);
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+        if (vec[v] < 0) continue;
+        const auto sr = buf_rsrc(in + (size_t)vec[v] * 12 * Vh32, 12u * Vh32 * (uint32_t)sizeof(cx<T>));
+        for (uint32_t k = threadIdx.x; k < S; k += blockDim.x) {
+            const int r = (int)(k / (uint32_t)Lxh);
+            const int yr = whole ? r : (y0 - 1 + r + Ly) % Ly;
+            const uint32_t off = (base + (uint32_t)(yr * Lxh) + (k - (uint32_t)(r * Lxh))) * (uint32_t)sizeof(cx<T>);
+            cx<T> w[12];
+#pragma unroll
+            for (int c = 0; c < 12; c++) w[c] = bload<cx<T>>(sr, off, (uint32_t)c * Vh32 * (uint32_t)sizeof(cx<T>));
+#pragma unroll
+            for (int c = 0; c < 12; c++) st[(uint32_t)(v * 12 + c) * S + k] = w[c];
+        }
+    }
+    __syncthreads();
+
+    const Stage<T> sg{st, S, whole ? y : yl + 1, whole ? 1 : 0};
+    cx<T> acc[NV][12];
+#pragma unroll
+    for (int v = 0; v < NV; v++)
+#pragma unroll
+        for (int c = 0; c < 12; c++) acc[v][c] = mk<T>(0, 0);
+    if (bwd)
+        split_hops<T, LT, NV, true, true>(g, links, in, vec, p, active, x, y, z, t, xh, h32, sg, acc);
+    else
+        split_hops<T, LT, NV, false, true>(g, links, in, vec, p, active, x, y, z, t, xh, h32, sg, acc);
+    __syncthreads();   // the stage is read; its LDS now takes the hand-over
+    const uint32_t xs = (uint32_t)St;
+    if (active) {
+        if (bwd)
+            split_handover<T, NV, true>(acc, st, xs, sl);
+        else
+            split_handover<T, NV, false>(acc, st, xs, sl);
+    }
+    __syncthreads();
+    const int nwave = 2 * nws;
+    if (bwd)
+        split_tail<T, NV, true>(e, vec, active, Vh32, h32, sl, wave, nwave, acc, st, xs, out, red_lds);
+    else
+        split_tail<T, NV, false>(e, vec, active, Vh32, h32, sl, wave, nwave, acc, st, xs, out, red_lds);
+    if (e.red) {
+        __syncthreads();
+        const int v = threadIdx.x;
+        if (v < NV) {
+            int qv = -1;
+#pragma unroll
+            for (int k = 0; k < NV; k++)
+                if (k == v) qv = vec[k];
+            if (qv >= 0) {
+                double sum = 0.0;
+                for (int w = 0; w < nwave; w++) sum += red_lds[v * nwave + w];
+                e.partials[(int64_t)qv * nsb + blk] = sum;
+            }
+        }
+    }
+}
+
+// LDS bytes of the staged variant for nv vectors of element size es (0 if it does not apply)
+static size_t plane_lds_bytes(const Geom& g, int nv, size_t es) {
+    if (g.Lxh > 256) return 0;
+    return (size_t)nv * 12 * (size_t)plane_stage_sites(g) * es;
+}
+constexpr size_t PLANE_LDS_MAX = 64 * 1024;
+
+static int norm_vb(int tps, int vb, int nvec) {
+    vb = vb < 1 ? 1 : (vb > nvec ? nvec : vb);
+    vb = vb > HOP_MAX_VB ? HOP_MAX_VB : vb;
+    if (tps == 5 || tps == 6) vb = 1;
+    if (tps == 7) vb = vb <= 2 ? 2 : 4;
+    if (tps == 8 || tps == 9) vb = vb <= 1 ? 1 : (vb <= 2 ? 2 : 4);
+    return vb;
+}
+
+bool hop_shape_ok(const Geom& g, Prec prec, int tps, int vb) {
+    if (tps < 1 || tps > 9) return false;
+    const size_t es = (prec == P64 || prec == P64R) ? 16 : 8;
+    if ((tps == 8 || tps == 9) && (double)g.Vh * 12.0 * (double)es >= 4294967296.0) return false;
+    if (tps == 9) {
+        const size_t b = plane_lds_bytes(g, norm_vb(9, vb, 4), es);
+        return b > 0 && b <= PLANE_LDS_MAX;
+    }
+    return true;
 }
 
 static int g_order = -1;
@@ -1103,8 +1303,10 @@ void set_hop_hoist_links(bool on) { g_hoist = on ? 1 : 0; }
 // tps 7: the multi-vector variant (two lanes per site, links loaded once for vb vectors, vb 2 or 4)
 // tps 8: the wave-split variant (forward and backward hops on separate wavefronts, vb 1, 2 or 4
 // vectors per workgroup)
-int hop_threads_per_site(int tps) { return (tps == 3 || tps == 5 || tps == 6 || tps == 7 || tps == 8) ? 2 : tps; }
+// tps 9: the LDS-staged variant (tiles of whole xy-rows, vb 1, 2 or 4); one workgroup per tile
+int hop_threads_per_site(int tps) { return (tps == 3 || tps >= 5) ? 2 : tps; }
 int hop_site_blocks(const Geom& g, int tps) {
+    if (tps == 9) return g.L[2] * g.L[3] * plane_tiles(g);
     return (int)((g.Vh * hop_threads_per_site(tps) + SCG_BLOCK - 1) / SCG_BLOCK);
 }
 
@@ -1131,13 +1333,11 @@ static void launch_t(const Geom& g, const void* links, const void* in, void* out
     e.cg = epi.cg;
     e.kappa2_dev = epi.kappa2_dev;
     const int64_t nsb = hop_site_blocks(g, tps);
-    vb = vb < 1 ? 1 : (vb > nvec ? nvec : vb);
-    vb = vb > HOP_MAX_VB ? HOP_MAX_VB : vb;
-    if (tps == 5 || tps == 6) vb = 1;
-    if (tps == 7) vb = vb <= 2 ? 2 : 4;
-    if (tps == 8) vb = vb <= 1 ? 1 : (vb <= 2 ? 2 : 4);
-    // the wave-split kernel addresses a vector and a link field with 32-bit byte offsets
-    if (tps == 8 && (double)g.Vh * 12.0 * (double)sizeof(cx<T>) >= 4294967296.0) tps = 3, vb = 1;
+    vb = norm_vb(tps, vb, nvec);
+    // the wave-split kernels address a vector with 32-bit byte offsets, the staged one needs its LDS:
+    // the handle's shapes were checked with hop_shape_ok (the reduction partials depend on the shape)
+    if ((tps == 8 || tps == 9) && (double)g.Vh * 12.0 * (double)sizeof(cx<T>) >= 4294967296.0)
+        throw std::runtime_error("stencil launch shape does not fit this lattice");
     const int64_t grid = xcd_grid(nsb * ((nvec + vb - 1) / vb));
     // site blocks per t-slice for the tiled visiting order (two lanes per site, 128 sites a block)
     const int64_t slice = g.Vh / g.L[3];
@@ -1157,7 +1357,20 @@ static void launch_t(const Geom& g, const void* links, const void* in, void* out
     else if (tps == 7)
         hipLaunchKernelGGL((hop_multi_kernel<T, LT, 4>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
                            (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e, L.cs, bps);
-    else if (tps == 8 && vb == 1)
+    else if (tps == 9) {
+        const size_t lds = plane_lds_bytes(g, vb, sizeof(cx<T>));
+        if (lds == 0 || lds > PLANE_LDS_MAX) throw std::runtime_error("stencil launch shape does not fit this lattice");
+        const int Pw = (plane_rows(g) * g.Lxh + SCG_WAVE - 1) / SCG_WAVE * SCG_WAVE;
+        if (vb == 1)
+            hipLaunchKernelGGL((hop_plane_kernel<T, LT, 1>), dim3((unsigned)grid, 1, L.nz), dim3(2 * Pw), lds, s, g, (const S*)links,
+                               (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e, L.cs, Pw);
+        else if (vb == 2)
+            hipLaunchKernelGGL((hop_plane_kernel<T, LT, 2>), dim3((unsigned)grid, 1, L.nz), dim3(2 * Pw), lds, s, g, (const S*)links,
+                               (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e, L.cs, Pw);
+        else
+            hipLaunchKernelGGL((hop_plane_kernel<T, LT, 4>), dim3((unsigned)grid, 1, L.nz), dim3(2 * Pw), lds, s, g, (const S*)links,
+                               (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e, L.cs, Pw);
+    } else if (tps == 8 && vb == 1)
         hipLaunchKernelGGL((hop_split_kernel<T, LT, 1>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
                            (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e, L.cs, bps);
     else if (tps == 8 && vb == 2)

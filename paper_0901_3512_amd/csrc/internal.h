@@ -167,6 +167,8 @@ struct HopEpi {
 void launch_hop(Prec prec, const Geom& g, const void* links, const void* in, void* out, int out_parity,
                 int nvec, const HopEpi& epi, int tps, int vb, const Launch& L);
 int hop_site_blocks(const Geom& g, int tps);
+// whether launch shape (tps, vb) of the stencil can run on this lattice at this precision
+bool hop_shape_ok(const Geom& g, Prec prec, int tps, int vb);
 bool hop_hoist_links();
 void set_hop_hoist_links(bool on);
 

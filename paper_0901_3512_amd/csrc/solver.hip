@@ -354,7 +354,7 @@ int64_t nsb_for(seedcg_s* h, bool low, int nvec) {
     const bool multi = nvec > 1;
     return hop_site_blocks(h->g, low ? (multi ? h->tps_lo_multi : h->tps_lo) : (multi ? h->tps64_multi : h->tps64));
 }
-int64_t nsb_of(seedcg_s* h, bool) { return hop_site_blocks(h->g, 4); }
+int64_t nsb_of(seedcg_s* h, bool) { return std::max(hop_site_blocks(h->g, 4), hop_site_blocks(h->g, 9)); }
 
 // host[c * bytes .. ] -> dev (configuration c's copy), for every configuration
 void to_cfg(seedcg_s* h, void* dev, const void* host, size_t bytes) {
@@ -1400,8 +1400,8 @@ void init_geometry(seedcg_s* h, const seedcg_params* p, const int32_t* dims) {
     // per workgroup; the vectors of a site block run as adjacent workgroups on one XCD
     h->tps64 = env_int("SEEDCG_TPS", 3);
     h->tps_lo = env_int("SEEDCG_TPS_LO", 3);
-    if (h->tps64 < 1 || h->tps64 > 8) h->tps64 = 3;
-    if (h->tps_lo < 1 || h->tps_lo > 8) h->tps_lo = 3;
+    if (h->tps64 < 1 || h->tps64 > 9) h->tps64 = 3;
+    if (h->tps_lo < 1 || h->tps_lo > 9) h->tps_lo = 3;
     h->vb64 = std::max(1, env_int("SEEDCG_VB", 1));
     h->vb_lo = std::max(1, env_int("SEEDCG_VB_LO", 1));
     h->tps64_multi = h->tps64;
@@ -1436,6 +1436,14 @@ void choose_link_formats(seedcg_s* h, bool special_unitary) {
     const bool rows2 = special_unitary && env_int("SEEDCG_LINK_ROWS", 2) != 9;
     h->hop64 = rows2 ? P64R : P64;
     h->hop_lo = h->lo_prec == P32 ? (rows2 ? P32R : P32) : h->lo_prec;
+    // launch shapes taken from the environment must fit this lattice (else the default one)
+    auto fit = [h](int& tps, int& vb, Prec pr) {
+        if (!hop_shape_ok(h->g, pr, tps, vb)) tps = 3, vb = 1;
+    };
+    fit(h->tps64, h->vb64, h->hop64);
+    fit(h->tps64_multi, h->vb64_multi, h->hop64);
+    fit(h->tps_lo, h->vb_lo, h->hop_lo);
+    fit(h->tps_lo_multi, h->vb_lo_multi, h->hop_lo);
 }
 
 bool env_shape_fixed() {
@@ -1463,8 +1471,10 @@ void tune_shape(seedcg_s* h, bool low, int nvec, const void* x, void* y) {
             return;
         }
     }
-    std::vector<std::pair<int, int>> cand{{8, 1}, {3, 1}, {5, 1}, {6, 1}, {4, 1}, {2, 1}, {1, 1}};
+    std::vector<std::pair<int, int>> cand{{9, 1}, {8, 1}, {3, 1}, {5, 1}, {6, 1}, {4, 1}, {2, 1}, {1, 1}};
     if (multi) {
+        cand.push_back({9, 2});                 // staged x/y neighbours, links once per pair / quad
+        cand.push_back({9, 4});
         cand.push_back({8, 2});                 // wave-split, links once per pair / quad of vectors
         cand.push_back({8, 4});
         cand.push_back({4, 2});
@@ -1481,6 +1491,7 @@ void tune_shape(seedcg_s* h, bool low, int nvec, const void* x, void* y) {
     h->timing_every = 0;
     try {
         for (const auto& c : cand) {
+            if (!hop_shape_ok(h->g, low ? h->hop_lo : h->hop64, c.first, c.second)) continue;
             tps = c.first;
             vb = c.second;
             apply_M_int(h, low, x, y, nvec, MOpts{});  // warm-up

@@ -1396,12 +1396,13 @@ void init_geometry(seedcg_s* h, const seedcg_params* p, const int32_t* dims) {
     h->N = 12 * g.Vh;
     h->lo = p->prec != SEEDCG_FP64;
     h->lo_prec = p->prec == SEEDCG_MIXED_FP32 ? P32 : (p->prec == SEEDCG_MIXED_FP32_BF16LINKS ? P32BF : P64);
-    // default stencil launch shape: 3 = two lanes per site (forward / backward hops), one vector
-    // per workgroup; the vectors of a site block run as adjacent workgroups on one XCD
-    h->tps64 = env_int("SEEDCG_TPS", 3);
-    h->tps_lo = env_int("SEEDCG_TPS_LO", 3);
-    if (h->tps64 < 1 || h->tps64 > 9) h->tps64 = 3;
-    if (h->tps_lo < 1 || h->tps_lo > 9) h->tps_lo = 3;
+    // default stencil launch shape: 8 = forward and backward hops on separate wavefronts, one vector
+    // per workgroup (the autotuner may pick another); the vectors of a site block run as adjacent
+    // workgroups on one XCD
+    h->tps64 = env_int("SEEDCG_TPS", 8);
+    h->tps_lo = env_int("SEEDCG_TPS_LO", 8);
+    if (h->tps64 < 1 || h->tps64 > 9) h->tps64 = 8;
+    if (h->tps_lo < 1 || h->tps_lo > 9) h->tps_lo = 8;
     h->vb64 = std::max(1, env_int("SEEDCG_VB", 1));
     h->vb_lo = std::max(1, env_int("SEEDCG_VB_LO", 1));
     h->tps64_multi = h->tps64;
@@ -1438,7 +1439,7 @@ void choose_link_formats(seedcg_s* h, bool special_unitary) {
     h->hop_lo = h->lo_prec == P32 ? (rows2 ? P32R : P32) : h->lo_prec;
     // launch shapes taken from the environment must fit this lattice (else the default one)
     auto fit = [h](int& tps, int& vb, Prec pr) {
-        if (!hop_shape_ok(h->g, pr, tps, vb)) tps = 3, vb = 1;
+        if (!hop_shape_ok(h->g, pr, tps, vb)) tps = 3, vb = 1;   // 3 fits every lattice
     };
     fit(h->tps64, h->vb64, h->hop64);
     fit(h->tps64_multi, h->vb64_multi, h->hop64);

@@ -4,9 +4,10 @@
   python -m paper_0901_3512_amd.profsummary bytes  <fetch-dir> <write-dir> --kernel hop_kernel
 
 `bytes` averages FETCH_SIZE and WRITE_SIZE (KiB per dispatch) over the dispatches of the named
-kernel that follow the copy probe and scales each by what the same counter reads for a plain
-device copy of exactly 1 GiB (the benchmark's --copy-probe, made just before its timed region: a
-1 GiB copy reads and writes 1,048,576 KiB), giving HBM bytes per launch of the timed region.
+kernel between the copy probe and the next 1 GiB copy, and scales each by what the same counter
+reads for a plain device copy of exactly 1 GiB (the benchmark's --copy-probe, made just before its
+timed region: a 1 GiB copy reads and writes 1,048,576 KiB), giving HBM bytes per launch of the
+timed region.
 """
 import argparse
 import csv
@@ -43,24 +44,41 @@ def _counter(d, name):
     return rows
 
 
-def _copy_reference(rows):
-    """Counter value of the 1 GiB copy probe and the last dispatch id of the probe: the largest copy
-    dispatches (the probe is by far the largest copy of a benchmark run)."""
-    cp = [(float(r["Counter_Value"]), int(r["Dispatch_Id"])) for r in rows if "copyBuffer" in r["Kernel_Name"]]
-    top = max(v for v, _ in cp)
-    big = [(v, d) for v, d in cp if v >= 0.9 * top]
-    return sum(v for v, _ in big) / len(big), max(d for _, d in big)
+def _copy_window(rows):
+    """The 1 GiB copy probe in a counter trace: (mean counter value of its copies, dispatch id of its
+    last copy, dispatch id of the next 1 GiB copy or None).  Big copies are those within 10% of the
+    largest; the probe is the first run of them with no other dispatch in between (a later run, such
+    as the benchmark's copy-rate measurement after its timed region, ends the window)."""
+    cp = [(int(r["Dispatch_Id"]), float(r["Counter_Value"])) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+    top = max(v for _, v in cp)
+    big = sorted((d, v) for d, v in cp if v >= 0.9 * top)
+    ids = sorted({int(r["Dispatch_Id"]) for r in rows})
+    probe = [big[0]]
+    for d, v in big[1:]:
+        if any(probe[-1][0] < x < d for x in ids):
+            break
+        probe.append((d, v))
+    last = probe[-1][0]
+    after = [d for d, _ in big if d > last]
+    return sum(v for _, v in probe) / len(probe), last, (after[0] if after else None)
 
 
 def bytes_per_launch(fetch_dir, write_dir, kernel):
     f = _counter(fetch_dir, "FETCH_SIZE")
     w = _counter(write_dir, "WRITE_SIZE")
-    fref, fd = _copy_reference(f)
-    wref, wd = _copy_reference(w)
+    fref, f0, f1 = _copy_window(f)
+    wref, w0, w1 = _copy_window(w)
     f_scale = GIB_KIB / fref
     w_scale = GIB_KIB / wref
-    fk = [float(r["Counter_Value"]) for r in f if kernel in r["Kernel_Name"] and int(r["Dispatch_Id"]) > fd]
-    wk = [float(r["Counter_Value"]) for r in w if kernel in r["Kernel_Name"] and int(r["Dispatch_Id"]) > wd]
+
+    def inside(r, a, b):
+        d = int(r["Dispatch_Id"])
+        return d > a and (b is None or d < b)
+
+    fk = [float(r["Counter_Value"]) for r in f if kernel in r["Kernel_Name"] and inside(r, f0, f1)]
+    wk = [float(r["Counter_Value"]) for r in w if kernel in r["Kernel_Name"] and inside(r, w0, w1)]
+    if not fk or not wk:
+        raise SystemExit(f"no {kernel} dispatch between the copy probe and the next 1 GiB copy")
     fetch = sum(fk) / len(fk) * f_scale * 1024.0
     write = sum(wk) / len(wk) * w_scale * 1024.0
     return dict(fetch_scale=f_scale, write_scale=w_scale, dispatches=len(fk), fetch_bytes=fetch,

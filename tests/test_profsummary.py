@@ -1,0 +1,39 @@
+"""Host logic of the rocprofv3 summaries: the copy-probe window of the HBM byte counters."""
+import csv
+import os
+
+from paper_0901_3512_amd.profsummary import _copy_window, bytes_per_launch
+
+
+def _row(d, k, v, name):
+    return {"Dispatch_Id": str(d), "Kernel_Name": k, "Counter_Value": str(v), "Counter_Name": name}
+
+
+def test_probe_is_the_first_run_of_big_copies():
+    rows = [_row(1, "copyBuffer", 10, "X"), _row(2, "hop_a", 5, "X"), _row(3, "copyBuffer", 1000, "X"),
+            _row(4, "copyBuffer", 990, "X"), _row(5, "copyBuffer", 1010, "X"), _row(6, "hop_a", 7, "X"),
+            _row(7, "hop_a", 9, "X"), _row(8, "copyBuffer", 1000, "X"), _row(9, "hop_a", 3, "X")]
+    ref, last, nxt = _copy_window(rows)
+    assert ref == 1000.0 and last == 5 and nxt == 8
+
+
+def _write(d, name, rows):
+    os.makedirs(d, exist_ok=True)
+    with open(os.path.join(d, "p_counter_collection.csv"), "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for r in rows:
+            w.writerow({**r, "Counter_Name": name})
+
+
+def test_bytes_per_launch_counts_only_the_timed_window(tmp_path):
+    # the probe reads 524,288 KiB for a 1 GiB copy (scale 2) and writes 1,048,576 KiB (scale 1)
+    fetch = [_row(1, "hop_a", 999, ""), _row(2, "copyBuffer", 524288, ""), _row(3, "hop_a", 100, ""),
+             _row(4, "hop_a", 300, ""), _row(5, "copyBuffer", 524288, ""), _row(6, "hop_a", 999, "")]
+    write = [_row(1, "hop_a", 999, ""), _row(2, "copyBuffer", 1048576, ""), _row(3, "hop_a", 50, ""),
+             _row(4, "hop_a", 50, ""), _row(5, "copyBuffer", 1048576, ""), _row(6, "hop_a", 999, "")]
+    _write(str(tmp_path / "f"), "FETCH_SIZE", fetch)
+    _write(str(tmp_path / "w"), "WRITE_SIZE", write)
+    r = bytes_per_launch(str(tmp_path / "f"), str(tmp_path / "w"), "hop_")
+    assert r["dispatches"] == 2
+    assert r["fetch_bytes"] == 200 * 2.0 * 1024 and r["write_bytes"] == 50 * 1.0 * 1024

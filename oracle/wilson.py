@@ -110,6 +110,13 @@ def matvec_M(op):
     return f
 
 
+def matvec_H(op):
+    """H = gamma5 A (Hermitian, indefinite) as a function on flattened vectors (one or a batch)."""
+    def f(x):
+        return flat(gamma5(op.apply_A(unflat(x, op.Vh))))
+    return f
+
+
 def dense(fn, n):
     """Dense matrix of a linear map on C^n, built column by column from unit vectors."""
     cols = np.empty((n, n), dtype=np.complex128)

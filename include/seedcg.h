@@ -134,6 +134,28 @@ seedcg_status seedcg_solve_rest(seedcg_t h, const double* B, double* X, int32_t 
    layouts as seedcg_solve_seed; nrhs <= 25. */
 seedcg_status seedcg_solve_repeated(seedcg_t h, const double* B, double* X, int32_t nrhs, seedcg_report* r);
 
+/* The indefinite formulation (section 2: for an indefinite matrix a QR or LQ factorisation of the
+   Lanczos matrix replaces the LU of Eq. 2).  Solves A x^j = phi^j, A the even-odd Wilson matrix
+   (section 3), through the Hermitian indefinite H = gamma5 A (H x = gamma5 phi, the same x as
+   M x = A^dag phi without the squared condition number):
+     - system 1 runs Lanczos on H with the MINRES form of the QR, past convergence and with periodic
+       reorthogonalisation as in Algorithm 1 (m = ceil(past_factor * i_conv), reorth_k, m_max as
+       for solve_seed; m_max = 0 takes a basis of up to 4096 vectors that fits in 75% of the free
+       HBM);
+     - every other system is seeded from the same Lanczos vectors by the minimal-residual projection
+       of its residual onto their span;
+     - plain MINRES on H finishes every system from its guess, until the FP64 true residual
+       ||phi - A x|| / ||phi|| <= tol.
+   Phi: device, nrhs canonical vectors [Vh][4][3] complex FP64 (layout as seedcg_solve_seed's B);
+   X: device, the initial guesses on entry (zeros for x_0 = 0), the solutions on return.
+   r->iters[j]: MINRES iterations (plus m for system 1); r->matvecs[j]: applications of A;
+   r->true_relres[j]: ||phi - A x|| / ||phi||; m_used, i_conv, seed_status, reorth_passes, t_seed_s
+   (the seeded Lanczos run) and t_rest_s (MINRES) as for solve_seed.  FP64 handles of one
+   configuration only (SEEDCG_ERR_STATE otherwise); nrhs <= 25.  Scalar recurrences run on the
+   host, with two synchronisations of the stream per iteration.  Returns SEEDCG_ERR_NOCONV when a
+   system reached max_iter MINRES iterations first (X then holds its last iterate). */
+seedcg_status seedcg_solve_indefinite(seedcg_t h, const double* Phi, double* X, int32_t nrhs, seedcg_report* r);
+
 /* Copies the Lanczos coefficients of the last solve_seed to HOST arrays: alpha_1..alpha_m into
    alpha[0..m-1] and beta_0..beta_m into beta[0..m]; cap is the length of alpha (beta needs cap+1).
    *m receives m.  Eq. (2) defines T from these. */

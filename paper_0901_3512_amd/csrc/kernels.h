@@ -107,4 +107,18 @@ void k_combine(bool v32, const void* V, int m, const double* S, int nout, void* 
 void defl_mu(const double* Ginv, const double* P, int nev, int ncol, const int32_t* map, int w, const CgVec* cg, double sign,
              double* E, const Launch& L);
 
+// generic FP64 vector combinations of the indefinite solver (minres.hip): out = [out +] sum_t a_t in_t
+// for each of nout outputs (nt <= 4 terms each, complex coefficients a_t = are + i aim)
+struct ZLC {
+    const void* in[4];
+    double are[4], aim[4];
+    int nt, acc;
+    void* out;
+};
+void zlincomb(const ZLC* o, int nout, int64_t n, hipStream_t s);
+// out[2p], out[2p+1] = Re, Im of a_p^dag b_p for np pairs of n-complex vectors; part holds
+// 2 * min(np, 32) * zdots_blocks(n) doubles
+void zdots(const void* const* a, const void* const* b, int np, int64_t n, double* part, double* out, hipStream_t s);
+int64_t zdots_blocks(int64_t n);
+
 }  // namespace scg

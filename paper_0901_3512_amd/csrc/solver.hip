@@ -1586,6 +1586,480 @@ void apply_layout(seedcg_s* h, int nrhs, int m_cap) {
     h->tabs.ensure(2 * sizeof(void*) * h->ncfg);
 }
 
+// ---------------------------------------------------------------------------------------------
+// The indefinite system H x = gamma5 phi, H = gamma5 A (section 2: a QR factorisation of the
+// Lanczos matrix replaces the LU for indefinite matrices).  RHS 1 runs Lanczos on H with the
+// MINRES form of that QR (Givens rotations of the (i+1) x i Lanczos matrix), past convergence and
+// with periodic reorthogonalisation as in Algorithm 1; every other RHS is seeded from the same
+// Lanczos vectors by the minimal-residual projection (the rotations applied to V^dag r_0^j); plain
+// MINRES then finishes every system.  FP64 throughout; the scalar recurrences run on the host.
+// ---------------------------------------------------------------------------------------------
+
+// out = H x = gamma5 (x - kappa^2 H_eo H_oe x) for the vectors listed in vmap (or the first nvec);
+// with d, the partials of Re d^dag out per vector
+// (nslots: vectors in x and out, the largest index vmap may list + 1)
+void apply_H_int(seedcg_s* h, const void* x, void* out, int nvec, int nslots, const int32_t* vmap, const void* d, double* partials) {
+    ensure_work(h, std::max(nvec, nslots));
+    const bool multi = nvec > 1;
+    const int tps = multi ? h->tps64_multi : h->tps64;
+    const int vb = multi ? h->vb64_multi : h->vb64;
+    HopEpi e{};
+    e.sy = 1.0;
+    e.vec_map = vmap;
+    const void* L = hop_links(h, false);
+    hop(h, h->hop64, L, x, h->t1_64.p, 1, nvec, e, tps, vb);
+    HopEpi e2 = e;
+    e2.combine = 1;
+    e2.apply_g5 = 1;
+    e2.kappa2 = h->p.kappa * h->p.kappa;
+    e2.x = x;
+    e2.red = d ? 1 : 0;
+    e2.d = d;
+    e2.partials = partials;
+    hop(h, h->hop64, L, h->t1_64.p, out, 0, nvec, e2, tps, vb);
+}
+
+struct Givens {
+    double c = 1.0, s = 0.0;
+};
+
+// One column of the QR of the Lanczos matrix: beta_{i-1}, alpha_i, beta_i with the two previous
+// rotations g2 = G_{i-2}, g1 = G_{i-1}; returns G_i and rho_i, delta_i, eps_i
+struct QrCol {
+    Givens g;
+    double rho, delta, eps;
+};
+QrCol qr_column(double bprev, double a, double b, const Givens& g2, const Givens& g1) {
+    QrCol q;
+    q.eps = g2.s * bprev;
+    const double dbar = g2.c * bprev;
+    q.delta = g1.c * dbar + g1.s * a;
+    const double gbar = -g1.s * dbar + g1.c * a;
+    q.rho = std::hypot(gbar, b);
+    if (q.rho > 0.0) {
+        q.g.c = gbar / q.rho;
+        q.g.s = b / q.rho;
+    }
+    return q;
+}
+
+struct IndefWork {
+    DBuf V, C, X, R0, Hb, F, W, Va, Vb, Wa, Wb, Wc, part, hpart, scal, P, E, pp, vmap;
+};
+
+// returns false when some system reached max_iter before tol (X then holds its last iterate)
+bool solve_indefinite_impl(seedcg_s* h, const double* Phi, double* Xout, int nrhs, seedcg_report* rep) {
+    using cxd = std::complex<double>;
+    if (h->lo) throw StateError{"solve_indefinite: FP64 handles only"};
+    if (h->ncfg != 1) throw StateError{"solve_indefinite: one configuration per handle"};
+    if (nrhs < 1 || nrhs > 25) throw ArgError{"solve_indefinite: 1 <= nrhs <= 25"};
+    const double t0 = now_s();
+    const int64_t N = h->N;
+    const int64_t vbytes = h->vec_bytes(false);
+    const hipStream_t s = h->s;
+    const Launch L = h->L();
+    const double tol = h->p.tol;
+    const int k = h->p.reorth_k;
+    const int max_iter = h->p.max_iter;
+    int m_cap = h->p.m_max;
+    if (m_cap <= 0) {
+        size_t freeb = 0, total = 0;
+        HIPCHK(hipMemGetInfo(&freeb, &total));
+        const double room = 0.75 * ((double)freeb - 4.0 * (1 << 30) - 10.0 * nrhs * vbytes);
+        m_cap = (int)std::min<double>(4096.0, std::max(2.0, room / (double)vbytes));
+    }
+    IndefWork wk;
+    wk.V.ensure((size_t)(m_cap + 1) * vbytes);
+    for (DBuf* b : {&wk.C, &wk.X, &wk.R0, &wk.Hb, &wk.Va, &wk.Vb, &wk.Wa, &wk.Wb, &wk.Wc}) b->ensure((size_t)nrhs * vbytes);
+    wk.F.ensure(vbytes);
+    wk.W.ensure(3 * vbytes);
+    const int64_t nb = zdots_blocks(N);
+    wk.part.ensure((size_t)2 * 32 * nb * sizeof(double));
+    const int64_t nsb = nsb_of(h, false);
+    wk.hpart.ensure((size_t)nrhs * nsb * sizeof(double));
+    wk.scal.ensure(256 * sizeof(double));
+    wk.vmap.ensure(32 * sizeof(int32_t));
+    auto vec = [&](const DBuf& b, int j) { return (void*)((char*)b.p + (int64_t)j * vbytes); };
+    auto vcol = [&](int i) { return (void*)((char*)wk.V.p + (int64_t)i * vbytes); };   // v_{i+1}, 0-based
+    double* scal = wk.scal.as<double>();
+    auto sync = [&]() { HIPCHK(hipStreamSynchronize(s)); };
+    auto dots = [&](const std::vector<const void*>& a, const std::vector<const void*>& b) {
+        const int np = (int)a.size();
+        std::vector<cxd> out(np);
+        std::vector<double> raw(2 * np);
+        for (int q = 0; q < np; q += 128) {
+            const int cnt = std::min(128, np - q);
+            zdots(a.data() + q, b.data() + q, cnt, N, wk.part.as<double>(), scal, s);
+            HIPCHK(hipMemcpyAsync(raw.data() + 2 * q, scal, 2 * cnt * sizeof(double), hipMemcpyDeviceToHost, s));
+            sync();
+        }
+        for (int q = 0; q < np; q++) out[q] = cxd(raw[2 * q], raw[2 * q + 1]);
+        return out;
+    };
+    auto norm = [&](const void* x) { return std::sqrt(std::max(0.0, dots({x}, {x})[0].real())); };
+    auto lin = [&](void* out, bool acc, std::initializer_list<std::pair<const void*, cxd>> terms) {
+        ZLC z{};
+        int t = 0;
+        for (const auto& tm : terms) {
+            z.in[t] = tm.first;
+            z.are[t] = tm.second.real();
+            z.aim[t] = tm.second.imag();
+            t++;
+        }
+        z.nt = t;
+        z.acc = acc ? 1 : 0;
+        z.out = out;
+        return z;
+    };
+    auto run = [&](const std::vector<ZLC>& zs) {
+        if (!zs.empty()) zlincomb(zs.data(), (int)zs.size(), N, s);
+    };
+    // H on the listed vectors of x (contiguous [nrhs][N]) into out; with red, returns Re x_j^dag H x_j
+    int n_apply = 0;
+    auto applyH = [&](const DBuf& x, const DBuf& out, const std::vector<int>& js, bool red) {
+        std::vector<int32_t> m(js.begin(), js.end());
+        HIPCHK(hipMemcpyAsync(wk.vmap.p, m.data(), m.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        apply_H_int(h, x.p, out.p, (int)js.size(), nrhs, wk.vmap.as<int32_t>(), red ? x.p : nullptr,
+                    red ? wk.hpart.as<double>() : nullptr);
+        n_apply++;
+        std::vector<double> a;
+        if (red) {
+            const int64_t ns = nsb_for(h, false, (int)js.size());
+            sum_partials(wk.hpart.as<double>(), ns, nrhs, scal, false, L);
+            std::vector<double> all(nrhs);
+            HIPCHK(hipMemcpyAsync(all.data(), scal, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+            sync();
+            for (int j : js) a.push_back(all[j]);
+        }
+        return a;
+    };
+    // x -= V_{0..nv-1} V^dag x, one CGS pass (coefficients on the matrix cores)
+    auto cgs_pass = [&](int nv, void* x) {
+        if (nv < 1) return;
+        ProjArgs a{};
+        a.V = wk.V.p;
+        a.ldv = N;
+        a.nv = nv;
+        a.R[0] = x;
+        a.nr = 1;
+        a.n = N;
+        a.kchunk = reorth_kchunk(N, nv);
+        const int64_t nch = proj_chunks(N, a.kchunk);
+        a.part_stride = 2 * (int64_t)nv;
+        wk.pp.ensure((size_t)nch * a.part_stride * sizeof(double));
+        a.part = wk.pp.as<double>();
+        wk.P.ensure((size_t)2 * nv * sizeof(double));
+        wk.E.ensure((size_t)2 * nv * sizeof(double));
+        project(false, a, (nv + 31) / 32, wk.P.as<double>(), L, true);
+        std::vector<double> c(2 * nv);
+        HIPCHK(hipMemcpyAsync(c.data(), wk.P.p, c.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        sync();
+        for (double& v : c) v = -v;
+        HIPCHK(hipMemcpyAsync(wk.E.p, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        for (int r0 = 0; r0 < nv; r0 += 32)
+            seed_update(false, false, vcol(r0), std::min(32, nv - r0), wk.E.as<double>() + 2 * r0, x, 1, N, nullptr, L);
+    };
+    int passes = 0;
+    auto orthogonalise = [&](int nv, void* x) {   // CGS with one DGKS repeat
+        const double n0 = norm(x);
+        cgs_pass(nv, x);
+        passes++;
+        if (norm(x) < n0 / std::sqrt(2.0)) {
+            cgs_pass(nv, x);
+            passes++;
+        }
+    };
+
+    // c^j = gamma5 phi^j, x^j from X, r_0^j = c^j - H x^j
+    pack_vec(false, Phi, wk.R0.p, h->g.Vh, nrhs, L);
+    gamma5_copy(false, wk.R0.p, wk.C.p, h->g.Vh, nrhs, L);
+    pack_vec(false, Xout, wk.X.p, h->g.Vh, nrhs, L);
+    std::vector<int> all(nrhs);
+    for (int j = 0; j < nrhs; j++) all[j] = j;
+    applyH(wk.X, wk.Hb, all, false);
+    {
+        std::vector<ZLC> zs;
+        for (int j = 0; j < nrhs; j++) zs.push_back(lin(vec(wk.R0, j), false, {{vec(wk.C, j), 1.0}, {vec(wk.Hb, j), -1.0}}));
+        run(zs);
+    }
+    std::vector<double> cn(nrhs);
+    {
+        std::vector<const void*> a;
+        for (int j = 0; j < nrhs; j++) a.push_back(vec(wk.C, j));
+        const auto d = dots(a, a);
+        for (int j = 0; j < nrhs; j++) cn[j] = std::sqrt(d[j].real());
+    }
+    std::vector<int32_t> iters(nrhs, 0), matvecs(nrhs, 1);
+
+    // ---- seeded Lanczos with the QR of Tbar -------------------------------------------------
+    const double beta0 = norm(vec(wk.R0, 0));
+    int m_used = 0, i_conv = 0, status = 0;
+    if (beta0 > 0.0 && cn[0] > 0.0) {
+        run({lin(vcol(0), false, {{vec(wk.R0, 0), 1.0 / beta0}})});
+        std::vector<cxd> u(nrhs);
+        u[0] = beta0;
+        if (nrhs > 1) {
+            std::vector<const void*> a(nrhs - 1, vcol(0)), b;
+            for (int j = 1; j < nrhs; j++) b.push_back(vec(wk.R0, j));
+            const auto d = dots(a, b);
+            for (int j = 1; j < nrhs; j++) u[j] = d[j - 1];
+        }
+        std::vector<double> alpha, beta{beta0};
+        Givens g1, g2;
+        int m_stop = m_cap;
+        const void* wm1 = nullptr;   // w_{i-1}
+        const void* wm2 = nullptr;   // w_{i-2}
+        for (int i = 1;; i++) {
+            void* v = vcol(i - 1);
+            // f = H v_i - beta_{i-1} v_{i-1} - alpha_i v_i, alpha_i = v_i^dag H v_i (fused in the stencil)
+            {
+                apply_H_int(h, v, wk.F.p, 1, 1, nullptr, v, wk.hpart.as<double>());
+                sum_partials(wk.hpart.as<double>(), nsb_for(h, false, 1), 1, scal, false, L);
+                double a = 0.0;
+                HIPCHK(hipMemcpyAsync(&a, scal, sizeof(double), hipMemcpyDeviceToHost, s));
+                sync();
+                alpha.push_back(a);
+            }
+            const double a = alpha.back();
+            if (i > 1)
+                run({lin(wk.F.p, true, {{v, -a}, {vcol(i - 2), -beta[i - 1]}})});
+            else
+                run({lin(wk.F.p, true, {{v, -a}})});
+            if (k > 0 && i % k == 0) {   // step 8
+                orthogonalise(i - 1, v);
+                const double nv = norm(v);
+                run({lin(v, false, {{v, 1.0 / nv}})});
+                orthogonalise(i, wk.F.p);
+            }
+            // beta_i = ||f|| and f^dag r_0^j in one pass
+            std::vector<const void*> da{wk.F.p}, db{wk.F.p};
+            for (int j = 1; j < nrhs; j++) {
+                da.push_back(wk.F.p);
+                db.push_back(vec(wk.R0, j));
+            }
+            const auto d = dots(da, db);
+            const double bi = std::sqrt(std::max(0.0, d[0].real()));
+            beta.push_back(bi);
+            const QrCol q = qr_column(i > 1 ? beta[i - 1] : 0.0, a, bi, g2, g1);
+            if (!(q.rho > 0.0)) {
+                status = 1;
+                break;
+            }
+            // w_i into the ring slot of w_{i-3}; x^j += tau^j_i w_i
+            void* w = (char*)wk.W.p + (int64_t)(i % 3) * vbytes;
+            std::vector<cxd> tau(nrhs);
+            for (int j = 0; j < nrhs; j++) {
+                const cxd eta = (j == 0 || bi == 0.0) ? cxd(0.0) : d[j] / bi;   // v_{i+1}^dag r_0^j
+                tau[j] = q.g.c * u[j] + q.g.s * eta;
+                u[j] = -q.g.s * u[j] + q.g.c * eta;
+            }
+            std::vector<ZLC> zs;
+            if (bi > 0.0) zs.push_back(lin(vcol(i), false, {{wk.F.p, 1.0 / bi}}));
+            {
+                ZLC z = lin(w, false, {{v, 1.0 / q.rho}});
+                if (wm1) {
+                    z.in[z.nt] = wm1;
+                    z.are[z.nt] = -q.delta / q.rho;
+                    z.aim[z.nt] = 0.0;
+                    z.nt++;
+                }
+                if (wm2) {
+                    z.in[z.nt] = wm2;
+                    z.are[z.nt] = -q.eps / q.rho;
+                    z.aim[z.nt] = 0.0;
+                    z.nt++;
+                }
+                zs.push_back(z);
+            }
+            for (int j = 0; j < nrhs; j++) {
+                ZLC z = lin(vec(wk.X, j), true, {{v, tau[j] / q.rho}});
+                if (wm1) {
+                    const cxd c = -tau[j] * q.delta / q.rho;
+                    z.in[z.nt] = wm1;
+                    z.are[z.nt] = c.real();
+                    z.aim[z.nt] = c.imag();
+                    z.nt++;
+                }
+                if (wm2) {
+                    const cxd c = -tau[j] * q.eps / q.rho;
+                    z.in[z.nt] = wm2;
+                    z.are[z.nt] = c.real();
+                    z.aim[z.nt] = c.imag();
+                    z.nt++;
+                }
+                zs.push_back(z);
+            }
+            run(zs);
+            m_used = i;
+            const double e = std::abs(u[0]);
+            if (i_conv == 0 && e <= tol * cn[0]) {
+                i_conv = i;
+                m_stop = std::min((int)std::ceil(h->p.past_factor * i_conv), m_cap);
+            }
+            double amax = 0.0;
+            for (double x : alpha) amax = std::max(amax, std::abs(x));
+            if (bi <= 1e-14 * amax) {
+                status = 1;
+                break;
+            }
+            if (i >= m_stop) {
+                if (i_conv == 0) status = 3;
+                break;
+            }
+            wm2 = wm1;
+            wm1 = w;
+            g2 = g1;
+            g1 = q.g;
+        }
+        iters[0] = m_used;
+        matvecs[0] += m_used;
+    }
+    const double t1 = now_s();
+
+    // ---- plain MINRES on every system from its guess, in lockstep ------------------------------
+    // v_cur / v_prev alternate between Va and Vb, the direction vectors rotate through Wa, Wb, Wc
+    struct St {
+        bool active = false, restart = true;
+        int it = 0;
+        double bprev = 0.0;
+        cxd u = 0.0;
+        Givens g1, g2;
+        bool have_w1 = false, have_w2 = false;
+    };
+    std::vector<St> st(nrhs);
+    std::vector<double> res(nrhs, 0.0);
+    DBuf* vcur = &wk.Va;
+    DBuf* vprev = &wk.Vb;
+    DBuf* wbuf[3] = {&wk.Wa, &wk.Wb, &wk.Wc};
+    int wnew = 0;   // the array that takes w_i; (wnew + 2) % 3 holds w_{i-1}, (wnew + 1) % 3 w_{i-2}
+    // true residuals of the listed systems into R0 (as r = c - H x) and their norms
+    auto residuals = [&](const std::vector<int>& js) {
+        applyH(wk.X, wk.Hb, js, false);
+        std::vector<ZLC> zs;
+        std::vector<const void*> a;
+        for (int j : js) {
+            zs.push_back(lin(vec(wk.R0, j), false, {{vec(wk.C, j), 1.0}, {vec(wk.Hb, j), -1.0}}));
+            a.push_back(vec(wk.R0, j));
+        }
+        run(zs);
+        const auto d = dots(a, a);
+        std::vector<double> r;
+        for (size_t q = 0; q < js.size(); q++) r.push_back(std::sqrt(std::max(0.0, d[q].real())));
+        return r;
+    };
+    std::vector<int> check = all;
+    bool noconv = false;
+    for (;;) {
+        // confirm or restart the systems whose estimate met tol (all of them at the start)
+        if (!check.empty()) {
+            const auto r = residuals(check);
+            std::vector<ZLC> zs;
+            for (size_t q = 0; q < check.size(); q++) {
+                const int j = check[q];
+                matvecs[j]++;
+                const double rel = cn[j] > 0.0 ? r[q] / cn[j] : 0.0;
+                res[j] = rel;
+                if (rel <= tol || cn[j] == 0.0) {
+                    st[j].active = false;
+                    continue;
+                }
+                if (st[j].it >= max_iter) {
+                    st[j].active = false;
+                    noconv = true;
+                    continue;
+                }
+                st[j] = St{};
+                st[j].active = true;
+                st[j].u = r[q];
+                zs.push_back(lin(vec(*vcur, j), false, {{vec(wk.R0, j), 1.0 / r[q]}}));
+                st[j].it = iters[j] - (j == 0 ? m_used : 0);
+            }
+            run(zs);
+            check.clear();
+        }
+        std::vector<int> act;
+        for (int j = 0; j < nrhs; j++)
+            if (st[j].active) act.push_back(j);
+        if (act.empty()) break;
+        // f = H v - alpha v - bprev v_prev (in Hb), alpha fused in the stencil
+        const auto al = applyH(*vcur, wk.Hb, act, true);
+        {
+            std::vector<ZLC> zs;
+            for (size_t q = 0; q < act.size(); q++) {
+                const int j = act[q];
+                if (st[j].bprev > 0.0)
+                    zs.push_back(lin(vec(wk.Hb, j), true, {{vec(*vcur, j), -al[q]}, {vec(*vprev, j), -st[j].bprev}}));
+                else
+                    zs.push_back(lin(vec(wk.Hb, j), true, {{vec(*vcur, j), -al[q]}}));
+            }
+            run(zs);
+        }
+        std::vector<const void*> fa;
+        for (int j : act) fa.push_back(vec(wk.Hb, j));
+        const auto ff = dots(fa, fa);
+        std::vector<ZLC> zv, zx;
+        std::vector<cxd> tauv(act.size());
+        std::vector<QrCol> qs(act.size());
+        for (size_t q = 0; q < act.size(); q++) {
+            const int j = act[q];
+            St& S = st[j];
+            const double bi = std::sqrt(std::max(0.0, ff[q].real()));
+            const QrCol c = qr_column(S.bprev, al[q], bi, S.g2, S.g1);
+            qs[q] = c;
+            const cxd tau = c.g.c * S.u;
+            S.u = -c.g.s * S.u;
+            tauv[q] = tau;
+            if (bi > 0.0) zv.push_back(lin(vec(*vprev, j), false, {{vec(wk.Hb, j), 1.0 / bi}}));
+            ZLC z = lin(vec(*wbuf[wnew], j), false, {{vec(*vcur, j), 1.0 / c.rho}});
+            if (S.have_w1) {
+                z.in[z.nt] = vec(*wbuf[(wnew + 2) % 3], j);
+                z.are[z.nt] = -c.delta / c.rho;
+                z.aim[z.nt] = 0.0;
+                z.nt++;
+            }
+            if (S.have_w2) {
+                z.in[z.nt] = vec(*wbuf[(wnew + 1) % 3], j);
+                z.are[z.nt] = -c.eps / c.rho;
+                z.aim[z.nt] = 0.0;
+                z.nt++;
+            }
+            zv.push_back(z);
+            zx.push_back(lin(vec(wk.X, j), true, {{vec(*wbuf[wnew], j), tau}}));
+            S.bprev = bi;
+            S.g2 = S.g1;
+            S.g1 = c.g;
+            S.have_w2 = S.have_w1;
+            S.have_w1 = true;
+            S.it++;
+            iters[j]++;
+            matvecs[j]++;
+            if (std::abs(S.u) <= tol * cn[j] || bi == 0.0 || S.it >= max_iter) check.push_back(j);
+        }
+        run(zv);   // v_next into the v_prev array, w_i into wbuf[wnew]
+        run(zx);   // x += tau w_i
+        std::swap(vcur, vprev);
+        wnew = (wnew + 1) % 3;
+        for (int j : check) st[j].active = false;
+    }
+    unpack_vec(false, wk.X.p, Xout, h->g.Vh, nrhs, L);
+    sync();
+    if (rep) {
+        for (int j = 0; j < nrhs; j++) {
+            if (rep->iters) rep->iters[j] = iters[j];
+            if (rep->matvecs) rep->matvecs[j] = matvecs[j];
+            if (rep->true_relres) rep->true_relres[j] = res[j];
+        }
+        rep->m_used = m_used;
+        rep->i_conv = i_conv;
+        rep->seed_status = status;
+        rep->reorth_passes = passes;
+        rep->t_seed_s = t1 - t0;
+        rep->t_rest_s = now_s() - t1;
+    }
+    (void)n_apply;
+    return !noconv;
+}
+
 seedcg_status fail(seedcg_s* h, seedcg_status code, const std::string& msg) {
     if (h)
         h->err = msg;
@@ -2062,6 +2536,18 @@ seedcg_status seedcg_solve_repeated(seedcg_t h, const double* B, double* X, int3
         }
         if (st == SEEDCG_ERR_NOCONV) h->err = "solve_repeated: max_iter reached before tol";
         return st;
+    });
+}
+
+seedcg_status seedcg_solve_indefinite(seedcg_t h, const double* Phi, double* X, int32_t nrhs, seedcg_report* r) {
+    if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "solve_indefinite: null handle");
+    return guarded(h, [&]() -> seedcg_status {
+        if (!Phi || !X) throw ArgError{"solve_indefinite: null pointer"};
+        if (!solve_indefinite_impl(h, Phi, X, nrhs, r)) {
+            h->err = "solve_indefinite: max_iter reached before tol";
+            return SEEDCG_ERR_NOCONV;
+        }
+        return SEEDCG_OK;
     });
 }
 

@@ -63,6 +63,7 @@ def load_library():
         "seedcg_solve_seed": (i32, [H, P, P, i32, ctypes.POINTER(Report)]),
         "seedcg_solve_rest": (i32, [H, P, P, i32, ctypes.POINTER(Report)]),
         "seedcg_solve_repeated": (i32, [H, P, P, i32, ctypes.POINTER(Report)]),
+        "seedcg_solve_indefinite": (i32, [H, P, P, i32, ctypes.POINTER(Report)]),
         "seedcg_get_tridiag": (i32, [H, ctypes.POINTER(dbl), ctypes.POINTER(dbl), i32, ctypes.POINTER(i32)]),
         "seedcg_get_basis_vector": (i32, [H, i32, P]),
         "seedcg_get_ritz": (i32, [H, ctypes.POINTER(dbl), i32, ctypes.POINTER(i32)]),
@@ -99,7 +100,7 @@ def load_library():
 def exported_symbols():
     """Names of the C ABI entry points this binding expects."""
     return ["seedcg_default_params", "seedcg_create", "seedcg_apply_M", "seedcg_apply_M_inner", "seedcg_apply_A", "seedcg_solve_seed",
-            "seedcg_solve_rest", "seedcg_solve_repeated", "seedcg_get_tridiag", "seedcg_get_basis_vector", "seedcg_get_ritz", "seedcg_project",
+            "seedcg_solve_rest", "seedcg_solve_repeated", "seedcg_solve_indefinite", "seedcg_get_tridiag", "seedcg_get_basis_vector", "seedcg_get_ritz", "seedcg_project",
             "seedcg_update", "seedcg_train_precond", "seedcg_use_precond", "seedcg_set_precond_weights",
             "seedcg_get_precond_weights", "seedcg_apply_P", "seedcg_precond_loss_grad", "seedcg_set_timing",
             "seedcg_get_timing", "seedcg_release_basis", "seedcg_destroy", "seedcg_last_error", "seedcg_create_batch",
@@ -241,6 +242,21 @@ class SeedCG:
         r, it, mv, rr = self._report(n)
         rc = self._lib.seedcg_solve_repeated(self._h, B.data_ptr(), X.data_ptr(), n, ctypes.byref(r))
         rep = dict(iters=list(it), matvecs=list(mv), true_relres=list(rr), m=r.m_used, i_conv=r.i_conv,
+                   status=STATUS.get(rc, rc))
+        if rc != 0 and (rc != -5 or raise_on_noconv):
+            self._rc(rc)
+        return X, rep
+
+    def solve_indefinite(self, Phi, X=None, raise_on_noconv=True):
+        """A x = phi through H = gamma5 A: seeded Lanczos with the QR (MINRES) factorisation, then
+        MINRES; Phi holds the right-hand sides phi (not A^dag phi).  Returns (X, report)."""
+        Phi = _check_vec(Phi, self.Vh, "Phi")
+        X = torch.zeros_like(Phi) if X is None else _check_vec(X, self.Vh, "X")
+        n = Phi.shape[0]
+        r, it, mv, rr = self._report(n)
+        rc = self._lib.seedcg_solve_indefinite(self._h, Phi.data_ptr(), X.data_ptr(), n, ctypes.byref(r))
+        rep = dict(iters=list(it), matvecs=list(mv), true_relres=list(rr), m=r.m_used, i_conv=r.i_conv,
+                   seed_status=r.seed_status, reorth_passes=r.reorth_passes, t_seed_s=r.t_seed_s, t_rest_s=r.t_rest_s,
                    status=STATUS.get(rc, rc))
         if rc != 0 and (rc != -5 or raise_on_noconv):
             self._rc(rc)

@@ -1,0 +1,97 @@
+"""The indefinite formulation (seedcg_solve_indefinite) on the GPU against the oracle.
+
+Bars:
+  * every system reaches the FP64 true residual ||phi - A x|| / ||phi|| <= 1e-10, judged by the
+    oracle's A, and (4^4) agrees with the dense solve to 1e-8;
+  * the solutions are those of the normal system M x = A^dag phi that Seed-CG solves (1e-8);
+  * the seeded Lanczos run matches the oracle's (oracle/seedminres.py, same k, tol and past):
+    m and i_conv within 1, and the MINRES iterations of every system within 10% (or 3) of the
+    oracle's from its own seeded guesses;
+  * edges: one right-hand side, a zero right-hand side, a mixed-precision handle (refused).
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import cuda, host, print_case
+from oracle import seedminres as smr
+from oracle.wilson import WilsonEO, dense, flat, gamma5, matvec_H
+from synth.configs import make_inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(name, dims):
+    U, phi, kappa = make_inputs(name)
+    op = WilsonEO(U, dims, kappa)
+    return dict(U=U, phi=phi, kappa=kappa, dims=dims, op=op, H=matvec_H(op))
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return _case("c1", (4, 4, 4, 4))
+
+
+@pytest.fixture(scope="module")
+def t8():
+    return _case("t8", (8, 8, 8, 8))
+
+
+def _relres_A(c, X):
+    op = c["op"]
+    R = c["phi"] - op.apply_A(X)
+    return np.linalg.norm(flat(R), axis=1) / np.linalg.norm(flat(c["phi"]), axis=1)
+
+
+def _solve(c, phi=None, **kw):
+    from paper_0901_3512_amd import SeedCG
+    s = SeedCG(cuda(c["U"]), c["dims"], c["kappa"], reorth_k=10, **kw)
+    X, rep = s.solve_indefinite(cuda(c["phi"] if phi is None else phi))
+    return s, host(X), rep
+
+
+@pytest.mark.parametrize("name", ["c1", "t8"])
+def test_solutions_and_parity_with_the_oracle(name, c1, t8):
+    c = c1 if name == "c1" else t8
+    print_case("indefinite", name)
+    s, X, rep = _solve(c)
+    res = _relres_A(c, X)
+    assert np.all(res <= 1e-10), res
+    assert np.allclose(rep["true_relres"], res, rtol=1e-3, atol=1e-14)
+    Cg5 = flat(gamma5(c["phi"]))
+    ref = smr.seed_minres(c["H"], Cg5, k=10, tol=1e-10, past=1.5)
+    assert abs(rep["m"] - ref["m"]) <= 1 and abs(rep["i_conv"] - ref["i_conv"]) <= 1, (rep["m"], ref["m"])
+    it_ref = []
+    for j in range(Cg5.shape[0]):
+        _, it, _ = smr.minres(c["H"], Cg5[j], ref["X"][j], tol=1e-10)
+        it_ref.append(it + (ref["m"] if j == 0 else 0))
+    for a, b in zip(rep["iters"], it_ref):
+        assert abs(a - b) <= max(3, 0.1 * b), (rep["iters"], it_ref)
+    # the same x as the normal system of Seed-CG
+    B = c["op"].apply_Adag(c["phi"])
+    Xs, _ = s.solve_seed(cuda(B))
+    Xs, _ = s.solve_rest(cuda(B), Xs)
+    err = np.linalg.norm(flat(X) - flat(host(Xs)), axis=1) / np.linalg.norm(flat(host(Xs)), axis=1)
+    assert np.all(err <= 1e-8), err
+    if name == "c1":
+        Hd = dense(c["H"], 12 * c["op"].Vh)
+        xs = np.linalg.solve(Hd, Cg5.T).T
+        e2 = np.linalg.norm(flat(X) - xs, axis=1) / np.linalg.norm(xs, axis=1)
+        assert np.all(e2 <= 1e-8), e2
+    print("indefinite", name, "m", rep["m"], "iters", rep["iters"], "oracle", it_ref)
+
+
+def test_edges(c1):
+    from paper_0901_3512_amd import SeedCG, SeedCGError
+    print_case("indefinite edges")
+    one = c1["phi"][:1]
+    _, X, rep = _solve(c1, phi=one)
+    assert _relres_A(dict(c1, phi=one), X)[0] <= 1e-10
+    z = c1["phi"].copy()
+    z[2] = 0.0
+    _, X, rep = _solve(c1, phi=z)
+    assert np.all(X[2] == 0) and rep["iters"][2] == 0
+    live = [0, 1, 3]
+    assert np.all(_relres_A(dict(c1, phi=z[live]), X[live]) <= 1e-10)
+    s = SeedCG(cuda(c1["U"]), c1["dims"], c1["kappa"], prec="mixed")
+    with pytest.raises(SeedCGError):
+        s.solve_indefinite(cuda(c1["phi"]))

@@ -146,7 +146,7 @@ def main():
 
     compare = None
     if not args.no_compare:
-        compare = compare_forms(args, cfg, Ud, kappa, B, value, prec)
+        compare = compare_forms(args, cfg, Ud, kappa, B, value, prec, phid)
     copy_gbs = copy_rate()
 
     cpu = None
@@ -177,10 +177,13 @@ def main():
     print(json.dumps(result), flush=True)
 
 
-def compare_forms(args, cfg, Ud, kappa, B, value_ref, prec_ref):
+def compare_forms(args, cfg, Ud, kappa, B, value_ref, prec_ref, phid):
     """The same lattice and right-hand sides solved by the other forms of the method, timed the same
-    way (1 warmup, then args.steps solves): mixed precision, and with --learned the learned K + mixed
-    (training on the seed solve's Ritz and basis vectors is part of every step)."""
+    way (1 warmup, then args.steps solves): traditional repeated seeding; in FP64, the indefinite
+    formulation (A x = phi through gamma5 A, seeded with the QR of the Lanczos matrix, finished by
+    MINRES; its residual is that of A x = phi, and the normal-equation residual of its solutions is
+    reported beside it); mixed precision, and with --learned the learned K + mixed (training on the
+    seed solve's Ritz and basis vectors is part of every step)."""
     import torch
     from paper_0901_3512_amd import SeedCG
     out = {"reference": {"form": prec_ref, "rhs_per_s": value_ref}}
@@ -200,6 +203,26 @@ def compare_forms(args, cfg, Ud, kappa, B, value_ref, prec_ref):
     out["repeated_seeding_" + prec_ref] = {"rhs_per_s": v, "vs_reference": v / value_ref, "iters": rr["iters"]}
     log(f"compare repeated seeding: {v:.2f} RHS/s ({v / value_ref:.2f}x)")
     s.close()
+    if prec_ref == "fp64":
+        s = SeedCG(Ud, cfg.dims, kappa, t_bc=cfg.t_bc, prec="fp64", reorth_k=cfg.reorth_k, past=cfg.past, tol=cfg.tol)
+        X, _ = s.solve_indefinite(phid)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        solved = 0
+        for _ in range(args.steps):
+            X, ri = s.solve_indefinite(phid)
+            solved += sum(1 for r in ri["true_relres"] if r <= cfg.tol)
+        torch.cuda.synchronize()
+        v = solved / (time.perf_counter() - t0)
+        MX = s.apply_M(X)
+        nres = (torch.linalg.vector_norm((B - MX).reshape(B.shape[0], -1), dim=1)
+                / torch.linalg.vector_norm(B.reshape(B.shape[0], -1), dim=1))
+        out["indefinite_qr_fp64"] = {"rhs_per_s": v, "vs_reference": v / value_ref, "m": ri["m"], "i_conv": ri["i_conv"],
+                                     "iters": ri["iters"], "max_relres_A": max(ri["true_relres"]),
+                                     "max_relres_normal": float(nres.max()), "t_seed_s": ri["t_seed_s"],
+                                     "t_rest_s": ri["t_rest_s"]}
+        log(f"compare indefinite (QR seeding of gamma5 A): {v:.2f} RHS/s ({v / value_ref:.2f}x)")
+        s.close()
     for prec, learned in forms:
         s = SeedCG(Ud, cfg.dims, kappa, t_bc=cfg.t_bc, prec=prec, reorth_k=cfg.reorth_k, past=cfg.past, tol=cfg.tol,
                    reliable_every=cfg.reliable_every)

@@ -1672,7 +1672,8 @@ bool solve_indefinite_impl(seedcg_s* h, const double* Phi, double* Xout, int nrh
     wk.V.ensure((size_t)(m_cap + 1) * vbytes);
     for (DBuf* b : {&wk.C, &wk.X, &wk.R0, &wk.Hb, &wk.Va, &wk.Vb, &wk.Wa, &wk.Wb, &wk.Wc}) b->ensure((size_t)nrhs * vbytes);
     wk.F.ensure(vbytes);
-    wk.W.ensure(3 * vbytes);
+    constexpr int WB = 32;   // seeding updates X += W_blk E_blk every WB steps (section 2's x^j updates, blocked)
+    wk.W.ensure(WB * vbytes);
     const int64_t nb = zdots_blocks(N);
     wk.part.ensure((size_t)2 * 32 * nb * sizeof(double));
     const int64_t nsb = nsb_of(h, false);
@@ -1756,6 +1757,7 @@ bool solve_indefinite_impl(seedcg_s* h, const double* Phi, double* Xout, int nrh
         sync();
         for (double& v : c) v = -v;
         HIPCHK(hipMemcpyAsync(wk.E.p, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        sync();
         for (int r0 = 0; r0 < nv; r0 += 32)
             seed_update(false, false, vcol(r0), std::min(32, nv - r0), wk.E.as<double>() + 2 * r0, x, 1, N, nullptr, L);
     };
@@ -1805,6 +1807,16 @@ bool solve_indefinite_impl(seedcg_s* h, const double* Phi, double* Xout, int nrh
             for (int j = 1; j < nrhs; j++) u[j] = d[j - 1];
         }
         std::vector<double> alpha, beta{beta0};
+        std::vector<cxd> eblk((size_t)WB * nrhs);
+        int nbuf = 0;   // steps whose w_i and tau_i wait in the ring for the next X update
+        wk.E.ensure((size_t)2 * WB * nrhs * sizeof(double));
+        auto flush = [&]() {
+            if (nbuf == 0) return;
+            HIPCHK(hipMemcpyAsync(wk.E.p, eblk.data(), (size_t)nbuf * nrhs * sizeof(cxd), hipMemcpyHostToDevice, s));
+            sync();
+            seed_update(false, false, wk.W.p, nbuf, wk.E.as<double>(), wk.X.p, nrhs, N, nullptr, L);
+            nbuf = 0;
+        };
         Givens g1, g2;
         int m_stop = m_cap;
         const void* wm1 = nullptr;   // w_{i-1}
@@ -1845,12 +1857,13 @@ bool solve_indefinite_impl(seedcg_s* h, const double* Phi, double* Xout, int nrh
                 status = 1;
                 break;
             }
-            // w_i into the ring slot of w_{i-3}; x^j += tau^j_i w_i
-            void* w = (char*)wk.W.p + (int64_t)(i % 3) * vbytes;
-            std::vector<cxd> tau(nrhs);
+            // w_i into ring slot (i - 1) % WB (the previous two slots hold w_{i-1}, w_{i-2}); tau^j_i
+            // waits in E_blk until the ring is full
+            const int slot = (i - 1) % WB;
+            void* w = (char*)wk.W.p + (int64_t)slot * vbytes;
             for (int j = 0; j < nrhs; j++) {
                 const cxd eta = (j == 0 || bi == 0.0) ? cxd(0.0) : d[j] / bi;   // v_{i+1}^dag r_0^j
-                tau[j] = q.g.c * u[j] + q.g.s * eta;
+                eblk[(size_t)slot * nrhs + j] = q.g.c * u[j] + q.g.s * eta;
                 u[j] = -q.g.s * u[j] + q.g.c * eta;
             }
             std::vector<ZLC> zs;
@@ -1871,25 +1884,8 @@ bool solve_indefinite_impl(seedcg_s* h, const double* Phi, double* Xout, int nrh
                 }
                 zs.push_back(z);
             }
-            for (int j = 0; j < nrhs; j++) {
-                ZLC z = lin(vec(wk.X, j), true, {{v, tau[j] / q.rho}});
-                if (wm1) {
-                    const cxd c = -tau[j] * q.delta / q.rho;
-                    z.in[z.nt] = wm1;
-                    z.are[z.nt] = c.real();
-                    z.aim[z.nt] = c.imag();
-                    z.nt++;
-                }
-                if (wm2) {
-                    const cxd c = -tau[j] * q.eps / q.rho;
-                    z.in[z.nt] = wm2;
-                    z.are[z.nt] = c.real();
-                    z.aim[z.nt] = c.imag();
-                    z.nt++;
-                }
-                zs.push_back(z);
-            }
             run(zs);
+            if (++nbuf == WB) flush();
             m_used = i;
             const double e = std::abs(u[0]);
             if (i_conv == 0 && e <= tol * cn[0]) {
@@ -1911,6 +1907,7 @@ bool solve_indefinite_impl(seedcg_s* h, const double* Phi, double* Xout, int nrh
             g2 = g1;
             g1 = q.g;
         }
+        flush();
         iters[0] = m_used;
         matvecs[0] += m_used;
     }

@@ -1533,6 +1533,12 @@ void autotune_single(seedcg_s* h, int nvec_multi) {
     cfg_zero(x.p, nvec_multi * h->vec_bytes(low), h->L());
     tune_shape(h, low, 1, x.p, y.p);
     tune_shape(h, low, nvec_multi, x.p, y.p);
+    if (low) {   // the FP64 stencil of the true residuals and reliable updates (several vectors)
+        x.ensure(nvec_multi * h->vec_bytes(false));
+        y.ensure(nvec_multi * h->vec_bytes(false));
+        cfg_zero(x.p, nvec_multi * h->vec_bytes(false), h->L());
+        tune_shape(h, false, nvec_multi, x.p, y.p);
+    }
     HIPCHK(hipStreamSynchronize(h->s));
     h->tuned = true;
 }
@@ -2246,6 +2252,10 @@ seedcg_status seedcg_create_batch(int32_t ncfg, const int32_t* dims, const doubl
                 zero_cfg(h, h->basis.p, h->vec_bytes(h->lo));
                 tune_shape(h, h->lo, 1, h->basis.p, h->f.p);
                 if (nrhs > 1) tune_shape(h, h->lo, nrhs, h->Pv.p, h->Qv.p);
+                if (h->lo && nrhs > 1) {   // the FP64 stencil of the true residuals and reliable updates
+                    zero_cfg(h, h->R64.p, nrhs * h->vec_bytes(false));
+                    tune_shape(h, false, nrhs, h->R64.p, h->Xint.p);
+                }
                 h->tuned = true;
             }
             HIPCHK(hipStreamSynchronize(h->s));

@@ -141,7 +141,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                 "traffic": measured_traffic(cfg, prec),
-                "kernel": "hop_kernel (even-odd Wilson hop, fused epilogues)", "launches_sampled": tm["launches"],
+                "kernel": "even-odd Wilson hop (hop_split_kernel, or the launch shape the autotuner picked), fused epilogues", "launches_sampled": tm["launches"],
                 "avg_launch_us": hop_ms * 1e3, "avg_launch_bytes": hop_bytes}
 
     compare = None

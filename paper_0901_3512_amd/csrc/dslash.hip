@@ -433,31 +433,32 @@ __device__ inline void st32(T* base, uint32_t idx, T v) {
     *(T*)((char*)base + idx * (uint32_t)sizeof(T)) = v;
 }
 
-// Epilogue of the two-lanes-per-site kernels for one vector: out = sy*[gamma5](x - kappa^2 v) +
+// Epilogue of the two-lanes-per-site kernels for one vector (NC of the 12 components, from the
+// component offset in lo): out = sy*[gamma5](x - kappa^2 v) +
 // cz z, with the reduction partial of Re d^dag out or |out|^2.  Every operand load is issued before
 // the first use (three independent batches of six), so the epilogue costs one memory round trip
 // instead of one per component and operand.
-template <typename T>
+template <typename T, int NC = 6>
 __device__ inline double epilogue2(const EpiDev<T>& e, const cx<T>* v, int bwd, size_t vo, int64_t Vh, uint32_t lo, cx<T>* __restrict__ out,
                                    T cz) {
-    cx<T> xv[6], zv[6], dv[6];
+    cx<T> xv[NC], zv[NC], dv[NC];
 #pragma unroll
-    for (int c = 0; c < 6; c++) xv[c] = zv[c] = dv[c] = mk<T>(0, 0);
+    for (int c = 0; c < NC; c++) xv[c] = zv[c] = dv[c] = mk<T>(0, 0);
     if (e.combine) {
 #pragma unroll
-        for (int c = 0; c < 6; c++) xv[c] = ld32(e.x + vo + (size_t)c * Vh, lo);
+        for (int c = 0; c < NC; c++) xv[c] = ld32(e.x + vo + (size_t)c * Vh, lo);
     }
     if (e.z) {
 #pragma unroll
-        for (int c = 0; c < 6; c++) zv[c] = ld32(e.z + vo + (size_t)c * Vh, lo);
+        for (int c = 0; c < NC; c++) zv[c] = ld32(e.z + vo + (size_t)c * Vh, lo);
     }
     if (e.red == 1) {
 #pragma unroll
-        for (int c = 0; c < 6; c++) dv[c] = ld32(e.d + vo + (size_t)c * Vh, lo);
+        for (int c = 0; c < NC; c++) dv[c] = ld32(e.d + vo + (size_t)c * Vh, lo);
     }
     double part = 0.0;
 #pragma unroll
-    for (int c = 0; c < 6; c++) {
+    for (int c = 0; c < NC; c++) {
         const cx<T> w = v[c];
         cx<T> y = w;
         if (e.combine) {
@@ -1252,6 +1253,99 @@ __global__ __launch_bounds__(512) void hop_plane_kernel(Geom g, const typename L
     }
 }
 
+// ---- quad-split variant ------------------------------------------------------------------
+// One vector per workgroup of 64 sites and four wavefronts: the forward x and y hops, the forward
+// z and t hops, and the same two pairs backward, each on a wavefront of its own.  A one-vector
+// launch (the Lanczos steps) then has four wavefronts per 64 sites instead of two, each with half
+// the dependent loads; the four partial sums meet in LDS and each wavefront writes three of the
+// twelve output components.
+template <typename T, typename LT>
+__global__ __launch_bounds__(SCG_BLOCK) void hop_quad_kernel(Geom g, const typename LinkLoad<LT>::Store* __restrict__ links,
+                                                             const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int p, int nvec,
+                                                             int64_t nsb, EpiDev<T> e, int64_t cs, int64_t bps) {
+    constexpr int NS = SCG_WAVE;   // sites per workgroup
+    __shared__ cx<T> xch[4 * 12 * NS];
+    __shared__ double red_lds[SCG_BLOCK / SCG_WAVE];
+    zoff_hop(cs, links, in, out, e);
+    if (e.gate_m && e.gate_i > *e.gate_m) return;
+    if (e.kappa2_dev) e.kappa2 = (T)*e.kappa2_dev;
+    const int64_t nblk = nsb * nvec;
+    const int64_t logical = xcd_logical_block(nblk);
+    if (logical >= nblk) return;
+    const int slot = (int)(logical % nvec);
+    const int64_t sb = logical / nvec;   // position in the visiting order (partials are indexed by it)
+    int q = e.vec_map ? e.vec_map[slot] : slot;
+    if (q >= 0 && e.cg && (e.cg[q].done || e.cg[q].frozen)) q = -1;
+    const int vec[1] = {__builtin_amdgcn_readfirstlane(q)};
+    if (vec[0] < 0) return;   // uniform over the workgroup
+    const int grp = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / SCG_WAVE));   // 0 fwd xy, 1 fwd zt, 2 bwd xy, 3 bwd zt
+    const int sl = (int)(threadIdx.x % SCG_WAVE);
+    const int64_t h = sb_order(sb, bps, g.L[3]) * NS + sl;
+    const bool active = h < g.Vh;
+    int x = 0, y = 0, z = 0, t = 0, xh = 0;
+    if (active) {
+        const uint32_t hu = (uint32_t)h;
+        xh = (int)(hu % (uint32_t)g.Lxh);
+        uint32_t r = hu / (uint32_t)g.Lxh;
+        y = (int)(r % (uint32_t)g.L[1]);
+        r /= (uint32_t)g.L[1];
+        z = (int)(r % (uint32_t)g.L[2]);
+        t = (int)(r / (uint32_t)g.L[2]);
+        x = 2 * xh + ((y + z + t + p) & 1);
+    }
+    const uint32_t Vh32 = (uint32_t)g.Vh, h32 = (uint32_t)h;
+    const Stage<T> sg{nullptr, 0, 0, 0};
+    cx<T> acc[1][12];
+#pragma unroll
+    for (int c = 0; c < 12; c++) acc[0][c] = mk<T>(0, 0);
+    if (active) {
+        if (grp == 0) {
+            split_dir<T, LT, 1, 0, false, false>(g, links, in, vec, p, x, y, z, t, xh, h32, sg, acc);
+            __builtin_amdgcn_sched_barrier(0);
+            split_dir<T, LT, 1, 1, false, false>(g, links, in, vec, p, x, y, z, t, xh, h32, sg, acc);
+        } else if (grp == 1) {
+            split_dir<T, LT, 1, 2, false, false>(g, links, in, vec, p, x, y, z, t, xh, h32, sg, acc);
+            __builtin_amdgcn_sched_barrier(0);
+            split_dir<T, LT, 1, 3, false, false>(g, links, in, vec, p, x, y, z, t, xh, h32, sg, acc);
+        } else if (grp == 2) {
+            split_dir<T, LT, 1, 0, true, false>(g, links, in, vec, p, x, y, z, t, xh, h32, sg, acc);
+            __builtin_amdgcn_sched_barrier(0);
+            split_dir<T, LT, 1, 1, true, false>(g, links, in, vec, p, x, y, z, t, xh, h32, sg, acc);
+        } else {
+            split_dir<T, LT, 1, 2, true, false>(g, links, in, vec, p, x, y, z, t, xh, h32, sg, acc);
+            __builtin_amdgcn_sched_barrier(0);
+            split_dir<T, LT, 1, 3, true, false>(g, links, in, vec, p, x, y, z, t, xh, h32, sg, acc);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 12; c++) xch[(grp * 12 + c) * NS + sl] = acc[0][c];
+    __syncthreads();
+    double part = 0.0;
+    if (active) {
+        cx<T> w[3];
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            const int cc = 3 * grp + c;
+            w[c] = xch[cc * NS + sl] + xch[(12 + cc) * NS + sl] + xch[(24 + cc) * NS + sl] + xch[(36 + cc) * NS + sl];
+        }
+        const size_t vo = (size_t)vec[0] * 12 * Vh32;
+        double czd = e.cz_host;
+        if (e.cz_dev) czd = e.cz_negate ? -e.cz_dev[vec[0]] : e.cz_dev[vec[0]];
+        const uint32_t lo = (uint32_t)(3 * grp) * Vh32 + h32;
+        part = epilogue2<T, 3>(e, w, grp >= 2 ? 1 : 0, vo, (int64_t)Vh32, lo, out, (T)czd);
+    }
+    if (e.red) {
+        for (int off = SCG_WAVE / 2; off > 0; off >>= 1) part += __shfl_xor(part, off);
+        if (sl == 0) red_lds[grp] = part;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double sum = 0.0;
+            for (int w = 0; w < SCG_BLOCK / SCG_WAVE; w++) sum += red_lds[w];
+            e.partials[(int64_t)vec[0] * nsb + sb] = sum;
+        }
+    }
+}
+
 // LDS bytes of the staged variant for nv vectors of element size es (0 if it does not apply)
 static size_t plane_lds_bytes(const Geom& g, int nv, size_t es) {
     if (g.Lxh > 256) return 0;
@@ -1265,13 +1359,14 @@ static int norm_vb(int tps, int vb, int nvec) {
     if (tps == 5 || tps == 6) vb = 1;
     if (tps == 7) vb = vb <= 2 ? 2 : 4;
     if (tps == 8 || tps == 9) vb = vb <= 1 ? 1 : (vb <= 2 ? 2 : 4);
+    if (tps == 10) vb = 1;
     return vb;
 }
 
 bool hop_shape_ok(const Geom& g, Prec prec, int tps, int vb) {
-    if (tps < 1 || tps > 9) return false;
+    if (tps < 1 || tps > 10) return false;
     const size_t es = (prec == P64 || prec == P64R) ? 16 : 8;
-    if ((tps == 8 || tps == 9) && (double)g.Vh * 12.0 * (double)es >= 4294967296.0) return false;
+    if (tps >= 8 && (double)g.Vh * 12.0 * (double)es >= 4294967296.0) return false;
     if (tps == 9) {
         const size_t b = plane_lds_bytes(g, norm_vb(9, vb, 4), es);
         return b > 0 && b <= PLANE_LDS_MAX;
@@ -1304,7 +1399,8 @@ void set_hop_hoist_links(bool on) { g_hoist = on ? 1 : 0; }
 // tps 8: the wave-split variant (forward and backward hops on separate wavefronts, vb 1, 2 or 4
 // vectors per workgroup)
 // tps 9: the LDS-staged variant (tiles of whole xy-rows, vb 1, 2 or 4); one workgroup per tile
-int hop_threads_per_site(int tps) { return (tps == 3 || tps >= 5) ? 2 : tps; }
+// tps 10: the quad-split variant (four wavefronts per 64 sites, one vector per workgroup)
+int hop_threads_per_site(int tps) { return tps == 10 ? 4 : ((tps == 3 || tps >= 5) ? 2 : tps); }
 int hop_site_blocks(const Geom& g, int tps) {
     if (tps == 9) return g.L[2] * g.L[3] * plane_tiles(g);
     return (int)((g.Vh * hop_threads_per_site(tps) + SCG_BLOCK - 1) / SCG_BLOCK);
@@ -1336,7 +1432,7 @@ static void launch_t(const Geom& g, const void* links, const void* in, void* out
     vb = norm_vb(tps, vb, nvec);
     // the wave-split kernels address a vector with 32-bit byte offsets, the staged one needs its LDS:
     // the handle's shapes were checked with hop_shape_ok (the reduction partials depend on the shape)
-    if ((tps == 8 || tps == 9) && (double)g.Vh * 12.0 * (double)sizeof(cx<T>) >= 4294967296.0)
+    if (tps >= 8 && (double)g.Vh * 12.0 * (double)sizeof(cx<T>) >= 4294967296.0)
         throw std::runtime_error("stencil launch shape does not fit this lattice");
     const int64_t grid = xcd_grid(nsb * ((nvec + vb - 1) / vb));
     // site blocks per t-slice for the tiled visiting order (two lanes per site, 128 sites a block)
@@ -1357,7 +1453,11 @@ static void launch_t(const Geom& g, const void* links, const void* in, void* out
     else if (tps == 7)
         hipLaunchKernelGGL((hop_multi_kernel<T, LT, 4>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
                            (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e, L.cs, bps);
-    else if (tps == 9) {
+    else if (tps == 10) {
+        const int64_t bps64 = (slice % SCG_WAVE == 0 && getenv_order()) ? slice / SCG_WAVE : 0;
+        hipLaunchKernelGGL((hop_quad_kernel<T, LT>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
+                           (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e, L.cs, bps64);
+    } else if (tps == 9) {
         const size_t lds = plane_lds_bytes(g, vb, sizeof(cx<T>));
         if (lds == 0 || lds > PLANE_LDS_MAX) throw std::runtime_error("stencil launch shape does not fit this lattice");
         const int Pw = (plane_rows(g) * g.Lxh + SCG_WAVE - 1) / SCG_WAVE * SCG_WAVE;

@@ -1401,8 +1401,8 @@ void init_geometry(seedcg_s* h, const seedcg_params* p, const int32_t* dims) {
     // workgroups on one XCD
     h->tps64 = env_int("SEEDCG_TPS", 8);
     h->tps_lo = env_int("SEEDCG_TPS_LO", 8);
-    if (h->tps64 < 1 || h->tps64 > 9) h->tps64 = 8;
-    if (h->tps_lo < 1 || h->tps_lo > 9) h->tps_lo = 8;
+    if (h->tps64 < 1 || h->tps64 > 10) h->tps64 = 8;
+    if (h->tps_lo < 1 || h->tps_lo > 10) h->tps_lo = 8;
     h->vb64 = std::max(1, env_int("SEEDCG_VB", 1));
     h->vb_lo = std::max(1, env_int("SEEDCG_VB_LO", 1));
     h->tps64_multi = h->tps64;
@@ -1472,7 +1472,7 @@ void tune_shape(seedcg_s* h, bool low, int nvec, const void* x, void* y) {
             return;
         }
     }
-    std::vector<std::pair<int, int>> cand{{9, 1}, {8, 1}, {3, 1}, {5, 1}, {6, 1}, {4, 1}, {2, 1}, {1, 1}};
+    std::vector<std::pair<int, int>> cand{{10, 1}, {9, 1}, {8, 1}, {3, 1}, {5, 1}, {6, 1}, {4, 1}, {2, 1}, {1, 1}};
     if (multi) {
         cand.push_back({9, 2});                 // staged x/y neighbours, links once per pair / quad
         cand.push_back({9, 4});

@@ -73,9 +73,15 @@ def test_batch_matches_oracle(cfgs, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_batch_equals_separate_handles(cfgs, prec):
+@pytest.mark.parametrize("shape", [None, ("9", "2"), ("10", "1"), ("3", "1")])
+def test_batch_equals_separate_handles(cfgs, prec, shape, monkeypatch):
+    """shape: a stencil launch shape (lanes-per-site code, vectors per workgroup) forced on both
+    sides; None = the default one."""
     from paper_0901_3512_amd import SeedCG
-    print_case("batch vs single", prec)
+    print_case("batch vs single", prec, shape)
+    if shape:
+        for k, v in (("SEEDCG_TPS", shape[0]), ("SEEDCG_TPS_LO", shape[0]), ("SEEDCG_VB", shape[1]), ("SEEDCG_VB_LO", shape[1])):
+            monkeypatch.setenv(k, v)
     b = _batch(cfgs, prec, m_max=300, autotune=False)
     Xb, reps = b.solve([cuda(c["B"]) for c in cfgs])
     for c, cfg in enumerate(cfgs):

@@ -143,6 +143,11 @@ def main():
                 "traffic": measured_traffic(cfg, prec),
                 "kernel": "even-odd Wilson hop (hop_split_kernel, or the launch shape the autotuner picked), fused epilogues", "launches_sampled": tm["launches"],
                 "avg_launch_us": hop_ms * 1e3, "avg_launch_bytes": hop_bytes}
+    if prec == "fp64" and achieved:
+        # the same launches priced with whole 3x3 links (18 reals) instead of the two rows (12 reals)
+        # the stencil reads for special-unitary fields: 8 links per output site, 6 reals more each
+        extra = (V // 2) * 8 * 6 * 8.0
+        roofline["achieved_18real_links"] = (hop_bytes + extra) / (hop_ms * 1e-3) / 1e9
 
     compare = None
     if not args.no_compare:

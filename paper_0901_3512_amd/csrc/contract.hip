@@ -8,7 +8,8 @@
 //
 // Split-K: a workgroup owns a K-chunk and up to 32 rows of V (two 16-row MFMA tiles) and
 // computes all 2*nr columns (up to three 16-column tiles) of its partial product, staging
-// 32 complex per row through LDS per step.  Partials go to part[chunk][row][j] and a second
+// 32 complex per row through LDS per step; the next step's staging is loaded into registers
+// while the current one is contracted.  Partials go to part[chunk][row][j] and a second
 // kernel sums the chunks in a fixed order (deterministic).  FP64 inputs use
 // v_mfma_f64_16x16x4; FP32 inputs use v_mfma_f32_16x16x4 with FP32 accumulation.
 //
@@ -42,28 +43,24 @@ struct MfmaAcc<float> {
 
 // TS: storage type of V and R; T: compute type (FP32 storage may be contracted in FP64)
 template <typename TS, typename T>
-__global__ __launch_bounds__(256) void proj_kernel(ProjArgs pa, int64_t cs) {
+__global__ __launch_bounds__(256) void proj_kernel(const ProjArgs pa, int64_t cs) {
     using Acc = MfmaAcc<T>;
     using V4 = typename Acc::V4;
     __shared__ T As[PJ_ROWS * PJ_LD];
     __shared__ T Bs[PJ_MAXR * PJ_LD];
 
-    if (cs) {
-        pa.V = zoff(pa.V, cs);
-        for (int j = 0; j < pa.nr; j++) pa.R[j] = zoff(pa.R[j], cs);
-        pa.part = zoff(pa.part, cs);
-        pa.st = zoff(pa.st, cs);
-        pa.flag = zoff(pa.flag, cs);
-    }
-    if (pa.st && pa.gate_i > pa.st->m) return;
-    if (pa.flag && *pa.flag == 0) return;
+    // the argument is only read (a write would make the compiler copy all of it to scratch)
+    const LzState* st = zoff(pa.st, cs);
+    const int32_t* flag = zoff(pa.flag, cs);
+    if (st && pa.gate_i > st->m) return;
+    if (flag && *flag == 0) return;
     int nvalid = pa.nv;
-    if (pa.st && pa.rows_from_m) nvalid = max(0, min(pa.nv, pa.st->m - pa.i0 + 1));
+    if (st && pa.rows_from_m) nvalid = max(0, min(pa.nv, st->m - pa.i0 + 1));
     const int row0 = blockIdx.y * PJ_ROWS;
     const int nrow = min(PJ_ROWS, nvalid - row0);
     if (nrow <= 0) return;
 
-    const TS* V = (const TS*)pa.V;
+    const TS* V = (const TS*)zoff(pa.V, cs);
     const int nr = pa.nr;
     const int ncol = 2 * nr;
     const int ncolt = (ncol + 15) / 16;
@@ -80,33 +77,54 @@ __global__ __launch_bounds__(256) void proj_kernel(ProjArgs pa, int64_t cs) {
         acc1[q] = 0;
     }
 
+    // the staging of step kb + PJ_KC is loaded into registers while step kb is contracted from
+    // LDS, so the global loads overlap the matrix-core work (one complex per thread and pass)
+    constexpr int NVU = PJ_ROWS * PJ_KC / 256;                 // V elements per thread
+    constexpr int NRU = (PJ_MAXR * PJ_KC + 255) / 256;         // R elements per thread (at most)
+    cx<TS> vreg[NVU], rreg[NRU];
+    const TS* vrow[NVU];      // this thread's V rows (null beyond nrow) and R vectors (null beyond nr)
+    const TS* rvec[NRU];
+#pragma unroll
+    for (int u = 0; u < NVU; u++) {
+        const int r = (threadIdx.x + 256 * u) / PJ_KC;
+        vrow[u] = r < nrow ? V + 2 * (int64_t)(row0 + r) * pa.ldv : nullptr;
+    }
+#pragma unroll
+    for (int u = 0; u < NRU; u++) {
+        const int j = (threadIdx.x + 256 * u) / PJ_KC;
+        rvec[u] = j < nr ? (const TS*)zoff(pa.R[j], cs) : nullptr;
+    }
+    const int cth = threadIdx.x % PJ_KC;   // the complex index within a step (256 is a multiple of PJ_KC)
+    auto fetch = [&vreg, &rreg, &vrow, &rvec, cth, k_end](int64_t kb) {
+        const bool cok = kb + cth < k_end;
+#pragma unroll
+        for (int u = 0; u < NVU; u++)
+            vreg[u] = (vrow[u] && cok) ? *(const cx<TS>*)(vrow[u] + 2 * (kb + cth)) : mk<TS>(0, 0);
+#pragma unroll
+        for (int u = 0; u < NRU; u++)
+            rreg[u] = (rvec[u] && cok) ? *(const cx<TS>*)(rvec[u] + 2 * (kb + cth)) : mk<TS>(0, 0);
+    };
+    if (k_begin < k_end) fetch(k_begin);
     for (int64_t kb = k_begin; kb < k_end; kb += PJ_KC) {
-        const int kc = (int)min((int64_t)PJ_KC, k_end - kb);
         __syncthreads();
-        // stage V rows and R vectors: one complex (two reals) per thread per pass
-        for (int idx = threadIdx.x; idx < PJ_ROWS * PJ_KC; idx += 256) {
+#pragma unroll
+        for (int u = 0; u < NVU; u++) {
+            const int idx = threadIdx.x + 256 * u;
             const int r = idx / PJ_KC, c = idx % PJ_KC;
-            T re = 0, im = 0;
-            if (r < nrow && c < kc) {
-                const TS* p = V + 2 * ((int64_t)(row0 + r) * pa.ldv + kb + c);
-                re = (T)p[0];
-                im = (T)p[1];
-            }
-            As[r * PJ_LD + 2 * c] = re;
-            As[r * PJ_LD + 2 * c + 1] = im;
+            As[r * PJ_LD + 2 * c] = (T)vreg[u].re;
+            As[r * PJ_LD + 2 * c + 1] = (T)vreg[u].im;
         }
-        for (int idx = threadIdx.x; idx < nr * PJ_KC; idx += 256) {
+#pragma unroll
+        for (int u = 0; u < NRU; u++) {
+            const int idx = threadIdx.x + 256 * u;
             const int j = idx / PJ_KC, c = idx % PJ_KC;
-            T re = 0, im = 0;
-            if (c < kc) {
-                const TS* p = (const TS*)pa.R[j] + 2 * (kb + c);
-                re = (T)p[0];
-                im = (T)p[1];
+            if (j < nr) {
+                Bs[j * PJ_LD + 2 * c] = (T)rreg[u].re;
+                Bs[j * PJ_LD + 2 * c + 1] = (T)rreg[u].im;
             }
-            Bs[j * PJ_LD + 2 * c] = re;
-            Bs[j * PJ_LD + 2 * c + 1] = im;
         }
         __syncthreads();
+        if (kb + PJ_KC < k_end) fetch(kb + PJ_KC);
         // this wave's output tiles: wave, wave + 4 (at most 6 tiles)
         for (int tsel = 0; tsel < 2; tsel++) {
             const int tile = wave + 4 * tsel;
@@ -138,7 +156,7 @@ __global__ __launch_bounds__(256) void proj_kernel(ProjArgs pa, int64_t cs) {
     }
 
     // write the partial tiles: part[chunk][row][j] complex (FP64)
-    double* out = pa.part + (int64_t)blockIdx.x * pa.part_stride;
+    double* out = zoff(pa.part, cs) + (int64_t)blockIdx.x * pa.part_stride;
     for (int tsel = 0; tsel < 2; tsel++) {
         const int tile = wave + 4 * tsel;
         if (tile >= ntiles) break;

@@ -2,6 +2,7 @@
 
   python -m paper_0901_3512_amd.profsummary stats  <dir-with-kernel_stats.csv> [--top N]
   python -m paper_0901_3512_amd.profsummary bytes  <fetch-dir> <write-dir> --kernel hop_kernel
+  python -m paper_0901_3512_amd.profsummary counters <dir-with-counter_collection.csv> --kernel proj_kernel
 
 `bytes` averages FETCH_SIZE and WRITE_SIZE (KiB per dispatch) over the dispatches of the named
 kernel between the copy probe and the next 1 GiB copy, and scales each by what the same counter
@@ -85,6 +86,38 @@ def bytes_per_launch(fetch_dir, write_dir, kernel):
                 write_bytes=write, traffic_bytes=fetch + write)
 
 
+def counters(d, kernel):
+    """Per kernel name containing `kernel`: dispatches, summed dispatch time, every counter's total,
+    and (when collected) the matrix-core busy fraction and MFMA TFLOP/s.  GRBM_GUI_ACTIVE is summed
+    over the 8 XCDs, SQ_VALU_MFMA_BUSY_CYCLES over the 1024 SIMDs; a MOPS unit is 512 flops."""
+    path = _one(os.path.join(d, "**", "*counter_collection.csv"))
+    agg, dur = {}, {}
+    for r in csv.DictReader(open(path)):
+        if kernel not in r["Kernel_Name"]:
+            continue
+        name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+        agg.setdefault(name, {}).setdefault(r["Counter_Name"], 0.0)
+        agg[name][r["Counter_Name"]] += float(r["Counter_Value"])
+        dur.setdefault(name, {})[r["Dispatch_Id"]] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    out = []
+    for name, c in agg.items():
+        n = len(dur[name])
+        t = sum(dur[name].values()) * 1e-9
+        line = f"{name}: dispatches {n}, total {t * 1e3:.2f} ms"
+        for key in sorted(c):
+            line += f", {key} {c[key]:.4g}"
+        if "GRBM_GUI_ACTIVE" in c and "SQ_VALU_MFMA_BUSY_CYCLES" in c:
+            line += f", MFMA busy fraction {c['SQ_VALU_MFMA_BUSY_CYCLES'] / (c['GRBM_GUI_ACTIVE'] / 8 * 1024):.4f}"
+        for p in ("F64", "F32"):
+            m = c.get(f"SQ_INSTS_VALU_MFMA_MOPS_{p}")
+            if m:
+                line += f", {p} TFLOP/s {m * 512 / t / 1e12:.2f}"
+        if "FETCH_SIZE" in c:
+            line += f", fetch KiB/dispatch {c['FETCH_SIZE'] / n:.4g}"
+        out.append(line)
+    return "\n".join(out)
+
+
 def source_digest(path):
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
@@ -100,9 +133,14 @@ def main():
     b.add_argument("write_dir")
     b.add_argument("--kernel", default="hop_")
     b.add_argument("--source", default=os.path.join(os.path.dirname(__file__), "csrc", "dslash.hip"))
+    c = sub.add_parser("counters")
+    c.add_argument("dir")
+    c.add_argument("--kernel", default="proj_kernel")
     args = ap.parse_args()
     if args.cmd == "stats":
         print(stats(args.dir, args.top))
+    elif args.cmd == "counters":
+        print(counters(args.dir, args.kernel))
     else:
         r = bytes_per_launch(args.fetch_dir, args.write_dir, args.kernel)
         print(f"kernel={args.kernel} dispatches={r['dispatches']}")

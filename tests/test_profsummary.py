@@ -37,3 +37,23 @@ def test_bytes_per_launch_counts_only_the_timed_window(tmp_path):
     r = bytes_per_launch(str(tmp_path / "f"), str(tmp_path / "w"), "hop_")
     assert r["dispatches"] == 2
     assert r["fetch_bytes"] == 200 * 2.0 * 1024 and r["write_bytes"] == 50 * 1.0 * 1024
+
+
+def test_counters_derive_mfma_busy_fraction_and_rate(tmp_path):
+    from paper_0901_3512_amd.profsummary import counters
+    d = tmp_path / "m"
+    d.mkdir()
+    with open(d / "x_counter_collection.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value", "Start_Timestamp",
+                                          "End_Timestamp"])
+        w.writeheader()
+        for dsp in (1, 2):
+            for cn, v in (("SQ_INSTS_VALU_MFMA_MOPS_F64", 1e6), ("GRBM_GUI_ACTIVE", 8e6),
+                          ("SQ_VALU_MFMA_BUSY_CYCLES", 1024e6 * 0.25)):
+                w.writerow(dict(Dispatch_Id=dsp, Kernel_Name="void scg::proj_kernel<double, double>(a)", Counter_Name=cn,
+                                Counter_Value=v, Start_Timestamp=0, End_Timestamp=1000000))
+            w.writerow(dict(Dispatch_Id=10 + dsp, Kernel_Name="void scg::other(a)", Counter_Name="GRBM_GUI_ACTIVE",
+                            Counter_Value=1, Start_Timestamp=0, End_Timestamp=1))
+    out = counters(str(d), "proj_kernel")
+    assert "dispatches 2" in out and "MFMA busy fraction 0.2500" in out and "F64 TFLOP/s 0.51" in out
+    assert "other" not in out

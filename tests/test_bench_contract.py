@@ -1,0 +1,30 @@
+"""Host-side parts of the benchmark contract (no GPU): the one-GPU refusal and the traffic figure's
+source check."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    out = json.loads(r.stdout.strip().splitlines()[-1])
+    assert out["n_gpus"] == 2 and "one GPU" in out["error"]
+
+
+def test_traffic_is_reported_only_for_the_current_stencil_source():
+    sys.path.insert(0, ROOT)
+    import bench
+    from synth.configs import CONFIGS
+    from paper_0901_3512_amd.profsummary import source_digest
+    cfg = CONFIGS["c2"]
+    path = os.path.join(ROOT, "profiles", "hop_kernel_16x16x16x32_fp64_traffic.txt")
+    kv = dict(l.strip().split("=", 1) for l in open(path) if "=" in l and not l.startswith("#"))
+    src = os.path.join(ROOT, "paper_0901_3512_amd", "csrc", "dslash.hip")
+    current = kv["source_sha256_16"] == source_digest(src)
+    t = bench.measured_traffic(cfg, "fp64")
+    assert (t == float(kv["traffic_bytes_per_launch"])) if current else (t is None)

@@ -165,6 +165,8 @@ struct EpiDev {
     const int32_t* vec_map;
     const CgVec* cg;
     const double* kappa2_dev;
+    cx<double>* X;     // red 3: CG iterate (always FP64)
+    cx<T>* R;          // red 3: CG residual
 };
 
 // move every per-configuration pointer of a launch to configuration blockIdx.z
@@ -183,6 +185,17 @@ __device__ inline void zoff_hop(int64_t cs, PL& links, PI& in, PO& out, EpiDev<T
     e.vec_map = zoff(e.vec_map, cs);
     e.cg = zoff(e.cg, cs);
     e.kappa2_dev = zoff(e.kappa2_dev, cs);
+    e.X = zoff(e.X, cs);
+    e.R = zoff(e.R, cs);
+}
+
+// the per-vector coefficient of the epilogue: alpha of the vector's CG record for the fused CG
+// update, else cz of the extra vector term
+template <typename T>
+__device__ inline double epi_coef(const EpiDev<T>& e, int vec) {
+    if (e.red == 3) return e.cg[vec].a;
+    if (e.cz_dev) return e.cz_negate ? -e.cz_dev[vec] : e.cz_dev[vec];
+    return e.cz_host;
 }
 
 // Site-block visiting order of the two-lanes-per-site kernels.  A site block (128 sites) lies in
@@ -436,11 +449,15 @@ __device__ inline void st32(T* base, uint32_t idx, T v) {
 // Epilogue of the two-lanes-per-site kernels for one vector (NC of the 12 components, from the
 // component offset in lo): out = sy*[gamma5](x - kappa^2 v) +
 // cz z, with the reduction partial of Re d^dag out or |out|^2.  Every operand load is issued before
-// the first use (three independent batches of six), so the epilogue costs one memory round trip
+// the first use (independent batches of NC), so the epilogue costs one memory round trip
 // instead of one per component and operand.
-template <typename T, int NC = 6>
+// red 3 (the CG update fused into the last hop of q = M p): q = out is not stored; with
+// a = cz (the vector's alpha), X += a p (p = d), R -= a q, and the partial is |R|^2 -- the same
+// arithmetic, in the same precisions, as the separate update kernel.
+template <typename T, int NC = 6, bool CGU = false>
 __device__ inline double epilogue2(const EpiDev<T>& e, const cx<T>* v, int bwd, size_t vo, int64_t Vh, uint32_t lo, cx<T>* __restrict__ out,
-                                   T cz) {
+                                   double cz) {
+    const T czt = (T)cz;
     cx<T> xv[NC], zv[NC], dv[NC];
 #pragma unroll
     for (int c = 0; c < NC; c++) xv[c] = zv[c] = dv[c] = mk<T>(0, 0);
@@ -452,11 +469,32 @@ __device__ inline double epilogue2(const EpiDev<T>& e, const cx<T>* v, int bwd, 
 #pragma unroll
         for (int c = 0; c < NC; c++) zv[c] = ld32(e.z + vo + (size_t)c * Vh, lo);
     }
-    if (e.red == 1) {
+    if (CGU || e.red == 1) {
 #pragma unroll
         for (int c = 0; c < NC; c++) dv[c] = ld32(e.d + vo + (size_t)c * Vh, lo);
     }
     double part = 0.0;
+    if constexpr (CGU) {
+        cx<T> rv[NC];
+        cx<double> sv[NC];
+#pragma unroll
+        for (int c = 0; c < NC; c++) {
+            rv[c] = ld32(e.R + vo + (size_t)c * Vh, lo);
+            sv[c] = ld32(e.X + vo + (size_t)c * Vh, lo);
+        }
+#pragma unroll
+        for (int c = 0; c < NC; c++) {
+            const cx<T> w = v[c];
+            cx<T> y = mk<T>(xv[c].re - e.kappa2 * w.re, xv[c].im - e.kappa2 * w.im);
+            if (e.apply_g5 && bwd) y = mk<T>(-y.re, -y.im);
+            const cx<T> q = mk<T>(e.sy * y.re, e.sy * y.im);
+            st32(e.X + vo + (size_t)c * Vh, lo, mk<double>(sv[c].re + cz * dv[c].re, sv[c].im + cz * dv[c].im));
+            const cx<T> rn = mk<T>((T)(rv[c].re - cz * q.re), (T)(rv[c].im - cz * q.im));
+            st32(e.R + vo + (size_t)c * Vh, lo, rn);
+            part += (double)rn.re * rn.re + (double)rn.im * rn.im;
+        }
+        return part;
+    }
 #pragma unroll
     for (int c = 0; c < NC; c++) {
         const cx<T> w = v[c];
@@ -466,7 +504,7 @@ __device__ inline double epilogue2(const EpiDev<T>& e, const cx<T>* v, int bwd, 
             if (e.apply_g5 && bwd) y = mk<T>(-y.re, -y.im);
         }
         cx<T> o = mk<T>(e.sy * y.re, e.sy * y.im);
-        if (e.z) o = mk<T>(o.re + cz * zv[c].re, o.im + cz * zv[c].im);
+        if (e.z) o = mk<T>(o.re + czt * zv[c].re, o.im + czt * zv[c].im);
         st32(out + vo + (size_t)c * Vh, lo, o);
         if (e.red == 1)
             part += (double)dv[c].re * (double)o.re + (double)dv[c].im * (double)o.im;
@@ -602,13 +640,12 @@ __global__ __launch_bounds__(SCG_BLOCK) void hop_lean_kernel(Geom g, const typen
         double part = 0.0;
         if (active) {
             const size_t vo = (size_t)vec * 12 * Vh;
-            double czd = e.cz_host;
-            if (e.cz_dev) czd = e.cz_negate ? -e.cz_dev[vec] : e.cz_dev[vec];
+            const double czd = epi_coef(e, vec);
             const uint32_t lo = (uint32_t)bwd * 6u * Vh32 + h32;
             cx<T> v[6];
 #pragma unroll
             for (int c = 0; c < 6; c++) v[c] = bwd ? acc[6 + c] : acc[c];
-            part = epilogue2<T>(e, v, bwd, vo, Vh, lo, out, (T)czd);
+            part = epilogue2<T>(e, v, bwd, vo, Vh, lo, out, czd);
         }
         if (e.red) {
             for (int off = SCG_WAVE / 2; off > 0; off >>= 1) part += __shfl_xor(part, off);
@@ -752,13 +789,12 @@ __global__ __launch_bounds__(SCG_BLOCK) void hop_multi_kernel(Geom g, const type
         double part = 0.0;
         if (active && vec[v] >= 0) {
             const size_t vo = (size_t)vec[v] * 12 * Vh;
-            double czd = e.cz_host;
-            if (e.cz_dev) czd = e.cz_negate ? -e.cz_dev[vec[v]] : e.cz_dev[vec[v]];
+            const double czd = epi_coef(e, vec[v]);
             const uint32_t lo = (uint32_t)bwd * 6u * Vh32 + h32;
             cx<T> w[6];
 #pragma unroll
             for (int c = 0; c < 6; c++) w[c] = bwd ? acc[v][6 + c] : acc[v][c];
-            part = epilogue2<T>(e, w, bwd, vo, Vh, lo, out, (T)czd);
+            part = epilogue2<T>(e, w, bwd, vo, Vh, lo, out, czd);
         }
         if (e.red) {
             for (int off = SCG_WAVE / 2; off > 0; off >>= 1) part += __shfl_xor(part, off);
@@ -1005,7 +1041,7 @@ __device__ __attribute__((always_inline)) inline void split_handover(const cx<T>
 }
 
 // the other side's six components added to this side's, then the epilogue on them
-template <typename T, int NV, bool BWD>
+template <typename T, int NV, bool BWD, bool CGU>
 __device__ __attribute__((always_inline)) inline void split_tail(const EpiDev<T>& e, const int (&vec)[NV], bool active, uint32_t Vh32,
                                                                  uint32_t h32, int sl, int wave, int nwave, const cx<T> (&acc)[NV][12],
                                                                  const cx<T>* xch, uint32_t xs, cx<T>* __restrict__ out, double* red_lds) {
@@ -1019,9 +1055,8 @@ __device__ __attribute__((always_inline)) inline void split_tail(const EpiDev<T>
 #pragma unroll
             for (int c = 0; c < 6; c++) w[c] = acc[v][own + c] + xch[(uint32_t)((v * 2 + (BWD ? 1 : 0)) * 6 + c) * xs + sl];
             const size_t vo = (size_t)vec[v] * 12 * Vh32;
-            double czd = e.cz_host;
-            if (e.cz_dev) czd = e.cz_negate ? -e.cz_dev[vec[v]] : e.cz_dev[vec[v]];
-            part = epilogue2<T>(e, w, BWD ? 1 : 0, vo, (int64_t)Vh32, lo, out, (T)czd);
+            const double czd = epi_coef(e, vec[v]);
+            part = epilogue2<T, 6, CGU>(e, w, BWD ? 1 : 0, vo, (int64_t)Vh32, lo, out, czd);
         }
         if (e.red) {
             for (int off = SCG_WAVE / 2; off > 0; off >>= 1) part += __shfl_xor(part, off);
@@ -1030,7 +1065,7 @@ __device__ __attribute__((always_inline)) inline void split_tail(const EpiDev<T>
     }
 }
 
-template <typename T, typename LT, int NV>
+template <typename T, typename LT, int NV, bool CGU = false>
 __global__ __launch_bounds__(SCG_BLOCK) void hop_split_kernel(Geom g, const typename LinkLoad<LT>::Store* __restrict__ links,
                                                               const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
                                                               int p, int nvec, int64_t nsb, EpiDev<T> e, int64_t cs, int64_t bps) {
@@ -1099,9 +1134,9 @@ __global__ __launch_bounds__(SCG_BLOCK) void hop_split_kernel(Geom g, const type
 
     constexpr int nwave = SCG_BLOCK / SCG_WAVE;
     if (bwd)
-        split_tail<T, NV, true>(e, vec, active, Vh32, h32, sl, wave, nwave, acc, xch, xs, out, red_lds);
+        split_tail<T, NV, true, CGU>(e, vec, active, Vh32, h32, sl, wave, nwave, acc, xch, xs, out, red_lds);
     else
-        split_tail<T, NV, false>(e, vec, active, Vh32, h32, sl, wave, nwave, acc, xch, xs, out, red_lds);
+        split_tail<T, NV, false, CGU>(e, vec, active, Vh32, h32, sl, wave, nwave, acc, xch, xs, out, red_lds);
     if (e.red) {
         __syncthreads();
         const int v = threadIdx.x;
@@ -1138,7 +1173,7 @@ __host__ __device__ inline int plane_stage_sites(const Geom& g) {
     return (R >= g.L[1] ? g.L[1] : R + 2) * g.Lxh;
 }
 
-template <typename T, typename LT, int NV>
+template <typename T, typename LT, int NV, bool CGU = false>
 __global__ __launch_bounds__(512) void hop_plane_kernel(Geom g, const typename LinkLoad<LT>::Store* __restrict__ links,
                                                         const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int p, int nvec,
                                                         int64_t nsb, EpiDev<T> e, int64_t cs, int Pw) {
@@ -1233,9 +1268,9 @@ __global__ __launch_bounds__(512) void hop_plane_kernel(Geom g, const typename L
     __syncthreads();
     const int nwave = 2 * nws;
     if (bwd)
-        split_tail<T, NV, true>(e, vec, active, Vh32, h32, sl, wave, nwave, acc, st, xs, out, red_lds);
+        split_tail<T, NV, true, CGU>(e, vec, active, Vh32, h32, sl, wave, nwave, acc, st, xs, out, red_lds);
     else
-        split_tail<T, NV, false>(e, vec, active, Vh32, h32, sl, wave, nwave, acc, st, xs, out, red_lds);
+        split_tail<T, NV, false, CGU>(e, vec, active, Vh32, h32, sl, wave, nwave, acc, st, xs, out, red_lds);
     if (e.red) {
         __syncthreads();
         const int v = threadIdx.x;
@@ -1259,7 +1294,7 @@ __global__ __launch_bounds__(512) void hop_plane_kernel(Geom g, const typename L
 // launch (the Lanczos steps) then has four wavefronts per 64 sites instead of two, each with half
 // the dependent loads; the four partial sums meet in LDS and each wavefront writes three of the
 // twelve output components.
-template <typename T, typename LT>
+template <typename T, typename LT, bool CGU = false>
 __global__ __launch_bounds__(SCG_BLOCK) void hop_quad_kernel(Geom g, const typename LinkLoad<LT>::Store* __restrict__ links,
                                                              const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int p, int nvec,
                                                              int64_t nsb, EpiDev<T> e, int64_t cs, int64_t bps) {
@@ -1329,10 +1364,9 @@ __global__ __launch_bounds__(SCG_BLOCK) void hop_quad_kernel(Geom g, const typen
             w[c] = xch[cc * NS + sl] + xch[(12 + cc) * NS + sl] + xch[(24 + cc) * NS + sl] + xch[(36 + cc) * NS + sl];
         }
         const size_t vo = (size_t)vec[0] * 12 * Vh32;
-        double czd = e.cz_host;
-        if (e.cz_dev) czd = e.cz_negate ? -e.cz_dev[vec[0]] : e.cz_dev[vec[0]];
+        const double czd = epi_coef(e, vec[0]);
         const uint32_t lo = (uint32_t)(3 * grp) * Vh32 + h32;
-        part = epilogue2<T, 3>(e, w, grp >= 2 ? 1 : 0, vo, (int64_t)Vh32, lo, out, (T)czd);
+        part = epilogue2<T, 3, CGU>(e, w, grp >= 2 ? 1 : 0, vo, (int64_t)Vh32, lo, out, czd);
     }
     if (e.red) {
         for (int off = SCG_WAVE / 2; off > 0; off >>= 1) part += __shfl_xor(part, off);
@@ -1406,6 +1440,35 @@ int hop_site_blocks(const Geom& g, int tps) {
     return (int)((g.Vh * hop_threads_per_site(tps) + SCG_BLOCK - 1) / SCG_BLOCK);
 }
 
+// the wave-split (tps 8), LDS-staged (9) and quad-split (10) stencils; CGU: with the CG update fused
+// into the epilogue
+template <typename T, typename LT, bool CGU>
+static void launch_wide(const Geom& g, const typename LinkLoad<LT>::Store* links, const cx<T>* in, cx<T>* out, int p, int nvec,
+                        int64_t nsb, const EpiDev<T>& e, int tps, int vb, int64_t grid, int64_t bps, const Launch& L) {
+    const hipStream_t s = L.s;
+    const dim3 gr((unsigned)grid, 1, L.nz);
+    if (tps == 10) {
+        const int64_t slice = g.Vh / g.L[3];
+        const int64_t bps64 = (slice % SCG_WAVE == 0 && getenv_order()) ? slice / SCG_WAVE : 0;
+        hipLaunchKernelGGL((hop_quad_kernel<T, LT, CGU>), gr, dim3(SCG_BLOCK), 0, s, g, links, in, out, p, nvec, nsb, e, L.cs, bps64);
+    } else if (tps == 9) {
+        const size_t lds = plane_lds_bytes(g, vb, sizeof(cx<T>));
+        if (lds == 0 || lds > PLANE_LDS_MAX) throw std::runtime_error("stencil launch shape does not fit this lattice");
+        const int Pw = (plane_rows(g) * g.Lxh + SCG_WAVE - 1) / SCG_WAVE * SCG_WAVE;
+        if (vb == 1)
+            hipLaunchKernelGGL((hop_plane_kernel<T, LT, 1, CGU>), gr, dim3(2 * Pw), lds, s, g, links, in, out, p, nvec, nsb, e, L.cs, Pw);
+        else if (vb == 2)
+            hipLaunchKernelGGL((hop_plane_kernel<T, LT, 2, CGU>), gr, dim3(2 * Pw), lds, s, g, links, in, out, p, nvec, nsb, e, L.cs, Pw);
+        else
+            hipLaunchKernelGGL((hop_plane_kernel<T, LT, 4, CGU>), gr, dim3(2 * Pw), lds, s, g, links, in, out, p, nvec, nsb, e, L.cs, Pw);
+    } else if (vb == 1)
+        hipLaunchKernelGGL((hop_split_kernel<T, LT, 1, CGU>), gr, dim3(SCG_BLOCK), 0, s, g, links, in, out, p, nvec, nsb, e, L.cs, bps);
+    else if (vb == 2)
+        hipLaunchKernelGGL((hop_split_kernel<T, LT, 2, CGU>), gr, dim3(SCG_BLOCK), 0, s, g, links, in, out, p, nvec, nsb, e, L.cs, bps);
+    else
+        hipLaunchKernelGGL((hop_split_kernel<T, LT, 4, CGU>), gr, dim3(SCG_BLOCK), 0, s, g, links, in, out, p, nvec, nsb, e, L.cs, bps);
+}
+
 template <typename T, typename LT>
 static void launch_t(const Geom& g, const void* links, const void* in, void* out, int p, int nvec, const HopEpi& epi,
                      int tps, int vb, const Launch& L) {
@@ -1428,6 +1491,11 @@ static void launch_t(const Geom& g, const void* links, const void* in, void* out
     e.vec_map = epi.vec_map;
     e.cg = epi.cg;
     e.kappa2_dev = epi.kappa2_dev;
+    e.X = (cx<double>*)epi.X;
+    e.R = (cx<T>*)epi.R;
+    if (epi.red == 3 && (!epi.cg || !epi.d || !epi.X || !epi.R || !epi.combine || epi.z || tps < 8 ||
+                         (double)g.Vh * 12.0 * 16.0 >= 4294967296.0))
+        throw std::runtime_error("fused CG update: needs cg, p, X, R, the combine and the tps 8, 9 or 10 stencil");
     const int64_t nsb = hop_site_blocks(g, tps);
     vb = norm_vb(tps, vb, nvec);
     // the wave-split kernels address a vector with 32-bit byte offsets, the staged one needs its LDS:
@@ -1441,6 +1509,13 @@ static void launch_t(const Geom& g, const void* links, const void* in, void* out
     using S = typename LinkLoad<LT>::Store;
     // links kept in registers across the vectors of a workgroup when one lane holds one direction
     const bool hoist = tps == 4 && hop_hoist_links();
+    if (tps >= 8) {
+        if (epi.red == 3)
+            launch_wide<T, LT, true>(g, (const S*)links, (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e, tps, vb, grid, bps, L);
+        else
+            launch_wide<T, LT, false>(g, (const S*)links, (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e, tps, vb, grid, bps, L);
+        return;
+    }
     if (tps == 3 && vb == 1)
         hipLaunchKernelGGL((hop_lean_kernel<T, LT, true, 1>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
                            (const cx<T>*)in, (cx<T>*)out, p, nvec, vb, nsb, e, L.cs, bps);
@@ -1452,32 +1527,6 @@ static void launch_t(const Geom& g, const void* links, const void* in, void* out
                            (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e, L.cs, bps);
     else if (tps == 7)
         hipLaunchKernelGGL((hop_multi_kernel<T, LT, 4>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
-                           (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e, L.cs, bps);
-    else if (tps == 10) {
-        const int64_t bps64 = (slice % SCG_WAVE == 0 && getenv_order()) ? slice / SCG_WAVE : 0;
-        hipLaunchKernelGGL((hop_quad_kernel<T, LT>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
-                           (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e, L.cs, bps64);
-    } else if (tps == 9) {
-        const size_t lds = plane_lds_bytes(g, vb, sizeof(cx<T>));
-        if (lds == 0 || lds > PLANE_LDS_MAX) throw std::runtime_error("stencil launch shape does not fit this lattice");
-        const int Pw = (plane_rows(g) * g.Lxh + SCG_WAVE - 1) / SCG_WAVE * SCG_WAVE;
-        if (vb == 1)
-            hipLaunchKernelGGL((hop_plane_kernel<T, LT, 1>), dim3((unsigned)grid, 1, L.nz), dim3(2 * Pw), lds, s, g, (const S*)links,
-                               (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e, L.cs, Pw);
-        else if (vb == 2)
-            hipLaunchKernelGGL((hop_plane_kernel<T, LT, 2>), dim3((unsigned)grid, 1, L.nz), dim3(2 * Pw), lds, s, g, (const S*)links,
-                               (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e, L.cs, Pw);
-        else
-            hipLaunchKernelGGL((hop_plane_kernel<T, LT, 4>), dim3((unsigned)grid, 1, L.nz), dim3(2 * Pw), lds, s, g, (const S*)links,
-                               (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e, L.cs, Pw);
-    } else if (tps == 8 && vb == 1)
-        hipLaunchKernelGGL((hop_split_kernel<T, LT, 1>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
-                           (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e, L.cs, bps);
-    else if (tps == 8 && vb == 2)
-        hipLaunchKernelGGL((hop_split_kernel<T, LT, 2>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
-                           (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e, L.cs, bps);
-    else if (tps == 8)
-        hipLaunchKernelGGL((hop_split_kernel<T, LT, 4>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,
                            (const cx<T>*)in, (cx<T>*)out, p, nvec, nsb, e, L.cs, bps);
     else if (tps == 5)
         hipLaunchKernelGGL((hop_lean_kernel<T, LT, true, 2>), dim3((unsigned)grid, 1, L.nz), dim3(SCG_BLOCK), 0, s, g, (const S*)links,

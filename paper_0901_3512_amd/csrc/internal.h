@@ -152,7 +152,7 @@ struct HopEpi {
     const double* cz_dev;  // device coefficient per vector (or NULL -> cz_host)
     int cz_negate;     // use -cz_dev[v]
     double cz_host;
-    int red;           // 0 none, 1 Re sum conj(d) * out, 2 sum |out|^2
+    int red;           // 0 none, 1 Re sum conj(d) * out, 2 sum |out|^2, 3 the CG update below
     const void* d;
     double* partials;  // [vec][nblocks_site]
     const int32_t* gate_m;  // if non-null: skip when gate_i > *gate_m
@@ -160,6 +160,10 @@ struct HopEpi {
     const int32_t* vec_map; // optional: vector slot -> stored vector index (-1: empty slot)
     const CgVec* cg;   // optional: skip vectors whose CG is done or frozen
     const double* kappa2_dev;  // optional: kappa^2 from device memory (per configuration)
+    // red 3: out (q) is not stored; instead X += a p and R -= a q with a = cg[vec].a, p = d, and the
+    // partials hold |R|^2.  X is FP64, R in the launch precision; needs cg and launch shape tps 8, 9 or 10.
+    void* X;
+    void* R;
 };
 
 // out(parity p) = H_{p,1-p} in, with the epilogue above, for nvec vectors.

@@ -150,6 +150,7 @@ struct seedcg_s {
     DBuf r64, tmap, rmap;            // FP64 start residuals; vector maps of checks and restarts
     // one CG iteration as a hipGraph per active-set width (not used while timing launches)
     bool use_graphs = true;
+    bool fuse_cg = true;    // CG update fused into the last stencil launch of q = M p (where the shape has it)
     hipStream_t cap_stream = nullptr;
     std::map<int, hipGraphExec_t> cg_graphs;
     Launch L() const { return Launch(s, ncfg, cs); }
@@ -259,12 +260,15 @@ void hop(seedcg_s* h, Prec pr, const void* L, const void* in, void* out, int par
         const double ss = (pr == P64 || pr == P64R) ? 8.0 : 4.0;
         const double lr = (pr == P64R || pr == P32R) ? 96.0 : 144.0;   // link reals per site (two rows or all)
         const double Vh = (double)h->g.Vh * h->ncfg;
-        int ops = 2 + (e.combine ? 1 : 0) + (e.z ? 1 : 0) + (e.red == 1 ? 1 : 0);
-        h->ev_bytes.push_back(Vh * lr * sl + (double)nvec * Vh * 24.0 * ss * ops);
+        // the fused CG update reads u, p, r and the FP64 x and writes r and x instead of out
+        const double per = e.red == 3 ? 5.0 * ss + 2.0 * 8.0 : ss * (2 + (e.combine ? 1 : 0) + (e.z ? 1 : 0) + (e.red == 1 ? 1 : 0));
+        h->ev_bytes.push_back(Vh * lr * sl + (double)nvec * Vh * 24.0 * per);
         h->ev_flops.push_back((double)nvec * Vh * 1320.0);
         h->ev_used++;
     }
 }
+
+int64_t nsb_for(seedcg_s* h, bool low, int nvec);
 
 struct MOpts {
     const void* z = nullptr;      // out = sy * M x + cz * z
@@ -278,7 +282,14 @@ struct MOpts {
     const int32_t* gate_m = nullptr;
     int gate_i = 0;
     const int32_t* vec_map = nullptr;
-    const CgVec* cg = nullptr;
+    CgVec* cg = nullptr;
+    // the CG step fused into M p (cg and vec_map set, red 0): |A p|^2 = p^dag M p is reduced on
+    // the second hop into partials, alpha = rr / p^dag M p is set between the hops, and the last
+    // hop applies x += alpha p, r -= alpha q without storing q, with the |r|^2 partials in rr_part
+    bool cg_fused = false;
+    void* X = nullptr;
+    void* R = nullptr;
+    double* rr_part = nullptr;
 };
 
 // out = M x for nvec vectors (M = A^dag A = gamma5 A gamma5 A), with the epilogue options on
@@ -308,7 +319,13 @@ void apply_M_int(seedcg_s* h, bool low, const void* x, void* out, int nvec, cons
     e2.apply_g5 = 1;
     e2.kappa2 = k2;
     e2.x = x;
-    hop(h, pr, L, t1, u, 0, nvec, e2, tps, vb);
+    HopEpi e2r = e2;
+    if (o.cg_fused) {
+        e2r.red = 2;
+        e2r.partials = o.partials;
+    }
+    hop(h, pr, L, t1, u, 0, nvec, e2r, tps, vb);
+    if (o.cg_fused) cg_alpha(o.cg, o.partials, nsb_for(h, low, nvec), o.vec_map, nvec, h->L(), false);
     // t1 = H_oe u
     hop(h, pr, L, u, t1, 1, nvec, e, tps, vb);
     // out = sy * gamma5 (u - kappa^2 H_eo t1) + cz z
@@ -322,7 +339,21 @@ void apply_M_int(seedcg_s* h, bool low, const void* x, void* out, int nvec, cons
     e4.red = o.red;
     e4.d = o.d;
     e4.partials = o.partials;
+    if (o.cg_fused) {
+        e4.red = 3;
+        e4.d = x;
+        e4.X = o.X;
+        e4.R = o.R;
+        e4.partials = o.rr_part;
+    }
     hop(h, pr, L, t1, out, 0, nvec, e4, tps, vb);
+}
+
+// whether the CG step can be fused into M p: launch shapes 8-10 carry that epilogue
+bool cg_fusable(const seedcg_s* h, bool low, int nvec) {
+    const bool multi = nvec > 1;
+    const int tps = low ? (multi ? h->tps_lo_multi : h->tps_lo) : (multi ? h->tps64_multi : h->tps64);
+    return h->fuse_cg && tps >= 8;
 }
 
 // y = A x or A^dag x = gamma5 A gamma5 x (FP64)
@@ -954,7 +985,7 @@ void alloc_rest(seedcg_s* h, int nrhs) {
     h->rmap.ensure(nrhs * sizeof(int32_t));
     const int64_t nsb64 = nsb_of(h, false), nsbl = nsb_of(h, lo), nb = norm2_blocks(h->N);
     h->cgpart.ensure(nrhs * std::max(nsb64, nsbl) * sizeof(double));
-    h->rrpart.ensure(nrhs * std::max(nb, nsb64) * sizeof(double));
+    h->rrpart.ensure(nrhs * std::max(nb, std::max(nsb64, nsbl)) * sizeof(double));
     h->norms.ensure(2 * nrhs * sizeof(double));
     ensure_work(h, nrhs);
 }
@@ -1087,6 +1118,21 @@ void redeflate(seedcg_s* h, void* Rw, int nrhs, const int32_t* map, int w) {
 void cg_iteration(seedcg_s* h, bool lo, bool pc, int nact, int nalloc, int64_t nb, int max_iter, void* Rw) {
     const Launch L = h->L();
     const int64_t nsbl = nsb_for(h, lo, nact);
+    if (!pc && cg_fusable(h, lo, nact)) {
+        MOpts o;
+        o.vec_map = h->vmap.as<int32_t>();
+        o.cg = h->cgv.as<CgVec>();
+        o.partials = h->cgpart.as<double>();
+        o.cg_fused = true;
+        o.X = h->Xint.p;
+        o.R = Rw;
+        o.rr_part = h->rrpart.as<double>();
+        apply_M_int(h, lo, h->Pv.p, h->Qv.p, nact, o);
+        cg_beta(h->cgv.as<CgVec>(), h->rrpart.as<double>(), nsbl, h->vmap.as<int32_t>(), nact, max_iter, L);
+        cg_p(lo, h->cgv.as<CgVec>(), h->vmap.as<int32_t>(), nact, h->Pv.p, Rw, h->N, false, L);
+        if (h->nev) deflate_step(h, false, Rw, nalloc, h->vmap.as<int32_t>(), nact, h->Pv.p, lo);
+        return;
+    }
     MOpts o;
     o.red = 1;
     o.d = h->Pv.p;
@@ -1235,6 +1281,8 @@ seedcg_status solve_rest_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report
         convert(lo, lo, Rw, h->Pv.p, nrhs * N, L);  // p = r
         if (h->nev) deflate_step(h, false, Rw, nrhs, nullptr, nrhs, h->Pv.p, lo, false);  // p = r - W mu
     }
+    // the device records carry rr_reliable too (every round trip copies them back to the host)
+    for (auto& x : cg) x.rr_reliable = x.rr;
     to_cfg(h, h->cgv.p, cg.data(), nrhs * sizeof(CgVec));
 
     const int max_iter = h->p.max_iter > 0 ? h->p.max_iter : 100000;
@@ -1246,7 +1294,6 @@ seedcg_status solve_rest_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report
     const int rel_every = lo ? std::max(1, h->p.reliable_every) : 0;
     const int G = lo ? std::min(h->sync_every, 4) : h->sync_every;
     std::vector<int> it_rel((size_t)C * nrhs, 0);
-    for (auto& x : cg) x.rr_reliable = x.rr;
     bool noconv = false;
     const bool graphs = h->use_graphs && h->timing_every == 0 && !pc;
     for (;;) {
@@ -1320,8 +1367,11 @@ seedcg_status solve_rest_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report
                 reload[c].push_back(j);
                 const bool stalled = is_rel[q] && rr >= x.rr_reliable;
                 if (x.frozen) {
-                    // the recursive residual met tol but the true one did not: go on from r = b - M x
-                    x.b = rr / x.rr;
+                    // the recursive residual (|r|^2 in pq since the freeze) met tol but the true one
+                    // did not: go on from r = b - M x with p = r + b p.  When the true residual is more
+                    // than a decade above the recursive one, the old direction belongs to a residual
+                    // that no longer exists: restart with p = r.
+                    x.b = rr <= 100.0 * x.pq ? rr / x.rr : 0.0;
                     x.frozen = 0;
                     restart[c].push_back(j);
                 } else if (stalled) {
@@ -1330,8 +1380,6 @@ seedcg_status solve_rest_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report
                     x.b = 0.0;
                     x.restarts += 1;
                     restart[c].push_back(j);
-                } else if (pc) {
-                    restart[c].push_back(j);  // z = P r changed too
                 }
                 x.rr_reliable = rr;
                 it_rel[q] = x.iters;
@@ -1346,13 +1394,12 @@ seedcg_status solve_rest_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report
             const int w = upload_map(h, h->tmap, reload);
             if (w) redeflate(h, Rw, nrhs, h->tmap.as<int32_t>(), w);
         }
-        if (pc && !restart[0].empty()) {
-            // preconditioned restart from the new residual: z = P r, p = z, rz = r^dag z
-            const std::vector<double> rz = precondition(restart[0]);
-            for (int j : restart[0]) {
-                cg[j].rz = rz[j];
-                cg[j].b = 0.0;
-            }
+        if (pc && !reload[0].empty()) {
+            // z = P r and rz = r^dag z for every replaced residual; the direction is kept (as
+            // without the preconditioner) except where it restarts with p = z
+            const std::vector<double> rz = precondition(reload[0]);
+            for (int j : reload[0]) cg[j].rz = rz[j];
+            for (int j : restart[0]) cg[j].b = 0.0;
         }
         to_cfg(h, h->cgv.p, cg.data(), nrhs * sizeof(CgVec));
         const int wr = upload_map(h, h->rmap, restart);
@@ -1412,6 +1459,7 @@ void init_geometry(seedcg_s* h, const seedcg_params* p, const int32_t* dims) {
     h->sync_every = std::max(1, env_int("SEEDCG_SYNC_EVERY", 16));
     h->debug = env_int("SEEDCG_DEBUG", 0);
     h->use_graphs = env_int("SEEDCG_GRAPHS", 1) != 0;
+    h->fuse_cg = env_int("SEEDCG_FUSE_CG", 1) != 0;
     HIPCHK(hipGetDevice(&h->device));
 }
 

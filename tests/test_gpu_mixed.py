@@ -127,3 +127,28 @@ def test_mixed_at_large_kappa_still_converges(c1):
     assert np.all(res <= 1e-10), res
     err = np.linalg.norm(x - c1["xs"], axis=1) / np.linalg.norm(c1["xs"], axis=1)
     assert np.all(err <= 1e-8), err
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 2, 6), (8, 8, 8, 8)])
+def test_mixed_cg_iterations_track_fp64(dims):
+    """Regression of the reliable updates when CG converges fast (a rough random field, kappa 0.12):
+    the decade trigger works from the first iteration on, and a true residual far above the
+    recursive one restarts the direction. Mixed CG then needs at most 1.5x FP64's iterations + 10
+    per right-hand side. Before the fix, two of five systems crawled for over 1000 iterations at a
+    frozen true residual of 3e-6."""
+    from paper_0901_3512_amd import SeedCG
+    print_case("mixed iterations vs fp64", dims)
+    rng = np.random.default_rng(11)
+    U = random_su3_links(dims, 0.4, rng)
+    op = WilsonEO(U, dims, 0.12)
+    B = rng.standard_normal((6, op.Vh, 4, 3)) + 1j * rng.standard_normal((6, op.Vh, 4, 3))
+    its = {}
+    for prec in ("fp64", "mixed"):
+        s = SeedCG(cuda(U), dims, 0.12, prec=prec, reorth_k=10)
+        X, _ = s.solve_seed(cuda(B))
+        X, rep = s.solve_rest(cuda(B), X)
+        res = np.linalg.norm(flat(B - op.apply_M(host(X))), axis=1) / np.linalg.norm(flat(B), axis=1)
+        assert np.all(res <= 1e-10), (prec, res)
+        its[prec] = rep["iters"]
+    assert all(m <= 1.5 * f + 10 for m, f in zip(its["mixed"][1:], its["fp64"][1:])), its
+    print("iterations", its)

@@ -41,7 +41,8 @@ def parse():
     ap.add_argument("--prec", default=None, help="override the workload precision (fp64|mixed|mixed_bf16)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=40, help="Lanczos steps in the oracle sample")
-    ap.add_argument("--sample-every", type=int, default=4, help="stencil launches per timed sample")
+    ap.add_argument("--sample-every", type=int, default=7,
+                    help="stencil launches per timed sample (coprime to the 4 launches of one M, so every launch kind is sampled)")
     ap.add_argument("--mbench", type=int, default=200, help="back-to-back M applications for D^dag D GB/s")
     ap.add_argument("--batch-n", type=int, default=64, help="c4: number of batch members (the workload has 64)")
     ap.add_argument("--deflate", type=int, default=0, help="deflated CG with this many Ritz vectors (0: plain CG)")

@@ -349,11 +349,12 @@ void apply_M_int(seedcg_s* h, bool low, const void* x, void* out, int nvec, cons
     hop(h, pr, L, t1, out, 0, nvec, e4, tps, vb);
 }
 
-// whether the CG step can be fused into M p: launch shapes 8-10 carry that epilogue
+// whether the CG step can be fused into M p: launch shapes 8-10 carry that epilogue, and its FP64
+// x must be addressable with 32-bit byte offsets within a vector
 bool cg_fusable(const seedcg_s* h, bool low, int nvec) {
     const bool multi = nvec > 1;
     const int tps = low ? (multi ? h->tps_lo_multi : h->tps_lo) : (multi ? h->tps64_multi : h->tps64);
-    return h->fuse_cg && tps >= 8;
+    return h->fuse_cg && tps >= 8 && (double)h->g.Vh * 12.0 * 16.0 < 4294967296.0;
 }
 
 // y = A x or A^dag x = gamma5 A gamma5 x (FP64)

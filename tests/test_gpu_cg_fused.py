@@ -57,3 +57,27 @@ def test_fused_cg_step_matches_separate_update(prec, dims, shape, monkeypatch):
     err = np.linalg.norm(flat(Xf - Xu), axis=1) / np.linalg.norm(flat(Xu), axis=1)
     assert np.all(err <= 1e-8), err
     print("fused", rf["iters"], "separate", ru["iters"])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_fused_cg_step_in_a_batch(prec, monkeypatch):
+    """A batch of four configurations in two shape classes (the configuration is one more grid
+    dimension of every launch): the fused step matches the separate update kernel, and every
+    solution meets the oracle's M."""
+    from paper_0901_3512_amd import SeedCGBatch
+    print_case("fused cg batch", prec)
+    dims = [(4, 4, 4, 4), (6, 4, 2, 6), (4, 4, 4, 4), (6, 4, 2, 6)]
+    probs = [_problem(d, nrhs=4, seed=30 + c) for c, d in enumerate(dims)]
+    out = {}
+    for fused in (True, False):
+        monkeypatch.setenv("SEEDCG_FUSE_CG", "1" if fused else "0")
+        b = SeedCGBatch([cuda(p[0]) for p in probs], dims, [p[1] for p in probs], 4, prec=prec, reorth_k=10)
+        X, reps = b.solve([cuda(p[3]) for p in probs])
+        out[fused] = ([host(x) for x in X], [r["iters"] for r in reps])
+    for c, (U, kappa, op, B) in enumerate(probs):
+        Xf, Xu = out[True][0][c], out[False][0][c]
+        res = np.linalg.norm(flat(B - op.apply_M(Xf)), axis=1) / np.linalg.norm(flat(B), axis=1)
+        assert np.all(res <= 1e-10), (c, res)
+        assert all(abs(a - b) <= 1 for a, b in zip(out[True][1][c], out[False][1][c])), (out[True][1][c], out[False][1][c])
+        err = np.linalg.norm(flat(Xf - Xu), axis=1) / np.linalg.norm(flat(Xu), axis=1)
+        assert np.all(err <= 1e-8), (c, err)

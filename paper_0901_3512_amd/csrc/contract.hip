@@ -8,8 +8,8 @@
 //
 // Split-K: a workgroup owns a K-chunk and up to 32 rows of V (two 16-row MFMA tiles) and
 // computes all 2*nr columns (up to three 16-column tiles) of its partial product, staging
-// 32 complex per row through LDS per step; the next step's staging is loaded into registers
-// while the current one is contracted.  Partials go to part[chunk][row][j] and a second
+// 32 complex per row through LDS per step; the next two steps' staging is loaded into two
+// register sets while the current one is contracted.  Partials go to part[chunk][row][j] and a second
 // kernel sums the chunks in a fixed order (deterministic).  FP64 inputs use
 // v_mfma_f64_16x16x4; FP32 inputs use v_mfma_f32_16x16x4 with FP32 accumulation.
 //
@@ -77,11 +77,15 @@ __global__ __launch_bounds__(256) void proj_kernel(const ProjArgs pa, int64_t cs
         acc1[q] = 0;
     }
 
-    // the staging of step kb + PJ_KC is loaded into registers while step kb is contracted from
-    // LDS, so the global loads overlap the matrix-core work (one complex per thread and pass)
+    // the staging of steps kb + PJ_KC and kb + 2 PJ_KC is loaded into two register sets while
+    // step kb is contracted from LDS, so two steps of global loads are always in flight behind
+    // the matrix-core work (one complex per thread and pass)
     constexpr int NVU = PJ_ROWS * PJ_KC / 256;                 // V elements per thread
     constexpr int NRU = (PJ_MAXR * PJ_KC + 255) / 256;         // R elements per thread (at most)
-    cx<TS> vreg[NVU], rreg[NRU];
+    struct Regs {
+        cx<TS> v[NVU], r[NRU];
+    };
+    Regs ra, rb;
     const TS* vrow[NVU];      // this thread's V rows (null beyond nrow) and R vectors (null beyond nr)
     const TS* rvec[NRU];
 #pragma unroll
@@ -95,36 +99,37 @@ __global__ __launch_bounds__(256) void proj_kernel(const ProjArgs pa, int64_t cs
         rvec[u] = j < nr ? (const TS*)zoff(pa.R[j], cs) : nullptr;
     }
     const int cth = threadIdx.x % PJ_KC;   // the complex index within a step (256 is a multiple of PJ_KC)
-    auto fetch = [&vreg, &rreg, &vrow, &rvec, cth, k_end](int64_t kb) {
+    auto fetch = [&vrow, &rvec, cth, k_end](Regs& g, int64_t kb) {
         const bool cok = kb + cth < k_end;
 #pragma unroll
         for (int u = 0; u < NVU; u++)
-            vreg[u] = (vrow[u] && cok) ? *(const cx<TS>*)(vrow[u] + 2 * (kb + cth)) : mk<TS>(0, 0);
+            g.v[u] = (vrow[u] && cok) ? *(const cx<TS>*)(vrow[u] + 2 * (kb + cth)) : mk<TS>(0, 0);
 #pragma unroll
         for (int u = 0; u < NRU; u++)
-            rreg[u] = (rvec[u] && cok) ? *(const cx<TS>*)(rvec[u] + 2 * (kb + cth)) : mk<TS>(0, 0);
+            g.r[u] = (rvec[u] && cok) ? *(const cx<TS>*)(rvec[u] + 2 * (kb + cth)) : mk<TS>(0, 0);
     };
-    if (k_begin < k_end) fetch(k_begin);
-    for (int64_t kb = k_begin; kb < k_end; kb += PJ_KC) {
+    // one step: the registers of step kb to LDS, the loads of step kb + 2 PJ_KC into the same
+    // registers, then the contraction of step kb
+    auto step = [&](Regs& g, int64_t kb) {
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < NVU; u++) {
             const int idx = threadIdx.x + 256 * u;
             const int r = idx / PJ_KC, c = idx % PJ_KC;
-            As[r * PJ_LD + 2 * c] = (T)vreg[u].re;
-            As[r * PJ_LD + 2 * c + 1] = (T)vreg[u].im;
+            As[r * PJ_LD + 2 * c] = (T)g.v[u].re;
+            As[r * PJ_LD + 2 * c + 1] = (T)g.v[u].im;
         }
 #pragma unroll
         for (int u = 0; u < NRU; u++) {
             const int idx = threadIdx.x + 256 * u;
             const int j = idx / PJ_KC, c = idx % PJ_KC;
             if (j < nr) {
-                Bs[j * PJ_LD + 2 * c] = (T)rreg[u].re;
-                Bs[j * PJ_LD + 2 * c + 1] = (T)rreg[u].im;
+                Bs[j * PJ_LD + 2 * c] = (T)g.r[u].re;
+                Bs[j * PJ_LD + 2 * c + 1] = (T)g.r[u].im;
             }
         }
         __syncthreads();
-        if (kb + PJ_KC < k_end) fetch(kb + PJ_KC);
+        if (kb + 2 * PJ_KC < k_end) fetch(g, kb + 2 * PJ_KC);
         // this wave's output tiles: wave, wave + 4 (at most 6 tiles)
         for (int tsel = 0; tsel < 2; tsel++) {
             const int tile = wave + 4 * tsel;
@@ -153,6 +158,12 @@ __global__ __launch_bounds__(256) void proj_kernel(const ProjArgs pa, int64_t cs
             else
                 acc1 = acc;
         }
+    };
+    if (k_begin < k_end) fetch(ra, k_begin);
+    if (k_begin + PJ_KC < k_end) fetch(rb, k_begin + PJ_KC);
+    for (int64_t kb = k_begin; kb < k_end; kb += 2 * PJ_KC) {
+        step(ra, kb);
+        if (kb + PJ_KC < k_end) step(rb, kb + PJ_KC);
     }
 
     // write the partial tiles: part[chunk][row][j] complex (FP64)

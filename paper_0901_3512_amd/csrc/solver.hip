@@ -1366,7 +1366,11 @@ seedcg_status solve_rest_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report
                     continue;
                 }
                 reload[c].push_back(j);
-                const bool stalled = is_rel[q] && rr >= x.rr_reliable;
+                // no decrease of the true residual since the previous replacement, while the recursive
+                // residual (x.rr) has run more than a decade below it: the inner operator is too far
+                // from M for the old directions.  (Without that gap the stall is CG's own plateau,
+                // which a restart would only prolong.)
+                const bool stalled = is_rel[q] && rr >= x.rr_reliable && rr > 100.0 * x.rr;
                 if (x.frozen) {
                     // the recursive residual (|r|^2 in pq since the freeze) met tol but the true one
                     // did not: go on from r = b - M x with p = r + b p.  When the true residual is more
@@ -1376,8 +1380,7 @@ seedcg_status solve_rest_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report
                     x.frozen = 0;
                     restart[c].push_back(j);
                 } else if (stalled) {
-                    // no decrease of the true residual since the previous replacement: the inner
-                    // operator is too far from M for the old directions; restart with p = r
+                    // restart with p = r
                     x.b = 0.0;
                     x.restarts += 1;
                     restart[c].push_back(j);

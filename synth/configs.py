@@ -11,7 +11,7 @@ from dataclasses import dataclass, field, replace
 
 import numpy as np
 
-from .links import random_su3_links, ape_smear
+from .links import random_su3_links, ape_smear, flux_background
 from .sources import point_sources, gaussian_sources, z2_sources
 
 _KAPPA_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "kappa.json")
@@ -36,6 +36,7 @@ class SolverConfig:
     reliable_every: int = 50
     t_bc: int = -1             # antiperiodic in t
     kappa_override: float = None
+    flux: tuple = None         # (n01, n23): links times a constant-flux background of that charge
     notes: str = ""
 
     @property
@@ -54,6 +55,11 @@ CONFIGS = {
     # 16^3 x 32, eps = 0.5 smeared by 2 APE steps (alpha 0.5), ratio 1e-5, 12 point sources, k = 20.
     "c2": SolverConfig("c2", (16, 16, 16, 32), 0.5, 1e-5, 0x5EED01, ape_steps=2, ape_alpha=0.5,
                        sources=(("point", 12),), reorth_k=20),
+    # The 16^3 x 32 workload on a topological background: the same links times one flux quantum
+    # through the (x, y) and the (z, t) planes, so that the operator has a few near-zero modes apart
+    # from the rest of its spectrum and the ratio 1e-5 becomes reachable near the critical kappa.
+    "c2t": SolverConfig("c2t", (16, 16, 16, 32), 0.5, 1e-5, 0x5EED01, ape_steps=2, ape_alpha=0.5,
+                        sources=(("point", 12),), reorth_k=20, flux=(1, 1)),
     # 24^3 x 48, eps = 0.3, ratio 1e-5, 12 point + 12 Z2 sources, mixed precision with BF16 links.
     "c3": SolverConfig("c3", (24, 24, 24, 48), 0.3, 1e-5, 0x5EED02,
                        sources=(("point", 12), ("z2", 12)), reorth_k=10, prec="mixed_bf16"),
@@ -113,6 +119,8 @@ def make_links(cfg):
     U = random_su3_links(cfg.dims, cfg.eps, rng)
     if cfg.ape_steps:
         U = ape_smear(U, cfg.dims, cfg.ape_alpha, cfg.ape_steps)
+    if cfg.flux:
+        U = flux_background(cfg.dims, *cfg.flux) @ U
     return U
 
 

@@ -1,8 +1,12 @@
-"""Random SU(3) gauge links, APE smearing and the plaquette diagnostic.
+"""Random SU(3) gauge links, APE smearing, a topological flux background and the plaquette diagnostic.
 
 Links are U = exp(i*eps*H) with H a random traceless Hermitian 3x3 matrix whose
 entries come from complex Gaussians; APE smearing mixes each link with its six
-staples and projects back onto SU(3).  Both are input generation only.
+staples and projects back onto SU(3).  The flux background is a constant abelian field
+strength with whole flux quanta through the (x, y) and (z, t) planes of the torus, embedded in
+SU(3) as diag(e^{i q_c phi}) with charges q = (1, 1, -2); its topological charge makes the Dirac
+operator carry near-zero modes that stand apart from the rest of the spectrum.  All of it is
+input generation only.
 """
 import numpy as np
 
@@ -92,6 +96,35 @@ def ape_smear(U, dims, alpha, steps):
             new[mu] = project_su3((1.0 - alpha) * U5[mu] + (alpha / 6.0) * S)
         U5 = new
     return U5.reshape(U.shape)
+
+
+def flux_background(dims, n01, n23, charges=(1, 1, -2)):
+    """A constant field strength on the torus, as SU(3) links (4, V, 3, 3).
+
+    In the (x, y) plane the phase per plaquette is theta = 2 pi n01 / (Lx Ly) (Landau gauge):
+    the y link at x carries theta * x, and the x link leaving the last x-slice, x = Lx - 1, carries
+    -theta * Lx * y, so that every plaquette, the wrapped ones included, carries theta and the
+    plane holds n01 flux quanta.  The (z, t) plane is built the same way from z and t with n23.
+    Every other plaquette is 1.  Colour c sees the phase times charges[c] (the charges sum to
+    zero, so each link has unit determinant).
+    """
+    Lx, Ly, Lz, Lt = (int(d) for d in dims)
+    t, z, y, x = np.meshgrid(np.arange(Lt), np.arange(Lz), np.arange(Ly), np.arange(Lx), indexing="ij")
+    th01 = 2.0 * np.pi * n01 / (Lx * Ly)
+    th23 = 2.0 * np.pi * n23 / (Lz * Lt)
+    phase = np.zeros((4, Lt, Lz, Ly, Lx))
+    phase[0] = np.where(x == Lx - 1, -th01 * Lx * y, 0.0)
+    phase[1] = th01 * x
+    phase[2] = np.where(z == Lz - 1, -th23 * Lz * t, 0.0)
+    phase[3] = th23 * z
+    q = np.asarray(charges, dtype=np.float64)
+    if abs(q.sum()) > 0:
+        raise ValueError("the charges must sum to zero (unit determinant)")
+    U = np.zeros((4, Lt * Lz * Ly * Lx, 3, 3), dtype=np.complex128)
+    ph = phase.reshape(4, -1)
+    for c in range(3):
+        U[:, :, c, c] = np.exp(1j * q[c] * ph)
+    return U
 
 
 def plaquette(U, dims):

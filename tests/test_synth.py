@@ -1,5 +1,6 @@
 """Input generators: SU(3) links, APE smearing, sources, reproducibility (CPU only)."""
 import numpy as np
+import pytest
 
 from synth import ape_smear, gaussian_sources, plaquette, point_sources, random_su3_links, z2_sources
 from synth.configs import CONFIGS, batch_members, make_inputs
@@ -54,3 +55,41 @@ def test_workloads():
     assert all(1e-4 <= c.ratio <= 1e-3 for c in m)
     U, phi, kappa = make_inputs("c1")
     assert phi.shape == (4, 128, 4, 3) and 0.7 < kappa < 0.9
+
+
+def test_flux_background_plaquettes_and_flux_quanta():
+    """Every (x, y) plaquette carries 2 pi n01 / (Lx Ly) per unit charge and every (z, t) one
+    2 pi n23 / (Lz Lt), the wrapped ones included; the other planes carry none; so each (x, y)
+    slice holds exactly n01 flux quanta and each (z, t) slice n23.  Links are special unitary."""
+    from synth.links import _as5, _axis, _dag, flux_background
+    dims = (4, 6, 4, 8)
+    n01, n23 = 1, 2
+    U = flux_background(dims, n01, n23)
+    eye = np.eye(3)
+    assert np.allclose(U @ _dag(U), eye, atol=1e-14)
+    assert np.allclose(np.linalg.det(U), 1.0, atol=1e-14)
+    U5 = _as5(U, dims)
+    want = {(0, 1): 2 * np.pi * n01 / (4 * 6), (2, 3): 2 * np.pi * n23 / (4 * 8)}
+    for mu in range(4):
+        for nu in range(mu + 1, 4):
+            P = (U5[mu] @ np.roll(U5[nu], -1, axis=_axis(mu)) @ _dag(np.roll(U5[mu], -1, axis=_axis(nu)))
+                 @ _dag(U5[nu]))
+            th = want.get((mu, nu), 0.0)
+            for c, q in enumerate((1, 1, -2)):
+                assert np.allclose(P[..., c, c], np.exp(1j * q * th), atol=1e-12), (mu, nu, c)
+            assert np.allclose(P * (1 - np.eye(3)), 0, atol=1e-14)   # diagonal: an abelian field
+    # flux quanta per slice: the plaquette angles of colour 0 summed over one (x, y) slice
+    P01 = (U5[0] @ np.roll(U5[1], -1, axis=_axis(0)) @ _dag(np.roll(U5[0], -1, axis=_axis(1))) @ _dag(U5[1]))
+    assert abs(np.angle(P01[0, 0, :, :, 0, 0]).sum() / (2 * np.pi) - n01) < 1e-12
+
+
+def test_flux_background_workload_keeps_the_base_links_and_charges_must_cancel():
+    from dataclasses import replace
+
+    from synth.configs import make_links
+    from synth.links import flux_background
+    base = make_links(CONFIGS["c1"])
+    with_flux = make_links(replace(CONFIGS["c1"], flux=(1, 1)))
+    assert np.allclose(with_flux, flux_background((4, 4, 4, 4), 1, 1) @ base, atol=0)
+    with pytest.raises(ValueError):
+        flux_background((4, 4, 4, 4), 1, 1, charges=(1, 1, 1))

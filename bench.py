@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--config", default="c2", help="c2 (default), c4 (the batch), or one batch member c4_00 ... c4_63")
     ap.add_argument("--prec", default=None, help="override the workload precision (fp64|mixed|mixed_bf16)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=40, help="Lanczos steps in the oracle sample")
@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--learned", action="store_true", help="compare also the learned preconditioner (2000 Adam steps)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 1 GiB device copy first (reference for the HBM byte counters)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the benchmark line: the cost of RHS 1 and the CG iterations of RHS 2 against the "
+                         "reorthogonalisation frequency k and the past-convergence factor (FP64, two right-hand sides)")
     return ap.parse_args()
 
 
@@ -71,7 +74,11 @@ def main():
 
     if args.config == "c4":
         return bench_batch(args)   # generates its inputs in worker processes before any GPU call
-    cfg = CONFIGS[args.config]
+    if args.config.startswith("c4_"):   # one member of the batched workload on its own
+        from synth.configs import batch_members
+        cfg = {m.name: m for m in batch_members()}[args.config]
+    else:
+        cfg = CONFIGS[args.config]
     prec = args.prec or cfg.prec
     dev = torch.device("cuda:0")
     t_gen = time.time()
@@ -84,6 +91,8 @@ def main():
     solver = SeedCG(Ud, cfg.dims, kappa, t_bc=cfg.t_bc, prec=prec, reorth_k=cfg.reorth_k, past=cfg.past,
                     tol=cfg.tol, reliable_every=cfg.reliable_every, deflate=args.deflate)
     B = solver.apply_A(phid, dagger=True)   # b = A^dag phi (input preparation, not timed)
+    if args.sweep:
+        return sweep(cfg, Ud, kappa, B)
     nrhs = B.shape[0]
     torch.cuda.synchronize()
 
@@ -185,7 +194,8 @@ def main():
 
 def compare_forms(args, cfg, Ud, kappa, B, value_ref, prec_ref, phid):
     """The same lattice and right-hand sides solved by the other forms of the method, timed the same
-    way (1 warmup, then args.steps solves): traditional repeated seeding; in FP64, the indefinite
+    way (1 warmup, then args.steps solves): traditional repeated seeding; batched plain CG from zero
+    on every right-hand side (no seeding); in FP64, the indefinite
     formulation (A x = phi through gamma5 A, seeded with the QR of the Lanczos matrix, finished by
     MINRES; its residual is that of A x = phi, and the normal-equation residual of its solutions is
     reported beside it); mixed precision, and with --learned the learned K + mixed (training on the
@@ -208,6 +218,21 @@ def compare_forms(args, cfg, Ud, kappa, B, value_ref, prec_ref, phid):
     v = solved / (time.perf_counter() - t0)
     out["repeated_seeding_" + prec_ref] = {"rhs_per_s": v, "vs_reference": v / value_ref, "iters": rr["iters"]}
     log(f"compare repeated seeding: {v:.2f} RHS/s ({v / value_ref:.2f}x)")
+    s.close()
+    # no seeding at all: batched CG on every right-hand side from x0 = 0 (what the method must beat)
+    s = SeedCG(Ud, cfg.dims, kappa, t_bc=cfg.t_bc, prec=prec_ref, reorth_k=cfg.reorth_k, tol=cfg.tol,
+               reliable_every=cfg.reliable_every)
+    s.solve_rest(B, torch.zeros_like(B))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solved = 0
+    for _ in range(args.steps):
+        _, rr = s.solve_rest(B, torch.zeros_like(B))
+        solved += sum(1 for r in rr["true_relres"] if r <= cfg.tol)
+    torch.cuda.synchronize()
+    v = solved / (time.perf_counter() - t0)
+    out["plain_cg_" + prec_ref] = {"rhs_per_s": v, "vs_reference": v / value_ref, "iters": rr["iters"]}
+    log(f"compare plain CG from zero: {v:.2f} RHS/s ({v / value_ref:.2f}x)")
     s.close()
     if prec_ref == "fp64":
         s = SeedCG(Ud, cfg.dims, kappa, t_bc=cfg.t_bc, prec="fp64", reorth_k=cfg.reorth_k, past=cfg.past, tol=cfg.tol)
@@ -260,6 +285,49 @@ def compare_forms(args, cfg, Ud, kappa, B, value_ref, prec_ref, phid):
         log(f"compare {key}: {v:.2f} RHS/s ({v / value_ref:.2f}x)")
         s.close()
     return out
+
+
+def sweep(cfg, Ud, kappa, B):
+    """The trade-offs of the first right-hand side, with one extra right-hand side as in the paper's
+    own test (Table 1: time of RHS 1 against k; Figures 1-2: CG of RHS 2 against m and k).
+    For every setting: one untimed solve, then solve_seed timed on RHS 1 (Lanczos past convergence,
+    reorthogonalisation, seeding of RHS 2), then CG on RHS 2 from its seeded guess.  Standard CG
+    on RHS 2 from zero is the reference."""
+    import torch
+    from paper_0901_3512_amd import SeedCG
+    B2 = B[:2].contiguous()
+
+    def make(k, past):
+        return SeedCG(Ud, cfg.dims, kappa, t_bc=cfg.t_bc, prec="fp64", reorth_k=k, past=past, tol=cfg.tol)
+
+    s = make(cfg.reorth_k, cfg.past)
+    _, rr = s.solve_rest(B2[1:], torch.zeros_like(B2[1:]))
+    std = rr["iters"][0]
+    del s
+
+    def one(k, past):
+        s = make(k, past)
+        X, _ = s.solve_seed(B2, torch.zeros_like(B2))
+        s.solve_rest(B2, X)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X, rs = s.solve_seed(B2, torch.zeros_like(B2))
+        torch.cuda.synchronize()
+        t_seed = time.perf_counter() - t0
+        X, rr = s.solve_rest(B2, X)
+        out = {"k": k, "past": past, "m": rs["m"], "i_conv": rs["i_conv"], "seed_status": rs["seed_status"],
+               "reorth_passes": rs["reorth_passes"], "t_rhs1_ms": t_seed * 1e3, "rhs1_cg_after": rr["iters"][0],
+               "rhs2_cg_iters": rr["iters"][1], "rhs2_vs_standard": rr["iters"][1] / std,
+               "max_true_relres": max(rr["true_relres"])}
+        log(json.dumps(out))
+        return out
+
+    ks = [one(k, cfg.past) for k in (10, 20, 50, 100, 200, 250, 0)]
+    pasts = [one(cfg.reorth_k, p) for p in (1.0, 1.2, 1.4, 1.6, 2.0)]
+    print(json.dumps({"metric": "RHS-1 cost and RHS-2 CG iterations vs reorthogonalisation frequency k and past factor",
+                      "config": {"workload": f"Seed-CG fp64 on {'x'.join(map(str, cfg.dims))}, 2 RHS, tol {cfg.tol}",
+                                 "kappa": kappa},
+                      "standard_cg_iters_rhs2": std, "k_sweep": ks, "past_sweep": pasts}))
 
 
 def copy_rate():

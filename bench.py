@@ -198,12 +198,13 @@ def compare_forms(args, cfg, Ud, kappa, B, value_ref, prec_ref, phid):
     on every right-hand side (no seeding); in FP64, the indefinite
     formulation (A x = phi through gamma5 A, seeded with the QR of the Lanczos matrix, finished by
     MINRES; its residual is that of A x = phi, and the normal-equation residual of its solutions is
-    reported beside it); mixed precision, and with --learned the learned K + mixed (training on the
+    reported beside it); mixed precision (FP32 basis and CG), FP64 Lanczos with FP32 CG, and with
+    --learned the learned K + mixed (training on the
     seed solve's Ritz and basis vectors is part of every step)."""
     import torch
     from paper_0901_3512_amd import SeedCG
     out = {"reference": {"form": prec_ref, "rhs_per_s": value_ref}}
-    forms = [("mixed", False)] + ([("mixed", True)] if args.learned else [])
+    forms = [("mixed", False), ("mixed_cg", False)] + ([("mixed", True)] if args.learned else [])
     # the paper's comparison: traditional repeated seeding (each system's own Lanczos to convergence)
     s = SeedCG(Ud, cfg.dims, kappa, t_bc=cfg.t_bc, prec=prec_ref, reorth_k=cfg.reorth_k, tol=cfg.tol,
                reliable_every=cfg.reliable_every)

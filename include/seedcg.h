@@ -52,7 +52,12 @@ typedef enum {
 typedef enum {
     SEEDCG_FP64 = 0,                 /* all vectors, links and arithmetic in FP64            */
     SEEDCG_MIXED_FP32 = 1,           /* FP32 stencil/basis/CG, FP64 reliable updates         */
-    SEEDCG_MIXED_FP32_BF16LINKS = 2  /* as MIXED_FP32 with the sloppy links stored as BF16   */
+    SEEDCG_MIXED_FP32_BF16LINKS = 2, /* as MIXED_FP32 with the sloppy links stored as BF16   */
+    SEEDCG_MIXED_FP32_CG = 3         /* FP64 Lanczos, basis and seeding (Algorithm 1 as in
+                                        FP64); FP32 stencil and CG with FP64 reliable updates.
+                                        For operators with near-zero modes, where an FP32
+                                        basis loses the seeding gain. Single handles only;
+                                        no deflation or learned preconditioner.             */
 } seedcg_prec;
 
 typedef struct {

@@ -126,7 +126,8 @@ struct seedcg_s {
     bool own_stream = false;  // batch classes run on a stream of their own
     int device = 0;
     std::string err;
-    bool lo = false;        // FP32 inner vectors (mixed precision)
+    bool lo = false;        // FP32 Lanczos basis and seeding (mixed precision)
+    bool cg_lo = false;     // FP32 CG with FP64 reliable updates (every mixed mode; lo implies it)
     Prec lo_prec = P64;     // precision of the inner stencil
     int64_t N = 0;          // complex per vector
     int tps64 = 3, tps_lo = 3;
@@ -234,7 +235,7 @@ void ensure_work(seedcg_s* h, int nvec) {
     h->t1_64.ensure(n * h->vec_bytes(false));
     h->u_64.ensure(n * h->vec_bytes(false));
     h->g5buf.ensure(n * h->vec_bytes(false));
-    if (h->lo) {
+    if (h->cg_lo) {
         h->t1_lo.ensure(n * h->vec_bytes(true));
         h->u_lo.ensure(n * h->vec_bytes(true));
     }
@@ -973,7 +974,7 @@ int64_t true_residual(seedcg_s* h, const std::vector<std::vector<int>>& vecs, vo
 }
 
 void alloc_rest(seedcg_s* h, int nrhs) {
-    const bool lo = h->lo;
+    const bool lo = h->cg_lo;
     h->Bint.ensure(nrhs * h->vec_bytes(false));
     h->Xint.ensure(nrhs * h->vec_bytes(false));
     h->R64.ensure(nrhs * h->vec_bytes(false));
@@ -1195,7 +1196,7 @@ hipGraphExec_t cg_graph(seedcg_s* h, bool lo, int nact, int nalloc, int64_t nb, 
 seedcg_status solve_rest_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report* rep) {
     if (nrhs < 1) throw ArgError{"solve_rest: nrhs < 1"};
     const double t0 = now_s();
-    const bool lo = h->lo;
+    const bool lo = h->cg_lo;
     const int64_t N = h->N;
     const int C = h->ncfg;
     const Launch L = h->L();
@@ -1445,8 +1446,9 @@ void init_geometry(seedcg_s* h, const seedcg_params* p, const int32_t* dims) {
     g.Vh = g.V / 2;
     g.t_bc = p->t_bc;
     h->N = 12 * g.Vh;
-    h->lo = p->prec != SEEDCG_FP64;
-    h->lo_prec = p->prec == SEEDCG_MIXED_FP32 ? P32 : (p->prec == SEEDCG_MIXED_FP32_BF16LINKS ? P32BF : P64);
+    h->lo = p->prec == SEEDCG_MIXED_FP32 || p->prec == SEEDCG_MIXED_FP32_BF16LINKS;
+    h->cg_lo = p->prec != SEEDCG_FP64;
+    h->lo_prec = p->prec == SEEDCG_MIXED_FP32_BF16LINKS ? P32BF : (h->cg_lo ? P32 : P64);
     // default stencil launch shape: 8 = forward and backward hops on separate wavefronts, one vector
     // per workgroup (the autotuner may pick another); the vectors of a site block run as adjacent
     // workgroups on one XCD
@@ -1577,13 +1579,14 @@ void tune_shape(seedcg_s* h, bool low, int nvec, const void* x, void* y) {
 // Tunes the inner-precision shapes of a single-configuration handle on scratch vectors.
 void autotune_single(seedcg_s* h, int nvec_multi) {
     if (!h->p.autotune || env_shape_fixed()) return;
-    const bool low = h->lo;
+    // one vector in the Lanczos precision, several in the CG precision
+    const bool low = h->cg_lo;
     DBuf x, y;
-    x.ensure(nvec_multi * h->vec_bytes(low));
-    y.ensure(nvec_multi * h->vec_bytes(low));
+    x.ensure(nvec_multi * h->vec_bytes(false));   // large enough for either precision
+    y.ensure(nvec_multi * h->vec_bytes(false));
     ensure_work(h, nvec_multi);
-    cfg_zero(x.p, nvec_multi * h->vec_bytes(low), h->L());
-    tune_shape(h, low, 1, x.p, y.p);
+    cfg_zero(x.p, nvec_multi * h->vec_bytes(false), h->L());
+    tune_shape(h, h->lo, 1, x.p, y.p);
     tune_shape(h, low, nvec_multi, x.p, y.p);
     if (low) {   // the FP64 stencil of the true residuals and reliable updates (several vectors)
         x.ensure(nvec_multi * h->vec_bytes(false));
@@ -1604,7 +1607,7 @@ size_t plan_layout(seedcg_s* h, int nrhs, int m_cap, std::vector<std::pair<DBuf*
     h->work_vecs = 0;
     try {
         h->links64.ensure(4 * h->g.V * 9 * 16);
-        if (h->lo) h->links_lo.ensure(4 * h->g.V * 9 * (h->lo_prec == P32 ? 8 : 4));
+        if (h->cg_lo) h->links_lo.ensure(4 * h->g.V * 9 * (h->lo_prec == P32 ? 8 : 4));
         if (h->hop64 == P64R) h->links64r.ensure(4 * h->g.V * 6 * 16);
         if (h->hop_lo == P32R) h->links_lor.ensure(4 * h->g.V * 6 * 8);
         h->kap2.ensure(sizeof(double));
@@ -2170,7 +2173,9 @@ seedcg_status seedcg_create(const seedcg_params* p, const double* links, seedcg_
     for (int d = 0; d < 4; d++)
         if (p->dims[d] < 2 || p->dims[d] % 2) return fail(nullptr, SEEDCG_ERR_ARG, "create: every extent must be even and >= 2");
     if (p->t_bc != 1 && p->t_bc != -1) return fail(nullptr, SEEDCG_ERR_ARG, "create: t_bc must be +1 or -1");
-    if (p->prec < 0 || p->prec > 2) return fail(nullptr, SEEDCG_ERR_ARG, "create: unknown precision");
+    if (p->prec < 0 || p->prec > 3) return fail(nullptr, SEEDCG_ERR_ARG, "create: unknown precision");
+    if (p->prec == SEEDCG_MIXED_FP32_CG && (p->deflate > 0 || p->precond != 0))
+        return fail(nullptr, SEEDCG_ERR_ARG, "create: MIXED_FP32_CG takes neither deflation nor the learned preconditioner");
     if (!(p->tol > 0.0)) return fail(nullptr, SEEDCG_ERR_ARG, "create: tol must be > 0");
     if (p->reorth_k < 0) return fail(nullptr, SEEDCG_ERR_ARG, "create: reorth_k must be >= 0");
     seedcg_s* h = new (std::nothrow) seedcg_s;
@@ -2181,7 +2186,7 @@ seedcg_status seedcg_create(const seedcg_params* p, const double* links, seedcg_
         const Geom& g = h->g;
         h->links64.ensure(4 * g.V * 9 * 16);
         pack_links(P64, g, links, h->links64.p, h->s);
-        if (h->lo) {
+        if (h->cg_lo) {
             h->links_lo.ensure(4 * g.V * 9 * (h->lo_prec == P32 ? 8 : 4));
             pack_links(h->lo_prec, g, links, h->links_lo.p, h->s);
         }
@@ -2223,7 +2228,7 @@ seedcg_status seedcg_create_batch(int32_t ncfg, const int32_t* dims, const doubl
         if (!(kappa[c] > 0.0)) return fail(nullptr, SEEDCG_ERR_ARG, "create_batch: kappa must be > 0");
     }
     if (p->t_bc != 1 && p->t_bc != -1) return fail(nullptr, SEEDCG_ERR_ARG, "create_batch: t_bc must be +1 or -1");
-    if (p->prec < 0 || p->prec > 2) return fail(nullptr, SEEDCG_ERR_ARG, "create_batch: unknown precision");
+    if (p->prec < 0 || p->prec > 2) return fail(nullptr, SEEDCG_ERR_ARG, "create_batch: unknown precision (MIXED_FP32_CG is per configuration)");
     if (!(p->tol > 0.0)) return fail(nullptr, SEEDCG_ERR_ARG, "create_batch: tol must be > 0");
     if (p->reorth_k < 0) return fail(nullptr, SEEDCG_ERR_ARG, "create_batch: reorth_k must be >= 0");
     if (p->precond != 0) return fail(nullptr, SEEDCG_ERR_ARG, "create_batch: the learned preconditioner is per configuration");
@@ -2490,11 +2495,12 @@ seedcg_status seedcg_apply_M_inner(seedcg_t h, const double* x, double* y, int32
         if (!x || !y || nvec < 1) throw ArgError{"apply_M_inner: null pointer or nvec < 1"};
         if (x == y) throw ArgError{"apply_M_inner: x and y alias"};
         DBuf xi, yi;
-        xi.ensure(nvec * h->vec_bytes(h->lo));
-        yi.ensure(nvec * h->vec_bytes(h->lo));
-        pack_vec(h->lo, x, xi.p, h->g.Vh, nvec, h->s);
-        apply_M_int(h, h->lo, xi.p, yi.p, nvec, MOpts{});
-        unpack_vec(h->lo, yi.p, y, h->g.Vh, nvec, h->s);
+        const bool lo = h->cg_lo;   // the CG's operator (the Lanczos one differs only in MIXED_FP32_CG)
+        xi.ensure(nvec * h->vec_bytes(lo));
+        yi.ensure(nvec * h->vec_bytes(lo));
+        pack_vec(lo, x, xi.p, h->g.Vh, nvec, h->s);
+        apply_M_int(h, lo, xi.p, yi.p, nvec, MOpts{});
+        unpack_vec(lo, yi.p, y, h->g.Vh, nvec, h->s);
         check_launch();
         HIPCHK(hipStreamSynchronize(h->s));
         return SEEDCG_OK;
@@ -2740,6 +2746,7 @@ seedcg_status seedcg_train_precond(seedcg_t h, int32_t steps, int32_t n_ritz, in
     // out[0..5]: initial loss, final loss, seconds, Ritz vectors, training vectors, accepted
     if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "train_precond: null handle");
     return guarded(h, [&]() -> seedcg_status {
+        if (h->cg_lo && !h->lo) throw StateError{"train_precond: not with MIXED_FP32_CG"};
         train_precond_impl(h, steps, n_ritz, n_lanczos, lr);
         if (out) {
             out[0] = h->k_loss0;
@@ -2757,6 +2764,7 @@ seedcg_status seedcg_use_precond(seedcg_t h, int32_t on) {
     if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "use_precond: null handle");
     return guarded(h, [&]() -> seedcg_status {
         if (on && !h->k_ready) throw StateError{"use_precond: the preconditioner has no weights"};
+        if (on && h->cg_lo && !h->lo) throw StateError{"use_precond: not with MIXED_FP32_CG"};
         h->p.precond = on ? 1 : 0;
         return SEEDCG_OK;
     });

@@ -12,8 +12,9 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libseedcg.so")
 
-FP64, MIXED_FP32, MIXED_FP32_BF16LINKS = 0, 1, 2
-_PREC = {"fp64": FP64, "mixed": MIXED_FP32, "mixed_fp32": MIXED_FP32, "mixed_bf16": MIXED_FP32_BF16LINKS}
+FP64, MIXED_FP32, MIXED_FP32_BF16LINKS, MIXED_FP32_CG = 0, 1, 2, 3
+_PREC = {"fp64": FP64, "mixed": MIXED_FP32, "mixed_fp32": MIXED_FP32, "mixed_bf16": MIXED_FP32_BF16LINKS,
+         "mixed_cg": MIXED_FP32_CG}
 STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_OOM", -3: "ERR_HIP", -4: "ERR_BREAKDOWN", -5: "ERR_NOCONV",
           -6: "ERR_STATE"}
 SEED_STATUS = {0: "ok", 1: "breakdown", 2: "indefinite", 3: "capped"}

@@ -110,9 +110,10 @@ seedcg_status seedcg_create(const seedcg_params* p, const double* links, seedcg_
 /* y = M x for nvec even-site vectors (section 3: M = A^dag A).  x and y may not alias. */
 seedcg_status seedcg_apply_M(seedcg_t h, const double* x, double* y, int32_t nvec);
 
-/* y = M x with the inner operator the solver iterates with: FP64 for SEEDCG_FP64; FP32 vectors
-   and arithmetic with FP32 or BF16-rounded links for the mixed precisions (x is rounded to FP32
-   on entry, y is returned widened to FP64).  Same layouts and rules as seedcg_apply_M. */
+/* y = M x with the inner operator the CG iterates with: FP64 for SEEDCG_FP64; FP32 vectors
+   and arithmetic with FP32 or BF16-rounded links for the mixed precisions, MIXED_FP32_CG
+   included (x is rounded to FP32 on entry, y is returned widened to FP64).  Same layouts and
+   rules as seedcg_apply_M. */
 seedcg_status seedcg_apply_M_inner(seedcg_t h, const double* x, double* y, int32_t nvec);
 
 /* y = A x (dagger = 0) or y = A^dag x (dagger = 1), A = 1 - kappa^2 H_eo H_oe (section 3);

@@ -11,6 +11,10 @@ oracle's search, 12 point sources, plain FP64 Seed-CG with k = 20.
 --config c4: the batched workload instead, 64 configurations of lattice sizes drawn from
 {8^4, 8^3 x 16, 12^3 x 24, 12^4}, 12 point sources each, mixed precision, every configuration
 solved by one batch call per step (value = right-hand sides solved per second over the batch).
+--config c2t: the 16^3 x 32 workload on a topological flux background (near-zero modes apart
+from the bulk); --config c4_NN: one member of the batch on its own.
+--sweep: instead of the benchmark line, RHS 1's cost and RHS 2's CG iterations against the
+reorthogonalisation frequency k and the past-convergence factor (one JSON line).
 
 Prints one JSON line (see the `result` dict at the end).
 """

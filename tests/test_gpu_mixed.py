@@ -33,7 +33,7 @@ def round_bf16(a):
     return _bf16(a.real) + 1j * _bf16(a.imag)
 
 
-@pytest.mark.parametrize("prec,rounder", [("mixed", round_fp32), ("mixed_bf16", round_bf16)])
+@pytest.mark.parametrize("prec,rounder", [("mixed", round_fp32), ("mixed_bf16", round_bf16), ("mixed_cg", round_fp32)])
 @pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 2, 6), (8, 8, 8, 16), (32, 34, 2, 2)])
 @pytest.mark.parametrize("shape", [("3", "1"), ("6", "1"), ("7", "2"), ("7", "4"), ("8", "1"), ("8", "2"), ("8", "4"),
                                    ("9", "1"), ("9", "2"), ("9", "4"), ("10", "1")])
@@ -191,3 +191,11 @@ def test_mixed_cg_mode_keeps_the_seeding_gain():
     s = SeedCG(cuda(U), cfg.dims, 0.17, prec="mixed_cg")
     with pytest.raises(SeedCGError):
         s.train_precond(steps=1)
+    # the other solvers of the handle: repeated seeding (FP64 Lanczos per system, FP32 CG). Its
+    # stop is the 1e-10 residual, and here cond(M) = 2.3e4, so the forward error may reach
+    # cond x 1e-10 = 2.3e-6 (3.9e-8 measured for one system).
+    X, rr = s.solve_repeated(cuda(B))
+    res = np.linalg.norm(flat(B - op.apply_M(host(X))), axis=1) / np.linalg.norm(flat(B), axis=1)
+    assert np.all(res <= 1e-10), res
+    err = np.linalg.norm(flat(host(X)) - xs, axis=1) / np.linalg.norm(xs, axis=1)
+    assert np.all(err <= 2.3e4 * 1e-10), err

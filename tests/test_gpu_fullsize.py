@@ -80,3 +80,38 @@ def test_32x64_learned_mixed():
     res = _sampled_relres(op, B, host(X), [1, 11])
     assert np.all(res <= 1e-10), res
     print("c5 size: m", rs["m"], "training", tr, "iters", rr["iters"], "oracle relres", res)
+
+
+@pytest.fixture(scope="module")
+def topological():
+    from synth.configs import make_inputs
+    cfg = CONFIGS["c2t"]
+    U, phi, kappa = make_inputs(cfg)
+    op = WilsonEO(U, cfg.dims, kappa)
+    B = op.apply_Adag(phi)
+    print_case("topological workload: the oracle's CG from zero (about 40 s on the host)")
+    cold = osc.cg(matvec_M(op), flat(B[1:2])[0], None, tol=1e-10)[1]
+    return cfg, U, kappa, op, B, cold
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_cg"])
+def test_16x32_topological_workload(prec, topological):
+    """The 16^3 x 32 workload on the flux background (kappa from the oracle's search, ratio 9.4e-6),
+    in the configuration the benchmark runs: every system reports the FP64 true relative residual
+    1e-10 and the oracle's M confirms three of them; the Lanczos run ends at m = ceil(1.5 i_conv);
+    and the seeded systems need at most 0.4x the CG iterations that the oracle's CG takes from zero
+    on one of them."""
+    from paper_0901_3512_amd import SeedCG
+    cfg, U, kappa, op, B, cold = topological
+    print_case("full size topological", cfg.dims, prec)
+    s = SeedCG(cuda(U), cfg.dims, kappa, prec=prec, reorth_k=cfg.reorth_k, past=cfg.past, tol=cfg.tol)
+    Bd = cuda(B)
+    X, rs = s.solve_seed(Bd)
+    X, rr = s.solve_rest(Bd, X)
+    assert max(rr["true_relres"]) <= 1e-10, rr["true_relres"]
+    Xh = host(X)
+    res = _sampled_relres(op, B, Xh, [0, 5, 11])
+    assert np.all(res <= 1e-10), res
+    assert rs["seed_status"] == "ok" and rs["m"] == int(np.ceil(cfg.past * rs["i_conv"])), (rs["m"], rs["i_conv"])
+    assert max(rr["iters"][1:]) <= 0.4 * cold, (rr["iters"], cold)
+    print("topological", prec, "m", rs["m"], "iters", rr["iters"], "oracle cold CG", cold)

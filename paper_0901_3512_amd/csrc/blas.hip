@@ -306,49 +306,21 @@ void lz_first_vector(bool fp32, const LzState* st, const void* r, void* v, int64
         hipLaunchKernelGGL(scale_from_kernel<double>, grid, dim3(256), 0, L.s, st, (const cx<double>*)r, (cx<double>*)v, n, L.cs);
 }
 
-// Step 6 scalars from alpha_i: gamma_{i-1} = beta_{i-1}/delta_{i-1}, delta_i, zeta_i.
-__global__ void lz_alpha_kernel(int i, LzState* st, const double* part, int64_t np, LzArrays a, int64_t cs) {
-    __shared__ double lds[SCG_BLOCK / SCG_WAVE];
-    st = zoff(st, cs);
-    part = zoff(part, cs);
-    a = zoff(a, cs);
-    if (i > st->m) return;
-    const double al = block_sum_array(part, np, lds);
-    if (threadIdx.x != 0) return;
-    double g, d, z;
-    if (i == 1) {
-        g = 0.0;
-        d = al;
-        z = st->beta0;
-    } else {
-        g = a.beta[i - 1] / a.delta[i - 1];
-        d = al - g * a.beta[i - 1];
-        z = -g * a.zeta[i - 1];
-    }
-    if (!(d > 0.0) || !isfinite(d)) {  // definiteness lost in rounding: end before step i changes anything
-        st->status = 2;
-        st->m = i - 1;
-        st->done = 1;
-        return;
-    }
-    a.alpha[i] = al;
-    a.delta[i] = d;
-    a.gam[i] = g;
-    a.zeta[i] = z;
-    st->max_abs_alpha = fmax(st->max_abs_alpha, fabs(al));
-}
-void lz_alpha(int i, LzState* st, const double* part, int64_t np, const LzArrays& a, const Launch& L) {
-    hipLaunchKernelGGL(lz_alpha_kernel, dim3(1, 1, L.nz), dim3(SCG_BLOCK), 0, L.s, i, st, part, np, a, L.cs);
-}
-
-// Steps 5-6 vectors: f -= alpha_i v_i (and ||f||^2 partials); w_i = (v_i - beta_{i-1} w_{i-1}) / delta_i;
-// x^1 += zeta_i w_i.
+// Steps 5-6 in one launch.  alpha_i = v_i^dag M v_i from the stencil's partials, then the step-6
+// scalars gamma_{i-1} = beta_{i-1}/delta_{i-1}, delta_i = alpha_i - gamma_{i-1} beta_{i-1},
+// zeta_i = -gamma_{i-1} zeta_{i-1}: every workgroup sums the partials in the same fixed order and
+// so holds the same values; workgroup 0 stores them (and ends the run at step i - 1 when delta_i
+// is not positive).  Then f -= alpha_i v_i (with ||f||^2 partials), w_i = (v_i - beta_{i-1} w_{i-1})
+// / delta_i and x^1 += zeta_i w_i.
 template <typename T>
-__global__ void lz_update_kernel(int i, const LzState* st, LzArrays a, cx<T>* __restrict__ f, const cx<T>* __restrict__ v,
-                                 const cx<T>* __restrict__ wprev, cx<T>* __restrict__ wout, cx<double>* __restrict__ x1,
-                                 double* f2part, int64_t n, int64_t cs) {
+__global__ void lz_update_kernel(int i, LzState* st, const double* apart, int64_t np, LzArrays a, cx<T>* __restrict__ f,
+                                 const cx<T>* __restrict__ v, const cx<T>* __restrict__ wprev, cx<T>* __restrict__ wout,
+                                 cx<double>* __restrict__ x1, double* f2part, int64_t n, int64_t cs) {
     __shared__ double lds[SCG_BLOCK / SCG_WAVE];
+    __shared__ double sc[4];   // alpha_i, delta_i, zeta_i, 1 if the step goes on
+    __shared__ int gate;
     st = zoff(st, cs);
+    apart = zoff(apart, cs);
     a = zoff(a, cs);
     f = zoff(f, cs);
     v = zoff(v, cs);
@@ -356,41 +328,83 @@ __global__ void lz_update_kernel(int i, const LzState* st, LzArrays a, cx<T>* __
     wout = zoff(wout, cs);
     x1 = zoff(x1, cs);
     f2part = zoff(f2part, cs);
-    if (i > st->m) return;
+    // one read of m for the whole workgroup (workgroup 0 may lower it below, concurrently)
+    if (threadIdx.x == 0) gate = i <= st->m;
+    __syncthreads();
+    if (!gate) return;
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const double al = a.alpha[i], d = a.delta[i], z = a.zeta[i];
+    cx<T> vv = mk<T>(0, 0), ff = mk<T>(0, 0), wp = mk<T>(0, 0);
+    cx<double> xx = mk<double>(0.0, 0.0);
+    if (k < n) {   // this thread's operands are loaded while the scalars are summed
+        vv = v[k];
+        ff = f[k];
+        if (i > 1) wp = wprev[k];
+        xx = x1[k];
+    }
+    const double al = block_sum_array(apart, np, lds);
+    if (threadIdx.x == 0) {
+        double g, d, z;
+        if (i == 1) {
+            g = 0.0;
+            d = al;
+            z = st->beta0;
+        } else {
+            g = a.beta[i - 1] / a.delta[i - 1];
+            d = al - g * a.beta[i - 1];
+            z = -g * a.zeta[i - 1];
+        }
+        const bool ok = d > 0.0 && isfinite(d);   // else definiteness was lost in rounding
+        sc[0] = al;
+        sc[1] = d;
+        sc[2] = z;
+        sc[3] = ok ? 1.0 : 0.0;
+        if (blockIdx.x == 0) {
+            if (ok) {
+                a.alpha[i] = al;
+                a.delta[i] = d;
+                a.gam[i] = g;
+                a.zeta[i] = z;
+                st->max_abs_alpha = fmax(st->max_abs_alpha, fabs(al));
+            } else {   // end before step i changes anything
+                st->status = 2;
+                st->m = i - 1;
+                st->done = 1;
+            }
+        }
+    }
+    __syncthreads();
+    if (sc[3] == 0.0) return;
+    const double d = sc[1], z = sc[2];
+    const T alt = (T)sc[0];
     const double bp = i > 1 ? a.beta[i - 1] : 0.0;
     double s = 0.0;
     if (k < n) {
-        const cx<T> vv = v[k];
-        cx<T> ff = f[k];
-        ff = mk<T>(ff.re - (T)al * vv.re, ff.im - (T)al * vv.im);
+        ff = mk<T>(ff.re - alt * vv.re, ff.im - alt * vv.im);
         f[k] = ff;
         s = (double)ff.re * ff.re + (double)ff.im * ff.im;
         double wr = vv.re, wi = vv.im;
         if (i > 1) {
-            const cx<T> wp = wprev[k];
             wr -= bp * wp.re;
             wi -= bp * wp.im;
         }
         wr /= d;
         wi /= d;
         wout[k] = mk<T>((T)wr, (T)wi);
-        cx<double> xx = x1[k];
         x1[k] = mk<double>(xx.re + z * wr, xx.im + z * wi);
     }
     s = block_sum(s, lds);
     if (threadIdx.x == 0) f2part[blockIdx.x] = s;
 }
-void lz_update(bool fp32, int i, const LzState* st, const LzArrays& a, void* f, const void* v, const void* wprev, void* wout,
-               double* x1, double* f2part, int64_t n, const Launch& L) {
+void lz_update(bool fp32, int i, LzState* st, const double* apart, int64_t np, const LzArrays& a, void* f, const void* v,
+               const void* wprev, void* wout, double* x1, double* f2part, int64_t n, const Launch& L) {
     const dim3 grid((unsigned)((n + SCG_BLOCK - 1) / SCG_BLOCK), 1, L.nz);
     if (fp32)
-        hipLaunchKernelGGL(lz_update_kernel<float>, grid, dim3(SCG_BLOCK), 0, L.s, i, st, a, (cx<float>*)f, (const cx<float>*)v,
-                           (const cx<float>*)wprev, (cx<float>*)wout, (cx<double>*)x1, f2part, n, L.cs);
+        hipLaunchKernelGGL(lz_update_kernel<float>, grid, dim3(SCG_BLOCK), 0, L.s, i, st, apart, np, a, (cx<float>*)f,
+                           (const cx<float>*)v, (const cx<float>*)wprev, (cx<float>*)wout, (cx<double>*)x1, f2part, n, L.cs);
     else
-        hipLaunchKernelGGL(lz_update_kernel<double>, grid, dim3(SCG_BLOCK), 0, L.s, i, st, a, (cx<double>*)f,
-                           (const cx<double>*)v, (const cx<double>*)wprev, (cx<double>*)wout, (cx<double>*)x1, f2part, n, L.cs);
+        hipLaunchKernelGGL(lz_update_kernel<double>, grid, dim3(SCG_BLOCK), 0, L.s, i, st, apart, np, a, (cx<double>*)f,
+                           (const cx<double>*)v, (const cx<double>*)wprev, (cx<double>*)wout, (cx<double>*)x1, f2part, n,
+                           L.cs);
 }
 
 // Step 9 scalars: beta_i = ||f||, the D-Lanczos residual estimate beta_i |zeta_i/delta_i|, i_conv,

@@ -59,9 +59,9 @@ void sum_partials(const double* part, int64_t nb, int nvec, double* out, bool sq
 
 void lz_start(LzState* st, const double* r2part, int64_t nb, const double* b2part, double* beta, const Launch& L);
 void lz_first_vector(bool fp32, const LzState* st, const void* r, void* v, int64_t n, const Launch& L);
-void lz_alpha(int i, LzState* st, const double* part, int64_t np, const LzArrays& a, const Launch& L);
-void lz_update(bool fp32, int i, const LzState* st, const LzArrays& a, void* f, const void* v, const void* wprev, void* wout,
-               double* x1, double* f2part, int64_t n, const Launch& L);
+// steps 5-6: alpha_i from the np stencil partials apart, the LU scalars, and the vector updates
+void lz_update(bool fp32, int i, LzState* st, const double* apart, int64_t np, const LzArrays& a, void* f, const void* v,
+               const void* wprev, void* wout, double* x1, double* f2part, int64_t n, const Launch& L);
 void lz_beta(int i, LzState* st, const double* part, int64_t np, const LzArrays& a, const Launch& L);
 void lz_next(bool fp32, int i, const LzState* st, const double* beta, const void* f, void* vn, int64_t n, const Launch& L);
 

@@ -649,12 +649,12 @@ void solve_seed_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report* rep) {
             o.gate_m = &st->m;
             o.gate_i = i;
             apply_M_int(h, lo, vi, h->f.p, 1, o);
-            // Step 6: LU scalars; f -= alpha_i v_i; w_i; x^1 += zeta_i w_i
-            lz_alpha(i, st, h->apart.as<double>(), nsb, A, L);
+            // Step 6: alpha_i and the LU scalars; f -= alpha_i v_i; w_i; x^1 += zeta_i w_i
             const int slot = i - i0;
             void* wout = (char*)h->wring.p + (int64_t)slot * h->vec_bytes(lo);
             const void* wprev = (const char*)h->wring.p + (int64_t)(slot > 0 ? slot - 1 : last_slot) * h->vec_bytes(lo);
-            lz_update(lo, i, st, A, h->f.p, vi, wprev, wout, h->x1.as<double>(), h->f2a.as<double>(), N, L);
+            lz_update(lo, i, st, h->apart.as<double>(), nsb, A, h->f.p, vi, wprev, wout, h->x1.as<double>(), h->f2a.as<double>(),
+                      N, L);
             // Step 7, blocked (before step 8 can touch v_i)
             const bool reorth_now = k > 0 && i % k == 0;
             if (slot + 1 == b || reorth_now) {

@@ -1711,7 +1711,7 @@ struct IndefWork {
 // returns false when some system reached max_iter before tol (X then holds its last iterate)
 bool solve_indefinite_impl(seedcg_s* h, const double* Phi, double* Xout, int nrhs, seedcg_report* rep) {
     using cxd = std::complex<double>;
-    if (h->lo) throw StateError{"solve_indefinite: FP64 handles only"};
+    if (h->cg_lo) throw StateError{"solve_indefinite: FP64 handles only"};
     if (h->ncfg != 1) throw StateError{"solve_indefinite: one configuration per handle"};
     if (nrhs < 1 || nrhs > 25) throw ArgError{"solve_indefinite: 1 <= nrhs <= 25"};
     const double t0 = now_s();

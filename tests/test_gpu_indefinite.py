@@ -7,7 +7,7 @@ Bars:
   * the seeded Lanczos run matches the oracle's (oracle/seedminres.py, same k, tol and past):
     m and i_conv within 1, and the MINRES iterations of every system within 10% (or 3) of the
     oracle's from its own seeded guesses;
-  * edges: one right-hand side, a zero right-hand side, a mixed-precision handle (refused).
+  * edges: one right-hand side, a zero right-hand side, mixed-precision handles (refused).
 """
 import numpy as np
 import pytest
@@ -92,9 +92,10 @@ def test_edges(c1):
     assert np.all(X[2] == 0) and rep["iters"][2] == 0
     live = [0, 1, 3]
     assert np.all(_relres_A(dict(c1, phi=z[live]), X[live]) <= 1e-10)
-    s = SeedCG(cuda(c1["U"]), c1["dims"], c1["kappa"], prec="mixed")
-    with pytest.raises(SeedCGError):
-        s.solve_indefinite(cuda(c1["phi"]))
+    for prec in ("mixed", "mixed_cg"):
+        s = SeedCG(cuda(c1["U"]), c1["dims"], c1["kappa"], prec=prec)
+        with pytest.raises(SeedCGError):
+            s.solve_indefinite(cuda(c1["phi"]))
 
 
 def test_full_size_16x16x16x32_sampled_against_oracle():

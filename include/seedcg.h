@@ -56,8 +56,8 @@ typedef enum {
     SEEDCG_MIXED_FP32_CG = 3         /* FP64 Lanczos, basis and seeding (Algorithm 1 as in
                                         FP64); FP32 stencil and CG with FP64 reliable updates.
                                         For operators with near-zero modes, where an FP32
-                                        basis loses the seeding gain. Single handles only;
-                                        no deflation or learned preconditioner.             */
+                                        basis loses the seeding gain. No deflation or
+                                        learned preconditioner.                             */
 } seedcg_prec;
 
 typedef struct {

@@ -2228,7 +2228,9 @@ seedcg_status seedcg_create_batch(int32_t ncfg, const int32_t* dims, const doubl
         if (!(kappa[c] > 0.0)) return fail(nullptr, SEEDCG_ERR_ARG, "create_batch: kappa must be > 0");
     }
     if (p->t_bc != 1 && p->t_bc != -1) return fail(nullptr, SEEDCG_ERR_ARG, "create_batch: t_bc must be +1 or -1");
-    if (p->prec < 0 || p->prec > 2) return fail(nullptr, SEEDCG_ERR_ARG, "create_batch: unknown precision (MIXED_FP32_CG is per configuration)");
+    if (p->prec < 0 || p->prec > 3) return fail(nullptr, SEEDCG_ERR_ARG, "create_batch: unknown precision");
+    if (p->prec == SEEDCG_MIXED_FP32_CG && p->deflate > 0)
+        return fail(nullptr, SEEDCG_ERR_ARG, "create_batch: MIXED_FP32_CG takes no deflation");
     if (!(p->tol > 0.0)) return fail(nullptr, SEEDCG_ERR_ARG, "create_batch: tol must be > 0");
     if (p->reorth_k < 0) return fail(nullptr, SEEDCG_ERR_ARG, "create_batch: reorth_k must be >= 0");
     if (p->precond != 0) return fail(nullptr, SEEDCG_ERR_ARG, "create_batch: the learned preconditioner is per configuration");
@@ -2296,7 +2298,7 @@ seedcg_status seedcg_create_batch(int32_t ncfg, const int32_t* dims, const doubl
             for (int i = 0; i < h->ncfg; i++) {
                 const int c = b->members[k][i];
                 pack_links(P64, g, links[c], (char*)h->links64.p + (int64_t)i * h->cs, h->s);
-                if (h->lo) pack_links(h->lo_prec, g, links[c], (char*)h->links_lo.p + (int64_t)i * h->cs, h->s);
+                if (h->cg_lo) pack_links(h->lo_prec, g, links[c], (char*)h->links_lo.p + (int64_t)i * h->cs, h->s);
                 if (h->hop64 == P64R) pack_links(P64R, g, links[c], (char*)h->links64r.p + (int64_t)i * h->cs, h->s);
                 if (h->hop_lo == P32R) pack_links(P32R, g, links[c], (char*)h->links_lor.p + (int64_t)i * h->cs, h->s);
                 k2.push_back(kappa[c] * kappa[c]);
@@ -2305,11 +2307,12 @@ seedcg_status seedcg_create_batch(int32_t ncfg, const int32_t* dims, const doubl
             check_launch();
             // launch shapes timed on the batch itself (zeroed vectors of the CG and Lanczos buffers)
             if (h->p.autotune && !env_shape_fixed()) {
-                zero_cfg(h, h->Pv.p, nrhs * h->vec_bytes(h->lo));
+                // one vector in the Lanczos precision, several in the CG precision
+                zero_cfg(h, h->Pv.p, nrhs * h->vec_bytes(h->cg_lo));
                 zero_cfg(h, h->basis.p, h->vec_bytes(h->lo));
                 tune_shape(h, h->lo, 1, h->basis.p, h->f.p);
-                if (nrhs > 1) tune_shape(h, h->lo, nrhs, h->Pv.p, h->Qv.p);
-                if (h->lo && nrhs > 1) {   // the FP64 stencil of the true residuals and reliable updates
+                if (nrhs > 1) tune_shape(h, h->cg_lo, nrhs, h->Pv.p, h->Qv.p);
+                if (h->cg_lo && nrhs > 1) {   // the FP64 stencil of the true residuals and reliable updates
                     zero_cfg(h, h->R64.p, nrhs * h->vec_bytes(false));
                     tune_shape(h, false, nrhs, h->R64.p, h->Xint.p);
                 }
@@ -2422,11 +2425,11 @@ seedcg_status seedcg_batch_info(seedcg_batch_t b, int32_t* nclass, int32_t* clas
         if (m_cap) m_cap[k] = b->cls[k]->m_cap;
         if (tune) {
             const seedcg_s* h = b->cls[k];
-            const bool lo = h->lo;
-            tune[4 * k + 0] = lo ? h->tps_lo : h->tps64;
-            tune[4 * k + 1] = lo ? h->vb_lo : h->vb64;
-            tune[4 * k + 2] = lo ? h->tps_lo_multi : h->tps64_multi;
-            tune[4 * k + 3] = lo ? h->vb_lo_multi : h->vb64_multi;
+            // one vector in the Lanczos precision, several in the CG precision
+            tune[4 * k + 0] = h->lo ? h->tps_lo : h->tps64;
+            tune[4 * k + 1] = h->lo ? h->vb_lo : h->vb64;
+            tune[4 * k + 2] = h->cg_lo ? h->tps_lo_multi : h->tps64_multi;
+            tune[4 * k + 3] = h->cg_lo ? h->vb_lo_multi : h->vb64_multi;
         }
     }
     return SEEDCG_OK;

@@ -50,7 +50,7 @@ def _batch(cfgs, prec, **kw):
                        cfgs[0]["B"].shape[0], prec=prec, reorth_k=10, **kw)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_cg"])
 def test_batch_matches_oracle(cfgs, prec):
     print_case("batch oracle", prec)
     b = _batch(cfgs, prec, m_max=400)
@@ -62,7 +62,7 @@ def test_batch_matches_oracle(cfgs, prec):
         res = osc.true_relres(cfg["mv"], flat(cfg["B"]), xb)
         assert np.all(res <= 1e-10), (c, res)
         assert np.allclose(rep["true_relres"], res, rtol=1e-3, atol=1e-14)
-        if prec == "fp64":
+        if prec != "mixed":   # FP64 Algorithm 1 (with an FP32 CG in mixed_cg)
             Md = dense(cfg["mv"], 12 * cfg["op"].Vh)
             xs = np.linalg.solve(Md, flat(cfg["B"]).T).T
             err = np.linalg.norm(xb - xs, axis=1) / np.linalg.norm(xs, axis=1)
@@ -72,7 +72,7 @@ def test_batch_matches_oracle(cfgs, prec):
         print("batch", prec, c, cfg["dims"], "m", rep["m"], "iters", rep["iters"])
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_cg"])
 @pytest.mark.parametrize("shape", [None, ("9", "2"), ("10", "1"), ("3", "1")])
 def test_batch_equals_separate_handles(cfgs, prec, shape, monkeypatch):
     """shape: a stencil launch shape (lanes-per-site code, vectors per workgroup) forced on both

@@ -160,10 +160,10 @@ def test_mixed_cg_mode_keeps_the_seeding_gain():
     solution within 1e-8 of the dense solve; the seed run identical to the FP64 one (same m, bit
     for bit the same seeded guesses); the seeded systems within 1.5x + 10 of FP64's CG iterations.
     The FP32 basis of MIXED_FP32 is reported beside it. Handles that combine the mode with
-    deflation, the learned preconditioner or a batch are refused."""
+    deflation or the learned preconditioner are refused."""
     from dataclasses import replace
 
-    from paper_0901_3512_amd import SeedCG, SeedCGBatch, SeedCGError
+    from paper_0901_3512_amd import SeedCG, SeedCGError
     from synth.configs import CONFIGS, make_links, make_sources
     print_case("mixed_cg flux 4^4")
     cfg = replace(CONFIGS["c1"], flux=(1, 1))
@@ -186,8 +186,6 @@ def test_mixed_cg_mode_keeps_the_seeding_gain():
     print("seeded CG iterations: fp64", out["fp64"][2], "mixed_cg", out["mixed_cg"][2], "mixed", out["mixed"][2])
     with pytest.raises(SeedCGError):
         SeedCG(cuda(U), cfg.dims, 0.17, prec="mixed_cg", deflate=4)
-    with pytest.raises(SeedCGError):
-        SeedCGBatch([cuda(U)], [cfg.dims], [0.17], 4, prec="mixed_cg")
     s = SeedCG(cuda(U), cfg.dims, 0.17, prec="mixed_cg")
     with pytest.raises(SeedCGError):
         s.train_precond(steps=1)

@@ -96,6 +96,16 @@ typedef struct {
     int32_t reorth_passes;    /* Gram-Schmidt passes (a DGKS repeat counts as a pass)                   */
     double t_seed_s;          /* wall seconds of solve_seed                                            */
     double t_rest_s;          /* wall seconds of solve_rest                                            */
+    /* HOST array of length nrhs supplied by the caller (may be NULL): the recursive residual
+       estimate at return.  solve_seed: the D-Lanczos estimate beta_m |zeta_m / delta_m| / ||b^1|| of
+       RHS 1 (Eq. 2) in entry 0, NaN for the seeded right-hand sides (no recursion ran on them);
+       solve_rest: sqrt(r^dag r) / ||b|| of the CG's recursive residual (the FP64 true residual where
+       the last check replaced it) */
+    double* est_relres;
+    /* filled by the library */
+    double orth_loss_max;     /* solve_seed: largest |v_j^dag v_i| / ||v_i|| (j < i) met by a
+                                 reorthogonalisation pass (step 8) before it acted; 0 without any pass */
+    double t_train_s;         /* solve_rest: seconds of the train_precond whose K it applied (0 if none) */
 } seedcg_report;
 
 /* Fills *p with the defaults: t_bc = -1, FP64, m_max = 0, reorth_k = 10, past_factor = 1.5,

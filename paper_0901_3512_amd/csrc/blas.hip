@@ -654,12 +654,26 @@ __global__ void reorth_scalar_kernel(int i, int pass, LzState* st, const double*
         s[q] = block_sum(v, lds);
         __syncthreads();
     }
+    // loss of orthogonality before this step's pass 1: the largest |v_j^dag v_i| / ||v_i||, j < i
+    double mx = 0.0;
+    if (pass == 1) {
+        for (int q = threadIdx.x; q < i - 1; q += blockDim.x) {
+            const cx<double> c = G[2 * q];
+            mx = fmax(mx, sqrt(c.re * c.re + c.im * c.im));
+        }
+        for (int off = SCG_WAVE / 2; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+        if (threadIdx.x % SCG_WAVE == 0) lds[threadIdx.x / SCG_WAVE] = mx;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int w = 0; w < (int)(blockDim.x / SCG_WAVE); w++) mx = fmax(mx, lds[w]);
+    }
     if (threadIdx.x != 0) return;
     st->nv = sqrt(s[0]);
     st->e = s[1] / s[0];
     st->e_im = s[2] / s[0];
     if (pass == 1) {
         st->v2_before = G[2 * (i - 1)].re;  // v_i^dag v_i before the pass
+        if (st->v2_before > 0.0) st->orth_loss = fmax(st->orth_loss, mx / sqrt(st->v2_before));
         st->passes += 2;
     } else {
         st->passes += (st->rep_v ? 1 : 0) + (st->rep_f ? 1 : 0);

@@ -16,6 +16,8 @@
 // MFMA operand layout (16x16x4, one block): lane l holds A[l%16][l/16] and B[l/16][l%16];
 // the 16x16 result is 4 values per lane in column l%16: rows l/16 + 4q for the FP64
 // instruction and rows 4*(l/16) + q for the FP32 one (q = 0..3; checked on gfx950).
+#include <stdexcept>
+
 #include "kernels.h"
 
 namespace scg {
@@ -205,6 +207,10 @@ __global__ void proj_reduce_kernel(const double* part, int64_t nchunks, int64_t 
 int64_t proj_chunks(int64_t n, int64_t kchunk) { return (n + kchunk - 1) / kchunk; }
 
 void project(bool fp32, const ProjArgs& a, int64_t nrowblocks, double* P, const Launch& L, bool fp64_math) {
+    // the kernel stages at most PJ_MAXR columns of R and writes its split-K partials to a.part
+    if (a.part == nullptr || P == nullptr) throw std::invalid_argument("project: partials or output buffer missing");
+    if (a.nr < 1 || a.nr > PJ_MAXR) throw std::invalid_argument("project: 1 <= nr <= 24 columns per contraction");
+    if (a.part_stride < 2 * (int64_t)a.nv * a.nr) throw std::invalid_argument("project: partial stride below 2 nv nr");
     const hipStream_t s = L.s;
     const int64_t nch = proj_chunks(a.n, a.kchunk);
     const dim3 grid((unsigned)nch, (unsigned)nrowblocks, L.nz);

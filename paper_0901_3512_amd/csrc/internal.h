@@ -123,6 +123,7 @@ struct LzState {
     double v2_before;   // ||v_i||^2 before it
     double nv, e;       // reorth: ||v'|| and (v'^dag f') / ||v'||^2 (re, im in e, e_im)
     double e_im;
+    double orth_loss;   // max over the reorthogonalisation passes of max_{j<i} |v_j^dag v_i| / ||v_i||
 };
 
 // Device-side scalars of the multi-RHS CG.

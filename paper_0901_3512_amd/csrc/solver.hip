@@ -21,6 +21,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -598,6 +599,19 @@ void solve_seed_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report* rep) {
         o.cz_host = 1.0;
         apply_M_int(h, false, h->Xint.p, h->r64.p, nrhs, o);
     }
+    {
+        // a non-finite entry of B or X makes r_0 non-finite: refuse it before any step runs
+        const int64_t nbr = norm2_blocks(N);
+        norm2_partials(false, h->r64.p, N, nrhs, h->apart.as<double>(), L);
+        sum_partials(h->apart.as<double>(), nbr, nrhs, h->P.as<double>(), false, L);
+        std::vector<double> r2((size_t)C * nrhs);
+        from_cfg(h, r2.data(), h->P.p, nrhs * sizeof(double));
+        HIPCHK(hipStreamSynchronize(h->s));
+        for (size_t q = 0; q < r2.size(); q++)
+            if (!std::isfinite(r2[q]))
+                throw ArgError{"solve_seed: right-hand side or starting guess " + std::to_string(q % nrhs) +
+                               " holds a non-finite value"};
+    }
     if (nr > 0) convert(false, lo, (char*)h->r64.p + h->vec_bytes(false), h->R0.p, nr * N, L);
     copy_cfg(h, h->x1.p, h->Xint.p, h->vec_bytes(false));
     zero_cfg(h, h->etaprev.p, 2 * 24 * sizeof(double));
@@ -688,9 +702,18 @@ void solve_seed_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report* rep) {
     h->defl_stale = true;
     h->seed_nrhs = nrhs;
     if (rep) {
+        // RHS 1's residual estimate after its last step (Eq. 2), per configuration
+        std::vector<double> est_m(C, 0.0);
+        for (int c = 0; c < C; c++)
+            HIPCHK(hipMemcpyAsync(&est_m[c], (const char*)(A.est + std::max(0, (int)hs[c].m)) + (int64_t)c * h->cs,
+                                  sizeof(double), hipMemcpyDeviceToHost, h->s));
+        HIPCHK(hipStreamSynchronize(h->s));
         const double t = now_s() - t0;
         for (int c = 0; c < C; c++) {
             seedcg_report& r = rep[c];
+            r.orth_loss_max = hs[c].orth_loss;
+            if (r.est_relres)
+                for (int j = 0; j < nrhs; j++) r.est_relres[j] = j == 0 ? est_m[c] : std::nan("");
             r.m_used = hs[c].m;
             r.i_conv = hs[c].i_conv;
             r.seed_status = hs[c].status;
@@ -1037,8 +1060,11 @@ ProjArgs defl_proj_args(seedcg_s* h, const void* rows, int nrows, const void* R,
     a.nr = nr;
     a.n = h->N;
     a.kchunk = kchunk_for(h->N, 1024);
-    a.part = h->projpart.as<double>();
     a.part_stride = 2 * 32 * 24;
+    // the partials buffer of the seed solve may have been released with the basis; the
+    // deflation space outlives it
+    h->projpart.ensure((size_t)proj_chunks(h->N, a.kchunk) * a.part_stride * sizeof(double));
+    a.part = h->projpart.as<double>();
     return a;
 }
 
@@ -1205,6 +1231,8 @@ seedcg_status solve_rest_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report
     void* Rw = lo ? h->Rv.p : h->R64.p;  // the recursive residual
     // deflated CG from the Ritz vectors of the last seed solve (one configuration, no learned P)
     const bool want_defl = h->p.deflate > 0 && C == 1 && h->have_seed && !(h->p.precond == 1 && h->k_ready && h->k_accepted);
+    // the deflation projections contract all right-hand sides at once (at most 24 columns)
+    if (want_defl && nrhs > 24) throw ArgError{"solve_rest: deflated CG takes at most 24 right-hand sides"};
     if (!want_defl)
         h->nev = 0;
     else if (h->defl_stale || h->nev == 0) {
@@ -1229,6 +1257,10 @@ seedcg_status solve_rest_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report
     HIPCHK(hipStreamSynchronize(h->s));
     auto bn = [&](int c, int j) { return hn[(size_t)c * 2 * nrhs + j]; };
     auto rr_of = [&](int c, int j) { return hn[(size_t)c * 2 * nrhs + nrhs + j]; };
+    for (int c = 0; c < C; c++)
+        for (int j = 0; j < nrhs; j++)
+            if (!std::isfinite(bn(c, j)) || !std::isfinite(rr_of(c, j)))
+                throw ArgError{"solve_rest: right-hand side or starting guess " + std::to_string(j) + " holds a non-finite value"};
     if (h->nev) {
         // the deflated start x += W G^{-1} W^dag r, then the true residuals again
         if (lo) convert(false, true, h->R64.p, h->Rv.p, nrhs * N, L);
@@ -1426,8 +1458,10 @@ seedcg_status solve_rest_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report
                 if (r.iters) r.iters[j] = cg[q].iters;
                 if (r.matvecs) r.matvecs[j] = matvecs[q];
                 if (r.true_relres) r.true_relres[j] = std::sqrt(rr_of(c, j)) / bn(c, j);
+                if (r.est_relres) r.est_relres[j] = std::sqrt(std::max(0.0, cg[q].rr)) / bn(c, j);
             }
             r.t_rest_s = t;
+            r.t_train_s = pc ? h->k_t_train : 0.0;
         }
     }
     return noconv ? SEEDCG_ERR_NOCONV : SEEDCG_OK;
@@ -2140,6 +2174,10 @@ seedcg_status guarded(seedcg_s* h, F&& f) {
         return fail(h, SEEDCG_ERR_HIP, e.what);
     } catch (const std::bad_alloc&) {
         return fail(h, SEEDCG_ERR_OOM, "host allocation failed");
+    } catch (const std::invalid_argument& e) {
+        return fail(h, SEEDCG_ERR_ARG, e.what());
+    } catch (const std::exception& e) {
+        return fail(h, SEEDCG_ERR_HIP, e.what());
     } catch (...) {
         return fail(h, SEEDCG_ERR_HIP, "unexpected exception");
     }

@@ -32,7 +32,9 @@ class Report(ctypes.Structure):
     _fields_ = [("iters", ctypes.POINTER(ctypes.c_int32)), ("matvecs", ctypes.POINTER(ctypes.c_int32)),
                 ("true_relres", ctypes.POINTER(ctypes.c_double)), ("m_used", ctypes.c_int32),
                 ("i_conv", ctypes.c_int32), ("seed_status", ctypes.c_int32), ("reorth_passes", ctypes.c_int32),
-                ("t_seed_s", ctypes.c_double), ("t_rest_s", ctypes.c_double)]
+                ("t_seed_s", ctypes.c_double), ("t_rest_s", ctypes.c_double),
+                ("est_relres", ctypes.POINTER(ctypes.c_double)), ("orth_loss_max", ctypes.c_double),
+                ("t_train_s", ctypes.c_double)]
 
 
 class SeedCGError(RuntimeError):
@@ -209,6 +211,8 @@ class SeedCG:
         r.iters = ctypes.cast(it, ctypes.POINTER(ctypes.c_int32))
         r.matvecs = ctypes.cast(mv, ctypes.POINTER(ctypes.c_int32))
         r.true_relres = ctypes.cast(rr, ctypes.POINTER(ctypes.c_double))
+        r._est = (ctypes.c_double * n)()   # kept alive with the report
+        r.est_relres = ctypes.cast(r._est, ctypes.POINTER(ctypes.c_double))
         return r, it, mv, rr
 
     def solve_seed(self, B, X=None):
@@ -219,7 +223,8 @@ class SeedCG:
         r, it, mv, rr = self._report(n)
         self._rc(self._lib.seedcg_solve_seed(self._h, B.data_ptr(), X.data_ptr(), n, ctypes.byref(r)))
         rep = dict(m=r.m_used, i_conv=r.i_conv, seed_status=SEED_STATUS.get(r.seed_status, r.seed_status),
-                   reorth_passes=r.reorth_passes, t_seed_s=r.t_seed_s, matvecs=list(mv))
+                   reorth_passes=r.reorth_passes, t_seed_s=r.t_seed_s, matvecs=list(mv), est_relres=list(r._est),
+                   orth_loss_max=r.orth_loss_max)
         return X, rep
 
     def solve_rest(self, B, X, raise_on_noconv=True):
@@ -230,7 +235,7 @@ class SeedCG:
         r, it, mv, rr = self._report(n)
         rc = self._lib.seedcg_solve_rest(self._h, B.data_ptr(), X.data_ptr(), n, ctypes.byref(r))
         rep = dict(iters=list(it), matvecs=list(mv), true_relres=list(rr), t_rest_s=r.t_rest_s,
-                   status=STATUS.get(rc, rc))
+                   est_relres=list(r._est), t_train_s=r.t_train_s, status=STATUS.get(rc, rc))
         if rc != 0 and (rc != -5 or raise_on_noconv):
             self._rc(rc)
         return X, rep

@@ -196,6 +196,18 @@ seedcg_status seedcg_get_basis_vector(seedcg_t h, int32_t i, double* v);
 seedcg_status seedcg_project(seedcg_t h, const double* Vv, int32_t nv, const double* R, int32_t nr,
                              int64_t n, double* P);
 
+/* seedcg_project without any device allocation, for callers that cannot allocate (code under
+   HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+   layouts and result as seedcg_project; the split-K partials live in a static device array of
+   4 MiB per GPU (2^19 doubles), allocated with the library's code object and held until the
+   process ends, so nv * nr may be at most 262144 (and nr <= 24): larger sizes return
+   SEEDCG_ERR_ARG without touching the GPU.  Where seedcg_project's K-chunking fits in the array
+   the two return the same bits; otherwise longer K-chunks change only the summation order.
+   Every call on one GPU shares that GPU's array: calls that overlap in time on one GPU (other
+   host threads, other streams) race on it and must be serialised by the caller. */
+seedcg_status seedcg_project_noalloc(seedcg_t h, const double* Vv, int32_t nv, const double* R, int32_t nr,
+                                     int64_t n, double* P);
+
 /* X += W E: W nw vectors, E an nw x nx row-major complex matrix (device), X nx vectors,
    n complex each (the seeding update of Algorithm 1 step 7, x^j += eta^j w_i, blocked). */
 seedcg_status seedcg_update(seedcg_t h, const double* W, int32_t nw, const double* E, double* X,

@@ -16,7 +16,10 @@
 // MFMA operand layout (16x16x4, one block): lane l holds A[l%16][l/16] and B[l/16][l%16];
 // the 16x16 result is 4 values per lane in column l%16: rows l/16 + 4q for the FP64
 // instruction and rows 4*(l/16) + q for the FP32 one (q = 0..3; checked on gfx950).
+#include <map>
+#include <mutex>
 #include <stdexcept>
+#include <string>
 
 #include "kernels.h"
 
@@ -205,6 +208,28 @@ __global__ void proj_reduce_kernel(const double* part, int64_t nchunks, int64_t 
 }
 
 int64_t proj_chunks(int64_t n, int64_t kchunk) { return (n + kchunk - 1) / kchunk; }
+
+// Split-K partials of the allocation-free contraction (seedcg_project_noalloc): one copy of this
+// array per GPU, held by the loaded code object until the process ends.  In host code its name is
+// only a stand-in for the device copy; proj_scratch() returns the device address to pass instead.
+static __device__ __align__(256) double scratch[PROJ_SCRATCH_DOUBLES];
+
+double* proj_scratch() {
+    static std::mutex mu;
+    static std::map<int, double*> addr;   // device ordinal -> address of that device's copy
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) throw std::runtime_error(std::string("hipGetDevice: ") + hipGetErrorString(e));
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(dev);
+    if (it != addr.end()) return it->second;
+    double* ptr = nullptr;
+    e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr)
+        throw std::runtime_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    addr[dev] = ptr;
+    return ptr;
+}
 
 void project(bool fp32, const ProjArgs& a, int64_t nrowblocks, double* P, const Launch& L, bool fp64_math) {
     // the kernel stages at most PJ_MAXR columns of R and writes its split-K partials to a.part

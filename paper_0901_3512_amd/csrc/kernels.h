@@ -38,6 +38,10 @@ struct ProjArgs {
 // fp32: V and R stored in FP32; fp64_math: contract them on the FP64 matrix cores anyway
 void project(bool fp32, const ProjArgs& a, int64_t nrowblocks, double* P, const Launch& L, bool fp64_math = false);
 int64_t proj_chunks(int64_t n, int64_t kchunk);
+// Static partials of the allocation-free contraction: PROJ_SCRATCH_DOUBLES doubles (4 MiB) per GPU.
+// proj_scratch() returns the current device's copy (its address is looked up once per device).
+constexpr int64_t PROJ_SCRATCH_DOUBLES = int64_t(1) << 19;
+double* proj_scratch();
 
 void pack_links(Prec prec, const Geom& g, const double* U, void* out, hipStream_t s);
 // per-block maxima of the distance of every link from SU(3) as its two-row format sees it

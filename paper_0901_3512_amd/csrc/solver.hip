@@ -2723,6 +2723,37 @@ seedcg_status seedcg_project(seedcg_t h, const double* Vv, int32_t nv, const dou
     });
 }
 
+seedcg_status seedcg_project_noalloc(seedcg_t h, const double* Vv, int32_t nv, const double* R, int32_t nr, int64_t n,
+                                     double* P) {
+    if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "project_noalloc: null handle");
+    return guarded(h, [&]() -> seedcg_status {
+        if (!Vv || !R || !P || nv < 1 || nr < 1 || n < 1) throw ArgError{"project_noalloc: null pointer or empty size"};
+        if (nr > 24) throw ArgError{"project_noalloc: at most 24 vectors in R"};
+        const int64_t per_chunk = 2 * (int64_t)nv * nr;   // partial doubles of one K-chunk
+        if (per_chunk > PROJ_SCRATCH_DOUBLES)
+            throw ArgError{"project_noalloc: nv * nr = " + std::to_string((int64_t)nv * nr) + " exceeds " +
+                           std::to_string(PROJ_SCRATCH_DOUBLES / 2) + " (static partials of " +
+                           std::to_string(PROJ_SCRATCH_DOUBLES * 8 >> 20) + " MiB)"};
+        ProjArgs a{};
+        a.V = Vv;
+        a.ldv = n;
+        a.nv = nv;
+        for (int j = 0; j < nr; j++) a.R[j] = R + 2 * (int64_t)j * n;
+        a.nr = nr;
+        a.n = n;
+        // seedcg_project's K-chunk (so the two agree bit for bit) unless its partials would not fit
+        a.kchunk = kchunk_for(n, std::max<int64_t>(1, 1024 / ((nv + 31) / 32)));
+        const int64_t max_chunks = PROJ_SCRATCH_DOUBLES / per_chunk;
+        if (proj_chunks(n, a.kchunk) > max_chunks) a.kchunk = ((n + max_chunks - 1) / max_chunks + 31) / 32 * 32;
+        a.part_stride = per_chunk;
+        a.part = proj_scratch();   // the device address of this GPU's copy, never the array's host-side name
+        project(false, a, (nv + 31) / 32, P, h->s);
+        check_launch();
+        HIPCHK(hipStreamSynchronize(h->s));
+        return SEEDCG_OK;
+    });
+}
+
 seedcg_status seedcg_update(seedcg_t h, const double* W, int32_t nw, const double* E, double* X, int32_t nx, int64_t n) {
     if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "update: null handle");
     return guarded(h, [&]() -> seedcg_status {

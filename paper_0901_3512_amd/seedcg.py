@@ -71,6 +71,7 @@ def load_library():
         "seedcg_get_basis_vector": (i32, [H, i32, P]),
         "seedcg_get_ritz": (i32, [H, ctypes.POINTER(dbl), i32, ctypes.POINTER(i32)]),
         "seedcg_project": (i32, [H, P, i32, P, i32, i64, P]),
+        "seedcg_project_noalloc": (i32, [H, P, i32, P, i32, i64, P]),
         "seedcg_update": (i32, [H, P, i32, P, P, i32, i64]),
         "seedcg_train_precond": (i32, [H, i32, i32, i32, dbl, ctypes.POINTER(dbl)]),
         "seedcg_use_precond": (i32, [H, i32]),
@@ -104,7 +105,7 @@ def exported_symbols():
     """Names of the C ABI entry points this binding expects."""
     return ["seedcg_default_params", "seedcg_create", "seedcg_apply_M", "seedcg_apply_M_inner", "seedcg_apply_A", "seedcg_solve_seed",
             "seedcg_solve_rest", "seedcg_solve_repeated", "seedcg_solve_indefinite", "seedcg_get_tridiag", "seedcg_get_basis_vector", "seedcg_get_ritz", "seedcg_project",
-            "seedcg_update", "seedcg_train_precond", "seedcg_use_precond", "seedcg_set_precond_weights",
+            "seedcg_project_noalloc", "seedcg_update", "seedcg_train_precond", "seedcg_use_precond", "seedcg_set_precond_weights",
             "seedcg_get_precond_weights", "seedcg_apply_P", "seedcg_precond_loss_grad", "seedcg_set_timing",
             "seedcg_get_timing", "seedcg_release_basis", "seedcg_destroy", "seedcg_last_error", "seedcg_create_batch",
             "seedcg_solve_batch", "seedcg_batch_info", "seedcg_batch_set_timing", "seedcg_batch_get_timing",
@@ -298,6 +299,19 @@ class SeedCG:
         P = torch.empty((Vv.shape[0], R.shape[0]), dtype=torch.complex128, device=self.device)
         self._rc(self._lib.seedcg_project(self._h, Vv.data_ptr(), Vv.shape[0], R.data_ptr(), R.shape[0],
                                           Vv.shape[1], P.data_ptr()))
+        return P
+
+    def project_noalloc(self, Vv, R, P=None):
+        """seedcg_project_noalloc: P = V^dag R with the partials in the library's static device array
+        (no allocation inside the library; P may be passed in to avoid torch's too)."""
+        Vv = Vv.reshape(Vv.shape[0], -1)
+        R = R.reshape(R.shape[0], -1)
+        assert Vv.is_contiguous() and R.is_contiguous() and Vv.shape[1] == R.shape[1]
+        if P is None:
+            P = torch.empty((Vv.shape[0], R.shape[0]), dtype=torch.complex128, device=self.device)
+        assert P.is_contiguous() and tuple(P.shape) == (Vv.shape[0], R.shape[0]) and P.dtype == torch.complex128
+        self._rc(self._lib.seedcg_project_noalloc(self._h, Vv.data_ptr(), Vv.shape[0], R.data_ptr(), R.shape[0],
+                                                  Vv.shape[1], P.data_ptr()))
         return P
 
     def update(self, W, E, X):

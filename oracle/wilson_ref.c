@@ -84,7 +84,7 @@ void oracle_hop(const int32_t* dims, int32_t t_bc, const cplx* U, const cplx* in
     for (int64_t iv = 0; iv < nvec; iv++) {
         const cplx* src = in + iv * Vh * 12;
         cplx* dst = out + iv * Vh * 12;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (Vh >= 4096)  /* small lattices: thread start-up costs more than the sites */
         for (int64_t h = 0; h < Vh; h++) {
             int64_t rest = h / Lxh;
             int64_t c[4];

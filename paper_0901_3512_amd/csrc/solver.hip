@@ -1388,11 +1388,13 @@ seedcg_status solve_rest_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report
                 const double rr = rr_of(c, j);
                 matvecs[q] += 1;
                 if (std::sqrt(rr) <= tol * x.bnorm) {
+                    if (x.frozen) x.rr = x.pq;   // the recursive |r|^2 at the freeze (the report's estimate)
                     x.done = 1;
                     x.frozen = 0;
                     continue;
                 }
                 if (x.iters >= max_iter || !std::isfinite(rr)) {
+                    if (x.frozen) x.rr = x.pq;
                     x.done = 1;
                     x.frozen = 0;
                     noconv = true;

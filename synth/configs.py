@@ -66,6 +66,13 @@ CONFIGS = {
     # 32^3 x 64, eps = 0.3, ratio 1e-6, 12 point sources (learned preconditioner workload).
     "c5": SolverConfig("c5", (32, 32, 32, 64), 0.3, 1e-6, 0x5EED04,
                        sources=(("point", 12),), reorth_k=10, prec="mixed"),
+    # The 24^3 x 48 and 32^3 x 64 workloads on the topological flux background: their plain links
+    # keep lambda_min / lambda_max above a few 1e-4 at every kappa (a dip near the critical kappa),
+    # while the flux's near-zero modes cross zero there and make the targets 1e-5 and 1e-6 reachable.
+    "c3t": SolverConfig("c3t", (24, 24, 24, 48), 0.3, 1e-5, 0x5EED02,
+                        sources=(("point", 12), ("z2", 12)), reorth_k=10, prec="mixed_bf16", flux=(1, 1)),
+    "c5t": SolverConfig("c5t", (32, 32, 32, 64), 0.3, 1e-6, 0x5EED04,
+                        sources=(("point", 12),), reorth_k=10, prec="mixed", flux=(1, 1)),
     # Tiny lattices used by the tests.
     "t2": SolverConfig("t2", (2, 2, 2, 2), 0.3, 1e-2, 0x5EED10, sources=(("gaussian", 3),),
                        reorth_k=5, kappa_override=0.12),

@@ -1,18 +1,25 @@
-"""Algorithm 1 of the paper (Seed-CG(m, k)) and plain CG, in FP64, step by step.
+"""Algorithm 1 of the paper (Seed-CG(m, k)) and plain CG, in FP64 (TEST INFRASTRUCTURE).
+
+Seed-CG is written here as one loop over the Lanczos steps i = 1, 2, ...: the three-term
+recurrence gives alpha_i, the LU factorisation of the tridiagonal T (Eq. 2) gains one row
+(delta_i, gamma_{i-1}, zeta_i) and updates the first system's iterate through w_i, the Galerkin
+seeding of Eq. (1) updates every other system through the eta recurrence, the basis is
+reorthogonalised every k steps, and beta_i gives the next Lanczos vector and the residual
+estimate.
 
 Vectors are flat complex128 arrays of length N; a batch of right-hand sides is (nrhs, N).
 `matvec` applies the Hermitian positive-definite M to one vector or to a batch.
 
 Readings of the paper taken here (where it is silent or garbled):
-  * Step 2 omits v_2: step 9 is applied at i = 1 as well, v_2 = f / beta_1, and
-    iteration 1 runs steps 8 and 9 like every other iteration.
-  * Steps 6-7 use v_i before step 8 changes it; the reorthonormalised v_i is what is
-    kept and used as v_{i-1} in the next step 5; alpha, beta (the matrix T) are not
-    recomputed after the reorthogonalisation.
-  * Step 8 is classical Gram-Schmidt: v_i against v_1..v_{i-1}, normalised, then f
-    against v_1..v_i; a pass is repeated once (Daniel-Gragg-Kaufman-Stewart) when it
+  * The algorithm's start does not form v_2: the end-of-step update v_{i+1} = f / beta_i is
+    applied at i = 1 as well, and the first Lanczos step is reorthogonalised and closed like any other.
+  * The LU row and the seeding use v_i before the reorthogonalisation changes it; the
+    reorthonormalised v_i is what is kept and used as v_{i-1} in the next three-term
+    recurrence; alpha, beta (the matrix T) are not recomputed after the reorthogonalisation.
+  * The reorthogonalisation is classical Gram-Schmidt: v_i against v_1..v_{i-1}, normalised,
+    then f against v_1..v_i; a pass is repeated once (Daniel-Gragg-Kaufman-Stewart) when it
     shrinks the vector's norm below 1/sqrt(2) of its norm before the pass.
-  * Step 1's r_0^j is computed once; the eta recurrence of step 7 always uses r_0^j.
+  * The initial residuals r_0^j are computed once; the eta recurrence always uses r_0^j.
   * Stopping: the paper fixes m up front.  With past > 0 and no fixed m, the residual
     estimate of D-Lanczos, ||r_i|| = beta_i |zeta_i / delta_i|, decides i_conv, the first
     i with estimate <= tol * ||b^1||, and then m = min(ceil(past * i_conv), m_max).
@@ -65,11 +72,11 @@ def seed_cg(matvec, B, X0=None, *, k, tol, past=1.5, m_max=2000, m=None):
     X = np.zeros_like(B) if X0 is None else np.array(X0, dtype=np.complex128, copy=True)
     m_cap = int(m) if m is not None else int(m_max)
 
-    # Step 1: initial residuals r_0^j = b^j - M x_0^j.
+    # initial residuals r_0^j = b^j - M x_0^j
     R0 = B - matvec(X) if X0 is not None and np.any(X != 0) else B.copy()
     b1 = _norm(B[0])
 
-    # Step 2: beta_0 = ||r_0^1||, v_1 = r_0^1 / beta_0.
+    # the Lanczos start: beta_0 = ||r_0^1||, v_1 = r_0^1 / beta_0
     beta0 = _norm(R0[0])
     V = np.empty((m_cap + 1, N), dtype=np.complex128)
     V[0] = R0[0] / beta0
@@ -85,13 +92,13 @@ def seed_cg(matvec, B, X0=None, *, k, tol, past=1.5, m_max=2000, m=None):
     i = 1
     while True:
         v = V[i - 1]
-        # Step 5 (step 2 at i = 1): f = M v_i - beta_{i-1} v_{i-1}; alpha_i = v_i^dag f; f -= alpha_i v_i.
+        # three-term recurrence: f = M v_i - beta_{i-1} v_{i-1}; alpha_i = v_i^dag f; f -= alpha_i v_i
         f = matvec(v)
         if i > 1:
             f = f - beta[i - 1] * V[i - 2]
         a = float(np.vdot(v, f).real)
         f = f - a * v
-        # Step 6 (step 3 at i = 1): the LU of T, Eq. (2), one row at a time.
+        # one more row of the LU of T (Eq. 2), and the first system's iterate along w_i
         if i == 1:
             g = 0.0
             d = a
@@ -110,18 +117,18 @@ def seed_cg(matvec, B, X0=None, *, k, tol, past=1.5, m_max=2000, m=None):
         zeta.append(z)
         w = v / d if i == 1 else (v - beta[i - 1] * w_prev) / d
         X[0] += z * w
-        # Step 7 (step 4 at i = 1): eta^j = v_i^dag r_0^j - gamma_{i-1} eta^j; x^j += eta^j w_i.
+        # Galerkin seeding (Eq. 1): eta^j = v_i^dag r_0^j - gamma_{i-1} eta^j; x^j += eta^j w_i
         if nrhs > 1:
             eta = (V[i - 1].conj() @ R0[1:].T) - g * eta
             X[1:] += eta[:, None] * w[None, :]
         m_used = i
-        # Step 8: periodic reorthogonalisation.
+        # periodic reorthogonalisation
         if k and i % k == 0:
             vi, p1 = _orthogonalise(V[:i - 1], V[i - 1])
             V[i - 1] = vi / _norm(vi)
             f, p2 = _orthogonalise(V[:i], f)
             passes += p1 + p2
-        # Step 9: beta_i = ||f||, v_{i+1} = f / beta_i.
+        # beta_i = ||f||, the residual estimate, the stopping rule and v_{i+1} = f / beta_i
         bi = _norm(f)
         beta.append(bi)
         e = bi * abs(z / d)

@@ -23,11 +23,11 @@ Readings taken here (the paper names the factorisation only):
     inside the Lanczos space.  Entry i of the rotated g^j is final once v_{i+1} exists: with
     u^j_1 = v_1^dag r_0^j and eta^j_{i+1} = v_{i+1}^dag r_0^j,
         tau^j_i = c_i u^j_i + s_i eta^j_{i+1},   u^j_{i+1} = -s_i u^j_i + c_i eta^j_{i+1},
-    and x^j += tau^j_i w_i.  This replaces the eta recurrence of Algorithm 1's step 7.
-  * Periodic reorthogonalisation (step 8) is as in Algorithm 1: classical Gram-Schmidt of v_i
+    and x^j += tau^j_i w_i.  This replaces the eta recurrence of Algorithm 1's seeding (Eq. 1).
+  * Periodic reorthogonalisation is as in Algorithm 1: classical Gram-Schmidt of v_i
     against v_1..v_{i-1}, renormalised, then f against v_1..v_i, with one DGKS repeat.  Column i of
-    Tbar needs beta_i, which exists only after step 8.  The QR step, w_i and every iterate update
-    of step i therefore use the basis as it stands after step 8.
+    Tbar needs beta_i, which exists only after the reorthogonalisation.  The QR step, w_i and every iterate update
+    of step i therefore use the basis as it stands after the reorthogonalisation.
   * Stopping as Algorithm 1: i_conv is the first step with |u_{i+1}| <= tol ||c^1||, and then
     m = min(ceil(past i_conv), m_max).  A beta_i at rounding level (<= 1e-14 max |alpha|) ends
     the run (invariant subspace).

@@ -306,7 +306,7 @@ void lz_first_vector(bool fp32, const LzState* st, const void* r, void* v, int64
         hipLaunchKernelGGL(scale_from_kernel<double>, grid, dim3(256), 0, L.s, st, (const cx<double>*)r, (cx<double>*)v, n, L.cs);
 }
 
-// Steps 5-6 in one launch.  alpha_i = v_i^dag M v_i from the stencil's partials, then the step-6
+// The Lanczos coefficient and the LU row of Eq. (2) in one launch.  alpha_i = v_i^dag M v_i from the stencil's partials, then the LU
 // scalars gamma_{i-1} = beta_{i-1}/delta_{i-1}, delta_i = alpha_i - gamma_{i-1} beta_{i-1},
 // zeta_i = -gamma_{i-1} zeta_{i-1}: every workgroup sums the partials in the same fixed order and
 // so holds the same values; workgroup 0 stores them (and ends the run at step i - 1 when delta_i
@@ -407,7 +407,7 @@ void lz_update(bool fp32, int i, LzState* st, const double* apart, int64_t np, c
                            L.cs);
 }
 
-// Step 9 scalars: beta_i = ||f||, the D-Lanczos residual estimate beta_i |zeta_i/delta_i|, i_conv,
+// End of a Lanczos step, scalars: beta_i = ||f||, the D-Lanczos residual estimate beta_i |zeta_i/delta_i|, i_conv,
 // m = min(ceil(past * i_conv), m_cap), breakdown.
 __global__ void lz_beta_kernel(int i, LzState* st, const double* part, int64_t np, LzArrays a, int64_t cs) {
     __shared__ double lds[SCG_BLOCK / SCG_WAVE];
@@ -441,7 +441,7 @@ void lz_beta(int i, LzState* st, const double* part, int64_t np, const LzArrays&
     hipLaunchKernelGGL(lz_beta_kernel, dim3(1, 1, L.nz), dim3(SCG_BLOCK), 0, L.s, i, st, part, np, a, L.cs);
 }
 
-// Step 9 vector: v_{i+1} = f / beta_i (only when another step follows).
+// End of a Lanczos step, vector: v_{i+1} = f / beta_i (only when another step follows).
 template <typename T>
 __global__ void lz_next_kernel(int i, const LzState* st, const double* beta, const cx<T>* __restrict__ f,
                                cx<T>* __restrict__ vn, int64_t n, int64_t cs) {
@@ -465,7 +465,7 @@ void lz_next(bool fp32, int i, const LzState* st, const double* beta, const void
 }
 
 // ---------------------------------------------------------------------------------------------
-// Step 7, blocked: eta^j_i = (V^dag r_0^j)_i - gamma_{i-1} eta^j_{i-1} over the rows of a block,
+// The seeding recurrence of Eq. (1), blocked: eta^j_i = (V^dag r_0^j)_i - gamma_{i-1} eta^j_{i-1} over the rows of a block,
 // then X^j += sum_i eta^j_i w_i.  Rows beyond m (the run ended inside the block) get eta = 0.
 // ---------------------------------------------------------------------------------------------
 __global__ void seed_eta_kernel(int i0, int nb, int nr, const LzState* st, const double* gam, const cx<double>* P,
@@ -548,7 +548,7 @@ void seed_update(bool w32, bool x32, const void* W, int nw, const double* E, voi
 }
 
 // ---------------------------------------------------------------------------------------------
-// Step 8: periodic reorthogonalisation of the pair [v_i, f] by classical Gram-Schmidt.
+// Periodic reorthogonalisation of the pair [v_i, f] by classical Gram-Schmidt (Algorithm 1).
 // G = V_{1..i}^dag [v_i, f] comes from the projection kernel.  Pass 1 always runs; pass 2
 // (the DGKS repeat) runs only for a vector whose norm fell below 1/sqrt(2) of its norm
 // before pass 1.

@@ -1,4 +1,5 @@
-// Dense contraction P = V^dag R on the matrix cores (Algorithm 1 steps 4, 7 and 8).
+// Dense contraction P = V^dag R on the matrix cores (Algorithm 1's seeding projections of Eq. (1) and its
+// reorthogonalisation coefficients).
 //
 // V is nv vectors, R nr vectors, each n complex numbers stored as interleaved (re, im).
 // The complex product is a real GEMM over K = 2n reals:

@@ -1,6 +1,6 @@
 """Pins of the oracle's Algorithm 1 (Seed-CG) and CG against the mathematics (CPU only).
 
-  * Eq. (2): T = L U with the gamma/delta recurrences of step 6.
+  * Eq. (2): T = L U with the gamma/delta recurrences of its LU.
   * T from the CG coefficients (the Lanczos-CG correspondence, Saad 6.7.3).
   * The D-Lanczos iterate x^1 equals the CG iterate, and beta_i |zeta_i/delta_i| equals
     the true residual norm.

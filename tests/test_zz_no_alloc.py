@@ -1,4 +1,4 @@
-"""seedcg_project_noalloc: the contraction P = V^dag R of Algorithm 1 steps 4, 7 and 8 with its
+"""seedcg_project_noalloc: the contraction P = V^dag R of Algorithm 1 (seeding and reorthogonalisation) with its
 split-K partials in the library's static device array, against seedcg_project (which allocates
 its partials) on the same inputs.
 

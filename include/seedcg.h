@@ -56,8 +56,8 @@ typedef enum {
     SEEDCG_MIXED_FP32_CG = 3         /* FP64 Lanczos, basis and seeding (Algorithm 1 as in
                                         FP64); FP32 stencil and CG with FP64 reliable updates.
                                         For operators with near-zero modes, where an FP32
-                                        basis loses the seeding gain. No deflation or
-                                        learned preconditioner.                             */
+                                        basis loses the seeding gain.  Deflation and the
+                                        learned K run in the CG's FP32.                     */
 } seedcg_prec;
 
 typedef struct {
@@ -74,13 +74,15 @@ typedef struct {
     int32_t reliable_every;   /* mixed precision: FP64 r = b - M x every n CG iterations         */
     int32_t seed_block;       /* seeding GEMM block b (1..32); 0 = 32                             */
     int32_t max_iter;         /* CG iterations per right-hand side in solve_rest                 */
-    int32_t precond;          /* 0: none                                                         */
+    int32_t precond;          /* 0: none; 1: solve_rest runs PCG with the learned K K^dag once
+                                 train_precond has accepted a K (seedcg_use_precond sets it)       */
     int32_t autotune;         /* 1: choose the stencil launch shapes (lanes per site, vectors per
                                  workgroup) by timing the candidates once per lattice shape;
                                  0: the fixed default (two lanes per site, one vector each)     */
-    int32_t deflate;          /* 0: plain CG in solve_rest; n > 0: deflated CG with the n (<= 24)
-                                 lowest Ritz vectors of the last solve_seed's T, lifted by its
-                                 stored basis (one configuration, no learned preconditioner)      */
+    int32_t deflate;          /* 0: plain CG in solve_rest; n > 0: deflated CG (deflated PCG with the
+                                 learned K) with the n (<= 24) lowest Ritz vectors of the last
+                                 solve_seed's T, lifted by its stored basis; one configuration,
+                                 at most 24 right-hand sides per solve_rest                        */
     void* stream;             /* hipStream_t; NULL = the null stream                             */
 } seedcg_params;
 
@@ -104,7 +106,7 @@ typedef struct {
     double* est_relres;
     /* filled by the library */
     double orth_loss_max;     /* solve_seed: largest |v_j^dag v_i| / ||v_i|| (j < i) met by a
-                                 reorthogonalisation pass (step 8) before it acted; 0 without any pass */
+                                 reorthogonalisation pass of Algorithm 1 before it acted; 0 without any pass */
     double t_train_s;         /* solve_rest: seconds of the train_precond whose K it applied (0 if none) */
 } seedcg_report;
 
@@ -189,7 +191,7 @@ seedcg_status seedcg_get_ritz(seedcg_t h, double* theta, int32_t cap, int32_t* n
    device vector v in the even-site layout. */
 seedcg_status seedcg_get_basis_vector(seedcg_t h, int32_t i, double* v);
 
-/* Building blocks of Algorithm 1 steps 4, 7 and 8 on flat complex vectors (device pointers,
+/* Building blocks of Algorithm 1 (seeding of Eq. 1, reorthogonalisation) on flat complex vectors (device pointers,
    any common element order): P = V^dag R, with V nv vectors and R nr vectors of n complex
    each, P an nv x nr row-major complex matrix (device).  This is the dense contraction that
    seeds the other right-hand sides and computes the reorthogonalisation coefficients. */
@@ -209,7 +211,7 @@ seedcg_status seedcg_project_noalloc(seedcg_t h, const double* Vv, int32_t nv, c
                                      int64_t n, double* P);
 
 /* X += W E: W nw vectors, E an nw x nx row-major complex matrix (device), X nx vectors,
-   n complex each (the seeding update of Algorithm 1 step 7, x^j += eta^j w_i, blocked). */
+   n complex each (the seeding update of Eq. (1), x^j += eta^j w_i, blocked). */
 seedcg_status seedcg_update(seedcg_t h, const double* W, int32_t nw, const double* E, double* X,
                             int32_t nx, int64_t n);
 
@@ -223,6 +225,22 @@ seedcg_status seedcg_set_timing(seedcg_t h, int32_t sample_every, int32_t max_sa
    their total flops (1320 per site and vector), and the number of stencil launches seen. */
 seedcg_status seedcg_get_timing(seedcg_t h, double* out);
 
+/* The sampled stencil launches of get_timing, by launch kind: rows of 8 doubles in out (HOST, cap
+   rows): link/spinor format (0 FP64, 1 FP32, 2 FP32 with BF16 links, 3 FP64 two-row links, 4 FP32
+   two-row links), vectors per launch, 1 if the CG update is fused into the launch, lanes per site,
+   vectors per workgroup, then the sampled launches, their total milliseconds and their total
+   algorithmic bytes.  *n receives the number of kinds (rows beyond cap are not written). */
+seedcg_status seedcg_get_timing_kinds(seedcg_t h, double* out, int32_t cap, int32_t* n);
+
+/* y = M x applied reps times back to back to nvec (1..25) internal vectors (zeros; the stencil's
+   work does not depend on the values) and timed with a pair of hipEvents on the stream: the D^dag D
+   rate of section 3's operator in FP64 (inner = 0) or in the CG's inner precision (inner = 1).
+   out (HOST, 4 doubles): milliseconds per application, its algorithmic bytes with the links in the
+   stored format (each of the four hops reads every link once for all vectors; 120 V spinor reals per
+   vector), the same with whole 3x3 links (288 V link reals), and the format code of the links (as in
+   seedcg_get_timing_kinds).  One configuration per handle. */
+seedcg_status seedcg_time_M(seedcg_t h, int32_t inner, int32_t nvec, int32_t reps, double* out);
+
 /* ---- learned preconditioner P = K K^dag (an addition to the paper's method) -------------------
    K = R_e L_3 L_2 L_1 E_e on full-lattice 12-spinors: E_e embeds an even-site vector (zero on odd
    sites), R_e restricts to the even sites, and each layer is
@@ -232,13 +250,31 @@ seedcg_status seedcg_get_timing(seedcg_t h, double* out);
    (x) 1) T_{-d}.  Weights are 3 x 9 complex 4x4 spin matrices, [layer][d][a][b], 432 complex
    (interleaved re, im), HOST arrays.  P is applied in FP32. */
 
-/* Trains K by `steps` Adam steps (learning rate lr, betas 0.9 / 0.999, eps 1e-8) from K = 1 on
-   the loss mean_s |K K^dag y_s - u_s|^2 / |u_s|^2 over u_s = the n_ritz lowest Ritz vectors of T
-   (V s, T s = theta s, from the last solve_seed) and n_lanczos stored basis vectors, y_s = M u_s.
-   out (HOST, 6 doubles, may be NULL): initial loss, final loss, seconds, Ritz vectors used,
-   training vectors, accepted (1 if the final loss is at most half the initial one; a K that is not
-   accepted is not used by solve_rest, which then runs plain CG: the fallback).
-   Needs the basis of the last solve_seed (SEEDCG_ERR_STATE otherwise). */
+/* Trains K by `steps` Adam steps (learning rate lr, betas 0.9 / 0.999, eps 1e-8, minibatches of two
+   pairs) on the loss mean_s |K K^dag y_s - u_s|^2 / |u_s|^2 over u_s = the n_ritz lowest Ritz vectors
+   of T (V s, T s = theta s, from the last solve_seed) and n_lanczos stored basis vectors (normalised
+   CG residuals) with their components along those Ritz vectors removed, y_s = M u_s with the CG's
+   operator.  Training starts from K = 1 + kappa^2 H_eo H_oe, the first term of the Neumann series of
+   A^{-1} (section 3), in every layer w_0 = 1, w_{+mu} = c (1 - gamma_mu), w_{-mu} = c (1 + gamma_mu),
+   c = kappa / sqrt(3).  (K = 1 with zero hops is a saddle point where no hop weight has a gradient.)
+   Plain Seed-CG then judges: RHS 2 of the last solve_seed (RHS 1 if it had one) is solved from its
+   seeded guess to tol, once with plain CG and once each with PCG (P = K K^dag) under the start and the
+   trained weights, by the solver of solve_rest (deflated when params.deflate > 0).  solve_rest iterates
+   on all the seeded systems at once, where M's links are read once for every vector and K's cost is
+   paid per vector, so each candidate's iterations are priced with the time of one application of M
+   (plus one of K K^dag) to that many vectors, timed with events: the cheapest wins.  The K with fewer
+   iterations of the two is kept as the weights.  If a K wins it is kept and solve_rest applies it when
+   precond is on; otherwise solve_rest runs plain CG (the fallback).
+   out (HOST, 18 doubles, may be NULL): initial loss, final loss, training seconds, Ritz vectors used,
+   training vectors, accepted (1 if a K won), the judge's seconds for plain CG, the start K and the
+   trained K on one system, their iterations in the same order, the choice (0 plain CG, 1 start K,
+   2 trained K), the seconds of one M and of one K K^dag on the seeded systems, and the predicted
+   seconds of plain CG, the start K and the trained K there.  Each Adam step takes the loss on a band of
+   two t-slices (seedcg_precond_loss_grad_band), the bands stepping through the lattice, with a step
+   size that decays from lr to 0 on a half cosine; the whole-lattice loss, taken at four checkpoints,
+   picks the trained weights (the start's when no checkpoint is lower, and the judge then runs the
+   start K once for both).  The final loss reported is the kept weights' whole-lattice loss.
+   Needs the basis of the last solve_seed (SEEDCG_ERR_STATE otherwise); one configuration per handle. */
 seedcg_status seedcg_train_precond(seedcg_t h, int32_t steps, int32_t n_ritz, int32_t n_lanczos, double lr, double* out);
 
 /* on != 0: solve_rest runs preconditioned CG with P = K K^dag (needs weights). */
@@ -254,6 +290,13 @@ seedcg_status seedcg_apply_P(seedcg_t h, const double* x, double* y, int32_t nve
 /* The training loss for pairs (U, Y) of S even-site vectors (device, canonical layout, 1 <= S <= 32)
    at the current weights, and its Wirtinger gradient dL/d(conj w) (HOST, 432 complex, may be NULL). */
 seedcg_status seedcg_precond_loss_grad(seedcg_t h, const double* U, const double* Y, int32_t S, double* loss, double* grad);
+
+/* The same loss and gradient with both norms of each pair taken over the even sites of the band of
+   t-slices [t0, t0 + nt) mod Lt only, the form each Adam step of train_precond takes (bands of two
+   slices stepping through the lattice).  Only the slices that loss depends on are computed: K K^dag
+   reaches six hops, so a band wider than Lt - 13 slices is taken as the whole lattice, as is nt = 0. */
+seedcg_status seedcg_precond_loss_grad_band(seedcg_t h, const double* U, const double* Y, int32_t S, int32_t t0, int32_t nt,
+                                            double* loss, double* grad);
 
 /* ---- batches of configurations (an addition to the paper's method) -------------------------
    Many independent gauge configurations, possibly of different lattice shapes, each with nrhs

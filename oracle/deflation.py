@@ -32,9 +32,14 @@ def ritz(V, alpha, beta, nev):
     return theta[:nev], U
 
 
-def deflated_cg(matvec, b, x0, W, *, tol, max_iter=100000, history=False):
+def deflated_cg(matvec, b, x0, W, *, tol, max_iter=100000, history=False, precond=None):
     """Deflated CG on M x = b from x0 with deflation vectors W (rows).  Returns (x, iterations,
-    true relative residual[, per-iteration (r, p) pairs when history is set])."""
+    true relative residual[, per-iteration (r, p) pairs when history is set]).
+
+    With a preconditioner P (precond(r) = P r, Hermitian positive definite) this is the deflated PCG
+    of the same paper: z_j = P r_j takes the place of r_j in the direction, p_0 = z_0 - W^T G^{-1} Z^dag z_0,
+    p_{j+1} = z_{j+1} + b_j p_j - W^T G^{-1} Z^dag z_{j+1}, with a_j = r_j^dag z_j / p_j^dag M p_j and
+    b_j = r_{j+1}^dag z_{j+1} / r_j^dag z_j; W^dag r_j = 0 and W^dag M p_j = 0 still hold."""
     b = np.asarray(b, dtype=np.complex128)
     x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.complex128, copy=True)
     W = np.atleast_2d(np.asarray(W, dtype=np.complex128)) if len(W) else np.zeros((0, b.size), np.complex128)
@@ -52,31 +57,33 @@ def deflated_cg(matvec, b, x0, W, *, tol, max_iter=100000, history=False):
         out = (x, 0, float(np.linalg.norm(r)) / bn)
         return out + (hist,) if history else out
 
-    def direction(r, p=None, beta=0.0):
-        d = r if p is None else r + beta * p
+    def direction(z, p=None, beta=0.0):
+        d = z if p is None else z + beta * p
         if nw:
-            d = d - W.T @ Ginv_apply(Z.conj() @ r)    # - W mu, mu = G^-1 Z^dag r
+            d = d - W.T @ Ginv_apply(Z.conj() @ z)    # - W mu, mu = G^-1 Z^dag z
         return d
 
-    p = direction(r)
-    rr = float(np.vdot(r, r).real)
+    P = precond if precond is not None else (lambda v: v)
+    z = P(r)
+    p = direction(z)
+    rz = float(np.vdot(r, z).real)
     it = 0
     while it < max_iter:
         if history:
             hist.append((r.copy(), p.copy()))
         q = matvec(p)
-        a = rr / float(np.vdot(p, q).real)
+        a = rz / float(np.vdot(p, q).real)
         x = x + a * p
         r = r - a * q
         it += 1
-        rr_new = float(np.vdot(r, r).real)
-        if math.sqrt(rr_new) <= tol * bn:
+        if float(np.linalg.norm(r)) <= tol * bn:
             r = b - matvec(x)
-            rr_new = float(np.vdot(r, r).real)
-            if math.sqrt(rr_new) <= tol * bn:
+            if float(np.linalg.norm(r)) <= tol * bn:
                 break
-        p = direction(r, p, rr_new / rr)
-        rr = rr_new
+        z = P(r)
+        rz_new = float(np.vdot(r, z).real)
+        p = direction(z, p, rz_new / rz)
+        rz = rz_new
     res = float(np.linalg.norm(b - matvec(x))) / bn
     out = (x, it, res)
     return out + (hist,) if history else out

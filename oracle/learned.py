@@ -13,8 +13,9 @@ The paper has no preconditioner; this follows the workload's reading of one:
   * the loss over training pairs (u_s, y_s = M u_s): mean_s ||K K^dag y_s - u_s||^2 / ||u_s||^2;
   * complex weights, Wirtinger gradients dL/d(conj w), and Adam on Re w and Im w as independent
     reals (dL/dRe w = 2 Re dL/dconj(w), dL/dIm w = 2 Im dL/dconj(w)).
-Weights are an array W[layer 0..2][d 0..8][4][4]; the initial K is the identity
-(w_{l,0} = 1, all hops 0).
+Weights are an array W[layer 0..2][d 0..8][4][4].  Training starts from the first Neumann term of
+A^{-1}, K = 1 + kappa^2 H_eo H_oe (neumann_weights); the identity (w_{l,0} = 1, all hops 0) is a
+saddle point of the loss.
 
 Parity: pinned by finite differences of the loss, by K = 1 at initialisation, by gauge
 covariance and by Hermiticity/positivity of K K^dag on a dense small lattice.
@@ -116,12 +117,42 @@ def identity_weights():
     return W
 
 
-def loss(lat, W, Y, Uv):
-    """mean_s ||K K^dag y_s - u_s||^2 / ||u_s||^2 for Y, Uv of shape (S, Vh, 4, 3)."""
+def neumann_weights(kappa):
+    """The training start: K = 1 + kappa^2 H_eo H_oe, the first term of the Neumann series of
+    A^{-1} = (1 - kappa^2 H_eo H_oe)^{-1} (section 3's even-odd operator).
+
+    Every layer gets w_0 = 1 and the Wilson hop's spin factors w_{+mu} = c (1 - gamma_mu),
+    w_{-mu} = c (1 + gamma_mu).  Through E_e and R_e only the paths of zero and two hops reach an
+    even site; the two-hop paths come from three layer pairs (w_0 of the third layer, of the second,
+    or of the first), so c^2 = kappa^2 / 3.  The identity start (all hops 0) is a saddle point of
+    the loss: every surviving hop path carries two hop weights, so the gradient of each one vanishes.
+    """
+    from oracle.dense import gamma_matrices
+    g = gamma_matrices()
+    c = kappa / np.sqrt(3.0)
+    W = identity_weights()
+    for mu in range(4):
+        W[:, 1 + mu] = c * (np.eye(4) - g[mu])
+        W[:, 5 + mu] = c * (np.eye(4) + g[mu])
+    return W
+
+
+def band_mask(lat, t0, nt):
+    """Even sites whose t lies in the band [t0, t0 + nt) mod Lt (the whole lattice for nt = None)."""
+    t = _coords(lat.dims)[lat.even, 3]
+    if nt is None:
+        return np.ones(t.shape, dtype=bool)
+    return ((t - t0) % lat.dims[3]) < nt
+
+
+def loss(lat, W, Y, Uv, band=None):
+    """mean_s ||K K^dag y_s - u_s||^2 / ||u_s||^2 for Y, Uv of shape (S, Vh, 4, 3); with band = (t0, nt)
+    both norms are taken over the even sites of that band of t-slices only."""
+    mask = band_mask(lat, *band) if band else band_mask(lat, 0, None)
     Z = apply_P(lat, W, Y)
-    e = Z - Uv
+    e = (Z - Uv)[:, mask]
     num = np.sum(np.abs(e) ** 2, axis=(1, 2, 3))
-    den = np.sum(np.abs(Uv) ** 2, axis=(1, 2, 3))
+    den = np.sum(np.abs(Uv[:, mask]) ** 2, axis=(1, 2, 3))
     return float(np.mean(num / den))
 
 
@@ -130,8 +161,10 @@ def _outer_grad(g, t):
     return np.einsum("xac,xbc->ab", g.reshape(-1, 4, 3), t.reshape(-1, 4, 3).conj())
 
 
-def grad(lat, W, Y, Uv):
-    """Wirtinger gradient dL/d(conj W), same shape as W, by reverse mode through the six layers."""
+def grad(lat, W, Y, Uv, band=None):
+    """Wirtinger gradient dL/d(conj W), same shape as W, by reverse mode through the six layers (of the
+    loss on a band of t-slices when band = (t0, nt) is given)."""
+    mask = band_mask(lat, *band) if band else band_mask(lat, 0, None)
     S = Y.shape[0]
     G = np.zeros_like(W)
     # forward, keeping every layer input
@@ -142,8 +175,9 @@ def grad(lat, W, Y, Uv):
     for l in range(NLAYER):                    # K: layers 1, 2, 3
         b.append(layer(lat, W[l], b[-1]))
     Z = lat.restrict(b[-1])
-    den = np.sum(np.abs(Uv) ** 2, axis=(1, 2, 3))
+    den = np.sum(np.abs(Uv[:, mask]) ** 2, axis=(1, 2, 3))
     g_even = (Z - Uv) / (S * den)[:, None, None, None]
+    g_even[:, ~mask] = 0.0
     # backward through K
     g = lat.embed(g_even)
     for l in reversed(range(NLAYER)):

@@ -63,7 +63,7 @@ void sum_partials(const double* part, int64_t nb, int nvec, double* out, bool sq
 
 void lz_start(LzState* st, const double* r2part, int64_t nb, const double* b2part, double* beta, const Launch& L);
 void lz_first_vector(bool fp32, const LzState* st, const void* r, void* v, int64_t n, const Launch& L);
-// steps 5-6: alpha_i from the np stencil partials apart, the LU scalars, and the vector updates
+// the Lanczos coefficient alpha_i from the np stencil partials apart, the LU scalars of Eq. (2), and the vector updates
 void lz_update(bool fp32, int i, LzState* st, const double* apart, int64_t np, const LzArrays& a, void* f, const void* v,
                const void* wprev, void* wout, double* x1, double* f2part, int64_t n, const Launch& L);
 void lz_beta(int i, LzState* st, const double* part, int64_t np, const LzArrays& a, const Launch& L);
@@ -92,15 +92,24 @@ void cg_p(bool fp32, const CgVec* cg, const int32_t* vec_map, int nact, void* P,
           const Launch& L);
 
 // learned preconditioner K (learned.hip); fields are [vec][parity][12][Vh] complex FP32
+// pmask: output parities computed (1 even, 2 odd, 3 both); zero_odd_input: the input is E_e x;
+// t0, nt: only the band of t-slices [t0, t0 + nt) mod Lt (nt = 0: the whole lattice); in_t0, in_nt: the
+// input is zero outside that band (in_nt = 0: no such band)
 void k_layer(const Geom& g, const void* links32, const void* in, void* out, const void* W, bool dagger, const int32_t* vmap,
-             int nvec, bool zero_odd_input, hipStream_t s);
+             int nvec, bool zero_odd_input, hipStream_t s, int pmask = 3, int t0 = 0, int nt = 0, int in_t0 = 0, int in_nt = 0);
+// the weight gradient of one layer, summed over the sites of pmask and the band (where the incoming gradient lives)
 void k_grad(const Geom& g, const void* links32, const void* gv, const void* in, bool dagger, int nvec, double* part, double* Gtot,
-            hipStream_t s);
+            hipStream_t s, bool zero_odd_input = false, int pmask = 3, int t0 = 0, int nt = 0);
+// |u|^2 partials of S even-site FP32 vectors over a band of t-slices (k_band_blocks per vector)
+void k_band_norm(const Geom& g, int t0, int nt, const void* u, int S, double* part, hipStream_t s);
+int64_t k_band_blocks(const Geom& g, int t0, int nt);
 int64_t k_grad_blocks(const Geom& g);
 void k_embed(bool x32, const void* x, void* full, int64_t n, const int32_t* vmap, int nvec, hipStream_t s);
 void k_restrict(bool x32, const void* full, void* x, int64_t n, const int32_t* vmap, int nvec, hipStream_t s);
 void k_zero_odd(void* full, int64_t n, int nvec, hipStream_t s);
-void k_residual(const void* zfull, const void* u, const double* unorm2, void* gfull, int64_t n, int S, double* part, hipStream_t s);
+// the loss residual on the even sites of the band (nt = 0: all of them)
+void k_residual(const void* zfull, const void* u, const double* unorm2, void* gfull, int64_t n, int S, double* part, hipStream_t s,
+                const Geom& g, int t0 = 0, int nt = 0);
 int64_t k_residual_blocks(int64_t n);
 void k_adam(double* Wm, void* W32, double* G, double* m, double* v, int t, double lr, int n, hipStream_t s);
 // X = V S for nout <= 16 outputs (S: m x nout row-major); X in FP32, or FP64 with x64

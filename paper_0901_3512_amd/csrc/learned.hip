@@ -18,71 +18,117 @@ __device__ inline int adj_dir(int d) { return d == 0 ? 0 : (d <= 4 ? d + 4 : d -
 
 struct Site {
     int x, y, z, t, xh;
-    int64_t row;
+    int row;
 };
-__device__ inline Site site_of(const Geom& g, int p, int64_t h) {
+// 32-bit site decoding (Vh < 2^31 at every lattice this library accepts)
+__device__ inline Site site_of(const Geom& g, int p, int h) {
     Site s;
-    s.xh = (int)(h % g.Lxh);
-    int64_t r = h / g.Lxh;
-    s.y = (int)(r % g.L[1]);
-    r /= g.L[1];
-    s.z = (int)(r % g.L[2]);
-    s.t = (int)(r / g.L[2]);
+    const int Lxh = g.Lxh, Ly = g.L[1], Lz = g.L[2];
+    s.xh = h % Lxh;
+    int r = h / Lxh;
+    s.y = r % Ly;
+    r /= Ly;
+    s.z = r % Lz;
+    s.t = r / Lz;
     s.x = 2 * s.xh + ((s.y + s.z + s.t + p) & 1);
     s.row = h - s.xh;
     return s;
 }
 // checkerboard index of the neighbour in direction mu, step +-1, and the boundary sign
-__device__ inline int64_t nb_index(const Geom& g, const Site& s, int mu, int step, float& sign) {
-    const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
+__device__ inline int nb_index(const Geom& g, const Site& s, int mu, int step, float& sign) {
+    const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3], Lxh = g.Lxh;
     sign = 1.f;
-    if (mu == 0) return s.row + (((s.x + step + Lx) % Lx) >> 1);
-    if (mu == 1) return s.xh + (int64_t)g.Lxh * (((s.y + step + Ly) % Ly) + (int64_t)Ly * (s.z + (int64_t)Lz * s.t));
-    if (mu == 2) return s.xh + (int64_t)g.Lxh * (s.y + (int64_t)Ly * (((s.z + step + Lz) % Lz) + (int64_t)Lz * s.t));
+    if (mu == 0) {
+        int xn = s.x + step;
+        xn = xn < 0 ? xn + Lx : (xn >= Lx ? xn - Lx : xn);
+        return s.row + (xn >> 1);
+    }
+    if (mu == 1) {
+        int yn = s.y + step;
+        yn = yn < 0 ? yn + Ly : (yn >= Ly ? yn - Ly : yn);
+        return s.xh + Lxh * (yn + Ly * (s.z + Lz * s.t));
+    }
+    if (mu == 2) {
+        int zn = s.z + step;
+        zn = zn < 0 ? zn + Lz : (zn >= Lz ? zn - Lz : zn);
+        return s.xh + Lxh * (s.y + Ly * (zn + Lz * s.t));
+    }
     if ((step == 1 && s.t == Lt - 1) || (step == -1 && s.t == 0)) sign = (float)g.t_bc;
-    return s.xh + (int64_t)g.Lxh * (s.y + (int64_t)Ly * (s.z + (int64_t)Lz * ((s.t + step + Lt) % Lt)));
+    int tn = s.t + step;
+    tn = tn < 0 ? tn + Lt : (tn >= Lt ? tn - Lt : tn);
+    return s.xh + Lxh * (s.y + Ly * (s.z + Lz * tn));
 }
 
-// (T_d in)(p, h) for one site: 4 spins x 3 colours
-__device__ inline void transport(const Geom& g, const cx<float>* __restrict__ links, const cx<float>* __restrict__ in,
-                                 int p, int64_t h, const Site& s, int d, cx<float> t[12]) {
-    const int64_t Vh = g.Vh;
-    if (d == 0) {
-        const cx<float>* src = in + (int64_t)p * 12 * Vh;
-#pragma unroll
-        for (int c = 0; c < 12; c++) t[c] = src[(int64_t)c * Vh + h];
-        return;
-    }
-    const int mu = (d - 1) & 3;
-    const bool fwd = d <= 4;
-    float sign;
-    const int64_t hn = nb_index(g, s, mu, fwd ? 1 : -1, sign);
-    const cx<float>* src = in + (int64_t)(1 - p) * 12 * Vh;
-    const int lp = fwd ? p : 1 - p;
-    const int64_t lh = fwd ? h : hn;
-    const cx<float>* lk = links + ((int64_t)(mu * 2 + lp) * 9) * Vh + lh;
+// the link of transport d at output site (p, h): U_mu(x) (d = +mu) or U_mu(x - mu) (d = -mu), read once
+// per site and direction and applied to every vector of the thread
+struct Hop {
     cx<float> u[9];
+    int hn;
+    float sign;
+    bool fwd;
+};
+__device__ inline void load_hop(const Geom& g, const cx<float>* __restrict__ links, int p, int h, const Site& s, int d, Hop& o) {
+    const int Vh = (int)g.Vh;
+    const int mu = (d - 1) & 3;
+    o.fwd = d <= 4;
+    o.hn = nb_index(g, s, mu, o.fwd ? 1 : -1, o.sign);
+    const int lp = o.fwd ? p : 1 - p;
+    const int lh = o.fwd ? h : o.hn;
+    const cx<float>* lk = links + (int64_t)((mu * 2 + lp) * 9) * Vh + lh;
 #pragma unroll
-    for (int c = 0; c < 9; c++) u[c] = lk[(int64_t)c * Vh];
+    for (int c = 0; c < 9; c++) o.u[c] = lk[(int64_t)c * Vh];
+}
+// (T_d src)(p, h) with the link of o; src is the field of one vector, [2][12][Vh]
+__device__ inline void apply_hop(const Hop& o, const cx<float>* __restrict__ src, int p, int Vh, cx<float> t[12]) {
+    const cx<float>* nb = src + (int64_t)(1 - p) * 12 * Vh + o.hn;
 #pragma unroll
     for (int sp = 0; sp < 4; sp++) {
         cx<float> v[3];
 #pragma unroll
-        for (int b = 0; b < 3; b++) v[b] = src[(int64_t)(3 * sp + b) * Vh + hn];
+        for (int b = 0; b < 3; b++) v[b] = nb[(int64_t)(3 * sp + b) * Vh];
 #pragma unroll
         for (int a = 0; a < 3; a++) {
             cx<float> acc = mk<float>(0.f, 0.f);
 #pragma unroll
-            for (int b = 0; b < 3; b++) acc = acc + (fwd ? cmul(u[a * 3 + b], v[b]) : cjmul(u[b * 3 + a], v[b]));
-            t[3 * sp + a] = sign * acc;
+            for (int b = 0; b < 3; b++) acc = acc + (o.fwd ? cmul(o.u[a * 3 + b], v[b]) : cjmul(o.u[b * 3 + a], v[b]));
+            t[3 * sp + a] = o.sign * acc;
         }
     }
 }
 
-// out = L in (dagger = 0) or L^dag in (dagger = 1), for the vectors listed in vmap (or 0..nvec-1)
+// Sites of a launch: the output parities of pmask (1 = even only, 2 = odd only, 3 = both) on the
+// band of nt consecutive t-slices starting at slice t0 (wrapping around the lattice; nt = Lt is the
+// whole lattice).  A t-slice holds S = Vh / Lt sites of each parity, contiguous in the checkerboard
+// index, so the grid index k runs over the selected parities, nt * S sites each.
+struct Band {
+    int t0, nt;
+};
+__device__ inline bool site_of_launch(const Geom& g, int pmask, Band b, int64_t k, int& p, int& h) {
+    const int S = (int)(g.Vh / g.L[3]);
+    const int per = b.nt * S;
+    const int np = pmask == 3 ? 2 : 1;
+    if (k >= (int64_t)np * per) return false;
+    const int kk = (int)k;
+    const int pi = kk / per;
+    const int rem = kk - pi * per;
+    p = pmask == 2 ? 1 : (pmask == 1 ? 0 : pi);
+    const int ts = rem / S;
+    int t = b.t0 + ts;
+    if (t >= g.L[3]) t -= g.L[3];
+    h = t * S + (rem - ts * S);
+    return true;
+}
+// with an even-only input (E_e x) the transport T_d vanishes at odd sites for d = 0 and at even
+// sites for the hops
+__device__ inline bool vanishes(int zero_odd_input, int d, int p) { return zero_odd_input && ((d == 0) ? (p == 1) : (p == 0)); }
+
+// out = L in (dagger = 0) or L^dag in (dagger = 1) on the output parities of pmask, for the vectors
+// listed in vmap (or 0..nvec-1): NV vectors per thread, every link read once per site and direction.
+template <int NV>
 __global__ __launch_bounds__(256) void k_layer_kernel(Geom g, const cx<float>* __restrict__ links, const cx<float>* __restrict__ in,
                                                       cx<float>* __restrict__ out, const cx<float>* __restrict__ W, int dagger,
-                                                      const int32_t* vmap, int zero_odd_input) {
+                                                      const int32_t* vmap, int nvec, int zero_odd_input, int pmask, Band band,
+                                                      Band in_band) {
     __shared__ cx<float> w[9 * 16];
     for (int k = threadIdx.x; k < 9 * 16; k += blockDim.x) {
         const int d = k / 16, e = k % 16, a = e / 4, b = e % 4;
@@ -94,62 +140,113 @@ __global__ __launch_bounds__(256) void k_layer_kernel(Geom g, const cx<float>* _
         }
     }
     __syncthreads();
-    const int vec = vmap ? vmap[blockIdx.y] : (int)blockIdx.y;
-    const int64_t Vh = g.Vh;
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= 2 * Vh) return;
-    const int p = (int)(k / Vh);
-    const int64_t h = k % Vh;
-    const cx<float>* src = in + (int64_t)vec * 24 * Vh;
-    cx<float>* dst = out + (int64_t)vec * 24 * Vh;
+    int p, h;
+    if (!site_of_launch(g, pmask, band, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, p, h)) return;
+    const int Vh = (int)g.Vh;
+    int vec[NV];
+#pragma unroll
+    for (int j = 0; j < NV; j++) {
+        const int slot = (int)blockIdx.y * NV + j;
+        vec[j] = slot < nvec ? (vmap ? vmap[slot] : slot) : -1;
+    }
     const Site s = site_of(g, p, h);
-    cx<float> acc[12];
+    cx<float> acc[NV][12];
 #pragma unroll
-    for (int c = 0; c < 12; c++) acc[c] = mk<float>(0.f, 0.f);
+    for (int j = 0; j < NV; j++)
+#pragma unroll
+        for (int c = 0; c < 12; c++) acc[j][c] = mk<float>(0.f, 0.f);
     for (int d = 0; d < 9; d++) {
-        // with an even-only input (E_e x) the odd-site terms vanish: skip them
-        if (zero_odd_input && ((d == 0) ? (p == 1) : (p == 0))) continue;
-        cx<float> t[12];
-        transport(g, links, src, p, h, s, d, t);
+        if (vanishes(zero_odd_input, d, p)) continue;
+        // an input known to vanish outside its band of t-slices (a back-propagated gradient): skip
+        // the terms that would read it there
+        if (in_band.nt < g.L[3]) {
+            int tin = s.t;
+            if (d == 4) tin = s.t + 1 == g.L[3] ? 0 : s.t + 1;
+            if (d == 8) tin = s.t == 0 ? g.L[3] - 1 : s.t - 1;
+            const int dt = tin - in_band.t0 < 0 ? tin - in_band.t0 + g.L[3] : tin - in_band.t0;
+            if (dt >= in_band.nt) continue;
+        }
+        Hop o;
+        if (d) load_hop(g, links, p, h, s, d, o);
 #pragma unroll
-        for (int a = 0; a < 4; a++)
+        for (int j = 0; j < NV; j++) {
+            if (vec[j] < 0) continue;
+            const cx<float>* src = in + (int64_t)vec[j] * 24 * Vh;
+            cx<float> t[12];
+            if (d == 0) {
 #pragma unroll
-            for (int b = 0; b < 4; b++) {
-                const cx<float> wab = w[d * 16 + a * 4 + b];
-#pragma unroll
-                for (int c = 0; c < 3; c++) acc[3 * a + c] = acc[3 * a + c] + cmul(wab, t[3 * b + c]);
+                for (int c = 0; c < 12; c++) t[c] = src[(int64_t)(p * 12 + c) * Vh + h];
+            } else {
+                apply_hop(o, src, p, Vh, t);
             }
+#pragma unroll
+            for (int a = 0; a < 4; a++)
+#pragma unroll
+                for (int b = 0; b < 4; b++) {
+                    const cx<float> wab = w[d * 16 + a * 4 + b];
+#pragma unroll
+                    for (int c = 0; c < 3; c++) acc[j][3 * a + c] = acc[j][3 * a + c] + cmul(wab, t[3 * b + c]);
+                }
+        }
     }
 #pragma unroll
-    for (int c = 0; c < 12; c++) dst[(int64_t)p * 12 * Vh + (int64_t)c * Vh + h] = acc[c];
+    for (int j = 0; j < NV; j++) {
+        if (vec[j] < 0) continue;
+        cx<float>* dst = out + (int64_t)vec[j] * 24 * Vh + (int64_t)p * 12 * Vh + h;
+#pragma unroll
+        for (int c = 0; c < 12; c++) dst[(int64_t)c * Vh] = acc[j][c];
+    }
 }
+
+// the band of t-slices [t0, t0 + nt) (mod Lt); nt <= 0 or nt >= Lt is the whole lattice
+Band make_band(const Geom& g, int t0, int nt) {
+    if (nt <= 0 || nt >= g.L[3]) return Band{0, g.L[3]};
+    t0 %= g.L[3];
+    if (t0 < 0) t0 += g.L[3];
+    return Band{t0, nt};
+}
+int64_t k_sites(const Geom& g, int pmask, Band b) { return (int64_t)(pmask == 3 ? 2 : 1) * b.nt * (g.Vh / g.L[3]); }
 
 void k_layer(const Geom& g, const void* links32, const void* in, void* out, const void* W, bool dagger, const int32_t* vmap,
-             int nvec, bool zero_odd_input, hipStream_t s) {
-    const dim3 grid((unsigned)((2 * g.Vh + 255) / 256), (unsigned)nvec);
-    hipLaunchKernelGGL(k_layer_kernel, grid, dim3(256), 0, s, g, (const cx<float>*)links32, (const cx<float>*)in, (cx<float>*)out,
-                       (const cx<float>*)W, (int)dagger, vmap, (int)zero_odd_input);
+             int nvec, bool zero_odd_input, hipStream_t s, int pmask, int t0, int nt, int in_t0, int in_nt) {
+    constexpr int NV = 4;
+    const Band b = make_band(g, t0, nt), ib = make_band(g, in_t0, in_nt);
+    const dim3 grid((unsigned)((k_sites(g, pmask, b) + 255) / 256), (unsigned)((nvec + NV - 1) / NV));
+    if (nvec == 1)
+        hipLaunchKernelGGL(k_layer_kernel<1>, dim3(grid.x, 1), dim3(256), 0, s, g, (const cx<float>*)links32, (const cx<float>*)in,
+                           (cx<float>*)out, (const cx<float>*)W, (int)dagger, vmap, nvec, (int)zero_odd_input, pmask, b, ib);
+    else
+        hipLaunchKernelGGL(k_layer_kernel<NV>, grid, dim3(256), 0, s, g, (const cx<float>*)links32, (const cx<float>*)in,
+                           (cx<float>*)out, (const cx<float>*)W, (int)dagger, vmap, nvec, (int)zero_odd_input, pmask, b, ib);
 }
 
-// partial sums over sites, colours and vectors of g[a][c] conj((T_dt in)[b][c]) for direction
-// d = blockIdx.y, with dt = d (layer L) or dt = -d (layer L^dag).  part[d][block][16] complex.
+// partial sums over the sites of pmask, colours and vectors of g[a][c] conj((T_dt in)[b][c]) for
+// direction d = blockIdx.y, with dt = d (layer L) or dt = -d (layer L^dag); each link is read once per
+// site for all vectors.  part[d][block][16] complex.
 __global__ __launch_bounds__(256) void k_grad_kernel(Geom g, const cx<float>* __restrict__ links, const cx<float>* __restrict__ gv,
-                                                     const cx<float>* __restrict__ in, int dagger, int nvec, double* part) {
+                                                     const cx<float>* __restrict__ in, int dagger, int nvec, int zero_odd_input,
+                                                     int pmask, Band band, double* part) {
     __shared__ double lds[4 * 32];
     const int d = blockIdx.y;
     const int dt = dagger ? adj_dir(d) : d;
-    const int64_t Vh = g.Vh;
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int Vh = (int)g.Vh;
     double acc[32];
 #pragma unroll
     for (int e = 0; e < 32; e++) acc[e] = 0.0;
-    if (k < 2 * Vh) {
-        const int p = (int)(k / Vh);
-        const int64_t h = k % Vh;
+    int p, h;
+    if (site_of_launch(g, pmask, band, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, p, h) && !vanishes(zero_odd_input, dt, p)) {
         const Site s = site_of(g, p, h);
+        Hop o;
+        if (dt) load_hop(g, links, p, h, s, dt, o);
         for (int v = 0; v < nvec; v++) {
+            const cx<float>* src = in + (int64_t)v * 24 * Vh;
             cx<float> t[12], q[12];
-            transport(g, links, in + (int64_t)v * 24 * Vh, p, h, s, dt, t);
+            if (dt == 0) {
+#pragma unroll
+                for (int c = 0; c < 12; c++) t[c] = src[(int64_t)(p * 12 + c) * Vh + h];
+            } else {
+                apply_hop(o, src, p, Vh, t);
+            }
             const cx<float>* gs = gv + (int64_t)v * 24 * Vh + (int64_t)p * 12 * Vh;
 #pragma unroll
             for (int c = 0; c < 12; c++) q[c] = gs[(int64_t)c * Vh + h];
@@ -209,10 +306,11 @@ __global__ void k_grad_reduce_kernel(const double* part, int64_t nblocks, int da
 int64_t k_grad_blocks(const Geom& g) { return (2 * g.Vh + 255) / 256; }
 
 void k_grad(const Geom& g, const void* links32, const void* gv, const void* in, bool dagger, int nvec, double* part, double* Gtot,
-            hipStream_t s) {
-    const int64_t nb = k_grad_blocks(g);
+            hipStream_t s, bool zero_odd_input, int pmask, int t0, int nt) {
+    const Band b = make_band(g, t0, nt);
+    const int64_t nb = (k_sites(g, pmask, b) + 255) / 256;
     hipLaunchKernelGGL(k_grad_kernel, dim3((unsigned)nb, 9), dim3(256), 0, s, g, (const cx<float>*)links32, (const cx<float>*)gv,
-                       (const cx<float>*)in, (int)dagger, nvec, part);
+                       (const cx<float>*)in, (int)dagger, nvec, (int)zero_odd_input, pmask, b, part);
     hipLaunchKernelGGL(k_grad_reduce_kernel, dim3(9), dim3(256), 0, s, part, nb, (int)dagger, Gtot);
 }
 
@@ -260,10 +358,31 @@ void k_zero_odd(void* full, int64_t n, int nvec, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_odd_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)nvec), dim3(256), 0, s, (cx<float>*)full, n);
 }
 
-// training residual: e = z - u on the even sites; loss partials |e|^2 / |u|^2; gradient field
-// g = E_e e / (S |u|^2)
-__global__ void k_residual_kernel(const cx<float>* __restrict__ zfull, const cx<float>* __restrict__ u, const double* unorm2,
-                                  cx<float>* __restrict__ gfull, int64_t n, int S, double* part) {
+// |u|^2 partials over the even sites of a band (the loss's normalisation), one row of blocks per vector
+__global__ void k_band_norm_kernel(Geom g, Band b, const cx<float>* __restrict__ u, int64_t n, double* part) {
+    __shared__ double lds[4];
+    const int v = blockIdx.y;
+    int p, h;
+    double s = 0.0;
+    if (site_of_launch(g, 1, b, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, p, h))
+        for (int c = 0; c < 12; c++) {
+            const cx<float> a = u[(int64_t)v * n + (int64_t)c * g.Vh + h];
+            s += (double)a.re * a.re + (double)a.im * a.im;
+        }
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) part[(int64_t)v * gridDim.x + blockIdx.x] = s;
+}
+int64_t k_band_blocks(const Geom& g, int t0, int nt) { return (k_sites(g, 1, make_band(g, t0, nt)) + 255) / 256; }
+void k_band_norm(const Geom& g, int t0, int nt, const void* u, int S, double* part, hipStream_t s) {
+    const Band b = make_band(g, t0, nt);
+    hipLaunchKernelGGL(k_band_norm_kernel, dim3((unsigned)k_band_blocks(g, t0, nt), (unsigned)S), dim3(256), 0, s, g, b,
+                       (const cx<float>*)u, 12 * g.Vh, part);
+}
+
+// training residual on the even sites of a band: e = z - u there; loss partials |e|^2 / |u|^2; the
+// gradient field g = E_e e / (S |u|^2) on the band and 0 everywhere else (every site of g is written)
+__global__ void k_residual_kernel(Geom g, Band b, const cx<float>* __restrict__ zfull, const cx<float>* __restrict__ u,
+                                  const double* unorm2, cx<float>* __restrict__ gfull, int64_t n, int S, double* part) {
     __shared__ double lds[4];
     const int v = blockIdx.y;
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -271,20 +390,27 @@ __global__ void k_residual_kernel(const cx<float>* __restrict__ zfull, const cx<
     if (k < 2 * n) {
         cx<float> gval = mk<float>(0.f, 0.f);
         if (k < n) {
-            const cx<float> z = zfull[(int64_t)v * 2 * n + k], uu = u[(int64_t)v * n + k];
-            const double er = (double)z.re - uu.re, ei = (double)z.im - uu.im;
-            e2 = er * er + ei * ei;
-            const double sc = 1.0 / ((double)S * unorm2[v]);
-            gval = mk<float>((float)(er * sc), (float)(ei * sc));
+            const int h = (int)(k % g.Vh);
+            const int t = h / (int)(g.Vh / g.L[3]);
+            const int dt = t - b.t0 < 0 ? t - b.t0 + g.L[3] : t - b.t0;
+            if (dt < b.nt) {
+                const cx<float> z = zfull[(int64_t)v * 2 * n + k], uu = u[(int64_t)v * n + k];
+                const double er = (double)z.re - uu.re, ei = (double)z.im - uu.im;
+                e2 = er * er + ei * ei;
+                const double sc = 1.0 / ((double)S * unorm2[v]);
+                gval = mk<float>((float)(er * sc), (float)(ei * sc));
+            }
         }
         gfull[(int64_t)v * 2 * n + k] = gval;
     }
     const double s = block_sum(e2, lds);
     if (threadIdx.x == 0) part[(int64_t)v * gridDim.x + blockIdx.x] = s / unorm2[v];
 }
-void k_residual(const void* zfull, const void* u, const double* unorm2, void* gfull, int64_t n, int S, double* part, hipStream_t s) {
-    hipLaunchKernelGGL(k_residual_kernel, dim3((unsigned)((2 * n + 255) / 256), (unsigned)S), dim3(256), 0, s, (const cx<float>*)zfull,
-                       (const cx<float>*)u, unorm2, (cx<float>*)gfull, n, S, part);
+void k_residual(const void* zfull, const void* u, const double* unorm2, void* gfull, int64_t n, int S, double* part, hipStream_t s,
+                const Geom& g, int t0, int nt) {
+    const Band b = make_band(g, t0, nt);
+    hipLaunchKernelGGL(k_residual_kernel, dim3((unsigned)((2 * n + 255) / 256), (unsigned)S), dim3(256), 0, s, g, b,
+                       (const cx<float>*)zfull, (const cx<float>*)u, unorm2, (cx<float>*)gfull, n, S, part);
 }
 int64_t k_residual_blocks(int64_t n) { return (2 * n + 255) / 256; }
 

@@ -1,16 +1,17 @@
 // Host runtime and C ABI of the Seed-CG library (Algorithm 1 of the paper and plain CG).
 //
 // The host only enqueues kernels: every scalar recurrence of Algorithm 1 (alpha, beta,
-// delta, gamma, zeta, the eta recurrence of step 7, the residual estimate, the choice of m)
+// delta, gamma, zeta, the eta recurrence of the seeding, the residual estimate, the choice of m)
 // lives in device memory and is updated by one-workgroup kernels, so an iteration never
 // waits for the host.  The host reads the device state once every `sync_every` steps to
 // learn whether the run has ended; kernels of steps beyond the device's m return at once.
 //
-// Step 7 is blocked: the projections v_i^dag r_0^j of up to b consecutive steps are one
-// MFMA contraction P = V_blk^dag R_0 taken before step 8 touches v_i, and the updates
+// The seeding of Eq. (1) is blocked: the projections v_i^dag r_0^j of up to b consecutive steps are one
+// MFMA contraction P = V_blk^dag R_0 taken before the reorthogonalisation touches v_i, and the updates
 // x^j += eta^j_i w_i of the block are one pass X += W_blk E over a ring of b w-vectors.
-// The result is the paper's step 7 exactly, summed in another order.
+// The result is the paper's seeding update exactly, summed in another order.
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <complex>
 #include <map>
@@ -173,7 +174,7 @@ struct seedcg_s {
     DBuf cgv, vmap, Pv, Rv, Qv, R64, cgpart, rrpart, respart, norms;
     // learned preconditioner P = K K^dag (FP32 weights, FP64 Adam master copy)
     bool k_ready = false;
-    bool k_accepted = false;   // the trained K passed the acceptance test (loss at most halved)
+    bool k_accepted = false;   // K won the judge against plain CG (solve_rest applies it when asked)
     DBuf kW32, kWm, kG, kAm, kAv, kpart, klinks32, kU, kY, kun2, klpart, kS, kfield, pfa, pfb, Zv, rzpart;
     // deflated CG: W (the lowest Ritz vectors of T lifted by V), Z = M W, (W^dag M W)^{-1},
     // coefficient blocks, Ritz coefficients
@@ -183,11 +184,21 @@ struct seedcg_s {
     std::vector<double> ritz_theta;
     int k_steps = 0, k_train_vecs = 0, k_ritz = 0;
     double k_loss0 = 0.0, k_loss1 = 0.0, k_t_train = 0.0;
+    // the judge: seconds and iterations of plain CG, PCG with the start K and with the trained K on one
+    // system, the seconds of one application of M and of K K^dag to the seeded systems, the predicted
+    // cost of each candidate there; the choice (0 plain CG, 1 start K, 2 trained K) and the judged
+    // system's starting residual
+    std::vector<double> k_judge = std::vector<double>(11, 0.0);
+    int k_choice = 0;
+    double k_judge_r0 = 0.0;
+    DBuf klossv, kbn;
     // sampled timing of the stencil launches (hipEvent pairs on the handle's stream)
     int timing_every = 0;
     int64_t hop_count = 0;
     std::vector<hipEvent_t> ev0, ev1;
     std::vector<double> ev_bytes, ev_flops;
+    std::vector<std::array<double, 5>> ev_kind;
+    std::map<std::array<double, 5>, std::array<double, 3>> t_kind;   // kind -> launches, ms, bytes
     size_t ev_used = 0;
     double t_ms = 0.0, t_bytes = 0.0, t_flops = 0.0;
     int64_t t_launches = 0;
@@ -266,6 +277,8 @@ void hop(seedcg_s* h, Prec pr, const void* L, const void* in, void* out, int par
         const double per = e.red == 3 ? 5.0 * ss + 2.0 * 8.0 : ss * (2 + (e.combine ? 1 : 0) + (e.z ? 1 : 0) + (e.red == 1 ? 1 : 0));
         h->ev_bytes.push_back(Vh * lr * sl + (double)nvec * Vh * 24.0 * per);
         h->ev_flops.push_back((double)nvec * Vh * 1320.0);
+        // the launch kind: precision and link format, vectors, fused CG update, lanes per site, vectors per workgroup
+        h->ev_kind.push_back({(double)pr, (double)nvec, (double)(e.red == 3), (double)tps, (double)vb});
         h->ev_used++;
     }
 }
@@ -589,7 +602,7 @@ void solve_seed_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report* rep) {
 
     pack_in(h, io, false, h->Bint.p, nrhs);
     pack_in(h, io, true, h->Xint.p, nrhs);
-    // Step 1: r_0^j = b^j - M x_0^j (FP64), kept in the inner precision for the projections;
+    // initial residuals r_0^j = b^j - M x_0^j (FP64), kept in the inner precision for the projections;
     // RHS 1's goes straight to v_1 after scaling.
     h->r64.ensure(nrhs * h->vec_bytes(false));
     {
@@ -626,7 +639,7 @@ void solve_seed_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report* rep) {
         x.past = h->p.past_factor;
     }
     to_cfg(h, st, hs.data(), sizeof(LzState));
-    // Step 2: beta_0 = ||r_0^1||, v_1 = r_0^1 / beta_0
+    // Lanczos start: beta_0 = ||r_0^1||, v_1 = r_0^1 / beta_0
     const int64_t nb = norm2_blocks(N);
     norm2_partials(false, h->r64.p, N, 1, h->f2a.as<double>(), L);
     norm2_partials(false, h->Bint.p, N, 1, h->f2a.as<double>() + nb, L);
@@ -652,7 +665,7 @@ void solve_seed_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report* rep) {
         for (; i <= i_end; i++) {
             void* vi = (char*)h->basis.p + (int64_t)(i - 1) * h->vec_bytes(lo);
             const void* vprev = i > 1 ? (const char*)h->basis.p + (int64_t)(i - 2) * h->vec_bytes(lo) : nullptr;
-            // Step 5: f = M v_i - beta_{i-1} v_{i-1}, alpha_i = v_i^dag f
+            // three-term recurrence: f = M v_i - beta_{i-1} v_{i-1}, alpha_i = v_i^dag f
             MOpts o;
             o.z = vprev;
             o.cz_dev = vprev ? &A.beta[i - 1] : nullptr;
@@ -663,22 +676,22 @@ void solve_seed_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report* rep) {
             o.gate_m = &st->m;
             o.gate_i = i;
             apply_M_int(h, lo, vi, h->f.p, 1, o);
-            // Step 6: alpha_i and the LU scalars; f -= alpha_i v_i; w_i; x^1 += zeta_i w_i
+            // alpha_i and the LU row of Eq. (2); f -= alpha_i v_i; w_i; x^1 += zeta_i w_i
             const int slot = i - i0;
             void* wout = (char*)h->wring.p + (int64_t)slot * h->vec_bytes(lo);
             const void* wprev = (const char*)h->wring.p + (int64_t)(slot > 0 ? slot - 1 : last_slot) * h->vec_bytes(lo);
             lz_update(lo, i, st, h->apart.as<double>(), nsb, A, h->f.p, vi, wprev, wout, h->x1.as<double>(), h->f2a.as<double>(),
                       N, L);
-            // Step 7, blocked (before step 8 can touch v_i)
+            // seeding of Eq. (1), blocked (before the reorthogonalisation can touch v_i)
             const bool reorth_now = k > 0 && i % k == 0;
             if (slot + 1 == b || reorth_now) {
                 flush_seed_block(h, i0, i, nrhs);
                 last_slot = slot;
                 i0 = i + 1;
             }
-            // Step 8
+            // periodic reorthogonalisation
             if (reorth_now) reorthogonalise(h, i);
-            // Step 9
+            // beta_i and the next Lanczos vector
             lz_beta(i, st, reorth_now ? h->f2b.as<double>() : h->f2a.as<double>(), nb, A, L);
             lz_next(lo, i, st, A.beta, h->f.p, (char*)h->basis.p + (int64_t)i * h->vec_bytes(lo), N, L);
         }
@@ -734,7 +747,7 @@ constexpr int K_NREAL = K_LAYERS * K_NW * 2;  // reals updated by Adam
 
 // FP32 links for the transports of K (the inner links when they are FP32, else a copy)
 const void* k_links(seedcg_s* h) {
-    if (h->lo && h->lo_prec == P32) return h->links_lo.p;
+    if (h->cg_lo && h->lo_prec == P32) return h->links_lo.p;
     if (!h->klinks32.p) {
         // repack from the FP64 internal copy: same layout, entry by entry
         h->klinks32.ensure(4 * h->g.V * 9 * 8);
@@ -752,14 +765,15 @@ void apply_P(seedcg_s* h, bool low, const void* r, void* z, const int32_t* vmap,
     h->pfb.ensure((int64_t)nalloc * 2 * N * 8);
     const void* L = k_links(h);
     k_embed(low, r, h->pfa.p, N, vmap, nact, h->s);
-    // K^dag = R_e L_1^dag L_2^dag L_3^dag E_e
-    k_layer(h->g, L, h->pfa.p, h->pfb.p, k_weights(h, 2), true, vmap, nact, true, h->s);
-    k_layer(h->g, L, h->pfb.p, h->pfa.p, k_weights(h, 1), true, vmap, nact, false, h->s);
-    k_layer(h->g, L, h->pfa.p, h->pfb.p, k_weights(h, 0), true, vmap, nact, false, h->s);
-    // K = R_e L_3 L_2 L_1 E_e (the odd half of pfb is ignored by the zero-odd layer)
-    k_layer(h->g, L, h->pfb.p, h->pfa.p, k_weights(h, 0), false, vmap, nact, true, h->s);
-    k_layer(h->g, L, h->pfa.p, h->pfb.p, k_weights(h, 1), false, vmap, nact, false, h->s);
-    k_layer(h->g, L, h->pfb.p, h->pfa.p, k_weights(h, 2), false, vmap, nact, false, h->s);
+    // K^dag = R_e L_1^dag L_2^dag L_3^dag E_e: the first layer sees an even-only input and the last
+    // one's odd outputs are dropped by R_e, so each of K^dag and K costs four half-lattice hops
+    k_layer(h->g, L, h->pfa.p, h->pfb.p, k_weights(h, 2), true, vmap, nact, true, h->s, 3);
+    k_layer(h->g, L, h->pfb.p, h->pfa.p, k_weights(h, 1), true, vmap, nact, false, h->s, 3);
+    k_layer(h->g, L, h->pfa.p, h->pfb.p, k_weights(h, 0), true, vmap, nact, false, h->s, 1);
+    // K = R_e L_3 L_2 L_1 E_e (the zero-odd layer reads only the even half of pfb)
+    k_layer(h->g, L, h->pfb.p, h->pfa.p, k_weights(h, 0), false, vmap, nact, true, h->s, 3);
+    k_layer(h->g, L, h->pfa.p, h->pfb.p, k_weights(h, 1), false, vmap, nact, false, h->s, 3);
+    k_layer(h->g, L, h->pfb.p, h->pfa.p, k_weights(h, 2), false, vmap, nact, false, h->s, 1);
     k_restrict(low, h->pfa.p, z, N, vmap, nact, h->s);
 }
 
@@ -824,57 +838,85 @@ void ritz_lowest(const std::vector<double>& a, const std::vector<double>& b, int
         for (int i = 0; i < m; i++) vecs[(size_t)i * nout + j] = ys[j][i];
 }
 
-// One pass over the training set (kU, kY, kun2 of S vectors): the loss and, if `backward`,
-// its gradient accumulated into kG.  Returns the loss when `want_loss` (else 0).
-double k_pass(seedcg_s* h, int S, bool backward, bool want_loss) {
+// One pass over training pairs off .. off+S-1 of (kU, kY): the loss of those pairs (their mean) and,
+// if `backward`, its gradient accumulated into kG.  Returns the loss when `want_loss` (else 0).
+// With band_nt > 0 the loss is taken on the even sites of the t-slices [band_t0, band_t0 + band_nt)
+// only, and every layer computes just the slices that loss depends on: K K^dag reaches 6 hops, so
+// the j-th of the six layers (K^dag's three, then K's) is needed on the band widened by 6 - j slices
+// on either side, and the gradient of its output lives there too.
+double k_pass(seedcg_s* h, int off, int S, bool backward, bool want_loss, int band_t0 = 0, int band_nt = 0) {
     const int64_t N = h->N;
+    const int Lt = h->g.L[3];
+    if (band_nt <= 0 || band_nt + 12 >= Lt) band_nt = 0;   // whole lattice
     const int64_t fb = (int64_t)S * 2 * N * 8;
     h->kfield.ensure(10 * fb);
     auto F = [&](int i) { return (void*)((char*)h->kfield.p + i * fb); };
     void *a0 = F(0), *a1 = F(1), *a2 = F(2), *a3 = F(3), *b0 = F(4), *b1 = F(5), *b2 = F(6), *b3 = F(7), *g = F(8), *gt = F(9);
+    const void* Uo = (const char*)h->kU.p + (int64_t)off * N * 8;
+    const void* Yo = (const char*)h->kY.p + (int64_t)off * N * 8;
     h->kpart.ensure(9 * k_grad_blocks(h->g) * 32 * sizeof(double));
     const int64_t nbr = k_residual_blocks(N);
-    h->klpart.ensure(std::max<int64_t>(norm2_blocks(N), nbr) * S * sizeof(double));
+    const int64_t nbb = k_band_blocks(h->g, band_t0, band_nt);
+    h->klpart.ensure(std::max({norm2_blocks(N), nbr, nbb}) * S * sizeof(double));
+    h->kbn.ensure(32 * sizeof(double));
     const void* L = k_links(h);
     double* Gl[3] = {h->kG.as<double>(), h->kG.as<double>() + K_NW * 2, h->kG.as<double>() + 2 * K_NW * 2};
+    // the band of layer j = 1..6 (the loss band widened by 6 - j slices each side); 0 slices: whole lattice
+    auto bt0 = [&](int j) { return band_nt ? band_t0 - (6 - j) : 0; };
+    auto bnt = [&](int j) { return band_nt ? band_nt + 2 * (6 - j) : 0; };
+    auto ks = h->s;
+    // |u|^2 on the loss band, the loss's normalisation
+    k_band_norm(h->g, bt0(6), bnt(6), Uo, S, h->klpart.as<double>(), ks);
+    sum_partials(h->klpart.as<double>(), nbb, S, h->kbn.as<double>(), false, ks);
     // forward: a = K^dag chain on E_e y, b = K chain on E_e R_e a3
-    k_embed(true, h->kY.p, a0, N, nullptr, S, h->s);
-    k_layer(h->g, L, a0, a1, k_weights(h, 2), true, nullptr, S, true, h->s);
-    k_layer(h->g, L, a1, a2, k_weights(h, 1), true, nullptr, S, false, h->s);
-    k_layer(h->g, L, a2, a3, k_weights(h, 0), true, nullptr, S, false, h->s);
-    HIPCHK(hipMemcpyAsync(b0, a3, fb, hipMemcpyDeviceToDevice, h->s));
-    k_zero_odd(b0, N, S, h->s);
-    k_layer(h->g, L, b0, b1, k_weights(h, 0), false, nullptr, S, true, h->s);
-    k_layer(h->g, L, b1, b2, k_weights(h, 1), false, nullptr, S, false, h->s);
-    k_layer(h->g, L, b2, b3, k_weights(h, 2), false, nullptr, S, false, h->s);
-    k_residual(b3, h->kU.p, h->kun2.as<double>(), g, N, S, h->klpart.as<double>(), h->s);
+    // (odd halves that a later step never reads are not computed: pmask 1 = even outputs only)
+    k_embed(true, Yo, a0, N, nullptr, S, ks);
+    k_layer(h->g, L, a0, a1, k_weights(h, 2), true, nullptr, S, true, ks, 3, bt0(1), bnt(1));
+    k_layer(h->g, L, a1, a2, k_weights(h, 1), true, nullptr, S, false, ks, 3, bt0(2), bnt(2));
+    k_layer(h->g, L, a2, a3, k_weights(h, 0), true, nullptr, S, false, ks, 1, bt0(3), bnt(3));
+    HIPCHK(hipMemcpyAsync(b0, a3, fb, hipMemcpyDeviceToDevice, ks));
+    k_zero_odd(b0, N, S, ks);
+    k_layer(h->g, L, b0, b1, k_weights(h, 0), false, nullptr, S, true, ks, 3, bt0(4), bnt(4));
+    k_layer(h->g, L, b1, b2, k_weights(h, 1), false, nullptr, S, false, ks, 3, bt0(5), bnt(5));
+    k_layer(h->g, L, b2, b3, k_weights(h, 2), false, nullptr, S, false, ks, 1, bt0(6), bnt(6));
+    k_residual(b3, Uo, h->kbn.as<double>(), g, N, S, h->klpart.as<double>(), ks, h->g, bt0(6), bnt(6));
     double loss = 0.0;
     if (want_loss) {
-        DBuf lossv;
-        lossv.ensure(S * sizeof(double));
-        sum_partials(h->klpart.as<double>(), nbr, S, lossv.as<double>(), false, h->s);
+        h->klossv.ensure(32 * sizeof(double));
+        sum_partials(h->klpart.as<double>(), nbr, S, h->klossv.as<double>(), false, ks);
         std::vector<double> lv(S);
-        HIPCHK(hipMemcpyAsync(lv.data(), lossv.p, S * sizeof(double), hipMemcpyDeviceToHost, h->s));
-        HIPCHK(hipStreamSynchronize(h->s));
+        HIPCHK(hipMemcpyAsync(lv.data(), h->klossv.p, S * sizeof(double), hipMemcpyDeviceToHost, ks));
+        HIPCHK(hipStreamSynchronize(ks));
         for (double v : lv) loss += v;
         loss /= S;
     }
     if (!backward) return loss;
-    // backward through K (layers 3, 2, 1) ...
-    k_grad(h->g, L, g, b2, false, S, h->kpart.as<double>(), Gl[2], h->s);
-    k_layer(h->g, L, g, gt, k_weights(h, 2), true, nullptr, S, false, h->s);
-    k_grad(h->g, L, gt, b1, false, S, h->kpart.as<double>(), Gl[1], h->s);
-    k_layer(h->g, L, gt, g, k_weights(h, 1), true, nullptr, S, false, h->s);
-    k_grad(h->g, L, g, b0, false, S, h->kpart.as<double>(), Gl[0], h->s);
-    k_layer(h->g, L, g, gt, k_weights(h, 0), true, nullptr, S, false, h->s);
-    k_zero_odd(gt, N, S, h->s);  // through E_e R_e
-    // ... and through K^dag (layers 1^dag, 2^dag, 3^dag)
-    k_grad(h->g, L, gt, a2, true, S, h->kpart.as<double>(), Gl[0], h->s);
-    k_layer(h->g, L, gt, g, k_weights(h, 0), false, nullptr, S, false, h->s);
-    k_grad(h->g, L, g, a1, true, S, h->kpart.as<double>(), Gl[1], h->s);
-    k_layer(h->g, L, g, gt, k_weights(h, 1), false, nullptr, S, false, h->s);
-    k_grad(h->g, L, gt, a0, true, S, h->kpart.as<double>(), Gl[2], h->s);
+    // backward through K (layers 3, 2, 1) and then K^dag (1^dag, 2^dag, 3^dag): the gradient of layer
+    // j's output lives on band j, and each back-propagated field is zero outside its band (the layer
+    // that reads it is told so)
+    k_grad(h->g, L, g, b2, false, S, h->kpart.as<double>(), Gl[2], ks, false, 1, bt0(6), bnt(6));
+    k_layer(h->g, L, g, gt, k_weights(h, 2), true, nullptr, S, true, ks, 3, bt0(5), bnt(5), bt0(6), bnt(6));
+    k_grad(h->g, L, gt, b1, false, S, h->kpart.as<double>(), Gl[1], ks, false, 3, bt0(5), bnt(5));
+    k_layer(h->g, L, gt, g, k_weights(h, 1), true, nullptr, S, false, ks, 3, bt0(4), bnt(4), bt0(5), bnt(5));
+    k_grad(h->g, L, g, b0, false, S, h->kpart.as<double>(), Gl[0], ks, true, 3, bt0(4), bnt(4));
+    k_layer(h->g, L, g, gt, k_weights(h, 0), true, nullptr, S, false, ks, 1, bt0(3), bnt(3), bt0(4), bnt(4));
+    k_zero_odd(gt, N, S, ks);  // through E_e R_e
+    k_grad(h->g, L, gt, a2, true, S, h->kpart.as<double>(), Gl[0], ks, false, 1, bt0(3), bnt(3));
+    k_layer(h->g, L, gt, g, k_weights(h, 0), false, nullptr, S, true, ks, 3, bt0(2), bnt(2), bt0(3), bnt(3));
+    k_grad(h->g, L, g, a1, true, S, h->kpart.as<double>(), Gl[1], ks, false, 3, bt0(2), bnt(2));
+    k_layer(h->g, L, g, gt, k_weights(h, 1), false, nullptr, S, false, ks, 3, bt0(1), bnt(1), bt0(2), bnt(2));
+    k_grad(h->g, L, gt, a0, true, S, h->kpart.as<double>(), Gl[2], ks, true, 3, bt0(1), bnt(1));
     return loss;
+}
+
+// mean loss over all S training pairs, taken in minibatches of mb
+double k_loss_all(seedcg_s* h, int S, int mb) {
+    double sum = 0.0;
+    for (int off = 0; off < S; off += mb) {
+        const int n = std::min(mb, S - off);
+        sum += n * k_pass(h, off, n, false, true);
+    }
+    return sum / S;
 }
 
 void k_alloc_weights(seedcg_s* h) {
@@ -894,11 +936,91 @@ void k_set_weights(seedcg_s* h, const double* w) {
     HIPCHK(hipStreamSynchronize(h->s));
 }
 
-// Trains K on the Ritz vectors of T (lowest n_ritz) and n_lanczos stored basis vectors, with
-// targets y = M u (inner precision), by `steps` Adam steps of the loss
-// mean_s |K K^dag y_s - u_s|^2 / |u_s|^2 from K = 1.
+// The training start: K = 1 + kappa^2 H_eo H_oe, the first term of the Neumann series of A^{-1}
+// (section 3: A = 1 - kappa^2 H_eo H_oe).  Each layer has w_0 = 1 and the Wilson hop's spin factors
+// w_{+mu} = c (1 - gamma_mu), w_{-mu} = c (1 + gamma_mu) with c = kappa / sqrt(3): through E_e and R_e
+// only paths of zero and two hops reach an even site, and three layer pairs carry the two hops.
+// (K = 1 with zero hops is a saddle point: every surviving hop path has two hop weights, so no hop
+// weight would ever receive a gradient.)
+std::vector<double> k_neumann_weights(double kappa) {
+    // Euclidean chiral basis, gamma_5 = diag(1, 1, -1, -1): gamma_k = [[0, -i s_k], [i s_k, 0]],
+    // gamma_4 = [[0, 1], [1, 0]]; entries as (re, im) over rows a and columns b
+    using C = std::complex<double>;
+    const C I(0.0, 1.0);
+    const C sig[3][2][2] = {{{0.0, 1.0}, {1.0, 0.0}}, {{0.0, -I}, {I, 0.0}}, {{1.0, 0.0}, {0.0, -1.0}}};
+    C gam[4][4][4] = {};
+    for (int k = 0; k < 3; k++)
+        for (int a = 0; a < 2; a++)
+            for (int b = 0; b < 2; b++) {
+                gam[k][a][2 + b] = -I * sig[k][a][b];
+                gam[k][2 + a][b] = I * sig[k][a][b];
+            }
+    for (int a = 0; a < 2; a++) gam[3][a][2 + a] = gam[3][2 + a][a] = 1.0;
+    const double c = kappa / std::sqrt(3.0);
+    std::vector<double> w(K_NREAL, 0.0);
+    auto put = [&](int l, int d, int a, int b, C v) {
+        w[(size_t)l * K_NW * 2 + 2 * (d * 16 + a * 4 + b)] = v.real();
+        w[(size_t)l * K_NW * 2 + 2 * (d * 16 + a * 4 + b) + 1] = v.imag();
+    };
+    for (int l = 0; l < K_LAYERS; l++)
+        for (int a = 0; a < 4; a++) {
+            put(l, 0, a, a, 1.0);
+            for (int mu = 0; mu < 4; mu++)
+                for (int b = 0; b < 4; b++) {
+                    const C id = a == b ? 1.0 : 0.0;
+                    put(l, 1 + mu, a, b, c * (id - gam[mu][a][b]));
+                    put(l, 5 + mu, a, b, c * (id + gam[mu][a][b]));
+                }
+        }
+    return w;
+}
+
+seedcg_status solve_rest_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report* rep);
+
+// The judge of the learned K (plain Seed-CG is the fallback and the judge): one system (canonical
+// layout b, starting guess x0) until its FP64 true relative residual is at most `target`, with the solver of
+// solve_rest (deflated when params.deflate asks for it), with or without K.  Returns the wall seconds
+// (infinite when it did not get there) and fills the iterations.
+double k_judge_run(seedcg_s* h, bool use_k, const double* b, const double* x0, double* x, double target, int& iters) {
+    HIPCHK(hipMemcpyAsync(x, x0, h->vec_bytes(false), hipMemcpyDeviceToDevice, h->s));
+    const seedcg_params saved = h->p;
+    const bool acc = h->k_accepted;
+    h->p.precond = use_k ? 1 : 0;
+    h->k_accepted = use_k;
+    h->p.tol = std::max(h->p.tol, target);
+    Io io;
+    io.B = b;
+    io.X = x;
+    int32_t it = 0;
+    double rr = 0.0;
+    seedcg_report rep{};
+    rep.iters = &it;
+    rep.true_relres = &rr;
+    const double t0 = now_s();
+    seedcg_status st = SEEDCG_OK;
+    try {
+        st = solve_rest_impl(h, io, 1, &rep);
+    } catch (...) {
+        h->p = saved;
+        h->k_accepted = acc;
+        throw;
+    }
+    const double t = now_s() - t0;
+    h->p = saved;
+    h->k_accepted = acc;
+    iters = it;
+    return st == SEEDCG_OK ? t : 1e300;
+}
+
+// Trains K by `steps` Adam steps from the Neumann start on pairs (u, y = M u) from the last seed
+// solve: the n_ritz lowest Ritz vectors of T and n_lanczos stored basis vectors (normalised CG
+// residuals) with their components along those Ritz vectors removed.  Minibatches of two pairs.
+// Then the judge solves RHS 2 from its seeded guess with plain CG, PCG with the start K and PCG with
+// the trained K, and prices each one's iterations with the time of one application of M (and of K K^dag)
+// to all the seeded systems; solve_rest applies K only when one of the K candidates is cheaper.
 void train_precond_impl(seedcg_s* h, int steps, int n_ritz, int n_lanczos, double lr) {
     if (!h->have_seed || !h->basis.p) throw StateError{"train_precond: needs the basis of a seed solve"};
+    if (h->ncfg != 1) throw StateError{"train_precond: one configuration per handle"};
     if (steps < 0 || n_ritz < 0 || n_lanczos < 0 || n_ritz > 16 || n_ritz + n_lanczos > 32 || n_ritz + n_lanczos < 1)
         throw ArgError{"train_precond: 0 <= n_ritz <= 16, 1 <= n_ritz + n_lanczos <= 32, steps >= 0"};
     const double t0 = now_s();
@@ -929,8 +1051,34 @@ void train_precond_impl(seedcg_s* h, int steps, int n_ritz, int n_lanczos, doubl
         convert(h->lo, true, (const char*)h->basis.p + (int64_t)(i - 1) * h->vec_bytes(h->lo), (char*)h->kU.p + (int64_t)(nr + j) * N * 8,
                 N, h->s);
     }
-    // y = M u with the inner operator
-    if (h->lo) {
+    if (nr > 0 && nl > 0) {
+        // u -= W (W^dag u) for the basis vectors, W the Ritz vectors (orthonormal to FP32 rounding)
+        for (int j0 = 0; j0 < nl; j0 += 24) {
+            const int nj = std::min(24, nl - j0);
+            ProjArgs a{};
+            a.V = h->kU.p;
+            a.ldv = N;
+            a.nv = nr;
+            for (int j = 0; j < nj; j++) a.R[j] = (const char*)h->kU.p + (int64_t)(nr + j0 + j) * N * 8;
+            a.nr = nj;
+            a.n = N;
+            a.kchunk = kchunk_for(N, 1024);
+            a.part_stride = 2 * 32 * 24;
+            h->projpart.ensure((size_t)proj_chunks(N, a.kchunk) * a.part_stride * sizeof(double));
+            a.part = h->projpart.as<double>();
+            h->kS.ensure(std::max(Sv.size(), (size_t)2 * 32 * 24) * sizeof(double));
+            project(true, a, 1, h->kS.as<double>(), h->s, true);
+            std::vector<double> P((size_t)2 * nr * nj);
+            HIPCHK(hipMemcpyAsync(P.data(), h->kS.p, P.size() * sizeof(double), hipMemcpyDeviceToHost, h->s));
+            HIPCHK(hipStreamSynchronize(h->s));
+            for (double& v : P) v = -v;
+            HIPCHK(hipMemcpyAsync(h->kS.p, P.data(), P.size() * sizeof(double), hipMemcpyHostToDevice, h->s));
+            seed_update(true, true, h->kU.p, nr, h->kS.as<double>(), (char*)h->kU.p + (int64_t)(nr + j0) * N * 8, nj, N, nullptr,
+                        h->s);
+        }
+    }
+    // y = M u with the operator the CG iterates with (the inner precision)
+    if (h->cg_lo) {
         apply_M_int(h, true, h->kU.p, h->kY.p, S, MOpts{});
     } else {
         DBuf u64, y64;
@@ -946,35 +1094,132 @@ void train_precond_impl(seedcg_s* h, int steps, int n_ritz, int n_lanczos, doubl
     h->klpart.ensure(std::max<int64_t>(nbn, k_residual_blocks(N)) * S * sizeof(double));
     norm2_partials(true, h->kU.p, N, S, h->klpart.as<double>(), h->s);
     sum_partials(h->klpart.as<double>(), nbn, S, h->kun2.as<double>(), false, h->s);
-    // weights: K = 1; Adam state cleared
-    std::vector<double> w0(K_NREAL, 0.0);
-    for (int l = 0; l < K_LAYERS; l++)
-        for (int a = 0; a < 4; a++) w0[(size_t)l * K_NW * 2 + 2 * (a * 4 + a)] = 1.0;
+    // weights: the Neumann start; Adam state cleared
+    const std::vector<double> w0 = k_neumann_weights(h->p.kappa);
     k_set_weights(h, w0.data());
     HIPCHK(hipMemsetAsync(h->kG.p, 0, K_NREAL * sizeof(double), h->s));
     HIPCHK(hipMemsetAsync(h->kAm.p, 0, K_NREAL * sizeof(double), h->s));
     HIPCHK(hipMemsetAsync(h->kAv.p, 0, K_NREAL * sizeof(double), h->s));
-    for (int step = 0; step <= steps; step++) {
-        const bool last = step == steps;
-        const double loss = k_pass(h, S, !last, step == 0 || last);
-        if (step == 0) h->k_loss0 = loss;
-        if (last) {
-            h->k_loss1 = loss;
-            break;
-        }
-        k_adam(h->kWm.as<double>(), h->kW32.p, h->kG.as<double>(), h->kAm.as<double>(), h->kAv.as<double>(), step + 1, lr, K_NREAL,
+    const int mb = std::min(2, S);
+    h->k_loss0 = k_loss_all(h, S, mb);
+    // each Adam step takes the loss on a band of two t-slices, the bands stepping through the lattice;
+    // the step size decays from lr to 0 on a half cosine, and the full-lattice loss at four checkpoints
+    // decides which weights are kept (the start's, unless one of them is lower)
+    const int band = 2;
+    const int every = std::max(1, (steps + 3) / 4);
+    std::vector<double> best = w0;
+    double best_loss = h->k_loss0;
+    for (int step = 0; step < steps; step++) {
+        const int o = (int)(((int64_t)step * mb) % S);
+        k_pass(h, o, std::min(mb, S - o), true, false, (int)(((int64_t)step * band) % h->g.L[3]), band);
+        const double lr_t = lr * 0.5 * (1.0 + std::cos(M_PI * step / steps));
+        k_adam(h->kWm.as<double>(), h->kW32.p, h->kG.as<double>(), h->kAm.as<double>(), h->kAv.as<double>(), step + 1, lr_t, K_NREAL,
                h->s);
         if ((step & 63) == 63) check_launch();
+        if ((step + 1) % every == 0 || step + 1 == steps) {
+            check_launch();
+            const double l = k_loss_all(h, S, mb);
+            if (l < best_loss) {
+                best_loss = l;
+                HIPCHK(hipMemcpyAsync(best.data(), h->kWm.p, K_NREAL * sizeof(double), hipMemcpyDeviceToHost, h->s));
+                HIPCHK(hipStreamSynchronize(h->s));
+            }
+        }
     }
     check_launch();
-    HIPCHK(hipStreamSynchronize(h->s));
+    k_set_weights(h, best.data());
+    h->k_loss1 = best_loss;
     h->kfield.release();
     h->k_steps = steps;
     h->k_ready = true;
-    // acceptance: keep K only if training at least halved the loss; otherwise solve_rest falls back
-    // to plain CG even when asked to precondition
-    h->k_accepted = h->k_loss1 <= 0.5 * h->k_loss0;
     h->k_t_train = now_s() - t0;
+    // the judge: time to solve RHS 2 (RHS 1 with one system) to tol from its seeded guess, with each
+    // candidate
+    std::vector<double> wt(K_NREAL);
+    HIPCHK(hipMemcpyAsync(wt.data(), h->kWm.p, K_NREAL * sizeof(double), hipMemcpyDeviceToHost, h->s));
+    HIPCHK(hipStreamSynchronize(h->s));
+    const int j = std::min(1, h->seed_nrhs - 1);
+    DBuf bj, x0, xj;
+    bj.ensure(h->vec_bytes(false));
+    x0.ensure(h->vec_bytes(false));
+    xj.ensure(h->vec_bytes(false));
+    unpack_vec(false, (const char*)h->Bint.p + (int64_t)j * h->vec_bytes(false), bj.as<double>(), h->g.Vh, 1, h->L());
+    unpack_vec(false, (const char*)h->Xint.p + (int64_t)j * h->vec_bytes(false), x0.as<double>(), h->g.Vh, 1, h->L());
+    {
+        // its starting FP64 true relative residual
+        MOpts o;
+        o.sy = -1.0;
+        o.z = (const char*)h->Bint.p + (int64_t)j * h->vec_bytes(false);
+        o.cz_host = 1.0;
+        apply_M_int(h, false, (const char*)h->Xint.p + (int64_t)j * h->vec_bytes(false), h->r64.p, 1, o);
+        norm2_partials(false, h->r64.p, N, 1, h->klpart.as<double>(), h->s);
+        norm2_partials(false, (const char*)h->Bint.p + (int64_t)j * h->vec_bytes(false), N, 1, h->klpart.as<double>() + nbn, h->s);
+        h->klossv.ensure(32 * sizeof(double));
+        sum_partials(h->klpart.as<double>(), nbn, 2, h->klossv.as<double>(), true, h->s);
+        double nr2[2];
+        HIPCHK(hipMemcpyAsync(nr2, h->klossv.p, 2 * sizeof(double), hipMemcpyDeviceToHost, h->s));
+        HIPCHK(hipStreamSynchronize(h->s));
+        h->k_judge_r0 = nr2[1] > 0.0 ? nr2[0] / nr2[1] : 0.0;
+    }
+    const double target = h->p.tol;   // the whole solve: K may help early and lose late (near-zero modes)
+    int it_cg = 0, it_start = 0, it_trained = 0;
+    const bool moved = best_loss < h->k_loss0;   // otherwise the kept weights are the start's
+    double t_trained = 0.0;
+    if (moved) t_trained = k_judge_run(h, true, bj.as<double>(), x0.as<double>(), xj.as<double>(), target, it_trained);
+    k_set_weights(h, w0.data());
+    const double t_start = k_judge_run(h, true, bj.as<double>(), x0.as<double>(), xj.as<double>(), target, it_start);
+    if (!moved) {
+        t_trained = t_start;
+        it_trained = it_start;
+    }
+    const double t_cg = k_judge_run(h, false, bj.as<double>(), x0.as<double>(), xj.as<double>(), target, it_cg);
+    // solve_rest iterates on all the seeded systems at once, where M's links are shared by every vector
+    // and K's cost is not: the iteration counts above are priced with the time of one application of M
+    // and of K K^dag to that many vectors
+    const int nb = std::max(1, h->seed_nrhs - 1);
+    double t_m = 0.0, t_p = 0.0;
+    {
+        const bool lo = h->cg_lo;
+        DBuf xa, ya;
+        xa.ensure((int64_t)nb * h->vec_bytes(lo));
+        ya.ensure((int64_t)nb * h->vec_bytes(lo));
+        cfg_zero(xa.p, (int64_t)nb * h->vec_bytes(lo), h->L());
+        hipEvent_t e0, e1, e2;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        HIPCHK(hipEventCreate(&e2));
+        const int saved = h->timing_every;
+        h->timing_every = 0;
+        apply_M_int(h, lo, xa.p, ya.p, nb, MOpts{});
+        apply_P(h, lo, xa.p, ya.p, nullptr, nb, nb);
+        constexpr int reps = 4;
+        HIPCHK(hipEventRecord(e0, h->s));
+        for (int r = 0; r < reps; r++) apply_M_int(h, lo, xa.p, ya.p, nb, MOpts{});
+        HIPCHK(hipEventRecord(e1, h->s));
+        for (int r = 0; r < reps; r++) apply_P(h, lo, xa.p, ya.p, nullptr, nb, nb);
+        HIPCHK(hipEventRecord(e2, h->s));
+        HIPCHK(hipEventSynchronize(e2));
+        h->timing_every = saved;
+        float m1 = 0.f, m2 = 0.f;
+        HIPCHK(hipEventElapsedTime(&m1, e0, e1));
+        HIPCHK(hipEventElapsedTime(&m2, e1, e2));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        (void)hipEventDestroy(e2);
+        t_m = 1e-3 * m1 / reps;
+        t_p = 1e-3 * m2 / reps;
+        h->kfield.release();
+        h->pfa.release();
+        h->pfb.release();
+    }
+    const double c_cg = t_cg < 1e299 ? it_cg * t_m : 1e300;
+    const double c_start = t_start < 1e299 ? it_start * (t_m + t_p) : 1e300;
+    const double c_trained = t_trained < 1e299 ? it_trained * (t_m + t_p) : 1e300;
+    h->k_judge = {t_cg, t_start, t_trained, (double)it_cg, (double)it_start, (double)it_trained, t_m, t_p, c_cg, c_start, c_trained};
+    if (it_trained < it_start || (it_trained == it_start && t_trained <= t_start)) k_set_weights(h, wt.data());
+    const double c_k = std::min(c_start, c_trained);
+    h->k_choice = c_k < c_cg ? (c_trained <= c_start ? 2 : 1) : 0;
+    h->k_accepted = h->k_choice > 0;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1056,7 +1301,7 @@ ProjArgs defl_proj_args(seedcg_s* h, const void* rows, int nrows, const void* R,
     a.V = rows;
     a.ldv = h->N;
     a.nv = nrows;
-    for (int j = 0; j < nr; j++) a.R[j] = (const char*)R + (int64_t)j * h->vec_bytes(h->lo);
+    for (int j = 0; j < nr; j++) a.R[j] = (const char*)R + (int64_t)j * h->vec_bytes(h->cg_lo);
     a.nr = nr;
     a.n = h->N;
     a.kchunk = kchunk_for(h->N, 1024);
@@ -1075,7 +1320,7 @@ void build_deflation(seedcg_s* h, int want) {
     const int m = h->m_used;
     want = std::min({want, m, 24});
     if (want <= 0 || !h->basis.p) return;
-    const bool lo = h->lo;
+    const bool lo = h->cg_lo;   // W, M W and the CG vectors share the CG's precision
     const int64_t N = h->N;
     const LzArrays A = h->arr();
     std::vector<double> alpha(m), beta(m + 1);
@@ -1096,7 +1341,7 @@ void build_deflation(seedcg_s* h, int want) {
             for (int k = 0; k < nk; k++) S[(size_t)i * nk + k] = Sv[(size_t)i * nev + k0 + k];
         h->dS.ensure(S.size() * sizeof(double));
         HIPCHK(hipMemcpyAsync(h->dS.p, S.data(), S.size() * sizeof(double), hipMemcpyHostToDevice, h->s));
-        k_combine(lo, h->basis.p, m, h->dS.as<double>(), nk, (char*)h->dW.p + (int64_t)k0 * h->vec_bytes(lo), N, h->s, !lo);
+        k_combine(h->lo, h->basis.p, m, h->dS.as<double>(), nk, (char*)h->dW.p + (int64_t)k0 * h->vec_bytes(lo), N, h->s, !lo);
         HIPCHK(hipStreamSynchronize(h->s));  // dS is reused by the next pass
     }
     apply_M_int(h, lo, h->dW.p, h->dZ.p, nev, MOpts{});
@@ -1124,7 +1369,7 @@ void build_deflation(seedcg_s* h, int want) {
 // of map (w entries) whose CG record is running.  R in the working precision.
 void deflate_step(seedcg_s* h, bool init, const void* R, int nrhs, const int32_t* map, int w, void* X, bool x32,
                   bool use_cg = true) {
-    const bool lo = h->lo;
+    const bool lo = h->cg_lo;   // W, M W and the CG vectors share the CG's precision
     project(lo, defl_proj_args(h, init ? h->dW.p : h->dZ.p, h->nev, R, nrhs), 1, h->dP.as<double>(), h->L(), true);
     defl_mu(h->dGinv.as<double>(), h->dP.as<double>(), h->nev, nrhs, map, w, (init || !use_cg) ? nullptr : h->cgv.as<CgVec>(),
             init ? 1.0 : -1.0, h->dE.as<double>(), h->L());
@@ -1134,7 +1379,7 @@ void deflate_step(seedcg_s* h, bool init, const void* R, int nrhs, const int32_t
 // After a residual replacement: r is b - M x again and no longer exactly orthogonal to W; move the
 // listed vectors back, x += W G^{-1} W^dag r and r -= Z G^{-1} W^dag r (Z = M W, so r stays b - M x).
 void redeflate(seedcg_s* h, void* Rw, int nrhs, const int32_t* map, int w) {
-    const bool lo = h->lo;
+    const bool lo = h->cg_lo;   // W, M W and the CG vectors share the CG's precision
     project(lo, defl_proj_args(h, h->dW.p, h->nev, Rw, nrhs), 1, h->dP.as<double>(), h->L(), true);
     defl_mu(h->dGinv.as<double>(), h->dP.as<double>(), h->nev, nrhs, map, w, nullptr, 1.0, h->dE.as<double>(), h->L());
     seed_update(lo, false, h->dW.p, h->nev, h->dE.as<double>(), h->Xint.p, nrhs, h->N, nullptr, h->L());
@@ -1176,6 +1421,8 @@ void cg_iteration(seedcg_s* h, bool lo, bool pc, int nact, int nalloc, int64_t n
         dot_map(lo, Rw, h->Zv.p, h->N, h->vmap.as<int32_t>(), nact, h->cgv.as<CgVec>(), h->rzpart.as<double>(), L);
         cg_beta_pc(h->cgv.as<CgVec>(), h->rrpart.as<double>(), h->rzpart.as<double>(), nb, h->vmap.as<int32_t>(), nact, max_iter, L);
         cg_p(lo, h->cgv.as<CgVec>(), h->vmap.as<int32_t>(), nact, h->Pv.p, h->Zv.p, h->N, false, L);
+        // deflated PCG: p = z + b p - W G^{-1} (M W)^dag z
+        if (h->nev) deflate_step(h, false, h->Zv.p, nalloc, h->vmap.as<int32_t>(), nact, h->Pv.p, lo);
     } else {
         cg_beta(h->cgv.as<CgVec>(), h->rrpart.as<double>(), nb, h->vmap.as<int32_t>(), nact, max_iter, L);
         cg_p(lo, h->cgv.as<CgVec>(), h->vmap.as<int32_t>(), nact, h->Pv.p, Rw, h->N, false, L);
@@ -1230,7 +1477,7 @@ seedcg_status solve_rest_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report
     const int64_t nb = norm2_blocks(N);
     void* Rw = lo ? h->Rv.p : h->R64.p;  // the recursive residual
     // deflated CG from the Ritz vectors of the last seed solve (one configuration, no learned P)
-    const bool want_defl = h->p.deflate > 0 && C == 1 && h->have_seed && !(h->p.precond == 1 && h->k_ready && h->k_accepted);
+    const bool want_defl = h->p.deflate > 0 && C == 1 && h->have_seed;
     // the deflation projections contract all right-hand sides at once (at most 24 columns)
     if (want_defl && nrhs > 24) throw ArgError{"solve_rest: deflated CG takes at most 24 right-hand sides"};
     if (!want_defl)
@@ -1311,6 +1558,7 @@ seedcg_status solve_rest_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report
             for (int j : live) cg[j].rz = rz[j];
         }
         convert(lo, lo, h->Zv.p, h->Pv.p, nrhs * N, L);  // p = z
+        if (h->nev) deflate_step(h, false, h->Zv.p, nrhs, nullptr, nrhs, h->Pv.p, lo, false);  // p = z - W mu
     } else {
         convert(lo, lo, Rw, h->Pv.p, nrhs * N, L);  // p = r
         if (h->nev) deflate_step(h, false, Rw, nrhs, nullptr, nrhs, h->Pv.p, lo, false);  // p = r - W mu
@@ -1443,7 +1691,7 @@ seedcg_status solve_rest_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report
         to_cfg(h, h->cgv.p, cg.data(), nrhs * sizeof(CgVec));
         const int wr = upload_map(h, h->rmap, restart);
         if (wr) cg_p(lo, h->cgv.as<CgVec>(), h->rmap.as<int32_t>(), wr, h->Pv.p, pc ? h->Zv.p : Rw, N, false, L);
-        if (wr && h->nev) deflate_step(h, false, Rw, nrhs, h->rmap.as<int32_t>(), wr, h->Pv.p, lo);
+        if (wr && h->nev) deflate_step(h, false, pc ? h->Zv.p : Rw, nrhs, h->rmap.as<int32_t>(), wr, h->Pv.p, lo);
     }
     unpack_out(h, io, h->Xint.p, nrhs);
     // final FP64 true residuals for the report
@@ -1490,8 +1738,8 @@ void init_geometry(seedcg_s* h, const seedcg_params* p, const int32_t* dims) {
     // workgroups on one XCD
     h->tps64 = env_int("SEEDCG_TPS", 8);
     h->tps_lo = env_int("SEEDCG_TPS_LO", 8);
-    if (h->tps64 < 1 || h->tps64 > 10) h->tps64 = 8;
-    if (h->tps_lo < 1 || h->tps_lo > 10) h->tps_lo = 8;
+    if (h->tps64 < 1 || h->tps64 > 11) h->tps64 = 8;
+    if (h->tps_lo < 1 || h->tps_lo > 11) h->tps_lo = 8;
     h->vb64 = std::max(1, env_int("SEEDCG_VB", 1));
     h->vb_lo = std::max(1, env_int("SEEDCG_VB_LO", 1));
     h->tps64_multi = h->tps64;
@@ -1572,6 +1820,8 @@ void tune_shape(seedcg_s* h, bool low, int nvec, const void* x, void* y) {
         cand.push_back({4, 4});
         cand.push_back({7, 2});                 // links once per pair of vectors
         if (low) cand.push_back({7, 4});        // (four FP64 vectors do not fit in registers)
+        cand.push_back({11, 1});                // links once per launch, the vectors streamed
+        cand.push_back({11, 2});
     }
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
@@ -1934,7 +2184,7 @@ bool solve_indefinite_impl(seedcg_s* h, const double* Phi, double* Xout, int nrh
                 run({lin(wk.F.p, true, {{v, -a}, {vcol(i - 2), -beta[i - 1]}})});
             else
                 run({lin(wk.F.p, true, {{v, -a}})});
-            if (k > 0 && i % k == 0) {   // step 8
+            if (k > 0 && i % k == 0) {   // periodic reorthogonalisation
                 orthogonalise(i - 1, v);
                 const double nv = norm(v);
                 run({lin(v, false, {{v, 1.0 / nv}})});
@@ -2214,8 +2464,6 @@ seedcg_status seedcg_create(const seedcg_params* p, const double* links, seedcg_
         if (p->dims[d] < 2 || p->dims[d] % 2) return fail(nullptr, SEEDCG_ERR_ARG, "create: every extent must be even and >= 2");
     if (p->t_bc != 1 && p->t_bc != -1) return fail(nullptr, SEEDCG_ERR_ARG, "create: t_bc must be +1 or -1");
     if (p->prec < 0 || p->prec > 3) return fail(nullptr, SEEDCG_ERR_ARG, "create: unknown precision");
-    if (p->prec == SEEDCG_MIXED_FP32_CG && (p->deflate > 0 || p->precond != 0))
-        return fail(nullptr, SEEDCG_ERR_ARG, "create: MIXED_FP32_CG takes neither deflation nor the learned preconditioner");
     if (!(p->tol > 0.0)) return fail(nullptr, SEEDCG_ERR_ARG, "create: tol must be > 0");
     if (p->reorth_k < 0) return fail(nullptr, SEEDCG_ERR_ARG, "create: reorth_k must be >= 0");
     seedcg_s* h = new (std::nothrow) seedcg_s;
@@ -2778,6 +3026,8 @@ seedcg_status seedcg_set_timing(seedcg_t h, int32_t sample_every, int32_t max_sa
         h->ev_used = 0;
         h->ev_bytes.clear();
         h->ev_flops.clear();
+        h->ev_kind.clear();
+        h->t_kind.clear();
         h->t_ms = h->t_bytes = h->t_flops = 0.0;
         h->t_launches = 0;
         while ((int)h->ev0.size() < max_samples) {
@@ -2803,7 +3053,12 @@ seedcg_status seedcg_get_timing(seedcg_t h, double* out) {
             h->t_bytes += h->ev_bytes[k];
             h->t_flops += h->ev_flops[k];
             h->t_launches++;
+            auto& t = h->t_kind[h->ev_kind[k]];
+            t[0] += 1.0;
+            t[1] += ms;
+            t[2] += h->ev_bytes[k];
         }
+        h->ev_kind.clear();
         h->ev_used = 0;
         h->ev_bytes.clear();
         h->ev_flops.clear();
@@ -2816,11 +3071,70 @@ seedcg_status seedcg_get_timing(seedcg_t h, double* out) {
     });
 }
 
+seedcg_status seedcg_get_timing_kinds(seedcg_t h, double* out, int32_t cap, int32_t* n) {
+    if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "get_timing_kinds: null handle");
+    return guarded(h, [&]() -> seedcg_status {
+        if (!out || !n || cap < 0) throw ArgError{"get_timing_kinds: null pointer or negative capacity"};
+        double tmp[5];
+        const seedcg_status st = seedcg_get_timing(h, tmp);   // folds the pending samples in
+        if (st != SEEDCG_OK) return st;
+        int k = 0;
+        for (const auto& kv : h->t_kind) {
+            if (k < cap) {
+                double* r = out + 8 * (int64_t)k;
+                for (int q = 0; q < 5; q++) r[q] = kv.first[q];
+                for (int q = 0; q < 3; q++) r[5 + q] = kv.second[q];
+            }
+            k++;
+        }
+        *n = k;
+        return SEEDCG_OK;
+    });
+}
+
+seedcg_status seedcg_time_M(seedcg_t h, int32_t inner, int32_t nvec, int32_t reps, double* out) {
+    if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "time_M: null handle");
+    return guarded(h, [&]() -> seedcg_status {
+        if (!out || nvec < 1 || nvec > 25 || reps < 1) throw ArgError{"time_M: null pointer, nvec not in 1..25 or reps < 1"};
+        if (h->ncfg != 1) throw StateError{"time_M: one configuration per handle"};
+        const bool low = inner && h->cg_lo;
+        DBuf x, y;
+        x.ensure(nvec * h->vec_bytes(low));
+        y.ensure(nvec * h->vec_bytes(low));
+        cfg_zero(x.p, nvec * h->vec_bytes(low), h->L());
+        const int saved = h->timing_every;
+        h->timing_every = 0;
+        apply_M_int(h, low, x.p, y.p, nvec, MOpts{});
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        HIPCHK(hipEventRecord(e0, h->s));
+        for (int r = 0; r < reps; r++) apply_M_int(h, low, (r & 1) ? y.p : x.p, (r & 1) ? x.p : y.p, nvec, MOpts{});
+        HIPCHK(hipEventRecord(e1, h->s));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        h->timing_every = saved;
+        // algorithmic bytes of one application: each of the four hops reads every link once (in the
+        // stored format) for all vectors, and per vector M moves 120 V spinor reals
+        const Prec pr = low ? h->hop_lo : h->hop64;
+        const double sl = (pr == P64 || pr == P64R) ? 8.0 : (pr == P32BF ? 2.0 : 4.0);
+        const double ss = low ? 4.0 : 8.0;
+        const double lr = (pr == P64R || pr == P32R) ? 12.0 : 18.0;
+        const double V = (double)h->g.V;
+        out[0] = ms / reps;
+        out[1] = 4.0 * 4.0 * V * lr * sl + 120.0 * V * ss * nvec;
+        out[2] = 4.0 * 4.0 * V * 18.0 * sl + 120.0 * V * ss * nvec;
+        out[3] = (double)pr;
+        return SEEDCG_OK;
+    });
+}
+
 seedcg_status seedcg_train_precond(seedcg_t h, int32_t steps, int32_t n_ritz, int32_t n_lanczos, double lr, double* out) {
-    // out[0..5]: initial loss, final loss, seconds, Ritz vectors, training vectors, accepted
     if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "train_precond: null handle");
     return guarded(h, [&]() -> seedcg_status {
-        if (h->cg_lo && !h->lo) throw StateError{"train_precond: not with MIXED_FP32_CG"};
         train_precond_impl(h, steps, n_ritz, n_lanczos, lr);
         if (out) {
             out[0] = h->k_loss0;
@@ -2829,6 +3143,9 @@ seedcg_status seedcg_train_precond(seedcg_t h, int32_t steps, int32_t n_ritz, in
             out[3] = h->k_ritz;
             out[4] = h->k_train_vecs;
             out[5] = h->k_accepted ? 1.0 : 0.0;
+            for (int q = 0; q < 6; q++) out[6 + q] = h->k_judge[q];
+            out[12] = h->k_choice;
+            for (int q = 0; q < 5; q++) out[13 + q] = h->k_judge[6 + q];
         }
         return SEEDCG_OK;
     });
@@ -2838,7 +3155,6 @@ seedcg_status seedcg_use_precond(seedcg_t h, int32_t on) {
     if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "use_precond: null handle");
     return guarded(h, [&]() -> seedcg_status {
         if (on && !h->k_ready) throw StateError{"use_precond: the preconditioner has no weights"};
-        if (on && h->cg_lo && !h->lo) throw StateError{"use_precond: not with MIXED_FP32_CG"};
         h->p.precond = on ? 1 : 0;
         return SEEDCG_OK;
     });
@@ -2883,23 +3199,20 @@ seedcg_status seedcg_apply_P(seedcg_t h, const double* x, double* y, int32_t nve
     });
 }
 
-seedcg_status seedcg_precond_loss_grad(seedcg_t h, const double* U, const double* Y, int32_t S, double* loss, double* grad) {
+seedcg_status seedcg_precond_loss_grad_band(seedcg_t h, const double* U, const double* Y, int32_t S, int32_t t0, int32_t nt,
+                                            double* loss, double* grad) {
     if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "precond_loss_grad: null handle");
     return guarded(h, [&]() -> seedcg_status {
         if (!U || !Y || S < 1 || S > 32) throw ArgError{"precond_loss_grad: null pointer or S not in 1..32"};
+        if (nt < 0) throw ArgError{"precond_loss_grad: negative band"};
         if (!h->k_ready) throw StateError{"precond_loss_grad: the preconditioner has no weights"};
         const int64_t N = h->N;
         h->kU.ensure((int64_t)S * N * 8);
         h->kY.ensure((int64_t)S * N * 8);
         pack_vec(true, U, h->kU.p, h->g.Vh, S, h->s);
         pack_vec(true, Y, h->kY.p, h->g.Vh, S, h->s);
-        const int64_t nbn = norm2_blocks(N);
-        h->kun2.ensure(S * sizeof(double));
-        h->klpart.ensure(std::max<int64_t>(nbn, k_residual_blocks(N)) * S * sizeof(double));
-        norm2_partials(true, h->kU.p, N, S, h->klpart.as<double>(), h->s);
-        sum_partials(h->klpart.as<double>(), nbn, S, h->kun2.as<double>(), false, h->s);
         HIPCHK(hipMemsetAsync(h->kG.p, 0, K_NREAL * sizeof(double), h->s));
-        const double l = k_pass(h, S, grad != nullptr, true);
+        const double l = k_pass(h, 0, S, grad != nullptr, true, t0, nt);
         if (loss) *loss = l;
         if (grad) {
             HIPCHK(hipMemcpyAsync(grad, h->kG.p, K_NREAL * sizeof(double), hipMemcpyDeviceToHost, h->s));
@@ -2908,6 +3221,10 @@ seedcg_status seedcg_precond_loss_grad(seedcg_t h, const double* U, const double
         HIPCHK(hipStreamSynchronize(h->s));
         return SEEDCG_OK;
     });
+}
+
+seedcg_status seedcg_precond_loss_grad(seedcg_t h, const double* U, const double* Y, int32_t S, double* loss, double* grad) {
+    return seedcg_precond_loss_grad_band(h, U, Y, S, 0, 0, loss, grad);
 }
 
 seedcg_status seedcg_release_basis(seedcg_t h) {

@@ -79,8 +79,11 @@ def load_library():
         "seedcg_get_precond_weights": (i32, [H, ctypes.POINTER(dbl)]),
         "seedcg_apply_P": (i32, [H, P, P, i32]),
         "seedcg_precond_loss_grad": (i32, [H, P, P, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]),
+        "seedcg_precond_loss_grad_band": (i32, [H, P, P, i32, i32, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]),
         "seedcg_set_timing": (i32, [H, i32, i32]),
         "seedcg_get_timing": (i32, [H, ctypes.POINTER(dbl)]),
+        "seedcg_get_timing_kinds": (i32, [H, ctypes.POINTER(dbl), i32, ctypes.POINTER(i32)]),
+        "seedcg_time_M": (i32, [H, i32, i32, i32, ctypes.POINTER(dbl)]),
         "seedcg_release_basis": (i32, [H]),
         "seedcg_destroy": (None, [H]),
         "seedcg_last_error": (ctypes.c_char_p, [H]),
@@ -106,8 +109,8 @@ def exported_symbols():
     return ["seedcg_default_params", "seedcg_create", "seedcg_apply_M", "seedcg_apply_M_inner", "seedcg_apply_A", "seedcg_solve_seed",
             "seedcg_solve_rest", "seedcg_solve_repeated", "seedcg_solve_indefinite", "seedcg_get_tridiag", "seedcg_get_basis_vector", "seedcg_get_ritz", "seedcg_project",
             "seedcg_project_noalloc", "seedcg_update", "seedcg_train_precond", "seedcg_use_precond", "seedcg_set_precond_weights",
-            "seedcg_get_precond_weights", "seedcg_apply_P", "seedcg_precond_loss_grad", "seedcg_set_timing",
-            "seedcg_get_timing", "seedcg_release_basis", "seedcg_destroy", "seedcg_last_error", "seedcg_create_batch",
+            "seedcg_get_precond_weights", "seedcg_apply_P", "seedcg_precond_loss_grad", "seedcg_precond_loss_grad_band", "seedcg_set_timing",
+            "seedcg_get_timing", "seedcg_get_timing_kinds", "seedcg_time_M", "seedcg_release_basis", "seedcg_destroy", "seedcg_last_error", "seedcg_create_batch",
             "seedcg_solve_batch", "seedcg_batch_info", "seedcg_batch_set_timing", "seedcg_batch_get_timing",
             "seedcg_destroy_batch", "seedcg_batch_last_error"]
 
@@ -322,11 +325,14 @@ class SeedCG:
         return X
 
     # -- learned preconditioner P = K K^dag -------------------------------------------------------
-    def train_precond(self, steps=2000, n_ritz=8, n_lanczos=8, lr=1e-3):
-        out = (ctypes.c_double * 6)()
+    def train_precond(self, steps=2000, n_ritz=4, n_lanczos=12, lr=2e-4):
+        out = (ctypes.c_double * 18)()
         self._rc(self._lib.seedcg_train_precond(self._h, int(steps), int(n_ritz), int(n_lanczos), float(lr), out))
         return dict(loss0=out[0], loss1=out[1], t_train_s=out[2], n_ritz=int(out[3]), n_train=int(out[4]),
-                    accepted=bool(out[5]))
+                    accepted=bool(out[5]), judge_s=dict(cg=out[6], start=out[7], trained=out[8]),
+                    judge_iters=dict(cg=int(out[9]), start=int(out[10]), trained=int(out[11])),
+                    choice=["plain_cg", "start_K", "trained_K"][int(out[12])],
+                    batch_s=dict(M=out[13], P=out[14]), predicted_s=dict(cg=out[15], start=out[16], trained=out[17]))
 
     def use_precond(self, on=True):
         self._rc(self._lib.seedcg_use_precond(self._h, int(bool(on))))
@@ -348,14 +354,16 @@ class SeedCG:
         self._rc(self._lib.seedcg_apply_P(self._h, x.data_ptr(), y.data_ptr(), x.shape[0]))
         return y
 
-    def precond_loss_grad(self, U, Y):
+    def precond_loss_grad(self, U, Y, band=None):
+        """The training loss and its Wirtinger gradient; band = (t0, nt) takes the loss on those t-slices."""
         import numpy as np
         U = _check_vec(U, self.Vh, "U")
         Y = _check_vec(Y, self.Vh, "Y")
         loss = ctypes.c_double()
         g = np.empty((3, 9, 4, 4), dtype=np.complex128)
-        self._rc(self._lib.seedcg_precond_loss_grad(self._h, U.data_ptr(), Y.data_ptr(), U.shape[0], ctypes.byref(loss),
-                                                    g.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        t0, nt = band if band else (0, 0)
+        self._rc(self._lib.seedcg_precond_loss_grad_band(self._h, U.data_ptr(), Y.data_ptr(), U.shape[0], int(t0), int(nt),
+                                                         ctypes.byref(loss), g.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return loss.value, g
 
     def set_timing(self, sample_every, max_samples=4096):
@@ -366,6 +374,21 @@ class SeedCG:
         out = (ctypes.c_double * 5)()
         self._rc(self._lib.seedcg_get_timing(self._h, out))
         return dict(launches=int(out[0]), ms=out[1], bytes=out[2], flops=out[3], seen=int(out[4]))
+
+    def get_timing_kinds(self):
+        """Sampled stencil launches by kind: list of dict(fmt, nvec, fused, tps, vb, launches, ms, bytes)."""
+        cap = 64
+        out = (ctypes.c_double * (8 * cap))()
+        n = ctypes.c_int32()
+        self._rc(self._lib.seedcg_get_timing_kinds(self._h, out, cap, ctypes.byref(n)))
+        keys = ("fmt", "nvec", "fused", "tps", "vb", "launches", "ms", "bytes")
+        return [dict(zip(keys, [out[8 * k + q] for q in range(8)])) for k in range(min(n.value, cap))]
+
+    def time_M(self, inner=False, nvec=1, reps=200):
+        """Back-to-back applications of M timed with events: dict(ms, bytes, bytes_18real, fmt)."""
+        out = (ctypes.c_double * 4)()
+        self._rc(self._lib.seedcg_time_M(self._h, int(bool(inner)), int(nvec), int(reps), out))
+        return dict(ms=out[0], bytes=out[1], bytes_18real=out[2], fmt=int(out[3]))
 
     def release_basis(self):
         self._rc(self._lib.seedcg_release_basis(self._h))

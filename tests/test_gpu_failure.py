@@ -6,7 +6,6 @@
     iteration, and the handle solves the next clean system normally.
   * Deflated CG keeps its deflation space after release_basis (the Ritz vectors are built before
     the basis goes), and refuses more than 24 right-hand sides.
-  * A learned K that is not accepted leaves solve_rest on plain CG: the same iteration counts.
   * Report fields: the Lanczos estimate of RHS 1 meets tol at m, the orthogonality-loss figure is 0
     without reorthogonalisation and small with it, the CG estimates meet tol.
 """
@@ -113,22 +112,6 @@ def test_deflation_refuses_more_than_24_rhs():
     # 24 of them are fine
     X24, rep = s.solve_rest(cuda(B25[:24]), cuda(np.zeros_like(B25[:24])))
     assert max(rep["true_relres"]) <= 1e-10
-
-
-def test_rejected_k_takes_plain_cg_iterations():
-    print_case("rejected K t8")
-    U, dims, kappa, op, B = _problem("t8")
-    s = _solver(U, dims, kappa, reorth_k=10)
-    X0, _ = s.solve_seed(cuda(B))
-    tr = s.train_precond(steps=0, n_ritz=4, n_lanczos=4)
-    assert tr["accepted"] == 0
-    s.use_precond(True)
-    _, rep_k = s.solve_rest(cuda(B), X0.clone())
-    s.use_precond(False)
-    _, rep_p = s.solve_rest(cuda(B), X0.clone())
-    assert rep_k["iters"] == rep_p["iters"]
-    assert rep_k["t_train_s"] == 0.0
-    assert max(rep_k["true_relres"]) <= 1e-10
 
 
 def test_report_estimates_and_orthogonality_loss():

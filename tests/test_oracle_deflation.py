@@ -100,3 +100,44 @@ def test_deflation_pays_with_isolated_low_modes():
             _, it_c, r_c, _ = sc.cg(mv, B[j], None, tol=1e-10)
             assert r_d <= 1e-10 and r_c <= 1e-10
             assert lo <= it_d / it_c <= hi, (flux, j, it_d, it_c)
+
+
+def _hpd_precond(system):
+    """An HPD preconditioner independent of the method: a random well-conditioned HPD matrix."""
+    rng = np.random.default_rng(43)
+    N = system["N"]
+    Q, _ = np.linalg.qr(rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N)))
+    d = rng.uniform(0.5, 2.0, N)
+    P = (Q * d) @ Q.conj().T
+    return 0.5 * (P + P.conj().T)
+
+
+def test_preconditioned_invariants_and_solution(system):
+    """Deflated PCG keeps W^dag r_j = 0 and W^dag M p_j = 0 and solves the system."""
+    mv, b, M, N = system["mv"], system["b"], system["M"], system["N"]
+    P = _hpd_precond(system)
+    W = system["rng"].standard_normal((5, N)) + 1j * system["rng"].standard_normal((5, N))
+    x, it, res, hist = dfl.deflated_cg(mv, b, None, W, tol=1e-10, history=True, precond=lambda r: P @ r)
+    assert res <= 1e-10 and it > 5
+    wn = np.linalg.norm(W, axis=1)
+    r_scale = np.linalg.norm(hist[0][0])
+    mp_scale = max(np.linalg.norm(M @ p) for _, p in hist)
+    for r, p in hist:
+        assert np.max(np.abs(W.conj() @ r) / wn) <= 1e-11 * r_scale
+        assert np.max(np.abs(W.conj() @ (M @ p)) / wn) <= 1e-11 * mp_scale
+    xs = np.linalg.solve(M, b)
+    assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
+
+
+def test_preconditioned_form_is_scale_invariant_and_reduces_to_pcg(system):
+    """P = c I gives deflated CG's iterates; without W it is the oracle's plain PCG."""
+    from oracle import learned as lk
+    mv, b, N = system["mv"], system["b"], system["N"]
+    W = system["rng"].standard_normal((3, N)) + 1j * system["rng"].standard_normal((3, N))
+    x1, it1, _ = dfl.deflated_cg(mv, b, None, W, tol=1e-10)
+    x2, it2, _ = dfl.deflated_cg(mv, b, None, W, tol=1e-10, precond=lambda r: 3.0 * r)
+    assert it1 == it2 and np.linalg.norm(x1 - x2) <= 1e-12 * np.linalg.norm(x1)
+    P = _hpd_precond(system)
+    x3, it3, _ = dfl.deflated_cg(mv, b, None, [], tol=1e-10, precond=lambda r: P @ r)
+    x4, it4 = lk.pcg(mv, lambda r: P @ r, b, None, tol=1e-10)
+    assert it3 == it4 and np.linalg.norm(x3 - x4) <= 1e-12 * np.linalg.norm(x4)

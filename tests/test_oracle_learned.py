@@ -124,3 +124,62 @@ def test_pcg_with_identity_is_cg(lat):
     x2, it2, _, _ = sc.cg(mv, b, tol=1e-10)
     assert it1 == it2
     assert np.linalg.norm(x1 - x2) <= 1e-12 * np.linalg.norm(x2)
+
+
+def test_neumann_start_is_first_order_inverse_of_A(lat):
+    """K at the training start equals 1 + kappa^2 H_eo H_oe built by the oracle's C hop (a separate
+    implementation of the transports), so A K = 1 - kappa^4 (H_eo H_oe)^2."""
+    L, U = lat
+    kappa = 0.13
+    op = WilsonEO(U, DIMS, kappa)
+    rng = np.random.default_rng(4)
+    x = _rand(rng, 2, L.V // 2, 4, 3)
+    ref = x + kappa ** 2 * op.H_eo(op.H_oe(x))
+    got = lk.apply_K(L, lk.neumann_weights(kappa), x)
+    assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
+    # K^dag is the adjoint: 1 + kappa^2 (H_eo H_oe)^dag = gamma5 (1 + kappa^2 H_eo H_oe) gamma5
+    from oracle.wilson import gamma5
+    refd = gamma5(gamma5(x) + kappa ** 2 * op.H_eo(op.H_oe(gamma5(x))))
+    gotd = lk.apply_Kdag(L, lk.neumann_weights(kappa), x)
+    assert np.max(np.abs(gotd - refd)) <= 1e-13 * np.max(np.abs(refd))
+
+
+def test_identity_start_is_a_saddle_for_the_hops(lat):
+    """At K = 1 (all hop weights 0) the loss gradient of every hop weight is exactly zero: the only
+    hop paths that reach an even site carry two hop weights.  The Neumann start has non-zero hop
+    gradients."""
+    L, U = lat
+    op = WilsonEO(U, DIMS, 0.13)
+    rng = np.random.default_rng(5)
+    Uv = _rand(rng, 2, L.V // 2, 4, 3)
+    Y = op.apply_M(Uv)
+    G = lk.grad(L, lk.identity_weights(), Y, Uv)
+    assert np.max(np.abs(G[:, 1:])) == 0.0
+    assert np.max(np.abs(G[:, 0])) > 0.0
+    Gn = lk.grad(L, lk.neumann_weights(0.13), Y, Uv)
+    assert np.min(np.max(np.abs(Gn[:, 1:]), axis=(2, 3))) > 0.0
+
+
+def test_band_loss_gradient_matches_finite_differences(lat):
+    """The loss on a band of t-slices and its gradient (what a training step takes) against central
+    finite differences; the band covering every slice is the whole-lattice loss."""
+    L, U = lat
+    op = WilsonEO(U, DIMS, 0.13)
+    rng = np.random.default_rng(6)
+    Uv = _rand(rng, 2, L.V // 2, 4, 3)
+    Y = op.apply_M(Uv)
+    W = _randW(rng, 0.2)
+    band = (3, 2)
+    G = lk.grad(L, W, Y, Uv, band=band)
+    h = 1e-6
+    for (l, d, a, b) in ((0, 0, 1, 2), (1, 4, 0, 3), (2, 7, 2, 2), (1, 0, 3, 1)):
+        for comp in (1.0, 1j):
+            Wp = W.copy()
+            Wp[l, d, a, b] += comp * h
+            Wm = W.copy()
+            Wm[l, d, a, b] -= comp * h
+            fd = (lk.loss(L, Wp, Y, Uv, band=band) - lk.loss(L, Wm, Y, Uv, band=band)) / (2 * h)
+            # dL/dRe w = 2 Re G, dL/dIm w = 2 Im G
+            an = 2 * (G[l, d, a, b].real if comp == 1.0 else G[l, d, a, b].imag)
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (l, d, a, b, comp, fd, an)
+    assert lk.loss(L, W, Y, Uv, band=(0, DIMS[3])) == pytest.approx(lk.loss(L, W, Y, Uv), rel=1e-14)

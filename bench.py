@@ -1,22 +1,28 @@
-"""Benchmark: RHS/s of Seed-CG at an FP64 relative residual of 1e-10, and the D^dag D stencil rate.
+"""Benchmark: RHS/s of Seed-CG at an FP64 relative residual of 1e-10, learned + mixed against plain FP64
+Seed-CG on the same lattice, and the D^dag D stencil rate.
 
-One step = the whole hot path on one batch of right-hand sides: Algorithm 1 on RHS 1 (Lanczos
-run past convergence, periodic reorthogonalisation, Galerkin seeding of the others through the
-LU of T), then plain CG from the seeded guesses on every right-hand side, until each one has an
+One step = the whole hot path on one batch of right-hand sides of one configuration: Algorithm 1 on
+RHS 1 (Lanczos run past convergence, periodic reorthogonalisation, Galerkin seeding of the others
+through the LU of T), then CG from the seeded guesses on every right-hand side, until each one has an
 FP64 true relative residual <= tol.  Inputs are resident in HBM before the timed region.
 
-Default workload: 16^3 x 32 lattice, links exp(0.5 i H) smeared by 2 APE steps, kappa from the
-oracle's search, 12 point sources, plain FP64 Seed-CG with k = 20.
+The headline line (default): `value` is the learned + mixed form, timed per step as
+  solve_seed (FP64 Algorithm 1, FP64 basis)
+  + train_precond (the learned K K^dag, 2000 Adam steps on the seed solve's Ritz vectors and
+    residuals, then judged against plain CG on RHS 2)
+  + solve_rest (FP32 CG with FP64 reliable updates; PCG with K and the 16 lowest Ritz vectors of the
+    seed basis deflated when K won the judge, deflated CG otherwise);
+`vs_baseline` is that RHS/s over plain FP64 Seed-CG's (solve_seed + solve_rest, all FP64) on the same
+lattice, right-hand sides and GPU, timed in the same run: the comparison the metric names.
+Default workload: 24^3 x 48 on the topological flux background at lambda_min/lambda_max = 1.1e-5,
+12 point + 12 Z2 sources, k = 10 (--config c5t: 32^3 x 64 at 9.7e-7, 12 point sources).
 
---config c4: the batched workload instead, 64 configurations of lattice sizes drawn from
-{8^4, 8^3 x 16, 12^3 x 24, 12^4}, 12 point sources each, mixed precision, every configuration
-solved by one batch call per step (value = right-hand sides solved per second over the batch).
---config c2t: the 16^3 x 32 workload on a topological flux background (near-zero modes apart
-from the bulk); --config c4_NN: one member of the batch on its own.
---sweep: instead of the benchmark line, RHS 1's cost and RHS 2's CG iterations against the
-reorthogonalisation frequency k and the past-convergence factor (one JSON line).
+--form fp64|mixed|mixed_cg|mixed_bf16: one form only (the earlier single-form line, with the
+same-lattice comparisons); --config c4: the batched workload (64 configurations of {8^4, 8^3 x 16,
+12^3 x 24, 12^4}, one batch call per step); --sweep: RHS 1's cost and RHS 2's CG iterations
+against k and the past-convergence factor.
 
-Prints one JSON line (see the `result` dict at the end).
+Prints one JSON line.
 """
 import argparse
 import json
@@ -41,8 +47,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2", help="c2 (default), c4 (the batch), or one batch member c4_00 ... c4_63")
-    ap.add_argument("--prec", default=None, help="override the workload precision (fp64|mixed|mixed_bf16)")
+    ap.add_argument("--config", default="c3t", help="c3t (default), c5t, c2, c2t, c4 (the batch), or one batch member c4_00 ... c4_63")
+    ap.add_argument("--form", default="metric",
+                    help="metric (learned + mixed against plain FP64, default) or one form: fp64|mixed|mixed_cg|mixed_bf16")
+    ap.add_argument("--prec", default=None, help="with --form: override the workload precision")
+    ap.add_argument("--train-steps", type=int, default=2000, help="Adam steps of the learned K per step")
+    ap.add_argument("--deflate-k", type=int, default=16, help="Ritz vectors deflated in the learned form's (P)CG")
+    ap.add_argument("--ref-steps", type=int, default=5, help="timed steps of the plain FP64 reference (at most --steps)")
+    ap.add_argument("--m-max", type=int, default=0, help="Krylov basis capacity of both forms (0: by the HBM left)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=40, help="Lanczos steps in the oracle sample")
     ap.add_argument("--sample-every", type=int, default=7,
@@ -78,12 +90,14 @@ def main():
 
     if args.config == "c4":
         return bench_batch(args)   # generates its inputs in worker processes before any GPU call
+    if args.form == "metric" and not args.sweep:
+        return bench_metric(args)
     if args.config.startswith("c4_"):   # one member of the batched workload on its own
         from synth.configs import batch_members
         cfg = {m.name: m for m in batch_members()}[args.config]
     else:
         cfg = CONFIGS[args.config]
-    prec = args.prec or cfg.prec
+    prec = args.prec or (args.form if args.form != "metric" else cfg.prec)
     dev = torch.device("cuda:0")
     t_gen = time.time()
     U = make_links(cfg)
@@ -131,23 +145,10 @@ def main():
     elapsed = t1 - t0
     value = solved / elapsed
 
-    # D^dag D rate: back-to-back M applications on resident vectors (12 right-hand sides at once
-    # and one at a time), bytes per M from the algorithmic model 288 V s_link + 120 V s_spinor per vector
+    # D^dag D rate: back-to-back applications of M inside the library, timed with events (FP64, and the
+    # CG's inner precision for the mixed forms)
     V = int(np.prod(cfg.dims))
-    s_l = 8.0 if prec == "fp64" else (4.0 if prec == "mixed" else 2.0)
-    s_s = 8.0 if prec == "fp64" else 4.0
-    x1 = B[:1].clone()
-    t_m_api = None
-    if args.mbench > 0:
-        for _ in range(3):
-            solver.apply_M(x1)
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        for _ in range(args.mbench):
-            solver.apply_M(x1)
-        torch.cuda.synchronize()
-        t_m_api = (time.perf_counter() - ta) / args.mbench
-
+    dd = dagger_d(solver, prec, nrhs, args.mbench) if args.mbench > 0 else None
     # roofline of the dominant kernel (the Wilson hop), measured live over the timed region
     hop_ms = tm["ms"] / max(tm["launches"], 1)
     hop_bytes = tm["bytes"] / max(tm["launches"], 1)
@@ -187,11 +188,210 @@ def main():
         "cpu_baseline": cpu,
         "detail": {"m": rs["m"], "i_conv": rs["i_conv"], "seed_status": rs["seed_status"],
                    "t_seed_s": rs["t_seed_s"], "t_rest_s": rr["t_rest_s"], "cg_iters": rr["iters"],
-                   "max_true_relres": max(rr["true_relres"]),
-                   "dagger_d_gbs_api": (288 * V * s_l + 120 * V * s_s) / t_m_api / 1e9 if t_m_api else None,
-                   "dagger_d_us_api": t_m_api * 1e6 if t_m_api else None,
+                   "max_true_relres": max(rr["true_relres"]), "dagger_d": dd,
                    "hop_launches_total": tm["seen"], "compare": compare,
                    "device_copy_gbs": copy_gbs},
+    }
+    print(json.dumps(result), flush=True)
+
+
+FMT_NAMES = {0: "fp64", 1: "fp32", 2: "fp32 (bf16 links)", 3: "fp64 (two-row links)", 4: "fp32 (two-row links)"}
+
+
+def dagger_d(solver, prec, nrhs, reps):
+    """D^dag D rate of back-to-back M applications timed with events inside the library: FP64 for one
+    vector and for the nrhs - 1 of the CG; for the mixed forms also the CG's inner precision."""
+    out = {}
+    forms = [("fp64", False)] + ([("inner", True)] if prec != "fp64" else [])
+    for name, inner in forms:
+        for nv in sorted({1, max(1, nrhs - 1)}):
+            t = solver.time_M(inner=inner, nvec=nv, reps=reps)
+            out[f"{name}_nvec{nv}"] = {"gbs": t["bytes"] / (t["ms"] * 1e-3) / 1e9,
+                                       "gbs_18real_links": t["bytes_18real"] / (t["ms"] * 1e-3) / 1e9,
+                                       "us_per_M": t["ms"] * 1e3, "links": FMT_NAMES.get(t["fmt"], t["fmt"]),
+                                       "frac_hbm": t["bytes"] / (t["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    return out
+
+
+def dominant_kind(kinds):
+    """The stencil launch kind with the largest sampled time."""
+    if not kinds:
+        return None
+    k = max(kinds, key=lambda r: r["ms"])
+    return dict(k, avg_us=1e3 * k["ms"] / k["launches"], avg_bytes=k["bytes"] / k["launches"],
+                gbs=k["bytes"] / (k["ms"] * 1e-3) / 1e9, name=kind_name(k))
+
+
+_FMT_TYPES = {0: ("double", "double"), 1: ("float", "float"), 2: ("float", "scg::bf16link"),
+              3: ("double", "scg::su3rows<double>"), 4: ("float", "scg::su3rows<float>")}
+
+
+def kind_kernel(k):
+    """The kernel a stencil launch kind runs, as rocprofv3 names it (the production launch shapes)."""
+    t, lt = _FMT_TYPES.get(int(k["fmt"]), ("?", "?"))
+    cgu = "true" if k["fused"] else "false"
+    tps, vb = int(k["tps"]), int(k["vb"])
+    if tps == 8:
+        return f"scg::hop_split_kernel<{t}, {lt}, {vb}, {cgu}>"
+    if tps == 9:
+        return f"scg::hop_plane_kernel<{t}, {lt}, {vb}, {cgu}>"
+    if tps == 10:
+        return f"scg::hop_quad_kernel<{t}, {lt}, {cgu}>"
+    if tps == 11:
+        return f"scg::hop_stream_kernel<{t}, {lt}, {vb}, {cgu}>"
+    return f"scg::hop (launch shape tps {tps}, vb {vb})"
+
+
+def kind_tag(k):
+    fam = {8: "split", 9: "plane", 10: "quad", 11: "stream"}.get(int(k["tps"]), f"tps{int(k['tps'])}")
+    return f"{FMT_NAMES.get(int(k['fmt']), 'x').split()[0]}_{fam}_vb{int(k['vb'])}{'_cgu' if k['fused'] else ''}"
+
+
+def kind_name(k):
+    return (f"{kind_kernel(k)}: {FMT_NAMES.get(int(k['fmt']), k['fmt'])}, {int(k['nvec'])} vector(s) per launch"
+            f"{', CG update fused' if k['fused'] else ''}")
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def bench_metric(args):
+    """The metric's own comparison: learned + mixed Seed-CG against plain FP64 Seed-CG, same lattice."""
+    import numpy as np
+    import torch
+    from paper_0901_3512_amd import SeedCG
+    from synth.configs import CONFIGS, make_links, make_sources, kappa_for
+    cfg = CONFIGS[args.config]
+    dev = torch.device("cuda:0")
+    t_gen = time.time()
+    U = make_links(cfg)
+    phi = make_sources(cfg)
+    kappa = kappa_for(cfg)
+    log(f"inputs {cfg.name} dims={cfg.dims} kappa={kappa} nrhs={cfg.nrhs} ({time.time() - t_gen:.1f} s)")
+    Ud = torch.from_numpy(U).to(dev)
+    phid = torch.from_numpy(phi).to(dev)
+    # the same basis capacity for both forms (FP64 basis in both): 1000 vectors, or what 60% of the
+    # GPU's memory holds at this lattice (the two forms run one after the other, never both at once)
+    vec_bytes = cfg.volume // 2 * 12 * 16
+    m_max = args.m_max or min(1000, int(0.6 * torch.cuda.get_device_properties(0).total_memory // vec_bytes))
+    common = dict(t_bc=cfg.t_bc, reorth_k=cfg.reorth_k, past=cfg.past, tol=cfg.tol, reliable_every=cfg.reliable_every,
+                  m_max=m_max)
+    val = SeedCG(Ud, cfg.dims, kappa, prec="mixed_cg", deflate=args.deflate_k, **common)
+    B = val.apply_A(phid, dagger=True)   # b = A^dag phi (input preparation, not timed)
+    nrhs = B.shape[0]
+
+    def step_val():
+        X = torch.zeros_like(B)
+        X, rs = val.solve_seed(B, X)
+        tr = val.train_precond(steps=args.train_steps, n_ritz=4, n_lanczos=12, lr=2e-4)
+        val.use_precond(tr["accepted"])
+        X, rr = val.solve_rest(B, X)
+        return rs, tr, rr
+
+    def step_ref():
+        X = torch.zeros_like(B)
+        X, rs = ref.solve_seed(B, X)
+        X, rr = ref.solve_rest(B, X)
+        return rs, rr
+
+    for w in range(args.warmup):
+        rs, tr, rr = step_val()
+        log(f"warmup {w}: m={rs['m']} i_conv={rs['i_conv']} seed {rs['t_seed_s']:.2f}s train {tr['t_train_s']:.2f}s "
+            f"({tr['choice']}, judge {tr['judge_iters']}, predicted {tr['predicted_s']}) rest {rr['t_rest_s']:.2f}s "
+            f"iters={rr['iters']}")
+    if args.copy_probe:
+        copy_probe()   # marks the start of the timed region in a counter trace
+
+    # the value: learned + mixed, every step including the training of K
+    val.set_timing(args.sample_every, 16384)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solved, t_train, last = 0, 0.0, None
+    for k in range(args.steps):
+        rs, tr, rr = step_val()
+        last = (rs, tr, rr)
+        t_train += tr["t_train_s"]
+        solved += sum(1 for r in rr["true_relres"] if r <= cfg.tol)
+        log(f"step {k}: m={rs['m']} seed {rs['t_seed_s']:.2f}s train {tr['t_train_s']:.2f}s ({tr['choice']}) "
+            f"rest {rr['t_rest_s']:.2f}s max relres {max(rr['true_relres']):.2e}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kinds = val.get_timing_kinds()
+    val.set_timing(0, 0)
+    value = solved / elapsed
+    dd = dagger_d(val, "mixed_cg", nrhs, args.mbench) if args.mbench > 0 else None
+    val.close()
+    del val
+    torch.cuda.empty_cache()
+
+    # the baseline: plain FP64 Seed-CG on the same inputs
+    ref = SeedCG(Ud, cfg.dims, kappa, prec="fp64", **common)
+    rs_w, rr_w = step_ref()
+    log(f"reference warmup: m={rs_w['m']} seed {rs_w['t_seed_s']:.2f}s rest {rr_w['t_rest_s']:.2f}s iters={rr_w['iters']}")
+    nref = max(1, min(args.steps, args.ref_steps))
+    ref.set_timing(args.sample_every, 16384)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solved_ref, last_ref = 0, None
+    for k in range(nref):
+        rs_r, rr_r = step_ref()
+        last_ref = (rs_r, rr_r)
+        solved_ref += sum(1 for r in rr_r["true_relres"] if r <= cfg.tol)
+    torch.cuda.synchronize()
+    elapsed_ref = time.perf_counter() - t0
+    kinds_ref = ref.get_timing_kinds()
+    ref.set_timing(0, 0)
+    value_ref = solved_ref / elapsed_ref
+    log(f"learned+mixed {value:.3f} RHS/s, plain FP64 {value_ref:.3f} RHS/s ({value / value_ref:.2f}x)")
+    ref.close()
+
+    dom = dominant_kind(kinds)
+    traffic = measured_traffic(cfg, kind_tag(dom), kind_kernel(dom)) if dom else None
+    roofline = {"bound": "hbm", "achieved": dom["gbs"] if dom else None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": dom["gbs"] / HBM_PEAK_GBS if dom else None, "traffic": traffic,
+                "kernel": dom["name"] if dom else None,
+                "launches_sampled": int(dom["launches"]) if dom else 0, "avg_launch_us": dom["avg_us"] if dom else None,
+                "avg_launch_bytes": dom["avg_bytes"] if dom else None,
+                "note": "the sampled launch kind with the largest stencil time in the timed learned + mixed steps; "
+                        "algorithmic bytes (links once per launch in the stored format, every spinor operand once)"}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(cfg, U, phi, kappa, last_ref, min(args.cpu_iters, 10 if cfg.volume > 300_000 else 40))
+    rs, tr, rr = last
+    rs_r, rr_r = last_ref
+    result = {
+        "metric": METRIC, "value": value, "unit": "RHS/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": value / value_ref, "dtype": "f64+f32 (learned + mixed)", "data": "synthetic",
+        "config": {"workload": f"learned + mixed Seed-CG against plain FP64 Seed-CG, Wilson even-odd M = A^dag A on "
+                               f"{'x'.join(map(str, cfg.dims))}"
+                               f"{' with a topological flux background' if cfg.flux else ''}, "
+                               f"lambda_min/lambda_max {cfg.ratio:g}, {nrhs} RHS, tol {cfg.tol:g}, k={cfg.reorth_k}",
+                   "name": cfg.name, "lattice": list(cfg.dims), "kappa": kappa, "nrhs": nrhs, "reorth_k": cfg.reorth_k,
+                   "past_factor": cfg.past, "tol": cfg.tol, "train_steps": args.train_steps,
+                   "deflated_ritz_vectors": args.deflate_k, "m_max": m_max},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "detail": {
+            "vs_baseline_is": "learned + mixed RHS/s (training counted) over plain FP64 Seed-CG RHS/s on the same lattice, "
+                              "inputs and GPU, timed in the same run",
+            "plain_fp64": {"rhs_per_s": value_ref, "steps": nref, "ms_per_step": 1e3 * elapsed_ref / nref, "m": rs_r["m"],
+                           "i_conv": rs_r["i_conv"], "t_seed_s": rs_r["t_seed_s"], "t_rest_s": rr_r["t_rest_s"],
+                           "cg_iters": rr_r["iters"], "max_true_relres": max(rr_r["true_relres"]),
+                           "dominant_stencil": dominant_kind(kinds_ref)},
+            "learned_mixed": {"rhs_per_s": value, "rhs_per_s_without_training": solved / max(elapsed - t_train, 1e-9),
+                              "t_train_s_per_step": t_train / args.steps, "m": rs["m"], "i_conv": rs["i_conv"],
+                              "t_seed_s": rs["t_seed_s"], "t_rest_s": rr["t_rest_s"], "cg_iters": rr["iters"],
+                              "max_true_relres": max(rr["true_relres"]), "training": tr},
+            "stencil_kinds": kinds, "dagger_d": dd, "device_copy_gbs": copy_rate(),
+        },
     }
     print(json.dumps(result), flush=True)
 
@@ -451,15 +651,18 @@ def bench_batch(args):
     print(json.dumps(result), flush=True)
 
 
-def measured_traffic(cfg, prec):
+def measured_traffic(cfg, tag, kernel=None):
     """HBM bytes per stencil launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary of this
-    workload, or None when there is none or the stencil source changed since it was taken."""
+    workload (and, when given, of this kernel), or None when there is none or the stencil source
+    changed since it was taken."""
     from paper_0901_3512_amd.profsummary import source_digest
-    name = f"hop_kernel_{'x'.join(map(str, cfg.dims))}_{prec}_traffic.txt"
+    name = f"hop_kernel_{'x'.join(map(str, cfg.dims))}_{tag}_traffic.txt"
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     kv = dict(l.strip().split("=", 1) for l in open(path) if "=" in l and not l.startswith("#"))
+    if kernel is not None and kv.get("kernel") != kernel:
+        return None
     src = os.path.join(ROOT, "paper_0901_3512_amd", "csrc", "dslash.hip")
     if kv.get("source_sha256_16") != source_digest(src):
         return None
@@ -475,11 +678,11 @@ def cpu_baseline(cfg, U, phi, kappa, rep, n_iter):
     op = WilsonEO(U, cfg.dims, kappa, t_bc=cfg.t_bc)
     mv = matvec_M(op)
     B = flat(op.apply_Adag(phi))
-    # (1) Algorithm 1 without step 8: cost per Lanczos step with the seeding of every RHS
+    # (1) Algorithm 1 without reorthogonalisation: cost per Lanczos step with the seeding of every RHS
     t0 = time.perf_counter()
     osc.seed_cg(mv, B, k=0, tol=cfg.tol, m=n_iter)
     t_step = (time.perf_counter() - t0) / n_iter
-    # (2) the same with step 8 at every step: the extra time per basis vector reorthogonalised against
+    # (2) the same reorthogonalised at every step: the extra time per basis vector reorthogonalised against
     t0 = time.perf_counter()
     osc.seed_cg(mv, B, k=1, tol=cfg.tol, m=n_iter)
     t_k1 = time.perf_counter() - t0
@@ -493,6 +696,7 @@ def cpu_baseline(cfg, U, phi, kappa, rep, n_iter):
     reorth_vecs = sum(range(k, m + 1, k)) if k else 0
     t_total = m * t_step + reorth_vecs * t_vec + sum(rr["iters"]) * t_cg
     return {"value": cfg.nrhs / t_total, "unit": "RHS/s", "cores": num_threads(), "kind": "oracle",
+            "cpu_model": cpu_model(), "extrapolated": True,
             "sample": f"{n_iter} Algorithm-1 steps on {cfg.nrhs} RHS without and with reorthogonalisation "
                       f"({t_step:.3f} s/step, {t_vec * 1e3:.2f} ms per basis vector reorthogonalised against) and "
                       f"{n_iter} CG steps ({t_cg:.3f} s/step) on {'x'.join(map(str, cfg.dims))}, extrapolated to the "

@@ -28,3 +28,18 @@ def test_traffic_is_reported_only_for_the_current_stencil_source():
     current = kv["source_sha256_16"] == source_digest(src)
     t = bench.measured_traffic(cfg, "fp64")
     assert (t == float(kv["traffic_bytes_per_launch"])) if current else (t is None)
+
+
+def test_dominant_kind_names_the_rocprof_kernel_and_traffic_needs_that_kernel():
+    sys.path.insert(0, ROOT)
+    import bench
+    from synth.configs import CONFIGS
+    kinds = [dict(fmt=3, nvec=1, fused=0, tps=8, vb=1, launches=100, ms=5.0, bytes=8e9),
+             dict(fmt=4, nvec=11, fused=1, tps=8, vb=2, launches=10, ms=9.0, bytes=9e9)]
+    d = bench.dominant_kind(kinds)
+    assert d["nvec"] == 11 and abs(d["avg_us"] - 900.0) < 1e-9 and abs(d["gbs"] - 1000.0) < 1e-9
+    assert bench.kind_kernel(d) == "scg::hop_split_kernel<float, scg::su3rows<float>, 2, true>"
+    assert bench.kind_tag(d) == "fp32_split_vb2_cgu"
+    assert bench.kind_kernel(dict(fmt=0, nvec=1, fused=0, tps=10, vb=1)) == "scg::hop_quad_kernel<double, double, false>"
+    # a traffic summary of another kernel is never used for this one
+    assert bench.measured_traffic(CONFIGS["c2"], "fp64", "scg::some_other_kernel") is None

@@ -19,6 +19,7 @@
 #include <hip/hip_bf16.h>
 #include <cstdlib>
 #include <stdexcept>
+#include <type_traits>
 
 namespace scg {
 
@@ -935,41 +936,16 @@ struct Stage {
     int rown, whole;
 };
 
-// One hop direction of the wave-split kernel for NV vectors: the neighbour's spinor projected
-// with (1 -/+ gamma_mu), multiplied by U (forward) or U^dag (backward) and reconstructed into acc.
-// PLANE: x and y neighbours come from the LDS stage.
-template <typename T, typename LT, int NV, int MU, bool BWD, bool PLANE>
-__device__ __attribute__((always_inline)) inline void split_dir(const Geom& g, const typename LinkLoad<LT>::Store* __restrict__ links, const cx<T>* __restrict__ in,
-                                 const int (&vec)[NV], int p, int x, int y, int z, int t, int xh, uint32_t h32,
-                                 const Stage<T>& sg, cx<T> (&acc)[NV][12]) {
+// The spinor half of one hop direction of the wave-split kernels for NV vectors: the neighbour's
+// spinor (site hn, or staged site ln with LDS) projected with (1 -/+ gamma_mu), multiplied by the
+// link u (forward) or u^dag (backward) and reconstructed into acc with the boundary sign.
+template <typename T, int NV, int MU, bool BWD, bool LDS>
+__device__ __attribute__((always_inline)) inline void split_body(const cx<T> (&u)[9], uint32_t hn, uint32_t ln, T sign,
+                                                                 const cx<T>* __restrict__ in, uint32_t Vh32, const int (&vec)[NV],
+                                                                 const Stage<T>& sg, cx<T> (&acc)[NV][12]) {
     using C = PJ<MU>;
     constexpr int s = BWD ? -1 : 1;   // the backward hop negates every coefficient
     constexpr int a0 = C::a0, a1 = 5 - C::a0;
-    int nsign;
-    const uint32_t hn = nb_split<MU, BWD>(g, x, y, z, t, xh, h32, nsign);
-    const T sign = (T)nsign;
-    constexpr bool LDS = PLANE && MU <= 1;
-    uint32_t ln = 0;   // the neighbour's staged site
-    if constexpr (LDS) {
-        if constexpr (MU == 0) {
-            const int xn = BWD ? (x == 0 ? g.L[0] - 1 : x - 1) : (x == g.L[0] - 1 ? 0 : x + 1);
-            ln = (uint32_t)(sg.rown * g.Lxh + (xn >> 1));
-        } else {
-            int rn = BWD ? sg.rown - 1 : sg.rown + 1;
-            if (sg.whole) rn = BWD ? (y == 0 ? g.L[1] - 1 : rn) : (y == g.L[1] - 1 ? 0 : rn);
-            ln = (uint32_t)(rn * g.Lxh + xh);
-        }
-    }
-    const uint32_t Vh32 = (uint32_t)g.Vh;
-    const uint32_t lpar = BWD ? 1u - (uint32_t)p : (uint32_t)p;
-    using S = typename LinkLoad<LT>::Store;
-    constexpr int NE = LinkLoad<LT>::NE;
-    const auto lr = buf_rsrc(links + (size_t)(MU * 2 + lpar) * NE * Vh32, (uint32_t)NE * Vh32 * (uint32_t)sizeof(S));
-    const uint32_t loff = (BWD ? hn : h32) * (uint32_t)sizeof(S);
-    cx<T> u[9];
-#pragma unroll
-    for (int c = 0; c < NE; c++) u[c] = LinkLoad<LT>::template cvt<T>(bload<S>(lr, loff, (uint32_t)c * Vh32 * (uint32_t)sizeof(S)));
-    if constexpr (NE == 6) su3_third_row(u);
     const uint32_t soff = hn * (uint32_t)sizeof(cx<T>);
 #pragma unroll
     for (int v = 0; v < NV; v++) {
@@ -1010,6 +986,61 @@ __device__ __attribute__((always_inline)) inline void split_dir(const Geom& g, c
             acc_fma(acc[v][9 + a], sign, umulc<s * C::d1r, s * C::d1i>(C::b0 == 1 ? ch[0] : ch[1]));
         }
     }
+}
+
+// The stored link of one hop direction of the wave-split kernels (forward: U_mu at the site;
+// backward: U_mu at the neighbour, of the other parity), with the neighbour's index and the
+// boundary sign of the hop.
+template <typename LT, int MU, bool BWD>
+__device__ __attribute__((always_inline)) inline void split_link(const Geom& g, const typename LinkLoad<LT>::Store* __restrict__ links,
+                                                                 int p, int x, int y, int z, int t, int xh, uint32_t h32,
+                                                                 typename LinkLoad<LT>::Store (&ul)[LinkLoad<LT>::NE], uint32_t& hn,
+                                                                 int& nsign) {
+    hn = nb_split<MU, BWD>(g, x, y, z, t, xh, h32, nsign);
+    const uint32_t Vh32 = (uint32_t)g.Vh;
+    const uint32_t lpar = BWD ? 1u - (uint32_t)p : (uint32_t)p;
+    using S = typename LinkLoad<LT>::Store;
+    constexpr int NE = LinkLoad<LT>::NE;
+    const auto lr = buf_rsrc(links + (size_t)(MU * 2 + lpar) * NE * Vh32, (uint32_t)NE * Vh32 * (uint32_t)sizeof(S));
+    const uint32_t loff = (BWD ? hn : h32) * (uint32_t)sizeof(S);
+#pragma unroll
+    for (int c = 0; c < NE; c++) ul[c] = bload<S>(lr, loff, (uint32_t)c * Vh32 * (uint32_t)sizeof(S));
+}
+
+// the link in the arithmetic precision, its third row rebuilt from the stored two
+template <typename T, typename LT>
+__device__ __attribute__((always_inline)) inline void split_widen(const typename LinkLoad<LT>::Store (&ul)[LinkLoad<LT>::NE], cx<T> (&u)[9]) {
+    constexpr int NE = LinkLoad<LT>::NE;
+#pragma unroll
+    for (int c = 0; c < NE; c++) u[c] = LinkLoad<LT>::template cvt<T>(ul[c]);
+    if constexpr (NE == 6) su3_third_row(u);
+}
+
+// One hop direction of the wave-split kernel for NV vectors.  PLANE: x and y neighbours come from
+// the LDS stage.
+template <typename T, typename LT, int NV, int MU, bool BWD, bool PLANE>
+__device__ __attribute__((always_inline)) inline void split_dir(const Geom& g, const typename LinkLoad<LT>::Store* __restrict__ links, const cx<T>* __restrict__ in,
+                                 const int (&vec)[NV], int p, int x, int y, int z, int t, int xh, uint32_t h32,
+                                 const Stage<T>& sg, cx<T> (&acc)[NV][12]) {
+    constexpr bool LDS = PLANE && MU <= 1;
+    uint32_t ln = 0;   // the neighbour's staged site
+    if constexpr (LDS) {
+        if constexpr (MU == 0) {
+            const int xn = BWD ? (x == 0 ? g.L[0] - 1 : x - 1) : (x == g.L[0] - 1 ? 0 : x + 1);
+            ln = (uint32_t)(sg.rown * g.Lxh + (xn >> 1));
+        } else {
+            int rn = BWD ? sg.rown - 1 : sg.rown + 1;
+            if (sg.whole) rn = BWD ? (y == 0 ? g.L[1] - 1 : rn) : (y == g.L[1] - 1 ? 0 : rn);
+            ln = (uint32_t)(rn * g.Lxh + xh);
+        }
+    }
+    typename LinkLoad<LT>::Store ul[LinkLoad<LT>::NE];
+    uint32_t hn;
+    int nsign;
+    split_link<LT, MU, BWD>(g, links, p, x, y, z, t, xh, h32, ul, hn, nsign);
+    cx<T> u[9];
+    split_widen<T, LT>(ul, u);
+    split_body<T, NV, MU, BWD, LDS>(u, hn, ln, (T)nsign, in, (uint32_t)g.Vh, vec, sg, acc);
 }
 
 // the four directions of one hop side
@@ -1151,6 +1182,161 @@ __global__ __launch_bounds__(SCG_BLOCK) void hop_split_kernel(Geom g, const type
                 e.partials[(int64_t)q * nsb + sb] = s;
             }
         }
+    }
+}
+
+// ---- link-resident multi-vector variant ------------------------------------------------------
+// The wave-split kernel for launches of many vectors.  One workgroup per site block runs through
+// every vector of the launch, NV at a time, holding the stored form of its side's four links in
+// registers all the while: each link is read from memory once per launch instead of once per group
+// of NV vectors.  The site blocks (all resident at once, or nearly) advance through the vectors
+// together, so a block's z and t neighbours for a vector were fetched for that same vector by the
+// blocks around it shortly before, as in a one-vector launch, instead of a whole set of vector groups
+// earlier.  The reduction partials are indexed like the wave-split kernel's.
+// An empty asm statement that claims to change the held link registers: without it the compiler
+// keeps the widened links (nine complex entries per direction) across the vector loop, which costs
+// more registers than the stored form it is rebuilt from.
+template <typename S>
+__device__ __attribute__((always_inline)) inline void opaque(S& v) {
+    if constexpr (sizeof(S) == 4) {
+        asm volatile("" : "+v"(v));
+    } else {
+        static_assert(sizeof(S) == 8, "held link entries are 4 or 8 bytes");
+        asm volatile("" : "+v"(v.re), "+v"(v.im));
+    }
+}
+
+template <typename T, typename LT, int NV, bool BWD>
+__device__ __attribute__((always_inline)) inline void stream_hops(const typename LinkLoad<LT>::Store (&ul)[4][LinkLoad<LT>::NE],
+                                                                  const uint32_t (&hn)[4], const T (&sgn)[4], const cx<T>* __restrict__ in,
+                                                                  uint32_t Vh32, const int (&vec)[NV], bool active, cx<T> (&acc)[NV][12]) {
+    if (!active) return;
+    const Stage<T> sg{nullptr, 0, 0, 0};
+    cx<T> u[9];
+    split_widen<T, LT>(ul[0], u);
+    split_body<T, NV, 0, BWD, false>(u, hn[0], 0, sgn[0], in, Vh32, vec, sg, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    split_widen<T, LT>(ul[1], u);
+    split_body<T, NV, 1, BWD, false>(u, hn[1], 0, sgn[1], in, Vh32, vec, sg, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    split_widen<T, LT>(ul[2], u);
+    split_body<T, NV, 2, BWD, false>(u, hn[2], 0, sgn[2], in, Vh32, vec, sg, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    split_widen<T, LT>(ul[3], u);
+    split_body<T, NV, 3, BWD, false>(u, hn[3], 0, sgn[3], in, Vh32, vec, sg, acc);
+}
+
+template <typename LT, bool BWD>
+__device__ __attribute__((always_inline)) inline void stream_links(const Geom& g, const typename LinkLoad<LT>::Store* __restrict__ links,
+                                                                   int p, int x, int y, int z, int t, int xh, uint32_t h32,
+                                                                   typename LinkLoad<LT>::Store (&ul)[4][LinkLoad<LT>::NE],
+                                                                   uint32_t (&hn)[4], int (&ns)[4]) {
+    split_link<LT, 0, BWD>(g, links, p, x, y, z, t, xh, h32, ul[0], hn[0], ns[0]);
+    split_link<LT, 1, BWD>(g, links, p, x, y, z, t, xh, h32, ul[1], hn[1], ns[1]);
+    split_link<LT, 2, BWD>(g, links, p, x, y, z, t, xh, h32, ul[2], hn[2], ns[2]);
+    split_link<LT, 3, BWD>(g, links, p, x, y, z, t, xh, h32, ul[3], hn[3], ns[3]);
+}
+
+template <typename T, typename LT, int NV, bool CGU = false>
+__global__ __launch_bounds__(SCG_BLOCK) void hop_stream_kernel(Geom g, const typename LinkLoad<LT>::Store* __restrict__ links,
+                                                               const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+                                                               int p, int nvec, int64_t nsb, EpiDev<T> e, int64_t cs, int64_t bps) {
+    __shared__ cx<T> xch[NV * 2 * 6 * (SCG_BLOCK / 2)];
+    __shared__ double red_lds[NV * (SCG_BLOCK / SCG_WAVE)];
+    zoff_hop(cs, links, in, out, e);
+    if (e.gate_m && e.gate_i > *e.gate_m) return;
+    if (e.kappa2_dev) e.kappa2 = (T)*e.kappa2_dev;
+    const int64_t sb = xcd_logical_block(nsb);   // position in the visiting order
+    if (sb >= nsb) return;
+    const int64_t Vh = g.Vh;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / SCG_WAVE));
+    const bool bwd = wave >= 2;                                   // uniform over the wavefront
+    const int sl = (wave & 1) * SCG_WAVE + (int)(threadIdx.x % SCG_WAVE);   // site within the block
+    const int64_t h = sb_order(sb, bps, g.L[3]) * (SCG_BLOCK / 2) + sl;
+    const bool active = h < Vh;
+
+    int x = 0, y = 0, z = 0, t = 0, xh = 0;
+    if (active) {
+        const uint32_t hu = (uint32_t)h;
+        xh = (int)(hu % (uint32_t)g.Lxh);
+        uint32_t r = hu / (uint32_t)g.Lxh;
+        y = (int)(r % (uint32_t)g.L[1]);
+        r /= (uint32_t)g.L[1];
+        z = (int)(r % (uint32_t)g.L[2]);
+        t = (int)(r / (uint32_t)g.L[2]);
+        x = 2 * xh + ((y + z + t + p) & 1);
+    }
+    const uint32_t Vh32 = (uint32_t)Vh, h32 = (uint32_t)h;
+
+    // this side's four links, read once for the whole launch
+    typename LinkLoad<LT>::Store ul[4][LinkLoad<LT>::NE];
+    uint32_t hn[4] = {0, 0, 0, 0};
+    int ns[4] = {1, 1, 1, 1};
+    if (active) {
+        if (bwd)
+            stream_links<LT, true>(g, links, p, x, y, z, t, xh, h32, ul, hn, ns);
+        else
+            stream_links<LT, false>(g, links, p, x, y, z, t, xh, h32, ul, hn, ns);
+    }
+    const T sgn[4] = {(T)ns[0], (T)ns[1], (T)ns[2], (T)ns[3]};
+
+    constexpr int nwave = SCG_BLOCK / SCG_WAVE;
+    constexpr uint32_t xs = SCG_BLOCK / 2;
+    const int nvg = (nvec + NV - 1) / NV;
+    for (int vg = 0; vg < nvg; vg++) {
+        // the group's vectors (-1: empty slot, or a vector whose CG is done or frozen); uniform
+        int vec[NV];
+        bool any = false;
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            const int slot = vg * NV + v;
+            int q = -1;
+            if (slot < nvec) {
+                q = e.vec_map ? e.vec_map[slot] : slot;
+                if (q >= 0 && e.cg && (e.cg[q].done || e.cg[q].frozen)) q = -1;
+            }
+            vec[v] = __builtin_amdgcn_readfirstlane(q);
+            any = any || vec[v] >= 0;
+        }
+        if (!any) continue;   // uniform over the workgroup
+#pragma unroll
+        for (int d = 0; d < 4; d++)
+#pragma unroll
+            for (int c = 0; c < LinkLoad<LT>::NE; c++) opaque(ul[d][c]);
+
+        cx<T> acc[NV][12];
+#pragma unroll
+        for (int v = 0; v < NV; v++)
+#pragma unroll
+            for (int c = 0; c < 12; c++) acc[v][c] = mk<T>(0, 0);
+        if (bwd) {
+            stream_hops<T, LT, NV, true>(ul, hn, sgn, in, Vh32, vec, active, acc);
+            split_handover<T, NV, true>(acc, xch, xs, sl);
+        } else {
+            stream_hops<T, LT, NV, false>(ul, hn, sgn, in, Vh32, vec, active, acc);
+            split_handover<T, NV, false>(acc, xch, xs, sl);
+        }
+        __syncthreads();
+        if (bwd)
+            split_tail<T, NV, true, CGU>(e, vec, active, Vh32, h32, sl, wave, nwave, acc, xch, xs, out, red_lds);
+        else
+            split_tail<T, NV, false, CGU>(e, vec, active, Vh32, h32, sl, wave, nwave, acc, xch, xs, out, red_lds);
+        if (e.red) {
+            __syncthreads();
+            const int v = threadIdx.x;
+            if (v < NV) {
+                int q = -1;
+#pragma unroll
+                for (int k = 0; k < NV; k++)
+                    if (k == v) q = vec[k];
+                if (q >= 0) {
+                    double s = 0.0;
+                    for (int w = 0; w < nwave; w++) s += red_lds[v * nwave + w];
+                    e.partials[(int64_t)q * nsb + sb] = s;
+                }
+            }
+        }
+        __syncthreads();   // the exchange and reduction LDS are rewritten by the next group
     }
 }
 
@@ -1394,12 +1580,14 @@ static int norm_vb(int tps, int vb, int nvec) {
     if (tps == 7) vb = vb <= 2 ? 2 : 4;
     if (tps == 8 || tps == 9) vb = vb <= 1 ? 1 : (vb <= 2 ? 2 : 4);
     if (tps == 10) vb = 1;
+    if (tps == 11) vb = vb <= 1 ? 1 : 2;
     return vb;
 }
 
 bool hop_shape_ok(const Geom& g, Prec prec, int tps, int vb) {
-    if (tps < 1 || tps > 10) return false;
+    if (tps < 1 || tps > 11) return false;
     const size_t es = (prec == P64 || prec == P64R) ? 16 : 8;
+    if (tps == 11 && es != 8) return false;   // FP32 arithmetic only (FP64 would not fit in registers)
     if (tps >= 8 && (double)g.Vh * 12.0 * (double)es >= 4294967296.0) return false;
     if (tps == 9) {
         const size_t b = plane_lds_bytes(g, norm_vb(9, vb, 4), es);
@@ -1434,14 +1622,16 @@ void set_hop_hoist_links(bool on) { g_hoist = on ? 1 : 0; }
 // vectors per workgroup)
 // tps 9: the LDS-staged variant (tiles of whole xy-rows, vb 1, 2 or 4); one workgroup per tile
 // tps 10: the quad-split variant (four wavefronts per 64 sites, one vector per workgroup)
+// tps 11: the link-resident variant (wave-split, one workgroup per site block for every vector of
+// the launch, vb 1 or 2 at a time)
 int hop_threads_per_site(int tps) { return tps == 10 ? 4 : ((tps == 3 || tps >= 5) ? 2 : tps); }
 int hop_site_blocks(const Geom& g, int tps) {
     if (tps == 9) return g.L[2] * g.L[3] * plane_tiles(g);
     return (int)((g.Vh * hop_threads_per_site(tps) + SCG_BLOCK - 1) / SCG_BLOCK);
 }
 
-// the wave-split (tps 8), LDS-staged (9) and quad-split (10) stencils; CGU: with the CG update fused
-// into the epilogue
+// the wave-split (tps 8), LDS-staged (9), quad-split (10) and link-resident (11) stencils; CGU: with
+// the CG update fused into the epilogue
 template <typename T, typename LT, bool CGU>
 static void launch_wide(const Geom& g, const typename LinkLoad<LT>::Store* links, const cx<T>* in, cx<T>* out, int p, int nvec,
                         int64_t nsb, const EpiDev<T>& e, int tps, int vb, int64_t grid, int64_t bps, const Launch& L) {
@@ -1461,6 +1651,13 @@ static void launch_wide(const Geom& g, const typename LinkLoad<LT>::Store* links
             hipLaunchKernelGGL((hop_plane_kernel<T, LT, 2, CGU>), gr, dim3(2 * Pw), lds, s, g, links, in, out, p, nvec, nsb, e, L.cs, Pw);
         else
             hipLaunchKernelGGL((hop_plane_kernel<T, LT, 4, CGU>), gr, dim3(2 * Pw), lds, s, g, links, in, out, p, nvec, nsb, e, L.cs, Pw);
+    } else if (tps == 11) {
+        if constexpr (!std::is_same<T, float>::value)
+            throw std::runtime_error("the link-resident stencil runs in FP32 only");
+        else if (vb == 1)
+            hipLaunchKernelGGL((hop_stream_kernel<T, LT, 1, CGU>), gr, dim3(SCG_BLOCK), 0, s, g, links, in, out, p, nvec, nsb, e, L.cs, bps);
+        else
+            hipLaunchKernelGGL((hop_stream_kernel<T, LT, 2, CGU>), gr, dim3(SCG_BLOCK), 0, s, g, links, in, out, p, nvec, nsb, e, L.cs, bps);
     } else if (vb == 1)
         hipLaunchKernelGGL((hop_split_kernel<T, LT, 1, CGU>), gr, dim3(SCG_BLOCK), 0, s, g, links, in, out, p, nvec, nsb, e, L.cs, bps);
     else if (vb == 2)
@@ -1495,14 +1692,14 @@ static void launch_t(const Geom& g, const void* links, const void* in, void* out
     e.R = (cx<T>*)epi.R;
     if (epi.red == 3 && (!epi.cg || !epi.d || !epi.X || !epi.R || !epi.combine || epi.z || tps < 8 ||
                          (double)g.Vh * 12.0 * 16.0 >= 4294967296.0))
-        throw std::runtime_error("fused CG update: needs cg, p, X, R, the combine and the tps 8, 9 or 10 stencil");
+        throw std::runtime_error("fused CG update: needs cg, p, X, R, the combine and a tps 8 to 11 stencil");
     const int64_t nsb = hop_site_blocks(g, tps);
     vb = norm_vb(tps, vb, nvec);
     // the wave-split kernels address a vector with 32-bit byte offsets, the staged one needs its LDS:
     // the handle's shapes were checked with hop_shape_ok (the reduction partials depend on the shape)
     if (tps >= 8 && (double)g.Vh * 12.0 * (double)sizeof(cx<T>) >= 4294967296.0)
         throw std::runtime_error("stencil launch shape does not fit this lattice");
-    const int64_t grid = xcd_grid(nsb * ((nvec + vb - 1) / vb));
+    const int64_t grid = xcd_grid(tps == 11 ? nsb : nsb * ((nvec + vb - 1) / vb));
     // site blocks per t-slice for the tiled visiting order (two lanes per site, 128 sites a block)
     const int64_t slice = g.Vh / g.L[3];
     const int64_t bps = (slice % (SCG_BLOCK / 2) == 0 && getenv_order()) ? slice / (SCG_BLOCK / 2) : 0;

@@ -19,7 +19,7 @@ from synth.links import random_su3_links
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [("8", "1"), ("8", "2"), ("8", "4"), ("9", "1"), ("9", "2"), ("9", "4"), ("10", "1")]
+SHAPES = [("8", "1"), ("8", "2"), ("8", "4"), ("9", "1"), ("9", "2"), ("9", "4"), ("10", "1"), ("11", "1"), ("11", "2")]
 
 
 def _problem(dims, nrhs=6, seed=11):
@@ -47,6 +47,8 @@ def _solve(U, dims, kappa, B, prec, fused, shape, monkeypatch):
 @pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 2, 6), (8, 8, 8, 8)])
 @pytest.mark.parametrize("shape", SHAPES)
 def test_fused_cg_step_matches_separate_update(prec, dims, shape, monkeypatch):
+    if prec == "fp64" and shape[0] == "11":
+        pytest.skip("the link-resident stencil (11) runs in FP32 only")
     print_case("fused cg", prec, dims, shape)
     U, kappa, op, B = _problem(dims)
     Xf, rf = _solve(U, dims, kappa, B, prec, True, shape, monkeypatch)

@@ -107,10 +107,11 @@ int64_t k_grad_blocks(const Geom& g);
 void k_embed(bool x32, const void* x, void* full, int64_t n, const int32_t* vmap, int nvec, hipStream_t s);
 void k_restrict(bool x32, const void* full, void* x, int64_t n, const int32_t* vmap, int nvec, hipStream_t s);
 void k_zero_odd(void* full, int64_t n, int nvec, hipStream_t s);
-// the loss residual on the even sites of the band (nt = 0: all of them)
+// the loss residual on the even sites of the band (nt = 0: all of them); the gradient field is written
+// there only
 void k_residual(const void* zfull, const void* u, const double* unorm2, void* gfull, int64_t n, int S, double* part, hipStream_t s,
                 const Geom& g, int t0 = 0, int nt = 0);
-int64_t k_residual_blocks(int64_t n);
+int64_t k_residual_blocks(const Geom& g, int t0 = 0, int nt = 0);
 void k_adam(double* Wm, void* W32, double* G, double* m, double* v, int t, double lr, int n, hipStream_t s);
 // X = V S for nout <= 16 outputs (S: m x nout row-major); X in FP32, or FP64 with x64
 void k_combine(bool v32, const void* V, int m, const double* S, int nout, void* X, int64_t n, hipStream_t s, bool x64 = false);

@@ -124,12 +124,19 @@ __device__ inline bool vanishes(int zero_odd_input, int d, int p) { return zero_
 
 // out = L in (dagger = 0) or L^dag in (dagger = 1) on the output parities of pmask, for the vectors
 // listed in vmap (or 0..nvec-1): NV vectors per thread, every link read once per site and direction.
+// A workgroup takes 128 sites: waves 0-1 the identity term and the forward transports d = 1..4,
+// waves 2-3 the backward transports d = 5..8, so each lane follows half the chain of dependent loads;
+// the backward half's sums reach the forward lanes through LDS.  Workgroup b takes vector group
+// b % nvg of site block b / nvg, so the groups of one site block run as neighbouring workgroups and
+// find its links in L2.
+constexpr int K_LAYER_SITES = 128;
 template <int NV>
 __global__ __launch_bounds__(256) void k_layer_kernel(Geom g, const cx<float>* __restrict__ links, const cx<float>* __restrict__ in,
                                                       cx<float>* __restrict__ out, const cx<float>* __restrict__ W, int dagger,
                                                       const int32_t* vmap, int nvec, int zero_odd_input, int pmask, Band band,
                                                       Band in_band) {
     __shared__ cx<float> w[9 * 16];
+    __shared__ cx<float> xch[NV * 12 * K_LAYER_SITES];
     for (int k = threadIdx.x; k < 9 * 16; k += blockDim.x) {
         const int d = k / 16, e = k % 16, a = e / 4, b = e % 4;
         if (!dagger) {
@@ -140,61 +147,77 @@ __global__ __launch_bounds__(256) void k_layer_kernel(Geom g, const cx<float>* _
         }
     }
     __syncthreads();
-    int p, h;
-    if (!site_of_launch(g, pmask, band, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, p, h)) return;
+    const int nvg = (nvec + NV - 1) / NV;
+    const int vg = (int)(blockIdx.x % (unsigned)nvg);
+    const int64_t sb = blockIdx.x / (unsigned)nvg;
+    const int side = (int)(threadIdx.x / K_LAYER_SITES);   // uniform over the wavefront
+    const int sl = (int)(threadIdx.x % K_LAYER_SITES);
+    int p = 0, h = 0;
+    const bool valid = site_of_launch(g, pmask, band, sb * K_LAYER_SITES + sl, p, h);
     const int Vh = (int)g.Vh;
     int vec[NV];
 #pragma unroll
     for (int j = 0; j < NV; j++) {
-        const int slot = (int)blockIdx.y * NV + j;
+        const int slot = vg * NV + j;
         vec[j] = slot < nvec ? (vmap ? vmap[slot] : slot) : -1;
     }
-    const Site s = site_of(g, p, h);
     cx<float> acc[NV][12];
 #pragma unroll
     for (int j = 0; j < NV; j++)
 #pragma unroll
         for (int c = 0; c < 12; c++) acc[j][c] = mk<float>(0.f, 0.f);
-    for (int d = 0; d < 9; d++) {
-        if (vanishes(zero_odd_input, d, p)) continue;
-        // an input known to vanish outside its band of t-slices (a back-propagated gradient): skip
-        // the terms that would read it there
-        if (in_band.nt < g.L[3]) {
-            int tin = s.t;
-            if (d == 4) tin = s.t + 1 == g.L[3] ? 0 : s.t + 1;
-            if (d == 8) tin = s.t == 0 ? g.L[3] - 1 : s.t - 1;
-            const int dt = tin - in_band.t0 < 0 ? tin - in_band.t0 + g.L[3] : tin - in_band.t0;
-            if (dt >= in_band.nt) continue;
-        }
-        Hop o;
-        if (d) load_hop(g, links, p, h, s, d, o);
-#pragma unroll
-        for (int j = 0; j < NV; j++) {
-            if (vec[j] < 0) continue;
-            const cx<float>* src = in + (int64_t)vec[j] * 24 * Vh;
-            cx<float> t[12];
-            if (d == 0) {
-#pragma unroll
-                for (int c = 0; c < 12; c++) t[c] = src[(int64_t)(p * 12 + c) * Vh + h];
-            } else {
-                apply_hop(o, src, p, Vh, t);
+    if (valid) {
+        const Site s = site_of(g, p, h);
+        const int d0 = side ? 5 : 0, d1 = side ? 9 : 5;
+        for (int d = d0; d < d1; d++) {
+            if (vanishes(zero_odd_input, d, p)) continue;
+            // an input known to vanish outside its band of t-slices (a back-propagated gradient): skip
+            // the terms that would read it there
+            if (in_band.nt < g.L[3]) {
+                int tin = s.t;
+                if (d == 4) tin = s.t + 1 == g.L[3] ? 0 : s.t + 1;
+                if (d == 8) tin = s.t == 0 ? g.L[3] - 1 : s.t - 1;
+                const int dt = tin - in_band.t0 < 0 ? tin - in_band.t0 + g.L[3] : tin - in_band.t0;
+                if (dt >= in_band.nt) continue;
             }
+            Hop o;
+            if (d) load_hop(g, links, p, h, s, d, o);
 #pragma unroll
-            for (int a = 0; a < 4; a++)
+            for (int j = 0; j < NV; j++) {
+                if (vec[j] < 0) continue;
+                const cx<float>* src = in + (int64_t)vec[j] * 24 * Vh;
+                cx<float> t[12];
+                if (d == 0) {
 #pragma unroll
-                for (int b = 0; b < 4; b++) {
-                    const cx<float> wab = w[d * 16 + a * 4 + b];
-#pragma unroll
-                    for (int c = 0; c < 3; c++) acc[j][3 * a + c] = acc[j][3 * a + c] + cmul(wab, t[3 * b + c]);
+                    for (int c = 0; c < 12; c++) t[c] = src[(int64_t)(p * 12 + c) * Vh + h];
+                } else {
+                    apply_hop(o, src, p, Vh, t);
                 }
+#pragma unroll
+                for (int a = 0; a < 4; a++)
+#pragma unroll
+                    for (int b = 0; b < 4; b++) {
+                        const cx<float> wab = w[d * 16 + a * 4 + b];
+#pragma unroll
+                        for (int c = 0; c < 3; c++) acc[j][3 * a + c] = acc[j][3 * a + c] + cmul(wab, t[3 * b + c]);
+                    }
+            }
         }
     }
+    if (side == 1) {
+#pragma unroll
+        for (int j = 0; j < NV; j++)
+#pragma unroll
+            for (int c = 0; c < 12; c++) xch[(j * 12 + c) * K_LAYER_SITES + sl] = acc[j][c];
+    }
+    __syncthreads();
+    if (side == 1 || !valid) return;
 #pragma unroll
     for (int j = 0; j < NV; j++) {
         if (vec[j] < 0) continue;
         cx<float>* dst = out + (int64_t)vec[j] * 24 * Vh + (int64_t)p * 12 * Vh + h;
 #pragma unroll
-        for (int c = 0; c < 12; c++) dst[(int64_t)c * Vh] = acc[j][c];
+        for (int c = 0; c < 12; c++) dst[(int64_t)c * Vh] = acc[j][c] + xch[(j * 12 + c) * K_LAYER_SITES + sl];
     }
 }
 
@@ -209,20 +232,24 @@ int64_t k_sites(const Geom& g, int pmask, Band b) { return (int64_t)(pmask == 3 
 
 void k_layer(const Geom& g, const void* links32, const void* in, void* out, const void* W, bool dagger, const int32_t* vmap,
              int nvec, bool zero_odd_input, hipStream_t s, int pmask, int t0, int nt, int in_t0, int in_nt) {
-    constexpr int NV = 4;
+    // two vectors per thread (four would spill and run one wave per SIMD)
+    constexpr int NV = 2;
     const Band b = make_band(g, t0, nt), ib = make_band(g, in_t0, in_nt);
-    const dim3 grid((unsigned)((k_sites(g, pmask, b) + 255) / 256), (unsigned)((nvec + NV - 1) / NV));
+    const int64_t nsb = (k_sites(g, pmask, b) + K_LAYER_SITES - 1) / K_LAYER_SITES;
     if (nvec == 1)
-        hipLaunchKernelGGL(k_layer_kernel<1>, dim3(grid.x, 1), dim3(256), 0, s, g, (const cx<float>*)links32, (const cx<float>*)in,
+        hipLaunchKernelGGL(k_layer_kernel<1>, dim3((unsigned)nsb), dim3(256), 0, s, g, (const cx<float>*)links32, (const cx<float>*)in,
                            (cx<float>*)out, (const cx<float>*)W, (int)dagger, vmap, nvec, (int)zero_odd_input, pmask, b, ib);
     else
-        hipLaunchKernelGGL(k_layer_kernel<NV>, grid, dim3(256), 0, s, g, (const cx<float>*)links32, (const cx<float>*)in,
-                           (cx<float>*)out, (const cx<float>*)W, (int)dagger, vmap, nvec, (int)zero_odd_input, pmask, b, ib);
+        hipLaunchKernelGGL(k_layer_kernel<NV>, dim3((unsigned)(nsb * ((nvec + NV - 1) / NV))), dim3(256), 0, s, g,
+                           (const cx<float>*)links32, (const cx<float>*)in, (cx<float>*)out, (const cx<float>*)W, (int)dagger, vmap,
+                           nvec, (int)zero_odd_input, pmask, b, ib);
 }
 
 // partial sums over the sites of pmask, colours and vectors of g[a][c] conj((T_dt in)[b][c]) for
 // direction d = blockIdx.y, with dt = d (layer L) or dt = -d (layer L^dag); each link is read once per
-// site for all vectors.  part[d][block][16] complex.
+// site for all vectors.  A thread takes K_GRAD_SPT sites (a workgroup K_GRAD_SPT consecutive runs of
+// 256) and sums their terms in FP32; the workgroup's sum is FP64.  part[d][block][16] complex.
+constexpr int K_GRAD_SPT = 4;
 __global__ __launch_bounds__(256) void k_grad_kernel(Geom g, const cx<float>* __restrict__ links, const cx<float>* __restrict__ gv,
                                                      const cx<float>* __restrict__ in, int dagger, int nvec, int zero_odd_input,
                                                      int pmask, Band band, double* part) {
@@ -230,14 +257,18 @@ __global__ __launch_bounds__(256) void k_grad_kernel(Geom g, const cx<float>* __
     const int d = blockIdx.y;
     const int dt = dagger ? adj_dir(d) : d;
     const int Vh = (int)g.Vh;
-    double acc[32];
+    float acc[32];
 #pragma unroll
-    for (int e = 0; e < 32; e++) acc[e] = 0.0;
-    int p, h;
-    if (site_of_launch(g, pmask, band, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, p, h) && !vanishes(zero_odd_input, dt, p)) {
+    for (int e = 0; e < 32; e++) acc[e] = 0.f;
+#pragma unroll 1
+    for (int r = 0; r < K_GRAD_SPT; r++) {
+        int p, h;
+        const int64_t k = ((int64_t)blockIdx.x * K_GRAD_SPT + r) * blockDim.x + threadIdx.x;
+        if (!site_of_launch(g, pmask, band, k, p, h) || vanishes(zero_odd_input, dt, p)) continue;
         const Site s = site_of(g, p, h);
         Hop o;
         if (dt) load_hop(g, links, p, h, s, dt, o);
+#pragma unroll 1
         for (int v = 0; v < nvec; v++) {
             const cx<float>* src = in + (int64_t)v * 24 * Vh;
             cx<float> t[12], q[12];
@@ -254,22 +285,19 @@ __global__ __launch_bounds__(256) void k_grad_kernel(Geom g, const cx<float>* __
             for (int a = 0; a < 4; a++)
 #pragma unroll
                 for (int b = 0; b < 4; b++) {
-                    float re = 0.f, im = 0.f;
 #pragma unroll
                     for (int c = 0; c < 3; c++) {
                         const cx<float> pr = cjmul(t[3 * b + c], q[3 * a + c]);  // q conj(t)
-                        re += pr.re;
-                        im += pr.im;
+                        acc[2 * (a * 4 + b)] += pr.re;
+                        acc[2 * (a * 4 + b) + 1] += pr.im;
                     }
-                    acc[2 * (a * 4 + b)] += re;
-                    acc[2 * (a * 4 + b) + 1] += im;
                 }
         }
     }
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
 #pragma unroll
     for (int e = 0; e < 32; e++) {
-        double v = acc[e];
+        double v = (double)acc[e];
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
         if (lane == 0) lds[wave * 32 + e] = v;
     }
@@ -308,7 +336,7 @@ int64_t k_grad_blocks(const Geom& g) { return (2 * g.Vh + 255) / 256; }
 void k_grad(const Geom& g, const void* links32, const void* gv, const void* in, bool dagger, int nvec, double* part, double* Gtot,
             hipStream_t s, bool zero_odd_input, int pmask, int t0, int nt) {
     const Band b = make_band(g, t0, nt);
-    const int64_t nb = (k_sites(g, pmask, b) + 255) / 256;
+    const int64_t nb = (k_sites(g, pmask, b) + 256 * K_GRAD_SPT - 1) / (256 * K_GRAD_SPT);
     hipLaunchKernelGGL(k_grad_kernel, dim3((unsigned)nb, 9), dim3(256), 0, s, g, (const cx<float>*)links32, (const cx<float>*)gv,
                        (const cx<float>*)in, (int)dagger, nvec, (int)zero_odd_input, pmask, b, part);
     hipLaunchKernelGGL(k_grad_reduce_kernel, dim3(9), dim3(256), 0, s, part, nb, (int)dagger, Gtot);
@@ -380,39 +408,34 @@ void k_band_norm(const Geom& g, int t0, int nt, const void* u, int S, double* pa
 }
 
 // training residual on the even sites of a band: e = z - u there; loss partials |e|^2 / |u|^2; the
-// gradient field g = E_e e / (S |u|^2) on the band and 0 everywhere else (every site of g is written)
+// gradient field g = E_e e / (S |u|^2) on the even sites of the band.  Nothing else of g is written:
+// the layers and gradients that read g take only its even sites on that band.
 __global__ void k_residual_kernel(Geom g, Band b, const cx<float>* __restrict__ zfull, const cx<float>* __restrict__ u,
                                   const double* unorm2, cx<float>* __restrict__ gfull, int64_t n, int S, double* part) {
     __shared__ double lds[4];
     const int v = blockIdx.y;
+    const int per = b.nt * (int)(g.Vh / g.L[3]);   // even sites of the band
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double e2 = 0.0;
-    if (k < 2 * n) {
-        cx<float> gval = mk<float>(0.f, 0.f);
-        if (k < n) {
-            const int h = (int)(k % g.Vh);
-            const int t = h / (int)(g.Vh / g.L[3]);
-            const int dt = t - b.t0 < 0 ? t - b.t0 + g.L[3] : t - b.t0;
-            if (dt < b.nt) {
-                const cx<float> z = zfull[(int64_t)v * 2 * n + k], uu = u[(int64_t)v * n + k];
-                const double er = (double)z.re - uu.re, ei = (double)z.im - uu.im;
-                e2 = er * er + ei * ei;
-                const double sc = 1.0 / ((double)S * unorm2[v]);
-                gval = mk<float>((float)(er * sc), (float)(ei * sc));
-            }
-        }
-        gfull[(int64_t)v * 2 * n + k] = gval;
+    int p, h;
+    if (k < 12 * (int64_t)per && site_of_launch(g, 1, b, k % per, p, h)) {
+        const int64_t idx = (k / per) * g.Vh + h;   // component k / per of even site h
+        const cx<float> z = zfull[(int64_t)v * 2 * n + idx], uu = u[(int64_t)v * n + idx];
+        const double er = (double)z.re - uu.re, ei = (double)z.im - uu.im;
+        e2 = er * er + ei * ei;
+        const double sc = 1.0 / ((double)S * unorm2[v]);
+        gfull[(int64_t)v * 2 * n + idx] = mk<float>((float)(er * sc), (float)(ei * sc));
     }
     const double s = block_sum(e2, lds);
     if (threadIdx.x == 0) part[(int64_t)v * gridDim.x + blockIdx.x] = s / unorm2[v];
 }
+int64_t k_residual_blocks(const Geom& g, int t0, int nt) { return (12 * k_sites(g, 1, make_band(g, t0, nt)) + 255) / 256; }
 void k_residual(const void* zfull, const void* u, const double* unorm2, void* gfull, int64_t n, int S, double* part, hipStream_t s,
                 const Geom& g, int t0, int nt) {
     const Band b = make_band(g, t0, nt);
-    hipLaunchKernelGGL(k_residual_kernel, dim3((unsigned)((2 * n + 255) / 256), (unsigned)S), dim3(256), 0, s, g, b,
+    hipLaunchKernelGGL(k_residual_kernel, dim3((unsigned)k_residual_blocks(g, t0, nt), (unsigned)S), dim3(256), 0, s, g, b,
                        (const cx<float>*)zfull, (const cx<float>*)u, unorm2, (cx<float>*)gfull, n, S, part);
 }
-int64_t k_residual_blocks(int64_t n) { return (2 * n + 255) / 256; }
 
 // Adam on the reals of 3 x 9 x 16 complex weights (FP64 master, FP32 copy for the kernels);
 // the gradient accumulator is cleared for the next step.

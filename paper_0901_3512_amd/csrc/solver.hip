@@ -851,19 +851,19 @@ double k_pass(seedcg_s* h, int off, int S, bool backward, bool want_loss, int ba
     const int64_t fb = (int64_t)S * 2 * N * 8;
     h->kfield.ensure(10 * fb);
     auto F = [&](int i) { return (void*)((char*)h->kfield.p + i * fb); };
-    void *a0 = F(0), *a1 = F(1), *a2 = F(2), *a3 = F(3), *b0 = F(4), *b1 = F(5), *b2 = F(6), *b3 = F(7), *g = F(8), *gt = F(9);
+    void *a0 = F(0), *a1 = F(1), *a2 = F(2), *a3 = F(3), *b1 = F(5), *b2 = F(6), *b3 = F(7), *g = F(8), *gt = F(9);
     const void* Uo = (const char*)h->kU.p + (int64_t)off * N * 8;
     const void* Yo = (const char*)h->kY.p + (int64_t)off * N * 8;
     h->kpart.ensure(9 * k_grad_blocks(h->g) * 32 * sizeof(double));
-    const int64_t nbr = k_residual_blocks(N);
     const int64_t nbb = k_band_blocks(h->g, band_t0, band_nt);
-    h->klpart.ensure(std::max({norm2_blocks(N), nbr, nbb}) * S * sizeof(double));
-    h->kbn.ensure(32 * sizeof(double));
     const void* L = k_links(h);
     double* Gl[3] = {h->kG.as<double>(), h->kG.as<double>() + K_NW * 2, h->kG.as<double>() + 2 * K_NW * 2};
     // the band of layer j = 1..6 (the loss band widened by 6 - j slices each side); 0 slices: whole lattice
     auto bt0 = [&](int j) { return band_nt ? band_t0 - (6 - j) : 0; };
     auto bnt = [&](int j) { return band_nt ? band_nt + 2 * (6 - j) : 0; };
+    const int64_t nbr = k_residual_blocks(h->g, bt0(6), bnt(6));
+    h->klpart.ensure(std::max({norm2_blocks(N), nbr, nbb}) * S * sizeof(double));
+    h->kbn.ensure(32 * sizeof(double));
     auto ks = h->s;
     // |u|^2 on the loss band, the loss's normalisation
     k_band_norm(h->g, bt0(6), bnt(6), Uo, S, h->klpart.as<double>(), ks);
@@ -874,8 +874,9 @@ double k_pass(seedcg_s* h, int off, int S, bool backward, bool want_loss, int ba
     k_layer(h->g, L, a0, a1, k_weights(h, 2), true, nullptr, S, true, ks, 3, bt0(1), bnt(1));
     k_layer(h->g, L, a1, a2, k_weights(h, 1), true, nullptr, S, false, ks, 3, bt0(2), bnt(2));
     k_layer(h->g, L, a2, a3, k_weights(h, 0), true, nullptr, S, false, ks, 1, bt0(3), bnt(3));
-    HIPCHK(hipMemcpyAsync(b0, a3, fb, hipMemcpyDeviceToDevice, ks));
-    k_zero_odd(b0, N, S, ks);
+    // E_e R_e a3 is a3 itself for every reader: layer 4 and its gradient take an even-only input
+    // (zero_odd_input), so they never read the odd half, which layer 3 did not write
+    void* b0 = a3;
     k_layer(h->g, L, b0, b1, k_weights(h, 0), false, nullptr, S, true, ks, 3, bt0(4), bnt(4));
     k_layer(h->g, L, b1, b2, k_weights(h, 1), false, nullptr, S, false, ks, 3, bt0(5), bnt(5));
     k_layer(h->g, L, b2, b3, k_weights(h, 2), false, nullptr, S, false, ks, 1, bt0(6), bnt(6));
@@ -900,7 +901,7 @@ double k_pass(seedcg_s* h, int off, int S, bool backward, bool want_loss, int ba
     k_layer(h->g, L, gt, g, k_weights(h, 1), true, nullptr, S, false, ks, 3, bt0(4), bnt(4), bt0(5), bnt(5));
     k_grad(h->g, L, g, b0, false, S, h->kpart.as<double>(), Gl[0], ks, true, 3, bt0(4), bnt(4));
     k_layer(h->g, L, g, gt, k_weights(h, 0), true, nullptr, S, false, ks, 1, bt0(3), bnt(3), bt0(4), bnt(4));
-    k_zero_odd(gt, N, S, ks);  // through E_e R_e
+    // through E_e R_e: the odd half of gt (not written above) is read by nobody below
     k_grad(h->g, L, gt, a2, true, S, h->kpart.as<double>(), Gl[0], ks, false, 1, bt0(3), bnt(3));
     k_layer(h->g, L, gt, g, k_weights(h, 0), false, nullptr, S, true, ks, 3, bt0(2), bnt(2), bt0(3), bnt(3));
     k_grad(h->g, L, g, a1, true, S, h->kpart.as<double>(), Gl[1], ks, false, 3, bt0(2), bnt(2));
@@ -1091,7 +1092,7 @@ void train_precond_impl(seedcg_s* h, int steps, int n_ritz, int n_lanczos, doubl
     }
     const int64_t nbn = norm2_blocks(N);
     h->kun2.ensure(S * sizeof(double));
-    h->klpart.ensure(std::max<int64_t>(nbn, k_residual_blocks(N)) * S * sizeof(double));
+    h->klpart.ensure(std::max<int64_t>(nbn, k_residual_blocks(h->g)) * S * sizeof(double));
     norm2_partials(true, h->kU.p, N, S, h->klpart.as<double>(), h->s);
     sum_partials(h->klpart.as<double>(), nbn, S, h->kun2.as<double>(), false, h->s);
     // weights: the Neumann start; Adam state cleared
@@ -1842,7 +1843,9 @@ void tune_shape(seedcg_s* h, bool low, int nvec, const void* x, void* y) {
             HIPCHK(hipEventSynchronize(e1));
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) {
+            // a later candidate must win by 3%: shapes within timing noise of each other (the
+            // one-vector FP64 shapes often are) then resolve to the same pick in every process
+            if (ms < 0.97f * best || best == 1e30f) {
                 best = ms;
                 pick = c;
             }

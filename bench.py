@@ -11,7 +11,8 @@ The headline line (default): `value` is the learned + mixed form, timed per step
   + train_precond (the learned K K^dag, 2000 Adam steps on the seed solve's Ritz vectors and
     residuals, then judged against plain CG on RHS 2)
   + solve_rest (FP32 CG with FP64 reliable updates; PCG with K and the 16 lowest Ritz vectors of the
-    seed basis deflated when K won the judge, deflated CG otherwise);
+    seed basis deflated when K won the judge, otherwise plain CG, deflated only when the judge priced
+    deflation cheaper);
 `vs_baseline` is that RHS/s over plain FP64 Seed-CG's (solve_seed + solve_rest, all FP64) on the same
 lattice, right-hand sides and GPU, timed in the same run: the comparison the metric names.
 Default workload: 24^3 x 48 on the topological flux background at lambda_min/lambda_max = 1.1e-5,
@@ -290,7 +291,9 @@ def bench_metric(args):
     def step_val():
         X = torch.zeros_like(B)
         X, rs = val.solve_seed(B, X)
+        t = time.perf_counter()
         tr = val.train_precond(steps=args.train_steps, n_ritz=4, n_lanczos=12, lr=2e-4)
+        tr["t_train_and_judge_s"] = time.perf_counter() - t
         val.use_precond(tr["accepted"])
         X, rr = val.solve_rest(B, X)
         return rs, tr, rr
@@ -319,8 +322,9 @@ def bench_metric(args):
         last = (rs, tr, rr)
         t_train += tr["t_train_s"]
         solved += sum(1 for r in rr["true_relres"] if r <= cfg.tol)
-        log(f"step {k}: m={rs['m']} seed {rs['t_seed_s']:.2f}s train {tr['t_train_s']:.2f}s ({tr['choice']}) "
-            f"rest {rr['t_rest_s']:.2f}s max relres {max(rr['true_relres']):.2e}")
+        log(f"step {k}: m={rs['m']} seed {rs['t_seed_s']:.2f}s train {tr['t_train_s']:.2f}s (+judge "
+            f"{tr['t_train_and_judge_s'] - tr['t_train_s']:.2f}s, {tr['choice']}, plain CG deflates: "
+            f"{tr['plain_cg_deflates']}) rest {rr['t_rest_s']:.2f}s max relres {max(rr['true_relres']):.2e}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     kinds = val.get_timing_kinds()
@@ -641,9 +645,13 @@ def bench_batch(args):
                                f"k={m0.reorth_k}", "name": "c4", "configurations": len(members), "sites": V,
                    "nrhs": nrhs, "precision": prec},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                     "traffic": measured_traffic(None, None, "hop_", name=f"hop_kernel_batch{len(members)}_{prec}_traffic.txt"),
                      "kernel": "hop kernels of the batch (one launch per shape class, concurrent classes)",
-                     "launches_sampled": tm["launches"], "avg_launch_us": hop_ms * 1e3, "avg_launch_bytes": hop_bytes},
+                     "launches_sampled": tm["launches"], "avg_launch_us": hop_ms * 1e3, "avg_launch_bytes": hop_bytes,
+                     "traffic_note": "HBM bytes per hop launch averaged over every hop dispatch of one timed solve "
+                                     "(rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled); achieved and avg_launch_bytes "
+                                     "average the event-sampled launches of one more solve"},
         "cpu_baseline": None,
         "detail": {"classes": info, "m": [r["m"] for r in last], "i_conv": [r["i_conv"] for r in last],
                    "iters": [r["iters"] for r in last], "max_true_relres": max(max(r["true_relres"]) for r in last)},
@@ -651,17 +659,18 @@ def bench_batch(args):
     print(json.dumps(result), flush=True)
 
 
-def measured_traffic(cfg, tag, kernel=None):
+def measured_traffic(cfg, tag, kernel=None, name=None):
     """HBM bytes per stencil launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary of this
     workload (and, when given, of this kernel), or None when there is none or the stencil source
     changed since it was taken."""
     from paper_0901_3512_amd.profsummary import source_digest
-    name = f"hop_kernel_{'x'.join(map(str, cfg.dims))}_{tag}_traffic.txt"
+    name = name or f"hop_kernel_{'x'.join(map(str, cfg.dims))}_{tag}_traffic.txt"
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     kv = dict(l.strip().split("=", 1) for l in open(path) if "=" in l and not l.startswith("#"))
-    if kernel is not None and kv.get("kernel") != kernel:
+    # "kernel=<name> dispatches=<n>" (the name holds spaces)
+    if kernel is not None and kv.get("kernel", "").rsplit(" dispatches=", 1)[0] != kernel:
         return None
     src = os.path.join(ROOT, "paper_0901_3512_amd", "csrc", "dslash.hip")
     if kv.get("source_sha256_16") != source_digest(src):

@@ -78,11 +78,17 @@ typedef struct {
                                  train_precond has accepted a K (seedcg_use_precond sets it)       */
     int32_t autotune;         /* 1: choose the stencil launch shapes (lanes per site, vectors per
                                  workgroup) by timing the candidates once per lattice shape;
-                                 0: the fixed default (two lanes per site, one vector each)     */
+                                 0: the fixed default (two lanes per site, one vector each).
+                                 The environment can fix them instead (profiler runs, whose
+                                 serialised dispatches make timing unreliable): SEEDCG_TPS and
+                                 SEEDCG_VB for one-vector FP64 launches, SEEDCG_TPS_MULTI and
+                                 SEEDCG_VB_MULTI for several vectors, the same with _LO for the
+                                 inner precision                                                  */
     int32_t deflate;          /* 0: plain CG in solve_rest; n > 0: deflated CG (deflated PCG with the
                                  learned K) with the n (<= 24) lowest Ritz vectors of the last
                                  solve_seed's T, lifted by its stored basis; one configuration,
-                                 at most 24 right-hand sides per solve_rest                        */
+                                 at most 24 right-hand sides per solve_rest.  After train_precond
+                                 plain CG deflates only if its judge found that cheaper            */
     void* stream;             /* hipStream_t; NULL = the null stream                             */
 } seedcg_params;
 
@@ -259,17 +265,21 @@ seedcg_status seedcg_time_M(seedcg_t h, int32_t inner, int32_t nvec, int32_t rep
    c = kappa / sqrt(3).  (K = 1 with zero hops is a saddle point where no hop weight has a gradient.)
    Plain Seed-CG then judges: RHS 2 of the last solve_seed (RHS 1 if it had one) is solved from its
    seeded guess to tol, once with plain CG and once each with PCG (P = K K^dag) under the start and the
-   trained weights, by the solver of solve_rest (deflated when params.deflate > 0).  solve_rest iterates
-   on all the seeded systems at once, where M's links are read once for every vector and K's cost is
-   paid per vector, so each candidate's iterations are priced with the time of one application of M
-   (plus one of K K^dag) to that many vectors, timed with events: the cheapest wins.  The K with fewer
+   trained weights, by the solver of solve_rest (deflated when params.deflate > 0; plain CG also once
+   without deflation then).  solve_rest iterates on all the seeded systems at once, where M's links
+   are read once for every vector and K's cost is paid per vector, so each candidate's iterations are
+   priced with the time of one application of M (plus one of K K^dag, plus one deflation step where
+   it deflates) to that many vectors, timed with events: the cheapest wins.  The K with fewer
    iterations of the two is kept as the weights.  If a K wins it is kept and solve_rest applies it when
-   precond is on; otherwise solve_rest runs plain CG (the fallback).
-   out (HOST, 18 doubles, may be NULL): initial loss, final loss, training seconds, Ritz vectors used,
+   precond is on; otherwise solve_rest runs plain CG (the fallback), deflated only if that was the
+   cheaper plain candidate.
+   out (HOST, 22 doubles, may be NULL): initial loss, final loss, training seconds, Ritz vectors used,
    training vectors, accepted (1 if a K won), the judge's seconds for plain CG, the start K and the
    trained K on one system, their iterations in the same order, the choice (0 plain CG, 1 start K,
-   2 trained K), the seconds of one M and of one K K^dag on the seeded systems, and the predicted
-   seconds of plain CG, the start K and the trained K there.  Each Adam step takes the loss on a band of
+   2 trained K), the seconds of one M and of one K K^dag on the seeded systems, the predicted
+   seconds of plain CG, the start K and the trained K there, then plain CG without deflation: its
+   iterations and predicted seconds, the seconds of one deflation step on the seeded systems, and
+   whether plain CG in solve_rest deflates (1) or not (0).  Each Adam step takes the loss on a band of
    two t-slices (seedcg_precond_loss_grad_band), the bands stepping through the lattice, with a step
    size that decays from lr to 0 on a half cosine; the whole-lattice loss, taken at four checkpoints,
    picks the trained weights (the start's when no checkpoint is lower, and the judge then runs the

@@ -191,6 +191,9 @@ struct seedcg_s {
     std::vector<double> k_judge = std::vector<double>(11, 0.0);
     int k_choice = 0;
     double k_judge_r0 = 0.0;
+    // the judge's verdict on deflating plain CG: -1 none (params.deflate decides), 0 off, 1 on
+    int judge_defl = -1;
+    double k_judge_cg0_it = 0.0, k_judge_cg0_c = 0.0, k_judge_td = 0.0;
     DBuf klossv, kbn;
     // sampled timing of the stencil launches (hipEvent pairs on the handle's stream)
     int timing_every = 0;
@@ -713,6 +716,7 @@ void solve_seed_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report* rep) {
     h->m_used = m_max;
     h->have_seed = true;
     h->defl_stale = true;
+    h->judge_defl = -1;
     h->seed_nrhs = nrhs;
     if (rep) {
         // RHS 1's residual estimate after its last step (Eq. 2), per configuration
@@ -977,17 +981,33 @@ std::vector<double> k_neumann_weights(double kappa) {
 }
 
 seedcg_status solve_rest_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report* rep);
+void deflate_step(seedcg_s* h, bool init, const void* R, int nrhs, const int32_t* map, int w, void* X, bool x32, bool use_cg);
 
 // The judge of the learned K (plain Seed-CG is the fallback and the judge): one system (canonical
 // layout b, starting guess x0) until its FP64 true relative residual is at most `target`, with the solver of
 // solve_rest (deflated when params.deflate asks for it), with or without K.  Returns the wall seconds
 // (infinite when it did not get there) and fills the iterations.
-double k_judge_run(seedcg_s* h, bool use_k, const double* b, const double* x0, double* x, double target, int& iters) {
+// One judge solve of system b from x0 to target: PCG with the current K (use_k) or plain CG, with
+// plain CG's deflation off when defl is false (the built deflation is kept for the later solves).
+double k_judge_run(seedcg_s* h, bool use_k, const double* b, const double* x0, double* x, double target, int& iters,
+                   bool defl = true) {
     HIPCHK(hipMemcpyAsync(x, x0, h->vec_bytes(false), hipMemcpyDeviceToDevice, h->s));
     const seedcg_params saved = h->p;
     const bool acc = h->k_accepted;
+    const int jd = h->judge_defl, nev = h->nev;
+    const std::vector<double> theta = h->ritz_theta;
+    auto restore = [&]() {
+        h->p = saved;
+        h->k_accepted = acc;
+        h->judge_defl = jd;
+        if (!defl) {
+            h->nev = nev;
+            h->ritz_theta = theta;
+        }
+    };
     h->p.precond = use_k ? 1 : 0;
     h->k_accepted = use_k;
+    h->judge_defl = defl ? -1 : 0;
     h->p.tol = std::max(h->p.tol, target);
     Io io;
     io.B = b;
@@ -1002,13 +1022,11 @@ double k_judge_run(seedcg_s* h, bool use_k, const double* b, const double* x0, d
     try {
         st = solve_rest_impl(h, io, 1, &rep);
     } catch (...) {
-        h->p = saved;
-        h->k_accepted = acc;
+        restore();
         throw;
     }
     const double t = now_s() - t0;
-    h->p = saved;
-    h->k_accepted = acc;
+    restore();
     iters = it;
     return st == SEEDCG_OK ? t : 1e300;
 }
@@ -1163,7 +1181,14 @@ void train_precond_impl(seedcg_s* h, int steps, int n_ritz, int n_lanczos, doubl
         h->k_judge_r0 = nr2[1] > 0.0 ? nr2[0] / nr2[1] : 0.0;
     }
     const double target = h->p.tol;   // the whole solve: K may help early and lose late (near-zero modes)
-    int it_cg = 0, it_start = 0, it_trained = 0;
+    int it_cg = 0, it_start = 0, it_trained = 0, it_cg0 = 0;
+    // plain CG with the handle's deflation first (it builds the deflation space), then without it
+    h->judge_defl = -1;
+    const bool defl_cand = h->p.deflate > 0 && h->seed_nrhs - 1 <= 24;
+    const double t_cg = k_judge_run(h, false, bj.as<double>(), x0.as<double>(), xj.as<double>(), target, it_cg);
+    double t_cg0 = t_cg;
+    it_cg0 = it_cg;
+    if (defl_cand) t_cg0 = k_judge_run(h, false, bj.as<double>(), x0.as<double>(), xj.as<double>(), target, it_cg0, false);
     const bool moved = best_loss < h->k_loss0;   // otherwise the kept weights are the start's
     double t_trained = 0.0;
     if (moved) t_trained = k_judge_run(h, true, bj.as<double>(), x0.as<double>(), xj.as<double>(), target, it_trained);
@@ -1173,22 +1198,23 @@ void train_precond_impl(seedcg_s* h, int steps, int n_ritz, int n_lanczos, doubl
         t_trained = t_start;
         it_trained = it_start;
     }
-    const double t_cg = k_judge_run(h, false, bj.as<double>(), x0.as<double>(), xj.as<double>(), target, it_cg);
     // solve_rest iterates on all the seeded systems at once, where M's links are shared by every vector
     // and K's cost is not: the iteration counts above are priced with the time of one application of M
     // and of K K^dag to that many vectors
     const int nb = std::max(1, h->seed_nrhs - 1);
-    double t_m = 0.0, t_p = 0.0;
+    const bool defl_built = defl_cand && h->nev > 0;
+    double t_m = 0.0, t_p = 0.0, t_d = 0.0;
     {
         const bool lo = h->cg_lo;
         DBuf xa, ya;
         xa.ensure((int64_t)nb * h->vec_bytes(lo));
         ya.ensure((int64_t)nb * h->vec_bytes(lo));
         cfg_zero(xa.p, (int64_t)nb * h->vec_bytes(lo), h->L());
-        hipEvent_t e0, e1, e2;
+        hipEvent_t e0, e1, e2, e3;
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
         HIPCHK(hipEventCreate(&e2));
+        HIPCHK(hipEventCreate(&e3));
         const int saved = h->timing_every;
         h->timing_every = 0;
         apply_M_int(h, lo, xa.p, ya.p, nb, MOpts{});
@@ -1199,28 +1225,43 @@ void train_precond_impl(seedcg_s* h, int steps, int n_ritz, int n_lanczos, doubl
         HIPCHK(hipEventRecord(e1, h->s));
         for (int r = 0; r < reps; r++) apply_P(h, lo, xa.p, ya.p, nullptr, nb, nb);
         HIPCHK(hipEventRecord(e2, h->s));
-        HIPCHK(hipEventSynchronize(e2));
+        // one deflation of a CG iteration: (M W)^dag r on the matrix cores, then p -= W G^{-1} (M W)^dag r
+        if (defl_built)
+            for (int r = 0; r < reps; r++) deflate_step(h, false, xa.p, nb, nullptr, nb, ya.p, lo, false);
+        HIPCHK(hipEventRecord(e3, h->s));
+        HIPCHK(hipEventSynchronize(e3));
         h->timing_every = saved;
-        float m1 = 0.f, m2 = 0.f;
+        float m1 = 0.f, m2 = 0.f, m3 = 0.f;
         HIPCHK(hipEventElapsedTime(&m1, e0, e1));
         HIPCHK(hipEventElapsedTime(&m2, e1, e2));
+        HIPCHK(hipEventElapsedTime(&m3, e2, e3));
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         (void)hipEventDestroy(e2);
+        (void)hipEventDestroy(e3);
         t_m = 1e-3 * m1 / reps;
         t_p = 1e-3 * m2 / reps;
+        t_d = defl_built ? 1e-3 * m3 / reps : 0.0;
         h->kfield.release();
         h->pfa.release();
         h->pfb.release();
     }
-    const double c_cg = t_cg < 1e299 ? it_cg * t_m : 1e300;
-    const double c_start = t_start < 1e299 ? it_start * (t_m + t_p) : 1e300;
-    const double c_trained = t_trained < 1e299 ? it_trained * (t_m + t_p) : 1e300;
+    // per iteration on the seeded systems: M; K K^dag for PCG; the deflation where it is applied
+    const double c_cg = t_cg < 1e299 ? it_cg * (t_m + t_d) : 1e300;
+    const double c_cg0 = t_cg0 < 1e299 ? it_cg0 * t_m : 1e300;
+    const double c_start = t_start < 1e299 ? it_start * (t_m + t_p + t_d) : 1e300;
+    const double c_trained = t_trained < 1e299 ? it_trained * (t_m + t_p + t_d) : 1e300;
     h->k_judge = {t_cg, t_start, t_trained, (double)it_cg, (double)it_start, (double)it_trained, t_m, t_p, c_cg, c_start, c_trained};
+    h->k_judge_cg0_it = it_cg0;
+    h->k_judge_cg0_c = c_cg0;
+    h->k_judge_td = t_d;
     if (it_trained < it_start || (it_trained == it_start && t_trained <= t_start)) k_set_weights(h, wt.data());
     const double c_k = std::min(c_start, c_trained);
-    h->k_choice = c_k < c_cg ? (c_trained <= c_start ? 2 : 1) : 0;
+    const double c_plain = std::min(c_cg, c_cg0);
+    h->k_choice = c_k < c_plain ? (c_trained <= c_start ? 2 : 1) : 0;
     h->k_accepted = h->k_choice > 0;
+    // plain CG (the fallback) deflates only when that was cheaper; PCG always deflates when asked to
+    h->judge_defl = defl_cand ? (c_cg <= c_cg0 ? 1 : 0) : -1;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1369,7 +1410,7 @@ void build_deflation(seedcg_s* h, int want) {
 // init: X += W G^{-1} W^dag R (all nrhs vectors);  otherwise: X -= W G^{-1} Z^dag R for the vectors
 // of map (w entries) whose CG record is running.  R in the working precision.
 void deflate_step(seedcg_s* h, bool init, const void* R, int nrhs, const int32_t* map, int w, void* X, bool x32,
-                  bool use_cg = true) {
+                  bool use_cg) {
     const bool lo = h->cg_lo;   // W, M W and the CG vectors share the CG's precision
     project(lo, defl_proj_args(h, init ? h->dW.p : h->dZ.p, h->nev, R, nrhs), 1, h->dP.as<double>(), h->L(), true);
     defl_mu(h->dGinv.as<double>(), h->dP.as<double>(), h->nev, nrhs, map, w, (init || !use_cg) ? nullptr : h->cgv.as<CgVec>(),
@@ -1404,7 +1445,7 @@ void cg_iteration(seedcg_s* h, bool lo, bool pc, int nact, int nalloc, int64_t n
         apply_M_int(h, lo, h->Pv.p, h->Qv.p, nact, o);
         cg_beta(h->cgv.as<CgVec>(), h->rrpart.as<double>(), nsbl, h->vmap.as<int32_t>(), nact, max_iter, L);
         cg_p(lo, h->cgv.as<CgVec>(), h->vmap.as<int32_t>(), nact, h->Pv.p, Rw, h->N, false, L);
-        if (h->nev) deflate_step(h, false, Rw, nalloc, h->vmap.as<int32_t>(), nact, h->Pv.p, lo);
+        if (h->nev) deflate_step(h, false, Rw, nalloc, h->vmap.as<int32_t>(), nact, h->Pv.p, lo, true);
         return;
     }
     MOpts o;
@@ -1423,11 +1464,11 @@ void cg_iteration(seedcg_s* h, bool lo, bool pc, int nact, int nalloc, int64_t n
         cg_beta_pc(h->cgv.as<CgVec>(), h->rrpart.as<double>(), h->rzpart.as<double>(), nb, h->vmap.as<int32_t>(), nact, max_iter, L);
         cg_p(lo, h->cgv.as<CgVec>(), h->vmap.as<int32_t>(), nact, h->Pv.p, h->Zv.p, h->N, false, L);
         // deflated PCG: p = z + b p - W G^{-1} (M W)^dag z
-        if (h->nev) deflate_step(h, false, h->Zv.p, nalloc, h->vmap.as<int32_t>(), nact, h->Pv.p, lo);
+        if (h->nev) deflate_step(h, false, h->Zv.p, nalloc, h->vmap.as<int32_t>(), nact, h->Pv.p, lo, true);
     } else {
         cg_beta(h->cgv.as<CgVec>(), h->rrpart.as<double>(), nb, h->vmap.as<int32_t>(), nact, max_iter, L);
         cg_p(lo, h->cgv.as<CgVec>(), h->vmap.as<int32_t>(), nact, h->Pv.p, Rw, h->N, false, L);
-        if (h->nev) deflate_step(h, false, Rw, nalloc, h->vmap.as<int32_t>(), nact, h->Pv.p, lo);
+        if (h->nev) deflate_step(h, false, Rw, nalloc, h->vmap.as<int32_t>(), nact, h->Pv.p, lo, true);
     }
 }
 
@@ -1477,8 +1518,10 @@ seedcg_status solve_rest_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report
     alloc_rest(h, nrhs);
     const int64_t nb = norm2_blocks(N);
     void* Rw = lo ? h->Rv.p : h->R64.p;  // the recursive residual
-    // deflated CG from the Ritz vectors of the last seed solve (one configuration, no learned P)
-    const bool want_defl = h->p.deflate > 0 && C == 1 && h->have_seed;
+    // deflated CG from the Ritz vectors of the last seed solve (one configuration); plain CG skips it
+    // when the judge of train_precond found it does not pay
+    const bool pc_on = h->p.precond && h->k_accepted;
+    const bool want_defl = h->p.deflate > 0 && C == 1 && h->have_seed && (pc_on || h->judge_defl != 0);
     // the deflation projections contract all right-hand sides at once (at most 24 columns)
     if (want_defl && nrhs > 24) throw ArgError{"solve_rest: deflated CG takes at most 24 right-hand sides"};
     if (!want_defl)
@@ -1512,7 +1555,7 @@ seedcg_status solve_rest_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report
     if (h->nev) {
         // the deflated start x += W G^{-1} W^dag r, then the true residuals again
         if (lo) convert(false, true, h->R64.p, h->Rv.p, nrhs * N, L);
-        deflate_step(h, true, Rw, nrhs, nullptr, nrhs, h->Xint.p, false);
+        deflate_step(h, true, Rw, nrhs, nullptr, nrhs, h->Xint.p, false, true);
         np = true_residual(h, all, h->R64.p, h->cgpart.as<double>());
         sum_partials(h->cgpart.as<double>(), np, nrhs, h->norms.as<double>() + nrhs, false, L);
         from_cfg(h, hn.data(), h->norms.p, 2 * nrhs * sizeof(double));
@@ -1692,7 +1735,7 @@ seedcg_status solve_rest_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report
         to_cfg(h, h->cgv.p, cg.data(), nrhs * sizeof(CgVec));
         const int wr = upload_map(h, h->rmap, restart);
         if (wr) cg_p(lo, h->cgv.as<CgVec>(), h->rmap.as<int32_t>(), wr, h->Pv.p, pc ? h->Zv.p : Rw, N, false, L);
-        if (wr && h->nev) deflate_step(h, false, pc ? h->Zv.p : Rw, nrhs, h->rmap.as<int32_t>(), wr, h->Pv.p, lo);
+        if (wr && h->nev) deflate_step(h, false, pc ? h->Zv.p : Rw, nrhs, h->rmap.as<int32_t>(), wr, h->Pv.p, lo, true);
     }
     unpack_out(h, io, h->Xint.p, nrhs);
     // final FP64 true residuals for the report
@@ -1743,10 +1786,13 @@ void init_geometry(seedcg_s* h, const seedcg_params* p, const int32_t* dims) {
     if (h->tps_lo < 1 || h->tps_lo > 11) h->tps_lo = 8;
     h->vb64 = std::max(1, env_int("SEEDCG_VB", 1));
     h->vb_lo = std::max(1, env_int("SEEDCG_VB_LO", 1));
-    h->tps64_multi = h->tps64;
-    h->tps_lo_multi = h->tps_lo;
-    h->vb64_multi = h->vb64;
-    h->vb_lo_multi = h->vb_lo;
+    // the several-vector launches take the same shape unless the environment names one of their own
+    h->tps64_multi = env_int("SEEDCG_TPS_MULTI", h->tps64);
+    h->tps_lo_multi = env_int("SEEDCG_TPS_LO_MULTI", h->tps_lo);
+    if (h->tps64_multi < 1 || h->tps64_multi > 11) h->tps64_multi = h->tps64;
+    if (h->tps_lo_multi < 1 || h->tps_lo_multi > 11) h->tps_lo_multi = h->tps_lo;
+    h->vb64_multi = std::max(1, env_int("SEEDCG_VB_MULTI", h->vb64));
+    h->vb_lo_multi = std::max(1, env_int("SEEDCG_VB_LO_MULTI", h->vb_lo));
     h->sync_every = std::max(1, env_int("SEEDCG_SYNC_EVERY", 16));
     h->debug = env_int("SEEDCG_DEBUG", 0);
     h->use_graphs = env_int("SEEDCG_GRAPHS", 1) != 0;
@@ -1787,7 +1833,10 @@ void choose_link_formats(seedcg_s* h, bool special_unitary) {
 }
 
 bool env_shape_fixed() {
-    return getenv("SEEDCG_TPS") || getenv("SEEDCG_TPS_LO") || getenv("SEEDCG_VB") || getenv("SEEDCG_VB_LO");
+    for (const char* k : {"SEEDCG_TPS", "SEEDCG_TPS_LO", "SEEDCG_VB", "SEEDCG_VB_LO", "SEEDCG_TPS_MULTI", "SEEDCG_TPS_LO_MULTI",
+                          "SEEDCG_VB_MULTI", "SEEDCG_VB_LO_MULTI"})
+        if (getenv(k)) return true;
+    return false;
 }
 
 // Process-wide cache of tuned launch shapes: (Lx, Ly, Lz, Lt, precision, configurations, nvec).
@@ -3149,6 +3198,10 @@ seedcg_status seedcg_train_precond(seedcg_t h, int32_t steps, int32_t n_ritz, in
             for (int q = 0; q < 6; q++) out[6 + q] = h->k_judge[q];
             out[12] = h->k_choice;
             for (int q = 0; q < 5; q++) out[13 + q] = h->k_judge[6 + q];
+            out[18] = h->k_judge_cg0_it;
+            out[19] = h->k_judge_cg0_c;
+            out[20] = h->k_judge_td;
+            out[21] = h->judge_defl == 0 ? 0.0 : 1.0;
         }
         return SEEDCG_OK;
     });

@@ -326,13 +326,15 @@ class SeedCG:
 
     # -- learned preconditioner P = K K^dag -------------------------------------------------------
     def train_precond(self, steps=2000, n_ritz=4, n_lanczos=12, lr=2e-4):
-        out = (ctypes.c_double * 18)()
+        out = (ctypes.c_double * 22)()
         self._rc(self._lib.seedcg_train_precond(self._h, int(steps), int(n_ritz), int(n_lanczos), float(lr), out))
         return dict(loss0=out[0], loss1=out[1], t_train_s=out[2], n_ritz=int(out[3]), n_train=int(out[4]),
                     accepted=bool(out[5]), judge_s=dict(cg=out[6], start=out[7], trained=out[8]),
-                    judge_iters=dict(cg=int(out[9]), start=int(out[10]), trained=int(out[11])),
+                    judge_iters=dict(cg=int(out[9]), start=int(out[10]), trained=int(out[11]), cg_no_deflation=int(out[18])),
                     choice=["plain_cg", "start_K", "trained_K"][int(out[12])],
-                    batch_s=dict(M=out[13], P=out[14]), predicted_s=dict(cg=out[15], start=out[16], trained=out[17]))
+                    batch_s=dict(M=out[13], P=out[14], deflation=out[20]),
+                    predicted_s=dict(cg=out[15], start=out[16], trained=out[17], cg_no_deflation=out[19]),
+                    plain_cg_deflates=bool(out[21]))
 
     def use_precond(self, on=True):
         self._rc(self._lib.seedcg_use_precond(self._h, int(bool(on))))

@@ -90,6 +90,13 @@ typedef struct {
                                  at most 24 right-hand sides per solve_rest.  After train_precond
                                  plain CG deflates only if its judge found that cheaper            */
     void* stream;             /* hipStream_t; NULL = the null stream                             */
+    int32_t basis_fp32;       /* FP64 and MIXED_FP32_CG: 1 stores the Krylov basis in FP32 while the
+                                 Lanczos recurrence, its coefficients and the LU of T stay FP64: each
+                                 finished v_i is rounded into its basis slot, the seeding and
+                                 reorthogonalisation projections contract the FP32 basis on the FP64
+                                 matrix cores, and the updates subtract the widened FP32 vectors from
+                                 the FP64 v_i and f.  Half the basis traffic and twice the capacity.
+                                 Single configurations only (create_batch refuses it).           */
 } seedcg_params;
 
 typedef struct {

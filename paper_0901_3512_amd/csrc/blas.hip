@@ -561,8 +561,9 @@ __device__ inline bool reorth_gate(int i, int pass, const LzState* st, bool& use
 }
 
 // v' = v - V_{1..i-1} c, f' = f - V_{1..i-1} d with c = G[:,0], d = G[:,1]; partials |v'|^2, v'^dag f'.
-template <typename T>
-__global__ __launch_bounds__(SCG_BLOCK) void reorth_update_kernel(int i, int pass, const LzState* st, const cx<T>* __restrict__ V,
+// TV: the stored basis (FP32 or FP64); T: v and f (FP32 only with an FP32 basis).
+template <typename TV, typename T>
+__global__ __launch_bounds__(SCG_BLOCK) void reorth_update_kernel(int i, int pass, const LzState* st, const cx<TV>* __restrict__ V,
                                                                    int64_t n, const cx<double>* __restrict__ G,
                                                                    cx<T>* __restrict__ v, cx<T>* __restrict__ f,
                                                                    double* part, int64_t cs) {
@@ -593,10 +594,10 @@ __global__ __launch_bounds__(SCG_BLOCK) void reorth_update_kernel(int i, int pas
         }
         __syncthreads();
         if (act) {
-            const cx<T>* Vp = V + (int64_t)r0 * n + k;
+            const cx<TV>* Vp = V + (int64_t)r0 * n + k;
 #pragma unroll 8
             for (int q = 0; q < nr; q++) {
-                const cx<T> b = Vp[(int64_t)q * n];
+                const cx<TV> b = Vp[(int64_t)q * n];
                 const cx<double> c = cd[2 * q], d = cd[2 * q + 1];
                 const double br = b.re, bi = b.im;
                 vr -= br * c.re - bi * c.im;
@@ -628,13 +629,16 @@ __global__ __launch_bounds__(SCG_BLOCK) void reorth_update_kernel(int i, int pas
     }
 }
 void reorth_update(bool fp32, int i, int pass, const LzState* st, const void* V, int64_t n, const double* G, void* v, void* f,
-                   double* part, const Launch& L) {
+                   double* part, const Launch& L, bool v32) {
     const dim3 grid((unsigned)((n + SCG_BLOCK - 1) / SCG_BLOCK), 1, L.nz);
     if (fp32)
-        hipLaunchKernelGGL(reorth_update_kernel<float>, grid, dim3(SCG_BLOCK), 0, L.s, i, pass, st, (const cx<float>*)V, n,
+        hipLaunchKernelGGL((reorth_update_kernel<float, float>), grid, dim3(SCG_BLOCK), 0, L.s, i, pass, st, (const cx<float>*)V, n,
                            (const cx<double>*)G, (cx<float>*)v, (cx<float>*)f, part, L.cs);
+    else if (v32)
+        hipLaunchKernelGGL((reorth_update_kernel<float, double>), grid, dim3(SCG_BLOCK), 0, L.s, i, pass, st, (const cx<float>*)V, n,
+                           (const cx<double>*)G, (cx<double>*)v, (cx<double>*)f, part, L.cs);
     else
-        hipLaunchKernelGGL(reorth_update_kernel<double>, grid, dim3(SCG_BLOCK), 0, L.s, i, pass, st, (const cx<double>*)V, n,
+        hipLaunchKernelGGL((reorth_update_kernel<double, double>), grid, dim3(SCG_BLOCK), 0, L.s, i, pass, st, (const cx<double>*)V, n,
                            (const cx<double>*)G, (cx<double>*)v, (cx<double>*)f, part, L.cs);
 }
 

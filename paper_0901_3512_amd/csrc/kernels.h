@@ -74,8 +74,9 @@ void seed_eta(int i0, int nb, int nr, const LzState* st, const double* gam, cons
 void seed_update(bool w32, bool x32, const void* W, int nw, const double* E, void* X, int nx, int64_t n, const int32_t* nrow_dev,
                  const Launch& L);
 
+// v32: the basis V is stored in FP32 while v and f are FP64 (fp32 false)
 void reorth_update(bool fp32, int i, int pass, const LzState* st, const void* V, int64_t n, const double* G, void* v, void* f,
-                   double* part, const Launch& L);
+                   double* part, const Launch& L, bool v32 = false);
 void reorth_scalar(int i, int pass, LzState* st, const double* part, int64_t nb, const double* G, const Launch& L);
 void reorth_finish(bool fp32, int i, int pass, const LzState* st, void* v, void* f, double* f2part, int64_t n, const Launch& L);
 void reorth_decide(int i, int pass, LzState* st, const double* f2b, const double* f2a, int64_t nb, const Launch& L);

@@ -129,6 +129,7 @@ struct seedcg_s {
     int device = 0;
     std::string err;
     bool lo = false;        // FP32 Lanczos basis and seeding (mixed precision)
+    bool blo = false;       // the stored basis in FP32 (lo, or FP64 Lanczos with an FP32 copy of each vector)
     bool cg_lo = false;     // FP32 CG with FP64 reliable updates (every mixed mode; lo implies it)
     Prec lo_prec = P64;     // precision of the inner stencil
     int64_t N = 0;          // complex per vector
@@ -176,6 +177,7 @@ struct seedcg_s {
     bool k_ready = false;
     bool k_accepted = false;   // K won the judge against plain CG (solve_rest applies it when asked)
     DBuf kW32, kWm, kG, kAm, kAv, kpart, klinks32, kU, kY, kun2, klpart, kS, kfield, pfa, pfb, Zv, rzpart;
+    DBuf vring, vt32;   // FP64 Lanczos ring and FP32 projection operands (FP32 copy of an FP64 basis)
     // deflated CG: W (the lowest Ritz vectors of T lifted by V), Z = M W, (W^dag M W)^{-1},
     // coefficient blocks, Ritz coefficients
     DBuf dW, dZ, dGinv, dP, dE, dS;
@@ -467,13 +469,18 @@ int64_t reorth_kchunk(int64_t n, int i) {
 }
 
 void alloc_seed(seedcg_s* h, int nrhs) {
-    const bool lo = h->lo;
+    const bool lo = h->lo, blo = h->blo;
     const int64_t N = h->N;
     const int b = seed_block_of(h);
     h->wring.ensure(b * h->vec_bytes(lo));
     h->f.ensure(h->vec_bytes(lo));
     h->x1.ensure(h->vec_bytes(false));
-    h->R0.ensure(std::max(1, nrhs - 1) * h->vec_bytes(lo));
+    // the right-hand sides' residuals are projected against the basis in its stored precision
+    h->R0.ensure(std::max(1, nrhs - 1) * h->vec_bytes(blo));
+    if (blo && !lo) {
+        h->vring.ensure(2 * h->vec_bytes(false));   // v_{i-1}, v_i of the FP64 recurrence
+        h->vt32.ensure(2 * h->vec_bytes(true));     // [v_i, f] rounded for the reorthogonalisation projection
+    }
     h->Bint.ensure(nrhs * h->vec_bytes(false));
     h->Xint.ensure(nrhs * h->vec_bytes(false));
     h->st.ensure(sizeof(LzState));
@@ -498,12 +505,12 @@ void alloc_seed(seedcg_s* h, int nrhs) {
         HIPCHK(hipMemGetInfo(&freeb, &total));
         const int64_t reserve = 4LL << 30;
         const int64_t avail = (int64_t)freeb - reserve + (int64_t)h->basis.bytes;
-        cap = std::max<int64_t>(0, (int64_t)(0.75 * (double)avail) / h->vec_bytes(lo));
+        cap = std::max<int64_t>(0, (int64_t)(0.75 * (double)avail) / h->vec_bytes(blo));
         cap = std::min<int64_t>(cap, 8192);
         if (cap < 2) throw OomError{"no room for a Krylov basis"};
     }
     h->m_cap = (int32_t)cap;
-    h->basis.ensure((size_t)cap * h->vec_bytes(lo));
+    h->basis.ensure((size_t)cap * h->vec_bytes(blo));
     h->arrays.ensure(6 * ((int64_t)cap + 2) * sizeof(double));
     h->G.ensure(2 * 2 * ((int64_t)cap + 1) * sizeof(double));
     int64_t part_doubles = proj_chunks(N, kchunk_for(N, 1024)) * 2 * 32 * 24;
@@ -514,14 +521,14 @@ void alloc_seed(seedcg_s* h, int nrhs) {
 
 void flush_seed_block(seedcg_s* h, int i0, int i1, int nrhs) {
     if (nrhs <= 1 || i1 < i0) return;
-    const bool lo = h->lo;
+    const bool lo = h->lo, blo = h->blo;
     const int64_t N = h->N;
     const int nb = i1 - i0 + 1, nr = nrhs - 1;
     ProjArgs a{};
-    a.V = (const char*)h->basis.p + (int64_t)(i0 - 1) * h->vec_bytes(lo);
+    a.V = (const char*)h->basis.p + (int64_t)(i0 - 1) * h->vec_bytes(blo);
     a.ldv = N;
     a.nv = nb;
-    for (int j = 0; j < nr; j++) a.R[j] = (const char*)h->R0.p + (int64_t)j * h->vec_bytes(lo);
+    for (int j = 0; j < nr; j++) a.R[j] = (const char*)h->R0.p + (int64_t)j * h->vec_bytes(blo);
     a.nr = nr;
     a.n = N;
     a.kchunk = kchunk_for(N, 1024);
@@ -531,26 +538,36 @@ void flush_seed_block(seedcg_s* h, int i0, int i1, int nrhs) {
     a.gate_i = i0;
     a.rows_from_m = 1;
     a.i0 = i0;
-    project(lo, a, 1, h->P.as<double>(), h->L());
+    // an FP32 copy of an FP64 Lanczos basis is contracted on the FP64 matrix cores
+    project(blo, a, 1, h->P.as<double>(), h->L(), blo && !lo);
     seed_eta(i0, nb, nr, h->st.as<LzState>(), h->arr().gam, h->P.as<double>(), h->E.as<double>(), h->etaprev.as<double>(),
              h->nvalid.as<int32_t>(), h->L());
     seed_update(lo, false, h->wring.p, nb, h->E.as<double>(), (char*)h->Xint.p + h->vec_bytes(false), nr, N,
                 h->nvalid.as<int32_t>(), h->L());
 }
 
-void reorthogonalise(seedcg_s* h, int i) {
-    const bool lo = h->lo;
+// vi: v_i as the recurrence holds it (the basis slot, or the FP64 ring with an FP32 basis copy)
+void reorthogonalise(seedcg_s* h, int i, void* vi) {
+    const bool lo = h->lo, blo = h->blo;
+    const bool split = blo && !lo;   // FP64 v_i and f against the FP32 stored basis
     const int64_t N = h->N;
     LzState* st = h->st.as<LzState>();
-    void* vi = (char*)h->basis.p + (int64_t)(i - 1) * h->vec_bytes(lo);
     const int64_t nb = norm2_blocks(N);
+    void* vt = h->vt32.p;
+    void* ft = split ? (char*)h->vt32.p + h->vec_bytes(true) : nullptr;
     for (int pass = 1; pass <= 2; pass++) {
+        if (split) {
+            // the projection takes [v_i, f] rounded to the basis' FP32 (its rounding errors are
+            // incoherent with the basis: their inner products with it are O(eps / sqrt(N)))
+            convert(false, true, vi, vt, N, h->L());
+            convert(false, true, h->f.p, ft, N, h->L());
+        }
         ProjArgs a{};
         a.V = h->basis.p;
         a.ldv = N;
         a.nv = i;
-        a.R[0] = vi;
-        a.R[1] = h->f.p;
+        a.R[0] = split ? vt : vi;
+        a.R[1] = split ? ft : h->f.p;
         a.nr = 2;
         a.n = N;
         a.kchunk = reorth_kchunk(N, i);
@@ -560,8 +577,8 @@ void reorthogonalise(seedcg_s* h, int i) {
         a.gate_i = i;
         a.flag = pass == 2 ? &st->rep_any : nullptr;
         // the reorthogonalisation coefficients are always accumulated in FP64
-        project(lo, a, (i + 31) / 32, h->G.as<double>(), h->L(), true);
-        reorth_update(lo, i, pass, st, h->basis.p, N, h->G.as<double>(), vi, h->f.p, h->rpart.as<double>(), h->L());
+        project(blo, a, (i + 31) / 32, h->G.as<double>(), h->L(), true);
+        reorth_update(lo, i, pass, st, h->basis.p, N, h->G.as<double>(), vi, h->f.p, h->rpart.as<double>(), h->L(), blo);
         reorth_scalar(i, pass, st, h->rpart.as<double>(), nb, h->G.as<double>(), h->L());
         reorth_finish(lo, i, pass, st, vi, h->f.p, h->f2b.as<double>(), N, h->L());
         reorth_decide(i, pass, st, h->f2a.as<double>(), h->f2b.as<double>(), nb, h->L());
@@ -628,7 +645,7 @@ void solve_seed_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report* rep) {
                 throw ArgError{"solve_seed: right-hand side or starting guess " + std::to_string(q % nrhs) +
                                " holds a non-finite value"};
     }
-    if (nr > 0) convert(false, lo, (char*)h->r64.p + h->vec_bytes(false), h->R0.p, nr * N, L);
+    if (nr > 0) convert(false, h->blo, (char*)h->r64.p + h->vec_bytes(false), h->R0.p, nr * N, L);
     copy_cfg(h, h->x1.p, h->Xint.p, h->vec_bytes(false));
     zero_cfg(h, h->etaprev.p, 2 * 24 * sizeof(double));
     zero_cfg(h, h->arrays.p, 6 * ((int64_t)h->m_cap + 2) * sizeof(double));
@@ -647,11 +664,23 @@ void solve_seed_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report* rep) {
     norm2_partials(false, h->r64.p, N, 1, h->f2a.as<double>(), L);
     norm2_partials(false, h->Bint.p, N, 1, h->f2a.as<double>() + nb, L);
     lz_start(st, h->f2a.as<double>(), nb, h->f2a.as<double>() + nb, A.beta, L);
+    // with an FP32 copy of an FP64 basis, v_{i-1} and v_i live in a two-vector FP64 ring and every
+    // finished v_i is rounded into its basis slot
+    const bool split = h->blo && !lo;
+    auto vcur = [&](int j) -> void* {   // v_j as the recurrence reads it
+        return split ? (char*)h->vring.p + (int64_t)((j - 1) & 1) * h->vec_bytes(false)
+                     : (char*)h->basis.p + (int64_t)(j - 1) * h->vec_bytes(lo);
+    };
+    auto store = [&](int j) {   // round v_j into its slot of the FP32 basis
+        if (split && j <= h->m_cap)
+            convert(false, true, vcur(j), (char*)h->basis.p + (int64_t)(j - 1) * h->vec_bytes(true), N, L);
+    };
     if (lo) {
         convert(false, true, h->r64.p, h->f.p, N, L);
         lz_first_vector(true, st, h->f.p, h->basis.p, N, L);
     } else {
-        lz_first_vector(false, st, h->r64.p, h->basis.p, N, L);
+        lz_first_vector(false, st, h->r64.p, vcur(1), N, L);
+        store(1);
     }
     check_launch();
 
@@ -666,8 +695,8 @@ void solve_seed_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report* rep) {
     while (!finished) {
         const int i_end = std::min<int>(h->m_cap, i + h->sync_every - 1);
         for (; i <= i_end; i++) {
-            void* vi = (char*)h->basis.p + (int64_t)(i - 1) * h->vec_bytes(lo);
-            const void* vprev = i > 1 ? (const char*)h->basis.p + (int64_t)(i - 2) * h->vec_bytes(lo) : nullptr;
+            void* vi = vcur(i);
+            const void* vprev = i > 1 ? vcur(i - 1) : nullptr;
             // three-term recurrence: f = M v_i - beta_{i-1} v_{i-1}, alpha_i = v_i^dag f
             MOpts o;
             o.z = vprev;
@@ -693,10 +722,16 @@ void solve_seed_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report* rep) {
                 i0 = i + 1;
             }
             // periodic reorthogonalisation
-            if (reorth_now) reorthogonalise(h, i);
+            if (reorth_now) {
+                reorthogonalise(h, i, vi);
+                store(i);   // the reorthonormalised v_i replaces its rounded copy
+            }
             // beta_i and the next Lanczos vector
             lz_beta(i, st, reorth_now ? h->f2b.as<double>() : h->f2a.as<double>(), nb, A, L);
-            lz_next(lo, i, st, A.beta, h->f.p, (char*)h->basis.p + (int64_t)i * h->vec_bytes(lo), N, L);
+            if (i < h->m_cap) {
+                lz_next(lo, i, st, A.beta, h->f.p, vcur(i + 1), N, L);
+                store(i + 1);
+            }
         }
         check_launch();
         from_cfg(h, hs.data(), st, sizeof(LzState));
@@ -1063,11 +1098,11 @@ void train_precond_impl(seedcg_s* h, int steps, int n_ritz, int n_lanczos, doubl
     if (nr > 0) {
         h->kS.ensure(Sv.size() * sizeof(double));
         HIPCHK(hipMemcpyAsync(h->kS.p, Sv.data(), Sv.size() * sizeof(double), hipMemcpyHostToDevice, h->s));
-        k_combine(h->lo, h->basis.p, m, h->kS.as<double>(), nr, h->kU.p, N, h->s);
+        k_combine(h->blo, h->basis.p, m, h->kS.as<double>(), nr, h->kU.p, N, h->s);
     }
     for (int j = 0; j < nl; j++) {  // basis vectors (normalised CG residuals), evenly spread over 1..m
         const int i = nl == 1 ? 1 : 1 + (int)((int64_t)j * (m - 1) / (nl - 1));
-        convert(h->lo, true, (const char*)h->basis.p + (int64_t)(i - 1) * h->vec_bytes(h->lo), (char*)h->kU.p + (int64_t)(nr + j) * N * 8,
+        convert(h->blo, true, (const char*)h->basis.p + (int64_t)(i - 1) * h->vec_bytes(h->blo), (char*)h->kU.p + (int64_t)(nr + j) * N * 8,
                 N, h->s);
     }
     if (nr > 0 && nl > 0) {
@@ -1383,7 +1418,7 @@ void build_deflation(seedcg_s* h, int want) {
             for (int k = 0; k < nk; k++) S[(size_t)i * nk + k] = Sv[(size_t)i * nev + k0 + k];
         h->dS.ensure(S.size() * sizeof(double));
         HIPCHK(hipMemcpyAsync(h->dS.p, S.data(), S.size() * sizeof(double), hipMemcpyHostToDevice, h->s));
-        k_combine(h->lo, h->basis.p, m, h->dS.as<double>(), nk, (char*)h->dW.p + (int64_t)k0 * h->vec_bytes(lo), N, h->s, !lo);
+        k_combine(h->blo, h->basis.p, m, h->dS.as<double>(), nk, (char*)h->dW.p + (int64_t)k0 * h->vec_bytes(lo), N, h->s, !lo);
         HIPCHK(hipStreamSynchronize(h->s));  // dS is reused by the next pass
     }
     apply_M_int(h, lo, h->dW.p, h->dZ.p, nev, MOpts{});
@@ -1775,6 +1810,7 @@ void init_geometry(seedcg_s* h, const seedcg_params* p, const int32_t* dims) {
     g.t_bc = p->t_bc;
     h->N = 12 * g.Vh;
     h->lo = p->prec == SEEDCG_MIXED_FP32 || p->prec == SEEDCG_MIXED_FP32_BF16LINKS;
+    h->blo = h->lo || p->basis_fp32 != 0;
     h->cg_lo = p->prec != SEEDCG_FP64;
     h->lo_prec = p->prec == SEEDCG_MIXED_FP32_BF16LINKS ? P32BF : (h->cg_lo ? P32 : P64);
     // default stencil launch shape: 8 = forward and backward hops on separate wavefronts, one vector
@@ -2559,6 +2595,8 @@ seedcg_status seedcg_create_batch(int32_t ncfg, const int32_t* dims, const doubl
     if (!p || !dims || !kappa || !links || !out) return fail(nullptr, SEEDCG_ERR_ARG, "create_batch: null pointer");
     *out = nullptr;
     if (ncfg < 1) return fail(nullptr, SEEDCG_ERR_ARG, "create_batch: ncfg < 1");
+    if (p->basis_fp32 && (p->prec == SEEDCG_FP64 || p->prec == SEEDCG_MIXED_FP32_CG))
+        return fail(nullptr, SEEDCG_ERR_ARG, "create_batch: an FP32 copy of an FP64 basis is for single configurations");
     if (nrhs < 1 || nrhs > 25) return fail(nullptr, SEEDCG_ERR_ARG, "create_batch: nrhs must be 1..25");
     for (int c = 0; c < ncfg; c++) {
         for (int d = 0; d < 4; d++)
@@ -2992,8 +3030,8 @@ seedcg_status seedcg_get_basis_vector(seedcg_t h, int32_t i, double* v) {
     return guarded(h, [&]() -> seedcg_status {
         if (!h->have_seed || !h->basis.p) throw StateError{"get_basis_vector: no basis"};
         if (i < 1 || i > h->m_used || !v) throw ArgError{"get_basis_vector: index out of range or null pointer"};
-        const void* src = (const char*)h->basis.p + (int64_t)(i - 1) * h->vec_bytes(h->lo);
-        unpack_vec(h->lo, src, v, h->g.Vh, 1, h->s);
+        const void* src = (const char*)h->basis.p + (int64_t)(i - 1) * h->vec_bytes(h->blo);
+        unpack_vec(h->blo, src, v, h->g.Vh, 1, h->s);
         check_launch();
         HIPCHK(hipStreamSynchronize(h->s));
         return SEEDCG_OK;
@@ -3290,6 +3328,8 @@ seedcg_status seedcg_release_basis(seedcg_t h) {
         h->basis.release();
         h->wring.release();
         h->projpart.release();
+        h->vring.release();
+        h->vt32.release();
         return SEEDCG_OK;
     });
 }

@@ -25,7 +25,8 @@ class Params(ctypes.Structure):
                 ("prec", ctypes.c_int32), ("m_max", ctypes.c_int32), ("reorth_k", ctypes.c_int32),
                 ("past_factor", ctypes.c_double), ("tol", ctypes.c_double), ("reliable_every", ctypes.c_int32),
                 ("seed_block", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("precond", ctypes.c_int32),
-                ("autotune", ctypes.c_int32), ("deflate", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("autotune", ctypes.c_int32), ("deflate", ctypes.c_int32), ("stream", ctypes.c_void_p),
+                ("basis_fp32", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -131,7 +132,8 @@ class SeedCG:
     """One gauge configuration: M = A^dag A with A = 1 - kappa^2 H_eo H_oe (see include/seedcg.h)."""
 
     def __init__(self, links, dims, kappa, *, t_bc=-1, prec="fp64", m_max=0, reorth_k=10, past=1.5,
-                 tol=1e-10, reliable_every=50, seed_block=32, max_iter=100000, autotune=True, deflate=0, stream=None):
+                 tol=1e-10, reliable_every=50, seed_block=32, max_iter=100000, autotune=True, deflate=0, basis_fp32=False,
+                 stream=None):
         lib = load_library()
         self.dims = tuple(int(d) for d in dims)
         self.V = self.dims[0] * self.dims[1] * self.dims[2] * self.dims[3]
@@ -157,6 +159,7 @@ class SeedCG:
         p.max_iter = int(max_iter)
         p.autotune = int(bool(autotune))
         p.deflate = int(deflate)
+        p.basis_fp32 = int(bool(basis_fp32))
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream

@@ -201,3 +201,50 @@ def test_mixed_cg_mode_keeps_the_seeding_gain():
     assert np.all(res <= 1e-10), res
     err = np.linalg.norm(flat(host(X)) - xs, axis=1) / np.linalg.norm(xs, axis=1)
     assert np.all(err <= 2.3e4 * 1e-10), err
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_cg"])
+def test_fp32_basis_copy_of_fp64_lanczos(t8, prec):
+    """basis_fp32: the FP64 Lanczos recurrence with each finished v_i rounded into an FP32 basis, the
+    projections contracting that basis on the FP64 matrix cores (8^4, k = 10).  Against the oracle:
+    m and i_conv within one step, the first 20 Lanczos coefficients to 1e-8 relative (the FP32 copy
+    enters T only through the reorthogonalisation coefficients, whose rounding errors are incoherent
+    with the basis), the seeded guesses to 1e-6; the stored vectors are the FP32 roundings of an
+    orthonormal set (|V^dag V - 1| <= 1e-6); every solution within 1e-8 of the FP64 solution and at
+    an FP64 true residual <= 1e-10."""
+    from paper_0901_3512_amd import SeedCG
+    print_case("fp32 basis copy", prec)
+    ref = t8["ref"]
+    s = SeedCG(cuda(t8["U"]), t8["dims"], t8["kappa"], prec=prec, reorth_k=10, basis_fp32=True)
+    X, rs = s.solve_seed(cuda(t8["B"]))
+    assert abs(rs["m"] - ref["m"]) <= 1 and abs(rs["i_conv"] - ref["i_conv"]) <= 1, (rs["m"], ref["m"])
+    a, b = s.get_tridiag()
+    n = min(20, len(a))
+    assert np.max(np.abs(np.array(a[:n]) - ref["alpha"][:n]) / np.abs(ref["alpha"][:n])) <= 1e-8
+    assert np.max(np.abs(np.array(b[:n]) - ref["beta"][:n]) / ref["beta"][:n]) <= 1e-8
+    rel = np.linalg.norm(flat(host(X)) - ref["X"], axis=1) / np.linalg.norm(ref["X"], axis=1)
+    assert np.max(rel[1:]) <= 1e-6, rel
+    V = np.stack([flat(host(s.get_basis_vector(i))) for i in range(1, rs["m"] + 1)])
+    assert np.all(V == V.astype(np.complex64).astype(np.complex128))   # FP32-representable entries
+    assert osc.orth_loss(V) <= 1e-6
+    X, rr = s.solve_rest(cuda(t8["B"]), X)
+    assert np.all(osc.true_relres(t8["mv"], flat(t8["B"]), flat(host(X))) <= 1e-10)
+    err = np.linalg.norm(flat(host(X)) - t8["xs"], axis=1) / np.linalg.norm(t8["xs"], axis=1)
+    assert np.max(err) <= 1e-8, err
+    print("fp32 basis copy", prec, "m", rs["m"], "iters", rr["iters"])
+
+
+def test_fp32_basis_copy_refused_for_batches():
+    from paper_0901_3512_amd import SeedCGError
+    from paper_0901_3512_amd.seedcg import Params, load_library
+    import ctypes
+    lib = load_library()
+    p = Params()
+    lib.seedcg_default_params(ctypes.byref(p))
+    p.basis_fp32 = 1
+    dims = (ctypes.c_int32 * 4)(4, 4, 4, 4)
+    kap = (ctypes.c_double * 1)(0.12)
+    links = (ctypes.c_void_p * 1)(None)
+    h = ctypes.c_void_p()
+    rc = lib.seedcg_create_batch(1, dims, kap, links, 3, ctypes.byref(p), ctypes.byref(h))
+    assert rc != 0 and not h.value

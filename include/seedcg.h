@@ -285,8 +285,10 @@ seedcg_status seedcg_time_M(seedcg_t h, int32_t inner, int32_t nvec, int32_t rep
    trained K on one system, their iterations in the same order, the choice (0 plain CG, 1 start K,
    2 trained K), the seconds of one M and of one K K^dag on the seeded systems, the predicted
    seconds of plain CG, the start K and the trained K there, then plain CG without deflation: its
-   iterations and predicted seconds, the seconds of one deflation step on the seeded systems, and
-   whether plain CG in solve_rest deflates (1) or not (0).  Each Adam step takes the loss on a band of
+   iterations and predicted seconds (that solve stops once it has run as many iterations as would
+   cost what the deflated one did, and its count is then a lower bound with seconds 1e300), the
+   seconds of one deflation step on the seeded systems, and whether plain CG in solve_rest deflates
+   (1) or not (0).  Each Adam step takes the loss on a band of
    two t-slices (seedcg_precond_loss_grad_band), the bands stepping through the lattice, with a step
    size that decays from lr to 0 on a half cosine; the whole-lattice loss, taken at four checkpoints,
    picks the trained weights (the start's when no checkpoint is lower, and the judge then runs the

@@ -1025,7 +1025,7 @@ void deflate_step(seedcg_s* h, bool init, const void* R, int nrhs, const int32_t
 // One judge solve of system b from x0 to target: PCG with the current K (use_k) or plain CG, with
 // plain CG's deflation off when defl is false (the built deflation is kept for the later solves).
 double k_judge_run(seedcg_s* h, bool use_k, const double* b, const double* x0, double* x, double target, int& iters,
-                   bool defl = true) {
+                   bool defl = true, int max_it = 0) {
     HIPCHK(hipMemcpyAsync(x, x0, h->vec_bytes(false), hipMemcpyDeviceToDevice, h->s));
     const seedcg_params saved = h->p;
     const bool acc = h->k_accepted;
@@ -1044,6 +1044,7 @@ double k_judge_run(seedcg_s* h, bool use_k, const double* b, const double* x0, d
     h->k_accepted = use_k;
     h->judge_defl = defl ? -1 : 0;
     h->p.tol = std::max(h->p.tol, target);
+    if (max_it > 0) h->p.max_iter = std::min(h->p.max_iter, max_it);
     Io io;
     io.B = b;
     io.X = x;
@@ -1217,25 +1218,13 @@ void train_precond_impl(seedcg_s* h, int steps, int n_ritz, int n_lanczos, doubl
     }
     const double target = h->p.tol;   // the whole solve: K may help early and lose late (near-zero modes)
     int it_cg = 0, it_start = 0, it_trained = 0, it_cg0 = 0;
-    // plain CG with the handle's deflation first (it builds the deflation space), then without it
+    // plain CG with the handle's deflation first (it builds the deflation space)
     h->judge_defl = -1;
     const bool defl_cand = h->p.deflate > 0 && h->seed_nrhs - 1 <= 24;
     const double t_cg = k_judge_run(h, false, bj.as<double>(), x0.as<double>(), xj.as<double>(), target, it_cg);
-    double t_cg0 = t_cg;
-    it_cg0 = it_cg;
-    if (defl_cand) t_cg0 = k_judge_run(h, false, bj.as<double>(), x0.as<double>(), xj.as<double>(), target, it_cg0, false);
-    const bool moved = best_loss < h->k_loss0;   // otherwise the kept weights are the start's
-    double t_trained = 0.0;
-    if (moved) t_trained = k_judge_run(h, true, bj.as<double>(), x0.as<double>(), xj.as<double>(), target, it_trained);
-    k_set_weights(h, w0.data());
-    const double t_start = k_judge_run(h, true, bj.as<double>(), x0.as<double>(), xj.as<double>(), target, it_start);
-    if (!moved) {
-        t_trained = t_start;
-        it_trained = it_start;
-    }
     // solve_rest iterates on all the seeded systems at once, where M's links are shared by every vector
-    // and K's cost is not: the iteration counts above are priced with the time of one application of M
-    // and of K K^dag to that many vectors
+    // and K's cost is not: the judge's iteration counts are priced with the time of one application of M,
+    // of K K^dag and of one deflation step to that many vectors
     const int nb = std::max(1, h->seed_nrhs - 1);
     const bool defl_built = defl_cand && h->nev > 0;
     double t_m = 0.0, t_p = 0.0, t_d = 0.0;
@@ -1280,6 +1269,24 @@ void train_precond_impl(seedcg_s* h, int steps, int n_ritz, int n_lanczos, doubl
         h->kfield.release();
         h->pfa.release();
         h->pfb.release();
+    }
+    // then plain CG without deflation, stopped once it has run the iterations that would cost as much
+    // as the deflated solve (it can no longer win; its count is then a lower bound)
+    double t_cg0 = t_cg;
+    it_cg0 = it_cg;
+    if (defl_cand) {
+        const double c_d = t_cg < 1e299 ? it_cg * (t_m + t_d) : 1e300;
+        const int cap = c_d < 1e299 && t_m > 0.0 ? (int)std::min(1e9, std::ceil(c_d / t_m)) + 1 : 0;
+        t_cg0 = k_judge_run(h, false, bj.as<double>(), x0.as<double>(), xj.as<double>(), target, it_cg0, false, cap);
+    }
+    const bool moved = best_loss < h->k_loss0;   // otherwise the kept weights are the start's
+    double t_trained = 0.0;
+    if (moved) t_trained = k_judge_run(h, true, bj.as<double>(), x0.as<double>(), xj.as<double>(), target, it_trained);
+    k_set_weights(h, w0.data());
+    const double t_start = k_judge_run(h, true, bj.as<double>(), x0.as<double>(), xj.as<double>(), target, it_start);
+    if (!moved) {
+        t_trained = t_start;
+        it_trained = it_start;
     }
     // per iteration on the seeded systems: M; K K^dag for PCG; the deflation where it is applied
     const double c_cg = t_cg < 1e299 ? it_cg * (t_m + t_d) : 1e300;

@@ -65,8 +65,10 @@ typedef struct {
     double kappa;             /* hopping parameter (Wilson r = 1)                                */
     int32_t t_bc;             /* -1: antiperiodic in t, +1: periodic                             */
     int32_t prec;             /* seedcg_prec                                                     */
-    int32_t m_max;            /* Krylov basis capacity (vectors); 0 = 3/4 of the free HBM less
-                                 4 GiB, at most 8192                                            */
+    int32_t m_max;            /* Krylov basis capacity (vectors); 0 = up to 3/4 of the free HBM
+                                 less 4 GiB, at most 8192, allocated as the run needs it (256
+                                 vectors first, then doubled at the host's checks; a batch
+                                 allocates it all)                                              */
     int32_t reorth_k;         /* periodic reorthogonalisation every k iterations; 0 = never      */
     double past_factor;       /* m = ceil(past_factor * i_conv) (Algorithm 1 run past convergence);
                                  <= 0 means m = m_max exactly (the paper's fixed m)             */

@@ -178,6 +178,10 @@ struct seedcg_s {
     bool k_accepted = false;   // K won the judge against plain CG (solve_rest applies it when asked)
     DBuf kW32, kWm, kG, kAm, kAv, kpart, klinks32, kU, kY, kun2, klpart, kS, kfield, pfa, pfb, Zv, rzpart;
     DBuf vring, vt32;   // FP64 Lanczos ring and FP32 projection operands (FP32 copy of an FP64 basis)
+    // With params.m_max = 0 (one configuration) the basis grows as the Lanczos run needs it, up to
+    // m_cap vectors: basis_phys vectors are allocated.
+    bool basis_grow = false;
+    int64_t basis_phys = 0;
     // deflated CG: W (the lowest Ritz vectors of T lifted by V), Z = M W, (W^dag M W)^{-1},
     // coefficient blocks, Ritz coefficients
     DBuf dW, dZ, dGinv, dP, dE, dS;
@@ -510,13 +514,46 @@ void alloc_seed(seedcg_s* h, int nrhs) {
         if (cap < 2) throw OomError{"no room for a Krylov basis"};
     }
     h->m_cap = (int32_t)cap;
-    h->basis.ensure((size_t)cap * h->vec_bytes(blo));
+    const int64_t vb = h->vec_bytes(blo);
+    h->basis_grow = h->p.m_max <= 0 && h->ncfg == 1 && !g_plan;
+    if (h->basis_grow) {
+        // the first 256 vectors now (SEEDCG_BASIS_FIRST), more at the host's checks as the run
+        // proceeds (grow_basis)
+        const int64_t first = std::min<int64_t>(cap, std::max(2, env_int("SEEDCG_BASIS_FIRST", 256)));
+        if ((int64_t)h->basis.bytes < first * vb) h->basis.ensure((size_t)first * vb);
+        h->basis_phys = (int64_t)h->basis.bytes / vb;
+    } else {
+        h->basis.ensure((size_t)cap * vb);
+        h->basis_phys = cap;
+    }
     h->arrays.ensure(6 * ((int64_t)cap + 2) * sizeof(double));
     h->G.ensure(2 * 2 * ((int64_t)cap + 1) * sizeof(double));
     int64_t part_doubles = proj_chunks(N, kchunk_for(N, 1024)) * 2 * 32 * 24;
     for (int64_t i = 1; i <= cap; i++)
         part_doubles = std::max<int64_t>(part_doubles, proj_chunks(N, reorth_kchunk(N, (int)i)) * 4 * i);
     h->projpart.ensure(part_doubles * sizeof(double));
+}
+
+// Makes room for basis slots 0..need-1 (need <= m_cap) at a host check, when no kernel is in flight:
+// a larger allocation (twice the current one, or need), the stored vectors copied over, the old one
+// freed.  Returns the vectors now allocated; if HBM cannot hold more, the allocation stays as it was
+// and the caller caps the run there.
+int64_t grow_basis(seedcg_s* h, int64_t need) {
+    if (!h->basis_grow || need <= h->basis_phys) return h->basis_phys;
+    const int64_t vb = h->vec_bytes(h->blo);
+    const int64_t to = std::min<int64_t>(h->m_cap, std::max<int64_t>(need, 2 * h->basis_phys));
+    void* np = nullptr;
+    if (hipMalloc(&np, (size_t)(to * vb)) != hipSuccess) {
+        (void)hipGetLastError();
+        return h->basis_phys;
+    }
+    HIPCHK(hipMemcpyAsync(np, h->basis.p, (size_t)(h->basis_phys * vb), hipMemcpyDeviceToDevice, h->s));
+    HIPCHK(hipStreamSynchronize(h->s));
+    (void)hipFree(h->basis.p);
+    h->basis.p = np;
+    h->basis.bytes = (size_t)(to * vb);
+    h->basis_phys = to;
+    return to;
 }
 
 void flush_seed_block(seedcg_s* h, int i0, int i1, int nrhs) {
@@ -693,7 +730,22 @@ void solve_seed_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report* rep) {
     int m_max = 0;       // largest m over the configurations
     bool finished = false;
     while (!finished) {
-        const int i_end = std::min<int>(h->m_cap, i + h->sync_every - 1);
+        int i_end = std::min<int>(h->m_cap, i + h->sync_every - 1);
+        if (h->basis_grow && i_end + 1 > h->basis_phys) {
+            // this chunk writes basis slots up to i_end (v_{i_end + 1}); the kernels of the last chunk
+            // have finished (the state was read back)
+            const int64_t have = grow_basis(h, std::min<int64_t>(h->m_cap, (int64_t)i_end + 1));
+            if (have < (int64_t)i_end + 1) {
+                // HBM is full: the run ends at the allocated capacity
+                h->m_cap = (int32_t)have;
+                for (auto& x : hs) {
+                    x.m_cap = h->m_cap;
+                    x.m = std::min(x.m, h->m_cap);
+                }
+                to_cfg(h, st, hs.data(), sizeof(LzState));
+                i_end = std::min<int>(h->m_cap, i + h->sync_every - 1);
+            }
+        }
         for (; i <= i_end; i++) {
             void* vi = vcur(i);
             const void* vprev = i > 1 ? vcur(i - 1) : nullptr;

@@ -254,3 +254,30 @@ def test_flux_background_seeding_matches_oracle():
     err = np.linalg.norm(flat(host(X)) - xs, axis=1) / np.linalg.norm(xs, axis=1)
     assert np.all(err <= 1e-8), err
     print("flux 4^4: m", rs["m"], "iters", rr["iters"], "oracle", it_ref)
+
+
+def test_basis_grows_as_the_run_needs_it(monkeypatch):
+    """params.m_max = 0: the basis starts small and grows at the host's checks (here from 8 vectors,
+    doubling), with the stored vectors copied over.  The run is bit for bit the one with the whole
+    capacity allocated up front, and the handle holds far less HBM than 3/4 of the free memory."""
+    import torch
+    print_case("growing basis")
+    U, dims, kappa, op, B = _setup("t4")
+    s0 = _solver(U, dims, kappa, reorth_k=10, m_max=400)
+    X0, r0 = s0.solve_seed(cuda(B))
+    a0, b0 = s0.get_tridiag()
+    s0.close()
+    monkeypatch.setenv("SEEDCG_BASIS_FIRST", "8")
+    free0, total = torch.cuda.mem_get_info()
+    s = _solver(U, dims, kappa, reorth_k=10)
+    X, r = s.solve_seed(cuda(B))
+    free1, _ = torch.cuda.mem_get_info()
+    assert r["m"] == r0["m"] and r["m"] > 32, (r["m"], r0["m"])
+    assert np.array_equal(host(X), host(X0))
+    a, b = s.get_tridiag()
+    assert np.array_equal(np.array(a), np.array(a0)) and np.array_equal(np.array(b), np.array(b0))
+    Vg = np.stack([flat(host(s.get_basis_vector(i))) for i in range(1, r["m"] + 1)])
+    assert osc.orth_loss(Vg) <= 1e-8
+    assert free0 - free1 < 0.05 * total, (free0 - free1, total)
+    X, rr = s.solve_rest(cuda(B), X)
+    assert np.all(osc.true_relres(matvec_M(op), flat(B), flat(host(X))) <= 1e-10)

@@ -26,6 +26,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "kernels.h"
 #include "seedcg.h"
 
@@ -108,6 +110,15 @@ struct DBuf {
     T* as() const {
         return (T*)p;
     }
+};
+
+// A named roctx range over the calling scope: the phases of a solve show up as ranges in a
+// rocprofv3 --marker-trace run (and cost a function call otherwise).
+struct Phase {
+    explicit Phase(const char* name) { roctxRangePushA(name); }
+    ~Phase() { roctxRangePop(); }
+    Phase(const Phase&) = delete;
+    Phase& operator=(const Phase&) = delete;
 };
 
 double now_s() {
@@ -1217,6 +1228,7 @@ void train_precond_impl(seedcg_s* h, int steps, int n_ritz, int n_lanczos, doubl
     std::vector<double> best = w0;
     double best_loss = h->k_loss0;
     for (int step = 0; step < steps; step++) {
+        const Phase adam_phase("seedcg_train_precond: Adam step");
         const int o = (int)(((int64_t)step * mb) % S);
         k_pass(h, o, std::min(mb, S - o), true, false, (int)(((int64_t)step * band) % h->g.L[3]), band);
         const double lr_t = lr * 0.5 * (1.0 + std::cos(M_PI * step / steps));
@@ -1268,6 +1280,7 @@ void train_precond_impl(seedcg_s* h, int steps, int n_ritz, int n_lanczos, doubl
         HIPCHK(hipStreamSynchronize(h->s));
         h->k_judge_r0 = nr2[1] > 0.0 ? nr2[0] / nr2[1] : 0.0;
     }
+    Phase judge_phase("seedcg_train_precond: judge");
     const double target = h->p.tol;   // the whole solve: K may help early and lose late (near-zero modes)
     int it_cg = 0, it_start = 0, it_trained = 0, it_cg0 = 0;
     // plain CG with the handle's deflation first (it builds the deflation space)
@@ -2770,6 +2783,7 @@ seedcg_status seedcg_create_batch(int32_t ncfg, const int32_t* dims, const doubl
 
 seedcg_status seedcg_solve_batch(seedcg_batch_t b, const double* const* B, double* const* X, seedcg_report* rep) {
     if (!b) return fail(nullptr, SEEDCG_ERR_ARG, "solve_batch: null batch");
+    Phase ph("seedcg_solve_batch");
     if (!B || !X) {
         b->err = "solve_batch: null pointer";
         return SEEDCG_ERR_ARG;
@@ -2966,6 +2980,7 @@ seedcg_status seedcg_apply_A(seedcg_t h, const double* x, double* y, int32_t nve
 
 seedcg_status seedcg_solve_seed(seedcg_t h, const double* B, double* X, int32_t nrhs, seedcg_report* r) {
     if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "solve_seed: null handle");
+    Phase ph("seedcg_solve_seed");
     return guarded(h, [&]() -> seedcg_status {
         if (!B || !X) throw ArgError{"solve_seed: null pointer"};
         Io io;
@@ -2978,6 +2993,7 @@ seedcg_status seedcg_solve_seed(seedcg_t h, const double* B, double* X, int32_t 
 
 seedcg_status seedcg_solve_rest(seedcg_t h, const double* B, double* X, int32_t nrhs, seedcg_report* r) {
     if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "solve_rest: null handle");
+    Phase ph("seedcg_solve_rest");
     return guarded(h, [&]() -> seedcg_status {
         if (!B || !X) throw ArgError{"solve_rest: null pointer"};
         Io io;
@@ -2991,6 +3007,7 @@ seedcg_status seedcg_solve_rest(seedcg_t h, const double* B, double* X, int32_t 
 
 seedcg_status seedcg_solve_repeated(seedcg_t h, const double* B, double* X, int32_t nrhs, seedcg_report* r) {
     if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "solve_repeated: null handle");
+    Phase ph("seedcg_solve_repeated");
     return guarded(h, [&]() -> seedcg_status {
         if (!B || !X || nrhs < 1) throw ArgError{"solve_repeated: null pointer or nrhs < 1"};
         if (nrhs > 25) throw ArgError{"solve_repeated: at most 25 right-hand sides"};
@@ -3046,6 +3063,7 @@ seedcg_status seedcg_solve_repeated(seedcg_t h, const double* B, double* X, int3
 
 seedcg_status seedcg_solve_indefinite(seedcg_t h, const double* Phi, double* X, int32_t nrhs, seedcg_report* r) {
     if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "solve_indefinite: null handle");
+    Phase ph("seedcg_solve_indefinite");
     return guarded(h, [&]() -> seedcg_status {
         if (!Phi || !X) throw ArgError{"solve_indefinite: null pointer"};
         if (!solve_indefinite_impl(h, Phi, X, nrhs, r)) {
@@ -3283,6 +3301,7 @@ seedcg_status seedcg_time_M(seedcg_t h, int32_t inner, int32_t nvec, int32_t rep
 
 seedcg_status seedcg_train_precond(seedcg_t h, int32_t steps, int32_t n_ritz, int32_t n_lanczos, double lr, double* out) {
     if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "train_precond: null handle");
+    Phase ph("seedcg_train_precond");
     return guarded(h, [&]() -> seedcg_status {
         train_precond_impl(h, steps, n_ritz, n_lanczos, lr);
         if (out) {

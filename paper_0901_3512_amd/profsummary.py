@@ -3,6 +3,7 @@
   python -m paper_0901_3512_amd.profsummary stats  <dir-with-kernel_stats.csv> [--top N]
   python -m paper_0901_3512_amd.profsummary bytes  <fetch-dir> <write-dir> --kernel hop_kernel
   python -m paper_0901_3512_amd.profsummary counters <dir-with-counter_collection.csv> --kernel proj_kernel
+  python -m paper_0901_3512_amd.profsummary markers  <dir-with-marker_api_stats.csv>
 
 `bytes` averages FETCH_SIZE and WRITE_SIZE (KiB per dispatch) over the dispatches of the named
 kernel between the copy probe and the next 1 GiB copy, and scales each by what the same counter
@@ -36,6 +37,18 @@ def stats(d, top):
         name = r["Name"].replace("void ", "")[:70]
         out.append(f"{name:70s} {int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:10.2f} "
                    f"{float(r['TotalDurationNs']) / 1e6:10.2f} {100 * float(r['TotalDurationNs']) / tot:6.1f}")
+    return "\n".join(out)
+
+
+def markers(d):
+    """The roctx ranges of a --marker-trace run: calls, average and total milliseconds per name."""
+    path = _one(os.path.join(d, "**", "*marker_api_stats.csv"))
+    rows = list(csv.DictReader(open(path)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = [f"{'range':50s} {'calls':>7s} {'avg_ms':>10s} {'total_ms':>10s}"]
+    for r in rows:
+        out.append(f"{r['Name'][:50]:50s} {int(r['Calls']):7d} {float(r['AverageNs']) / 1e6:10.3f} "
+                   f"{float(r['TotalDurationNs']) / 1e6:10.1f}")
     return "\n".join(out)
 
 
@@ -133,12 +146,16 @@ def main():
     b.add_argument("write_dir")
     b.add_argument("--kernel", default="hop_")
     b.add_argument("--source", default=os.path.join(os.path.dirname(__file__), "csrc", "dslash.hip"))
+    mk = sub.add_parser("markers")
+    mk.add_argument("dir")
     c = sub.add_parser("counters")
     c.add_argument("dir")
     c.add_argument("--kernel", default="proj_kernel")
     args = ap.parse_args()
     if args.cmd == "stats":
         print(stats(args.dir, args.top))
+    elif args.cmd == "markers":
+        print(markers(args.dir))
     elif args.cmd == "counters":
         print(counters(args.dir, args.kernel))
     else:

@@ -122,6 +122,46 @@ __device__ inline bool site_of_launch(const Geom& g, int pmask, Band b, int64_t 
 // sites for the hops
 __device__ inline bool vanishes(int zero_odd_input, int d, int p) { return zero_odd_input && ((d == 0) ? (p == 1) : (p == 0)); }
 
+// One term of a layer at output site (p, h): acc += (w_d (x) 1) (T_d in) for the NV vectors of vec.
+template <int NV>
+__device__ __attribute__((always_inline)) inline void k_layer_term(int d, const Geom& g, const cx<float>* __restrict__ links,
+                                                                   const cx<float>* __restrict__ in, const cx<float>* w,
+                                                                   const int (&vec)[NV], int zero_odd_input, Band in_band, int p,
+                                                                   int h, const Site& s, int Vh, cx<float> (&acc)[NV][12]) {
+    if (vanishes(zero_odd_input, d, p)) return;
+    // an input known to vanish outside its band of t-slices (a back-propagated gradient): skip the
+    // terms that would read it there
+    if (in_band.nt < g.L[3]) {
+        int tin = s.t;
+        if (d == 4) tin = s.t + 1 == g.L[3] ? 0 : s.t + 1;
+        if (d == 8) tin = s.t == 0 ? g.L[3] - 1 : s.t - 1;
+        const int dt = tin - in_band.t0 < 0 ? tin - in_band.t0 + g.L[3] : tin - in_band.t0;
+        if (dt >= in_band.nt) return;
+    }
+    Hop o;
+    if (d) load_hop(g, links, p, h, s, d, o);
+#pragma unroll
+    for (int j = 0; j < NV; j++) {
+        if (vec[j] < 0) continue;
+        const cx<float>* src = in + (int64_t)vec[j] * 24 * Vh;
+        cx<float> t[12];
+        if (d == 0) {
+#pragma unroll
+            for (int c = 0; c < 12; c++) t[c] = src[(int64_t)(p * 12 + c) * Vh + h];
+        } else {
+            apply_hop(o, src, p, Vh, t);
+        }
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+#pragma unroll
+            for (int b = 0; b < 4; b++) {
+                const cx<float> wab = w[d * 16 + a * 4 + b];
+#pragma unroll
+                for (int c = 0; c < 3; c++) acc[j][3 * a + c] = acc[j][3 * a + c] + cmul(wab, t[3 * b + c]);
+            }
+    }
+}
+
 // out = L in (dagger = 0) or L^dag in (dagger = 1) on the output parities of pmask, for the vectors
 // listed in vmap (or 0..nvec-1): NV vectors per thread, every link read once per site and direction.
 // A workgroup takes 128 sites: waves 0-1 the identity term and the forward transports d = 1..4,
@@ -168,40 +208,13 @@ __global__ __launch_bounds__(256) void k_layer_kernel(Geom g, const cx<float>* _
         for (int c = 0; c < 12; c++) acc[j][c] = mk<float>(0.f, 0.f);
     if (valid) {
         const Site s = site_of(g, p, h);
-        const int d0 = side ? 5 : 0, d1 = side ? 9 : 5;
-        for (int d = d0; d < d1; d++) {
-            if (vanishes(zero_odd_input, d, p)) continue;
-            // an input known to vanish outside its band of t-slices (a back-propagated gradient): skip
-            // the terms that would read it there
-            if (in_band.nt < g.L[3]) {
-                int tin = s.t;
-                if (d == 4) tin = s.t + 1 == g.L[3] ? 0 : s.t + 1;
-                if (d == 8) tin = s.t == 0 ? g.L[3] - 1 : s.t - 1;
-                const int dt = tin - in_band.t0 < 0 ? tin - in_band.t0 + g.L[3] : tin - in_band.t0;
-                if (dt >= in_band.nt) continue;
-            }
-            Hop o;
-            if (d) load_hop(g, links, p, h, s, d, o);
+        // the directions unrolled, so that each one's transport is resolved at compile time
+        if (side == 0) {
 #pragma unroll
-            for (int j = 0; j < NV; j++) {
-                if (vec[j] < 0) continue;
-                const cx<float>* src = in + (int64_t)vec[j] * 24 * Vh;
-                cx<float> t[12];
-                if (d == 0) {
+            for (int d = 0; d < 5; d++) k_layer_term<NV>(d, g, links, in, w, vec, zero_odd_input, in_band, p, h, s, Vh, acc);
+        } else {
 #pragma unroll
-                    for (int c = 0; c < 12; c++) t[c] = src[(int64_t)(p * 12 + c) * Vh + h];
-                } else {
-                    apply_hop(o, src, p, Vh, t);
-                }
-#pragma unroll
-                for (int a = 0; a < 4; a++)
-#pragma unroll
-                    for (int b = 0; b < 4; b++) {
-                        const cx<float> wab = w[d * 16 + a * 4 + b];
-#pragma unroll
-                        for (int c = 0; c < 3; c++) acc[j][3 * a + c] = acc[j][3 * a + c] + cmul(wab, t[3 * b + c]);
-                    }
-            }
+            for (int d = 5; d < 9; d++) k_layer_term<NV>(d, g, links, in, w, vec, zero_odd_input, in_band, p, h, s, Vh, acc);
         }
     }
     if (side == 1) {
@@ -249,11 +262,13 @@ void k_layer(const Geom& g, const void* links32, const void* in, void* out, cons
 // direction d = blockIdx.y, with dt = d (layer L) or dt = -d (layer L^dag); each link is read once per
 // site for all vectors.  A thread takes K_GRAD_SPT sites (a workgroup K_GRAD_SPT consecutive runs of
 // 256) and sums their terms in FP32; the workgroup's sum is FP64.  part[d][block][16] complex.
+// (Workgroups of 256 threads: the reduction below assumes it.)
 constexpr int K_GRAD_SPT = 4;
 __global__ __launch_bounds__(256) void k_grad_kernel(Geom g, const cx<float>* __restrict__ links, const cx<float>* __restrict__ gv,
                                                      const cx<float>* __restrict__ in, int dagger, int nvec, int zero_odd_input,
                                                      int pmask, Band band, double* part) {
-    __shared__ double lds[4 * 32];
+    __shared__ double lds[8 * 32];
+    __shared__ float tile[256 * 33];
     const int d = blockIdx.y;
     const int dt = dagger ? adj_dir(d) : d;
     const int Vh = (int)g.Vh;
@@ -294,16 +309,21 @@ __global__ __launch_bounds__(256) void k_grad_kernel(Geom g, const cx<float>* __
                 }
         }
     }
-    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    // the workgroup's sum through LDS: every thread's 32 values as a row, then 8 groups of 32 rows
+    // summed column by column in FP64, then the 8 group sums (fixed order throughout)
 #pragma unroll
-    for (int e = 0; e < 32; e++) {
-        double v = (double)acc[e];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        if (lane == 0) lds[wave * 32 + e] = v;
+    for (int e = 0; e < 32; e++) tile[threadIdx.x * 33 + e] = acc[e];
+    __syncthreads();
+    {
+        const int e = threadIdx.x % 32, grp = threadIdx.x / 32;
+        double v = 0.0;
+        for (int r = 0; r < 32; r++) v += (double)tile[(grp * 32 + r) * 33 + e];
+        lds[grp * 32 + e] = v;
     }
     __syncthreads();
     if (threadIdx.x < 32) {
-        const double v = lds[threadIdx.x] + lds[32 + threadIdx.x] + lds[64 + threadIdx.x] + lds[96 + threadIdx.x];
+        double v = 0.0;
+        for (int grp = 0; grp < 8; grp++) v += lds[grp * 32 + threadIdx.x];
         part[((int64_t)d * gridDim.x + blockIdx.x) * 32 + threadIdx.x] = v;
     }
 }

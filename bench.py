@@ -7,7 +7,8 @@ through the LU of T), then CG from the seeded guesses on every right-hand side, 
 FP64 true relative residual <= tol.  Inputs are resident in HBM before the timed region.
 
 The headline line (default): `value` is the learned + mixed form, timed per step as
-  solve_seed (FP64 Algorithm 1, FP64 basis)
+  solve_seed (FP64 Algorithm 1; FP64 basis, plus an FP32 copy of it that only the periodic
+    reorthogonalisation reads where HBM holds both: --basis)
   + train_precond (the learned K K^dag, 2000 Adam steps on the seed solve's Ritz vectors and
     residuals, then judged against plain CG on RHS 2)
   + solve_rest (FP32 CG with FP64 reliable updates; PCG with K and the 16 lowest Ritz vectors of the
@@ -56,6 +57,9 @@ def parse():
     ap.add_argument("--deflate-k", type=int, default=16, help="Ritz vectors deflated in the learned form's (P)CG")
     ap.add_argument("--ref-steps", type=int, default=5, help="timed steps of the plain FP64 reference (at most --steps)")
     ap.add_argument("--m-max", type=int, default=0, help="Krylov basis capacity of both forms (0: by the HBM left)")
+    ap.add_argument("--basis", default="auto", choices=("auto", "fp64", "fp32", "reorth"),
+                    help="the learned + mixed form's Krylov basis: FP64; FP32; FP64 plus an FP32 copy read only by the "
+                         "reorthogonalisation; auto = reorth where HBM holds both at the capacity, else FP64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=40, help="Lanczos steps in the oracle sample")
     ap.add_argument("--sample-every", type=int, default=7,
@@ -284,7 +288,14 @@ def bench_metric(args):
     m_max = args.m_max or min(1000, int(0.6 * torch.cuda.get_device_properties(0).total_memory // vec_bytes))
     common = dict(t_bc=cfg.t_bc, reorth_k=cfg.reorth_k, past=cfg.past, tol=cfg.tol, reliable_every=cfg.reliable_every,
                   m_max=m_max)
-    val = SeedCG(Ud, cfg.dims, kappa, prec="mixed_cg", deflate=args.deflate_k, **common)
+    # the value form's basis: the FP64 basis (the seeding keeps its full gain) plus an FP32 copy that
+    # halves the reorthogonalisation's reads, where 60% of the GPU's memory holds both at the capacity
+    basis = args.basis
+    if basis == "auto":
+        hbm = torch.cuda.get_device_properties(0).total_memory
+        basis = "reorth" if m_max * vec_bytes * 3 // 2 <= 0.6 * hbm else "fp64"
+    val = SeedCG(Ud, cfg.dims, kappa, prec="mixed_cg", deflate=args.deflate_k,
+                 basis_fp32={"fp64": False, "fp32": True, "reorth": "reorth"}[basis], **common)
     B = val.apply_A(phid, dagger=True)   # b = A^dag phi (input preparation, not timed)
     nrhs = B.shape[0]
 
@@ -380,7 +391,9 @@ def bench_metric(args):
                                f"lambda_min/lambda_max {cfg.ratio:g}, {nrhs} RHS, tol {cfg.tol:g}, k={cfg.reorth_k}",
                    "name": cfg.name, "lattice": list(cfg.dims), "kappa": kappa, "nrhs": nrhs, "reorth_k": cfg.reorth_k,
                    "past_factor": cfg.past, "tol": cfg.tol, "train_steps": args.train_steps,
-                   "deflated_ritz_vectors": args.deflate_k, "m_max": m_max},
+                   "deflated_ritz_vectors": args.deflate_k, "m_max": m_max,
+                   "learned_mixed_basis": {"fp64": "FP64", "fp32": "FP32",
+                                           "reorth": "FP64, FP32 copy for the reorthogonalisation"}[basis]},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "detail": {

@@ -92,13 +92,19 @@ typedef struct {
                                  at most 24 right-hand sides per solve_rest.  After train_precond
                                  plain CG deflates only if its judge found that cheaper            */
     void* stream;             /* hipStream_t; NULL = the null stream                             */
-    int32_t basis_fp32;       /* FP64 and MIXED_FP32_CG: 1 stores the Krylov basis in FP32 while the
-                                 Lanczos recurrence, its coefficients and the LU of T stay FP64: each
-                                 finished v_i is rounded into its basis slot, the seeding and
-                                 reorthogonalisation projections contract the FP32 basis on the FP64
-                                 matrix cores, and the updates subtract the widened FP32 vectors from
-                                 the FP64 v_i and f.  Half the basis traffic and twice the capacity.
-                                 Single configurations only (create_batch refuses it).           */
+    int32_t basis_fp32;       /* FP64 and MIXED_FP32_CG (0 otherwise; 0, 1 or 2, else ERR_ARG):
+                                 1 stores the Krylov basis in FP32 while the Lanczos recurrence, its
+                                 coefficients and the LU of T stay FP64: each finished v_i is rounded
+                                 into its basis slot, the seeding and reorthogonalisation projections
+                                 contract the FP32 basis on the FP64 matrix cores, and the updates
+                                 subtract the widened FP32 vectors from the FP64 v_i and f.  Half the
+                                 basis traffic and twice the capacity.
+                                 2 keeps the FP64 basis for everything the method reads from it (the
+                                 seeding of Eq. (1), the Ritz vectors, the basis vectors handed out)
+                                 and adds an FP32 copy of every finished v_i that only the periodic
+                                 reorthogonalisation reads, as 1 does: half its traffic, orthogonality
+                                 to FP32 rounding, 1.5x the memory of the FP64 basis.
+                                 Single configurations only (create_batch refuses both).         */
 } seedcg_params;
 
 typedef struct {

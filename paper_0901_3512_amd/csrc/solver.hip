@@ -141,6 +141,7 @@ struct seedcg_s {
     std::string err;
     bool lo = false;        // FP32 Lanczos basis and seeding (mixed precision)
     bool blo = false;       // the stored basis in FP32 (lo, or FP64 Lanczos with an FP32 copy of each vector)
+    bool rcopy = false;     // an FP64 basis plus an FP32 copy of it that only the reorthogonalisation reads
     bool cg_lo = false;     // FP32 CG with FP64 reliable updates (every mixed mode; lo implies it)
     Prec lo_prec = P64;     // precision of the inner stencil
     int64_t N = 0;          // complex per vector
@@ -189,6 +190,7 @@ struct seedcg_s {
     bool k_accepted = false;   // K won the judge against plain CG (solve_rest applies it when asked)
     DBuf kW32, kWm, kG, kAm, kAv, kpart, klinks32, kU, kY, kun2, klpart, kS, kfield, pfa, pfb, Zv, rzpart;
     DBuf vring, vt32;   // FP64 Lanczos ring and FP32 projection operands (FP32 copy of an FP64 basis)
+    DBuf basis32;       // the FP32 copy of the FP64 basis that the reorthogonalisation reads (rcopy)
     // With params.m_max = 0 (one configuration) the basis grows as the Lanczos run needs it, up to
     // m_cap vectors: basis_phys vectors are allocated.
     bool basis_grow = false;
@@ -492,10 +494,8 @@ void alloc_seed(seedcg_s* h, int nrhs) {
     h->x1.ensure(h->vec_bytes(false));
     // the right-hand sides' residuals are projected against the basis in its stored precision
     h->R0.ensure(std::max(1, nrhs - 1) * h->vec_bytes(blo));
-    if (blo && !lo) {
-        h->vring.ensure(2 * h->vec_bytes(false));   // v_{i-1}, v_i of the FP64 recurrence
-        h->vt32.ensure(2 * h->vec_bytes(true));     // [v_i, f] rounded for the reorthogonalisation projection
-    }
+    if (blo && !lo) h->vring.ensure(2 * h->vec_bytes(false));   // v_{i-1}, v_i of the FP64 recurrence
+    if ((blo && !lo) || h->rcopy) h->vt32.ensure(2 * h->vec_bytes(true));   // [v_i, f] rounded for the reorthogonalisation projection
     h->Bint.ensure(nrhs * h->vec_bytes(false));
     h->Xint.ensure(nrhs * h->vec_bytes(false));
     h->st.ensure(sizeof(LzState));
@@ -519,8 +519,9 @@ void alloc_seed(seedcg_s* h, int nrhs) {
         size_t freeb = 0, total = 0;
         HIPCHK(hipMemGetInfo(&freeb, &total));
         const int64_t reserve = 4LL << 30;
-        const int64_t avail = (int64_t)freeb - reserve + (int64_t)h->basis.bytes;
-        cap = std::max<int64_t>(0, (int64_t)(0.75 * (double)avail) / h->vec_bytes(blo));
+        const int64_t avail = (int64_t)freeb - reserve + (int64_t)h->basis.bytes + (int64_t)h->basis32.bytes;
+        const int64_t per = h->vec_bytes(blo) + (h->rcopy ? h->vec_bytes(true) : 0);
+        cap = std::max<int64_t>(0, (int64_t)(0.75 * (double)avail) / per);
         cap = std::min<int64_t>(cap, 8192);
         if (cap < 2) throw OomError{"no room for a Krylov basis"};
     }
@@ -533,8 +534,14 @@ void alloc_seed(seedcg_s* h, int nrhs) {
         const int64_t first = std::min<int64_t>(cap, std::max(2, env_int("SEEDCG_BASIS_FIRST", 256)));
         if ((int64_t)h->basis.bytes < first * vb) h->basis.ensure((size_t)first * vb);
         h->basis_phys = (int64_t)h->basis.bytes / vb;
+        if (h->rcopy) {
+            const int64_t vb32 = h->vec_bytes(true);
+            if ((int64_t)h->basis32.bytes < first * vb32) h->basis32.ensure((size_t)first * vb32);
+            h->basis_phys = std::min<int64_t>(h->basis_phys, (int64_t)h->basis32.bytes / vb32);
+        }
     } else {
         h->basis.ensure((size_t)cap * vb);
+        if (h->rcopy) h->basis32.ensure((size_t)cap * h->vec_bytes(true));
         h->basis_phys = cap;
     }
     h->arrays.ensure(6 * ((int64_t)cap + 2) * sizeof(double));
@@ -551,18 +558,30 @@ void alloc_seed(seedcg_s* h, int nrhs) {
 // and the caller caps the run there.
 int64_t grow_basis(seedcg_s* h, int64_t need) {
     if (!h->basis_grow || need <= h->basis_phys) return h->basis_phys;
-    const int64_t vb = h->vec_bytes(h->blo);
+    const int64_t vb = h->vec_bytes(h->blo), vb32 = h->vec_bytes(true);
     const int64_t to = std::min<int64_t>(h->m_cap, std::max<int64_t>(need, 2 * h->basis_phys));
-    void* np = nullptr;
+    void *np = nullptr, *np32 = nullptr;
     if (hipMalloc(&np, (size_t)(to * vb)) != hipSuccess) {
         (void)hipGetLastError();
         return h->basis_phys;
     }
+    if (h->rcopy && hipMalloc(&np32, (size_t)(to * vb32)) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(np);
+        return h->basis_phys;
+    }
     HIPCHK(hipMemcpyAsync(np, h->basis.p, (size_t)(h->basis_phys * vb), hipMemcpyDeviceToDevice, h->s));
+    if (h->rcopy)
+        HIPCHK(hipMemcpyAsync(np32, h->basis32.p, (size_t)(h->basis_phys * vb32), hipMemcpyDeviceToDevice, h->s));
     HIPCHK(hipStreamSynchronize(h->s));
     (void)hipFree(h->basis.p);
     h->basis.p = np;
     h->basis.bytes = (size_t)(to * vb);
+    if (h->rcopy) {
+        (void)hipFree(h->basis32.p);
+        h->basis32.p = np32;
+        h->basis32.bytes = (size_t)(to * vb32);
+    }
     h->basis_phys = to;
     return to;
 }
@@ -596,8 +615,11 @@ void flush_seed_block(seedcg_s* h, int i0, int i1, int nrhs) {
 
 // vi: v_i as the recurrence holds it (the basis slot, or the FP64 ring with an FP32 basis copy)
 void reorthogonalise(seedcg_s* h, int i, void* vi) {
-    const bool lo = h->lo, blo = h->blo;
-    const bool split = blo && !lo;   // FP64 v_i and f against the FP32 stored basis
+    const bool lo = h->lo;
+    // FP64 v_i and f against FP32 basis vectors: the stored basis, or the FP32 copy of an FP64 one
+    const bool split = (h->blo && !lo) || h->rcopy;
+    const bool v32 = h->blo || h->rcopy;
+    void* V = h->rcopy ? h->basis32.p : h->basis.p;
     const int64_t N = h->N;
     LzState* st = h->st.as<LzState>();
     const int64_t nb = norm2_blocks(N);
@@ -611,7 +633,7 @@ void reorthogonalise(seedcg_s* h, int i, void* vi) {
             convert(false, true, h->f.p, ft, N, h->L());
         }
         ProjArgs a{};
-        a.V = h->basis.p;
+        a.V = V;
         a.ldv = N;
         a.nv = i;
         a.R[0] = split ? vt : vi;
@@ -625,8 +647,8 @@ void reorthogonalise(seedcg_s* h, int i, void* vi) {
         a.gate_i = i;
         a.flag = pass == 2 ? &st->rep_any : nullptr;
         // the reorthogonalisation coefficients are always accumulated in FP64
-        project(blo, a, (i + 31) / 32, h->G.as<double>(), h->L(), true);
-        reorth_update(lo, i, pass, st, h->basis.p, N, h->G.as<double>(), vi, h->f.p, h->rpart.as<double>(), h->L(), blo);
+        project(v32, a, (i + 31) / 32, h->G.as<double>(), h->L(), true);
+        reorth_update(lo, i, pass, st, V, N, h->G.as<double>(), vi, h->f.p, h->rpart.as<double>(), h->L(), v32);
         reorth_scalar(i, pass, st, h->rpart.as<double>(), nb, h->G.as<double>(), h->L());
         reorth_finish(lo, i, pass, st, vi, h->f.p, h->f2b.as<double>(), N, h->L());
         reorth_decide(i, pass, st, h->f2a.as<double>(), h->f2b.as<double>(), nb, h->L());
@@ -719,9 +741,10 @@ void solve_seed_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report* rep) {
         return split ? (char*)h->vring.p + (int64_t)((j - 1) & 1) * h->vec_bytes(false)
                      : (char*)h->basis.p + (int64_t)(j - 1) * h->vec_bytes(lo);
     };
-    auto store = [&](int j) {   // round v_j into its slot of the FP32 basis
-        if (split && j <= h->m_cap)
-            convert(false, true, vcur(j), (char*)h->basis.p + (int64_t)(j - 1) * h->vec_bytes(true), N, L);
+    auto store = [&](int j) {   // round v_j into its slot of the FP32 basis, or of the FP32 copy
+        if ((split || h->rcopy) && j <= h->m_cap)
+            convert(false, true, vcur(j), (char*)(h->rcopy ? h->basis32.p : h->basis.p) + (int64_t)(j - 1) * h->vec_bytes(true), N,
+                    L);
     };
     if (lo) {
         convert(false, true, h->r64.p, h->f.p, N, L);
@@ -1882,7 +1905,8 @@ void init_geometry(seedcg_s* h, const seedcg_params* p, const int32_t* dims) {
     g.t_bc = p->t_bc;
     h->N = 12 * g.Vh;
     h->lo = p->prec == SEEDCG_MIXED_FP32 || p->prec == SEEDCG_MIXED_FP32_BF16LINKS;
-    h->blo = h->lo || p->basis_fp32 != 0;
+    h->blo = h->lo || p->basis_fp32 == 1;
+    h->rcopy = !h->lo && p->basis_fp32 == 2;
     h->cg_lo = p->prec != SEEDCG_FP64;
     h->lo_prec = p->prec == SEEDCG_MIXED_FP32_BF16LINKS ? P32BF : (h->cg_lo ? P32 : P64);
     // default stencil launch shape: 8 = forward and backward hops on separate wavefronts, one vector
@@ -2626,6 +2650,7 @@ seedcg_status seedcg_create(const seedcg_params* p, const double* links, seedcg_
     if (p->prec < 0 || p->prec > 3) return fail(nullptr, SEEDCG_ERR_ARG, "create: unknown precision");
     if (!(p->tol > 0.0)) return fail(nullptr, SEEDCG_ERR_ARG, "create: tol must be > 0");
     if (p->reorth_k < 0) return fail(nullptr, SEEDCG_ERR_ARG, "create: reorth_k must be >= 0");
+    if (p->basis_fp32 < 0 || p->basis_fp32 > 2) return fail(nullptr, SEEDCG_ERR_ARG, "create: basis_fp32 must be 0, 1 or 2");
     seedcg_s* h = new (std::nothrow) seedcg_s;
     if (!h) return fail(nullptr, SEEDCG_ERR_OOM, "create: host allocation failed");
     seedcg_status st = guarded(h, [&]() -> seedcg_status {
@@ -3408,6 +3433,7 @@ seedcg_status seedcg_release_basis(seedcg_t h) {
         h->projpart.release();
         h->vring.release();
         h->vt32.release();
+        h->basis32.release();
         return SEEDCG_OK;
     });
 }

@@ -159,7 +159,9 @@ class SeedCG:
         p.max_iter = int(max_iter)
         p.autotune = int(bool(autotune))
         p.deflate = int(deflate)
-        p.basis_fp32 = int(bool(basis_fp32))
+        # False / True / "reorth": FP64 basis; FP32 basis; FP64 basis plus an FP32 copy read only by
+        # the reorthogonalisation
+        p.basis_fp32 = 2 if basis_fp32 == "reorth" else int(bool(basis_fp32))
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream

@@ -52,6 +52,10 @@ def test_create_rejects_bad_arguments_on_host(lib):
     p.t_bc = 0
     assert lib.seedcg_create(ctypes.byref(p), dummy, ctypes.byref(h)) == -1
     p.t_bc = -1
+    p.basis_fp32 = 3   # 0, 1 or 2
+    assert lib.seedcg_create(ctypes.byref(p), dummy, ctypes.byref(h)) == -1
+    assert b"basis_fp32" in lib.seedcg_last_error(None)
+    p.basis_fp32 = 0
     p.tol = 0.0
     assert lib.seedcg_create(ctypes.byref(p), dummy, ctypes.byref(h)) == -1
     assert lib.seedcg_create(None, dummy, ctypes.byref(h)) == -1

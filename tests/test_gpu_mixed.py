@@ -234,6 +234,36 @@ def test_fp32_basis_copy_of_fp64_lanczos(t8, prec):
     print("fp32 basis copy", prec, "m", rs["m"], "iters", rr["iters"])
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed_cg"])
+def test_fp32_reorth_copy_of_fp64_basis(t8, prec):
+    """basis_fp32 = "reorth": the FP64 basis serves the seeding, and an FP32 copy of every finished v_i
+    serves the periodic reorthogonalisation only (8^4, k = 10).  Against the oracle: m and i_conv within
+    one step, the first 20 Lanczos coefficients to 1e-8 relative (the copy enters T only through the
+    reorthogonalisation coefficients), the seeded guesses to 1e-6; the basis vectors handed out are the
+    FP64 ones (not FP32-representable) and orthonormal to FP32 rounding; every solution within 1e-8 of
+    the FP64 solution and at an FP64 true residual <= 1e-10."""
+    from paper_0901_3512_amd import SeedCG
+    print_case("fp32 reorth copy", prec)
+    ref = t8["ref"]
+    s = SeedCG(cuda(t8["U"]), t8["dims"], t8["kappa"], prec=prec, reorth_k=10, basis_fp32="reorth")
+    X, rs = s.solve_seed(cuda(t8["B"]))
+    assert abs(rs["m"] - ref["m"]) <= 1 and abs(rs["i_conv"] - ref["i_conv"]) <= 1, (rs["m"], ref["m"])
+    a, b = s.get_tridiag()
+    n = min(20, len(a))
+    assert np.max(np.abs(np.array(a[:n]) - ref["alpha"][:n]) / np.abs(ref["alpha"][:n])) <= 1e-8
+    assert np.max(np.abs(np.array(b[:n]) - ref["beta"][:n]) / ref["beta"][:n]) <= 1e-8
+    rel = np.linalg.norm(flat(host(X)) - ref["X"], axis=1) / np.linalg.norm(ref["X"], axis=1)
+    assert np.max(rel[1:]) <= 1e-6, rel
+    V = np.stack([flat(host(s.get_basis_vector(i))) for i in range(1, rs["m"] + 1)])
+    assert not np.all(V == V.astype(np.complex64).astype(np.complex128))   # the FP64 vectors
+    assert osc.orth_loss(V) <= 1e-6
+    X, rr = s.solve_rest(cuda(t8["B"]), X)
+    assert np.all(osc.true_relres(t8["mv"], flat(t8["B"]), flat(host(X))) <= 1e-10)
+    err = np.linalg.norm(flat(host(X)) - t8["xs"], axis=1) / np.linalg.norm(t8["xs"], axis=1)
+    assert np.max(err) <= 1e-8, err
+    print("fp32 reorth copy", prec, "m", rs["m"], "orth", osc.orth_loss(V), "iters", rr["iters"])
+
+
 def test_fp32_basis_copy_refused_for_batches():
     from paper_0901_3512_amd import SeedCGError
     from paper_0901_3512_amd.seedcg import Params, load_library

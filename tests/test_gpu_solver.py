@@ -281,3 +281,23 @@ def test_basis_grows_as_the_run_needs_it(monkeypatch):
     assert free0 - free1 < 0.05 * total, (free0 - free1, total)
     X, rr = s.solve_rest(cuda(B), X)
     assert np.all(osc.true_relres(matvec_M(op), flat(B), flat(host(X))) <= 1e-10)
+
+
+def test_basis_and_its_reorth_copy_grow_together(monkeypatch):
+    """basis_fp32 = "reorth" with m_max = 0: the FP64 basis and its FP32 copy start at 8 vectors and
+    grow together; the run is bit for bit the one with the whole capacity allocated up front."""
+    print_case("growing basis with its FP32 reorthogonalisation copy")
+    U, dims, kappa, op, B = _setup("t4")
+    s0 = _solver(U, dims, kappa, reorth_k=10, m_max=400, basis_fp32="reorth")
+    X0, r0 = s0.solve_seed(cuda(B))
+    a0, _ = s0.get_tridiag()
+    s0.close()
+    monkeypatch.setenv("SEEDCG_BASIS_FIRST", "8")
+    s = _solver(U, dims, kappa, reorth_k=10, basis_fp32="reorth")
+    X, r = s.solve_seed(cuda(B))
+    assert r["m"] == r0["m"] and r["m"] > 32, (r["m"], r0["m"])
+    assert np.array_equal(host(X), host(X0))
+    a, _ = s.get_tridiag()
+    assert np.array_equal(np.array(a), np.array(a0))
+    X, rr = s.solve_rest(cuda(B), X)
+    assert np.all(osc.true_relres(matvec_M(op), flat(B), flat(host(X))) <= 1e-10)

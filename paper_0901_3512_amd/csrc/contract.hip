@@ -210,6 +210,102 @@ __global__ void proj_reduce_kernel(const double* part, int64_t nchunks, int64_t 
 
 int64_t proj_chunks(int64_t n, int64_t kchunk) { return (n + kchunk - 1) / kchunk; }
 
+// The reorthogonalisation coefficients V_{1..i}^dag [v_i, f]: at most two columns, which would fill two
+// of the sixteen columns of a matrix-core tile, so they are formed on the vector units in FP64 instead.
+// A workgroup takes a K-chunk and RP_ROWS rows of V; each thread runs through the chunk with stride
+// 256, reading the one or two R entries once and the RP_ROWS entries of V at that index (row
+// addresses are uniform; a row beyond the last valid one reads the last valid row again and is not
+// written), and keeps FP64 sums per row and column.  The workgroup's sums are formed in a fixed
+// order through LDS and written to part[chunk][row][j] like proj_kernel's, so proj_reduce_kernel
+// finishes them.  TV, TR: storage of V and of R (FP32 entries are widened exactly).
+constexpr int RP_ROWS = 16;
+template <typename TV, typename TR>
+__global__ __launch_bounds__(256) void reorth_proj_kernel(const ProjArgs pa, int64_t cs) {
+    __shared__ double tile[256 * (RP_ROWS + 1)];
+    __shared__ double grp[16 * RP_ROWS];
+    const LzState* st = zoff(pa.st, cs);
+    const int32_t* flag = zoff(pa.flag, cs);
+    if (st && pa.gate_i > st->m) return;
+    if (flag && *flag == 0) return;
+    int nvalid = pa.nv;
+    if (st && pa.rows_from_m) nvalid = max(0, min(pa.nv, st->m - pa.i0 + 1));
+    const int row0 = blockIdx.y * RP_ROWS;
+    const int nrow = min(RP_ROWS, nvalid - row0);
+    if (nrow <= 0) return;
+    const int nr = pa.nr;
+    const cx<TR>* R0 = (const cx<TR>*)zoff(pa.R[0], cs);
+    const cx<TR>* R1 = (const cx<TR>*)zoff(pa.R[nr > 1 ? 1 : 0], cs);
+    const cx<TV>* Vb = (const cx<TV>*)zoff(pa.V, cs);
+    const cx<TV>* vrow[RP_ROWS];
+#pragma unroll
+    for (int r = 0; r < RP_ROWS; r++) vrow[r] = Vb + (int64_t)(row0 + min(r, nrow - 1)) * pa.ldv;
+    const int64_t k_begin = (int64_t)blockIdx.x * pa.kchunk;
+    const int64_t k_end = min(pa.n, k_begin + pa.kchunk);
+    // acc[r][0..3]: Re, Im of conj(V_r) R_0 and of conj(V_r) R_1
+    double acc[RP_ROWS][4];
+#pragma unroll
+    for (int r = 0; r < RP_ROWS; r++)
+#pragma unroll
+        for (int c = 0; c < 4; c++) acc[r][c] = 0.0;
+#pragma unroll 1
+    for (int64_t k = k_begin + threadIdx.x; k < k_end; k += 256) {
+        const cx<TR> a = R0[k], b = R1[k];
+        cx<TV> v[RP_ROWS];
+#pragma unroll
+        for (int r = 0; r < RP_ROWS; r++) v[r] = vrow[r][k];
+        const double ar = a.re, ai = a.im, br = b.re, bi = b.im;
+#pragma unroll
+        for (int r = 0; r < RP_ROWS; r++) {
+            const double vr = v[r].re, vi = v[r].im;
+            acc[r][0] = fma(vr, ar, fma(vi, ai, acc[r][0]));
+            acc[r][1] = fma(vr, ai, fma(-vi, ar, acc[r][1]));
+            acc[r][2] = fma(vr, br, fma(vi, bi, acc[r][2]));
+            acc[r][3] = fma(vr, bi, fma(-vi, br, acc[r][3]));
+        }
+    }
+    // per column component c: the 256 threads' row sums through LDS, 16 groups of 16 threads summed
+    // row by row, then the 16 group sums (fixed order throughout)
+    double* out = zoff(pa.part, cs) + (int64_t)blockIdx.x * pa.part_stride;
+    const int e = threadIdx.x % RP_ROWS, g = threadIdx.x / RP_ROWS;
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+        if (c >= 2 * nr) break;   // uniform
+#pragma unroll
+        for (int r = 0; r < RP_ROWS; r++) tile[threadIdx.x * (RP_ROWS + 1) + r] = acc[r][c];
+        __syncthreads();
+        double sum = 0.0;
+        for (int q = 0; q < 16; q++) sum += tile[(g * 16 + q) * (RP_ROWS + 1) + e];
+        grp[g * RP_ROWS + e] = sum;
+        __syncthreads();
+        if (threadIdx.x < RP_ROWS && (int)threadIdx.x < nrow) {
+            double t = 0.0;
+            for (int q = 0; q < 16; q++) t += grp[q * RP_ROWS + threadIdx.x];
+            out[2 * ((int64_t)(row0 + threadIdx.x) * nr + (c >> 1)) + (c & 1)] = t;
+        }
+        __syncthreads();
+    }
+}
+
+void reorth_project(bool v32, bool r32, const ProjArgs& a, double* P, const Launch& L) {
+    if (a.part == nullptr || P == nullptr) throw std::invalid_argument("reorth_project: partials or output buffer missing");
+    if (a.nr < 1 || a.nr > 2) throw std::invalid_argument("reorth_project: one or two columns");
+    if (a.part_stride < 2 * (int64_t)a.nv * a.nr) throw std::invalid_argument("reorth_project: partial stride below 2 nv nr");
+    const hipStream_t s = L.s;
+    const int64_t nch = proj_chunks(a.n, a.kchunk);
+    const dim3 grid((unsigned)nch, (unsigned)((a.nv + RP_ROWS - 1) / RP_ROWS), L.nz);
+    if (v32 && r32)
+        hipLaunchKernelGGL((reorth_proj_kernel<float, float>), grid, dim3(256), 0, s, a, L.cs);
+    else if (v32)
+        hipLaunchKernelGGL((reorth_proj_kernel<float, double>), grid, dim3(256), 0, s, a, L.cs);
+    else if (!r32)
+        hipLaunchKernelGGL((reorth_proj_kernel<double, double>), grid, dim3(256), 0, s, a, L.cs);
+    else
+        throw std::invalid_argument("reorth_project: an FP64 basis takes FP64 columns");
+    const int64_t len = 2 * (int64_t)a.nv * a.nr;
+    hipLaunchKernelGGL(proj_reduce_kernel, dim3((unsigned)((len * SCG_WAVE + 255) / 256), 1, L.nz), dim3(256), 0, s, a.part, nch,
+                       a.part_stride, len, P, a.st, a.gate_i, a.flag, L.cs);
+}
+
 // Split-K partials of the allocation-free contraction (seedcg_project_noalloc): one copy of this
 // array per GPU, held by the loaded code object until the process ends.  In host code its name is
 // only a stand-in for the device copy; proj_scratch() returns the device address to pass instead.

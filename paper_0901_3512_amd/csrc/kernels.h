@@ -38,6 +38,9 @@ struct ProjArgs {
 // fp32: V and R stored in FP32; fp64_math: contract them on the FP64 matrix cores anyway
 void project(bool fp32, const ProjArgs& a, int64_t nrowblocks, double* P, const Launch& L, bool fp64_math = false);
 int64_t proj_chunks(int64_t n, int64_t kchunk);
+// V^dag R for the reorthogonalisation's one or two columns, FP64 arithmetic on the vector units
+// (v32: V stored in FP32; r32: R stored in FP32), partials and output as project()
+void reorth_project(bool v32, bool r32, const ProjArgs& a, double* P, const Launch& L);
 // Static partials of the allocation-free contraction: PROJ_SCRATCH_DOUBLES doubles (4 MiB) per GPU.
 // proj_scratch() returns the current device's copy (its address is looked up once per device).
 constexpr int64_t PROJ_SCRATCH_DOUBLES = int64_t(1) << 19;

@@ -189,7 +189,7 @@ struct seedcg_s {
     bool k_ready = false;
     bool k_accepted = false;   // K won the judge against plain CG (solve_rest applies it when asked)
     DBuf kW32, kWm, kG, kAm, kAv, kpart, klinks32, kU, kY, kun2, klpart, kS, kfield, pfa, pfb, Zv, rzpart;
-    DBuf vring, vt32;   // FP64 Lanczos ring and FP32 projection operands (FP32 copy of an FP64 basis)
+    DBuf vring;         // FP64 Lanczos ring (FP32 copy of an FP64 basis)
     DBuf basis32;       // the FP32 copy of the FP64 basis that the reorthogonalisation reads (rcopy)
     // With params.m_max = 0 (one configuration) the basis grows as the Lanczos run needs it, up to
     // m_cap vectors: basis_phys vectors are allocated.
@@ -478,8 +478,8 @@ int64_t kchunk_for(int64_t n, int64_t target_chunks) {
     return std::max<int64_t>(std::min<int64_t>(kc, 65536), 512);
 }
 
-// K-chunk of the reorthogonalisation coefficients V_{1..i}^dag [v_i, f]: about 2048 workgroups
-// over the (chunk, 32-row block) grid, at least 96 chunks.
+// K-chunk of the reorthogonalisation coefficients V_{1..i}^dag [v_i, f]: about 2048 / ceil(i / 32)
+// chunks, at least 96.
 int64_t reorth_kchunk(int64_t n, int i) {
     const int64_t rowblocks = (i + 31) / 32;
     return kchunk_for(n, std::max<int64_t>(96, 2048 / rowblocks));
@@ -495,7 +495,6 @@ void alloc_seed(seedcg_s* h, int nrhs) {
     // the right-hand sides' residuals are projected against the basis in its stored precision
     h->R0.ensure(std::max(1, nrhs - 1) * h->vec_bytes(blo));
     if (blo && !lo) h->vring.ensure(2 * h->vec_bytes(false));   // v_{i-1}, v_i of the FP64 recurrence
-    if ((blo && !lo) || h->rcopy) h->vt32.ensure(2 * h->vec_bytes(true));   // [v_i, f] rounded for the reorthogonalisation projection
     h->Bint.ensure(nrhs * h->vec_bytes(false));
     h->Xint.ensure(nrhs * h->vec_bytes(false));
     h->st.ensure(sizeof(LzState));
@@ -616,28 +615,20 @@ void flush_seed_block(seedcg_s* h, int i0, int i1, int nrhs) {
 // vi: v_i as the recurrence holds it (the basis slot, or the FP64 ring with an FP32 basis copy)
 void reorthogonalise(seedcg_s* h, int i, void* vi) {
     const bool lo = h->lo;
-    // FP64 v_i and f against FP32 basis vectors: the stored basis, or the FP32 copy of an FP64 one
-    const bool split = (h->blo && !lo) || h->rcopy;
+    // the basis vectors it reads: the stored basis, or the FP32 copy of an FP64 one; v_i and f are
+    // FP32 only in the FP32 Lanczos (lo)
     const bool v32 = h->blo || h->rcopy;
     void* V = h->rcopy ? h->basis32.p : h->basis.p;
     const int64_t N = h->N;
     LzState* st = h->st.as<LzState>();
     const int64_t nb = norm2_blocks(N);
-    void* vt = h->vt32.p;
-    void* ft = split ? (char*)h->vt32.p + h->vec_bytes(true) : nullptr;
     for (int pass = 1; pass <= 2; pass++) {
-        if (split) {
-            // the projection takes [v_i, f] rounded to the basis' FP32 (its rounding errors are
-            // incoherent with the basis: their inner products with it are O(eps / sqrt(N)))
-            convert(false, true, vi, vt, N, h->L());
-            convert(false, true, h->f.p, ft, N, h->L());
-        }
         ProjArgs a{};
         a.V = V;
         a.ldv = N;
         a.nv = i;
-        a.R[0] = split ? vt : vi;
-        a.R[1] = split ? ft : h->f.p;
+        a.R[0] = vi;
+        a.R[1] = h->f.p;
         a.nr = 2;
         a.n = N;
         a.kchunk = reorth_kchunk(N, i);
@@ -646,8 +637,8 @@ void reorthogonalise(seedcg_s* h, int i, void* vi) {
         a.st = st;
         a.gate_i = i;
         a.flag = pass == 2 ? &st->rep_any : nullptr;
-        // the reorthogonalisation coefficients are always accumulated in FP64
-        project(v32, a, (i + 31) / 32, h->G.as<double>(), h->L(), true);
+        // the reorthogonalisation coefficients, always accumulated in FP64
+        reorth_project(v32, lo, a, h->G.as<double>(), h->L());
         reorth_update(lo, i, pass, st, V, N, h->G.as<double>(), vi, h->f.p, h->rpart.as<double>(), h->L(), v32);
         reorth_scalar(i, pass, st, h->rpart.as<double>(), nb, h->G.as<double>(), h->L());
         reorth_finish(lo, i, pass, st, vi, h->f.p, h->f2b.as<double>(), N, h->L());
@@ -3432,7 +3423,6 @@ seedcg_status seedcg_release_basis(seedcg_t h) {
         h->wring.release();
         h->projpart.release();
         h->vring.release();
-        h->vt32.release();
         h->basis32.release();
         return SEEDCG_OK;
     });

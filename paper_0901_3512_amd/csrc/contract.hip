@@ -212,24 +212,57 @@ int64_t proj_chunks(int64_t n, int64_t kchunk) { return (n + kchunk - 1) / kchun
 
 // The reorthogonalisation coefficients V_{1..i}^dag [v_i, f]: at most two columns, which would fill two
 // of the sixteen columns of a matrix-core tile, so they are formed on the vector units in FP64 instead.
-// A workgroup takes a K-chunk and RP_ROWS rows of V; each thread runs through the chunk with stride
-// 256, reading the one or two R entries once and the RP_ROWS entries of V at that index (row
-// addresses are uniform; a row beyond the last valid one reads the last valid row again and is not
-// written), and keeps FP64 sums per row and column.  The workgroup's sums are formed in a fixed
-// order through LDS and written to part[chunk][row][j] like proj_kernel's, so proj_reduce_kernel
-// finishes them.  TV, TR: storage of V and of R (FP32 entries are widened exactly).
-constexpr int RP_ROWS = 16;
+// A workgroup takes a K-chunk and RP_ROWS rows of V (the row blocks of one chunk run one after another
+// on one XCD, so the chunk of R is fetched once into its L2); each thread runs through the chunk with stride
+// 256 * EPL, reading EPL consecutive entries (16 bytes of each row of V: one FP64 complex, or two FP32
+// ones) of the one or two R vectors once and of the RP_ROWS rows of V (row addresses are uniform; a
+// row beyond the last valid one reads the last valid row again and is not written), and keeps FP64
+// sums per row and column.  The workgroup's sums are formed in a fixed order through LDS and written
+// to part[chunk][row][j] like proj_kernel's, so proj_reduce_kernel finishes them.  TV, TR: storage
+// of V and of R (FP32 entries are widened exactly).  With FP32 V the chunk bounds and n are even.
+// 8 rows keep 122 VGPRs (4 waves per SIMD) with every load of a step in flight; 16 rows took 240
+// and the compiler then issued the loads one at a time
+constexpr int RP_ROWS = 8;
+template <typename T>
+struct Pair16;   // EPL consecutive complex entries as 16-byte loads
+template <>
+struct Pair16<double> {
+    static constexpr int EPL = 1;
+    __device__ static inline void load(const cx<double>* p, double (&re)[1], double (&im)[1]) {
+        const double2 q = *(const double2*)p;
+        re[0] = q.x;
+        im[0] = q.y;
+    }
+};
+template <>
+struct Pair16<float> {
+    static constexpr int EPL = 2;
+    __device__ static inline void load(const cx<float>* p, float (&re)[2], float (&im)[2]) {
+        const float4 q = *(const float4*)p;
+        re[0] = q.x;
+        im[0] = q.y;
+        re[1] = q.z;
+        im[1] = q.w;
+    }
+};
 template <typename TV, typename TR>
 __global__ __launch_bounds__(256) void reorth_proj_kernel(const ProjArgs pa, int64_t cs) {
+    constexpr int EPL = Pair16<TV>::EPL;
     __shared__ double tile[256 * (RP_ROWS + 1)];
-    __shared__ double grp[16 * RP_ROWS];
+    constexpr int G = 256 / RP_ROWS;   // groups of RP_ROWS threads in the final sums
+    __shared__ double grp[256];
     const LzState* st = zoff(pa.st, cs);
     const int32_t* flag = zoff(pa.flag, cs);
     if (st && pa.gate_i > st->m) return;
     if (flag && *flag == 0) return;
     int nvalid = pa.nv;
     if (st && pa.rows_from_m) nvalid = max(0, min(pa.nv, st->m - pa.i0 + 1));
-    const int row0 = blockIdx.y * RP_ROWS;
+    const int nrb = (pa.nv + RP_ROWS - 1) / RP_ROWS;
+    const int64_t nch = (pa.n + pa.kchunk - 1) / pa.kchunk;
+    const int64_t w = xcd_logical_block(nch * nrb);
+    if (w >= nch * nrb) return;
+    const int64_t chunk = w / nrb;
+    const int row0 = (int)(w % nrb) * RP_ROWS;
     const int nrow = min(RP_ROWS, nvalid - row0);
     if (nrow <= 0) return;
     const int nr = pa.nr;
@@ -239,7 +272,7 @@ __global__ __launch_bounds__(256) void reorth_proj_kernel(const ProjArgs pa, int
     const cx<TV>* vrow[RP_ROWS];
 #pragma unroll
     for (int r = 0; r < RP_ROWS; r++) vrow[r] = Vb + (int64_t)(row0 + min(r, nrow - 1)) * pa.ldv;
-    const int64_t k_begin = (int64_t)blockIdx.x * pa.kchunk;
+    const int64_t k_begin = chunk * pa.kchunk;
     const int64_t k_end = min(pa.n, k_begin + pa.kchunk);
     // acc[r][0..3]: Re, Im of conj(V_r) R_0 and of conj(V_r) R_1
     double acc[RP_ROWS][4];
@@ -248,24 +281,33 @@ __global__ __launch_bounds__(256) void reorth_proj_kernel(const ProjArgs pa, int
 #pragma unroll
         for (int c = 0; c < 4; c++) acc[r][c] = 0.0;
 #pragma unroll 1
-    for (int64_t k = k_begin + threadIdx.x; k < k_end; k += 256) {
-        const cx<TR> a = R0[k], b = R1[k];
-        cx<TV> v[RP_ROWS];
+    for (int64_t k = k_begin + EPL * threadIdx.x; k < k_end; k += EPL * 256) {
+        double ar[EPL], ai[EPL], br[EPL], bi[EPL];
 #pragma unroll
-        for (int r = 0; r < RP_ROWS; r++) v[r] = vrow[r][k];
-        const double ar = a.re, ai = a.im, br = b.re, bi = b.im;
-#pragma unroll
-        for (int r = 0; r < RP_ROWS; r++) {
-            const double vr = v[r].re, vi = v[r].im;
-            acc[r][0] = fma(vr, ar, fma(vi, ai, acc[r][0]));
-            acc[r][1] = fma(vr, ai, fma(-vi, ar, acc[r][1]));
-            acc[r][2] = fma(vr, br, fma(vi, bi, acc[r][2]));
-            acc[r][3] = fma(vr, bi, fma(-vi, br, acc[r][3]));
+        for (int e = 0; e < EPL; e++) {
+            const cx<TR> a = R0[k + e], b = R1[k + e];
+            ar[e] = a.re;
+            ai[e] = a.im;
+            br[e] = b.re;
+            bi[e] = b.im;
         }
+        TV vr[RP_ROWS][EPL], vi[RP_ROWS][EPL];   // widened where they are used
+#pragma unroll
+        for (int r = 0; r < RP_ROWS; r++) Pair16<TV>::load(vrow[r] + k, vr[r], vi[r]);
+#pragma unroll
+        for (int r = 0; r < RP_ROWS; r++)
+#pragma unroll
+            for (int e = 0; e < EPL; e++) {
+                const double x = vr[r][e], y = vi[r][e];
+                acc[r][0] = fma(x, ar[e], fma(y, ai[e], acc[r][0]));
+                acc[r][1] = fma(x, ai[e], fma(-y, ar[e], acc[r][1]));
+                acc[r][2] = fma(x, br[e], fma(y, bi[e], acc[r][2]));
+                acc[r][3] = fma(x, bi[e], fma(-y, br[e], acc[r][3]));
+            }
     }
-    // per column component c: the 256 threads' row sums through LDS, 16 groups of 16 threads summed
-    // row by row, then the 16 group sums (fixed order throughout)
-    double* out = zoff(pa.part, cs) + (int64_t)blockIdx.x * pa.part_stride;
+    // per column component c: the 256 threads' row sums through LDS, G groups of RP_ROWS threads summed
+    // row by row, then the G group sums (fixed order throughout)
+    double* out = zoff(pa.part, cs) + chunk * pa.part_stride;
     const int e = threadIdx.x % RP_ROWS, g = threadIdx.x / RP_ROWS;
 #pragma unroll
     for (int c = 0; c < 4; c++) {
@@ -274,12 +316,12 @@ __global__ __launch_bounds__(256) void reorth_proj_kernel(const ProjArgs pa, int
         for (int r = 0; r < RP_ROWS; r++) tile[threadIdx.x * (RP_ROWS + 1) + r] = acc[r][c];
         __syncthreads();
         double sum = 0.0;
-        for (int q = 0; q < 16; q++) sum += tile[(g * 16 + q) * (RP_ROWS + 1) + e];
+        for (int q = 0; q < RP_ROWS; q++) sum += tile[(g * RP_ROWS + q) * (RP_ROWS + 1) + e];
         grp[g * RP_ROWS + e] = sum;
         __syncthreads();
         if (threadIdx.x < RP_ROWS && (int)threadIdx.x < nrow) {
             double t = 0.0;
-            for (int q = 0; q < 16; q++) t += grp[q * RP_ROWS + threadIdx.x];
+            for (int q = 0; q < G; q++) t += grp[q * RP_ROWS + threadIdx.x];
             out[2 * ((int64_t)(row0 + threadIdx.x) * nr + (c >> 1)) + (c & 1)] = t;
         }
         __syncthreads();
@@ -290,9 +332,11 @@ void reorth_project(bool v32, bool r32, const ProjArgs& a, double* P, const Laun
     if (a.part == nullptr || P == nullptr) throw std::invalid_argument("reorth_project: partials or output buffer missing");
     if (a.nr < 1 || a.nr > 2) throw std::invalid_argument("reorth_project: one or two columns");
     if (a.part_stride < 2 * (int64_t)a.nv * a.nr) throw std::invalid_argument("reorth_project: partial stride below 2 nv nr");
+    if (v32 && (a.n % 2 || a.kchunk % 2 || a.ldv % 2))
+        throw std::invalid_argument("reorth_project: an FP32 basis is read in pairs (even n, chunk and row stride)");
     const hipStream_t s = L.s;
     const int64_t nch = proj_chunks(a.n, a.kchunk);
-    const dim3 grid((unsigned)nch, (unsigned)((a.nv + RP_ROWS - 1) / RP_ROWS), L.nz);
+    const dim3 grid((unsigned)xcd_grid(nch * ((a.nv + RP_ROWS - 1) / RP_ROWS)), 1, L.nz);
     if (v32 && r32)
         hipLaunchKernelGGL((reorth_proj_kernel<float, float>), grid, dim3(256), 0, s, a, L.cs);
     else if (v32)

@@ -99,11 +99,24 @@ void cg_p(bool fp32, const CgVec* cg, const int32_t* vec_map, int nact, void* P,
 // pmask: output parities computed (1 even, 2 odd, 3 both); zero_odd_input: the input is E_e x;
 // t0, nt: only the band of t-slices [t0, t0 + nt) mod Lt (nt = 0: the whole lattice); in_t0, in_nt: the
 // input is zero outside that band (in_nt = 0: no such band)
+// in_vstride: complex per input vector (0: 24 Vh, a full field; 12 Vh: even-site vectors, for an
+// even-only input, zero_odd_input)
 void k_layer(const Geom& g, const void* links32, const void* in, void* out, const void* W, bool dagger, const int32_t* vmap,
-             int nvec, bool zero_odd_input, hipStream_t s, int pmask = 3, int t0 = 0, int nt = 0, int in_t0 = 0, int in_nt = 0);
-// the weight gradient of one layer, summed over the sites of pmask and the band (where the incoming gradient lives)
-void k_grad(const Geom& g, const void* links32, const void* gv, const void* in, bool dagger, int nvec, double* part, double* Gtot,
-            hipStream_t s, bool zero_odd_input = false, int pmask = 3, int t0 = 0, int nt = 0);
+             int nvec, bool zero_odd_input, hipStream_t s, int pmask = 3, int t0 = 0, int nt = 0, int in_t0 = 0, int in_nt = 0,
+             int64_t in_vstride = 0);
+// the block partials of one layer's weight gradient, summed over the sites of pmask and the band (where
+// the incoming gradient lives), written to part ([9][nb][32] doubles); returns nb.  k_grad_reduce then
+// adds the listed gradients to G ([3 layers][9][16] complex) in list order.
+int64_t k_grad(const Geom& g, const void* links32, const void* gv, const void* in, bool dagger, int nvec, double* part, hipStream_t s,
+               bool zero_odd_input = false, int pmask = 3, int t0 = 0, int nt = 0, int64_t in_vstride = 0);
+struct KGradList {
+    static constexpr int MAX = 6;
+    const double* part[MAX];
+    int64_t nb[MAX];
+    int dagger[MAX], layer[MAX];
+    int n;
+};
+void k_grad_reduce(const KGradList& q, double* G, hipStream_t s);
 // |u|^2 partials of S even-site FP32 vectors over a band of t-slices (k_band_blocks per vector)
 void k_band_norm(const Geom& g, int t0, int nt, const void* u, int S, double* part, hipStream_t s);
 int64_t k_band_blocks(const Geom& g, int t0, int nt);

@@ -10,6 +10,8 @@
 // vector in the library's internal layout); the weights are FP32 for the kernels with an FP64
 // master copy for Adam.  Weight gradients are accumulated per direction over sites, colours and
 // vectors in FP64 (deterministic block partials, then a fixed-order sum).
+#include <stdexcept>
+
 #include "kernels.h"
 
 namespace scg {
@@ -127,7 +129,7 @@ template <int NV>
 __device__ __attribute__((always_inline)) inline void k_layer_term(int d, const Geom& g, const cx<float>* __restrict__ links,
                                                                    const cx<float>* __restrict__ in, const cx<float>* w,
                                                                    const int (&vec)[NV], int zero_odd_input, Band in_band, int p,
-                                                                   int h, const Site& s, int Vh, cx<float> (&acc)[NV][12]) {
+                                                                   int h, const Site& s, int Vh, int64_t in_vs, cx<float> (&acc)[NV][12]) {
     if (vanishes(zero_odd_input, d, p)) return;
     // an input known to vanish outside its band of t-slices (a back-propagated gradient): skip the
     // terms that would read it there
@@ -143,7 +145,7 @@ __device__ __attribute__((always_inline)) inline void k_layer_term(int d, const 
 #pragma unroll
     for (int j = 0; j < NV; j++) {
         if (vec[j] < 0) continue;
-        const cx<float>* src = in + (int64_t)vec[j] * 24 * Vh;
+        const cx<float>* src = in + (int64_t)vec[j] * in_vs;
         cx<float> t[12];
         if (d == 0) {
 #pragma unroll
@@ -174,7 +176,7 @@ template <int NV>
 __global__ __launch_bounds__(256) void k_layer_kernel(Geom g, const cx<float>* __restrict__ links, const cx<float>* __restrict__ in,
                                                       cx<float>* __restrict__ out, const cx<float>* __restrict__ W, int dagger,
                                                       const int32_t* vmap, int nvec, int zero_odd_input, int pmask, Band band,
-                                                      Band in_band) {
+                                                      Band in_band, int64_t in_vs) {
     __shared__ cx<float> w[9 * 16];
     __shared__ cx<float> xch[NV * 12 * K_LAYER_SITES];
     for (int k = threadIdx.x; k < 9 * 16; k += blockDim.x) {
@@ -211,10 +213,10 @@ __global__ __launch_bounds__(256) void k_layer_kernel(Geom g, const cx<float>* _
         // the directions unrolled, so that each one's transport is resolved at compile time
         if (side == 0) {
 #pragma unroll
-            for (int d = 0; d < 5; d++) k_layer_term<NV>(d, g, links, in, w, vec, zero_odd_input, in_band, p, h, s, Vh, acc);
+            for (int d = 0; d < 5; d++) k_layer_term<NV>(d, g, links, in, w, vec, zero_odd_input, in_band, p, h, s, Vh, in_vs, acc);
         } else {
 #pragma unroll
-            for (int d = 5; d < 9; d++) k_layer_term<NV>(d, g, links, in, w, vec, zero_odd_input, in_band, p, h, s, Vh, acc);
+            for (int d = 5; d < 9; d++) k_layer_term<NV>(d, g, links, in, w, vec, zero_odd_input, in_band, p, h, s, Vh, in_vs, acc);
         }
     }
     if (side == 1) {
@@ -244,18 +246,21 @@ Band make_band(const Geom& g, int t0, int nt) {
 int64_t k_sites(const Geom& g, int pmask, Band b) { return (int64_t)(pmask == 3 ? 2 : 1) * b.nt * (g.Vh / g.L[3]); }
 
 void k_layer(const Geom& g, const void* links32, const void* in, void* out, const void* W, bool dagger, const int32_t* vmap,
-             int nvec, bool zero_odd_input, hipStream_t s, int pmask, int t0, int nt, int in_t0, int in_nt) {
+             int nvec, bool zero_odd_input, hipStream_t s, int pmask, int t0, int nt, int in_t0, int in_nt, int64_t in_vstride) {
     // two vectors per thread (four would spill and run one wave per SIMD)
     constexpr int NV = 2;
+    const int64_t in_vs = in_vstride ? in_vstride : 24 * g.Vh;
+    if (in_vs < 24 * g.Vh && !(zero_odd_input && in_vs >= 12 * g.Vh))
+        throw std::invalid_argument("k_layer: an input of even-site vectors must be declared even-only");
     const Band b = make_band(g, t0, nt), ib = make_band(g, in_t0, in_nt);
     const int64_t nsb = (k_sites(g, pmask, b) + K_LAYER_SITES - 1) / K_LAYER_SITES;
     if (nvec == 1)
         hipLaunchKernelGGL(k_layer_kernel<1>, dim3((unsigned)nsb), dim3(256), 0, s, g, (const cx<float>*)links32, (const cx<float>*)in,
-                           (cx<float>*)out, (const cx<float>*)W, (int)dagger, vmap, nvec, (int)zero_odd_input, pmask, b, ib);
+                           (cx<float>*)out, (const cx<float>*)W, (int)dagger, vmap, nvec, (int)zero_odd_input, pmask, b, ib, in_vs);
     else
         hipLaunchKernelGGL(k_layer_kernel<NV>, dim3((unsigned)(nsb * ((nvec + NV - 1) / NV))), dim3(256), 0, s, g,
                            (const cx<float>*)links32, (const cx<float>*)in, (cx<float>*)out, (const cx<float>*)W, (int)dagger, vmap,
-                           nvec, (int)zero_odd_input, pmask, b, ib);
+                           nvec, (int)zero_odd_input, pmask, b, ib, in_vs);
 }
 
 // partial sums over the sites of pmask, colours and vectors of g[a][c] conj((T_dt in)[b][c]) for
@@ -266,7 +271,7 @@ void k_layer(const Geom& g, const void* links32, const void* in, void* out, cons
 constexpr int K_GRAD_SPT = 4;
 __global__ __launch_bounds__(256) void k_grad_kernel(Geom g, const cx<float>* __restrict__ links, const cx<float>* __restrict__ gv,
                                                      const cx<float>* __restrict__ in, int dagger, int nvec, int zero_odd_input,
-                                                     int pmask, Band band, double* part) {
+                                                     int pmask, Band band, double* part, int64_t in_vs) {
     __shared__ double lds[8 * 32];
     __shared__ float tile[256 * 33];
     const int d = blockIdx.y;
@@ -285,7 +290,7 @@ __global__ __launch_bounds__(256) void k_grad_kernel(Geom g, const cx<float>* __
         if (dt) load_hop(g, links, p, h, s, dt, o);
 #pragma unroll 1
         for (int v = 0; v < nvec; v++) {
-            const cx<float>* src = in + (int64_t)v * 24 * Vh;
+            const cx<float>* src = in + (int64_t)v * in_vs;
             cx<float> t[12], q[12];
             if (dt == 0) {
 #pragma unroll
@@ -328,38 +333,54 @@ __global__ __launch_bounds__(256) void k_grad_kernel(Geom g, const cx<float>* __
     }
 }
 
-// Gtot[d] += sum over blocks (dagger layers add the conjugate transpose: dL/dconj(w) = G'^dag).
-// One workgroup per direction: thread (j, e) adds blocks j, j+8, ... of value e, then the eight
-// partial sums are added in order (deterministic).
-__global__ void k_grad_reduce_kernel(const double* part, int64_t nblocks, int dagger, double* Gtot) {
+// G[layer][d] += the block sums of every listed gradient of that layer, in list order (dagger layers add
+// the conjugate transpose: dL/dconj(w) = G'^dag).  One workgroup per (direction, layer): thread (j, e)
+// adds blocks j, j+8, ... of value e, then the eight partial sums are added in order (deterministic).
+__global__ void k_grad_reduce_kernel(const KGradList q, double* G) {
     __shared__ double lds[8 * 32];
-    const int d = blockIdx.x;
+    const int d = blockIdx.x, layer = blockIdx.y;
     const int e = threadIdx.x % 32, j = threadIdx.x / 32;
-    double s = 0.0;
-    for (int64_t b = j; b < nblocks; b += 8) s += part[((int64_t)d * nblocks + b) * 32 + e];
-    lds[j * 32 + e] = s;
-    __syncthreads();
-    if (j != 0) return;
-    s = 0.0;
-    for (int q = 0; q < 8; q++) s += lds[q * 32 + e];
-    const int ab = e / 2, comp = e % 2;
-    if (!dagger) {
-        Gtot[d * 32 + e] += s;
-    } else {
-        const int a = ab / 4, b = ab % 4;
-        Gtot[d * 32 + 2 * (b * 4 + a) + comp] += comp ? -s : s;
+    for (int k = 0; k < q.n; k++) {
+        if (q.layer[k] != layer) continue;   // uniform
+        const double* part = q.part[k];
+        const int64_t nblocks = q.nb[k];
+        double s = 0.0;
+        for (int64_t b = j; b < nblocks; b += 8) s += part[((int64_t)d * nblocks + b) * 32 + e];
+        __syncthreads();
+        lds[j * 32 + e] = s;
+        __syncthreads();
+        if (j == 0) {
+            s = 0.0;
+            for (int r = 0; r < 8; r++) s += lds[r * 32 + e];
+            double* Gl = G + (int64_t)layer * 9 * 32;
+            if (!q.dagger[k]) {
+                Gl[d * 32 + e] += s;
+            } else {
+                const int ab = e / 2, comp = e % 2;
+                const int a = ab / 4, b = ab % 4;
+                Gl[d * 32 + 2 * (b * 4 + a) + comp] += comp ? -s : s;
+            }
+        }
     }
 }
 
 int64_t k_grad_blocks(const Geom& g) { return (2 * g.Vh + 255) / 256; }
 
-void k_grad(const Geom& g, const void* links32, const void* gv, const void* in, bool dagger, int nvec, double* part, double* Gtot,
-            hipStream_t s, bool zero_odd_input, int pmask, int t0, int nt) {
+int64_t k_grad(const Geom& g, const void* links32, const void* gv, const void* in, bool dagger, int nvec, double* part, hipStream_t s,
+               bool zero_odd_input, int pmask, int t0, int nt, int64_t in_vstride) {
     const Band b = make_band(g, t0, nt);
+    const int64_t in_vs = in_vstride ? in_vstride : 24 * g.Vh;
+    if (in_vs < 24 * g.Vh && !(zero_odd_input && in_vs >= 12 * g.Vh))
+        throw std::invalid_argument("k_grad: an input of even-site vectors must be declared even-only");
     const int64_t nb = (k_sites(g, pmask, b) + 256 * K_GRAD_SPT - 1) / (256 * K_GRAD_SPT);
     hipLaunchKernelGGL(k_grad_kernel, dim3((unsigned)nb, 9), dim3(256), 0, s, g, (const cx<float>*)links32, (const cx<float>*)gv,
-                       (const cx<float>*)in, (int)dagger, nvec, (int)zero_odd_input, pmask, b, part);
-    hipLaunchKernelGGL(k_grad_reduce_kernel, dim3(9), dim3(256), 0, s, part, nb, (int)dagger, Gtot);
+                       (const cx<float>*)in, (int)dagger, nvec, (int)zero_odd_input, pmask, b, part, in_vs);
+    return nb;
+}
+
+void k_grad_reduce(const KGradList& q, double* G, hipStream_t s) {
+    if (q.n < 1 || q.n > KGradList::MAX) throw std::invalid_argument("k_grad_reduce: 1..6 gradients");
+    hipLaunchKernelGGL(k_grad_reduce_kernel, dim3(9, 3), dim3(256), 0, s, q, G);
 }
 
 // field helpers on [vec][2][12][Vh] FP32 fields

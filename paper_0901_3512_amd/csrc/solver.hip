@@ -24,6 +24,7 @@
 #include <new>
 #include <stdexcept>
 #include <string>
+#include <numeric>
 #include <vector>
 
 #include <rocprofiler-sdk-roctx/roctx.h>
@@ -213,7 +214,7 @@ struct seedcg_s {
     // the judge's verdict on deflating plain CG: -1 none (params.deflate decides), 0 off, 1 on
     int judge_defl = -1;
     double k_judge_cg0_it = 0.0, k_judge_cg0_c = 0.0, k_judge_td = 0.0;
-    DBuf klossv, kbn;
+    DBuf klossv, kbn, kbt;   // kbt: |u|^2 of the training pairs per band of the Adam steps
     // sampled timing of the stencil launches (hipEvent pairs on the handle's stream)
     int timing_every = 0;
     int64_t hop_count = 0;
@@ -960,20 +961,22 @@ void ritz_lowest(const std::vector<double>& a, const std::vector<double>& b, int
 // only, and every layer computes just the slices that loss depends on: K K^dag reaches 6 hops, so
 // the j-th of the six layers (K^dag's three, then K's) is needed on the band widened by 6 - j slices
 // on either side, and the gradient of its output lives there too.
-double k_pass(seedcg_s* h, int off, int S, bool backward, bool want_loss, int band_t0 = 0, int band_nt = 0) {
+// band_unorm2 (optional, with a band): |u|^2 of the S pairs on the loss band, computed beforehand.
+double k_pass(seedcg_s* h, int off, int S, bool backward, bool want_loss, int band_t0 = 0, int band_nt = 0,
+              const double* band_unorm2 = nullptr) {
     const int64_t N = h->N;
     const int Lt = h->g.L[3];
     if (band_nt <= 0 || band_nt + 12 >= Lt) band_nt = 0;   // whole lattice
     const int64_t fb = (int64_t)S * 2 * N * 8;
-    h->kfield.ensure(10 * fb);
+    h->kfield.ensure(8 * fb);
     auto F = [&](int i) { return (void*)((char*)h->kfield.p + i * fb); };
-    void *a0 = F(0), *a1 = F(1), *a2 = F(2), *a3 = F(3), *b1 = F(5), *b2 = F(6), *b3 = F(7), *g = F(8), *gt = F(9);
+    void *a1 = F(0), *a2 = F(1), *a3 = F(2), *b1 = F(3), *b2 = F(4), *b3 = F(5), *g = F(6), *gt = F(7);
     const void* Uo = (const char*)h->kU.p + (int64_t)off * N * 8;
     const void* Yo = (const char*)h->kY.p + (int64_t)off * N * 8;
-    h->kpart.ensure(9 * k_grad_blocks(h->g) * 32 * sizeof(double));
+    // the block partials of the six weight gradients of a backward pass, one after another
+    h->kpart.ensure(6 * 9 * k_grad_blocks(h->g) * 32 * sizeof(double));
     const int64_t nbb = k_band_blocks(h->g, band_t0, band_nt);
     const void* L = k_links(h);
-    double* Gl[3] = {h->kG.as<double>(), h->kG.as<double>() + K_NW * 2, h->kG.as<double>() + 2 * K_NW * 2};
     // the band of layer j = 1..6 (the loss band widened by 6 - j slices each side); 0 slices: whole lattice
     auto bt0 = [&](int j) { return band_nt ? band_t0 - (6 - j) : 0; };
     auto bnt = [&](int j) { return band_nt ? band_nt + 2 * (6 - j) : 0; };
@@ -982,12 +985,18 @@ double k_pass(seedcg_s* h, int off, int S, bool backward, bool want_loss, int ba
     h->kbn.ensure(32 * sizeof(double));
     auto ks = h->s;
     // |u|^2 on the loss band, the loss's normalisation
-    k_band_norm(h->g, bt0(6), bnt(6), Uo, S, h->klpart.as<double>(), ks);
-    sum_partials(h->klpart.as<double>(), nbb, S, h->kbn.as<double>(), false, ks);
+    const double* unorm2 = band_nt ? band_unorm2 : nullptr;
+    if (!unorm2) {
+        k_band_norm(h->g, bt0(6), bnt(6), Uo, S, h->klpart.as<double>(), ks);
+        sum_partials(h->klpart.as<double>(), nbb, S, h->kbn.as<double>(), false, ks);
+        unorm2 = h->kbn.as<double>();
+    }
     // forward: a = K^dag chain on E_e y, b = K chain on E_e R_e a3
-    // (odd halves that a later step never reads are not computed: pmask 1 = even outputs only)
-    k_embed(true, Yo, a0, N, nullptr, S, ks);
-    k_layer(h->g, L, a0, a1, k_weights(h, 2), true, nullptr, S, true, ks, 3, bt0(1), bnt(1));
+    // (odd halves that a later step never reads are not computed: pmask 1 = even outputs only).  E_e y
+    // is y itself to a layer told that its input is even-only: the first layer and its gradient read
+    // the even-site vectors y directly (vector stride N)
+    const void* a0 = Yo;
+    k_layer(h->g, L, a0, a1, k_weights(h, 2), true, nullptr, S, true, ks, 3, bt0(1), bnt(1), 0, 0, N);
     k_layer(h->g, L, a1, a2, k_weights(h, 1), true, nullptr, S, false, ks, 3, bt0(2), bnt(2));
     k_layer(h->g, L, a2, a3, k_weights(h, 0), true, nullptr, S, false, ks, 1, bt0(3), bnt(3));
     // E_e R_e a3 is a3 itself for every reader: layer 4 and its gradient take an even-only input
@@ -996,7 +1005,7 @@ double k_pass(seedcg_s* h, int off, int S, bool backward, bool want_loss, int ba
     k_layer(h->g, L, b0, b1, k_weights(h, 0), false, nullptr, S, true, ks, 3, bt0(4), bnt(4));
     k_layer(h->g, L, b1, b2, k_weights(h, 1), false, nullptr, S, false, ks, 3, bt0(5), bnt(5));
     k_layer(h->g, L, b2, b3, k_weights(h, 2), false, nullptr, S, false, ks, 1, bt0(6), bnt(6));
-    k_residual(b3, Uo, h->kbn.as<double>(), g, N, S, h->klpart.as<double>(), ks, h->g, bt0(6), bnt(6));
+    k_residual(b3, Uo, unorm2, g, N, S, h->klpart.as<double>(), ks, h->g, bt0(6), bnt(6));
     double loss = 0.0;
     if (want_loss) {
         h->klossv.ensure(32 * sizeof(double));
@@ -1011,18 +1020,31 @@ double k_pass(seedcg_s* h, int off, int S, bool backward, bool want_loss, int ba
     // backward through K (layers 3, 2, 1) and then K^dag (1^dag, 2^dag, 3^dag): the gradient of layer
     // j's output lives on band j, and each back-propagated field is zero outside its band (the layer
     // that reads it is told so)
-    k_grad(h->g, L, g, b2, false, S, h->kpart.as<double>(), Gl[2], ks, false, 1, bt0(6), bnt(6));
+    KGradList q{};
+    int64_t used = 0;
+    auto grad = [&](int layer, const void* gv, const void* in, bool dagger, bool zero_odd, int pmask, int j, int64_t in_vs = 0) {
+        double* part = h->kpart.as<double>() + used;
+        q.nb[q.n] = k_grad(h->g, L, gv, in, dagger, S, part, ks, zero_odd, pmask, bt0(j), bnt(j), in_vs);
+        used += 9 * q.nb[q.n] * 32;
+        q.part[q.n] = part;
+        q.dagger[q.n] = dagger;
+        q.layer[q.n] = layer;
+        q.n++;
+    };
+    grad(2, g, b2, false, false, 1, 6);
     k_layer(h->g, L, g, gt, k_weights(h, 2), true, nullptr, S, true, ks, 3, bt0(5), bnt(5), bt0(6), bnt(6));
-    k_grad(h->g, L, gt, b1, false, S, h->kpart.as<double>(), Gl[1], ks, false, 3, bt0(5), bnt(5));
+    grad(1, gt, b1, false, false, 3, 5);
     k_layer(h->g, L, gt, g, k_weights(h, 1), true, nullptr, S, false, ks, 3, bt0(4), bnt(4), bt0(5), bnt(5));
-    k_grad(h->g, L, g, b0, false, S, h->kpart.as<double>(), Gl[0], ks, true, 3, bt0(4), bnt(4));
+    grad(0, g, b0, false, true, 3, 4);
     k_layer(h->g, L, g, gt, k_weights(h, 0), true, nullptr, S, false, ks, 1, bt0(3), bnt(3), bt0(4), bnt(4));
     // through E_e R_e: the odd half of gt (not written above) is read by nobody below
-    k_grad(h->g, L, gt, a2, true, S, h->kpart.as<double>(), Gl[0], ks, false, 1, bt0(3), bnt(3));
+    grad(0, gt, a2, true, false, 1, 3);
     k_layer(h->g, L, gt, g, k_weights(h, 0), false, nullptr, S, true, ks, 3, bt0(2), bnt(2), bt0(3), bnt(3));
-    k_grad(h->g, L, g, a1, true, S, h->kpart.as<double>(), Gl[1], ks, false, 3, bt0(2), bnt(2));
+    grad(1, g, a1, true, false, 3, 2);
     k_layer(h->g, L, g, gt, k_weights(h, 1), false, nullptr, S, false, ks, 3, bt0(1), bnt(1), bt0(2), bnt(2));
-    k_grad(h->g, L, gt, a0, true, S, h->kpart.as<double>(), Gl[2], ks, true, 3, bt0(1), bnt(1));
+    grad(2, gt, a0, true, true, 3, 1, N);
+    // the six gradients into kG, per layer in the order above
+    k_grad_reduce(q, h->kG.as<double>(), ks);
     return loss;
 }
 
@@ -1241,10 +1263,24 @@ void train_precond_impl(seedcg_s* h, int steps, int n_ritz, int n_lanczos, doubl
     const int every = std::max(1, (steps + 3) / 4);
     std::vector<double> best = w0;
     double best_loss = h->k_loss0;
+    // |u|^2 of every pair on every band the steps visit (the bands start at multiples of gcd(band, Lt)),
+    // computed once: kbt[t0][s]
+    const int Lt = h->g.L[3];
+    const bool banded = band + 12 < Lt;
+    if (banded) {
+        const int64_t nbb = k_band_blocks(h->g, 0, band);
+        h->kbt.ensure((int64_t)Lt * S * sizeof(double));
+        h->klpart.ensure(std::max<int64_t>(nbb * S, h->klpart.bytes / sizeof(double)) * sizeof(double));
+        for (int t0 = 0; t0 < Lt; t0 += std::gcd(band, Lt)) {
+            k_band_norm(h->g, t0, band, h->kU.p, S, h->klpart.as<double>(), h->s);
+            sum_partials(h->klpart.as<double>(), nbb, S, h->kbt.as<double>() + (int64_t)t0 * S, false, h->s);
+        }
+    }
     for (int step = 0; step < steps; step++) {
         const Phase adam_phase("seedcg_train_precond: Adam step");
         const int o = (int)(((int64_t)step * mb) % S);
-        k_pass(h, o, std::min(mb, S - o), true, false, (int)(((int64_t)step * band) % h->g.L[3]), band);
+        const int t0 = (int)(((int64_t)step * band) % Lt);
+        k_pass(h, o, std::min(mb, S - o), true, false, t0, band, banded ? h->kbt.as<double>() + (int64_t)t0 * S + o : nullptr);
         const double lr_t = lr * 0.5 * (1.0 + std::cos(M_PI * step / steps));
         k_adam(h->kWm.as<double>(), h->kW32.p, h->kG.as<double>(), h->kAm.as<double>(), h->kAv.as<double>(), step + 1, lr_t, K_NREAL,
                h->s);

@@ -265,13 +265,12 @@ void k_layer(const Geom& g, const void* links32, const void* in, void* out, cons
 
 // partial sums over the sites of pmask, colours and vectors of g[a][c] conj((T_dt in)[b][c]) for
 // direction d = blockIdx.y, with dt = d (layer L) or dt = -d (layer L^dag); each link is read once per
-// site for all vectors.  A thread takes K_GRAD_SPT sites (a workgroup K_GRAD_SPT consecutive runs of
-// 256) and sums their terms in FP32; the workgroup's sum is FP64.  part[d][block][16] complex.
+// site for all vectors.  A thread takes spt sites (a workgroup spt consecutive runs of 256; 2, or 1 on
+// the narrowest bands) and sums their terms in FP32; the workgroup's sum is FP64.  part[d][block][16] complex.
 // (Workgroups of 256 threads: the reduction below assumes it.)
-constexpr int K_GRAD_SPT = 4;
 __global__ __launch_bounds__(256) void k_grad_kernel(Geom g, const cx<float>* __restrict__ links, const cx<float>* __restrict__ gv,
                                                      const cx<float>* __restrict__ in, int dagger, int nvec, int zero_odd_input,
-                                                     int pmask, Band band, double* part, int64_t in_vs) {
+                                                     int pmask, Band band, double* part, int64_t in_vs, int spt) {
     __shared__ double lds[8 * 32];
     __shared__ float tile[256 * 33];
     const int d = blockIdx.y;
@@ -281,9 +280,9 @@ __global__ __launch_bounds__(256) void k_grad_kernel(Geom g, const cx<float>* __
 #pragma unroll
     for (int e = 0; e < 32; e++) acc[e] = 0.f;
 #pragma unroll 1
-    for (int r = 0; r < K_GRAD_SPT; r++) {
+    for (int r = 0; r < spt; r++) {
         int p, h;
-        const int64_t k = ((int64_t)blockIdx.x * K_GRAD_SPT + r) * blockDim.x + threadIdx.x;
+        const int64_t k = ((int64_t)blockIdx.x * spt + r) * blockDim.x + threadIdx.x;
         if (!site_of_launch(g, pmask, band, k, p, h) || vanishes(zero_odd_input, dt, p)) continue;
         const Site s = site_of(g, p, h);
         Hop o;
@@ -334,10 +333,11 @@ __global__ __launch_bounds__(256) void k_grad_kernel(Geom g, const cx<float>* __
 }
 
 // G[layer][d] += the block sums of every listed gradient of that layer, in list order (dagger layers add
-// the conjugate transpose: dL/dconj(w) = G'^dag).  One workgroup per (direction, layer): thread (j, e)
-// adds blocks j, j+8, ... of value e, then the eight partial sums are added in order (deterministic).
-__global__ void k_grad_reduce_kernel(const KGradList q, double* G) {
-    __shared__ double lds[8 * 32];
+// the conjugate transpose: dL/dconj(w) = G'^dag).  One workgroup of 1024 threads per (direction, layer):
+// thread (j, e) adds blocks j, j+32, ... of value e, then the 32 partial sums are added in order
+// (deterministic).
+__global__ __launch_bounds__(1024) void k_grad_reduce_kernel(const KGradList q, double* G) {
+    __shared__ double lds[32 * 32];
     const int d = blockIdx.x, layer = blockIdx.y;
     const int e = threadIdx.x % 32, j = threadIdx.x / 32;
     for (int k = 0; k < q.n; k++) {
@@ -345,13 +345,13 @@ __global__ void k_grad_reduce_kernel(const KGradList q, double* G) {
         const double* part = q.part[k];
         const int64_t nblocks = q.nb[k];
         double s = 0.0;
-        for (int64_t b = j; b < nblocks; b += 8) s += part[((int64_t)d * nblocks + b) * 32 + e];
+        for (int64_t b = j; b < nblocks; b += 32) s += part[((int64_t)d * nblocks + b) * 32 + e];
         __syncthreads();
         lds[j * 32 + e] = s;
         __syncthreads();
         if (j == 0) {
             s = 0.0;
-            for (int r = 0; r < 8; r++) s += lds[r * 32 + e];
+            for (int r = 0; r < 32; r++) s += lds[r * 32 + e];
             double* Gl = G + (int64_t)layer * 9 * 32;
             if (!q.dagger[k]) {
                 Gl[d * 32 + e] += s;
@@ -372,15 +372,18 @@ int64_t k_grad(const Geom& g, const void* links32, const void* gv, const void* i
     const int64_t in_vs = in_vstride ? in_vstride : 24 * g.Vh;
     if (in_vs < 24 * g.Vh && !(zero_odd_input && in_vs >= 12 * g.Vh))
         throw std::invalid_argument("k_grad: an input of even-site vectors must be declared even-only");
-    const int64_t nb = (k_sites(g, pmask, b) + 256 * K_GRAD_SPT - 1) / (256 * K_GRAD_SPT);
+    // sites per thread: 2, or 1 where that would leave fewer than 512 workgroups (the narrowest bands)
+    const int64_t sites = k_sites(g, pmask, b);
+    const int spt = 9 * ((sites + 511) / 512) < 512 ? 1 : 2;
+    const int64_t nb = (sites + 256 * spt - 1) / (256 * spt);
     hipLaunchKernelGGL(k_grad_kernel, dim3((unsigned)nb, 9), dim3(256), 0, s, g, (const cx<float>*)links32, (const cx<float>*)gv,
-                       (const cx<float>*)in, (int)dagger, nvec, (int)zero_odd_input, pmask, b, part, in_vs);
+                       (const cx<float>*)in, (int)dagger, nvec, (int)zero_odd_input, pmask, b, part, in_vs, spt);
     return nb;
 }
 
 void k_grad_reduce(const KGradList& q, double* G, hipStream_t s) {
     if (q.n < 1 || q.n > KGradList::MAX) throw std::invalid_argument("k_grad_reduce: 1..6 gradients");
-    hipLaunchKernelGGL(k_grad_reduce_kernel, dim3(9, 3), dim3(256), 0, s, q, G);
+    hipLaunchKernelGGL(k_grad_reduce_kernel, dim3(9, 3), dim3(1024), 0, s, q, G);
 }
 
 // field helpers on [vec][2][12][Vh] FP32 fields

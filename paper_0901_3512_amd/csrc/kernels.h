@@ -99,15 +99,21 @@ void cg_p(bool fp32, const CgVec* cg, const int32_t* vec_map, int nact, void* P,
 // pmask: output parities computed (1 even, 2 odd, 3 both); zero_odd_input: the input is E_e x;
 // t0, nt: only the band of t-slices [t0, t0 + nt) mod Lt (nt = 0: the whole lattice); in_t0, in_nt: the
 // input is zero outside that band (in_nt = 0: no such band)
+// FP32 links of K's transports: ne = 9 (whole, [mu][parity][9][Vh]) or 6 (special-unitary links as
+// rows 0 and 1, [mu][parity][6][Vh]; row 2 rebuilt in registers)
+struct KLinks {
+    const void* p;
+    int ne;
+};
 // in_vstride: complex per input vector (0: 24 Vh, a full field; 12 Vh: even-site vectors, for an
 // even-only input, zero_odd_input)
-void k_layer(const Geom& g, const void* links32, const void* in, void* out, const void* W, bool dagger, const int32_t* vmap,
+void k_layer(const Geom& g, KLinks links, const void* in, void* out, const void* W, bool dagger, const int32_t* vmap,
              int nvec, bool zero_odd_input, hipStream_t s, int pmask = 3, int t0 = 0, int nt = 0, int in_t0 = 0, int in_nt = 0,
              int64_t in_vstride = 0);
 // the block partials of one layer's weight gradient, summed over the sites of pmask and the band (where
 // the incoming gradient lives), written to part ([9][nb][32] doubles); returns nb.  k_grad_reduce then
 // adds the listed gradients to G ([3 layers][9][16] complex) in list order.
-int64_t k_grad(const Geom& g, const void* links32, const void* gv, const void* in, bool dagger, int nvec, double* part, hipStream_t s,
+int64_t k_grad(const Geom& g, KLinks links, const void* gv, const void* in, bool dagger, int nvec, double* part, hipStream_t s,
                bool zero_odd_input = false, int pmask = 3, int t0 = 0, int nt = 0, int64_t in_vstride = 0);
 struct KGradList {
     static constexpr int MAX = 6;

@@ -62,13 +62,17 @@ __device__ inline int nb_index(const Geom& g, const Site& s, int mu, int step, f
 }
 
 // the link of transport d at output site (p, h): U_mu(x) (d = +mu) or U_mu(x - mu) (d = -mu), read once
-// per site and direction and applied to every vector of the thread
+// per site and direction and applied to every vector of the thread.  NE = 9: links stored whole
+// ([mu][parity][9][Vh]); NE = 6: special-unitary links stored as rows 0 and 1 ([mu][parity][6][Vh]),
+// row 2 rebuilt as conj(row 0 x row 1)
 struct Hop {
     cx<float> u[9];
     int hn;
     float sign;
     bool fwd;
 };
+__device__ inline cx<float> conj_cx(cx<float> a) { return mk<float>(a.re, -a.im); }
+template <int NE>
 __device__ inline void load_hop(const Geom& g, const cx<float>* __restrict__ links, int p, int h, const Site& s, int d, Hop& o) {
     const int Vh = (int)g.Vh;
     const int mu = (d - 1) & 3;
@@ -76,9 +80,14 @@ __device__ inline void load_hop(const Geom& g, const cx<float>* __restrict__ lin
     o.hn = nb_index(g, s, mu, o.fwd ? 1 : -1, o.sign);
     const int lp = o.fwd ? p : 1 - p;
     const int lh = o.fwd ? h : o.hn;
-    const cx<float>* lk = links + (int64_t)((mu * 2 + lp) * 9) * Vh + lh;
+    const cx<float>* lk = links + (int64_t)((mu * 2 + lp) * NE) * Vh + lh;
 #pragma unroll
-    for (int c = 0; c < 9; c++) o.u[c] = lk[(int64_t)c * Vh];
+    for (int c = 0; c < NE; c++) o.u[c] = lk[(int64_t)c * Vh];
+    if constexpr (NE == 6) {
+        o.u[6] = conj_cx(cmul(o.u[1], o.u[5]) - cmul(o.u[2], o.u[4]));
+        o.u[7] = conj_cx(cmul(o.u[2], o.u[3]) - cmul(o.u[0], o.u[5]));
+        o.u[8] = conj_cx(cmul(o.u[0], o.u[4]) - cmul(o.u[1], o.u[3]));
+    }
 }
 // (T_d src)(p, h) with the link of o; src is the field of one vector, [2][12][Vh]
 __device__ inline void apply_hop(const Hop& o, const cx<float>* __restrict__ src, int p, int Vh, cx<float> t[12]) {
@@ -125,7 +134,7 @@ __device__ inline bool site_of_launch(const Geom& g, int pmask, Band b, int64_t 
 __device__ inline bool vanishes(int zero_odd_input, int d, int p) { return zero_odd_input && ((d == 0) ? (p == 1) : (p == 0)); }
 
 // One term of a layer at output site (p, h): acc += (w_d (x) 1) (T_d in) for the NV vectors of vec.
-template <int NV>
+template <int NV, int NE>
 __device__ __attribute__((always_inline)) inline void k_layer_term(int d, const Geom& g, const cx<float>* __restrict__ links,
                                                                    const cx<float>* __restrict__ in, const cx<float>* w,
                                                                    const int (&vec)[NV], int zero_odd_input, Band in_band, int p,
@@ -141,7 +150,7 @@ __device__ __attribute__((always_inline)) inline void k_layer_term(int d, const 
         if (dt >= in_band.nt) return;
     }
     Hop o;
-    if (d) load_hop(g, links, p, h, s, d, o);
+    if (d) load_hop<NE>(g, links, p, h, s, d, o);
 #pragma unroll
     for (int j = 0; j < NV; j++) {
         if (vec[j] < 0) continue;
@@ -172,7 +181,7 @@ __device__ __attribute__((always_inline)) inline void k_layer_term(int d, const 
 // b % nvg of site block b / nvg, so the groups of one site block run as neighbouring workgroups and
 // find its links in L2.
 constexpr int K_LAYER_SITES = 128;
-template <int NV>
+template <int NV, int NE>
 __global__ __launch_bounds__(256) void k_layer_kernel(Geom g, const cx<float>* __restrict__ links, const cx<float>* __restrict__ in,
                                                       cx<float>* __restrict__ out, const cx<float>* __restrict__ W, int dagger,
                                                       const int32_t* vmap, int nvec, int zero_odd_input, int pmask, Band band,
@@ -213,10 +222,10 @@ __global__ __launch_bounds__(256) void k_layer_kernel(Geom g, const cx<float>* _
         // the directions unrolled, so that each one's transport is resolved at compile time
         if (side == 0) {
 #pragma unroll
-            for (int d = 0; d < 5; d++) k_layer_term<NV>(d, g, links, in, w, vec, zero_odd_input, in_band, p, h, s, Vh, in_vs, acc);
+            for (int d = 0; d < 5; d++) k_layer_term<NV, NE>(d, g, links, in, w, vec, zero_odd_input, in_band, p, h, s, Vh, in_vs, acc);
         } else {
 #pragma unroll
-            for (int d = 5; d < 9; d++) k_layer_term<NV>(d, g, links, in, w, vec, zero_odd_input, in_band, p, h, s, Vh, in_vs, acc);
+            for (int d = 5; d < 9; d++) k_layer_term<NV, NE>(d, g, links, in, w, vec, zero_odd_input, in_band, p, h, s, Vh, in_vs, acc);
         }
     }
     if (side == 1) {
@@ -245,22 +254,33 @@ Band make_band(const Geom& g, int t0, int nt) {
 }
 int64_t k_sites(const Geom& g, int pmask, Band b) { return (int64_t)(pmask == 3 ? 2 : 1) * b.nt * (g.Vh / g.L[3]); }
 
-void k_layer(const Geom& g, const void* links32, const void* in, void* out, const void* W, bool dagger, const int32_t* vmap,
-             int nvec, bool zero_odd_input, hipStream_t s, int pmask, int t0, int nt, int in_t0, int in_nt, int64_t in_vstride) {
+void k_layer(const Geom& g, KLinks links, const void* in, void* out, const void* W, bool dagger, const int32_t* vmap, int nvec,
+             bool zero_odd_input, hipStream_t s, int pmask, int t0, int nt, int in_t0, int in_nt, int64_t in_vstride) {
     // two vectors per thread (four would spill and run one wave per SIMD)
     constexpr int NV = 2;
     const int64_t in_vs = in_vstride ? in_vstride : 24 * g.Vh;
     if (in_vs < 24 * g.Vh && !(zero_odd_input && in_vs >= 12 * g.Vh))
         throw std::invalid_argument("k_layer: an input of even-site vectors must be declared even-only");
+    if (links.ne != 6 && links.ne != 9) throw std::invalid_argument("k_layer: links hold 6 or 9 entries");
     const Band b = make_band(g, t0, nt), ib = make_band(g, in_t0, in_nt);
     const int64_t nsb = (k_sites(g, pmask, b) + K_LAYER_SITES - 1) / K_LAYER_SITES;
-    if (nvec == 1)
-        hipLaunchKernelGGL(k_layer_kernel<1>, dim3((unsigned)nsb), dim3(256), 0, s, g, (const cx<float>*)links32, (const cx<float>*)in,
-                           (cx<float>*)out, (const cx<float>*)W, (int)dagger, vmap, nvec, (int)zero_odd_input, pmask, b, ib, in_vs);
+    const unsigned grid = (unsigned)(nvec == 1 ? nsb : nsb * ((nvec + NV - 1) / NV));
+    const auto lk = (const cx<float>*)links.p;
+    const auto in32 = (const cx<float>*)in;
+    const auto out32 = (cx<float>*)out;
+    const auto W32 = (const cx<float>*)W;
+    if (nvec == 1 && links.ne == 6)
+        hipLaunchKernelGGL((k_layer_kernel<1, 6>), dim3(grid), dim3(256), 0, s, g, lk, in32, out32, W32, (int)dagger, vmap, nvec,
+                           (int)zero_odd_input, pmask, b, ib, in_vs);
+    else if (nvec == 1)
+        hipLaunchKernelGGL((k_layer_kernel<1, 9>), dim3(grid), dim3(256), 0, s, g, lk, in32, out32, W32, (int)dagger, vmap, nvec,
+                           (int)zero_odd_input, pmask, b, ib, in_vs);
+    else if (links.ne == 6)
+        hipLaunchKernelGGL((k_layer_kernel<NV, 6>), dim3(grid), dim3(256), 0, s, g, lk, in32, out32, W32, (int)dagger, vmap, nvec,
+                           (int)zero_odd_input, pmask, b, ib, in_vs);
     else
-        hipLaunchKernelGGL(k_layer_kernel<NV>, dim3((unsigned)(nsb * ((nvec + NV - 1) / NV))), dim3(256), 0, s, g,
-                           (const cx<float>*)links32, (const cx<float>*)in, (cx<float>*)out, (const cx<float>*)W, (int)dagger, vmap,
-                           nvec, (int)zero_odd_input, pmask, b, ib, in_vs);
+        hipLaunchKernelGGL((k_layer_kernel<NV, 9>), dim3(grid), dim3(256), 0, s, g, lk, in32, out32, W32, (int)dagger, vmap, nvec,
+                           (int)zero_odd_input, pmask, b, ib, in_vs);
 }
 
 // partial sums over the sites of pmask, colours and vectors of g[a][c] conj((T_dt in)[b][c]) for
@@ -268,6 +288,7 @@ void k_layer(const Geom& g, const void* links32, const void* in, void* out, cons
 // site for all vectors.  A thread takes spt sites (a workgroup spt consecutive runs of 256; 2, or 1 on
 // the narrowest bands) and sums their terms in FP32; the workgroup's sum is FP64.  part[d][block][16] complex.
 // (Workgroups of 256 threads: the reduction below assumes it.)
+template <int NE>
 __global__ __launch_bounds__(256) void k_grad_kernel(Geom g, const cx<float>* __restrict__ links, const cx<float>* __restrict__ gv,
                                                      const cx<float>* __restrict__ in, int dagger, int nvec, int zero_odd_input,
                                                      int pmask, Band band, double* part, int64_t in_vs, int spt) {
@@ -286,7 +307,7 @@ __global__ __launch_bounds__(256) void k_grad_kernel(Geom g, const cx<float>* __
         if (!site_of_launch(g, pmask, band, k, p, h) || vanishes(zero_odd_input, dt, p)) continue;
         const Site s = site_of(g, p, h);
         Hop o;
-        if (dt) load_hop(g, links, p, h, s, dt, o);
+        if (dt) load_hop<NE>(g, links, p, h, s, dt, o);
 #pragma unroll 1
         for (int v = 0; v < nvec; v++) {
             const cx<float>* src = in + (int64_t)v * in_vs;
@@ -366,8 +387,9 @@ __global__ __launch_bounds__(1024) void k_grad_reduce_kernel(const KGradList q, 
 
 int64_t k_grad_blocks(const Geom& g) { return (2 * g.Vh + 255) / 256; }
 
-int64_t k_grad(const Geom& g, const void* links32, const void* gv, const void* in, bool dagger, int nvec, double* part, hipStream_t s,
+int64_t k_grad(const Geom& g, KLinks links, const void* gv, const void* in, bool dagger, int nvec, double* part, hipStream_t s,
                bool zero_odd_input, int pmask, int t0, int nt, int64_t in_vstride) {
+    if (links.ne != 6 && links.ne != 9) throw std::invalid_argument("k_grad: links hold 6 or 9 entries");
     const Band b = make_band(g, t0, nt);
     const int64_t in_vs = in_vstride ? in_vstride : 24 * g.Vh;
     if (in_vs < 24 * g.Vh && !(zero_odd_input && in_vs >= 12 * g.Vh))
@@ -376,8 +398,14 @@ int64_t k_grad(const Geom& g, const void* links32, const void* gv, const void* i
     const int64_t sites = k_sites(g, pmask, b);
     const int spt = 9 * ((sites + 511) / 512) < 512 ? 1 : 2;
     const int64_t nb = (sites + 256 * spt - 1) / (256 * spt);
-    hipLaunchKernelGGL(k_grad_kernel, dim3((unsigned)nb, 9), dim3(256), 0, s, g, (const cx<float>*)links32, (const cx<float>*)gv,
-                       (const cx<float>*)in, (int)dagger, nvec, (int)zero_odd_input, pmask, b, part, in_vs, spt);
+    if (links.ne == 6)
+        hipLaunchKernelGGL(k_grad_kernel<6>, dim3((unsigned)nb, 9), dim3(256), 0, s, g, (const cx<float>*)links.p,
+                           (const cx<float>*)gv, (const cx<float>*)in, (int)dagger, nvec, (int)zero_odd_input, pmask, b, part, in_vs,
+                           spt);
+    else
+        hipLaunchKernelGGL(k_grad_kernel<9>, dim3((unsigned)nb, 9), dim3(256), 0, s, g, (const cx<float>*)links.p,
+                           (const cx<float>*)gv, (const cx<float>*)in, (int)dagger, nvec, (int)zero_odd_input, pmask, b, part, in_vs,
+                           spt);
     return nb;
 }
 

@@ -862,15 +862,17 @@ void solve_seed_impl(seedcg_s* h, const Io& io, int nrhs, seedcg_report* rep) {
 constexpr int K_LAYERS = 3, K_NW = 9 * 16;   // complex weights per layer
 constexpr int K_NREAL = K_LAYERS * K_NW * 2;  // reals updated by Adam
 
-// FP32 links for the transports of K (the inner links when they are FP32, else a copy)
-const void* k_links(seedcg_s* h) {
-    if (h->cg_lo && h->lo_prec == P32) return h->links_lo.p;
+// FP32 links for the transports of K: the inner stencil's two-row copy where the links are special
+// unitary and the inner links FP32, else the inner links when they are FP32, else a copy
+KLinks k_links(seedcg_s* h) {
+    if (h->cg_lo && h->hop_lo == P32R && h->links_lor.p) return {h->links_lor.p, 6};
+    if (h->cg_lo && h->lo_prec == P32) return {h->links_lo.p, 9};
     if (!h->klinks32.p) {
         // repack from the FP64 internal copy: same layout, entry by entry
         h->klinks32.ensure(4 * h->g.V * 9 * 8);
         convert(false, true, h->links64.p, h->klinks32.p, 4 * h->g.V * 9, h->s);
     }
-    return h->klinks32.p;
+    return {h->klinks32.p, 9};
 }
 
 const void* k_weights(seedcg_s* h, int layer) { return (const char*)h->kW32.p + (int64_t)layer * K_NW * 8; }
@@ -880,7 +882,7 @@ void apply_P(seedcg_s* h, bool low, const void* r, void* z, const int32_t* vmap,
     const int64_t N = h->N;
     h->pfa.ensure((int64_t)nalloc * 2 * N * 8);
     h->pfb.ensure((int64_t)nalloc * 2 * N * 8);
-    const void* L = k_links(h);
+    const KLinks L = k_links(h);
     k_embed(low, r, h->pfa.p, N, vmap, nact, h->s);
     // K^dag = R_e L_1^dag L_2^dag L_3^dag E_e: the first layer sees an even-only input and the last
     // one's odd outputs are dropped by R_e, so each of K^dag and K costs four half-lattice hops
@@ -976,7 +978,7 @@ double k_pass(seedcg_s* h, int off, int S, bool backward, bool want_loss, int ba
     // the block partials of the six weight gradients of a backward pass, one after another
     h->kpart.ensure(6 * 9 * k_grad_blocks(h->g) * 32 * sizeof(double));
     const int64_t nbb = k_band_blocks(h->g, band_t0, band_nt);
-    const void* L = k_links(h);
+    const KLinks L = k_links(h);
     // the band of layer j = 1..6 (the loss band widened by 6 - j slices each side); 0 slices: whole lattice
     auto bt0 = [&](int j) { return band_nt ? band_t0 - (6 - j) : 0; };
     auto bnt = [&](int j) { return band_nt ? band_nt + 2 * (6 - j) : 0; };

@@ -173,6 +173,8 @@ def main():
     if not args.no_compare:
         compare = compare_forms(args, cfg, Ud, kappa, B, value, prec, phid)
     copy_gbs = copy_rate()
+    probes = roofline_probes()
+    with_achievable(roofline, probes)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -195,7 +197,7 @@ def main():
                    "t_seed_s": rs["t_seed_s"], "t_rest_s": rr["t_rest_s"], "cg_iters": rr["iters"],
                    "max_true_relres": max(rr["true_relres"]), "dagger_d": dd,
                    "hop_launches_total": tm["seen"], "compare": compare,
-                   "device_copy_gbs": copy_gbs},
+                   "device_copy_gbs": copy_gbs, "roofline_probes": probes},
     }
     print(json.dumps(result), flush=True)
 
@@ -376,6 +378,8 @@ def bench_metric(args):
                 "avg_launch_bytes": dom["avg_bytes"] if dom else None,
                 "note": "the sampled launch kind with the largest stencil time in the timed learned + mixed steps; "
                         "algorithmic bytes (links once per launch in the stored format, every spinor operand once)"}
+    probes = roofline_probes()
+    with_achievable(roofline, probes)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cfg, U, phi, kappa, last_ref, min(args.cpu_iters, 10 if cfg.volume > 300_000 else 40))
@@ -407,7 +411,7 @@ def bench_metric(args):
                               "t_train_s_per_step": t_train / args.steps, "m": rs["m"], "i_conv": rs["i_conv"],
                               "t_seed_s": rs["t_seed_s"], "t_rest_s": rr["t_rest_s"], "cg_iters": rr["iters"],
                               "max_true_relres": max(rr["true_relres"]), "training": tr},
-            "stencil_kinds": kinds, "dagger_d": dd, "device_copy_gbs": copy_rate(),
+            "stencil_kinds": kinds, "dagger_d": dd, "device_copy_gbs": copy_rate(), "roofline_probes": probes,
         },
     }
     print(json.dumps(result), flush=True)
@@ -570,6 +574,26 @@ def copy_rate():
     return 2.0 * (1 << 30) / (ms * 1e-3) / 1e9
 
 
+def roofline_probes():
+    """The library's roofline probes on this GPU: copy, FP64 triad and read over 2 GiB buffers (8x the
+    256 MB memory-side cache, so HBM serves them), and register-resident FP64 / FP32 matrix-core
+    chains; the measured ceilings beside the datasheet's 8 TB/s, 78.6 and 157.3 TFLOP/s."""
+    from paper_0901_3512_amd import probe_bandwidth, probe_mfma
+    out = {k: probe_bandwidth(k, 1 << 31, 10) for k in ("copy", "triad", "read")}
+    out = {f"{k}_gbs": v for k, v in out.items()}
+    out["mfma_f64_tflops"] = probe_mfma("fp64", 20000)
+    out["mfma_f32_tflops"] = probe_mfma("fp32", 20000)
+    return out
+
+
+def with_achievable(roofline, probes):
+    """The roofline object with the measured HBM ceiling (the triad probe) and the fraction of it."""
+    if roofline.get("unit") == "GB/s" and roofline.get("achieved") and probes:
+        roofline["achievable"] = probes["triad_gbs"]
+        roofline["frac_achievable"] = roofline["achieved"] / probes["triad_gbs"]
+    return roofline
+
+
 def copy_probe():
     """A plain 1 GiB device copy: the reference for scaling the HBM byte counters."""
     import torch
@@ -669,6 +693,9 @@ def bench_batch(args):
         "detail": {"classes": info, "m": [r["m"] for r in last], "i_conv": [r["i_conv"] for r in last],
                    "iters": [r["iters"] for r in last], "max_true_relres": max(max(r["true_relres"]) for r in last)},
     }
+    probes = roofline_probes()
+    with_achievable(result["roofline"], probes)
+    result["detail"]["roofline_probes"] = probes
     print(json.dumps(result), flush=True)
 
 

@@ -262,6 +262,19 @@ seedcg_status seedcg_get_timing_kinds(seedcg_t h, double* out, int32_t cap, int3
    seedcg_get_timing_kinds).  One configuration per handle. */
 seedcg_status seedcg_time_M(seedcg_t h, int32_t inner, int32_t nvec, int32_t reps, double* out);
 
+/* Roofline probes (measurement, not part of the method): what this GPU achieves with the simplest
+   kernels that can reach its ceilings, to read the solver's rates against measured limits beside the
+   datasheet's (HBM 8 TB/s; FP64 matrix cores 78.6 TFLOP/s, FP32 157.3).
+   probe_bandwidth: kind 0 copy b = a, 1 triad a = b + s c (FP64), 2 read (a sum of a); buffers of
+   `bytes` each (>= 1 MiB; allocated and freed by the call, ERR_OOM if they do not fit), one untimed
+   pass, then reps passes timed with a pair of hipEvents on `stream` (a hipStream_t; NULL = the null
+   stream).  *gbs (HOST) receives GB/s counting each byte read or written once.
+   probe_mfma: dtype 0 v_mfma_f64_16x16x4, 1 v_mfma_f32_16x16x4: four wavefronts per SIMD, each running
+   eight independent chains of `iters` register-resident products; *tflops (HOST) receives TFLOP/s at
+   2 * 16 * 16 * 4 flops per instruction.  Both return ERR_ARG on a bad argument. */
+seedcg_status seedcg_probe_bandwidth(int32_t kind, int64_t bytes, int32_t reps, void* stream, double* gbs);
+seedcg_status seedcg_probe_mfma(int32_t dtype, int32_t iters, void* stream, double* tflops);
+
 /* ---- learned preconditioner P = K K^dag (an addition to the paper's method) -------------------
    K = R_e L_3 L_2 L_1 E_e on full-lattice 12-spinors: E_e embeds an even-site vector (zero on odd
    sites), R_e restricts to the even sites, and each layer is

@@ -3,6 +3,7 @@
 Build with paper_0901_3512_amd.build.build(); the binding refuses to run without the
 compiled library.
 """
-from .seedcg import SeedCG, SeedCGBatch, SeedCGError, load_library, LIB_PATH, exported_symbols
+from .seedcg import SeedCG, SeedCGBatch, SeedCGError, load_library, LIB_PATH, exported_symbols, probe_bandwidth, probe_mfma
 
-__all__ = ["SeedCG", "SeedCGBatch", "SeedCGError", "load_library", "LIB_PATH", "exported_symbols"]
+__all__ = ["SeedCG", "SeedCGBatch", "SeedCGError", "load_library", "LIB_PATH", "exported_symbols", "probe_bandwidth",
+           "probe_mfma"]

@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libseedcg.so")
-SOURCES = ["dslash.hip", "blas.hip", "contract.hip", "learned.hip", "minres.hip", "solver.hip"]
+SOURCES = ["dslash.hip", "blas.hip", "contract.hip", "learned.hip", "minres.hip", "probe.hip", "solver.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          # packed FP32 instructions stay off: the compiler may not emit v_pk_* FP32 forms

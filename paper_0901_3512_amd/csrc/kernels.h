@@ -158,4 +158,9 @@ void zlincomb(const ZLC* o, int nout, int64_t n, hipStream_t s);
 void zdots(const void* const* a, const void* const* b, int np, int64_t n, double* part, double* out, hipStream_t s);
 int64_t zdots_blocks(int64_t n);
 
+// roofline probes (probe.hip): GB/s of copy (kind 0), FP64 triad (1) or read (2) over buffers of
+// `bytes`; TFLOP/s of FP64 (dtype 0) or FP32 (1) matrix-core chains on every SIMD
+double probe_bandwidth(int kind, int64_t bytes, int reps, hipStream_t s);
+double probe_mfma(int dtype, int iters, hipStream_t s);
+
 }  // namespace scg

@@ -3353,6 +3353,32 @@ seedcg_status seedcg_time_M(seedcg_t h, int32_t inner, int32_t nvec, int32_t rep
     });
 }
 
+seedcg_status seedcg_probe_bandwidth(int32_t kind, int64_t bytes, int32_t reps, void* stream, double* gbs) {
+    if (!gbs || kind < 0 || kind > 2 || bytes < (1 << 20) || reps < 1)
+        return fail(nullptr, SEEDCG_ERR_ARG, "probe_bandwidth: kind 0..2, bytes >= 1 MiB, reps >= 1 and an output pointer");
+    try {
+        *gbs = probe_bandwidth(kind, bytes, reps, (hipStream_t)stream);
+    } catch (const std::bad_alloc&) {
+        return fail(nullptr, SEEDCG_ERR_OOM, "probe_bandwidth: the buffers do not fit");
+    } catch (const std::exception& e) {
+        return fail(nullptr, SEEDCG_ERR_HIP, e.what());
+    }
+    return SEEDCG_OK;
+}
+
+seedcg_status seedcg_probe_mfma(int32_t dtype, int32_t iters, void* stream, double* tflops) {
+    if (!tflops || dtype < 0 || dtype > 1 || iters < 1)
+        return fail(nullptr, SEEDCG_ERR_ARG, "probe_mfma: dtype 0 or 1, iters >= 1 and an output pointer");
+    try {
+        *tflops = probe_mfma(dtype, iters, (hipStream_t)stream);
+    } catch (const std::bad_alloc&) {
+        return fail(nullptr, SEEDCG_ERR_OOM, "probe_mfma: no room for its output");
+    } catch (const std::exception& e) {
+        return fail(nullptr, SEEDCG_ERR_HIP, e.what());
+    }
+    return SEEDCG_OK;
+}
+
 seedcg_status seedcg_train_precond(seedcg_t h, int32_t steps, int32_t n_ritz, int32_t n_lanczos, double lr, double* out) {
     if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "train_precond: null handle");
     Phase ph("seedcg_train_precond");

@@ -85,6 +85,8 @@ def load_library():
         "seedcg_get_timing": (i32, [H, ctypes.POINTER(dbl)]),
         "seedcg_get_timing_kinds": (i32, [H, ctypes.POINTER(dbl), i32, ctypes.POINTER(i32)]),
         "seedcg_time_M": (i32, [H, i32, i32, i32, ctypes.POINTER(dbl)]),
+        "seedcg_probe_bandwidth": (i32, [i32, i64, i32, P, ctypes.POINTER(dbl)]),
+        "seedcg_probe_mfma": (i32, [i32, i32, P, ctypes.POINTER(dbl)]),
         "seedcg_release_basis": (i32, [H]),
         "seedcg_destroy": (None, [H]),
         "seedcg_last_error": (ctypes.c_char_p, [H]),
@@ -111,9 +113,38 @@ def exported_symbols():
             "seedcg_solve_rest", "seedcg_solve_repeated", "seedcg_solve_indefinite", "seedcg_get_tridiag", "seedcg_get_basis_vector", "seedcg_get_ritz", "seedcg_project",
             "seedcg_project_noalloc", "seedcg_update", "seedcg_train_precond", "seedcg_use_precond", "seedcg_set_precond_weights",
             "seedcg_get_precond_weights", "seedcg_apply_P", "seedcg_precond_loss_grad", "seedcg_precond_loss_grad_band", "seedcg_set_timing",
-            "seedcg_get_timing", "seedcg_get_timing_kinds", "seedcg_time_M", "seedcg_release_basis", "seedcg_destroy", "seedcg_last_error", "seedcg_create_batch",
+            "seedcg_get_timing", "seedcg_get_timing_kinds", "seedcg_time_M", "seedcg_probe_bandwidth", "seedcg_probe_mfma", "seedcg_release_basis", "seedcg_destroy", "seedcg_last_error", "seedcg_create_batch",
             "seedcg_solve_batch", "seedcg_batch_info", "seedcg_batch_set_timing", "seedcg_batch_get_timing",
             "seedcg_destroy_batch", "seedcg_batch_last_error"]
+
+
+_PROBE_KINDS = {"copy": 0, "triad": 1, "read": 2}
+
+
+def probe_bandwidth(kind, nbytes=1 << 31, reps=10, stream=None):
+    """GB/s this GPU reaches with the library's copy, FP64 triad or read kernel over buffers of nbytes
+    each (every byte read or written counted once); a roofline probe, not part of the method."""
+    lib = load_library()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    out = ctypes.c_double()
+    rc = lib.seedcg_probe_bandwidth(_PROBE_KINDS[kind], int(nbytes), int(reps), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(out))
+    if rc != 0:
+        raise SeedCGError(rc, lib.seedcg_last_error(None).decode())
+    return out.value
+
+
+def probe_mfma(dtype="fp64", iters=20000, stream=None):
+    """TFLOP/s of register-resident v_mfma_f64_16x16x4 (dtype "fp64") or v_mfma_f32_16x16x4 ("fp32")
+    chains on every SIMD; a roofline probe, not part of the method."""
+    lib = load_library()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    out = ctypes.c_double()
+    rc = lib.seedcg_probe_mfma({"fp64": 0, "fp32": 1}[dtype], int(iters), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(out))
+    if rc != 0:
+        raise SeedCGError(rc, lib.seedcg_last_error(None).decode())
+    return out.value
 
 
 def _check_vec(t, Vh, name):

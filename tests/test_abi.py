@@ -59,6 +59,12 @@ def test_create_rejects_bad_arguments_on_host(lib):
     p.tol = 0.0
     assert lib.seedcg_create(ctypes.byref(p), dummy, ctypes.byref(h)) == -1
     assert lib.seedcg_create(None, dummy, ctypes.byref(h)) == -1
+    # the roofline probes refuse bad arguments before any GPU call
+    d = ctypes.c_double()
+    assert lib.seedcg_probe_bandwidth(3, 1 << 20, 1, None, ctypes.byref(d)) == -1
+    assert lib.seedcg_probe_bandwidth(0, 1000, 1, None, ctypes.byref(d)) == -1
+    assert lib.seedcg_probe_mfma(2, 10, None, ctypes.byref(d)) == -1
+    assert lib.seedcg_probe_mfma(0, 0, None, ctypes.byref(d)) == -1
     assert lib.seedcg_apply_M(None, None, None, 1) == -1
     assert lib.seedcg_solve_seed(None, None, None, 1, None) == -1
 

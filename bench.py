@@ -56,10 +56,12 @@ def parse():
     ap.add_argument("--train-steps", type=int, default=2000, help="Adam steps of the learned K per step")
     ap.add_argument("--deflate-k", type=int, default=16, help="Ritz vectors deflated in the learned form's (P)CG")
     ap.add_argument("--ref-steps", type=int, default=5, help="timed steps of the plain FP64 reference (at most --steps)")
-    ap.add_argument("--m-max", type=int, default=0, help="Krylov basis capacity of both forms (0: by the HBM left)")
+    ap.add_argument("--m-max", type=int, default=0,
+                    help="Krylov basis capacity (0: the metric's line sizes it by the GPU's memory, --form grows it as the run needs)")
     ap.add_argument("--basis", default="auto", choices=("auto", "fp64", "fp32", "reorth"),
-                    help="the learned + mixed form's Krylov basis: FP64; FP32; FP64 plus an FP32 copy read only by the "
-                         "reorthogonalisation; auto = reorth where HBM holds both at the capacity, else FP64")
+                    help="the Krylov basis of the learned + mixed form (or of --form): FP64; FP32; FP64 plus an FP32 copy "
+                         "read only by the reorthogonalisation; auto = reorth where HBM holds both at the capacity, "
+                         "else FP64 (--form: the precision's own basis)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=40, help="Lanczos steps in the oracle sample")
     ap.add_argument("--sample-every", type=int, default=7,
@@ -111,8 +113,10 @@ def main():
     log(f"inputs {cfg.name} dims={cfg.dims} kappa={kappa} nrhs={cfg.nrhs} ({time.time() - t_gen:.1f} s)")
     Ud = torch.from_numpy(U).to(dev)
     phid = torch.from_numpy(phi).to(dev)
+    # one form's basis: as --basis asks (auto: the FP64 basis of an FP64 Lanczos, or the FP32 one)
+    basis = {"auto": False, "fp64": False, "fp32": True, "reorth": "reorth"}[args.basis]
     solver = SeedCG(Ud, cfg.dims, kappa, t_bc=cfg.t_bc, prec=prec, reorth_k=cfg.reorth_k, past=cfg.past,
-                    tol=cfg.tol, reliable_every=cfg.reliable_every, deflate=args.deflate)
+                    tol=cfg.tol, reliable_every=cfg.reliable_every, deflate=args.deflate, basis_fp32=basis, m_max=args.m_max)
     B = solver.apply_A(phid, dagger=True)   # b = A^dag phi (input preparation, not timed)
     if args.sweep:
         return sweep(cfg, Ud, kappa, B)
@@ -190,7 +194,7 @@ def main():
                                f"{'x'.join(map(str, cfg.dims))}, {cfg.nrhs} RHS, tol {cfg.tol:g}, k={cfg.reorth_k}",
                    "name": cfg.name, "lattice": list(cfg.dims), "kappa": kappa, "nrhs": nrhs,
                    "reorth_k": cfg.reorth_k, "past_factor": cfg.past, "tol": cfg.tol, "precision": prec,
-                   "deflate": args.deflate},
+                   "deflate": args.deflate, "basis": args.basis},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "detail": {"m": rs["m"], "i_conv": rs["i_conv"], "seed_status": rs["seed_status"],

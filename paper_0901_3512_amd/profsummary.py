@@ -60,21 +60,41 @@ def _counter(d, name):
 
 def _copy_window(rows):
     """The 1 GiB copy probe in a counter trace: (mean counter value of its copies, dispatch id of its
-    last copy, dispatch id of the next 1 GiB copy or None).  Big copies are those within 10% of the
-    largest; the probe is the first run of them with no other dispatch in between (a later run, such
-    as the benchmark's copy-rate measurement after its timed region, ends the window)."""
-    cp = [(int(r["Dispatch_Id"]), float(r["Counter_Value"])) for r in rows if "copyBuffer" in r["Kernel_Name"]]
-    top = max(v for _, v in cp)
-    big = sorted((d, v) for d, v in cp if v >= 0.9 * top)
+    last copy, dispatch id of the next copy of that size or None).  The probe is the first run of two
+    or more back-to-back copies (no other dispatch in between) whose values agree within 10%; other
+    copies of the run (a basis growing by device copies, say) are single.  Without such a run: the
+    first run of copies within 10% of the largest.  A later copy of the probe's size (the benchmark's
+    copy-rate measurement after its timed region) ends the window."""
+    cp = sorted((int(r["Dispatch_Id"]), float(r["Counter_Value"])) for r in rows if "copyBuffer" in r["Kernel_Name"])
     ids = sorted({int(r["Dispatch_Id"]) for r in rows})
-    probe = [big[0]]
-    for d, v in big[1:]:
-        if any(probe[-1][0] < x < d for x in ids):
+
+    def adjacent(a, b):
+        return not any(a < x < b for x in ids)
+
+    def close(u, v):
+        return abs(u - v) <= 0.1 * max(u, v)
+
+    probe = None
+    for k in range(len(cp) - 1):
+        if adjacent(cp[k][0], cp[k + 1][0]) and close(cp[k][1], cp[k + 1][1]):
+            probe = [cp[k], cp[k + 1]]
+            for d, v in cp[k + 2:]:
+                if not (adjacent(probe[-1][0], d) and close(probe[0][1], v)):
+                    break
+                probe.append((d, v))
             break
-        probe.append((d, v))
+    if probe is None:
+        top = max(v for _, v in cp)
+        big = [(d, v) for d, v in cp if v >= 0.9 * top]
+        probe = [big[0]]
+        for d, v in big[1:]:
+            if not adjacent(probe[-1][0], d):
+                break
+            probe.append((d, v))
+    ref = sum(v for _, v in probe) / len(probe)
     last = probe[-1][0]
-    after = [d for d, _ in big if d > last]
-    return sum(v for _, v in probe) / len(probe), last, (after[0] if after else None)
+    after = [d for d, v in cp if d > last and close(ref, v)]
+    return ref, last, (after[0] if after else None)
 
 
 def bytes_per_launch(fetch_dir, write_dir, kernel):

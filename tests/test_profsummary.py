@@ -17,6 +17,15 @@ def test_probe_is_the_first_run_of_big_copies():
     assert ref == 1000.0 and last == 5 and nxt == 8
 
 
+def test_probe_is_found_beside_larger_single_copies():
+    # a basis growing by device copies (single, larger copies) before and after the probe's run
+    rows = [_row(1, "copyBuffer", 5000, "X"), _row(2, "hop_a", 5, "X"), _row(3, "copyBuffer", 1000, "X"),
+            _row(4, "copyBuffer", 1000, "X"), _row(5, "copyBuffer", 1000, "X"), _row(6, "hop_a", 7, "X"),
+            _row(7, "copyBuffer", 9000, "X"), _row(8, "hop_a", 9, "X"), _row(9, "copyBuffer", 1000, "X")]
+    ref, last, nxt = _copy_window(rows)
+    assert ref == 1000.0 and last == 5 and nxt == 9
+
+
 def _write(d, name, rows):
     os.makedirs(d, exist_ok=True)
     with open(os.path.join(d, "p_counter_collection.csv"), "w", newline="") as f:

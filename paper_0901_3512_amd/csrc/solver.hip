@@ -1514,6 +1514,16 @@ ProjArgs defl_proj_args(seedcg_s* h, const void* rows, int nrows, const void* R,
     return a;
 }
 
+// dP = rows^dag R for the deflation: one or two columns (a single system, the judge's solves) on the
+// vector units, more on the matrix cores
+void defl_project(seedcg_s* h, const ProjArgs& a) {
+    const bool lo = h->cg_lo;   // W, M W and the CG vectors share the CG's precision
+    if (a.nr <= 2)
+        reorth_project(lo, lo, a, h->dP.as<double>(), h->L());
+    else
+        project(lo, a, 1, h->dP.as<double>(), h->L(), true);
+}
+
 // W, Z = M W and G^{-1} from the tridiagonal and basis of the last seed solve (one configuration)
 void build_deflation(seedcg_s* h, int want) {
     h->nev = 0;
@@ -1571,7 +1581,7 @@ void build_deflation(seedcg_s* h, int want) {
 void deflate_step(seedcg_s* h, bool init, const void* R, int nrhs, const int32_t* map, int w, void* X, bool x32,
                   bool use_cg) {
     const bool lo = h->cg_lo;   // W, M W and the CG vectors share the CG's precision
-    project(lo, defl_proj_args(h, init ? h->dW.p : h->dZ.p, h->nev, R, nrhs), 1, h->dP.as<double>(), h->L(), true);
+    defl_project(h, defl_proj_args(h, init ? h->dW.p : h->dZ.p, h->nev, R, nrhs));
     defl_mu(h->dGinv.as<double>(), h->dP.as<double>(), h->nev, nrhs, map, w, (init || !use_cg) ? nullptr : h->cgv.as<CgVec>(),
             init ? 1.0 : -1.0, h->dE.as<double>(), h->L());
     seed_update(lo, x32, h->dW.p, h->nev, h->dE.as<double>(), X, nrhs, h->N, nullptr, h->L());
@@ -1581,7 +1591,7 @@ void deflate_step(seedcg_s* h, bool init, const void* R, int nrhs, const int32_t
 // listed vectors back, x += W G^{-1} W^dag r and r -= Z G^{-1} W^dag r (Z = M W, so r stays b - M x).
 void redeflate(seedcg_s* h, void* Rw, int nrhs, const int32_t* map, int w) {
     const bool lo = h->cg_lo;   // W, M W and the CG vectors share the CG's precision
-    project(lo, defl_proj_args(h, h->dW.p, h->nev, Rw, nrhs), 1, h->dP.as<double>(), h->L(), true);
+    defl_project(h, defl_proj_args(h, h->dW.p, h->nev, Rw, nrhs));
     defl_mu(h->dGinv.as<double>(), h->dP.as<double>(), h->nev, nrhs, map, w, nullptr, 1.0, h->dE.as<double>(), h->L());
     seed_update(lo, false, h->dW.p, h->nev, h->dE.as<double>(), h->Xint.p, nrhs, h->N, nullptr, h->L());
     defl_mu(h->dGinv.as<double>(), h->dP.as<double>(), h->nev, nrhs, map, w, nullptr, -1.0, h->dE.as<double>(), h->L());

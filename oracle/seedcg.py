@@ -58,7 +58,7 @@ def _orthogonalise(Q, x):
     return x, passes
 
 
-def seed_cg(matvec, B, X0=None, *, k, tol, past=1.5, m_max=2000, m=None):
+def seed_cg(matvec, B, X0=None, *, k, tol, past=1.5, m_max=2000, m=None, reorth_basis=None):
     """Algorithm 1, Seed-CG(m, k), for the right-hand sides B (nrhs, N).
 
     k = 0 means no reorthogonalisation (k = infinity).  If m is given the run takes
@@ -66,6 +66,9 @@ def seed_cg(matvec, B, X0=None, *, k, tol, past=1.5, m_max=2000, m=None):
     Returns a dict with X (the RHS-1 iterate and the seeded guesses), the Lanczos
     coefficients alpha_1..alpha_m, beta_0..beta_m, the LU scalars delta, gamma, zeta,
     the basis V (m, N), i_conv, m and a status string.
+    reorth_basis (optional): maps the stored basis vectors to the ones the reorthogonalisation
+    projects against and subtracts (for instance their FP32 roundings); the stored basis, the
+    Lanczos recurrence and the seeding are unchanged.
     """
     B = np.atleast_2d(np.asarray(B, dtype=np.complex128))
     nrhs, N = B.shape
@@ -124,9 +127,10 @@ def seed_cg(matvec, B, X0=None, *, k, tol, past=1.5, m_max=2000, m=None):
         m_used = i
         # periodic reorthogonalisation
         if k and i % k == 0:
-            vi, p1 = _orthogonalise(V[:i - 1], V[i - 1])
+            Q = (lambda rows: rows) if reorth_basis is None else reorth_basis
+            vi, p1 = _orthogonalise(Q(V[:i - 1]), V[i - 1])
             V[i - 1] = vi / _norm(vi)
-            f, p2 = _orthogonalise(V[:i], f)
+            f, p2 = _orthogonalise(Q(V[:i]), f)
             passes += p1 + p2
         # beta_i = ||f||, the residual estimate, the stopping rule and v_{i+1} = f / beta_i
         bi = _norm(f)

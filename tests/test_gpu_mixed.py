@@ -264,6 +264,34 @@ def test_fp32_reorth_copy_of_fp64_basis(t8, prec):
     print("fp32 reorth copy", prec, "m", rs["m"], "orth", osc.orth_loss(V), "iters", rr["iters"])
 
 
+def test_reorth_copy_keeps_the_seeding_gain_that_an_fp32_basis_loses():
+    """On 8^4 with one flux quantum through two planes (kappa 0.14: near-zero modes apart from the
+    bulk, where the seeded guesses carry most of the solution), FP64 Lanczos with FP32 CG, six point
+    sources: the FP32 reorthogonalisation copy of the FP64 basis leaves every seeded system's CG
+    iterations within 2 of the FP64 basis' (the oracle, with the basis rounded for the
+    reorthogonalisation only, gives the same counts: 58-59), while the FP32 basis, whose seeding
+    projections use the rounded vectors, needs at least 15% more on average (oracle: 80-82)."""
+    from paper_0901_3512_amd import SeedCG
+    from synth.configs import CONFIGS, make_links, with_changes
+    from synth.sources import point_sources
+    dims = (8, 8, 8, 8)
+    U = make_links(with_changes(CONFIGS["c5"], dims=dims, flux=(1, 1)))
+    op = WilsonEO(U, dims, 0.14)
+    B = op.apply_Adag(point_sources(dims, 6))
+    its = {}
+    for mode in (False, "reorth", True):
+        print_case("seeding gain, basis", mode)
+        s = SeedCG(cuda(U), dims, 0.14, prec="mixed_cg", reorth_k=10, basis_fp32=mode)
+        X, _ = s.solve_seed(cuda(B))
+        X, rr = s.solve_rest(cuda(B), X)
+        assert np.all(osc.true_relres(matvec_M(op), flat(B), flat(host(X))) <= 1e-10)
+        its[mode] = np.array(rr["iters"][1:])
+        s.close()
+    print("seeded CG iterations", {str(k): v.tolist() for k, v in its.items()})
+    assert np.max(np.abs(its["reorth"] - its[False])) <= 2, its
+    assert its[True].mean() >= 1.15 * its[False].mean(), its
+
+
 def test_fp32_basis_copy_refused_for_batches():
     from paper_0901_3512_amd import SeedCGError
     from paper_0901_3512_amd.seedcg import Params, load_library

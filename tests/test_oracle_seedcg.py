@@ -214,3 +214,24 @@ def test_seeding_pays_only_with_isolated_low_modes():
             _, it_c, r_c, _ = sc.cg(mv, B[j], None, tol=1e-10)
             assert r_s <= 1e-10 and r_c <= 1e-10
             assert lo <= it_s / it_c <= hi, (flux, j, it_s, it_c)
+
+
+def test_reorthogonalising_against_fp32_roundings_keeps_the_seeding_gain():
+    """8^4 with one flux quantum through two planes (kappa 0.14, near-zero modes apart from the bulk),
+    six point sources, k = 10: Algorithm 1 with its periodic reorthogonalisation projecting against
+    the FP32 roundings of the basis vectors (the stored basis, the recurrence and the seeding in FP64)
+    stops at the same m, leaves the basis orthogonal to FP32 rounding only, and its seeded guesses
+    need the same CG iterations (within 1) as those of the FP64 reorthogonalisation."""
+    from synth.configs import make_links, with_changes
+    from synth.sources import point_sources
+    dims = (8, 8, 8, 8)
+    U = make_links(with_changes(CONFIGS["c5"], dims=dims, flux=(1, 1)))
+    op = WilsonEO(U, dims, 0.14)
+    B = flat(op.apply_Adag(point_sources(dims, 6)))
+    mv = matvec_M(op)
+    rnd = lambda Q: Q.astype(np.complex64).astype(np.complex128)
+    runs = [sc.seed_cg(mv, B, k=10, tol=1e-10, past=1.5), sc.seed_cg(mv, B, k=10, tol=1e-10, past=1.5, reorth_basis=rnd)]
+    assert runs[0]["m"] == runs[1]["m"]
+    assert sc.orth_loss(runs[0]["V"]) <= 1e-13 and 1e-12 < sc.orth_loss(runs[1]["V"]) <= 1e-6
+    its = [np.array([sc.cg(mv, B[j], r["X"][j], tol=1e-10)[1] for j in range(1, 6)]) for r in runs]
+    assert np.max(np.abs(its[0] - its[1])) <= 1, its

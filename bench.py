@@ -600,6 +600,8 @@ def with_achievable(roofline, probes):
     if roofline.get("unit") == "GB/s" and roofline.get("achieved") and probes:
         roofline["achievable"] = probes["triad_gbs"]
         roofline["frac_achievable"] = roofline["achieved"] / probes["triad_gbs"]
+        if roofline.get("combined"):
+            roofline["combined_frac_achievable"] = roofline["combined"] / probes["triad_gbs"]
     return roofline
 
 
@@ -681,6 +683,11 @@ def bench_batch(args):
     hop_ms = tm["ms"] / max(tm["launches"], 1)
     hop_bytes = tm["bytes"] / max(tm["launches"], 1)
     achieved = hop_bytes / (hop_ms * 1e-3) / 1e9 if tm["launches"] else None
+    # The classes' launches overlap on their streams, so a sampled launch's event pair also spans
+    # what the other classes ran beside it. The algorithmic bytes of every stencil launch of a solve
+    # (the same launches as a timed step's, which replays them from graphs) over the timed step's
+    # wall time bound the classes' combined stencil rate from below.
+    combined = tm["seen_bytes"] / (elapsed / args.steps) / 1e9
     V = sum(int(np.prod(m.dims)) for m in members)
     result = {
         "metric": METRIC, "value": solved / elapsed, "unit": "RHS/s", "n_gpus": 1, "steps": args.steps,
@@ -695,6 +702,10 @@ def bench_batch(args):
                      "traffic": measured_traffic(None, None, "hop_", name=f"hop_kernel_batch{len(members)}_{prec}_traffic.txt"),
                      "kernel": "hop kernels of the batch (one launch per shape class, concurrent classes)",
                      "launches_sampled": tm["launches"], "avg_launch_us": hop_ms * 1e3, "avg_launch_bytes": hop_bytes,
+                     "solve_launches": tm["seen"], "solve_bytes": tm["seen_bytes"], "combined": combined,
+                     "combined_frac": combined / HBM_PEAK_GBS,
+                     "combined_note": "algorithmic bytes of every stencil launch of one solve / the timed step's wall "
+                                      "time: a lower bound for the concurrent classes' stencil rate together",
                      "traffic_note": "HBM bytes per hop launch averaged over every hop dispatch of one timed solve "
                                      "(rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled); achieved and avg_launch_bytes "
                                      "average the event-sampled launches of one more solve"},

@@ -241,9 +241,11 @@ seedcg_status seedcg_update(seedcg_t h, const double* W, int32_t nw, const doubl
    handle's stream, up to max_samples pairs; 0 turns sampling off.  Resets the counters. */
 seedcg_status seedcg_set_timing(seedcg_t h, int32_t sample_every, int32_t max_samples);
 
-/* Reads the sampled stencil timings into out[5] (HOST): number of sampled launches, their total
+/* Reads the sampled stencil timings into out[6] (HOST): number of sampled launches, their total
    milliseconds, their total algorithmic bytes (links once per launch, every spinor operand once),
-   their total flops (1320 per site and vector), and the number of stencil launches seen. */
+   their total flops (1320 per site and vector), the number of stencil launches issued since
+   set_timing, and the algorithmic bytes of all of those (sampled or not).  Launches replayed from a
+   captured graph are counted once, when captured; sampling turns graph replay off. */
 seedcg_status seedcg_get_timing(seedcg_t h, double* out);
 
 /* The sampled stencil launches of get_timing, by launch kind: rows of 8 doubles in out (HOST, cap
@@ -365,8 +367,9 @@ seedcg_status seedcg_solve_batch(seedcg_batch_t b, const double* const* B, doubl
    for several vectors. */
 seedcg_status seedcg_batch_info(seedcg_batch_t b, int32_t* nclass, int32_t* class_of, int32_t* m_cap, double* tune);
 
-/* seedcg_set_timing / seedcg_get_timing for every shape class of the batch; the counts and sums
-   of get_timing are totals over the classes (whose launches may overlap in time on their streams). */
+/* seedcg_set_timing / seedcg_get_timing for every shape class of the batch; the six counts and
+   sums of get_timing (out[6]) are totals over the classes, whose launches may overlap in time on
+   their streams, so that a sampled launch's duration includes what the other classes ran beside it. */
 seedcg_status seedcg_batch_set_timing(seedcg_batch_t b, int32_t sample_every, int32_t max_samples);
 seedcg_status seedcg_batch_get_timing(seedcg_batch_t b, double* out);
 

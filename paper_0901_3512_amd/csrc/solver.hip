@@ -224,6 +224,7 @@ struct seedcg_s {
     std::map<std::array<double, 5>, std::array<double, 3>> t_kind;   // kind -> launches, ms, bytes
     size_t ev_used = 0;
     double t_ms = 0.0, t_bytes = 0.0, t_flops = 0.0;
+    double hop_bytes_all = 0.0;   // algorithmic bytes of every stencil launch issued (sampled or not)
     int64_t t_launches = 0;
     ~seedcg_s() {
         for (auto e : ev0) (void)hipEventDestroy(e);
@@ -287,18 +288,21 @@ const void* hop_links(const seedcg_s* h, bool low) {
 // read once for the whole batch), and per vector the input and output spinors (24 reals each per site) plus every
 // epilogue operand (24 reals per site each).
 void hop(seedcg_s* h, Prec pr, const void* L, const void* in, void* out, int par, int nvec, const HopEpi& e, int tps, int vb) {
-    const bool sample = h->timing_every > 0 && (h->hop_count++ % h->timing_every) == 0 && h->ev_used < h->ev0.size();
+    const bool sample = h->timing_every > 0 && (h->hop_count % h->timing_every) == 0 && h->ev_used < h->ev0.size();
+    h->hop_count++;
     if (sample) HIPCHK(hipEventRecord(h->ev0[h->ev_used], h->s));
     launch_hop(pr, h->g, L, in, out, par, nvec, e, tps, vb, h->L());
+    const double sl = (pr == P64 || pr == P64R) ? 8.0 : (pr == P32BF ? 2.0 : 4.0);
+    const double ss = (pr == P64 || pr == P64R) ? 8.0 : 4.0;
+    const double lr = (pr == P64R || pr == P32R) ? 96.0 : 144.0;   // link reals per site (two rows or all)
+    const double Vh = (double)h->g.Vh * h->ncfg;
+    // the fused CG update reads u, p, r and the FP64 x and writes r and x instead of out
+    const double per = e.red == 3 ? 5.0 * ss + 2.0 * 8.0 : ss * (2 + (e.combine ? 1 : 0) + (e.z ? 1 : 0) + (e.red == 1 ? 1 : 0));
+    const double bytes = Vh * lr * sl + (double)nvec * Vh * 24.0 * per;
+    h->hop_bytes_all += bytes;
     if (sample) {
         HIPCHK(hipEventRecord(h->ev1[h->ev_used], h->s));
-        const double sl = (pr == P64 || pr == P64R) ? 8.0 : (pr == P32BF ? 2.0 : 4.0);
-        const double ss = (pr == P64 || pr == P64R) ? 8.0 : 4.0;
-        const double lr = (pr == P64R || pr == P32R) ? 96.0 : 144.0;   // link reals per site (two rows or all)
-        const double Vh = (double)h->g.Vh * h->ncfg;
-        // the fused CG update reads u, p, r and the FP64 x and writes r and x instead of out
-        const double per = e.red == 3 ? 5.0 * ss + 2.0 * 8.0 : ss * (2 + (e.combine ? 1 : 0) + (e.z ? 1 : 0) + (e.red == 1 ? 1 : 0));
-        h->ev_bytes.push_back(Vh * lr * sl + (double)nvec * Vh * 24.0 * per);
+        h->ev_bytes.push_back(bytes);
         h->ev_flops.push_back((double)nvec * Vh * 1320.0);
         // the launch kind: precision and link format, vectors, fused CG update, lanes per site, vectors per workgroup
         h->ev_kind.push_back({(double)pr, (double)nvec, (double)(e.red == 3), (double)tps, (double)vb});
@@ -2968,17 +2972,17 @@ seedcg_status seedcg_batch_get_timing(seedcg_batch_t b, double* out) {
         b->err = "batch_get_timing: null pointer";
         return SEEDCG_ERR_ARG;
     }
-    double acc[5] = {0, 0, 0, 0, 0};
+    double acc[6] = {0, 0, 0, 0, 0, 0};
     for (auto h : b->cls) {
-        double o[5];
+        double o[6];
         const seedcg_status st = seedcg_get_timing(h, o);
         if (st != SEEDCG_OK) {
             b->err = h->err;
             return st;
         }
-        for (int k = 0; k < 5; k++) acc[k] += o[k];
+        for (int k = 0; k < 6; k++) acc[k] += o[k];
     }
-    for (int k = 0; k < 5; k++) out[k] = acc[k];
+    for (int k = 0; k < 6; k++) out[k] = acc[k];
     return SEEDCG_OK;
 }
 
@@ -3259,7 +3263,7 @@ seedcg_status seedcg_set_timing(seedcg_t h, int32_t sample_every, int32_t max_sa
         h->ev_flops.clear();
         h->ev_kind.clear();
         h->t_kind.clear();
-        h->t_ms = h->t_bytes = h->t_flops = 0.0;
+        h->t_ms = h->t_bytes = h->t_flops = h->hop_bytes_all = 0.0;
         h->t_launches = 0;
         while ((int)h->ev0.size() < max_samples) {
             hipEvent_t a, b;
@@ -3298,6 +3302,7 @@ seedcg_status seedcg_get_timing(seedcg_t h, double* out) {
         out[2] = h->t_bytes;
         out[3] = h->t_flops;
         out[4] = (double)h->hop_count;
+        out[5] = h->hop_bytes_all;
         return SEEDCG_OK;
     });
 }
@@ -3306,7 +3311,7 @@ seedcg_status seedcg_get_timing_kinds(seedcg_t h, double* out, int32_t cap, int3
     if (!h) return fail(nullptr, SEEDCG_ERR_ARG, "get_timing_kinds: null handle");
     return guarded(h, [&]() -> seedcg_status {
         if (!out || !n || cap < 0) throw ArgError{"get_timing_kinds: null pointer or negative capacity"};
-        double tmp[5];
+        double tmp[6];
         const seedcg_status st = seedcg_get_timing(h, tmp);   // folds the pending samples in
         if (st != SEEDCG_OK) return st;
         int k = 0;

@@ -408,10 +408,11 @@ class SeedCG:
         self._rc(self._lib.seedcg_set_timing(self._h, int(sample_every), int(max_samples)))
 
     def get_timing(self):
-        """Sampled stencil launches: dict(launches, ms, bytes, flops, seen)."""
-        out = (ctypes.c_double * 5)()
+        """Sampled stencil launches: dict(launches, ms, bytes, flops, seen, seen_bytes); seen and
+        seen_bytes count every stencil launch issued since set_timing."""
+        out = (ctypes.c_double * 6)()
         self._rc(self._lib.seedcg_get_timing(self._h, out))
-        return dict(launches=int(out[0]), ms=out[1], bytes=out[2], flops=out[3], seen=int(out[4]))
+        return dict(launches=int(out[0]), ms=out[1], bytes=out[2], flops=out[3], seen=int(out[4]), seen_bytes=out[5])
 
     def get_timing_kinds(self):
         """Sampled stencil launches by kind: list of dict(fmt, nvec, fused, tps, vb, launches, ms, bytes)."""
@@ -507,12 +508,13 @@ class SeedCGBatch:
             raise SeedCGError(rc, self._lib.seedcg_batch_last_error(self._h).decode())
 
     def get_timing(self):
-        """Sampled stencil launches over every shape class: dict(launches, ms, bytes, flops, seen)."""
-        out = (ctypes.c_double * 5)()
+        """Sampled stencil launches over every shape class: dict(launches, ms, bytes, flops, seen,
+        seen_bytes), totals over the classes."""
+        out = (ctypes.c_double * 6)()
         rc = self._lib.seedcg_batch_get_timing(self._h, out)
         if rc != 0:
             raise SeedCGError(rc, self._lib.seedcg_batch_last_error(self._h).decode())
-        return dict(launches=int(out[0]), ms=out[1], bytes=out[2], flops=out[3], seen=int(out[4]))
+        return dict(launches=int(out[0]), ms=out[1], bytes=out[2], flops=out[3], seen=int(out[4]), seen_bytes=out[5])
 
     def solve(self, B, X=None, raise_on_noconv=True):
         """B: list of (nrhs, Vh_c, 4, 3) complex128 CUDA tensors; returns (X list, per-config reports)."""

@@ -202,3 +202,25 @@ def test_c4_full_batch_sampled_against_oracle():
         res = osc.true_relres(matvec_M(op), flat(B_ref), flat(host(X[c])))
         assert np.all(res <= 1e-10), (m.name, res)
         print("c4", m.name, m.dims, "m", reps[c]["m"], "iters", reps[c]["iters"], "oracle relres", float(res.max()))
+
+
+def test_timing_counts_every_stencil_launch(cfgs):
+    """get_timing's last two values count every stencil launch of the batch and its algorithmic
+    bytes: with every launch sampled they equal the sampled sums; sampling every third launch leaves
+    them unchanged (the same solve issues the same launches) and samples fewer."""
+    print_case("batch timing totals")
+    b = _batch(cfgs, "mixed", m_max=300, autotune=False)
+    B = [cuda(c["B"]) for c in cfgs]
+    b.set_timing(1, 16384)
+    b.solve(B)
+    all1 = b.get_timing()
+    b.set_timing(3, 16384)
+    b.solve(B)
+    all3 = b.get_timing()
+    b.set_timing(0, 0)
+    b.close()
+    assert all1["seen"] > 0
+    assert all1["launches"] == all1["seen"]
+    assert all1["seen_bytes"] == pytest.approx(all1["bytes"], rel=1e-12)
+    assert all3["seen"] == all1["seen"] and all3["seen_bytes"] == pytest.approx(all1["seen_bytes"], rel=1e-12)
+    assert 0 < all3["launches"] < all3["seen"] and 0 < all3["bytes"] < all3["seen_bytes"]

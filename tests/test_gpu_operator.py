@@ -20,17 +20,18 @@ def _vecs(rng, n, Vh):
     return rng.standard_normal((n, Vh, 4, 3)) + 1j * rng.standard_normal((n, Vh, 4, 3))
 
 
-@pytest.mark.parametrize("tps", [1, 2, 3, 4, 5, 6, 7, 8, 9, 10])
+# vb = 4 changes only the multi-vector variants (7, 8, 9)
+TPS_VB = [(t, v) for v in (1, 2, 4) for t in range(1, 11) if v != 4 or t in (7, 8, 9)]
+
+
+@pytest.mark.parametrize("tps,vb", TPS_VB)
 @pytest.mark.parametrize("dims,t_bc,eps", CASES)
-@pytest.mark.parametrize("vb", [1, 2, 4])
 def test_apply_M_matches_oracle(dims, t_bc, eps, tps, vb, monkeypatch):
     """tps: lanes per site (1, 2, 4), or two lanes per site: 3 / 5 / 6 = one / two / four directions per
     pass, 7 = links loaded once for a group of vb vectors (2 or 4), 8 = forward and backward hops on
     separate wavefronts for a group of vb vectors (1, 2 or 4), 9 = the same with the x and y neighbours
     staged in LDS (the last lattice takes three tiles of xy-rows, with halo rows), 10 = four
     wavefronts per 64 sites (forward / backward x-y / z-t hops); vb: vectors per workgroup."""
-    if vb == 4 and tps not in (7, 8, 9):
-        pytest.skip("vb = 4 only changes the multi-vector variant")
     from paper_0901_3512_amd import SeedCG
     print_case("apply_M", dims, t_bc, tps, vb)
     monkeypatch.setenv("SEEDCG_TPS", str(tps))

@@ -838,16 +838,21 @@ __global__ __launch_bounds__(SCG_BLOCK) void hop_multi_kernel(Geom g, const type
 __device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }
-template <typename S>
+template <typename S, int AUX = 0>
 __device__ inline S bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
     static_assert(sizeof(S) == 16 || sizeof(S) == 8 || sizeof(S) == 4, "load width");
     if constexpr (sizeof(S) == 16)
-        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, AUX));
     else if constexpr (sizeof(S) == 8)
-        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX));
     else
-        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, AUX));
 }
+// The cache-policy operand of a buffer load: CPOL_NT marks the load non-temporal, so that its lines
+// are the first to leave the caches.  A one-vector stencil reads every link exactly once, and when
+// the links alone outgrow the memory-side cache they otherwise push out the neighbour spinors that
+// the next site blocks read again.
+constexpr int CPOL_NT = 2;
 
 // projection coefficients of proj_of(mu) as compile-time constants (forward hop)
 template <int MU>
@@ -991,7 +996,7 @@ __device__ __attribute__((always_inline)) inline void split_body(const cx<T> (&u
 // The stored link of one hop direction of the wave-split kernels (forward: U_mu at the site;
 // backward: U_mu at the neighbour, of the other parity), with the neighbour's index and the
 // boundary sign of the hop.
-template <typename LT, int MU, bool BWD>
+template <typename LT, int MU, bool BWD, int LAUX = 0>
 __device__ __attribute__((always_inline)) inline void split_link(const Geom& g, const typename LinkLoad<LT>::Store* __restrict__ links,
                                                                  int p, int x, int y, int z, int t, int xh, uint32_t h32,
                                                                  typename LinkLoad<LT>::Store (&ul)[LinkLoad<LT>::NE], uint32_t& hn,
@@ -1004,7 +1009,7 @@ __device__ __attribute__((always_inline)) inline void split_link(const Geom& g, 
     const auto lr = buf_rsrc(links + (size_t)(MU * 2 + lpar) * NE * Vh32, (uint32_t)NE * Vh32 * (uint32_t)sizeof(S));
     const uint32_t loff = (BWD ? hn : h32) * (uint32_t)sizeof(S);
 #pragma unroll
-    for (int c = 0; c < NE; c++) ul[c] = bload<S>(lr, loff, (uint32_t)c * Vh32 * (uint32_t)sizeof(S));
+    for (int c = 0; c < NE; c++) ul[c] = bload<S, LAUX>(lr, loff, (uint32_t)c * Vh32 * (uint32_t)sizeof(S));
 }
 
 // the link in the arithmetic precision, its third row rebuilt from the stored two
@@ -1017,8 +1022,8 @@ __device__ __attribute__((always_inline)) inline void split_widen(const typename
 }
 
 // One hop direction of the wave-split kernel for NV vectors.  PLANE: x and y neighbours come from
-// the LDS stage.
-template <typename T, typename LT, int NV, int MU, bool BWD, bool PLANE>
+// the LDS stage; LAUX: the cache policy of the link loads.
+template <typename T, typename LT, int NV, int MU, bool BWD, bool PLANE, int LAUX = 0>
 __device__ __attribute__((always_inline)) inline void split_dir(const Geom& g, const typename LinkLoad<LT>::Store* __restrict__ links, const cx<T>* __restrict__ in,
                                  const int (&vec)[NV], int p, int x, int y, int z, int t, int xh, uint32_t h32,
                                  const Stage<T>& sg, cx<T> (&acc)[NV][12]) {
@@ -1037,7 +1042,7 @@ __device__ __attribute__((always_inline)) inline void split_dir(const Geom& g, c
     typename LinkLoad<LT>::Store ul[LinkLoad<LT>::NE];
     uint32_t hn;
     int nsign;
-    split_link<LT, MU, BWD>(g, links, p, x, y, z, t, xh, h32, ul, hn, nsign);
+    split_link<LT, MU, BWD, LAUX>(g, links, p, x, y, z, t, xh, h32, ul, hn, nsign);
     cx<T> u[9];
     split_widen<T, LT>(ul, u);
     split_body<T, NV, MU, BWD, LDS>(u, hn, ln, (T)nsign, in, (uint32_t)g.Vh, vec, sg, acc);
@@ -1479,11 +1484,11 @@ __global__ __launch_bounds__(512) void hop_plane_kernel(Geom g, const typename L
 // z and t hops, and the same two pairs backward, each on a wavefront of its own.  A one-vector
 // launch (the Lanczos steps) then has four wavefronts per 64 sites instead of two, each with half
 // the dependent loads; the four partial sums meet in LDS and each wavefront writes three of the
-// twelve output components.
-template <typename T, typename LT, bool CGU = false>
-__global__ __launch_bounds__(SCG_BLOCK) void hop_quad_kernel(Geom g, const typename LinkLoad<LT>::Store* __restrict__ links,
-                                                             const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int p, int nvec,
-                                                             int64_t nsb, EpiDev<T> e, int64_t cs, int64_t bps) {
+// twelve output components.  LAUX: the cache policy of the link loads.
+template <typename T, typename LT, bool CGU, int LAUX>
+__device__ __attribute__((always_inline)) inline void quad_body(Geom g, const typename LinkLoad<LT>::Store* __restrict__ links,
+                                                                const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int p, int nvec,
+                                                                int64_t nsb, EpiDev<T> e, int64_t cs, int64_t bps) {
     constexpr int NS = SCG_WAVE;   // sites per workgroup
     __shared__ cx<T> xch[4 * 12 * NS];
     __shared__ double red_lds[SCG_BLOCK / SCG_WAVE];
@@ -1521,21 +1526,21 @@ __global__ __launch_bounds__(SCG_BLOCK) void hop_quad_kernel(Geom g, const typen
     for (int c = 0; c < 12; c++) acc[0][c] = mk<T>(0, 0);
     if (active) {
         if (grp == 0) {
-            split_dir<T, LT, 1, 0, false, false>(g, links, in, vec, p, x, y, z, t, xh, h32, sg, acc);
+            split_dir<T, LT, 1, 0, false, false, LAUX>(g, links, in, vec, p, x, y, z, t, xh, h32, sg, acc);
             __builtin_amdgcn_sched_barrier(0);
-            split_dir<T, LT, 1, 1, false, false>(g, links, in, vec, p, x, y, z, t, xh, h32, sg, acc);
+            split_dir<T, LT, 1, 1, false, false, LAUX>(g, links, in, vec, p, x, y, z, t, xh, h32, sg, acc);
         } else if (grp == 1) {
-            split_dir<T, LT, 1, 2, false, false>(g, links, in, vec, p, x, y, z, t, xh, h32, sg, acc);
+            split_dir<T, LT, 1, 2, false, false, LAUX>(g, links, in, vec, p, x, y, z, t, xh, h32, sg, acc);
             __builtin_amdgcn_sched_barrier(0);
-            split_dir<T, LT, 1, 3, false, false>(g, links, in, vec, p, x, y, z, t, xh, h32, sg, acc);
+            split_dir<T, LT, 1, 3, false, false, LAUX>(g, links, in, vec, p, x, y, z, t, xh, h32, sg, acc);
         } else if (grp == 2) {
-            split_dir<T, LT, 1, 0, true, false>(g, links, in, vec, p, x, y, z, t, xh, h32, sg, acc);
+            split_dir<T, LT, 1, 0, true, false, LAUX>(g, links, in, vec, p, x, y, z, t, xh, h32, sg, acc);
             __builtin_amdgcn_sched_barrier(0);
-            split_dir<T, LT, 1, 1, true, false>(g, links, in, vec, p, x, y, z, t, xh, h32, sg, acc);
+            split_dir<T, LT, 1, 1, true, false, LAUX>(g, links, in, vec, p, x, y, z, t, xh, h32, sg, acc);
         } else {
-            split_dir<T, LT, 1, 2, true, false>(g, links, in, vec, p, x, y, z, t, xh, h32, sg, acc);
+            split_dir<T, LT, 1, 2, true, false, LAUX>(g, links, in, vec, p, x, y, z, t, xh, h32, sg, acc);
             __builtin_amdgcn_sched_barrier(0);
-            split_dir<T, LT, 1, 3, true, false>(g, links, in, vec, p, x, y, z, t, xh, h32, sg, acc);
+            split_dir<T, LT, 1, 3, true, false, LAUX>(g, links, in, vec, p, x, y, z, t, xh, h32, sg, acc);
         }
     }
 #pragma unroll
@@ -1566,6 +1571,21 @@ __global__ __launch_bounds__(SCG_BLOCK) void hop_quad_kernel(Geom g, const typen
     }
 }
 
+template <typename T, typename LT, bool CGU = false>
+__global__ __launch_bounds__(SCG_BLOCK) void hop_quad_kernel(Geom g, const typename LinkLoad<LT>::Store* __restrict__ links,
+                                                             const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int p, int nvec,
+                                                             int64_t nsb, EpiDev<T> e, int64_t cs, int64_t bps) {
+    quad_body<T, LT, CGU, 0>(g, links, in, out, p, nvec, nsb, e, cs, bps);
+}
+// the same with non-temporal link loads (tps 12): for one-vector launches whose links outgrow the
+// memory-side cache
+template <typename T, typename LT, bool CGU = false>
+__global__ __launch_bounds__(SCG_BLOCK) void hop_quad_nt_kernel(Geom g, const typename LinkLoad<LT>::Store* __restrict__ links,
+                                                                const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int p, int nvec,
+                                                                int64_t nsb, EpiDev<T> e, int64_t cs, int64_t bps) {
+    quad_body<T, LT, CGU, CPOL_NT>(g, links, in, out, p, nvec, nsb, e, cs, bps);
+}
+
 // LDS bytes of the staged variant for nv vectors of element size es (0 if it does not apply)
 static size_t plane_lds_bytes(const Geom& g, int nv, size_t es) {
     if (g.Lxh > 256) return 0;
@@ -1579,13 +1599,13 @@ static int norm_vb(int tps, int vb, int nvec) {
     if (tps == 5 || tps == 6) vb = 1;
     if (tps == 7) vb = vb <= 2 ? 2 : 4;
     if (tps == 8 || tps == 9) vb = vb <= 1 ? 1 : (vb <= 2 ? 2 : 4);
-    if (tps == 10) vb = 1;
+    if (tps == 10 || tps == 12) vb = 1;
     if (tps == 11) vb = vb <= 1 ? 1 : 2;
     return vb;
 }
 
 bool hop_shape_ok(const Geom& g, Prec prec, int tps, int vb) {
-    if (tps < 1 || tps > 11) return false;
+    if (tps < 1 || tps > 12) return false;
     const size_t es = (prec == P64 || prec == P64R) ? 16 : 8;
     if (tps == 11 && es != 8) return false;   // FP32 arithmetic only (FP64 would not fit in registers)
     if (tps >= 8 && (double)g.Vh * 12.0 * (double)es >= 4294967296.0) return false;
@@ -1624,23 +1644,28 @@ void set_hop_hoist_links(bool on) { g_hoist = on ? 1 : 0; }
 // tps 10: the quad-split variant (four wavefronts per 64 sites, one vector per workgroup)
 // tps 11: the link-resident variant (wave-split, one workgroup per site block for every vector of
 // the launch, vb 1 or 2 at a time)
-int hop_threads_per_site(int tps) { return tps == 10 ? 4 : ((tps == 3 || tps >= 5) ? 2 : tps); }
+// tps 12: the quad-split variant with non-temporal link loads
+int hop_threads_per_site(int tps) { return (tps == 10 || tps == 12) ? 4 : ((tps == 3 || tps >= 5) ? 2 : tps); }
 int hop_site_blocks(const Geom& g, int tps) {
     if (tps == 9) return g.L[2] * g.L[3] * plane_tiles(g);
     return (int)((g.Vh * hop_threads_per_site(tps) + SCG_BLOCK - 1) / SCG_BLOCK);
 }
 
-// the wave-split (tps 8), LDS-staged (9), quad-split (10) and link-resident (11) stencils; CGU: with
+// the wave-split (tps 8), LDS-staged (9), quad-split (10, 12) and link-resident (11) stencils; CGU: with
 // the CG update fused into the epilogue
 template <typename T, typename LT, bool CGU>
 static void launch_wide(const Geom& g, const typename LinkLoad<LT>::Store* links, const cx<T>* in, cx<T>* out, int p, int nvec,
                         int64_t nsb, const EpiDev<T>& e, int tps, int vb, int64_t grid, int64_t bps, const Launch& L) {
     const hipStream_t s = L.s;
     const dim3 gr((unsigned)grid, 1, L.nz);
-    if (tps == 10) {
+    if (tps == 10 || tps == 12) {
         const int64_t slice = g.Vh / g.L[3];
         const int64_t bps64 = (slice % SCG_WAVE == 0 && getenv_order()) ? slice / SCG_WAVE : 0;
-        hipLaunchKernelGGL((hop_quad_kernel<T, LT, CGU>), gr, dim3(SCG_BLOCK), 0, s, g, links, in, out, p, nvec, nsb, e, L.cs, bps64);
+        if (tps == 10)
+            hipLaunchKernelGGL((hop_quad_kernel<T, LT, CGU>), gr, dim3(SCG_BLOCK), 0, s, g, links, in, out, p, nvec, nsb, e, L.cs, bps64);
+        else
+            hipLaunchKernelGGL((hop_quad_nt_kernel<T, LT, CGU>), gr, dim3(SCG_BLOCK), 0, s, g, links, in, out, p, nvec, nsb, e, L.cs,
+                               bps64);
     } else if (tps == 9) {
         const size_t lds = plane_lds_bytes(g, vb, sizeof(cx<T>));
         if (lds == 0 || lds > PLANE_LDS_MAX) throw std::runtime_error("stencil launch shape does not fit this lattice");

@@ -1957,15 +1957,15 @@ void init_geometry(seedcg_s* h, const seedcg_params* p, const int32_t* dims) {
     // workgroups on one XCD
     h->tps64 = env_int("SEEDCG_TPS", 8);
     h->tps_lo = env_int("SEEDCG_TPS_LO", 8);
-    if (h->tps64 < 1 || h->tps64 > 11) h->tps64 = 8;
-    if (h->tps_lo < 1 || h->tps_lo > 11) h->tps_lo = 8;
+    if (h->tps64 < 1 || h->tps64 > 12) h->tps64 = 8;
+    if (h->tps_lo < 1 || h->tps_lo > 12) h->tps_lo = 8;
     h->vb64 = std::max(1, env_int("SEEDCG_VB", 1));
     h->vb_lo = std::max(1, env_int("SEEDCG_VB_LO", 1));
     // the several-vector launches take the same shape unless the environment names one of their own
     h->tps64_multi = env_int("SEEDCG_TPS_MULTI", h->tps64);
     h->tps_lo_multi = env_int("SEEDCG_TPS_LO_MULTI", h->tps_lo);
-    if (h->tps64_multi < 1 || h->tps64_multi > 11) h->tps64_multi = h->tps64;
-    if (h->tps_lo_multi < 1 || h->tps_lo_multi > 11) h->tps_lo_multi = h->tps_lo;
+    if (h->tps64_multi < 1 || h->tps64_multi > 12) h->tps64_multi = h->tps64;
+    if (h->tps_lo_multi < 1 || h->tps_lo_multi > 12) h->tps_lo_multi = h->tps_lo;
     h->vb64_multi = std::max(1, env_int("SEEDCG_VB_MULTI", h->vb64));
     h->vb_lo_multi = std::max(1, env_int("SEEDCG_VB_LO_MULTI", h->vb_lo));
     h->sync_every = std::max(1, env_int("SEEDCG_SYNC_EVERY", 16));
@@ -2035,7 +2035,7 @@ void tune_shape(seedcg_s* h, bool low, int nvec, const void* x, void* y) {
             return;
         }
     }
-    std::vector<std::pair<int, int>> cand{{10, 1}, {9, 1}, {8, 1}, {3, 1}, {5, 1}, {6, 1}, {4, 1}, {2, 1}, {1, 1}};
+    std::vector<std::pair<int, int>> cand{{10, 1}, {12, 1}, {9, 1}, {8, 1}, {3, 1}, {5, 1}, {6, 1}, {4, 1}, {2, 1}, {1, 1}};
     if (multi) {
         cand.push_back({9, 2});                 // staged x/y neighbours, links once per pair / quad
         cand.push_back({9, 4});

@@ -60,11 +60,12 @@ def _counter(d, name):
 
 def _copy_window(rows):
     """The 1 GiB copy probe in a counter trace: (mean counter value of its copies, dispatch id of its
-    last copy, dispatch id of the next copy of that size or None).  The probe is the first run of two
-    or more back-to-back copies (no other dispatch in between) whose values agree within 10%; other
-    copies of the run (a basis growing by device copies, say) are single.  Without such a run: the
-    first run of copies within 10% of the largest.  A later copy of the probe's size (the benchmark's
-    copy-rate measurement after its timed region) ends the window."""
+    last copy, dispatch id of the next copy of that size or None).  The probe is a run of two or more
+    back-to-back copies (no other dispatch in between) whose values agree within 10%: the first such
+    run within 10% of the largest one, since smaller runs (a batch placing its configurations, say)
+    can come first and other large copies (a basis growing by device copies) are single.  Without such
+    a run: the first run of copies within 10% of the largest.  A later copy of the probe's size (the
+    benchmark's copy-rate measurement after its timed region) ends the window."""
     cp = sorted((int(r["Dispatch_Id"]), float(r["Counter_Value"])) for r in rows if "copyBuffer" in r["Kernel_Name"])
     ids = sorted({int(r["Dispatch_Id"]) for r in rows})
 
@@ -74,15 +75,23 @@ def _copy_window(rows):
     def close(u, v):
         return abs(u - v) <= 0.1 * max(u, v)
 
-    probe = None
-    for k in range(len(cp) - 1):
+    runs = []
+    k = 0
+    while k < len(cp) - 1:
         if adjacent(cp[k][0], cp[k + 1][0]) and close(cp[k][1], cp[k + 1][1]):
-            probe = [cp[k], cp[k + 1]]
+            run = [cp[k], cp[k + 1]]
             for d, v in cp[k + 2:]:
-                if not (adjacent(probe[-1][0], d) and close(probe[0][1], v)):
+                if not (adjacent(run[-1][0], d) and close(run[0][1], v)):
                     break
-                probe.append((d, v))
-            break
+                run.append((d, v))
+            runs.append(run)
+            k += len(run)
+        else:
+            k += 1
+    probe = None
+    if runs:
+        top = max(r[0][1] for r in runs)
+        probe = next(r for r in runs if close(r[0][1], top))
     if probe is None:
         top = max(v for _, v in cp)
         big = [(d, v) for d, v in cp if v >= 0.9 * top]

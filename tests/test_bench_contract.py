@@ -41,21 +41,25 @@ def test_dominant_kind_names_the_rocprof_kernel_and_traffic_needs_that_kernel():
     assert bench.kind_kernel(d) == "scg::hop_split_kernel<float, scg::su3rows<float>, 2, true>"
     assert bench.kind_tag(d) == "fp32_split_vb2_cgu"
     assert bench.kind_kernel(dict(fmt=0, nvec=1, fused=0, tps=10, vb=1)) == "scg::hop_quad_kernel<double, double, false>"
+    assert bench.kind_kernel(dict(fmt=3, nvec=1, fused=0, tps=12, vb=1)) == "scg::hop_quad_nt_kernel<double, scg::su3rows<double>, false>"
+    assert bench.kind_tag(dict(fmt=3, nvec=1, fused=0, tps=12, vb=1)) == "fp64_quadnt_vb1"
     # a traffic summary of another kernel is never used for this one
     assert bench.measured_traffic(CONFIGS["c2"], "fp64", "scg::some_other_kernel") is None
 
 
 def test_headline_traffic_summary_is_found_for_its_own_kernel():
-    """The committed 24^3 x 48 summary of the one-vector FP64 launches names its kernel on a line that
-    also carries the dispatch count; the lookup takes the name alone and needs the current source."""
+    """The committed 24^3 x 48 summaries of the one-vector FP64 launches (non-temporal quad split) and
+    of the 23-vector FP32 ones name their kernel on a line that also carries the dispatch count; the
+    lookup takes the name alone and needs the current source."""
     sys.path.insert(0, ROOT)
     import bench
     from synth.configs import CONFIGS
     from paper_0901_3512_amd.profsummary import source_digest
-    k = dict(fmt=3, nvec=1, fused=0, tps=10, vb=1)
-    path = os.path.join(ROOT, "profiles", f"hop_kernel_24x24x24x48_{bench.kind_tag(k)}_traffic.txt")
-    kv = dict(l.strip().split("=", 1) for l in open(path) if "=" in l and not l.startswith("#"))
-    current = kv["source_sha256_16"] == source_digest(os.path.join(ROOT, "paper_0901_3512_amd", "csrc", "dslash.hip"))
-    t = bench.measured_traffic(CONFIGS["c3t"], bench.kind_tag(k), bench.kind_kernel(k))
-    assert (t == float(kv["traffic_bytes_per_launch"])) if current else (t is None)
-    assert bench.measured_traffic(CONFIGS["c3t"], bench.kind_tag(k), "scg::hop_split_kernel<double, double, 1, false>") is None
+    for k in (dict(fmt=3, nvec=1, fused=0, tps=12, vb=1), dict(fmt=4, nvec=23, fused=0, tps=11, vb=1)):
+        path = os.path.join(ROOT, "profiles", f"hop_kernel_24x24x24x48_{bench.kind_tag(k)}_traffic.txt")
+        kv = dict(l.strip().split("=", 1) for l in open(path) if "=" in l and not l.startswith("#"))
+        assert kv["kernel"].rsplit(" dispatches=", 1)[0] == bench.kind_kernel(k)
+        current = kv["source_sha256_16"] == source_digest(os.path.join(ROOT, "paper_0901_3512_amd", "csrc", "dslash.hip"))
+        t = bench.measured_traffic(CONFIGS["c3t"], bench.kind_tag(k), bench.kind_kernel(k))
+        assert (t == float(kv["traffic_bytes_per_launch"])) if current else (t is None)
+        assert bench.measured_traffic(CONFIGS["c3t"], bench.kind_tag(k), "scg::hop_split_kernel<double, double, 1, false>") is None

@@ -73,7 +73,7 @@ def test_batch_matches_oracle(cfgs, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_cg"])
-@pytest.mark.parametrize("shape", [None, ("9", "2"), ("10", "1"), ("3", "1"), ("11", "2")])
+@pytest.mark.parametrize("shape", [None, ("9", "2"), ("10", "1"), ("3", "1"), ("11", "2"), ("12", "1")])
 def test_batch_equals_separate_handles(cfgs, prec, shape, monkeypatch):
     """shape: a stencil launch shape (lanes-per-site code, vectors per workgroup) forced on both
     sides; None = the default one."""

@@ -19,7 +19,7 @@ from synth.links import random_su3_links
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [("8", "1"), ("8", "2"), ("8", "4"), ("9", "1"), ("9", "2"), ("9", "4"), ("10", "1"), ("11", "1"), ("11", "2")]
+SHAPES = [("8", "1"), ("8", "2"), ("8", "4"), ("9", "1"), ("9", "2"), ("9", "4"), ("10", "1"), ("11", "1"), ("11", "2"), ("12", "1")]
 
 
 def _problem(dims, nrhs=6, seed=11):

@@ -36,7 +36,7 @@ def round_bf16(a):
 @pytest.mark.parametrize("prec,rounder", [("mixed", round_fp32), ("mixed_bf16", round_bf16), ("mixed_cg", round_fp32)])
 @pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 2, 6), (8, 8, 8, 16), (32, 34, 2, 2)])
 @pytest.mark.parametrize("shape", [("3", "1"), ("6", "1"), ("7", "2"), ("7", "4"), ("8", "1"), ("8", "2"), ("8", "4"),
-                                   ("9", "1"), ("9", "2"), ("9", "4"), ("10", "1"), ("11", "1"), ("11", "2")])
+                                   ("9", "1"), ("9", "2"), ("9", "4"), ("10", "1"), ("11", "1"), ("11", "2"), ("12", "1")])
 def test_inner_operator_matches_oracle_on_rounded_inputs(prec, rounder, dims, shape, monkeypatch):
     from paper_0901_3512_amd import SeedCG
     print_case("inner", prec, dims, shape)

@@ -20,8 +20,9 @@ def _vecs(rng, n, Vh):
     return rng.standard_normal((n, Vh, 4, 3)) + 1j * rng.standard_normal((n, Vh, 4, 3))
 
 
-# vb = 4 changes only the multi-vector variants (7, 8, 9)
-TPS_VB = [(t, v) for v in (1, 2, 4) for t in range(1, 11) if v != 4 or t in (7, 8, 9)]
+# vb = 4 changes only the multi-vector variants (7, 8, 9); the quad-split ones (10, 12) take one
+# vector per workgroup whatever vb asks
+TPS_VB = [(t, v) for v in (1, 2, 4) for t in range(1, 13) if t != 11 and (v != 4 or t in (7, 8, 9))]
 
 
 @pytest.mark.parametrize("tps,vb", TPS_VB)
@@ -31,7 +32,8 @@ def test_apply_M_matches_oracle(dims, t_bc, eps, tps, vb, monkeypatch):
     pass, 7 = links loaded once for a group of vb vectors (2 or 4), 8 = forward and backward hops on
     separate wavefronts for a group of vb vectors (1, 2 or 4), 9 = the same with the x and y neighbours
     staged in LDS (the last lattice takes three tiles of xy-rows, with halo rows), 10 = four
-    wavefronts per 64 sites (forward / backward x-y / z-t hops); vb: vectors per workgroup."""
+    wavefronts per 64 sites (forward / backward x-y / z-t hops), 12 = 10 with non-temporal link loads;
+    vb: vectors per workgroup."""
     from paper_0901_3512_amd import SeedCG
     print_case("apply_M", dims, t_bc, tps, vb)
     monkeypatch.setenv("SEEDCG_TPS", str(tps))

@@ -26,6 +26,16 @@ def test_probe_is_found_beside_larger_single_copies():
     assert ref == 1000.0 and last == 5 and nxt == 9
 
 
+def test_probe_is_found_after_smaller_runs_of_copies():
+    # a batch placing its same-shape configurations by back-to-back device copies before the probe
+    rows = [_row(1, "copyBuffer", 20, "X"), _row(2, "copyBuffer", 20, "X"), _row(3, "copyBuffer", 21, "X"),
+            _row(4, "hop_a", 5, "X"), _row(5, "copyBuffer", 1000, "X"), _row(6, "copyBuffer", 1000, "X"),
+            _row(7, "copyBuffer", 1000, "X"), _row(8, "hop_a", 7, "X"), _row(9, "copyBuffer", 1000, "X"),
+            _row(10, "copyBuffer", 1000, "X")]
+    ref, last, nxt = _copy_window(rows)
+    assert ref == 1000.0 and last == 7 and nxt == 9
+
+
 def _write(d, name, rows):
     os.makedirs(d, exist_ok=True)
     with open(os.path.join(d, "p_counter_collection.csv"), "w", newline="") as f:

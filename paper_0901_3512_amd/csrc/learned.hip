@@ -72,17 +72,36 @@ struct Hop {
     bool fwd;
 };
 __device__ inline cx<float> conj_cx(cx<float> a) { return mk<float>(a.re, -a.im); }
+
+// Raw buffer loads: the base of a field in scalar registers and one 32-bit byte offset per lane, the
+// component's offset in the scalar soffset operand, instead of a 64-bit address per component.  The
+// bases (a direction's links, one vector's field) are uniform over the workgroup, and every field
+// spans fewer than 2^32 bytes (k_layer and k_grad check it).
+__device__ inline __amdgpu_buffer_rsrc_t kbuf(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ inline cx<float> kld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(cx<float>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+// one vector's field [2][12][Vh] at base + vec * vs (vs < 24 Vh: the even half only, vs complex)
+__device__ inline __amdgpu_buffer_rsrc_t kfield(const cx<float>* base, int vec, int64_t vs, int64_t Vh) {
+    const int v = __builtin_amdgcn_readfirstlane(vec);
+    return kbuf(base + (int64_t)v * vs, (uint32_t)((vs < 24 * Vh ? vs : 24 * Vh) * (int64_t)sizeof(cx<float>)));
+}
+
 template <int NE>
 __device__ inline void load_hop(const Geom& g, const cx<float>* __restrict__ links, int p, int h, const Site& s, int d, Hop& o) {
-    const int Vh = (int)g.Vh;
+    const uint32_t Vh = (uint32_t)g.Vh;
     const int mu = (d - 1) & 3;
     o.fwd = d <= 4;
     o.hn = nb_index(g, s, mu, o.fwd ? 1 : -1, o.sign);
-    const int lp = o.fwd ? p : 1 - p;
-    const int lh = o.fwd ? h : o.hn;
-    const cx<float>* lk = links + (int64_t)((mu * 2 + lp) * NE) * Vh + lh;
+    const uint32_t lp = (uint32_t)(o.fwd ? p : 1 - p);
+    const uint32_t lh = (uint32_t)(o.fwd ? h : o.hn);
+    // the links of direction mu, both parities: [parity][NE][Vh]
+    const auto lr = kbuf(links + (size_t)mu * 2 * NE * Vh, 2u * NE * Vh * (uint32_t)sizeof(cx<float>));
+    const uint32_t voff = (lp * NE * Vh + lh) * (uint32_t)sizeof(cx<float>);
 #pragma unroll
-    for (int c = 0; c < NE; c++) o.u[c] = lk[(int64_t)c * Vh];
+    for (int c = 0; c < NE; c++) o.u[c] = kld(lr, voff, (uint32_t)c * Vh * (uint32_t)sizeof(cx<float>));
     if constexpr (NE == 6) {
         o.u[6] = conj_cx(cmul(o.u[1], o.u[5]) - cmul(o.u[2], o.u[4]));
         o.u[7] = conj_cx(cmul(o.u[2], o.u[3]) - cmul(o.u[0], o.u[5]));
@@ -90,13 +109,13 @@ __device__ inline void load_hop(const Geom& g, const cx<float>* __restrict__ lin
     }
 }
 // (T_d src)(p, h) with the link of o; src is the field of one vector, [2][12][Vh]
-__device__ inline void apply_hop(const Hop& o, const cx<float>* __restrict__ src, int p, int Vh, cx<float> t[12]) {
-    const cx<float>* nb = src + (int64_t)(1 - p) * 12 * Vh + o.hn;
+__device__ inline void apply_hop(const Hop& o, __amdgpu_buffer_rsrc_t src, int p, uint32_t Vh, cx<float> t[12]) {
+    const uint32_t voff = ((uint32_t)(1 - p) * 12u * Vh + (uint32_t)o.hn) * (uint32_t)sizeof(cx<float>);
 #pragma unroll
     for (int sp = 0; sp < 4; sp++) {
         cx<float> v[3];
 #pragma unroll
-        for (int b = 0; b < 3; b++) v[b] = nb[(int64_t)(3 * sp + b) * Vh];
+        for (int b = 0; b < 3; b++) v[b] = kld(src, voff, (uint32_t)(3 * sp + b) * Vh * (uint32_t)sizeof(cx<float>));
 #pragma unroll
         for (int a = 0; a < 3; a++) {
             cx<float> acc = mk<float>(0.f, 0.f);
@@ -154,13 +173,14 @@ __device__ __attribute__((always_inline)) inline void k_layer_term(int d, const 
 #pragma unroll
     for (int j = 0; j < NV; j++) {
         if (vec[j] < 0) continue;
-        const cx<float>* src = in + (int64_t)vec[j] * in_vs;
+        const auto src = kfield(in, vec[j], in_vs, Vh);
         cx<float> t[12];
         if (d == 0) {
+            const uint32_t voff = ((uint32_t)p * 12u * (uint32_t)Vh + (uint32_t)h) * (uint32_t)sizeof(cx<float>);
 #pragma unroll
-            for (int c = 0; c < 12; c++) t[c] = src[(int64_t)(p * 12 + c) * Vh + h];
+            for (int c = 0; c < 12; c++) t[c] = kld(src, voff, (uint32_t)c * (uint32_t)Vh * (uint32_t)sizeof(cx<float>));
         } else {
-            apply_hop(o, src, p, Vh, t);
+            apply_hop(o, src, p, (uint32_t)Vh, t);
         }
 #pragma unroll
         for (int a = 0; a < 4; a++)
@@ -245,6 +265,10 @@ __global__ __launch_bounds__(256) void k_layer_kernel(Geom g, const cx<float>* _
     }
 }
 
+// the 32-bit byte offsets of the buffer loads: a vector's field (24 Vh complex) and a direction's
+// links (2 x 9 Vh complex at most) stay below 2^32 bytes
+bool k_offsets_fit(const Geom& g) { return (double)g.Vh * 24.0 * (double)sizeof(cx<float>) < 4294967296.0; }
+
 // the band of t-slices [t0, t0 + nt) (mod Lt); nt <= 0 or nt >= Lt is the whole lattice
 Band make_band(const Geom& g, int t0, int nt) {
     if (nt <= 0 || nt >= g.L[3]) return Band{0, g.L[3]};
@@ -262,6 +286,7 @@ void k_layer(const Geom& g, KLinks links, const void* in, void* out, const void*
     if (in_vs < 24 * g.Vh && !(zero_odd_input && in_vs >= 12 * g.Vh))
         throw std::invalid_argument("k_layer: an input of even-site vectors must be declared even-only");
     if (links.ne != 6 && links.ne != 9) throw std::invalid_argument("k_layer: links hold 6 or 9 entries");
+    if (!k_offsets_fit(g)) throw std::invalid_argument("k_layer: a field of this lattice spans 2^32 bytes or more");
     const Band b = make_band(g, t0, nt), ib = make_band(g, in_t0, in_nt);
     const int64_t nsb = (k_sites(g, pmask, b) + K_LAYER_SITES - 1) / K_LAYER_SITES;
     const unsigned grid = (unsigned)(nvec == 1 ? nsb : nsb * ((nvec + NV - 1) / NV));
@@ -310,17 +335,19 @@ __global__ __launch_bounds__(256) void k_grad_kernel(Geom g, const cx<float>* __
         if (dt) load_hop<NE>(g, links, p, h, s, dt, o);
 #pragma unroll 1
         for (int v = 0; v < nvec; v++) {
-            const cx<float>* src = in + (int64_t)v * in_vs;
+            const auto src = kfield(in, v, in_vs, Vh);
+            const uint32_t so = (uint32_t)Vh * (uint32_t)sizeof(cx<float>);   // one component
+            const uint32_t voff = ((uint32_t)p * 12u * (uint32_t)Vh + (uint32_t)h) * (uint32_t)sizeof(cx<float>);
             cx<float> t[12], q[12];
             if (dt == 0) {
 #pragma unroll
-                for (int c = 0; c < 12; c++) t[c] = src[(int64_t)(p * 12 + c) * Vh + h];
+                for (int c = 0; c < 12; c++) t[c] = kld(src, voff, (uint32_t)c * so);
             } else {
-                apply_hop(o, src, p, Vh, t);
+                apply_hop(o, src, p, (uint32_t)Vh, t);
             }
-            const cx<float>* gs = gv + (int64_t)v * 24 * Vh + (int64_t)p * 12 * Vh;
+            const auto gs = kfield(gv, v, 24 * (int64_t)Vh, Vh);
 #pragma unroll
-            for (int c = 0; c < 12; c++) q[c] = gs[(int64_t)c * Vh + h];
+            for (int c = 0; c < 12; c++) q[c] = kld(gs, voff, (uint32_t)c * so);
 #pragma unroll
             for (int a = 0; a < 4; a++)
 #pragma unroll
@@ -390,6 +417,7 @@ int64_t k_grad_blocks(const Geom& g) { return (2 * g.Vh + 255) / 256; }
 int64_t k_grad(const Geom& g, KLinks links, const void* gv, const void* in, bool dagger, int nvec, double* part, hipStream_t s,
                bool zero_odd_input, int pmask, int t0, int nt, int64_t in_vstride) {
     if (links.ne != 6 && links.ne != 9) throw std::invalid_argument("k_grad: links hold 6 or 9 entries");
+    if (!k_offsets_fit(g)) throw std::invalid_argument("k_grad: a field of this lattice spans 2^32 bytes or more");
     const Band b = make_band(g, t0, nt);
     const int64_t in_vs = in_vstride ? in_vstride : 24 * g.Vh;
     if (in_vs < 24 * g.Vh && !(zero_odd_input && in_vs >= 12 * g.Vh))

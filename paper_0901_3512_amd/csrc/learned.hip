@@ -195,19 +195,24 @@ __device__ __attribute__((always_inline)) inline void k_layer_term(int d, const 
 
 // out = L in (dagger = 0) or L^dag in (dagger = 1) on the output parities of pmask, for the vectors
 // listed in vmap (or 0..nvec-1): NV vectors per thread, every link read once per site and direction.
-// A workgroup takes 128 sites: waves 0-1 the identity term and the forward transports d = 1..4,
-// waves 2-3 the backward transports d = 5..8, so each lane follows half the chain of dependent loads;
-// the backward half's sums reach the forward lanes through LDS.  Workgroup b takes vector group
+// NG = 4: a workgroup takes 64 sites, one wavefront per quarter of the nine terms (the identity and
+// the forward x and y transports, forward z and t, backward x and y, backward z and t), so each lane
+// follows a quarter of the chain of dependent loads; the other three quarters' sums reach the first
+// wavefront through LDS and are added in that order.  NG = 2: 128 sites, waves 0-1 the identity and
+// the forward transports, waves 2-3 the backward ones.  The narrow launches of the training take
+// NG = 4 (latency-bound), launches of several vector groups NG = 2 (fewer link reads per site
+// block).  Workgroup b takes vector group
 // b % nvg of site block b / nvg, so the groups of one site block run as neighbouring workgroups and
 // find its links in L2.
-constexpr int K_LAYER_SITES = 128;
-template <int NV, int NE>
+template <int NV, int NE, int NG>
 __global__ __launch_bounds__(256) void k_layer_kernel(Geom g, const cx<float>* __restrict__ links, const cx<float>* __restrict__ in,
                                                       cx<float>* __restrict__ out, const cx<float>* __restrict__ W, int dagger,
                                                       const int32_t* vmap, int nvec, int zero_odd_input, int pmask, Band band,
                                                       Band in_band, int64_t in_vs) {
+    static_assert(NG == 2 || NG == 4, "two or four wavefront groups");
+    constexpr int K_LAYER_SITES = 256 / NG;
     __shared__ cx<float> w[9 * 16];
-    __shared__ cx<float> xch[NV * 12 * K_LAYER_SITES];
+    __shared__ cx<float> xch[(NG - 1) * NV * 12 * K_LAYER_SITES];
     for (int k = threadIdx.x; k < 9 * 16; k += blockDim.x) {
         const int d = k / 16, e = k % 16, a = e / 4, b = e % 4;
         if (!dagger) {
@@ -221,7 +226,7 @@ __global__ __launch_bounds__(256) void k_layer_kernel(Geom g, const cx<float>* _
     const int nvg = (nvec + NV - 1) / NV;
     const int vg = (int)(blockIdx.x % (unsigned)nvg);
     const int64_t sb = blockIdx.x / (unsigned)nvg;
-    const int side = (int)(threadIdx.x / K_LAYER_SITES);   // uniform over the wavefront
+    const int grp = (int)(threadIdx.x / K_LAYER_SITES);   // uniform over the wavefront
     const int sl = (int)(threadIdx.x % K_LAYER_SITES);
     int p = 0, h = 0;
     const bool valid = site_of_launch(g, pmask, band, sb * K_LAYER_SITES + sl, p, h);
@@ -240,28 +245,45 @@ __global__ __launch_bounds__(256) void k_layer_kernel(Geom g, const cx<float>* _
     if (valid) {
         const Site s = site_of(g, p, h);
         // the directions unrolled, so that each one's transport is resolved at compile time
-        if (side == 0) {
+        if (NG == 2 && grp == 0) {
 #pragma unroll
             for (int d = 0; d < 5; d++) k_layer_term<NV, NE>(d, g, links, in, w, vec, zero_odd_input, in_band, p, h, s, Vh, in_vs, acc);
-        } else {
+        } else if (NG == 2) {
 #pragma unroll
             for (int d = 5; d < 9; d++) k_layer_term<NV, NE>(d, g, links, in, w, vec, zero_odd_input, in_band, p, h, s, Vh, in_vs, acc);
+        } else if (grp == 0) {
+#pragma unroll
+            for (int d = 0; d < 3; d++) k_layer_term<NV, NE>(d, g, links, in, w, vec, zero_odd_input, in_band, p, h, s, Vh, in_vs, acc);
+        } else if (grp == 1) {
+#pragma unroll
+            for (int d = 3; d < 5; d++) k_layer_term<NV, NE>(d, g, links, in, w, vec, zero_odd_input, in_band, p, h, s, Vh, in_vs, acc);
+        } else if (grp == 2) {
+#pragma unroll
+            for (int d = 5; d < 7; d++) k_layer_term<NV, NE>(d, g, links, in, w, vec, zero_odd_input, in_band, p, h, s, Vh, in_vs, acc);
+        } else {
+#pragma unroll
+            for (int d = 7; d < 9; d++) k_layer_term<NV, NE>(d, g, links, in, w, vec, zero_odd_input, in_band, p, h, s, Vh, in_vs, acc);
         }
     }
-    if (side == 1) {
+    if (grp > 0) {
 #pragma unroll
         for (int j = 0; j < NV; j++)
 #pragma unroll
-            for (int c = 0; c < 12; c++) xch[(j * 12 + c) * K_LAYER_SITES + sl] = acc[j][c];
+            for (int c = 0; c < 12; c++) xch[(((grp - 1) * NV + j) * 12 + c) * K_LAYER_SITES + sl] = acc[j][c];
     }
     __syncthreads();
-    if (side == 1 || !valid) return;
+    if (grp > 0 || !valid) return;
 #pragma unroll
     for (int j = 0; j < NV; j++) {
         if (vec[j] < 0) continue;
         cx<float>* dst = out + (int64_t)vec[j] * 24 * Vh + (int64_t)p * 12 * Vh + h;
 #pragma unroll
-        for (int c = 0; c < 12; c++) dst[(int64_t)c * Vh] = acc[j][c] + xch[(j * 12 + c) * K_LAYER_SITES + sl];
+        for (int c = 0; c < 12; c++) {
+            cx<float> o = acc[j][c];
+#pragma unroll
+            for (int q = 0; q < NG - 1; q++) o = o + xch[((q * NV + j) * 12 + c) * K_LAYER_SITES + sl];
+            dst[(int64_t)c * Vh] = o;
+        }
     }
 }
 
@@ -288,24 +310,25 @@ void k_layer(const Geom& g, KLinks links, const void* in, void* out, const void*
     if (links.ne != 6 && links.ne != 9) throw std::invalid_argument("k_layer: links hold 6 or 9 entries");
     if (!k_offsets_fit(g)) throw std::invalid_argument("k_layer: a field of this lattice spans 2^32 bytes or more");
     const Band b = make_band(g, t0, nt), ib = make_band(g, in_t0, in_nt);
-    const int64_t nsb = (k_sites(g, pmask, b) + K_LAYER_SITES - 1) / K_LAYER_SITES;
-    const unsigned grid = (unsigned)(nvec == 1 ? nsb : nsb * ((nvec + NV - 1) / NV));
+    // one vector group: four wavefront groups of 64 sites; several: two of 128
+    const int64_t nvg = nvec == 1 ? 1 : (nvec + NV - 1) / NV;
+    const int64_t sites_per_wg = nvg == 1 ? 64 : 128;
+    const int64_t nsb = (k_sites(g, pmask, b) + sites_per_wg - 1) / sites_per_wg;
+    const unsigned grid = (unsigned)(nsb * nvg);
     const auto lk = (const cx<float>*)links.p;
     const auto in32 = (const cx<float>*)in;
     const auto out32 = (cx<float>*)out;
     const auto W32 = (const cx<float>*)W;
-    if (nvec == 1 && links.ne == 6)
-        hipLaunchKernelGGL((k_layer_kernel<1, 6>), dim3(grid), dim3(256), 0, s, g, lk, in32, out32, W32, (int)dagger, vmap, nvec,
-                           (int)zero_odd_input, pmask, b, ib, in_vs);
-    else if (nvec == 1)
-        hipLaunchKernelGGL((k_layer_kernel<1, 9>), dim3(grid), dim3(256), 0, s, g, lk, in32, out32, W32, (int)dagger, vmap, nvec,
-                           (int)zero_odd_input, pmask, b, ib, in_vs);
-    else if (links.ne == 6)
-        hipLaunchKernelGGL((k_layer_kernel<NV, 6>), dim3(grid), dim3(256), 0, s, g, lk, in32, out32, W32, (int)dagger, vmap, nvec,
-                           (int)zero_odd_input, pmask, b, ib, in_vs);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, g, lk, in32, out32, W32, (int)dagger, vmap, nvec, (int)zero_odd_input,
+                           pmask, b, ib, in_vs);
+    };
+    if (nvec == 1)
+        links.ne == 6 ? go(k_layer_kernel<1, 6, 4>) : go(k_layer_kernel<1, 9, 4>);
+    else if (nvg == 1)
+        links.ne == 6 ? go(k_layer_kernel<NV, 6, 4>) : go(k_layer_kernel<NV, 9, 4>);
     else
-        hipLaunchKernelGGL((k_layer_kernel<NV, 9>), dim3(grid), dim3(256), 0, s, g, lk, in32, out32, W32, (int)dagger, vmap, nvec,
-                           (int)zero_odd_input, pmask, b, ib, in_vs);
+        links.ne == 6 ? go(k_layer_kernel<NV, 6, 2>) : go(k_layer_kernel<NV, 9, 2>);
 }
 
 // partial sums over the sites of pmask, colours and vectors of g[a][c] conj((T_dt in)[b][c]) for

@@ -319,6 +319,10 @@ seedcg_status seedcg_probe_mfma(int32_t dtype, int32_t iters, void* stream, doub
    Needs the basis of the last solve_seed (SEEDCG_ERR_STATE otherwise); one configuration per handle. */
 seedcg_status seedcg_train_precond(seedcg_t h, int32_t steps, int32_t n_ritz, int32_t n_lanczos, double lr, double* out);
 
+/* The kernels of K address a vector's field (24 Vh complex FP32) with 32-bit byte offsets: on a
+   lattice with Vh >= 22.4 M sites per parity, train_precond, apply_P, the loss calls and PCG return
+   SEEDCG_ERR_ARG. */
+
 /* on != 0: solve_rest runs preconditioned CG with P = K K^dag (needs weights). */
 seedcg_status seedcg_use_precond(seedcg_t h, int32_t on);
 
